@@ -1,0 +1,208 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) D2Q9 lattice-Boltzmann library with the
+ * velocity-interpolation-based bounce-back (VIBB) wall closure of Zhang et al.,
+ * arXiv:1903.01111.
+ *
+ * What one time step computes (the paper's Sections 2 and 3):
+ *   1. for every fluid->solid link (x_f, i', q, u_w): the population f_i(x_f, t+1)
+ *      that would stream out of the solid, by VIBB (Section 3.1: bounce-back from
+ *      the departure point d, whose density, non-equilibrium part and velocity
+ *      are interpolated along the link) or by halfway bounce-back; plus the
+ *      momentum-exchange force on the solid;
+ *   2. pull streaming f_i(x, t+1) = f+_i(x - e_i, t) at every fluid node
+ *      (Section 2, the evolution equation);
+ *   3. BGK collision f+ = f - (f - f^eq)/tau (Section 2), with a body force by
+ *      Guo's scheme;
+ *   4. optional open columns (Section 4.3): a non-equilibrium extrapolation
+ *      velocity inlet at x = 0 and a zero-gradient (copy) outlet at x = nx-1.
+ *
+ * Conventions
+ *   - Lattice: nx x ny nodes, node (x, y) at index y*nx + x in every host array.
+ *     Periodic in y; periodic in x unless x_bc = LBM_X_OPEN.
+ *   - Velocities (the order fixed by the rows j_x, j_y of the paper's MRT matrix):
+ *       e0=(0,0) e1=(1,0) e2=(0,1) e3=(-1,0) e4=(0,-1)
+ *       e5=(1,1) e6=(-1,1) e7=(-1,-1) e8=(1,-1)
+ *   - A link is (node, dir): node is a fluid node x_f, dir = i' in 1..8 points
+ *     from x_f into the solid node x_s = x_f + e_{i'}; q = |x_f - x_w|/|x_f - x_s|
+ *     in (0, 1] (Section 3); u_w is the wall velocity at x_w.
+ *   - Every call returns lbm_status (0 = success, < 0 = error); no exception
+ *     crosses the ABI.  lbm_last_error() describes the last failure.
+ *   - Host arrays passed in are owned by the caller and copied during the call;
+ *     no pointer is kept.  Device memory is a workspace the caller allocates
+ *     (lbm_workspace_bytes) and keeps alive until lbm_destroy; the library never
+ *     frees it.
+ *   - Work is enqueued on params.stream (a hipStream_t; NULL = the null stream).
+ *     Calls that return host data synchronise that stream.
+ *   - One host thread may use a context at a time.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lbm_status;
+#define LBM_OK 0
+#define LBM_E_ARG (-1)      /* invalid argument or size */
+#define LBM_E_GEOM (-2)     /* invalid geometry or link list */
+#define LBM_E_NOMEM (-3)    /* workspace too small, or a host allocation failed */
+#define LBM_E_DEVICE (-4)   /* no usable GPU, or a HIP call failed */
+#define LBM_E_STATE (-5)    /* call out of order (e.g. step before geometry) */
+#define LBM_E_UNSTABLE (-6) /* a non-finite value was read back */
+
+/* storage of the populations in device memory.  All store f_i - w_i (deviation
+ * from the rest state); F64 computes in FP64, the others in FP32.  The 16-bit
+ * forms store (f_i - w_i) * 2^dev_scale_log2 rounded to nearest even. */
+#define LBM_F64 0
+#define LBM_F32 1
+#define LBM_F16_DEV 2
+#define LBM_BF16_DEV 3
+
+#define LBM_X_PERIODIC 0
+#define LBM_X_OPEN 1 /* inlet at x = 0, outlet at x = nx-1 */
+
+#define LBM_SCHEME_VIBB 0 /* Section 3.1 */
+#define LBM_SCHEME_HBB 1  /* halfway bounce-back (Section 3) */
+
+/* obstacle primitives of lbm_geometry; geo = (cx, cy, r) */
+#define LBM_PRIM_DISC 0  /* solid where |x - c| <= r */
+#define LBM_PRIM_RING 1  /* solid where |x - c| >= r */
+#define LBM_PRIM_BELOW 2 /* solid where y <= cy */
+#define LBM_PRIM_ABOVE 3 /* solid where y >= cy */
+
+typedef struct {
+    int32_t nx, ny;         /* lattice size, >= 1 each; nx >= 3 with LBM_X_OPEN */
+    int32_t x_bc;           /* LBM_X_PERIODIC or LBM_X_OPEN */
+    int32_t storage;        /* LBM_F64 .. LBM_BF16_DEV */
+    double tau;             /* BGK relaxation time, > 1/2 (tau = 3 nu + 1/2, Section 2) */
+    double gx, gy;          /* body acceleration; force density rho*g (Guo forcing) */
+    double rho0;            /* reference density of the moving-wall term 6 w rho0 e.u_w */
+    int32_t n_obj;          /* number of force accumulators, >= 1 */
+    int32_t dev_scale_log2; /* 16-bit storage scale exponent k, |k| <= 30 */
+    int32_t device;         /* HIP device ordinal */
+    int32_t reserved;       /* must be 0 */
+    void *stream;           /* hipStream_t the work is enqueued on; NULL = null stream */
+} lbm_params;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Message for the last failure on ctx, or of the calling thread when ctx is NULL
+ * (e.g. a failed lbm_create).  Never NULL; valid until the next call. */
+const char *lbm_last_error(const lbm_ctx *ctx);
+
+/* ---------------------------------------------------------------------------
+ * Geometry (host only; no GPU needed).
+ * ------------------------------------------------------------------------- */
+
+/* Solid mask and fluid->solid links of a union of primitives (Section 3: node
+ * classification and q).  A node is solid when any primitive holds it (a node on
+ * a circle is solid; periodic directions use minimum-image offsets).  For each
+ * fluid node that is streamed (not an open column) and each direction i' whose
+ * neighbour x_f + e_{i'} is solid, one link is emitted; q is the fraction of the
+ * link to the first crossing of a primitive that holds that neighbour, u_w the
+ * rigid velocity (ux, uy) + omega x (x_w - c) of that primitive at
+ * x_w = x_f + q e_{i'}, obj its obj id.
+ *   kind[n_prim], geo[3*n_prim] = (cx, cy, r), motion[3*n_prim] = (ux, uy, omega),
+ *   prim_obj[n_prim];  mask_out[ny*nx] (1 = solid);  links ordered by node, then dir.
+ * The link arrays (node, dir, q, uw[2*k], obj) are written only if the count does
+ * not exceed max_links; *n_links_out always receives the count (call once with
+ * max_links = 0 to size them).  Errors: LBM_E_ARG. */
+lbm_status lbm_geometry(int32_t nx, int32_t ny, int32_t x_bc, int32_t n_prim, const int32_t *kind,
+                        const double *geo, const double *motion, const int32_t *prim_obj,
+                        uint8_t *mask_out, int64_t max_links, int32_t *node, int8_t *dir,
+                        double *q, double *uw, int32_t *obj, int64_t *n_links_out);
+
+/* Validates a mask and link list against params without touching a device:
+ * sizes, q in (0,1], every link from a streamed fluid node into a solid node,
+ * no duplicate (node, dir), every pull from a solid node covered by a link, obj
+ * in [0, n_obj), open columns backed by a fluid neighbour column.  uw, obj and
+ * scheme may be NULL (0, 0, VIBB).  *n_fallback (may be NULL) receives the number
+ * of VIBB links whose second node x_ff = x_f - e_{i'} is solid: they fall back to
+ * halfway bounce-back.  Errors: LBM_E_ARG, LBM_E_GEOM (message names the index). */
+lbm_status lbm_check_geometry(const lbm_params *p, const uint8_t *mask, int64_t n_links,
+                              const int32_t *node, const int8_t *dir, const double *q,
+                              const double *uw, const int32_t *obj, const int8_t *scheme,
+                              int64_t *n_fallback);
+
+/* ---------------------------------------------------------------------------
+ * Lattice context.
+ * ------------------------------------------------------------------------- */
+
+/* Device bytes the context needs for params and up to max_links links, or 0 if
+ * params are invalid. */
+size_t lbm_workspace_bytes(const lbm_params *p, int64_t max_links);
+
+/* Creates a context over a device workspace of at least
+ * lbm_workspace_bytes(p, max_links) bytes (256-byte aligned; the caller owns it).
+ * max_links is read from the workspace size.  Launches nothing.
+ * Errors: LBM_E_ARG, LBM_E_NOMEM, LBM_E_DEVICE (no GPU). */
+lbm_status lbm_create(const lbm_params *p, void *workspace, size_t bytes, lbm_ctx **out);
+
+void lbm_destroy(lbm_ctx *ctx); /* frees host-side state only */
+
+/* Uploads the geometry (validated as lbm_check_geometry; nothing on the device
+ * changes if it fails), resets the force accumulators and the step counter.
+ * The populations must then be initialised.  Errors: LBM_E_GEOM, LBM_E_NOMEM
+ * (more links than the workspace holds), LBM_E_DEVICE. */
+lbm_status lbm_set_geometry(lbm_ctx *ctx, const uint8_t *mask, int64_t n_links,
+                            const int32_t *node, const int8_t *dir, const double *q,
+                            const double *uw, const int32_t *obj, const int8_t *scheme);
+
+/* Inlet velocity per row (ny values each; NULL = 0) for LBM_X_OPEN.  Default 0. */
+lbm_status lbm_set_inlet(lbm_ctx *ctx, const double *ux, const double *uy);
+
+/* Post-collision populations f+ = f^eq(rho, u) at every fluid node (Section 2,
+ * equilibrium), from host fields of ny*nx values (NULL: rho0, 0, 0).
+ * Errors: LBM_E_STATE before lbm_set_geometry. */
+lbm_status lbm_init_equilibrium(lbm_ctx *ctx, const double *rho, const double *ux,
+                                const double *uy);
+
+/* Enqueues n >= 0 time steps; returns without waiting.  Errors: LBM_E_STATE. */
+lbm_status lbm_step(lbm_ctx *ctx, int64_t n);
+
+/* Waits for the context's stream. */
+lbm_status lbm_sync(lbm_ctx *ctx);
+
+int64_t lbm_step_count(const lbm_ctx *ctx); /* steps since geometry / set_state */
+
+/* Density and physical velocity u = (sum f+ e)/rho - g/2 (Section 2 moments with
+ * Guo's half-force shift) at every node into host arrays of ny*nx doubles (may be
+ * NULL); solid nodes read 0.  Synchronises.  Errors: LBM_E_STATE, LBM_E_UNSTABLE
+ * (non-finite value found). */
+lbm_status lbm_moments(lbm_ctx *ctx, double *rho, double *ux, double *uy);
+
+/* Raw post-collision populations f+_i (including w_i) into a host array of
+ * 9*ny*nx doubles, node-major: f[(y*nx + x)*9 + i]; solid nodes read 0. */
+lbm_status lbm_populations(lbm_ctx *ctx, double *f);
+
+/* Momentum-exchange force of the fluid on object obj: last = the latest step,
+ * sum = accumulated since geometry / lbm_force_reset over *nsum steps (any output
+ * may be NULL).  Accumulated in FP64 on the device.  Synchronises.
+ * Errors: LBM_E_ARG (obj range), LBM_E_UNSTABLE (non-finite). */
+lbm_status lbm_force(lbm_ctx *ctx, int32_t obj, double last[2], double sum[2], int64_t *nsum);
+lbm_status lbm_force_reset(lbm_ctx *ctx);
+
+/* Total mass sum over fluid nodes of sum_i f+_i, reduced in FP64.  Synchronises. */
+lbm_status lbm_mass(lbm_ctx *ctx, double *mass);
+
+/* Checkpoint: the population buffer in storage precision plus the step counter
+ * and force accumulators.  lbm_state_bytes gives the size of the host buffer. */
+size_t lbm_state_bytes(const lbm_ctx *ctx);
+lbm_status lbm_get_state(lbm_ctx *ctx, void *host, size_t bytes);
+lbm_status lbm_set_state(lbm_ctx *ctx, const void *host, size_t bytes);
+
+/* Kernel timing: while on, lbm_step brackets every link and bulk launch with HIP
+ * events on the context's stream (no graph replay).  lbm_kernel_times
+ * synchronises and returns the summed durations in ms and the number of steps
+ * timed since profiling was switched on. */
+lbm_status lbm_set_profiling(lbm_ctx *ctx, int32_t on);
+lbm_status lbm_kernel_times(lbm_ctx *ctx, double *link_ms, double *bulk_ms, int64_t *n_steps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

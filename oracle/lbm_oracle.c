@@ -229,12 +229,33 @@ int64_t ORC(geometry)(int nx, int ny, int x_open, int nprim, const int32_t *ptyp
                       real_t *q, real_t *uw, int32_t *obj)
 {
     orc_grid g = {nx, ny, x_open};
-    for (int y = 0; y < ny; ++y)
-        for (int x = 0; x < nx; ++x) {
-            int s = 0;
-            for (int p = 0; p < nprim; ++p) s |= inside(ptype[p], pc + 3 * p, &g, x, y);
-            solid[y * nx + x] = (uint8_t)s;
+    /* owner[n]: the one primitive holding node n, -1 none, -2 several.  Discs
+     * are only tested over their bounding box (with periodic wrap). */
+    int32_t *owner = (int32_t *)malloc(sizeof(int32_t) * (size_t)nx * ny);
+    for (int n = 0; n < nx * ny; ++n) {
+        solid[n] = 0;
+        owner[n] = -1;
+    }
+    for (int p = 0; p < nprim; ++p) {
+        int xa = 0, xb = nx - 1, ya = 0, yb = ny - 1;
+        if (ptype[p] == 0) {
+            xa = (int)floor(RE(pc[3 * p]) - RE(pc[3 * p + 2])) - 1;
+            xb = (int)ceil(RE(pc[3 * p]) + RE(pc[3 * p + 2])) + 1;
+            ya = (int)floor(RE(pc[3 * p + 1]) - RE(pc[3 * p + 2])) - 1;
+            yb = (int)ceil(RE(pc[3 * p + 1]) + RE(pc[3 * p + 2])) + 1;
         }
+        for (int yy = ya; yy <= yb; ++yy)
+            for (int xx = xa; xx <= xb; ++xx) {
+                int x = xx, y = ((yy % ny) + ny) % ny;
+                if (x_open && (x < 0 || x >= nx)) continue;
+                x = ((x % nx) + nx) % nx;
+                if (!inside(ptype[p], pc + 3 * p, &g, x, y)) continue;
+                int n = y * nx + x;
+                if (owner[n] == p) continue;
+                solid[n] = 1;
+                owner[n] = owner[n] == -1 ? p : -2;
+            }
+    }
     int64_t n = 0;
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
@@ -248,7 +269,8 @@ int64_t ORC(geometry)(int nx, int ny, int x_open, int nprim, const int32_t *ptyp
                 if (!solid[ys * nx + xs]) continue;
                 real_t best = 0, brx = 0, bry = 0;
                 int bp = -1;
-                for (int p = 0; p < nprim; ++p) {
+                int own = owner[ys * nx + xs];
+                for (int p = (own >= 0 ? own : 0); p < (own >= 0 ? own + 1 : nprim); ++p) {
                     if (!inside(ptype[p], pc + 3 * p, &g, xs, ys)) continue;
                     real_t rx, ry;
                     real_t s = crossing(ptype[p], pc + 3 * p, &g, x, y, EX[ip], EY[ip], &rx, &ry);
@@ -272,6 +294,7 @@ int64_t ORC(geometry)(int nx, int ny, int x_open, int nprim, const int32_t *ptyp
                 ++n;
             }
         }
+    free(owner);
     return n;
 }
 

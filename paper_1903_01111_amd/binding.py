@@ -1,0 +1,353 @@
+"""Thin ctypes binding of the C ABI in include/lbm.h (same names, argument
+marshalling only), plus ``Lattice``, a small owner of a context whose device
+workspace is a torch tensor and whose stream is torch's current stream.
+
+Every step of the method runs in the HIP library; if the library is missing this
+module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+from . import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm_vibb.so")
+
+LBM_OK, LBM_E_ARG, LBM_E_GEOM, LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_STATE, LBM_E_UNSTABLE = (
+    0, -1, -2, -3, -4, -5, -6)
+LBM_F64, LBM_F32, LBM_F16_DEV, LBM_BF16_DEV = 0, 1, 2, 3
+LBM_X_PERIODIC, LBM_X_OPEN = 0, 1
+STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16": LBM_F16_DEV, "bf16": LBM_BF16_DEV}
+STATUS_NAMES = {0: "LBM_OK", -1: "LBM_E_ARG", -2: "LBM_E_GEOM", -3: "LBM_E_NOMEM",
+                -4: "LBM_E_DEVICE", -5: "LBM_E_STATE", -6: "LBM_E_UNSTABLE"}
+
+
+class lbm_params(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("x_bc", C.c_int32),
+                ("storage", C.c_int32), ("tau", C.c_double), ("gx", C.c_double),
+                ("gy", C.c_double), ("rho0", C.c_double), ("n_obj", C.c_int32),
+                ("dev_scale_log2", C.c_int32), ("device", C.c_int32),
+                ("reserved", C.c_int32), ("stream", C.c_void_p)]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported symbol
+_P, _V, _I64, _I32, _D = C.c_void_p, None, C.c_int64, C.c_int32, C.c_double
+SIGNATURES = [
+    ("lbm_last_error", C.c_char_p, [_P]),
+    ("lbm_geometry", _I32, [_I32, _I32, _I32, _I32, _P, _P, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P]),
+    ("lbm_check_geometry", _I32, [_P, _P, _I64, _P, _P, _P, _P, _P, _P, _P]),
+    ("lbm_workspace_bytes", C.c_size_t, [_P, _I64]),
+    ("lbm_create", _I32, [_P, _P, C.c_size_t, _P]),
+    ("lbm_destroy", _V, [_P]),
+    ("lbm_set_geometry", _I32, [_P, _P, _I64, _P, _P, _P, _P, _P, _P]),
+    ("lbm_set_inlet", _I32, [_P, _P, _P]),
+    ("lbm_init_equilibrium", _I32, [_P, _P, _P, _P]),
+    ("lbm_step", _I32, [_P, _I64]),
+    ("lbm_sync", _I32, [_P]),
+    ("lbm_step_count", _I64, [_P]),
+    ("lbm_moments", _I32, [_P, _P, _P, _P]),
+    ("lbm_populations", _I32, [_P, _P]),
+    ("lbm_force", _I32, [_P, _I32, _P, _P, _P]),
+    ("lbm_force_reset", _I32, [_P]),
+    ("lbm_mass", _I32, [_P, _P]),
+    ("lbm_state_bytes", C.c_size_t, [_P]),
+    ("lbm_get_state", _I32, [_P, _P, C.c_size_t]),
+    ("lbm_set_state", _I32, [_P, _P, C.c_size_t]),
+    ("lbm_set_profiling", _I32, [_P, _I32]),
+    ("lbm_kernel_times", _I32, [_P, _P, _P, _P]),
+]
+
+
+def lib():
+    """Loads the HIP library (built by paper_1903_01111_amd.build)."""
+    global _lib
+    if _lib is None:
+        try:
+            # torch's HIP runtime is loaded first so that the library binds to the
+            # same runtime instance as the torch tensors it receives
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1903_01111_amd.build` (or __graft_entry__.build())")
+        h = C.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            fn = getattr(h, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = h
+    return _lib
+
+
+def _p(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _err(ctx=None) -> str:
+    m = lib().lbm_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def check(status: int, ctx=None):
+    if status != LBM_OK:
+        raise LbmError(status, _err(ctx))
+
+
+# ---------------------------------------------------------------------------
+# Same-name wrappers (numpy arrays for host buffers, ints for device pointers).
+# ---------------------------------------------------------------------------
+
+def lbm_last_error(ctx=None) -> str:
+    return _err(ctx)
+
+
+def lbm_geometry(nx, ny, x_bc, kind, geo, motion, prim_obj):
+    """Returns (mask (ny,nx) uint8, node, dir, q, uw (n,2), obj)."""
+    kind = np.ascontiguousarray(kind, np.int32)
+    geo = np.ascontiguousarray(geo, np.float64).reshape(-1, 3)
+    motion = np.ascontiguousarray(motion, np.float64).reshape(-1, 3)
+    prim_obj = np.ascontiguousarray(prim_obj, np.int32)
+    mask = np.zeros((ny, nx), np.uint8)
+    n = C.c_int64(0)
+    args = [nx, ny, x_bc, len(kind), _p(kind), _p(geo), _p(motion), _p(prim_obj), _p(mask)]
+    check(lib().lbm_geometry(*args, 0, None, None, None, None, None, C.byref(n)))
+    k = n.value
+    node = np.zeros(k, np.int32)
+    d = np.zeros(k, np.int8)
+    q = np.zeros(k)
+    uw = np.zeros((k, 2))
+    obj = np.zeros(k, np.int32)
+    check(lib().lbm_geometry(*args, k, _p(node), _p(d), _p(q), _p(uw), _p(obj), C.byref(n)))
+    return mask, node, d, q, uw, obj
+
+
+def lbm_check_geometry(params, mask, node, dir, q, uw=None, obj=None, scheme=None):
+    """Returns the number of VIBB links that fall back to halfway bounce-back."""
+    nfb = C.c_int64(0)
+    arrs = _link_arrays(mask, node, dir, q, uw, obj, scheme)
+    check(lib().lbm_check_geometry(C.byref(params), _p(arrs[0]), len(arrs[1]),
+                                   *[_p(a) for a in arrs[1:]], C.byref(nfb)))
+    return nfb.value
+
+
+def _link_arrays(mask, node, dir, q, uw, obj, scheme):
+    mask = np.ascontiguousarray(mask, np.uint8)
+    node = np.ascontiguousarray(node, np.int32)
+    dir = np.ascontiguousarray(dir, np.int8)
+    q = np.ascontiguousarray(q, np.float64)
+    uw = None if uw is None else np.ascontiguousarray(uw, np.float64).reshape(-1, 2)
+    obj = None if obj is None else np.ascontiguousarray(obj, np.int32)
+    scheme = None if scheme is None else np.ascontiguousarray(scheme, np.int8)
+    return mask, node, dir, q, uw, obj, scheme
+
+
+def lbm_workspace_bytes(params, max_links) -> int:
+    return lib().lbm_workspace_bytes(C.byref(params), int(max_links))
+
+
+def lbm_create(params, workspace_ptr, nbytes):
+    ctx = C.c_void_p()
+    check(lib().lbm_create(C.byref(params), C.c_void_p(workspace_ptr), nbytes, C.byref(ctx)))
+    return ctx
+
+
+def lbm_destroy(ctx):
+    lib().lbm_destroy(ctx)
+
+
+def lbm_set_geometry(ctx, mask, node, dir, q, uw=None, obj=None, scheme=None):
+    a = _link_arrays(mask, node, dir, q, uw, obj, scheme)
+    check(lib().lbm_set_geometry(ctx, _p(a[0]), len(a[1]), *[_p(x) for x in a[1:]]), ctx)
+
+
+def lbm_set_inlet(ctx, ux=None, uy=None):
+    ux = None if ux is None else np.ascontiguousarray(ux, np.float64)
+    uy = None if uy is None else np.ascontiguousarray(uy, np.float64)
+    check(lib().lbm_set_inlet(ctx, _p(ux), _p(uy)), ctx)
+
+
+def lbm_init_equilibrium(ctx, rho=None, ux=None, uy=None):
+    f = lambda a: None if a is None else np.ascontiguousarray(a, np.float64)
+    rho, ux, uy = f(rho), f(ux), f(uy)
+    check(lib().lbm_init_equilibrium(ctx, _p(rho), _p(ux), _p(uy)), ctx)
+
+
+def lbm_step(ctx, n):
+    check(lib().lbm_step(ctx, int(n)), ctx)
+
+
+def lbm_sync(ctx):
+    check(lib().lbm_sync(ctx), ctx)
+
+
+def lbm_step_count(ctx) -> int:
+    return lib().lbm_step_count(ctx)
+
+
+def lbm_moments(ctx, ny, nx):
+    rho = np.zeros((ny, nx))
+    ux = np.zeros((ny, nx))
+    uy = np.zeros((ny, nx))
+    check(lib().lbm_moments(ctx, _p(rho), _p(ux), _p(uy)), ctx)
+    return rho, ux, uy
+
+
+def lbm_populations(ctx, ny, nx):
+    f = np.zeros((ny, nx, 9))
+    check(lib().lbm_populations(ctx, _p(f)), ctx)
+    return f
+
+
+def lbm_force(ctx, obj=0):
+    last = np.zeros(2)
+    s = np.zeros(2)
+    n = C.c_int64(0)
+    check(lib().lbm_force(ctx, obj, _p(last), _p(s), C.byref(n)), ctx)
+    return last, s, n.value
+
+
+def lbm_force_reset(ctx):
+    check(lib().lbm_force_reset(ctx), ctx)
+
+
+def lbm_mass(ctx) -> float:
+    m = C.c_double(0)
+    check(lib().lbm_mass(ctx, C.byref(m)), ctx)
+    return m.value
+
+
+def lbm_state_bytes(ctx) -> int:
+    return lib().lbm_state_bytes(ctx)
+
+
+def lbm_get_state(ctx) -> np.ndarray:
+    buf = np.zeros(lbm_state_bytes(ctx), np.uint8)
+    check(lib().lbm_get_state(ctx, _p(buf), buf.nbytes), ctx)
+    return buf
+
+
+def lbm_set_state(ctx, buf):
+    buf = np.ascontiguousarray(buf, np.uint8)
+    check(lib().lbm_set_state(ctx, _p(buf), buf.nbytes), ctx)
+
+
+def lbm_set_profiling(ctx, on: bool):
+    check(lib().lbm_set_profiling(ctx, int(bool(on))), ctx)
+
+
+def lbm_kernel_times(ctx):
+    a = C.c_double(0)
+    b = C.c_double(0)
+    n = C.c_int64(0)
+    check(lib().lbm_kernel_times(ctx, C.byref(a), C.byref(b), C.byref(n)), ctx)
+    return a.value, b.value, n.value
+
+
+# ---------------------------------------------------------------------------
+# Convenience owner of one context.
+# ---------------------------------------------------------------------------
+
+def make_params(nx, ny, *, x_open=False, storage="f32", tau=0.8, gx=0.0, gy=0.0, rho0=1.0,
+                n_obj=1, dev_scale_log2=0, device=0, stream=None) -> lbm_params:
+    return lbm_params(nx, ny, LBM_X_OPEN if x_open else LBM_X_PERIODIC, STORAGE.get(storage, storage),
+                      tau, gx, gy, rho0, n_obj, dev_scale_log2, device, 0, stream)
+
+
+def case_geometry(case: W.Case):
+    """Mask and links of a workloads.Case from the library's geometry routine,
+    with the per-object scheme applied."""
+    kind, geo, mot, obj = W.prim_arrays(case.prims)
+    mask, node, d, q, uw, lobj = lbm_geometry(case.nx, case.ny,
+                                              LBM_X_OPEN if case.x_open else LBM_X_PERIODIC,
+                                              kind, geo, mot, obj)
+    scheme = None
+    if case.scheme_of_obj is not None:
+        scheme = np.asarray(case.scheme_of_obj, np.int8)[lobj]
+    return mask, node, d, q, uw, lobj, scheme
+
+
+class Lattice:
+    """One lattice on one GPU: workspace from torch, work on torch's current stream."""
+
+    def __init__(self, case: W.Case, storage="f32", dev_scale_log2=0, device=0, geometry=None,
+                 max_links=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise LbmError(LBM_E_DEVICE, "no GPU visible to torch")
+        self.case = case
+        self.device = torch.device("cuda", device)
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        self.params = make_params(case.nx, case.ny, x_open=case.x_open, storage=storage, tau=case.tau,
+                                  gx=case.gx, gy=case.gy, rho0=case.rho0, n_obj=case.n_obj,
+                                  dev_scale_log2=dev_scale_log2, device=device, stream=stream)
+        geo = geometry if geometry is not None else case_geometry(case)
+        self.mask, self.node, self.dir, self.q, self.uw, self.obj, self.scheme = geo
+        nl = len(self.node) if max_links is None else max_links
+        nbytes = lbm_workspace_bytes(self.params, nl)
+        if nbytes == 0:
+            raise LbmError(LBM_E_ARG, "invalid lattice parameters")
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = self._ws.data_ptr()
+        ptr += (-ptr) % 256
+        self.ctx = lbm_create(self.params, ptr, nbytes)
+        lbm_set_geometry(self.ctx, self.mask, self.node, self.dir, self.q, self.uw, self.obj,
+                         self.scheme)
+        if case.x_open:
+            u = case.inlet()
+            lbm_set_inlet(self.ctx, u[:, 0], u[:, 1])
+        rho, ux, uy = case.init_fields()
+        lbm_init_equilibrium(self.ctx, rho, ux, uy)
+
+    def step(self, n=1):
+        lbm_step(self.ctx, n)
+        return self
+
+    def sync(self):
+        lbm_sync(self.ctx)
+
+    def moments(self):
+        return lbm_moments(self.ctx, self.case.ny, self.case.nx)
+
+    def populations(self):
+        return lbm_populations(self.ctx, self.case.ny, self.case.nx)
+
+    def force(self, obj=0):
+        return lbm_force(self.ctx, obj)
+
+    def mass(self):
+        return lbm_mass(self.ctx)
+
+    @property
+    def n_links(self):
+        return len(self.node)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            lbm_sync(self.ctx)
+            lbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "ctx", None) is not None:
+                lbm_destroy(self.ctx)
+                self.ctx = None
+        except Exception:
+            pass

@@ -1,0 +1,548 @@
+// HIP kernels (gfx950) of the D2Q9 BGK step with velocity-interpolation-based
+// bounce-back walls (arXiv:1903.01111).
+//
+// Per time step two launches read the post-collision state A = f+(t):
+//   link kernel  -- one lane per fluid->solid link computes the population that
+//                   streams out of the solid (Section 3.1, VIBB, or halfway
+//                   bounce-back) and writes it into the link's solid-node slot of
+//                   A, where the pull of the bulk kernel picks it up; it also
+//                   reduces the momentum-exchange force in FP64;
+//   bulk kernel  -- one lane per node: pull streaming from A (Section 2,
+//                   evolution equation), moments, BGK collision with Guo forcing,
+//                   store into B; lanes next to an open column also write the
+//                   inlet / outlet column (Section 4.3).
+// Populations are kept as deviations f_i - w_i from the rest state, which keeps
+// FP32 and 16-bit storage accurate at low Mach number; all collision arithmetic
+// is done in that form.
+//
+// The work is HBM-bound (about 2.8 flop per byte in FP32), so the kernels are
+// written for coalescing: SoA planes with rows padded to 64 elements, each
+// 64-lane wavefront covering one aligned run of a row.  No MFMA: nothing here is
+// a dense contraction.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Lattice constants (Section 2).  Velocity order as in the paper's MRT matrix.
+// ---------------------------------------------------------------------------
+constexpr int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+template <class R>
+__device__ constexpr R wgt(int i)
+{
+    return i == 0 ? R(4) / R(9) : (i <= 4 ? R(1) / R(9) : R(1) / R(36));
+}
+
+// runtime-indexed lookups for the link kernel (direction differs per lane):
+// component + 1 packed in two bits per direction
+constexpr uint32_t pack2(const int *c)
+{
+    uint32_t r = 0;
+    for (int i = 0; i < 9; ++i) r |= (uint32_t)(c[i] + 1) << (2 * i);
+    return r;
+}
+constexpr uint32_t PCX = pack2(CX), PCY = pack2(CY);
+__device__ __forceinline__ int cx_of(int i) { return (int)((PCX >> (2 * i)) & 3u) - 1; }
+__device__ __forceinline__ int cy_of(int i) { return (int)((PCY >> (2 * i)) & 3u) - 1; }
+__device__ __forceinline__ int opp_of(int i)
+{
+    return i == 0 ? 0 : (i <= 4 ? ((i + 1) & 3) + 1 : ((i - 3) & 3) + 5);
+}
+
+// ---------------------------------------------------------------------------
+// Storage codecs: value stored = (f - w) [* 2^k for the 16-bit forms].
+// ---------------------------------------------------------------------------
+template <int ST>
+struct Codec;
+
+template <>
+struct Codec<0> {  // LBM_F64
+    using T = double;
+    using R = double;
+    static __device__ __forceinline__ R ld(T v, float) { return v; }
+    static __device__ __forceinline__ T st(R v, float) { return v; }
+};
+
+template <>
+struct Codec<1> {  // LBM_F32
+    using T = float;
+    using R = float;
+    static __device__ __forceinline__ R ld(T v, float) { return v; }
+    static __device__ __forceinline__ T st(R v, float) { return v; }
+};
+
+template <>
+struct Codec<2> {  // LBM_F16_DEV
+    using T = __half;
+    using R = float;
+    static __device__ __forceinline__ R ld(T v, float inv) { return __half2float(v) * inv; }
+    static __device__ __forceinline__ T st(R v, float scale) { return __float2half_rn(v * scale); }
+};
+
+template <>
+struct Codec<3> {  // LBM_BF16_DEV, bits of a bfloat16 in a uint16
+    using T = uint16_t;
+    using R = float;
+    static __device__ __forceinline__ R ld(T v, float inv)
+    {
+        return __uint_as_float((uint32_t)v << 16) * inv;
+    }
+    static __device__ __forceinline__ T st(R v, float scale)
+    {
+        uint32_t u = __float_as_uint(v * scale);
+        if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+        u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+        return (uint16_t)(u >> 16);
+    }
+};
+
+// Equilibrium in deviation form: f^eq_i - w_i = w_i (drho + rho (3 e.u + 9/2 (e.u)^2 - 3/2 u.u))
+template <class R>
+__device__ __forceinline__ R deq(R w, R eu, R drho, R rho, R usq)
+{
+    return w * (drho + rho * (R(3) * eu + R(4.5) * eu * eu - R(1.5) * usq));
+}
+
+// ---------------------------------------------------------------------------
+// Link kernel.
+// ---------------------------------------------------------------------------
+template <int ST>
+__global__ __launch_bounds__(256) void link_kernel(Grid g, Phys ph, typename Codec<ST>::T *__restrict__ A,
+                                                   Links L, double *__restrict__ bank,
+                                                   double *__restrict__ fsum)
+{
+    using C = Codec<ST>;
+    using T = typename C::T;
+    using R = typename C::R;
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = l < L.n;
+    double fx = 0.0, fy = 0.0;
+    int obj = -1;
+    if (active) {
+        const int32_t nf = L.nf[l], nff = L.nff[l], ns = L.ns[l];
+        const uint32_t meta = L.meta[l];
+        const int ip = (int)(meta & 15u), i = opp_of(ip);
+        obj = (int)(meta >> 8);
+        const int cxp = cx_of(ip), cyp = cy_of(ip);
+        const R w = ip <= 4 ? R(1) / R(9) : R(1) / R(36);
+        const R *qv = static_cast<const R *>(L.q);
+        R uwx = R(0), uwy = R(0);
+        if (L.uw) {
+            const R *u = static_cast<const R *>(L.uw);
+            uwx = u[2 * l];
+            uwy = u[2 * l + 1];
+        }
+        // moving-wall momentum term 6 w_{i'} rho0 e_i.u_w, with e_i = -e_{i'}
+        const R wall = -R(6) * w * R(ph.rho0) * (R(cxp) * uwx + R(cyp) * uwy);
+        const T *Aip = A + (int64_t)ip * g.plane;
+        const R fpf = C::ld(Aip[nf], ph.inv_scale);
+        R v;
+        if (nff < 0) {
+            v = fpf + wall;  // halfway bounce-back
+        } else {
+            // moments of f and ff at time t (physical velocity: j/rho - g/2)
+            R drf = R(0), jxf = R(0), jyf = R(0), drff = R(0), jxff = R(0), jyff = R(0);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const R a = C::ld(A[(int64_t)k * g.plane + nf], ph.inv_scale);
+                const R b = C::ld(A[(int64_t)k * g.plane + nff], ph.inv_scale);
+                drf += a;
+                drff += b;
+                jxf += R(CX[k]) * a;
+                jyf += R(CY[k]) * a;
+                jxff += R(CX[k]) * b;
+                jyff += R(CY[k]) * b;
+            }
+            const R fpff = C::ld(Aip[nff], ph.inv_scale);
+            const R rf = R(1) + drf, rff = R(1) + drff;
+            const R hgx = R(0.5) * R(ph.gx), hgy = R(0.5) * R(ph.gy);
+            const R ufx = jxf / rf - hgx, ufy = jyf / rf - hgy;
+            const R uffx = jxff / rff - hgx, uffy = jyff / rff - hgy;
+            const R q = qv[l];
+            const R a2q = R(2) * q, b2q = R(1) - R(2) * q;
+            // density at the departure point d (extrapolated when q > 1/2)
+            const R drd = a2q * drf + b2q * drff;
+            const R rd = R(1) + drd;
+            // non-equilibrium parts at f and ff, interpolated per unit density
+            const R neqf = fpf - deq(w, R(cxp) * ufx + R(cyp) * ufy, drf, rf, ufx * ufx + ufy * ufy);
+            const R neqff = fpff - deq(w, R(cxp) * uffx + R(cyp) * uffy, drff, rff, uffx * uffx + uffy * uffy);
+            const R neqd = rd * (a2q * neqf / rf + b2q * neqff / rff);
+            // velocity at d: u*_d from (f, ff) or (f, wall), u**_d from (ff, wall)
+            R usx, usy;
+            if (q <= R(0.5)) {
+                usx = a2q * ufx + b2q * uffx;
+                usy = a2q * ufy + b2q * uffy;
+            } else {
+                const R cf = (R(1) - q) / q, cw = (R(2) * q - R(1)) / q;
+                usx = cf * ufx + cw * uwx;
+                usy = cf * ufy + cw * uwy;
+            }
+            const R inv1q = R(1) / (R(1) + q);
+            const R cff = (R(1) - q) * inv1q, cww = a2q * inv1q;
+            const R ussx = cff * uffx + cww * uwx, ussy = cff * uffy + cww * uwy;
+            const R udx = (usx + R(2) * ussx) / R(3), udy = (usy + R(2) * ussy) / R(3);
+            v = deq(w, R(cxp) * udx + R(cyp) * udy, drd, rd, udx * udx + udy * udy) + neqd + wall;
+        }
+        A[(int64_t)i * g.plane + ns] = C::st(v, ph.scale);
+        // momentum exchange: f+_{i'}(x_f) into the wall and f_i(x_f) back, both along e_{i'}
+        const double m = (double)fpf + (double)v + 2.0 * (double)w;
+        fx = cxp * m;
+        fy = cyp * m;
+    }
+    // FP64 wavefront reduction; links are sorted by object, so a wavefront
+    // usually holds one object and issues one atomic pair.
+    const int obj0 = __shfl(obj, 0);
+    const bool uniform = __all(obj == obj0 || obj < 0);
+    if (uniform) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            fx += __shfl_xor(fx, off);
+            fy += __shfl_xor(fy, off);
+        }
+        if ((threadIdx.x & 63) == 0 && obj0 >= 0) {
+            unsafeAtomicAdd(&bank[2 * obj0], fx);
+            unsafeAtomicAdd(&bank[2 * obj0 + 1], fy);
+            unsafeAtomicAdd(&fsum[2 * obj0], fx);
+            unsafeAtomicAdd(&fsum[2 * obj0 + 1], fy);
+        }
+    } else if (obj >= 0) {
+        unsafeAtomicAdd(&bank[2 * obj], fx);
+        unsafeAtomicAdd(&bank[2 * obj + 1], fy);
+        unsafeAtomicAdd(&fsum[2 * obj], fx);
+        unsafeAtomicAdd(&fsum[2 * obj + 1], fy);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Bulk kernel: pull, moments, BGK + Guo, store.  Block = 64 x 4 lanes.
+// ---------------------------------------------------------------------------
+constexpr int BX = 64, BY = 4;
+
+template <int ST, bool OPEN, bool FORCE>
+__global__ __launch_bounds__(BX *BY) void bulk_kernel(Grid g, Phys ph,
+                                                      const typename Codec<ST>::T *__restrict__ A,
+                                                      typename Codec<ST>::T *__restrict__ B,
+                                                      const uint8_t *__restrict__ mask,
+                                                      const typename Codec<ST>::R *__restrict__ uin,
+                                                      double *__restrict__ zero_bank, int32_t n_zero)
+{
+    using C = Codec<ST>;
+    using T = typename C::T;
+    using R = typename C::R;
+    {
+        // clear the force bank of the next step
+        const int64_t gt = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * (BX * BY) +
+                           threadIdx.y * BX + threadIdx.x;
+        const int64_t nt = (int64_t)gridDim.x * gridDim.y * (BX * BY);
+        for (int64_t k = gt; k < n_zero; k += nt) zero_bank[k] = 0.0;
+    }
+    const int x = blockIdx.x * BX + threadIdx.x;
+    const int y = blockIdx.y * BY + threadIdx.y;
+    if (x >= g.nx || y >= g.ny) return;
+    if (OPEN && (x == 0 || x == g.nx - 1)) return;
+    const int32_t row = y * g.pitch;
+    if (mask[row + x]) return;
+
+    int xm, xp;
+    if (OPEN) {
+        xm = x - 1;
+        xp = x + 1;
+    } else {
+        xm = x == 0 ? g.nx - 1 : x - 1;
+        xp = x == g.nx - 1 ? 0 : x + 1;
+    }
+    const int32_t rm = (y == 0 ? g.ny - 1 : y - 1) * g.pitch;
+    const int32_t rp = (y == g.ny - 1 ? 0 : y + 1) * g.pitch;
+    const int64_t P = g.plane;
+    const float inv = ph.inv_scale;
+
+    // pull: f_i(x, t+1) = f+_i(x - e_i, t)
+    R f[9];
+    f[0] = C::ld(A[row + x], inv);
+    f[1] = C::ld(A[1 * P + row + xm], inv);
+    f[2] = C::ld(A[2 * P + rm + x], inv);
+    f[3] = C::ld(A[3 * P + row + xp], inv);
+    f[4] = C::ld(A[4 * P + rp + x], inv);
+    f[5] = C::ld(A[5 * P + rm + xm], inv);
+    f[6] = C::ld(A[6 * P + rm + xp], inv);
+    f[7] = C::ld(A[7 * P + rp + xp], inv);
+    f[8] = C::ld(A[8 * P + rp + xm], inv);
+
+    const R drho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+    const R rho = R(1) + drho;
+    const R jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+    const R jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    const R irho = R(1) / rho;
+    R ux = jx * irho, uy = jy * irho;
+    R Fx = R(0), Fy = R(0);
+    if (FORCE) {
+        Fx = rho * R(ph.gx);
+        Fy = rho * R(ph.gy);
+        ux += R(0.5) * R(ph.gx);
+        uy += R(0.5) * R(ph.gy);
+    }
+    const R usq = ux * ux + uy * uy;
+    const R om = R(ph.omega);
+    const R cf = R(1) - R(0.5) * om;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const R w = wgt<R>(i);
+        const R eu = R(CX[i]) * ux + R(CY[i]) * uy;
+        R v = f[i] - om * (f[i] - deq(w, eu, drho, rho, usq));
+        if (FORCE)
+            v += cf * w * ((R(3) * (R(CX[i]) - ux) + R(9) * eu * R(CX[i])) * Fx +
+                           (R(3) * (R(CY[i]) - uy) + R(9) * eu * R(CY[i])) * Fy);
+        f[i] = v;
+        B[i * P + row + x] = C::st(v, ph.scale);
+    }
+    if (OPEN) {
+        if (x == 1 && !mask[row]) {
+            // velocity inlet by non-equilibrium extrapolation:
+            // f+(0) = f^eq(rho_1, u_in) + f+(1) - f^eq(rho_1, u_1)
+            const R vx = uin[2 * y], vy = uin[2 * y + 1];
+            const R vsq = vx * vx + vy * vy;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const R w = wgt<R>(i);
+                const R ev = R(CX[i]) * vx + R(CY[i]) * vy;
+                const R eu = R(CX[i]) * ux + R(CY[i]) * uy;
+                const R d = w * rho * ((R(3) * ev + R(4.5) * ev * ev - R(1.5) * vsq) -
+                                       (R(3) * eu + R(4.5) * eu * eu - R(1.5) * usq));
+                B[i * P + row] = C::st(f[i] + d, ph.scale);
+            }
+        }
+        if (x == g.nx - 2 && !mask[row + g.nx - 1]) {
+            // zero-gradient outlet: copy every population of the last fluid column
+#pragma unroll
+            for (int i = 0; i < 9; ++i) B[i * P + row + g.nx - 1] = C::st(f[i], ph.scale);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Initialisation, moments and mass.
+// ---------------------------------------------------------------------------
+template <int ST>
+__global__ void init_kernel(Grid g, Phys ph, typename Codec<ST>::T *__restrict__ A,
+                            const uint8_t *__restrict__ mask, const double *__restrict__ stage,
+                            int32_t y0, int32_t rows)
+{
+    using C = Codec<ST>;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)rows * g.nx) return;
+    const int y = y0 + (int)(k / g.nx), x = (int)(k % g.nx);
+    const int32_t n = y * g.pitch + x;
+    const bool solid = mask[n] != 0;
+    const double rho = stage[3 * k], ux = stage[3 * k + 1], uy = stage[3 * k + 2];
+    const double usq = ux * ux + uy * uy;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const double eu = CX[i] * ux + CY[i] * uy;
+        const double d = solid ? 0.0 : deq<double>(wgt<double>(i), eu, rho - 1.0, rho, usq);
+        A[(int64_t)i * g.plane + n] = C::st((typename Codec<ST>::R)d, ph.scale);
+    }
+}
+
+template <int ST>
+__global__ void moments_kernel(Grid g, Phys ph, const typename Codec<ST>::T *__restrict__ A,
+                               const uint8_t *__restrict__ mask, double *__restrict__ stage,
+                               int32_t y0, int32_t rows)
+{
+    using C = Codec<ST>;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)rows * g.nx) return;
+    const int y = y0 + (int)(k / g.nx), x = (int)(k % g.nx);
+    const int32_t n = y * g.pitch + x;
+    if (mask[n]) {
+        stage[3 * k] = stage[3 * k + 1] = stage[3 * k + 2] = 0.0;
+        return;
+    }
+    double dr = 0, jx = 0, jy = 0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const double v = (double)C::ld(A[(int64_t)i * g.plane + n], ph.inv_scale);
+        dr += v;
+        jx += CX[i] * v;
+        jy += CY[i] * v;
+    }
+    const double rho = 1.0 + dr;
+    stage[3 * k] = rho;
+    stage[3 * k + 1] = jx / rho - 0.5 * ph.gx;
+    stage[3 * k + 2] = jy / rho - 0.5 * ph.gy;
+}
+
+constexpr int MASS_THREADS = 256;
+
+template <int ST>
+__global__ __launch_bounds__(MASS_THREADS) void mass_kernel(Grid g, Phys ph,
+                                                           const typename Codec<ST>::T *__restrict__ A,
+                                                           const uint8_t *__restrict__ mask,
+                                                           double *__restrict__ partials)
+{
+    using C = Codec<ST>;
+    __shared__ double red[MASS_THREADS / 64];
+    const int64_t N = (int64_t)g.nx * g.ny;
+    double s = 0.0;
+    for (int64_t k = (int64_t)blockIdx.x * MASS_THREADS + threadIdx.x; k < N;
+         k += (int64_t)gridDim.x * MASS_THREADS) {
+        const int y = (int)(k / g.nx), x = (int)(k % g.nx);
+        const int32_t n = y * g.pitch + x;
+        if (mask[n]) continue;
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            s += (double)C::ld(A[(int64_t)i * g.plane + n], ph.inv_scale) + wgt<double>(i);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < MASS_THREADS / 64; ++k) t += red[k];
+        partials[blockIdx.x] = t;
+    }
+}
+
+template <int ST>
+hipError_t link_t(const Grid &g, const Phys &ph, void *A, const Links &L, double *bank, double *fsum,
+                  hipStream_t s)
+{
+    if (L.n == 0) return hipSuccess;
+    const int threads = 256;
+    const unsigned blocks = (unsigned)((L.n + threads - 1) / threads);
+    hipLaunchKernelGGL(link_kernel<ST>, dim3(blocks), dim3(threads), 0, s, g, ph,
+                       static_cast<typename Codec<ST>::T *>(A), L, bank, fsum);
+    return hipGetLastError();
+}
+
+template <int ST, bool OPEN, bool FORCE>
+hipError_t bulk_t(const Grid &g, const Phys &ph, const void *A, void *B, const uint8_t *mask,
+                  const void *uin, double *zb, int32_t nz, hipStream_t s)
+{
+    using C = Codec<ST>;
+    dim3 grid((g.nx + BX - 1) / BX, (g.ny + BY - 1) / BY);
+    hipLaunchKernelGGL((bulk_kernel<ST, OPEN, FORCE>), grid, dim3(BX, BY), 0, s, g, ph,
+                       static_cast<const typename C::T *>(A), static_cast<typename C::T *>(B), mask,
+                       static_cast<const typename C::R *>(uin), zb, nz);
+    return hipGetLastError();
+}
+
+template <int ST>
+hipError_t bulk_dispatch(const Grid &g, const Phys &ph, const void *A, void *B, const uint8_t *mask,
+                         const void *uin, double *zb, int32_t nz, hipStream_t s)
+{
+    const bool force = ph.gx != 0.0 || ph.gy != 0.0;
+    if (g.x_open)
+        return force ? bulk_t<ST, true, true>(g, ph, A, B, mask, uin, zb, nz, s)
+                     : bulk_t<ST, true, false>(g, ph, A, B, mask, uin, zb, nz, s);
+    return force ? bulk_t<ST, false, true>(g, ph, A, B, mask, uin, zb, nz, s)
+                 : bulk_t<ST, false, false>(g, ph, A, B, mask, uin, zb, nz, s);
+}
+
+}  // namespace
+
+hipError_t launch_link(int storage, const Grid &g, const Phys &ph, void *A, const Links &L,
+                       double *bank, double *fsum, hipStream_t s)
+{
+    switch (storage) {
+    case 0: return link_t<0>(g, ph, A, L, bank, fsum, s);
+    case 1: return link_t<1>(g, ph, A, L, bank, fsum, s);
+    case 2: return link_t<2>(g, ph, A, L, bank, fsum, s);
+    case 3: return link_t<3>(g, ph, A, L, bank, fsum, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_bulk(int storage, const Grid &g, const Phys &ph, const void *A, void *B,
+                       const uint8_t *mask, const void *uin, double *zb, int32_t nz, hipStream_t s)
+{
+    switch (storage) {
+    case 0: return bulk_dispatch<0>(g, ph, A, B, mask, uin, zb, nz, s);
+    case 1: return bulk_dispatch<1>(g, ph, A, B, mask, uin, zb, nz, s);
+    case 2: return bulk_dispatch<2>(g, ph, A, B, mask, uin, zb, nz, s);
+    case 3: return bulk_dispatch<3>(g, ph, A, B, mask, uin, zb, nz, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+namespace {
+template <int ST>
+hipError_t init_t(const Grid &g, const Phys &ph, void *A, const uint8_t *mask, const double *stage,
+                  int32_t y0, int32_t rows, hipStream_t s)
+{
+    const int64_t n = (int64_t)rows * g.nx;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(init_kernel<ST>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, ph,
+                       static_cast<typename Codec<ST>::T *>(A), mask, stage, y0, rows);
+    return hipGetLastError();
+}
+template <int ST>
+hipError_t moments_t(const Grid &g, const Phys &ph, const void *A, const uint8_t *mask,
+                     double *stage, int32_t y0, int32_t rows, hipStream_t s)
+{
+    const int64_t n = (int64_t)rows * g.nx;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(moments_kernel<ST>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, ph,
+                       static_cast<const typename Codec<ST>::T *>(A), mask, stage, y0, rows);
+    return hipGetLastError();
+}
+template <int ST>
+hipError_t mass_t(const Grid &g, const Phys &ph, const void *A, const uint8_t *mask,
+                  double *partials, int32_t nb, hipStream_t s)
+{
+    hipLaunchKernelGGL(mass_kernel<ST>, dim3(nb), dim3(MASS_THREADS), 0, s, g, ph,
+                       static_cast<const typename Codec<ST>::T *>(A), mask, partials);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_init(int storage, const Grid &g, const Phys &ph, void *A, const uint8_t *mask,
+                       const double *stage, int32_t y0, int32_t rows, hipStream_t s)
+{
+    switch (storage) {
+    case 0: return init_t<0>(g, ph, A, mask, stage, y0, rows, s);
+    case 1: return init_t<1>(g, ph, A, mask, stage, y0, rows, s);
+    case 2: return init_t<2>(g, ph, A, mask, stage, y0, rows, s);
+    case 3: return init_t<3>(g, ph, A, mask, stage, y0, rows, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_moments(int storage, const Grid &g, const Phys &ph, const void *A,
+                          const uint8_t *mask, double *stage, int32_t y0, int32_t rows, hipStream_t s)
+{
+    switch (storage) {
+    case 0: return moments_t<0>(g, ph, A, mask, stage, y0, rows, s);
+    case 1: return moments_t<1>(g, ph, A, mask, stage, y0, rows, s);
+    case 2: return moments_t<2>(g, ph, A, mask, stage, y0, rows, s);
+    case 3: return moments_t<3>(g, ph, A, mask, stage, y0, rows, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int32_t mass_blocks(const Grid &g)
+{
+    const int64_t N = (int64_t)g.nx * g.ny;
+    int64_t b = (N + MASS_THREADS - 1) / MASS_THREADS;
+    return (int32_t)(b < 1024 ? (b < 1 ? 1 : b) : 1024);
+}
+
+hipError_t launch_mass(int storage, const Grid &g, const Phys &ph, const void *A, const uint8_t *mask,
+                       double *partials, int32_t nb, hipStream_t s)
+{
+    switch (storage) {
+    case 0: return mass_t<0>(g, ph, A, mask, partials, nb, s);
+    case 1: return mass_t<1>(g, ph, A, mask, partials, nb, s);
+    case 2: return mass_t<2>(g, ph, A, mask, partials, nb, s);
+    case 3: return mass_t<3>(g, ph, A, mask, partials, nb, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace lbm

@@ -1,0 +1,946 @@
+// Host runtime of the C ABI declared in include/lbm.h: argument and geometry
+// validation, workspace layout, link preprocessing, the step loop (HIP graph
+// replay of a fixed number of steps), read-back, checkpoints and kernel timing.
+// All arithmetic of a time step runs in the HIP kernels (lbm_kernels.hip).
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_internal.h"
+
+namespace {
+
+thread_local std::string g_thread_error = "no error";
+
+constexpr int EXR[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int EYR[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr int OPPR[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+constexpr double WR[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                          1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+
+constexpr int GRAPH_STEPS = 16;        // steps per captured graph (even)
+constexpr int64_t STAGE_NODES = 1 << 20;  // nodes per read-back / init chunk
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+size_t elem_bytes(int storage)
+{
+    switch (storage) {
+    case LBM_F64: return 8;
+    case LBM_F32: return 4;
+    default: return 2;
+    }
+}
+size_t real_bytes(int storage) { return storage == LBM_F64 ? 8 : 4; }
+
+struct Layout {
+    int32_t pitch;
+    int64_t plane;  // elements per population plane
+    size_t off_A, off_B, off_mask, off_nf, off_nff, off_ns, off_meta, off_q, off_uw, off_uin,
+        off_force, off_partials, off_stage, total;
+};
+
+// Plane stride: rows padded to 64 elements; the plane size in 256-byte units is
+// kept odd so that the nine planes do not start on the same memory channel.
+Layout make_layout(const lbm_params &p, int64_t max_links)
+{
+    Layout L{};
+    const size_t eb = elem_bytes(p.storage), rb = real_bytes(p.storage);
+    L.pitch = (p.nx + 63) / 64 * 64;
+    size_t pb = align256((size_t)L.pitch * p.ny * eb);
+    if ((pb / 256) % 2 == 0) pb += 256;
+    L.plane = (int64_t)(pb / eb);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    L.off_A = take(9 * pb);
+    L.off_B = take(9 * pb);
+    L.off_mask = take((size_t)L.pitch * p.ny);
+    const size_t nl = (size_t)std::max<int64_t>(max_links, 0);
+    L.off_nf = take(nl * 4);
+    L.off_nff = take(nl * 4);
+    L.off_ns = take(nl * 4);
+    L.off_meta = take(nl * 4);
+    L.off_q = take(nl * rb);
+    L.off_uw = take(nl * 2 * rb);
+    L.off_uin = take((size_t)p.ny * 2 * rb);
+    L.off_force = take((size_t)p.n_obj * 6 * sizeof(double));
+    L.off_partials = take(1024 * sizeof(double));
+    L.off_stage = take((size_t)std::min<int64_t>((int64_t)p.nx * p.ny, STAGE_NODES) * 3 *
+                       sizeof(double) + (size_t)p.nx * 3 * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+bool params_ok(const lbm_params *p, std::string *why)
+{
+    char m[256];
+    if (!p) {
+        *why = "null params";
+        return false;
+    }
+    if (p->nx < 1 || p->ny < 1) {
+        *why = "nx and ny must be >= 1";
+        return false;
+    }
+    const int64_t pitch = (p->nx + 63) / 64 * 64;
+    if (pitch * p->ny >= ((int64_t)1 << 31) / 2) {
+        *why = "lattice too large for 32-bit plane offsets";
+        return false;
+    }
+    if (p->x_bc != LBM_X_PERIODIC && p->x_bc != LBM_X_OPEN) {
+        *why = "x_bc must be LBM_X_PERIODIC or LBM_X_OPEN";
+        return false;
+    }
+    if (p->x_bc == LBM_X_OPEN && p->nx < 3) {
+        *why = "an open lattice needs nx >= 3";
+        return false;
+    }
+    if (p->storage < LBM_F64 || p->storage > LBM_BF16_DEV) {
+        *why = "unknown storage";
+        return false;
+    }
+    if (!(p->tau > 0.5) || !std::isfinite(p->tau)) {
+        std::snprintf(m, sizeof m, "tau must be finite and > 1/2 (got %g)", p->tau);
+        *why = m;
+        return false;
+    }
+    if (!std::isfinite(p->gx) || !std::isfinite(p->gy) || !std::isfinite(p->rho0)) {
+        *why = "gx, gy and rho0 must be finite";
+        return false;
+    }
+    if (p->n_obj < 1 || p->n_obj > (1 << 23)) {
+        *why = "n_obj must be in [1, 2^23]";
+        return false;
+    }
+    if (p->dev_scale_log2 < -30 || p->dev_scale_log2 > 30) {
+        *why = "dev_scale_log2 must be in [-30, 30]";
+        return false;
+    }
+    if (p->reserved != 0) {
+        *why = "reserved must be 0";
+        return false;
+    }
+    return true;
+}
+
+struct Prepared {
+    std::vector<int32_t> nf, nff, ns;
+    std::vector<uint32_t> meta;
+    std::vector<double> q, uw;
+    bool has_uw = false;
+    int64_t n_fallback = 0;
+};
+
+// Validates mask and links; on success fills the device-ready link arrays
+// (sorted by object, then node, then direction).
+lbm_status prepare_geometry(const lbm_params &p, const uint8_t *mask, int64_t n, const int32_t *node,
+                            const int8_t *dir, const double *q, const double *uw,
+                            const int32_t *obj, const int8_t *scheme, int32_t pitch, Prepared *out,
+                            std::string *why)
+{
+    char m[256];
+    const int nx = p.nx, ny = p.ny;
+    const bool open = p.x_bc == LBM_X_OPEN;
+    const int64_t N = (int64_t)nx * ny;
+    if (!mask || n < 0 || (n > 0 && (!node || !dir || !q))) {
+        *why = "null mask or link array";
+        return LBM_E_ARG;
+    }
+    for (int64_t k = 0; k < N; ++k)
+        if (mask[k] > 1) {
+            std::snprintf(m, sizeof m, "mask[%lld] = %d is not 0 or 1", (long long)k, mask[k]);
+            *why = m;
+            return LBM_E_GEOM;
+        }
+    if (open)
+        for (int y = 0; y < ny; ++y) {
+            const int64_t r = (int64_t)y * nx;
+            if ((!mask[r] && mask[r + 1]) || (!mask[r + nx - 1] && mask[r + nx - 2])) {
+                std::snprintf(m, sizeof m, "open column node of row %d has a solid neighbour column", y);
+                *why = m;
+                return LBM_E_GEOM;
+            }
+        }
+    std::vector<uint16_t> have((size_t)N, 0);
+    for (int64_t l = 0; l < n; ++l) {
+        const int32_t nd = node[l];
+        const int d = dir[l];
+        if (nd < 0 || nd >= N || d < 1 || d > 8) {
+            std::snprintf(m, sizeof m, "link %lld: node or dir out of range", (long long)l);
+            *why = m;
+            return LBM_E_GEOM;
+        }
+        const int x = nd % nx, y = nd / nx;
+        if (mask[nd] || (open && (x == 0 || x == nx - 1))) {
+            std::snprintf(m, sizeof m, "link %lld: node %d is solid or an open column", (long long)l, nd);
+            *why = m;
+            return LBM_E_GEOM;
+        }
+        int xs = x + EXR[d];
+        if (open && (xs < 0 || xs >= nx)) {
+            std::snprintf(m, sizeof m, "link %lld: leaves the open lattice", (long long)l);
+            *why = m;
+            return LBM_E_GEOM;
+        }
+        xs = (xs + nx) % nx;
+        const int ys = (y + EYR[d] + ny) % ny;
+        if (!mask[(int64_t)ys * nx + xs]) {
+            std::snprintf(m, sizeof m, "link %lld: node %d + e_%d is not solid", (long long)l, nd, d);
+            *why = m;
+            return LBM_E_GEOM;
+        }
+        if (!(q[l] > 0.0 && q[l] <= 1.0)) {
+            std::snprintf(m, sizeof m, "link %lld: q = %g outside (0, 1]", (long long)l, q[l]);
+            *why = m;
+            return LBM_E_GEOM;
+        }
+        if (uw && (!std::isfinite(uw[2 * l]) || !std::isfinite(uw[2 * l + 1]))) {
+            std::snprintf(m, sizeof m, "link %lld: non-finite wall velocity", (long long)l);
+            *why = m;
+            return LBM_E_GEOM;
+        }
+        if (obj && (obj[l] < 0 || obj[l] >= p.n_obj)) {
+            std::snprintf(m, sizeof m, "link %lld: obj %d outside [0, %d)", (long long)l, obj[l], p.n_obj);
+            *why = m;
+            return LBM_E_GEOM;
+        }
+        if (scheme && scheme[l] != LBM_SCHEME_VIBB && scheme[l] != LBM_SCHEME_HBB) {
+            std::snprintf(m, sizeof m, "link %lld: unknown scheme %d", (long long)l, scheme[l]);
+            *why = m;
+            return LBM_E_GEOM;
+        }
+        if (have[nd] & (1u << d)) {
+            std::snprintf(m, sizeof m, "link %lld: duplicate (node %d, dir %d)", (long long)l, nd, d);
+            *why = m;
+            return LBM_E_GEOM;
+        }
+        have[nd] |= (uint16_t)(1u << d);
+    }
+    // every pull from a solid node must be covered by a link
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            const int64_t nd = (int64_t)y * nx + x;
+            if (mask[nd] || (open && (x == 0 || x == nx - 1))) continue;
+            for (int i = 1; i < 9; ++i) {
+                const int xs = (x - EXR[i] + nx) % nx, ys = (y - EYR[i] + ny) % ny;
+                if (mask[(int64_t)ys * nx + xs] && !(have[nd] & (1u << OPPR[i]))) {
+                    std::snprintf(m, sizeof m, "node %lld pulls direction %d from a solid node with no link",
+                                  (long long)nd, i);
+                    *why = m;
+                    return LBM_E_GEOM;
+                }
+            }
+        }
+    if (!out) return LBM_OK;
+    std::vector<int64_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+        const int oa = obj ? obj[a] : 0, ob = obj ? obj[b] : 0;
+        if (oa != ob) return oa < ob;
+        if (node[a] != node[b]) return node[a] < node[b];
+        return dir[a] < dir[b];
+    });
+    out->nf.resize(n);
+    out->nff.resize(n);
+    out->ns.resize(n);
+    out->meta.resize(n);
+    out->q.resize(n);
+    out->has_uw = false;
+    if (uw)
+        for (int64_t l = 0; l < n && !out->has_uw; ++l)
+            out->has_uw = uw[2 * l] != 0.0 || uw[2 * l + 1] != 0.0;
+    out->uw.assign(out->has_uw ? 2 * n : 0, 0.0);
+    out->n_fallback = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t l = order[k];
+        const int nd = node[l], d = dir[l], x = nd % nx, y = nd / nx;
+        const int xs = (x + EXR[d] + nx) % nx, ys = (y + EYR[d] + ny) % ny;
+        int xf2 = x - EXR[d];
+        const int yf2 = (y - EYR[d] + ny) % ny;
+        bool ff_ok = true;
+        if (open && (xf2 < 0 || xf2 >= nx)) ff_ok = false;
+        xf2 = (xf2 + nx) % nx;
+        if (ff_ok && mask[(int64_t)yf2 * nx + xf2]) ff_ok = false;
+        const bool vibb = !scheme || scheme[l] == LBM_SCHEME_VIBB;
+        if (vibb && !ff_ok) ++out->n_fallback;
+        out->nf[k] = y * pitch + x;
+        out->nff[k] = (vibb && ff_ok) ? yf2 * pitch + xf2 : -1;
+        out->ns[k] = ys * pitch + xs;
+        out->meta[k] = (uint32_t)d | ((uint32_t)(obj ? obj[l] : 0) << 8);
+        out->q[k] = q[l];
+        if (out->has_uw) {
+            out->uw[2 * k] = uw[2 * l];
+            out->uw[2 * k + 1] = uw[2 * l + 1];
+        }
+    }
+    return LBM_OK;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+    lbm_params p{};
+    Layout lay{};
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;  // private stream the step graph is captured on
+    std::string err = "no error";
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    int64_t max_links = 0, n_links = 0;
+    bool has_uw = false, have_geom = false, have_init = false;
+    void *cur = nullptr, *nxt = nullptr;
+    int64_t step = 0, nsum = 0;
+    // graph of GRAPH_STEPS steps starting from buffer `graph_cur`
+    hipGraphExec_t gexec = nullptr;
+    void *graph_cur = nullptr;
+    // profiling
+    bool prof = false;
+    std::vector<hipEvent_t> events;
+    size_t ev_used = 0;
+    double link_ms = 0, bulk_ms = 0;
+    int64_t prof_steps = 0;
+
+    lbm::Grid grid() const
+    {
+        return lbm::Grid{p.nx, p.ny, lay.pitch, p.x_bc == LBM_X_OPEN ? 1 : 0, lay.plane};
+    }
+    lbm::Phys phys() const
+    {
+        const float sc = std::ldexp(1.0f, p.storage >= LBM_F16_DEV ? p.dev_scale_log2 : 0);
+        return lbm::Phys{1.0 / p.tau, p.gx, p.gy, p.rho0, sc, 1.0f / sc};
+    }
+    lbm::Links links() const
+    {
+        return lbm::Links{reinterpret_cast<const int32_t *>(ws + lay.off_nf),
+                          reinterpret_cast<const int32_t *>(ws + lay.off_nff),
+                          reinterpret_cast<const int32_t *>(ws + lay.off_ns),
+                          reinterpret_cast<const uint32_t *>(ws + lay.off_meta),
+                          ws + lay.off_q, has_uw ? ws + lay.off_uw : nullptr, n_links};
+    }
+    uint8_t *mask() const { return reinterpret_cast<uint8_t *>(ws + lay.off_mask); }
+    double *force() const { return reinterpret_cast<double *>(ws + lay.off_force); }
+    double *bank(int64_t t) const { return force() + (size_t)(t & 1) * 2 * p.n_obj; }
+    double *fsum() const { return force() + 4 * (size_t)p.n_obj; }
+    double *stage() const { return reinterpret_cast<double *>(ws + lay.off_stage); }
+    double *partials() const { return reinterpret_cast<double *>(ws + lay.off_partials); }
+
+    lbm_status fail(lbm_status s, const char *fmt, ...)
+    {
+        char m[512];
+        va_list ap;
+        va_start(ap, fmt);
+        std::vsnprintf(m, sizeof m, fmt, ap);
+        va_end(ap);
+        err = m;
+        return s;
+    }
+    lbm_status hip(hipError_t e, const char *what)
+    {
+        if (e == hipSuccess) return LBM_OK;
+        return fail(LBM_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+    }
+    void drop_graph()
+    {
+        if (gexec) hipGraphExecDestroy(gexec);
+        gexec = nullptr;
+        graph_cur = nullptr;
+    }
+};
+
+extern "C" void lbm_set_thread_error(const char *msg) { g_thread_error = msg; }
+
+namespace {
+
+lbm_status enqueue_step(lbm_ctx *c, bool timed)
+{
+    const lbm::Grid g = c->grid();
+    const lbm::Phys ph = c->phys();
+    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+    if (timed) {
+        while (c->events.size() < c->ev_used + 3) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return c->fail(LBM_E_DEVICE, "hipEventCreate failed");
+            c->events.push_back(e);
+        }
+        e0 = c->events[c->ev_used];
+        e1 = c->events[c->ev_used + 1];
+        e2 = c->events[c->ev_used + 2];
+        c->ev_used += 3;
+        hipEventRecord(e0, c->stream);
+    }
+    lbm_status s = c->hip(lbm::launch_link(c->p.storage, g, ph, c->cur, c->links(), c->bank(c->step),
+                                           c->fsum(), c->stream), "link kernel launch");
+    if (s) return s;
+    if (timed) hipEventRecord(e1, c->stream);
+    s = c->hip(lbm::launch_bulk(c->p.storage, g, ph, c->cur, c->nxt, c->mask(),
+                                c->ws + c->lay.off_uin, c->bank(c->step + 1), 2 * c->p.n_obj,
+                                c->stream), "bulk kernel launch");
+    if (s) return s;
+    if (timed) hipEventRecord(e2, c->stream);
+    std::swap(c->cur, c->nxt);
+    ++c->step;
+    ++c->nsum;
+    return LBM_OK;
+}
+
+lbm_status collect_times(lbm_ctx *c)
+{
+    if (c->ev_used == 0) return LBM_OK;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return c->fail(LBM_E_DEVICE, "sync failed");
+    for (size_t k = 0; k + 2 < c->ev_used; k += 3) {
+        float a = 0, b = 0;
+        hipEventElapsedTime(&a, c->events[k], c->events[k + 1]);
+        hipEventElapsedTime(&b, c->events[k + 1], c->events[k + 2]);
+        c->link_ms += a;
+        c->bulk_ms += b;
+        ++c->prof_steps;
+    }
+    c->ev_used = 0;
+    return LBM_OK;
+}
+
+// Captures GRAPH_STEPS steps on a private stream (the caller's stream may be the
+// null stream, which cannot be captured); the graph is launched on the caller's
+// stream.
+lbm_status build_graph(lbm_ctx *c)
+{
+    c->drop_graph();
+    if (!c->cap_stream &&
+        hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        c->cap_stream = nullptr;
+        return c->fail(LBM_E_DEVICE, "hipStreamCreateWithFlags failed");
+    }
+    void *start = c->cur;
+    const int64_t step0 = c->step, nsum0 = c->nsum;
+    hipGraph_t graph = nullptr;
+    hipStream_t user = c->stream;
+    c->stream = c->cap_stream;
+    lbm_status s = c->hip(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed),
+                          "hipStreamBeginCapture");
+    if (s) {
+        c->stream = user;
+        return s;
+    }
+    for (int k = 0; k < GRAPH_STEPS && !s; ++k) s = enqueue_step(c, false);
+    hipError_t e = hipStreamEndCapture(c->stream, &graph);
+    c->stream = user;
+    // capture only records; restore the host-side counters
+    c->step = step0;
+    c->nsum = nsum0;
+    if (c->cur != start) std::swap(c->cur, c->nxt);
+    if (s) {
+        if (graph) hipGraphDestroy(graph);
+        return s;
+    }
+    if ((s = c->hip(e, "hipStreamEndCapture"))) return s;
+    e = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if ((s = c->hip(e, "hipGraphInstantiate"))) {
+        c->gexec = nullptr;
+        return s;
+    }
+    c->graph_cur = start;
+    return LBM_OK;
+}
+
+lbm_status check_finite(lbm_ctx *c, const double *v, size_t n, const char *what)
+{
+    for (size_t k = 0; k < n; ++k)
+        if (!std::isfinite(v[k])) return c->fail(LBM_E_UNSTABLE, "non-finite %s read back", what);
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lbm_last_error(const lbm_ctx *ctx)
+{
+    return ctx ? ctx->err.c_str() : g_thread_error.c_str();
+}
+
+lbm_status lbm_check_geometry(const lbm_params *p, const uint8_t *mask, int64_t n_links,
+                              const int32_t *node, const int8_t *dir, const double *q,
+                              const double *uw, const int32_t *obj, const int8_t *scheme,
+                              int64_t *n_fallback)
+{
+    std::string why;
+    if (!params_ok(p, &why)) {
+        g_thread_error = "lbm_check_geometry: " + why;
+        return LBM_E_ARG;
+    }
+    Prepared prep;
+    const int32_t pitch = (p->nx + 63) / 64 * 64;
+    lbm_status s = prepare_geometry(*p, mask, n_links, node, dir, q, uw, obj, scheme, pitch,
+                                    n_fallback ? &prep : nullptr, &why);
+    if (s) {
+        g_thread_error = "lbm_check_geometry: " + why;
+        return s;
+    }
+    if (n_fallback) *n_fallback = prep.n_fallback;
+    return LBM_OK;
+}
+
+size_t lbm_workspace_bytes(const lbm_params *p, int64_t max_links)
+{
+    std::string why;
+    if (!params_ok(p, &why) || max_links < 0) return 0;
+    return make_layout(*p, max_links).total;
+}
+
+lbm_status lbm_create(const lbm_params *p, void *workspace, size_t bytes, lbm_ctx **out)
+{
+    std::string why;
+    if (!out) {
+        g_thread_error = "lbm_create: null output pointer";
+        return LBM_E_ARG;
+    }
+    *out = nullptr;
+    if (!params_ok(p, &why)) {
+        g_thread_error = "lbm_create: " + why;
+        return LBM_E_ARG;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        g_thread_error = "lbm_create: no HIP device available";
+        return LBM_E_DEVICE;
+    }
+    if (p->device < 0 || p->device >= ndev) {
+        g_thread_error = "lbm_create: device ordinal out of range";
+        return LBM_E_ARG;
+    }
+    if (!workspace || ((uintptr_t)workspace & 255)) {
+        g_thread_error = "lbm_create: workspace must be non-null and 256-byte aligned";
+        return LBM_E_ARG;
+    }
+    // largest link capacity the workspace holds
+    const Layout base = make_layout(*p, 0);
+    if (bytes < base.total) {
+        g_thread_error = "lbm_create: workspace too small";
+        return LBM_E_NOMEM;
+    }
+    const size_t per_link = 16 + 3 * real_bytes(p->storage);
+    int64_t cap = (int64_t)((bytes - base.total) / per_link);
+    while (cap > 0 && make_layout(*p, cap).total > bytes) --cap;
+    lbm_ctx *c = new (std::nothrow) lbm_ctx;
+    if (!c) {
+        g_thread_error = "lbm_create: out of host memory";
+        return LBM_E_NOMEM;
+    }
+    c->p = *p;
+    c->lay = make_layout(*p, cap);
+    c->max_links = cap;
+    c->ws = static_cast<char *>(workspace);
+    c->ws_bytes = bytes;
+    c->stream = static_cast<hipStream_t>(p->stream);
+    c->cur = c->ws + c->lay.off_A;
+    c->nxt = c->ws + c->lay.off_B;
+    if (hipSetDevice(p->device) != hipSuccess) {
+        delete c;
+        g_thread_error = "lbm_create: hipSetDevice failed";
+        return LBM_E_DEVICE;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx *c)
+{
+    if (!c) return;
+    c->drop_graph();
+    for (hipEvent_t e : c->events) hipEventDestroy(e);
+    if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+    delete c;
+}
+
+lbm_status lbm_set_geometry(lbm_ctx *c, const uint8_t *mask, int64_t n_links, const int32_t *node,
+                            const int8_t *dir, const double *q, const double *uw, const int32_t *obj,
+                            const int8_t *scheme)
+{
+    if (!c) return LBM_E_ARG;
+    std::string why;
+    Prepared prep;
+    lbm_status s = prepare_geometry(c->p, mask, n_links, node, dir, q, uw, obj, scheme, c->lay.pitch,
+                                    &prep, &why);
+    if (s) return c->fail(s, "lbm_set_geometry: %s", why.c_str());
+    if (n_links > c->max_links)
+        return c->fail(LBM_E_NOMEM, "lbm_set_geometry: %lld links exceed the workspace capacity %lld",
+                       (long long)n_links, (long long)c->max_links);
+    c->drop_graph();
+    const int nx = c->p.nx, ny = c->p.ny;
+    const hipStream_t st = c->stream;
+    // mask rows padded to the pitch (padding marked solid: never streamed)
+    std::vector<uint8_t> m((size_t)c->lay.pitch * ny, 1);
+    for (int y = 0; y < ny; ++y) std::memcpy(&m[(size_t)y * c->lay.pitch], mask + (size_t)y * nx, nx);
+    if ((s = c->hip(hipMemcpyAsync(c->mask(), m.data(), m.size(), hipMemcpyHostToDevice, st),
+                    "mask upload")))
+        return s;
+    const size_t n = (size_t)n_links;
+    const size_t rb = real_bytes(c->p.storage);
+    std::vector<float> qf, uwf;
+    const void *qsrc = prep.q.data(), *uwsrc = prep.uw.data();
+    if (rb == 4) {
+        qf.assign(prep.q.begin(), prep.q.end());
+        uwf.assign(prep.uw.begin(), prep.uw.end());
+        qsrc = qf.data();
+        uwsrc = uwf.data();
+    }
+    struct Up {
+        size_t off;
+        const void *src;
+        size_t bytes;
+    } ups[] = {{c->lay.off_nf, prep.nf.data(), n * 4},   {c->lay.off_nff, prep.nff.data(), n * 4},
+               {c->lay.off_ns, prep.ns.data(), n * 4},   {c->lay.off_meta, prep.meta.data(), n * 4},
+               {c->lay.off_q, qsrc, n * rb},
+               {c->lay.off_uw, uwsrc, prep.has_uw ? 2 * n * rb : 0}};
+    for (const Up &u : ups)
+        if (u.bytes && (s = c->hip(hipMemcpyAsync(c->ws + u.off, u.src, u.bytes,
+                                                  hipMemcpyHostToDevice, st), "link upload")))
+            return s;
+    // both population buffers start at zero (solid slots included)
+    if ((s = c->hip(hipMemsetAsync(c->ws + c->lay.off_A, 0, c->lay.off_mask - c->lay.off_A, st),
+                    "population clear")))
+        return s;
+    if ((s = c->hip(hipMemsetAsync(c->force(), 0, (size_t)c->p.n_obj * 6 * sizeof(double), st),
+                    "force clear")))
+        return s;
+    if ((s = c->hip(hipStreamSynchronize(st), "geometry upload")))  // host vectors die here
+        return s;
+    c->n_links = n_links;
+    c->has_uw = prep.has_uw;
+    c->have_geom = true;
+    c->have_init = false;
+    c->cur = c->ws + c->lay.off_A;
+    c->nxt = c->ws + c->lay.off_B;
+    c->step = 0;
+    c->nsum = 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_inlet(lbm_ctx *c, const double *ux, const double *uy)
+{
+    if (!c) return LBM_E_ARG;
+    const int ny = c->p.ny;
+    std::vector<double> v((size_t)2 * ny, 0.0);
+    for (int y = 0; y < ny; ++y) {
+        v[2 * y] = ux ? ux[y] : 0.0;
+        v[2 * y + 1] = uy ? uy[y] : 0.0;
+        if (!std::isfinite(v[2 * y]) || !std::isfinite(v[2 * y + 1]))
+            return c->fail(LBM_E_ARG, "lbm_set_inlet: non-finite velocity in row %d", y);
+    }
+    lbm_status s;
+    if (real_bytes(c->p.storage) == 4) {
+        std::vector<float> f(v.begin(), v.end());
+        s = c->hip(hipMemcpyAsync(c->ws + c->lay.off_uin, f.data(), f.size() * 4,
+                                  hipMemcpyHostToDevice, c->stream), "inlet upload");
+        if (!s) s = c->hip(hipStreamSynchronize(c->stream), "inlet upload");
+    } else {
+        s = c->hip(hipMemcpyAsync(c->ws + c->lay.off_uin, v.data(), v.size() * 8,
+                                  hipMemcpyHostToDevice, c->stream), "inlet upload");
+        if (!s) s = c->hip(hipStreamSynchronize(c->stream), "inlet upload");
+    }
+    return s;
+}
+
+lbm_status lbm_init_equilibrium(lbm_ctx *c, const double *rho, const double *ux, const double *uy)
+{
+    if (!c) return LBM_E_ARG;
+    if (!c->have_geom) return c->fail(LBM_E_STATE, "lbm_init_equilibrium before lbm_set_geometry");
+    c->drop_graph();
+    const int nx = c->p.nx, ny = c->p.ny;
+    const int rows_per = (int)std::max<int64_t>(1, STAGE_NODES / nx);
+    std::vector<double> h;
+    lbm_status s;
+    for (int y0 = 0; y0 < ny; y0 += rows_per) {
+        const int rows = std::min(rows_per, ny - y0);
+        h.assign((size_t)3 * rows * nx, 0.0);
+        for (int64_t k = 0; k < (int64_t)rows * nx; ++k) {
+            const int64_t n = (int64_t)y0 * nx + k;
+            h[3 * k] = rho ? rho[n] : c->p.rho0;
+            h[3 * k + 1] = ux ? ux[n] : 0.0;
+            h[3 * k + 2] = uy ? uy[n] : 0.0;
+            if (!std::isfinite(h[3 * k]) || !std::isfinite(h[3 * k + 1]) || !std::isfinite(h[3 * k + 2]))
+                return c->fail(LBM_E_ARG, "lbm_init_equilibrium: non-finite value at node %lld",
+                               (long long)n);
+        }
+        if ((s = c->hip(hipMemcpyAsync(c->stage(), h.data(), h.size() * 8, hipMemcpyHostToDevice,
+                                       c->stream), "init upload")))
+            return s;
+        if ((s = c->hip(lbm::launch_init(c->p.storage, c->grid(), c->phys(), c->cur, c->mask(),
+                                         c->stage(), y0, rows, c->stream), "init kernel")))
+            return s;
+        if ((s = c->hip(hipStreamSynchronize(c->stream), "init")))  // h is reused
+            return s;
+    }
+    c->have_init = true;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx *c, int64_t n)
+{
+    if (!c) return LBM_E_ARG;
+    if (n < 0) return c->fail(LBM_E_ARG, "lbm_step: negative step count");
+    if (!c->have_geom || !c->have_init)
+        return c->fail(LBM_E_STATE, "lbm_step before lbm_set_geometry and initialisation");
+    lbm_status s;
+    if (c->prof) {
+        for (int64_t k = 0; k < n; ++k)
+            if ((s = enqueue_step(c, true))) return s;
+        if (c->ev_used > 3 * 256) return collect_times(c);
+        return LBM_OK;
+    }
+    while (n > 0) {
+        if (n >= GRAPH_STEPS) {
+            if (!c->gexec || c->graph_cur != c->cur) {
+                if ((s = build_graph(c))) return s;
+            }
+            if ((s = c->hip(hipGraphLaunch(c->gexec, c->stream), "hipGraphLaunch"))) return s;
+            c->step += GRAPH_STEPS;
+            c->nsum += GRAPH_STEPS;  // GRAPH_STEPS is even: buffers return to their roles
+            n -= GRAPH_STEPS;
+        } else {
+            if ((s = enqueue_step(c, false))) return s;
+            --n;
+        }
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_sync(lbm_ctx *c)
+{
+    if (!c) return LBM_E_ARG;
+    return c->hip(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+}
+
+int64_t lbm_step_count(const lbm_ctx *c) { return c ? c->step : -1; }
+
+lbm_status lbm_moments(lbm_ctx *c, double *rho, double *ux, double *uy)
+{
+    if (!c) return LBM_E_ARG;
+    if (!c->have_geom || !c->have_init) return c->fail(LBM_E_STATE, "lbm_moments before initialisation");
+    const int nx = c->p.nx, ny = c->p.ny;
+    const int rows_per = (int)std::max<int64_t>(1, STAGE_NODES / nx);
+    std::vector<double> h;
+    lbm_status s;
+    for (int y0 = 0; y0 < ny; y0 += rows_per) {
+        const int rows = std::min(rows_per, ny - y0);
+        h.resize((size_t)3 * rows * nx);
+        if ((s = c->hip(lbm::launch_moments(c->p.storage, c->grid(), c->phys(), c->cur, c->mask(),
+                                            c->stage(), y0, rows, c->stream), "moments kernel")))
+            return s;
+        if ((s = c->hip(hipMemcpyAsync(h.data(), c->stage(), h.size() * 8, hipMemcpyDeviceToHost,
+                                       c->stream), "moments read-back")))
+            return s;
+        if ((s = c->hip(hipStreamSynchronize(c->stream), "moments"))) return s;
+        if ((s = check_finite(c, h.data(), h.size(), "moment"))) return s;
+        for (int64_t k = 0; k < (int64_t)rows * nx; ++k) {
+            const int64_t n = (int64_t)y0 * nx + k;
+            if (rho) rho[n] = h[3 * k];
+            if (ux) ux[n] = h[3 * k + 1];
+            if (uy) uy[n] = h[3 * k + 2];
+        }
+    }
+    return LBM_OK;
+}
+
+namespace {
+double half_to_double(uint16_t h)
+{
+    const int sgn = h >> 15, ex = (h >> 10) & 31, man = h & 1023;
+    double v;
+    if (ex == 0) v = std::ldexp((double)man, -24);
+    else if (ex == 31) v = man ? NAN : INFINITY;
+    else v = std::ldexp((double)(man | 1024), ex - 25);
+    return sgn ? -v : v;
+}
+double bf16_to_double(uint16_t b)
+{
+    uint32_t u = (uint32_t)b << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+}  // namespace
+
+lbm_status lbm_populations(lbm_ctx *c, double *f)
+{
+    if (!c || !f) return LBM_E_ARG;
+    if (!c->have_geom || !c->have_init) return c->fail(LBM_E_STATE, "lbm_populations before initialisation");
+    const int nx = c->p.nx, ny = c->p.ny, pitch = c->lay.pitch;
+    const size_t eb = elem_bytes(c->p.storage);
+    const double inv = std::ldexp(1.0, c->p.storage >= LBM_F16_DEV ? -c->p.dev_scale_log2 : 0);
+    std::vector<uint8_t> mask((size_t)pitch * ny);
+    std::vector<char> plane((size_t)pitch * ny * eb);
+    lbm_status s;
+    if ((s = c->hip(hipMemcpy(mask.data(), c->mask(), mask.size(), hipMemcpyDeviceToHost), "mask read")))
+        return s;
+    if ((s = c->hip(hipStreamSynchronize(c->stream), "populations"))) return s;
+    for (int i = 0; i < 9; ++i) {
+        const char *src = static_cast<const char *>(c->cur) + (size_t)i * c->lay.plane * eb;
+        if ((s = c->hip(hipMemcpy(plane.data(), src, plane.size(), hipMemcpyDeviceToHost), "plane read")))
+            return s;
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const size_t k = (size_t)y * pitch + x;
+                double d;
+                switch (c->p.storage) {
+                case LBM_F64: std::memcpy(&d, &plane[k * 8], 8); break;
+                case LBM_F32: {
+                    float v;
+                    std::memcpy(&v, &plane[k * 4], 4);
+                    d = v;
+                    break;
+                }
+                case LBM_F16_DEV: {
+                    uint16_t v;
+                    std::memcpy(&v, &plane[k * 2], 2);
+                    d = half_to_double(v) * inv;
+                    break;
+                }
+                default: {
+                    uint16_t v;
+                    std::memcpy(&v, &plane[k * 2], 2);
+                    d = bf16_to_double(v) * inv;
+                }
+                }
+                f[((size_t)y * nx + x) * 9 + i] = mask[k] ? 0.0 : d + WR[i];
+            }
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_force(lbm_ctx *c, int32_t obj, double last[2], double sum[2], int64_t *nsum)
+{
+    if (!c) return LBM_E_ARG;
+    if (obj < 0 || obj >= c->p.n_obj) return c->fail(LBM_E_ARG, "lbm_force: obj %d out of range", obj);
+    double h[4] = {0, 0, 0, 0};
+    lbm_status s;
+    if (c->step > 0 &&
+        (s = c->hip(hipMemcpyAsync(h, c->bank(c->step - 1) + 2 * obj, 16, hipMemcpyDeviceToHost,
+                                   c->stream), "force read")))
+        return s;
+    if ((s = c->hip(hipMemcpyAsync(h + 2, c->fsum() + 2 * obj, 16, hipMemcpyDeviceToHost, c->stream),
+                    "force read")))
+        return s;
+    if ((s = c->hip(hipStreamSynchronize(c->stream), "force read"))) return s;
+    if ((s = check_finite(c, h, 4, "force"))) return s;
+    if (last) last[0] = h[0], last[1] = h[1];
+    if (sum) sum[0] = h[2], sum[1] = h[3];
+    if (nsum) *nsum = c->nsum;
+    return LBM_OK;
+}
+
+lbm_status lbm_force_reset(lbm_ctx *c)
+{
+    if (!c) return LBM_E_ARG;
+    lbm_status s = c->hip(hipMemsetAsync(c->fsum(), 0, (size_t)c->p.n_obj * 2 * sizeof(double), c->stream),
+                          "force reset");
+    if (s) return s;
+    c->nsum = 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_mass(lbm_ctx *c, double *m)
+{
+    if (!c || !m) return LBM_E_ARG;
+    if (!c->have_geom || !c->have_init) return c->fail(LBM_E_STATE, "lbm_mass before initialisation");
+    const int nb = lbm::mass_blocks(c->grid());
+    std::vector<double> h(nb);
+    lbm_status s;
+    if ((s = c->hip(lbm::launch_mass(c->p.storage, c->grid(), c->phys(), c->cur, c->mask(), c->partials(),
+                                     nb, c->stream), "mass kernel")))
+        return s;
+    if ((s = c->hip(hipMemcpyAsync(h.data(), c->partials(), nb * 8, hipMemcpyDeviceToHost, c->stream),
+                    "mass read")))
+        return s;
+    if ((s = c->hip(hipStreamSynchronize(c->stream), "mass"))) return s;
+    double t = 0;
+    for (double v : h) t += v;
+    if (!std::isfinite(t)) return c->fail(LBM_E_UNSTABLE, "non-finite mass");
+    *m = t;
+    return LBM_OK;
+}
+
+size_t lbm_state_bytes(const lbm_ctx *c)
+{
+    if (!c) return 0;
+    return 9 * (size_t)c->lay.plane * elem_bytes(c->p.storage) + 6 * (size_t)c->p.n_obj * sizeof(double) +
+           2 * sizeof(int64_t);
+}
+
+lbm_status lbm_get_state(lbm_ctx *c, void *host, size_t bytes)
+{
+    if (!c || !host) return LBM_E_ARG;
+    if (bytes < lbm_state_bytes(c)) return c->fail(LBM_E_ARG, "lbm_get_state: buffer too small");
+    if (!c->have_geom || !c->have_init) return c->fail(LBM_E_STATE, "lbm_get_state before initialisation");
+    char *h = static_cast<char *>(host);
+    const size_t pb = 9 * (size_t)c->lay.plane * elem_bytes(c->p.storage);
+    int64_t hdr[2] = {c->step, c->nsum};
+    std::memcpy(h, hdr, sizeof hdr);
+    lbm_status s;
+    if ((s = c->hip(hipStreamSynchronize(c->stream), "state"))) return s;
+    if ((s = c->hip(hipMemcpy(h + sizeof hdr, c->cur, pb, hipMemcpyDeviceToHost), "state read"))) return s;
+    return c->hip(hipMemcpy(h + sizeof hdr + pb, c->force(), 6 * (size_t)c->p.n_obj * 8,
+                            hipMemcpyDeviceToHost), "state read");
+}
+
+lbm_status lbm_set_state(lbm_ctx *c, const void *host, size_t bytes)
+{
+    if (!c || !host) return LBM_E_ARG;
+    if (!c->have_geom) return c->fail(LBM_E_STATE, "lbm_set_state before lbm_set_geometry");
+    if (bytes < lbm_state_bytes(c)) return c->fail(LBM_E_ARG, "lbm_set_state: buffer too small");
+    c->drop_graph();
+    const char *h = static_cast<const char *>(host);
+    const size_t pb = 9 * (size_t)c->lay.plane * elem_bytes(c->p.storage);
+    int64_t hdr[2];
+    std::memcpy(hdr, h, sizeof hdr);
+    lbm_status s;
+    if ((s = c->hip(hipStreamSynchronize(c->stream), "state"))) return s;
+    // the step parity selects the buffer roles and the force bank
+    c->cur = c->ws + ((hdr[0] & 1) ? c->lay.off_B : c->lay.off_A);
+    c->nxt = c->ws + ((hdr[0] & 1) ? c->lay.off_A : c->lay.off_B);
+    if ((s = c->hip(hipMemcpy(c->cur, h + sizeof hdr, pb, hipMemcpyHostToDevice), "state write"))) return s;
+    if ((s = c->hip(hipMemcpy(c->force(), h + sizeof hdr + pb, 6 * (size_t)c->p.n_obj * 8,
+                              hipMemcpyHostToDevice), "state write")))
+        return s;
+    c->step = hdr[0];
+    c->nsum = hdr[1];
+    c->have_init = true;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_profiling(lbm_ctx *c, int32_t on)
+{
+    if (!c) return LBM_E_ARG;
+    lbm_status s = collect_times(c);
+    if (s) return s;
+    c->prof = on != 0;
+    c->link_ms = c->bulk_ms = 0;
+    c->prof_steps = 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_kernel_times(lbm_ctx *c, double *link_ms, double *bulk_ms, int64_t *n_steps)
+{
+    if (!c) return LBM_E_ARG;
+    lbm_status s = collect_times(c);
+    if (s) return s;
+    if (link_ms) *link_ms = c->link_ms;
+    if (bulk_ms) *bulk_ms = c->bulk_ms;
+    if (n_steps) *n_steps = c->prof_steps;
+    return LBM_OK;
+}
+
+}  // extern "C"

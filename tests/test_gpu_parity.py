@@ -1,0 +1,219 @@
+"""GPU parity: the HIP library against the FP64 CPU oracle on the same seeded
+inputs, called through the C ABI.
+
+Tolerances:
+* FP64 storage: populations within 1e-13 absolute, velocity e_u <= 1e-11 (the
+  two sides differ only in summation order and in the deviation form f - w);
+* FP32 storage: e_u = max|u_gpu - u_ref| / max|u_ref| <= 1e-5 after 1000 steps
+  (the stated bound of the method's FP32 form), forces within 1e-5 relative.
+The library computes its own geometry; its agreement with the oracle's geometry
+is checked on the CPU (test_abi.py)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1903_01111_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1903_01111_amd import binding
+    binding.lib()
+    return binding
+
+
+def e_u(u, v, ur, vr):
+    ref = max(np.abs(ur).max(), np.abs(vr).max())
+    return max(np.abs(u - ur).max(), np.abs(v - vr).max()) / ref
+
+
+def compare(B, case, storage, nsteps, tol_u, tol_f=None, tol_pop=None, chunks=None):
+    lat = B.Lattice(case, storage=storage)
+    print(f"[parity] {case.name} {storage} {nsteps} steps links={lat.n_links}", flush=True)
+    if chunks:
+        for c in chunks:
+            lat.step(c)
+    else:
+        lat.step(nsteps)
+    rho, ux, uy = lat.moments()
+    fp, g, fs, _, _ = oracle.run_case(case, nsteps=nsteps)
+    rr, uxr, uyr = oracle.moments(fp, g.solid, (case.gx, case.gy))
+    err = e_u(ux, uy, uxr, uyr)
+    fl = g.solid == 0
+    drho = np.abs(rho - rr)[fl].max()
+    out = dict(e_u=err, drho=drho)
+    if tol_pop is not None:
+        f = lat.populations()
+        out["pop"] = np.abs(f - fp).max()
+        assert out["pop"] <= tol_pop, out
+    if tol_f is not None and len(g.node):
+        for o in range(case.n_obj):
+            last, s, n = lat.force(o)
+            assert n == nsteps
+            ref = fs[o]
+            scale = max(np.abs(ref).max(), 1e-300)
+            out[f"force{o}"] = np.abs(s - ref).max() / scale
+            assert out[f"force{o}"] <= tol_f, out
+    lat.close()
+    print(f"[parity] {case.name} {storage}: {out}", flush=True)
+    assert err <= tol_u, out
+    assert drho <= 10 * tol_u, out
+    return out
+
+
+def small_channel(**kw):
+    return W.perturb(W.poiseuille_channel(**kw), seed=1, amp_rho=1e-3, amp_u=1e-3)
+
+
+def small_cylinder(nx=192, ny=64, r=7.3, re=100.0):
+    c = W.cylinder_channel(nx=nx, ny=ny, radius=r, centre=(nx / 4, ny / 2), re=re, seed=4)
+    return c
+
+
+def small_porous(nx=160, ny=96, seed=2):
+    c = W.porous_medium(nx=nx, ny=ny, rmin=3.0, rmax=7.0, seed=seed, tau=0.7, g=1e-5)
+    return W.perturb(c, seed=seed, amp_rho=1e-3, amp_u=1e-3)
+
+
+def spinning(nx=100, ny=37):
+    """Ragged sizes (not multiples of 64), moving and spinning walls, two objects."""
+    prims = [W.Prim(W.PRIM_DISC, cx=30.3, cy=18.7, r=6.6, omega=0.002, obj=0),
+             W.Prim(W.PRIM_DISC, cx=71.9, cy=3.1, r=5.05, ux=-0.01, uy=0.005, obj=1)]
+    c = W.Case(f"spinning_{nx}x{ny}", nx, ny, False, 0.65, gx=2e-6, gy=-1e-6, prims=prims, n_obj=2)
+    return W.perturb(c, seed=7, amp_rho=2e-3, amp_u=2e-3)
+
+
+# --- FP64: the kernels reproduce the oracle to round-off --------------------
+
+@pytest.mark.parametrize("case", [
+    lambda: small_channel(),                      # the 64 x 32 channel, q = 0.3
+    lambda: small_channel(nx=1, ny_fluid=40, q=0.77, u_top=0.01),
+    lambda: small_cylinder(),
+    lambda: small_porous(),
+    lambda: spinning(),
+    lambda: W.walled_cylinder(160, 60.0, 0.37, 0.61),
+], ids=["channel", "column", "cylinder", "porous", "spinning_ragged", "walled_cylinder"])
+def test_fp64_matches_oracle(B, case):
+    compare(B, case(), "f64", 300, tol_u=1e-11, tol_f=1e-10, tol_pop=1e-13)
+
+
+def test_fp64_graph_and_plain_steps_agree(B):
+    """37 steps as graph replays (16 + 16) plus plain launches, in uneven chunks."""
+    compare(B, small_porous(96, 64, seed=5), "f64", 37, tol_u=1e-11, tol_f=1e-10, tol_pop=1e-13,
+            chunks=[5, 16, 3, 13])
+
+
+# --- FP32: the method's stated bound after 1000 steps -----------------------
+
+@pytest.mark.parametrize("case", [
+    lambda: small_channel(),
+    lambda: small_cylinder(),
+    lambda: small_porous(),
+    lambda: spinning(),
+    lambda: W.walled_cylinder(160, 60.0, 0.37, 0.61),
+], ids=["channel", "cylinder", "porous", "spinning_ragged", "walled_cylinder"])
+def test_fp32_matches_oracle_after_1000_steps(B, case):
+    compare(B, case(), "f32", 1000, tol_u=1e-5, tol_f=1e-5)
+
+
+# --- properties -----------------------------------------------------------------
+
+def test_rest_state_is_fixed_on_gpu(B):
+    case = W.porous_medium(nx=128, ny=64, rmin=3, rmax=6, seed=8, g=0.0)
+    for storage in ("f64", "f32", "f16", "bf16"):
+        lat = B.Lattice(case, storage=storage)
+        lat.step(50)
+        rho, ux, uy = lat.moments()
+        fl = lat.mask == 0
+        assert np.abs(rho[fl] - 1).max() == 0 and np.abs(ux).max() == 0 and np.abs(uy).max() == 0
+        lat.close()
+
+
+def test_mass_and_balance_on_gpu(B):
+    """GPU mass (FP64 reduction) against the oracle; halfway bounce-back conserves it."""
+    case = small_porous(96, 64, seed=9)
+    lat = B.Lattice(case, storage="f64")
+    m0 = lat.mass()
+    lat.step(20)
+    m1 = lat.mass()
+    fp, g, _, _, _ = oracle.run_case(case, nsteps=20)
+    assert abs(m1 - oracle.mass(fp, g.solid)) < 1e-10
+    lat.close()
+    mask, node, d, q, uw, obj, _ = B.case_geometry(case)
+    lat = B.Lattice(case, storage="f64",
+                    geometry=(mask, node, d, q, uw, obj, np.ones(len(node), np.int8)))
+    m0 = lat.mass()
+    lat.step(20)
+    assert abs(lat.mass() - m0) < 1e-11
+    lat.close()
+
+
+def test_checkpoint_resume_is_bitwise(B):
+    case = small_cylinder(128, 48, 5.2)
+    a = B.Lattice(case, storage="f32")
+    a.step(21)
+    st = B.lbm_get_state(a.ctx)
+    a.step(19)
+    fa = a.populations()
+    la, sa, na = a.force()
+    b = B.Lattice(case, storage="f32")
+    B.lbm_set_state(b.ctx, st)
+    assert B.lbm_step_count(b.ctx) == 21
+    b.step(19)
+    fb = b.populations()
+    lb, sb, nb = b.force()
+    assert np.array_equal(fa, fb)
+    assert np.array_equal(la, lb) and na == nb == 40
+    assert np.abs(sa - sb).max() <= 1e-12 * np.abs(sa).max()  # atomics change summation order
+    a.close()
+    b.close()
+
+
+def test_profiling_mode_matches_graph_mode(B):
+    case = small_porous(128, 64, seed=11)
+    a = B.Lattice(case, storage="f32")
+    a.step(40)
+    b = B.Lattice(case, storage="f32")
+    B.lbm_set_profiling(b.ctx, True)
+    b.step(40)
+    link_ms, bulk_ms, n = B.lbm_kernel_times(b.ctx)
+    assert n == 40 and bulk_ms > 0 and link_ms > 0
+    assert np.array_equal(a.populations(), b.populations())
+    a.close()
+    b.close()
+
+
+def test_lattice_without_walls(B):
+    """No links at all: a periodic shear wave, FP64."""
+    ny, nx = 48, 70
+    y = np.arange(ny)[:, None] * np.ones((1, nx))
+    c = W.Case("wave", nx, ny, False, 0.9, init_ux=1e-3 * np.sin(2 * np.pi * y / ny))
+    compare(B, c, "f64", 200, tol_u=1e-11, tol_pop=1e-13)
+
+
+def test_state_errors_through_abi(B):
+    case = small_cylinder(64, 32, 4.0)
+    lat = B.Lattice(case, storage="f32")
+    with pytest.raises(B.LbmError) as e:
+        lat.force(3)
+    assert e.value.status == B.LBM_E_ARG
+    with pytest.raises(B.LbmError) as e:
+        B.lbm_step(lat.ctx, -1)
+    assert e.value.status == B.LBM_E_ARG
+    lat.close()
+
+
+# --- full-size workloads, a few steps against the oracle at full size -----------
+
+@pytest.mark.parametrize("which", ["cylinder_2048x512", "porous_8192x2048"])
+def test_full_size_workloads_short(B, which):
+    if which.startswith("cylinder"):
+        case, n = W.cylinder_channel(), 20
+    else:
+        case, n = W.porous_medium(), 3
+    compare(B, case, "f32", n, tol_u=1e-5, tol_f=1e-5)
