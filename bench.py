@@ -1,0 +1,221 @@
+#!/usr/bin/env python3
+"""Throughput of the D2Q9 BGK + VIBB time step on one MI355X.
+
+One step = one pass of the whole hot path over the lattice: the boundary-link
+kernel (velocity-interpolation-based bounce-back for every fluid->solid link and
+the momentum-exchange force) and the fused pull-stream / BGK-collision kernel.
+
+Default workload: the random porous medium, 8192 x 2048 nodes, discs of radius
+U[5,15] to porosity 0.6, body force 1e-6, tau = 0.7, FP32 storage -- the one
+workload whose working set (about 1.2 GB) exceeds the 256 MB last-level cache,
+so its bandwidth is an HBM figure.
+
+Prints ONE JSON line: MLUPS over the timed steps, the HBM roofline of the bulk
+kernel (durations from HIP events recorded around every launch on the stream the
+kernels run on), and the FP64 CPU oracle timed on a bounded sample of the same
+workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1903_01111_amd", "csrc", "lbm_kernels.hip")
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "bulk_kernel_porous_8192x2048_f32_counters.txt")
+METRIC = ("MLUPS + % HBM roofline at stated drag/velocity error; "
+          "FP16-store & adjoint vs FP32")
+BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+
+
+def kernel_hash():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:12]
+
+
+def counter_traffic():
+    """HBM bytes per bulk launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    if not os.path.exists(COUNTER_SUMMARY):
+        return None
+    txt = open(COUNTER_SUMMARY).read()
+    m = dict(re.findall(r"^(\w+):\s*(\S+)", txt, flags=re.M))
+    if m.get("kernel_source_sha256_12") != kernel_hash():
+        return None
+    try:
+        return float(m["hbm_bytes_per_bulk_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def workload(name):
+    from paper_1903_01111_amd import workloads as W
+    if name == "porous":
+        return W.porous_medium()
+    if name == "cylinder":
+        return W.cylinder_channel()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def algorithmic_bytes(case, mask, n_links, n_vibb, storage):
+    """Bytes the method must move per launch (no cache reuse assumed beyond one
+    read of every input and one write of every output):
+    bulk: 9 loads + 9 stores per fluid node, 1 mask byte per node, plus the two
+          open columns written again; link: per link 16 B of indices, q (and u_w),
+          the populations of f and ff (9 + 9 for VIBB, 1 for halfway bounce-back)
+          and one store."""
+    s = BYTES[storage]
+    rb = 8 if storage == "f64" else 4
+    n = case.nx * case.ny
+    nf = int((mask == 0).sum())
+    bulk = nf * 18 * s + n
+    if case.x_open:
+        bulk += 2 * case.ny * 9 * s
+    link = n_links * (16 + rb + s) + n_vibb * 18 * s + (n_links - n_vibb) * s
+    return bulk, link
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="porous", choices=["porous", "cylinder"])
+    ap.add_argument("--storage", default="f32", choices=list(BYTES))
+    ap.add_argument("--cpu-steps", type=int, default=4,
+                    help="oracle steps on the full lattice for the CPU baseline (0: skip)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one 1 GiB device copy (counter calibration under rocprofv3)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part "
+                                   "of it (the lattice would be split into y-slabs with halo "
+                                   "exchange, which is not implemented)", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1903_01111_amd import binding as B
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    t_setup = time.perf_counter()
+    case = workload(args.workload)
+    lat = B.Lattice(case, storage=args.storage)
+    n_nodes = case.nx * case.ny
+    n_fluid = int((lat.mask == 0).sum())
+    nfb = B.lbm_check_geometry(lat.params, lat.mask, lat.node, lat.dir, lat.q, lat.uw, lat.obj,
+                               lat.scheme)
+    n_hbb = int((lat.scheme == 1).sum()) if lat.scheme is not None else 0
+    n_vibb = lat.n_links - n_hbb - nfb
+    print(f"[bench] {case.name}: {n_nodes} nodes, {n_fluid} fluid, {lat.n_links} links "
+          f"({nfb} fall back to halfway bounce-back), storage {args.storage}, "
+          f"setup {time.perf_counter() - t_setup:.1f}s", file=sys.stderr, flush=True)
+
+    if args.calibrate_copy:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    lat.step(args.warmup)
+    lat.sync()
+    rho, ux, uy = lat.moments()  # raises LBM_E_UNSTABLE on a non-finite state
+    torch.cuda.synchronize()
+
+    # timed region: every launch bracketed by HIP events on the kernels' stream
+    B.lbm_set_profiling(lat.ctx, True)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    ev0.record()
+    lat.step(args.steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = ev0.elapsed_time(ev1)
+    link_ms, bulk_ms, n_timed = B.lbm_kernel_times(lat.ctx)
+    B.lbm_set_profiling(lat.ctx, False)
+    assert n_timed == args.steps
+    _, fsum, nsum = lat.force(0)
+    lat.moments()  # finite check after the timed steps
+
+    mlups = n_nodes * args.steps / (ms * 1e-3) / 1e6
+    bulk_bytes, link_bytes = algorithmic_bytes(case, lat.mask, lat.n_links, n_vibb, args.storage)
+    bulk_avg_s = bulk_ms * 1e-3 / args.steps
+    link_avg_s = link_ms * 1e-3 / args.steps
+    achieved = bulk_bytes / bulk_avg_s / 1e9
+    print(f"[bench] {args.steps} steps in {ms:.1f} ms (wall {wall:.2f}s): {mlups:.0f} MLUPS; "
+          f"bulk {bulk_avg_s * 1e6:.1f} us/launch = {achieved:.0f} GB/s; link "
+          f"{link_avg_s * 1e6:.1f} us/launch", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.storage,
+        "data": "synthetic",
+        "config": {"workload": case.name, "nx": case.nx, "ny": case.ny, "tau": case.tau,
+                   "body_force": case.gx, "n_discs": len(case.prims), "fluid_nodes": n_fluid,
+                   "links": lat.n_links, "hbb_fallback_links": nfb,
+                   "boundary": "VIBB (velocity-interpolation bounce-back)",
+                   "collision": "BGK + Guo forcing", "storage": args.storage},
+        "mflups_fluid": round(n_fluid * args.steps / (ms * 1e-3) / 1e6, 1),
+        "step_algorithmic_GBps": round((bulk_bytes + link_bytes) / (ms * 1e-3 / args.steps) / 1e9, 1),
+        "roofline": {"bound": "hbm", "kernel": "bulk (pull + BGK collision)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": counter_traffic(),
+                     "algorithmic_bytes_per_launch": bulk_bytes,
+                     "avg_launch_us": round(bulk_avg_s * 1e6, 2)},
+        "link_kernel": {"avg_launch_us": round(link_avg_s * 1e6, 2),
+                        "algorithmic_bytes_per_launch": link_bytes,
+                        "GBps": round(link_bytes / link_avg_s / 1e9, 1) if link_avg_s > 0 else None},
+        "drag_per_step_mean": [float(fsum[0] / max(nsum, 1)), float(fsum[1] / max(nsum, 1))],
+    }
+
+    if args.cpu_steps > 0:
+        import oracle
+
+        g = oracle.case_geometry(case)
+        fp = oracle.init_equilibrium(g.solid, *case.init_fields())
+        t0 = time.perf_counter()
+        oracle.run(fp, g, tau=case.tau, gx=case.gx, gy=case.gy, rho0=case.rho0,
+                   x_open=case.x_open, n_obj=case.n_obj, nsteps=args.cpu_steps,
+                   u_in=case.inlet(), scheme=oracle.case_scheme(case, g))
+        cpu_s = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(n_nodes * args.cpu_steps / cpu_s / 1e6, 3),
+                               "unit": "MLUPS", "cores": 1, "kind": "oracle",
+                               "sample": f"{args.cpu_steps} steps of the full {case.nx}x{case.ny} "
+                                         f"lattice, FP64, single thread ({cpu_s:.1f}s)"}
+        # the GPU from the same initial state, same steps: the error this run is stated at
+        rho0, ux0, uy0 = case.init_fields()
+        B.lbm_init_equilibrium(lat.ctx, rho0, ux0, uy0)
+        lat.step(args.cpu_steps)
+        _, gux, guy = lat.moments()
+        _, oux, ouy = oracle.moments(fp, g.solid, (case.gx, case.gy))
+        ref = max(np.abs(oux).max(), np.abs(ouy).max())
+        err = max(np.abs(gux - oux).max(), np.abs(guy - ouy).max()) / ref
+        out["error_vs_oracle"] = {"e_u": float(err), "steps": args.cpu_steps,
+                                  "definition": "max|u_gpu - u_oracle| / max|u_oracle|"}
+    lat.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

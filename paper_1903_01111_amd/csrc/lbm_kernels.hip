@@ -102,11 +102,29 @@ struct Codec<3> {  // LBM_BF16_DEV, bits of a bfloat16 in a uint16
     }
 };
 
-// Equilibrium in deviation form: f^eq_i - w_i = w_i (drho + rho (3 e.u + 9/2 (e.u)^2 - 3/2 u.u))
+// Deviation-form arithmetic.  rho = 1 + dr is never formed: in FP32 its rounding
+// (2^-24 relative) is systematic for a slowly varying flow and would drift the
+// velocity step after step.  Instead
+//   u   = j/rho = j + j*(1/rho - 1),  1/rho - 1 = -dr/(1 + dr)
+//   f^eq_i - w_i = w_i (dr + P_i + dr P_i),  P_i = 3 e.u + 9/2 (e.u)^2 - 3/2 u.u
+// keep every term at the precision of its own (small) magnitude.
 template <class R>
-__device__ __forceinline__ R deq(R w, R eu, R drho, R rho, R usq)
+__device__ __forceinline__ R inv_rho_m1(R dr)
 {
-    return w * (drho + rho * (R(3) * eu + R(4.5) * eu * eu - R(1.5) * usq));
+    return -dr / (R(1) + dr);
+}
+
+template <class R>
+__device__ __forceinline__ R poly(R eu, R usq)
+{
+    return R(3) * eu + R(4.5) * eu * eu - R(1.5) * usq;
+}
+
+template <class R>
+__device__ __forceinline__ R deq(R w, R eu, R dr, R usq)
+{
+    const R P = poly(eu, usq);
+    return w * (dr + P + dr * P);
 }
 
 // ---------------------------------------------------------------------------
@@ -160,19 +178,20 @@ __global__ __launch_bounds__(256) void link_kernel(Grid g, Phys ph, typename Cod
                 jyff += R(CY[k]) * b;
             }
             const R fpff = C::ld(Aip[nff], ph.inv_scale);
-            const R rf = R(1) + drf, rff = R(1) + drff;
             const R hgx = R(0.5) * R(ph.gx), hgy = R(0.5) * R(ph.gy);
-            const R ufx = jxf / rf - hgx, ufy = jyf / rf - hgy;
-            const R uffx = jxff / rff - hgx, uffy = jyff / rff - hgy;
+            const R irf = inv_rho_m1(drf), irff = inv_rho_m1(drff);
+            const R ufx = jxf + jxf * irf - hgx, ufy = jyf + jyf * irf - hgy;
+            const R uffx = jxff + jxff * irff - hgx, uffy = jyff + jyff * irff - hgy;
             const R q = qv[l];
             const R a2q = R(2) * q, b2q = R(1) - R(2) * q;
             // density at the departure point d (extrapolated when q > 1/2)
             const R drd = a2q * drf + b2q * drff;
-            const R rd = R(1) + drd;
-            // non-equilibrium parts at f and ff, interpolated per unit density
-            const R neqf = fpf - deq(w, R(cxp) * ufx + R(cyp) * ufy, drf, rf, ufx * ufx + ufy * ufy);
-            const R neqff = fpff - deq(w, R(cxp) * uffx + R(cyp) * uffy, drff, rff, uffx * uffx + uffy * uffy);
-            const R neqd = rd * (a2q * neqf / rf + b2q * neqff / rff);
+            // non-equilibrium parts at f and ff, interpolated per unit density and
+            // rescaled by rho_d: rho_d/rho_f = 1 + (dr_d - dr_f)/(1 + dr_f)
+            const R neqf = fpf - deq(w, R(cxp) * ufx + R(cyp) * ufy, drf, ufx * ufx + ufy * ufy);
+            const R neqff = fpff - deq(w, R(cxp) * uffx + R(cyp) * uffy, drff, uffx * uffx + uffy * uffy);
+            const R neqd = a2q * (neqf + neqf * ((drd - drf) / (R(1) + drf))) +
+                           b2q * (neqff + neqff * ((drd - drff) / (R(1) + drff)));
             // velocity at d: u*_d from (f, ff) or (f, wall), u**_d from (ff, wall)
             R usx, usy;
             if (q <= R(0.5)) {
@@ -187,7 +206,7 @@ __global__ __launch_bounds__(256) void link_kernel(Grid g, Phys ph, typename Cod
             const R cff = (R(1) - q) * inv1q, cww = a2q * inv1q;
             const R ussx = cff * uffx + cww * uwx, ussy = cff * uffy + cww * uwy;
             const R udx = (usx + R(2) * ussx) / R(3), udy = (usy + R(2) * ussy) / R(3);
-            v = deq(w, R(cxp) * udx + R(cyp) * udy, drd, rd, udx * udx + udy * udy) + neqd + wall;
+            v = deq(w, R(cxp) * udx + R(cyp) * udy, drd, udx * udx + udy * udy) + neqd + wall;
         }
         A[(int64_t)i * g.plane + ns] = C::st(v, ph.scale);
         // momentum exchange: f+_{i'}(x_f) into the wall and f_i(x_f) back, both along e_{i'}
@@ -275,15 +294,15 @@ __global__ __launch_bounds__(BX *BY) void bulk_kernel(Grid g, Phys ph,
     f[8] = C::ld(A[8 * P + rp + xm], inv);
 
     const R drho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
-    const R rho = R(1) + drho;
     const R jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
     const R jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
-    const R irho = R(1) / rho;
-    R ux = jx * irho, uy = jy * irho;
+    const R ir = inv_rho_m1(drho);
+    R ux = jx + jx * ir, uy = jy + jy * ir;
     R Fx = R(0), Fy = R(0);
     if (FORCE) {
-        Fx = rho * R(ph.gx);
-        Fy = rho * R(ph.gy);
+        // force density F = rho g; velocity shifted by half the force (Guo)
+        Fx = R(ph.gx) + drho * R(ph.gx);
+        Fy = R(ph.gy) + drho * R(ph.gy);
         ux += R(0.5) * R(ph.gx);
         uy += R(0.5) * R(ph.gy);
     }
@@ -294,7 +313,7 @@ __global__ __launch_bounds__(BX *BY) void bulk_kernel(Grid g, Phys ph,
     for (int i = 0; i < 9; ++i) {
         const R w = wgt<R>(i);
         const R eu = R(CX[i]) * ux + R(CY[i]) * uy;
-        R v = f[i] - om * (f[i] - deq(w, eu, drho, rho, usq));
+        R v = f[i] - om * (f[i] - deq(w, eu, drho, usq));
         if (FORCE)
             v += cf * w * ((R(3) * (R(CX[i]) - ux) + R(9) * eu * R(CX[i])) * Fx +
                            (R(3) * (R(CY[i]) - uy) + R(9) * eu * R(CY[i])) * Fy);
@@ -312,8 +331,8 @@ __global__ __launch_bounds__(BX *BY) void bulk_kernel(Grid g, Phys ph,
                 const R w = wgt<R>(i);
                 const R ev = R(CX[i]) * vx + R(CY[i]) * vy;
                 const R eu = R(CX[i]) * ux + R(CY[i]) * uy;
-                const R d = w * rho * ((R(3) * ev + R(4.5) * ev * ev - R(1.5) * vsq) -
-                                       (R(3) * eu + R(4.5) * eu * eu - R(1.5) * usq));
+                const R dp = poly(ev, vsq) - poly(eu, usq);
+                const R d = w * (dp + drho * dp);
                 B[i * P + row] = C::st(f[i] + d, ph.scale);
             }
         }
@@ -344,7 +363,7 @@ __global__ void init_kernel(Grid g, Phys ph, typename Codec<ST>::T *__restrict__
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         const double eu = CX[i] * ux + CY[i] * uy;
-        const double d = solid ? 0.0 : deq<double>(wgt<double>(i), eu, rho - 1.0, rho, usq);
+        const double d = solid ? 0.0 : deq<double>(wgt<double>(i), eu, rho - 1.0, usq);
         A[(int64_t)i * g.plane + n] = C::st((typename Codec<ST>::R)d, ph.scale);
     }
 }
