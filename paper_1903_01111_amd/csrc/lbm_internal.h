@@ -23,6 +23,22 @@ struct Phys {
     float inv_scale;  // 2^-k
 };
 
+// Mask byte of a node: bit 0 solid, bit 1 "moments wanted" (the node is x_f or
+// x_ff of some VIBB link).  The bulk kernel stores (rho - 1, ux, uy) of every
+// flagged node after collision; the link kernel of the next step reads them
+// instead of gathering the nine populations of both nodes.  The slot of a
+// flagged node is its rank in plane order: seg_base[y*pitch/64 + x/64] (flagged
+// nodes before that 64-node row segment) plus the flagged lanes below it in its
+// wavefront.
+constexpr uint8_t MASK_SOLID = 1, MASK_MOMENTS = 2;
+
+struct Side {
+    void *M;                  // real[3K]: rho - 1, ux, uy (physical velocity)
+    const int32_t *seg_base;  // [ny * pitch / 64]
+    const int32_t *mnode;     // [K] plane offset of each flagged node
+    int64_t K;
+};
+
 // Compacted boundary links, sorted by (obj, node).  Indices are offsets inside
 // a plane.  meta = dir | (obj << 8).
 struct Links {
@@ -30,6 +46,8 @@ struct Links {
     const int32_t *nff;  // x_ff = x_f - e_{i'}, or -1: halfway bounce-back
     const int32_t *ns;   // x_s = x_f + e_{i'}: its slot of plane i = opp(i')
                          // receives f_i(x_f, t+1) for the next pull
+    const int32_t *sf;   // moment slot of x_f (VIBB links)
+    const int32_t *sff;  // moment slot of x_ff (VIBB links)
     const uint32_t *meta;
     const void *q;       // real[n]
     const void *uw;      // real[2n] or nullptr (still walls)
@@ -37,11 +55,16 @@ struct Links {
 };
 
 hipError_t launch_link(int storage, const Grid &g, const Phys &ph, void *A, const Links &L,
-                       double *force_bank, double *force_sum, hipStream_t s);
+                       const void *M, double *force_bank, double *force_sum, hipStream_t s);
 
 hipError_t launch_bulk(int storage, const Grid &g, const Phys &ph, const void *A, void *B,
-                       const uint8_t *mask, const void *uin, double *zero_bank, int32_t n_zero,
-                       hipStream_t s);
+                       const uint8_t *mask, const void *uin, const Side &side, double *zero_bank,
+                       int32_t n_zero, hipStream_t s);
+
+// Recomputes the side moments of every flagged node from the populations in A
+// (after initialisation or a restored checkpoint).
+hipError_t launch_refresh(int storage, const Grid &g, const Phys &ph, const void *A,
+                          const Side &side, hipStream_t s);
 
 // Equilibrium initialisation of rows [y0, y0+rows) of A from staged doubles
 // (rho, ux, uy interleaved per node, rows*nx nodes).

@@ -132,8 +132,8 @@ __device__ __forceinline__ R deq(R w, R eu, R dr, R usq)
 // ---------------------------------------------------------------------------
 template <int ST>
 __global__ __launch_bounds__(256) void link_kernel(Grid g, Phys ph, typename Codec<ST>::T *__restrict__ A,
-                                                   Links L, double *__restrict__ bank,
-                                                   double *__restrict__ fsum)
+                                                   Links L, const typename Codec<ST>::R *__restrict__ M,
+                                                   double *__restrict__ bank, double *__restrict__ fsum)
 {
     using C = Codec<ST>;
     using T = typename C::T;
@@ -164,24 +164,11 @@ __global__ __launch_bounds__(256) void link_kernel(Grid g, Phys ph, typename Cod
         if (nff < 0) {
             v = fpf + wall;  // halfway bounce-back
         } else {
-            // moments of f and ff at time t (physical velocity: j/rho - g/2)
-            R drf = R(0), jxf = R(0), jyf = R(0), drff = R(0), jxff = R(0), jyff = R(0);
-#pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                const R a = C::ld(A[(int64_t)k * g.plane + nf], ph.inv_scale);
-                const R b = C::ld(A[(int64_t)k * g.plane + nff], ph.inv_scale);
-                drf += a;
-                drff += b;
-                jxf += R(CX[k]) * a;
-                jyf += R(CY[k]) * a;
-                jxff += R(CX[k]) * b;
-                jyff += R(CY[k]) * b;
-            }
+            // moments of f and ff at time t, stored by the previous bulk step
+            const int32_t sf = L.sf[l], sff = L.sff[l];
+            const R drf = M[3 * sf], ufx = M[3 * sf + 1], ufy = M[3 * sf + 2];
+            const R drff = M[3 * sff], uffx = M[3 * sff + 1], uffy = M[3 * sff + 2];
             const R fpff = C::ld(Aip[nff], ph.inv_scale);
-            const R hgx = R(0.5) * R(ph.gx), hgy = R(0.5) * R(ph.gy);
-            const R irf = inv_rho_m1(drf), irff = inv_rho_m1(drff);
-            const R ufx = jxf + jxf * irf - hgx, ufy = jyf + jyf * irf - hgy;
-            const R uffx = jxff + jxff * irff - hgx, uffy = jyff + jyff * irff - hgy;
             const R q = qv[l];
             const R a2q = R(2) * q, b2q = R(1) - R(2) * q;
             // density at the departure point d (extrapolated when q > 1/2)
@@ -239,34 +226,42 @@ __global__ __launch_bounds__(256) void link_kernel(Grid g, Phys ph, typename Cod
 }
 
 // ---------------------------------------------------------------------------
-// Bulk kernel: pull, moments, BGK + Guo, store.  Block = 64 x 4 lanes.
+// Bulk kernel: pull, moments, BGK + Guo, store.  A block of BX x (256/BX) lanes
+// covers BX consecutive nodes of 256/BX rows; every 64-lane wavefront is one
+// aligned 64-node run of a row, so each population plane is read and written
+// as contiguous 256-byte (FP32) runs.
 // ---------------------------------------------------------------------------
-constexpr int BX = 64, BY = 4;
-
-template <int ST, bool OPEN, bool FORCE>
-__global__ __launch_bounds__(BX *BY) void bulk_kernel(Grid g, Phys ph,
-                                                      const typename Codec<ST>::T *__restrict__ A,
-                                                      typename Codec<ST>::T *__restrict__ B,
-                                                      const uint8_t *__restrict__ mask,
-                                                      const typename Codec<ST>::R *__restrict__ uin,
-                                                      double *__restrict__ zero_bank, int32_t n_zero)
+template <int ST, bool OPEN, bool FORCE, int BX>
+__global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
+                                                   const typename Codec<ST>::T *__restrict__ A,
+                                                   typename Codec<ST>::T *__restrict__ B,
+                                                   const uint8_t *__restrict__ mask,
+                                                   const typename Codec<ST>::R *__restrict__ uin,
+                                                   Side side, double *__restrict__ zero_bank,
+                                                   int32_t n_zero)
 {
     using C = Codec<ST>;
     using T = typename C::T;
     using R = typename C::R;
+    constexpr int BY = 256 / BX;
     {
         // clear the force bank of the next step
-        const int64_t gt = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * (BX * BY) +
+        const int64_t gt = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * 256 +
                            threadIdx.y * BX + threadIdx.x;
-        const int64_t nt = (int64_t)gridDim.x * gridDim.y * (BX * BY);
+        const int64_t nt = (int64_t)gridDim.x * gridDim.y * 256;
         for (int64_t k = gt; k < n_zero; k += nt) zero_bank[k] = 0.0;
     }
     const int x = blockIdx.x * BX + threadIdx.x;
     const int y = blockIdx.y * BY + threadIdx.y;
-    if (x >= g.nx || y >= g.ny) return;
-    if (OPEN && (x == 0 || x == g.nx - 1)) return;
+    const bool inside = x < g.nx && y < g.ny;
     const int32_t row = y * g.pitch;
-    if (mask[row + x]) return;
+    const uint8_t m = inside ? mask[row + x] : MASK_SOLID;
+    // moment slots of the flagged nodes of this 64-node run (all lanes vote)
+    const uint64_t flagged = __ballot((m & MASK_MOMENTS) != 0);
+    if (!inside || (m & MASK_SOLID)) return;
+    if (OPEN && (x == 0 || x == g.nx - 1)) return;
+    const int lane = threadIdx.x & 63;
+    const int32_t seg = y * (g.pitch >> 6) + (x >> 6);
 
     int xm, xp;
     if (OPEN) {
@@ -320,10 +315,19 @@ __global__ __launch_bounds__(BX *BY) void bulk_kernel(Grid g, Phys ph,
         f[i] = v;
         B[i * P + row + x] = C::st(v, ph.scale);
     }
+    // the post-collision moments are the collision's own (rho, u): with Guo's
+    // shift the physical velocity of f+ equals the collision velocity
+    R *Mv = static_cast<R *>(side.M);
+    if (m & MASK_MOMENTS) {
+        const int32_t k = side.seg_base[seg] + (int32_t)__popcll(flagged & ((1ull << lane) - 1ull));
+        Mv[3 * k] = drho;
+        Mv[3 * k + 1] = ux;
+        Mv[3 * k + 2] = uy;
+    }
     if (OPEN) {
-        if (x == 1 && !mask[row]) {
+        if (x == 1 && !(mask[row] & MASK_SOLID)) {
             // velocity inlet by non-equilibrium extrapolation:
-            // f+(0) = f^eq(rho_1, u_in) + f+(1) - f^eq(rho_1, u_1)
+            // f+(0) = f^eq(rho_1, u_in) + f+(1) - f^eq(rho_1, u_1); its moments are (rho_1, u_in)
             const R vx = uin[2 * y], vy = uin[2 * y + 1];
             const R vsq = vx * vx + vy * vy;
 #pragma unroll
@@ -335,18 +339,57 @@ __global__ __launch_bounds__(BX *BY) void bulk_kernel(Grid g, Phys ph,
                 const R d = w * (dp + drho * dp);
                 B[i * P + row] = C::st(f[i] + d, ph.scale);
             }
+            if (flagged & 1ull) {
+                const int32_t k = side.seg_base[y * (g.pitch >> 6)];
+                Mv[3 * k] = drho;
+                Mv[3 * k + 1] = vx;
+                Mv[3 * k + 2] = vy;
+            }
         }
-        if (x == g.nx - 2 && !mask[row + g.nx - 1]) {
+        const uint8_t me = mask[row + g.nx - 1];
+        if (x == g.nx - 2 && !(me & MASK_SOLID)) {
             // zero-gradient outlet: copy every population of the last fluid column
 #pragma unroll
             for (int i = 0; i < 9; ++i) B[i * P + row + g.nx - 1] = C::st(f[i], ph.scale);
+            if (me & MASK_MOMENTS) {
+                const int xe = g.nx - 1;
+                const int32_t k = ((xe >> 6) == (x >> 6))
+                                      ? side.seg_base[seg] + (int32_t)__popcll(flagged & ((1ull << (xe & 63)) - 1ull))
+                                      : side.seg_base[seg + 1];
+                Mv[3 * k] = drho;
+                Mv[3 * k + 1] = ux;
+                Mv[3 * k + 2] = uy;
+            }
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Initialisation, moments and mass.
+// Initialisation, side-moment refresh, moments and mass.
 // ---------------------------------------------------------------------------
+template <int ST>
+__global__ void refresh_kernel(Grid g, Phys ph, const typename Codec<ST>::T *__restrict__ A, Side side)
+{
+    using C = Codec<ST>;
+    using R = typename C::R;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= side.K) return;
+    const int32_t n = side.mnode[k];
+    R dr = R(0), jx = R(0), jy = R(0);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const R v = C::ld(A[(int64_t)i * g.plane + n], ph.inv_scale);
+        dr += v;
+        jx += R(CX[i]) * v;
+        jy += R(CY[i]) * v;
+    }
+    const R ir = inv_rho_m1(dr);
+    R *Mv = static_cast<R *>(side.M);
+    Mv[3 * k] = dr;
+    Mv[3 * k + 1] = jx + jx * ir - R(0.5) * R(ph.gx);
+    Mv[3 * k + 2] = jy + jy * ir - R(0.5) * R(ph.gy);
+}
+
 template <int ST>
 __global__ void init_kernel(Grid g, Phys ph, typename Codec<ST>::T *__restrict__ A,
                             const uint8_t *__restrict__ mask, const double *__restrict__ stage,
@@ -357,7 +400,7 @@ __global__ void init_kernel(Grid g, Phys ph, typename Codec<ST>::T *__restrict__
     if (k >= (int64_t)rows * g.nx) return;
     const int y = y0 + (int)(k / g.nx), x = (int)(k % g.nx);
     const int32_t n = y * g.pitch + x;
-    const bool solid = mask[n] != 0;
+    const bool solid = (mask[n] & MASK_SOLID) != 0;
     const double rho = stage[3 * k], ux = stage[3 * k + 1], uy = stage[3 * k + 2];
     const double usq = ux * ux + uy * uy;
 #pragma unroll
@@ -378,7 +421,7 @@ __global__ void moments_kernel(Grid g, Phys ph, const typename Codec<ST>::T *__r
     if (k >= (int64_t)rows * g.nx) return;
     const int y = y0 + (int)(k / g.nx), x = (int)(k % g.nx);
     const int32_t n = y * g.pitch + x;
-    if (mask[n]) {
+    if (mask[n] & MASK_SOLID) {
         stage[3 * k] = stage[3 * k + 1] = stage[3 * k + 2] = 0.0;
         return;
     }
@@ -412,7 +455,7 @@ __global__ __launch_bounds__(MASS_THREADS) void mass_kernel(Grid g, Phys ph,
          k += (int64_t)gridDim.x * MASS_THREADS) {
         const int y = (int)(k / g.nx), x = (int)(k % g.nx);
         const int32_t n = y * g.pitch + x;
-        if (mask[n]) continue;
+        if (mask[n] & MASK_SOLID) continue;
 #pragma unroll
         for (int i = 0; i < 9; ++i)
             s += (double)C::ld(A[(int64_t)i * g.plane + n], ph.inv_scale) + wgt<double>(i);
@@ -429,63 +472,89 @@ __global__ __launch_bounds__(MASS_THREADS) void mass_kernel(Grid g, Phys ph,
 }
 
 template <int ST>
-hipError_t link_t(const Grid &g, const Phys &ph, void *A, const Links &L, double *bank, double *fsum,
-                  hipStream_t s)
+hipError_t link_t(const Grid &g, const Phys &ph, void *A, const Links &L, const void *M, double *bank,
+                  double *fsum, hipStream_t s)
 {
     if (L.n == 0) return hipSuccess;
     const int threads = 256;
     const unsigned blocks = (unsigned)((L.n + threads - 1) / threads);
     hipLaunchKernelGGL(link_kernel<ST>, dim3(blocks), dim3(threads), 0, s, g, ph,
-                       static_cast<typename Codec<ST>::T *>(A), L, bank, fsum);
+                       static_cast<typename Codec<ST>::T *>(A), L,
+                       static_cast<const typename Codec<ST>::R *>(M), bank, fsum);
     return hipGetLastError();
 }
 
+constexpr int BULK_BX = 256;
+
 template <int ST, bool OPEN, bool FORCE>
 hipError_t bulk_t(const Grid &g, const Phys &ph, const void *A, void *B, const uint8_t *mask,
-                  const void *uin, double *zb, int32_t nz, hipStream_t s)
+                  const void *uin, const Side &side, double *zb, int32_t nz, hipStream_t s)
 {
     using C = Codec<ST>;
+    constexpr int BX = BULK_BX, BY = 256 / BULK_BX;
     dim3 grid((g.nx + BX - 1) / BX, (g.ny + BY - 1) / BY);
-    hipLaunchKernelGGL((bulk_kernel<ST, OPEN, FORCE>), grid, dim3(BX, BY), 0, s, g, ph,
+    hipLaunchKernelGGL((bulk_kernel<ST, OPEN, FORCE, BX>), grid, dim3(BX, BY), 0, s, g, ph,
                        static_cast<const typename C::T *>(A), static_cast<typename C::T *>(B), mask,
-                       static_cast<const typename C::R *>(uin), zb, nz);
+                       static_cast<const typename C::R *>(uin), side, zb, nz);
     return hipGetLastError();
 }
 
 template <int ST>
 hipError_t bulk_dispatch(const Grid &g, const Phys &ph, const void *A, void *B, const uint8_t *mask,
-                         const void *uin, double *zb, int32_t nz, hipStream_t s)
+                         const void *uin, const Side &side, double *zb, int32_t nz, hipStream_t s)
 {
     const bool force = ph.gx != 0.0 || ph.gy != 0.0;
     if (g.x_open)
-        return force ? bulk_t<ST, true, true>(g, ph, A, B, mask, uin, zb, nz, s)
-                     : bulk_t<ST, true, false>(g, ph, A, B, mask, uin, zb, nz, s);
-    return force ? bulk_t<ST, false, true>(g, ph, A, B, mask, uin, zb, nz, s)
-                 : bulk_t<ST, false, false>(g, ph, A, B, mask, uin, zb, nz, s);
+        return force ? bulk_t<ST, true, true>(g, ph, A, B, mask, uin, side, zb, nz, s)
+                     : bulk_t<ST, true, false>(g, ph, A, B, mask, uin, side, zb, nz, s);
+    return force ? bulk_t<ST, false, true>(g, ph, A, B, mask, uin, side, zb, nz, s)
+                 : bulk_t<ST, false, false>(g, ph, A, B, mask, uin, side, zb, nz, s);
+}
+
+template <int ST>
+hipError_t refresh_t(const Grid &g, const Phys &ph, const void *A, const Side &side, hipStream_t s)
+{
+    if (side.K == 0) return hipSuccess;
+    hipLaunchKernelGGL(refresh_kernel<ST>, dim3((unsigned)((side.K + 255) / 256)), dim3(256), 0, s, g,
+                       ph, static_cast<const typename Codec<ST>::T *>(A), side);
+    return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_link(int storage, const Grid &g, const Phys &ph, void *A, const Links &L,
-                       double *bank, double *fsum, hipStream_t s)
+                       const void *M, double *bank, double *fsum, hipStream_t s)
 {
     switch (storage) {
-    case 0: return link_t<0>(g, ph, A, L, bank, fsum, s);
-    case 1: return link_t<1>(g, ph, A, L, bank, fsum, s);
-    case 2: return link_t<2>(g, ph, A, L, bank, fsum, s);
-    case 3: return link_t<3>(g, ph, A, L, bank, fsum, s);
+    case 0: return link_t<0>(g, ph, A, L, M, bank, fsum, s);
+    case 1: return link_t<1>(g, ph, A, L, M, bank, fsum, s);
+    case 2: return link_t<2>(g, ph, A, L, M, bank, fsum, s);
+    case 3: return link_t<3>(g, ph, A, L, M, bank, fsum, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_bulk(int storage, const Grid &g, const Phys &ph, const void *A, void *B,
-                       const uint8_t *mask, const void *uin, double *zb, int32_t nz, hipStream_t s)
+                       const uint8_t *mask, const void *uin, const Side &side, double *zb, int32_t nz,
+                       hipStream_t s)
 {
     switch (storage) {
-    case 0: return bulk_dispatch<0>(g, ph, A, B, mask, uin, zb, nz, s);
-    case 1: return bulk_dispatch<1>(g, ph, A, B, mask, uin, zb, nz, s);
-    case 2: return bulk_dispatch<2>(g, ph, A, B, mask, uin, zb, nz, s);
-    case 3: return bulk_dispatch<3>(g, ph, A, B, mask, uin, zb, nz, s);
+    case 0: return bulk_dispatch<0>(g, ph, A, B, mask, uin, side, zb, nz, s);
+    case 1: return bulk_dispatch<1>(g, ph, A, B, mask, uin, side, zb, nz, s);
+    case 2: return bulk_dispatch<2>(g, ph, A, B, mask, uin, side, zb, nz, s);
+    case 3: return bulk_dispatch<3>(g, ph, A, B, mask, uin, side, zb, nz, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_refresh(int storage, const Grid &g, const Phys &ph, const void *A, const Side &side,
+                          hipStream_t s)
+{
+    switch (storage) {
+    case 0: return refresh_t<0>(g, ph, A, side, s);
+    case 1: return refresh_t<1>(g, ph, A, side, s);
+    case 2: return refresh_t<2>(g, ph, A, side, s);
+    case 3: return refresh_t<3>(g, ph, A, side, s);
     default: return hipErrorInvalidValue;
     }
 }

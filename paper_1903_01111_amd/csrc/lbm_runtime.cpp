@@ -44,9 +44,13 @@ size_t real_bytes(int storage) { return storage == LBM_F64 ? 8 : 4; }
 struct Layout {
     int32_t pitch;
     int64_t plane;  // elements per population plane
-    size_t off_A, off_B, off_mask, off_nf, off_nff, off_ns, off_meta, off_q, off_uw, off_uin,
-        off_force, off_partials, off_stage, total;
+    size_t off_A, off_B, off_mask, off_segbase, off_nf, off_nff, off_ns, off_sf, off_sff, off_meta,
+        off_q, off_uw, off_mnode, off_M, off_uin, off_force, off_partials, off_stage, total;
 };
+
+// device bytes per link of capacity (link arrays, and up to two flagged nodes
+// with their side moments)
+size_t bytes_per_link(int storage) { return 24 + 3 * real_bytes(storage) + 2 * (4 + 3 * real_bytes(storage)); }
 
 // Plane stride: rows padded to 64 elements; the plane size in 256-byte units is
 // kept odd so that the nine planes do not start on the same memory channel.
@@ -67,13 +71,18 @@ Layout make_layout(const lbm_params &p, int64_t max_links)
     L.off_A = take(9 * pb);
     L.off_B = take(9 * pb);
     L.off_mask = take((size_t)L.pitch * p.ny);
+    L.off_segbase = take((size_t)(L.pitch / 64) * p.ny * 4);
     const size_t nl = (size_t)std::max<int64_t>(max_links, 0);
     L.off_nf = take(nl * 4);
     L.off_nff = take(nl * 4);
     L.off_ns = take(nl * 4);
+    L.off_sf = take(nl * 4);
+    L.off_sff = take(nl * 4);
     L.off_meta = take(nl * 4);
     L.off_q = take(nl * rb);
     L.off_uw = take(nl * 2 * rb);
+    L.off_mnode = take(2 * nl * 4);
+    L.off_M = take(2 * nl * 3 * rb);
     L.off_uin = take((size_t)p.ny * 2 * rb);
     L.off_force = take((size_t)p.n_obj * 6 * sizeof(double));
     L.off_partials = take(1024 * sizeof(double));
@@ -136,9 +145,12 @@ bool params_ok(const lbm_params *p, std::string *why)
 }
 
 struct Prepared {
-    std::vector<int32_t> nf, nff, ns;
+    std::vector<int32_t> nf, nff, ns, sf, sff;
     std::vector<uint32_t> meta;
     std::vector<double> q, uw;
+    std::vector<uint8_t> mask;       // padded to the pitch: solid bit, moments bit
+    std::vector<int32_t> seg_base;   // flagged nodes before each 64-node row segment
+    std::vector<int32_t> mnode;      // plane offset of each flagged node, in slot order
     bool has_uw = false;
     int64_t n_fallback = 0;
 };
@@ -263,6 +275,11 @@ lbm_status prepare_geometry(const lbm_params &p, const uint8_t *mask, int64_t n,
             out->has_uw = uw[2 * l] != 0.0 || uw[2 * l + 1] != 0.0;
     out->uw.assign(out->has_uw ? 2 * n : 0, 0.0);
     out->n_fallback = 0;
+    // padded mask; padding columns count as solid and are never streamed
+    out->mask.assign((size_t)pitch * ny, lbm::MASK_SOLID);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x)
+            out->mask[(size_t)y * pitch + x] = mask[(int64_t)y * nx + x] ? lbm::MASK_SOLID : 0;
     for (int64_t k = 0; k < n; ++k) {
         const int64_t l = order[k];
         const int nd = node[l], d = dir[l], x = nd % nx, y = nd / nx;
@@ -284,7 +301,32 @@ lbm_status prepare_geometry(const lbm_params &p, const uint8_t *mask, int64_t n,
             out->uw[2 * k] = uw[2 * l];
             out->uw[2 * k + 1] = uw[2 * l + 1];
         }
+        if (out->nff[k] >= 0) {
+            out->mask[out->nf[k]] |= lbm::MASK_MOMENTS;
+            out->mask[out->nff[k]] |= lbm::MASK_MOMENTS;
+        }
     }
+    // moment slots: rank of each flagged node in plane order
+    const int64_t nseg = (int64_t)(pitch / 64) * ny;
+    out->seg_base.assign((size_t)nseg, 0);
+    out->mnode.clear();
+    std::vector<int32_t> slot;  // plane offset -> slot, only read for flagged nodes
+    slot.assign(out->mask.size(), -1);
+    for (int64_t sgm = 0; sgm < nseg; ++sgm) {
+        out->seg_base[sgm] = (int32_t)out->mnode.size();
+        for (int64_t o = sgm * 64; o < sgm * 64 + 64; ++o)
+            if (out->mask[o] & lbm::MASK_MOMENTS) {
+                slot[o] = (int32_t)out->mnode.size();
+                out->mnode.push_back((int32_t)o);
+            }
+    }
+    out->sf.assign(n, -1);
+    out->sff.assign(n, -1);
+    for (int64_t k = 0; k < n; ++k)
+        if (out->nff[k] >= 0) {
+            out->sf[k] = slot[out->nf[k]];
+            out->sff[k] = slot[out->nff[k]];
+        }
     return LBM_OK;
 }
 
@@ -298,7 +340,7 @@ struct lbm_ctx {
     std::string err = "no error";
     char *ws = nullptr;
     size_t ws_bytes = 0;
-    int64_t max_links = 0, n_links = 0;
+    int64_t max_links = 0, n_links = 0, n_moment_nodes = 0;
     bool has_uw = false, have_geom = false, have_init = false;
     void *cur = nullptr, *nxt = nullptr;
     int64_t step = 0, nsum = 0;
@@ -326,8 +368,15 @@ struct lbm_ctx {
         return lbm::Links{reinterpret_cast<const int32_t *>(ws + lay.off_nf),
                           reinterpret_cast<const int32_t *>(ws + lay.off_nff),
                           reinterpret_cast<const int32_t *>(ws + lay.off_ns),
+                          reinterpret_cast<const int32_t *>(ws + lay.off_sf),
+                          reinterpret_cast<const int32_t *>(ws + lay.off_sff),
                           reinterpret_cast<const uint32_t *>(ws + lay.off_meta),
                           ws + lay.off_q, has_uw ? ws + lay.off_uw : nullptr, n_links};
+    }
+    lbm::Side side() const
+    {
+        return lbm::Side{ws + lay.off_M, reinterpret_cast<const int32_t *>(ws + lay.off_segbase),
+                         reinterpret_cast<const int32_t *>(ws + lay.off_mnode), n_moment_nodes};
     }
     uint8_t *mask() const { return reinterpret_cast<uint8_t *>(ws + lay.off_mask); }
     double *force() const { return reinterpret_cast<double *>(ws + lay.off_force); }
@@ -380,13 +429,14 @@ lbm_status enqueue_step(lbm_ctx *c, bool timed)
         c->ev_used += 3;
         hipEventRecord(e0, c->stream);
     }
-    lbm_status s = c->hip(lbm::launch_link(c->p.storage, g, ph, c->cur, c->links(), c->bank(c->step),
-                                           c->fsum(), c->stream), "link kernel launch");
+    lbm_status s = c->hip(lbm::launch_link(c->p.storage, g, ph, c->cur, c->links(), c->ws + c->lay.off_M,
+                                           c->bank(c->step), c->fsum(), c->stream),
+                          "link kernel launch");
     if (s) return s;
     if (timed) hipEventRecord(e1, c->stream);
     s = c->hip(lbm::launch_bulk(c->p.storage, g, ph, c->cur, c->nxt, c->mask(),
-                                c->ws + c->lay.off_uin, c->bank(c->step + 1), 2 * c->p.n_obj,
-                                c->stream), "bulk kernel launch");
+                                c->ws + c->lay.off_uin, c->side(), c->bank(c->step + 1),
+                                2 * c->p.n_obj, c->stream), "bulk kernel launch");
     if (s) return s;
     if (timed) hipEventRecord(e2, c->stream);
     std::swap(c->cur, c->nxt);
@@ -531,7 +581,7 @@ lbm_status lbm_create(const lbm_params *p, void *workspace, size_t bytes, lbm_ct
         g_thread_error = "lbm_create: workspace too small";
         return LBM_E_NOMEM;
     }
-    const size_t per_link = 16 + 3 * real_bytes(p->storage);
+    const size_t per_link = bytes_per_link(p->storage);
     int64_t cap = (int64_t)((bytes - base.total) / per_link);
     while (cap > 0 && make_layout(*p, cap).total > bytes) --cap;
     lbm_ctx *c = new (std::nothrow) lbm_ctx;
@@ -579,13 +629,9 @@ lbm_status lbm_set_geometry(lbm_ctx *c, const uint8_t *mask, int64_t n_links, co
         return c->fail(LBM_E_NOMEM, "lbm_set_geometry: %lld links exceed the workspace capacity %lld",
                        (long long)n_links, (long long)c->max_links);
     c->drop_graph();
-    const int nx = c->p.nx, ny = c->p.ny;
     const hipStream_t st = c->stream;
-    // mask rows padded to the pitch (padding marked solid: never streamed)
-    std::vector<uint8_t> m((size_t)c->lay.pitch * ny, 1);
-    for (int y = 0; y < ny; ++y) std::memcpy(&m[(size_t)y * c->lay.pitch], mask + (size_t)y * nx, nx);
-    if ((s = c->hip(hipMemcpyAsync(c->mask(), m.data(), m.size(), hipMemcpyHostToDevice, st),
-                    "mask upload")))
+    if ((s = c->hip(hipMemcpyAsync(c->mask(), prep.mask.data(), prep.mask.size(), hipMemcpyHostToDevice,
+                                   st), "mask upload")))
         return s;
     const size_t n = (size_t)n_links;
     const size_t rb = real_bytes(c->p.storage);
@@ -602,9 +648,12 @@ lbm_status lbm_set_geometry(lbm_ctx *c, const uint8_t *mask, int64_t n_links, co
         const void *src;
         size_t bytes;
     } ups[] = {{c->lay.off_nf, prep.nf.data(), n * 4},   {c->lay.off_nff, prep.nff.data(), n * 4},
-               {c->lay.off_ns, prep.ns.data(), n * 4},   {c->lay.off_meta, prep.meta.data(), n * 4},
+               {c->lay.off_ns, prep.ns.data(), n * 4},   {c->lay.off_sf, prep.sf.data(), n * 4},
+               {c->lay.off_sff, prep.sff.data(), n * 4}, {c->lay.off_meta, prep.meta.data(), n * 4},
                {c->lay.off_q, qsrc, n * rb},
-               {c->lay.off_uw, uwsrc, prep.has_uw ? 2 * n * rb : 0}};
+               {c->lay.off_uw, uwsrc, prep.has_uw ? 2 * n * rb : 0},
+               {c->lay.off_segbase, prep.seg_base.data(), prep.seg_base.size() * 4},
+               {c->lay.off_mnode, prep.mnode.data(), prep.mnode.size() * 4}};
     for (const Up &u : ups)
         if (u.bytes && (s = c->hip(hipMemcpyAsync(c->ws + u.off, u.src, u.bytes,
                                                   hipMemcpyHostToDevice, st), "link upload")))
@@ -619,6 +668,7 @@ lbm_status lbm_set_geometry(lbm_ctx *c, const uint8_t *mask, int64_t n_links, co
     if ((s = c->hip(hipStreamSynchronize(st), "geometry upload")))  // host vectors die here
         return s;
     c->n_links = n_links;
+    c->n_moment_nodes = (int64_t)prep.mnode.size();
     c->has_uw = prep.has_uw;
     c->have_geom = true;
     c->have_init = false;
@@ -684,6 +734,9 @@ lbm_status lbm_init_equilibrium(lbm_ctx *c, const double *rho, const double *ux,
         if ((s = c->hip(hipStreamSynchronize(c->stream), "init")))  // h is reused
             return s;
     }
+    if ((s = c->hip(lbm::launch_refresh(c->p.storage, c->grid(), c->phys(), c->cur, c->side(), c->stream),
+                    "side-moment refresh")))
+        return s;
     c->have_init = true;
     return LBM_OK;
 }
@@ -815,7 +868,7 @@ lbm_status lbm_populations(lbm_ctx *c, double *f)
                     d = bf16_to_double(v) * inv;
                 }
                 }
-                f[((size_t)y * nx + x) * 9 + i] = mask[k] ? 0.0 : d + WR[i];
+                f[((size_t)y * nx + x) * 9 + i] = (mask[k] & lbm::MASK_SOLID) ? 0.0 : d + WR[i];
             }
     }
     return LBM_OK;
@@ -914,6 +967,9 @@ lbm_status lbm_set_state(lbm_ctx *c, const void *host, size_t bytes)
     if ((s = c->hip(hipMemcpy(c->cur, h + sizeof hdr, pb, hipMemcpyHostToDevice), "state write"))) return s;
     if ((s = c->hip(hipMemcpy(c->force(), h + sizeof hdr + pb, 6 * (size_t)c->p.n_obj * 8,
                               hipMemcpyHostToDevice), "state write")))
+        return s;
+    if ((s = c->hip(lbm::launch_refresh(c->p.storage, c->grid(), c->phys(), c->cur, c->side(), c->stream),
+                    "side-moment refresh")))
         return s;
     c->step = hdr[0];
     c->nsum = hdr[1];
