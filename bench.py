@@ -59,6 +59,13 @@ def workload(name):
         return W.porous_medium()
     if name == "cylinder":
         return W.cylinder_channel()
+    if name == "dense":
+        # the same lattice with no obstacle: every node fluid, no links (bulk kernel only)
+        import numpy as np
+        c = W.Case("dense_8192x2048", 8192, 2048, False, 0.7, gx=1e-6)
+        y = np.arange(2048)[:, None] * np.ones((1, 8192))
+        c.init_ux = 1e-3 * np.sin(2 * np.pi * y / 2048)
+        return c
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -85,7 +92,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="porous", choices=["porous", "cylinder"])
+    ap.add_argument("--workload", default="porous", choices=["porous", "cylinder", "dense"])
     ap.add_argument("--storage", default="f32", choices=list(BYTES))
     ap.add_argument("--cpu-steps", type=int, default=4,
                     help="oracle steps on the full lattice for the CPU baseline (0: skip)")

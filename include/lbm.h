@@ -189,8 +189,10 @@ lbm_status lbm_force_reset(lbm_ctx *ctx);
 /* Total mass sum over fluid nodes of sum_i f+_i, reduced in FP64.  Synchronises. */
 lbm_status lbm_mass(lbm_ctx *ctx, double *mass);
 
-/* Checkpoint: the population buffer in storage precision plus the step counter
- * and force accumulators.  lbm_state_bytes gives the size of the host buffer. */
+/* Checkpoint: the population buffer in storage precision, the step counter, the
+ * force accumulators and the stored moments of the boundary-adjacent nodes, so
+ * that a restored run continues bitwise.  lbm_state_bytes gives the size of the
+ * host buffer; a state only fits a context with the same params and geometry. */
 size_t lbm_state_bytes(const lbm_ctx *ctx);
 lbm_status lbm_get_state(lbm_ctx *ctx, void *host, size_t bytes);
 lbm_status lbm_set_state(lbm_ctx *ctx, const void *host, size_t bytes);

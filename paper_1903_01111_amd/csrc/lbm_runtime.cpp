@@ -926,11 +926,14 @@ lbm_status lbm_mass(lbm_ctx *c, double *m)
     return LBM_OK;
 }
 
+// Checkpoint layout: {step, nsum} | populations (nine planes, storage precision) |
+// force accumulators | side moments of the flagged nodes (they are part of the
+// state: recomputing them from rounded populations would not resume bitwise).
 size_t lbm_state_bytes(const lbm_ctx *c)
 {
     if (!c) return 0;
     return 9 * (size_t)c->lay.plane * elem_bytes(c->p.storage) + 6 * (size_t)c->p.n_obj * sizeof(double) +
-           2 * sizeof(int64_t);
+           2 * sizeof(int64_t) + (size_t)c->n_moment_nodes * 3 * real_bytes(c->p.storage);
 }
 
 lbm_status lbm_get_state(lbm_ctx *c, void *host, size_t bytes)
@@ -945,7 +948,11 @@ lbm_status lbm_get_state(lbm_ctx *c, void *host, size_t bytes)
     lbm_status s;
     if ((s = c->hip(hipStreamSynchronize(c->stream), "state"))) return s;
     if ((s = c->hip(hipMemcpy(h + sizeof hdr, c->cur, pb, hipMemcpyDeviceToHost), "state read"))) return s;
-    return c->hip(hipMemcpy(h + sizeof hdr + pb, c->force(), 6 * (size_t)c->p.n_obj * 8,
+    const size_t fb = 6 * (size_t)c->p.n_obj * 8;
+    if ((s = c->hip(hipMemcpy(h + sizeof hdr + pb, c->force(), fb, hipMemcpyDeviceToHost), "state read")))
+        return s;
+    return c->hip(hipMemcpy(h + sizeof hdr + pb + fb, c->ws + c->lay.off_M,
+                            (size_t)c->n_moment_nodes * 3 * real_bytes(c->p.storage),
                             hipMemcpyDeviceToHost), "state read");
 }
 
@@ -965,11 +972,12 @@ lbm_status lbm_set_state(lbm_ctx *c, const void *host, size_t bytes)
     c->cur = c->ws + ((hdr[0] & 1) ? c->lay.off_B : c->lay.off_A);
     c->nxt = c->ws + ((hdr[0] & 1) ? c->lay.off_A : c->lay.off_B);
     if ((s = c->hip(hipMemcpy(c->cur, h + sizeof hdr, pb, hipMemcpyHostToDevice), "state write"))) return s;
-    if ((s = c->hip(hipMemcpy(c->force(), h + sizeof hdr + pb, 6 * (size_t)c->p.n_obj * 8,
-                              hipMemcpyHostToDevice), "state write")))
+    const size_t fb = 6 * (size_t)c->p.n_obj * 8;
+    if ((s = c->hip(hipMemcpy(c->force(), h + sizeof hdr + pb, fb, hipMemcpyHostToDevice), "state write")))
         return s;
-    if ((s = c->hip(lbm::launch_refresh(c->p.storage, c->grid(), c->phys(), c->cur, c->side(), c->stream),
-                    "side-moment refresh")))
+    if ((s = c->hip(hipMemcpy(c->ws + c->lay.off_M, h + sizeof hdr + pb + fb,
+                              (size_t)c->n_moment_nodes * 3 * real_bytes(c->p.storage),
+                              hipMemcpyHostToDevice), "state write")))
         return s;
     c->step = hdr[0];
     c->nsum = hdr[1];
