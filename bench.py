@@ -134,6 +134,9 @@ def main():
 
     lat.step(args.warmup)
     lat.sync()
+    cfg, tuned_ms = B.lbm_autotune(lat.ctx, 20)  # keeps the fastest launch shape, restores the state
+    print(f"[bench] autotuned {cfg.as_dict()} ({tuned_ms * 1e3:.1f} us/step)", file=sys.stderr,
+          flush=True)
     rho, ux, uy = lat.moments()  # raises LBM_E_UNSTABLE on a non-finite state
     torch.cuda.synchronize()
 
@@ -181,7 +184,8 @@ def main():
                    "body_force": case.gx, "n_discs": len(case.prims), "fluid_nodes": n_fluid,
                    "links": lat.n_links, "hbb_fallback_links": nfb,
                    "boundary": "VIBB (velocity-interpolation bounce-back)",
-                   "collision": "BGK + Guo forcing", "storage": args.storage},
+                   "collision": "BGK + Guo forcing", "storage": args.storage,
+                   "kernel_config": cfg.as_dict()},
         "mflups_fluid": round(n_fluid * args.steps / (ms * 1e-3) / 1e6, 1),
         "step_algorithmic_GBps": round((bulk_bytes + link_bytes) / (ms * 1e-3 / args.steps) / 1e9, 1),
         "roofline": {"bound": "hbm", "kernel": "bulk (pull + BGK collision)",

@@ -204,6 +204,26 @@ lbm_status lbm_set_state(lbm_ctx *ctx, const void *host, size_t bytes);
 lbm_status lbm_set_profiling(lbm_ctx *ctx, int32_t on);
 lbm_status lbm_kernel_times(lbm_ctx *ctx, double *link_ms, double *bulk_ms, int64_t *n_steps);
 
+/* Launch configuration of the step kernels.  Every configuration computes the same
+ * result; they differ in speed only. */
+typedef struct {
+    int32_t bulk_block_x;     /* bulk kernel: 64, 128 or 256 lanes along x per 256-lane block */
+    int32_t bulk_store_solid; /* 1: lanes of solid nodes store too, so rows are written in full lines */
+    int32_t link_block;       /* link kernel lanes per block: 64..1024, a multiple of 64 */
+    int32_t graph_steps;      /* steps per captured HIP graph: even, 2..1024 */
+} lbm_kernel_config;
+
+lbm_status lbm_get_kernel_config(const lbm_ctx *ctx, lbm_kernel_config *cfg);
+/* Errors: LBM_E_ARG for an unsupported configuration (the previous one stays). */
+lbm_status lbm_set_kernel_config(lbm_ctx *ctx, const lbm_kernel_config *cfg);
+
+/* Autotuner: times every bulk shape and link block size for steps_per_trial steps
+ * on the current state, keeps the fastest, and restores the state (populations,
+ * step counter, forces), so results do not depend on having tuned.  Needs host
+ * memory for one checkpoint.  chosen and best_ms_per_step may be NULL. */
+lbm_status lbm_autotune(lbm_ctx *ctx, int32_t steps_per_trial, lbm_kernel_config *chosen,
+                        double *best_ms_per_step);
+
 #ifdef __cplusplus
 }
 #endif

@@ -35,6 +35,14 @@ class lbm_params(C.Structure):
                 ("reserved", C.c_int32), ("stream", C.c_void_p)]
 
 
+class lbm_kernel_config(C.Structure):
+    _fields_ = [("bulk_block_x", C.c_int32), ("bulk_store_solid", C.c_int32),
+                ("link_block", C.c_int32), ("graph_steps", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class LbmError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
@@ -68,6 +76,9 @@ SIGNATURES = [
     ("lbm_set_state", _I32, [_P, _P, C.c_size_t]),
     ("lbm_set_profiling", _I32, [_P, _I32]),
     ("lbm_kernel_times", _I32, [_P, _P, _P, _P]),
+    ("lbm_get_kernel_config", _I32, [_P, _P]),
+    ("lbm_set_kernel_config", _I32, [_P, _P]),
+    ("lbm_autotune", _I32, [_P, _I32, _P, _P]),
 ]
 
 
@@ -257,6 +268,24 @@ def lbm_kernel_times(ctx):
     n = C.c_int64(0)
     check(lib().lbm_kernel_times(ctx, C.byref(a), C.byref(b), C.byref(n)), ctx)
     return a.value, b.value, n.value
+
+
+def lbm_get_kernel_config(ctx) -> lbm_kernel_config:
+    k = lbm_kernel_config()
+    check(lib().lbm_get_kernel_config(ctx, C.byref(k)), ctx)
+    return k
+
+
+def lbm_set_kernel_config(ctx, cfg: lbm_kernel_config):
+    check(lib().lbm_set_kernel_config(ctx, C.byref(cfg)), ctx)
+
+
+def lbm_autotune(ctx, steps_per_trial=20):
+    """Returns (chosen lbm_kernel_config, ms per step)."""
+    k = lbm_kernel_config()
+    ms = C.c_double(0)
+    check(lib().lbm_autotune(ctx, int(steps_per_trial), C.byref(k), C.byref(ms)), ctx)
+    return k, ms.value
 
 
 # ---------------------------------------------------------------------------

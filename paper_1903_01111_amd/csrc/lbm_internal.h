@@ -54,12 +54,26 @@ struct Links {
     int64_t n;
 };
 
+// Wavefront partial forces of the link kernel, reduced per object by a second
+// launch: capacity one entry per 64 links of capacity, rounded up to a block.
+struct Reduce {
+    double2 *wpart;
+    int32_t *wobj;
+};
+
+// Launch shape of the bulk kernel (chosen by the autotuner).
+struct BulkConfig {
+    int32_t block_x;      // 64, 128 or 256 lanes along x; 256/block_x rows
+    int32_t store_solid;  // lanes of solid nodes store zeros too (full-line writes)
+};
+
 hipError_t launch_link(int storage, const Grid &g, const Phys &ph, void *A, const Links &L,
-                       const void *M, double *force_bank, double *force_sum, hipStream_t s);
+                       const void *M, const Reduce &red, double *force_bank, double *force_sum,
+                       int block, hipStream_t s);
 
 hipError_t launch_bulk(int storage, const Grid &g, const Phys &ph, const void *A, void *B,
                        const uint8_t *mask, const void *uin, const Side &side, double *zero_bank,
-                       int32_t n_zero, hipStream_t s);
+                       int32_t n_zero, const BulkConfig &cf, hipStream_t s);
 
 // Recomputes the side moments of every flagged node from the populations in A
 // (after initialisation or a restored checkpoint).

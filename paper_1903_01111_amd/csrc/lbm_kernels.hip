@@ -131,9 +131,10 @@ __device__ __forceinline__ R deq(R w, R eu, R dr, R usq)
 // Link kernel.
 // ---------------------------------------------------------------------------
 template <int ST>
-__global__ __launch_bounds__(256) void link_kernel(Grid g, Phys ph, typename Codec<ST>::T *__restrict__ A,
-                                                   Links L, const typename Codec<ST>::R *__restrict__ M,
-                                                   double *__restrict__ bank, double *__restrict__ fsum)
+__global__ __launch_bounds__(1024) void link_kernel(Grid g, Phys ph, typename Codec<ST>::T *__restrict__ A,
+                                                    Links L, const typename Codec<ST>::R *__restrict__ M,
+                                                    double2 *__restrict__ wpart, int32_t *__restrict__ wobj,
+                                                    double *__restrict__ bank, double *__restrict__ fsum)
 {
     using C = Codec<ST>;
     using T = typename C::T;
@@ -201,8 +202,11 @@ __global__ __launch_bounds__(256) void link_kernel(Grid g, Phys ph, typename Cod
         fx = cxp * m;
         fy = cyp * m;
     }
-    // FP64 wavefront reduction; links are sorted by object, so a wavefront
-    // usually holds one object and issues one atomic pair.
+    // FP64 wavefront reduction.  Links are sorted by object, so a wavefront
+    // usually holds one object: it leaves one partial sum for force_reduce_kernel
+    // (no atomics: thousands of wavefronts adding into the same address would
+    // serialise).  A wavefront spanning several objects adds per lane.
+    const int64_t wave = l >> 6;
     const int obj0 = __shfl(obj, 0);
     const bool uniform = __all(obj == obj0 || obj < 0);
     if (uniform) {
@@ -211,17 +215,69 @@ __global__ __launch_bounds__(256) void link_kernel(Grid g, Phys ph, typename Cod
             fx += __shfl_xor(fx, off);
             fy += __shfl_xor(fy, off);
         }
-        if ((threadIdx.x & 63) == 0 && obj0 >= 0) {
-            unsafeAtomicAdd(&bank[2 * obj0], fx);
-            unsafeAtomicAdd(&bank[2 * obj0 + 1], fy);
-            unsafeAtomicAdd(&fsum[2 * obj0], fx);
-            unsafeAtomicAdd(&fsum[2 * obj0 + 1], fy);
+        if ((threadIdx.x & 63) == 0) {
+            wpart[wave] = make_double2(fx, fy);
+            wobj[wave] = obj0;
         }
-    } else if (obj >= 0) {
-        unsafeAtomicAdd(&bank[2 * obj], fx);
-        unsafeAtomicAdd(&bank[2 * obj + 1], fy);
-        unsafeAtomicAdd(&fsum[2 * obj], fx);
-        unsafeAtomicAdd(&fsum[2 * obj + 1], fy);
+    } else {
+        if (obj >= 0) {
+            unsafeAtomicAdd(&bank[2 * obj], fx);
+            unsafeAtomicAdd(&bank[2 * obj + 1], fy);
+            unsafeAtomicAdd(&fsum[2 * obj], fx);
+            unsafeAtomicAdd(&fsum[2 * obj + 1], fy);
+        }
+        if ((threadIdx.x & 63) == 0) wobj[wave] = -1;
+    }
+}
+
+// Sums the wavefront partials of the link kernel per object (they are in object
+// order) into this step's force bank and the running sum.  One block; each lane
+// walks a contiguous chunk, and lanes whose open segment is the same object
+// combine it across the wavefront before the atomic.
+__global__ __launch_bounds__(1024) void force_reduce_kernel(const double2 *__restrict__ wpart,
+                                                            const int32_t *__restrict__ wobj, int64_t nw,
+                                                            double *__restrict__ bank,
+                                                            double *__restrict__ fsum)
+{
+    const int64_t chunk = (nw + blockDim.x - 1) / blockDim.x;
+    const int64_t k0 = (int64_t)threadIdx.x * chunk;
+    const int64_t k1 = k0 + chunk < nw ? k0 + chunk : nw;
+    int cur = -1;
+    double ax = 0.0, ay = 0.0;
+    for (int64_t k = k0; k < k1; ++k) {
+        const int o = wobj[k];
+        if (o < 0) continue;
+        if (o != cur) {
+            if (cur >= 0) {
+                unsafeAtomicAdd(&bank[2 * cur], ax);
+                unsafeAtomicAdd(&bank[2 * cur + 1], ay);
+                unsafeAtomicAdd(&fsum[2 * cur], ax);
+                unsafeAtomicAdd(&fsum[2 * cur + 1], ay);
+            }
+            cur = o;
+            ax = ay = 0.0;
+        }
+        const double2 v = wpart[k];
+        ax += v.x;
+        ay += v.y;
+    }
+    int top = cur;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) top = max(top, __shfl_xor(top, off));
+    if (__all(cur == top || cur < 0)) {
+        if (cur < 0) ax = ay = 0.0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            ax += __shfl_xor(ax, off);
+            ay += __shfl_xor(ay, off);
+        }
+        cur = (threadIdx.x & 63) == 0 ? top : -1;
+    }
+    if (cur >= 0) {
+        unsafeAtomicAdd(&bank[2 * cur], ax);
+        unsafeAtomicAdd(&bank[2 * cur + 1], ay);
+        unsafeAtomicAdd(&fsum[2 * cur], ax);
+        unsafeAtomicAdd(&fsum[2 * cur + 1], ay);
     }
 }
 
@@ -231,7 +287,7 @@ __global__ __launch_bounds__(256) void link_kernel(Grid g, Phys ph, typename Cod
 // aligned 64-node run of a row, so each population plane is read and written
 // as contiguous 256-byte (FP32) runs.
 // ---------------------------------------------------------------------------
-template <int ST, bool OPEN, bool FORCE, int BX>
+template <int ST, bool OPEN, bool FORCE, int BX, bool STORE_SOLID>
 __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
                                                    const typename Codec<ST>::T *__restrict__ A,
                                                    typename Codec<ST>::T *__restrict__ B,
@@ -258,8 +314,18 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
     const uint8_t m = inside ? mask[row + x] : MASK_SOLID;
     // moment slots of the flagged nodes of this 64-node run (all lanes vote)
     const uint64_t flagged = __ballot((m & MASK_MOMENTS) != 0);
-    if (!inside || (m & MASK_SOLID)) return;
+    if (!inside) return;
     if (OPEN && (x == 0 || x == g.nx - 1)) return;
+    if (m & MASK_SOLID) {
+        if (STORE_SOLID) {
+            // solid slots of B are never read before the next link kernel rewrites
+            // the ones that matter; storing them keeps every cache line of B fully
+            // written (no partial-line writes at solid boundaries)
+#pragma unroll
+            for (int i = 0; i < 9; ++i) B[(int64_t)i * g.plane + row + x] = T(0);
+        }
+        return;
+    }
     const int lane = threadIdx.x & 63;
     const int32_t seg = y * (g.pitch >> 6) + (x >> 6);
 
@@ -472,43 +538,63 @@ __global__ __launch_bounds__(MASS_THREADS) void mass_kernel(Grid g, Phys ph,
 }
 
 template <int ST>
-hipError_t link_t(const Grid &g, const Phys &ph, void *A, const Links &L, const void *M, double *bank,
-                  double *fsum, hipStream_t s)
+hipError_t link_t(const Grid &g, const Phys &ph, void *A, const Links &L, const void *M,
+                  const Reduce &red, double *bank, double *fsum, int block, hipStream_t s)
 {
     if (L.n == 0) return hipSuccess;
-    const int threads = 256;
-    const unsigned blocks = (unsigned)((L.n + threads - 1) / threads);
-    hipLaunchKernelGGL(link_kernel<ST>, dim3(blocks), dim3(threads), 0, s, g, ph,
+    const unsigned blocks = (unsigned)((L.n + block - 1) / block);
+    hipLaunchKernelGGL(link_kernel<ST>, dim3(blocks), dim3(block), 0, s, g, ph,
                        static_cast<typename Codec<ST>::T *>(A), L,
-                       static_cast<const typename Codec<ST>::R *>(M), bank, fsum);
+                       static_cast<const typename Codec<ST>::R *>(M), red.wpart, red.wobj, bank, fsum);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t nw = (int64_t)blocks * (block / 64);
+    hipLaunchKernelGGL(force_reduce_kernel, dim3(1), dim3(1024), 0, s, red.wpart, red.wobj, nw, bank, fsum);
     return hipGetLastError();
 }
 
-constexpr int BULK_BX = 256;
-
-template <int ST, bool OPEN, bool FORCE>
+template <int ST, bool OPEN, bool FORCE, int BX, bool SS>
 hipError_t bulk_t(const Grid &g, const Phys &ph, const void *A, void *B, const uint8_t *mask,
                   const void *uin, const Side &side, double *zb, int32_t nz, hipStream_t s)
 {
     using C = Codec<ST>;
-    constexpr int BX = BULK_BX, BY = 256 / BULK_BX;
+    constexpr int BY = 256 / BX;
     dim3 grid((g.nx + BX - 1) / BX, (g.ny + BY - 1) / BY);
-    hipLaunchKernelGGL((bulk_kernel<ST, OPEN, FORCE, BX>), grid, dim3(BX, BY), 0, s, g, ph,
+    hipLaunchKernelGGL((bulk_kernel<ST, OPEN, FORCE, BX, SS>), grid, dim3(BX, BY), 0, s, g, ph,
                        static_cast<const typename C::T *>(A), static_cast<typename C::T *>(B), mask,
                        static_cast<const typename C::R *>(uin), side, zb, nz);
     return hipGetLastError();
 }
 
+template <int ST, bool OPEN, bool FORCE>
+hipError_t bulk_shape(const Grid &g, const Phys &ph, const void *A, void *B, const uint8_t *mask,
+                      const void *uin, const Side &side, double *zb, int32_t nz, const BulkConfig &cf,
+                      hipStream_t s)
+{
+#define LBM_BULK_SHAPE(BXV, SSV)                                                                  \
+    if (cf.block_x == BXV && cf.store_solid == SSV)                                              \
+        return bulk_t<ST, OPEN, FORCE, BXV, SSV>(g, ph, A, B, mask, uin, side, zb, nz, s);
+    LBM_BULK_SHAPE(64, false)
+    LBM_BULK_SHAPE(64, true)
+    LBM_BULK_SHAPE(128, false)
+    LBM_BULK_SHAPE(128, true)
+    LBM_BULK_SHAPE(256, false)
+    LBM_BULK_SHAPE(256, true)
+#undef LBM_BULK_SHAPE
+    return hipErrorInvalidValue;
+}
+
 template <int ST>
 hipError_t bulk_dispatch(const Grid &g, const Phys &ph, const void *A, void *B, const uint8_t *mask,
-                         const void *uin, const Side &side, double *zb, int32_t nz, hipStream_t s)
+                         const void *uin, const Side &side, double *zb, int32_t nz, const BulkConfig &cf,
+                         hipStream_t s)
 {
     const bool force = ph.gx != 0.0 || ph.gy != 0.0;
     if (g.x_open)
-        return force ? bulk_t<ST, true, true>(g, ph, A, B, mask, uin, side, zb, nz, s)
-                     : bulk_t<ST, true, false>(g, ph, A, B, mask, uin, side, zb, nz, s);
-    return force ? bulk_t<ST, false, true>(g, ph, A, B, mask, uin, side, zb, nz, s)
-                 : bulk_t<ST, false, false>(g, ph, A, B, mask, uin, side, zb, nz, s);
+        return force ? bulk_shape<ST, true, true>(g, ph, A, B, mask, uin, side, zb, nz, cf, s)
+                     : bulk_shape<ST, true, false>(g, ph, A, B, mask, uin, side, zb, nz, cf, s);
+    return force ? bulk_shape<ST, false, true>(g, ph, A, B, mask, uin, side, zb, nz, cf, s)
+                 : bulk_shape<ST, false, false>(g, ph, A, B, mask, uin, side, zb, nz, cf, s);
 }
 
 template <int ST>
@@ -523,26 +609,28 @@ hipError_t refresh_t(const Grid &g, const Phys &ph, const void *A, const Side &s
 }  // namespace
 
 hipError_t launch_link(int storage, const Grid &g, const Phys &ph, void *A, const Links &L,
-                       const void *M, double *bank, double *fsum, hipStream_t s)
+                       const void *M, const Reduce &red, double *bank, double *fsum, int block,
+                       hipStream_t s)
 {
+    if (block < 64 || block > 1024 || block % 64) return hipErrorInvalidValue;
     switch (storage) {
-    case 0: return link_t<0>(g, ph, A, L, M, bank, fsum, s);
-    case 1: return link_t<1>(g, ph, A, L, M, bank, fsum, s);
-    case 2: return link_t<2>(g, ph, A, L, M, bank, fsum, s);
-    case 3: return link_t<3>(g, ph, A, L, M, bank, fsum, s);
+    case 0: return link_t<0>(g, ph, A, L, M, red, bank, fsum, block, s);
+    case 1: return link_t<1>(g, ph, A, L, M, red, bank, fsum, block, s);
+    case 2: return link_t<2>(g, ph, A, L, M, red, bank, fsum, block, s);
+    case 3: return link_t<3>(g, ph, A, L, M, red, bank, fsum, block, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_bulk(int storage, const Grid &g, const Phys &ph, const void *A, void *B,
                        const uint8_t *mask, const void *uin, const Side &side, double *zb, int32_t nz,
-                       hipStream_t s)
+                       const BulkConfig &cf, hipStream_t s)
 {
     switch (storage) {
-    case 0: return bulk_dispatch<0>(g, ph, A, B, mask, uin, side, zb, nz, s);
-    case 1: return bulk_dispatch<1>(g, ph, A, B, mask, uin, side, zb, nz, s);
-    case 2: return bulk_dispatch<2>(g, ph, A, B, mask, uin, side, zb, nz, s);
-    case 3: return bulk_dispatch<3>(g, ph, A, B, mask, uin, side, zb, nz, s);
+    case 0: return bulk_dispatch<0>(g, ph, A, B, mask, uin, side, zb, nz, cf, s);
+    case 1: return bulk_dispatch<1>(g, ph, A, B, mask, uin, side, zb, nz, cf, s);
+    case 2: return bulk_dispatch<2>(g, ph, A, B, mask, uin, side, zb, nz, cf, s);
+    case 3: return bulk_dispatch<3>(g, ph, A, B, mask, uin, side, zb, nz, cf, s);
     default: return hipErrorInvalidValue;
     }
 }

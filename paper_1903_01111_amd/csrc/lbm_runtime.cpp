@@ -26,7 +26,6 @@ constexpr int OPPR[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 constexpr double WR[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
                           1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
 
-constexpr int GRAPH_STEPS = 16;        // steps per captured graph (even)
 constexpr int64_t STAGE_NODES = 1 << 20;  // nodes per read-back / init chunk
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -45,12 +44,14 @@ struct Layout {
     int32_t pitch;
     int64_t plane;  // elements per population plane
     size_t off_A, off_B, off_mask, off_segbase, off_nf, off_nff, off_ns, off_sf, off_sff, off_meta,
-        off_q, off_uw, off_mnode, off_M, off_uin, off_force, off_partials, off_stage, total;
+        off_q, off_uw, off_mnode, off_M, off_wpart, off_wobj, off_uin, off_force, off_partials,
+        off_stage, total;
+    int64_t wave_cap;  // wavefront partials of the link kernel
 };
 
 // device bytes per link of capacity (link arrays, and up to two flagged nodes
 // with their side moments)
-size_t bytes_per_link(int storage) { return 24 + 3 * real_bytes(storage) + 2 * (4 + 3 * real_bytes(storage)); }
+size_t bytes_per_link(int storage) { return 25 + 3 * real_bytes(storage) + 2 * (4 + 3 * real_bytes(storage)); }
 
 // Plane stride: rows padded to 64 elements; the plane size in 256-byte units is
 // kept odd so that the nine planes do not start on the same memory channel.
@@ -83,6 +84,9 @@ Layout make_layout(const lbm_params &p, int64_t max_links)
     L.off_uw = take(nl * 2 * rb);
     L.off_mnode = take(2 * nl * 4);
     L.off_M = take(2 * nl * 3 * rb);
+    L.wave_cap = (int64_t)(nl + 63) / 64 + 16;
+    L.off_wpart = take((size_t)L.wave_cap * 16);
+    L.off_wobj = take((size_t)L.wave_cap * 4);
     L.off_uin = take((size_t)p.ny * 2 * rb);
     L.off_force = take((size_t)p.n_obj * 6 * sizeof(double));
     L.off_partials = take(1024 * sizeof(double));
@@ -344,7 +348,8 @@ struct lbm_ctx {
     bool has_uw = false, have_geom = false, have_init = false;
     void *cur = nullptr, *nxt = nullptr;
     int64_t step = 0, nsum = 0;
-    // graph of GRAPH_STEPS steps starting from buffer `graph_cur`
+    lbm_kernel_config kcfg{256, 0, 256, 16};
+    // graph of kcfg.graph_steps steps starting from buffer `graph_cur`
     hipGraphExec_t gexec = nullptr;
     void *graph_cur = nullptr;
     // profiling
@@ -373,6 +378,12 @@ struct lbm_ctx {
                           reinterpret_cast<const uint32_t *>(ws + lay.off_meta),
                           ws + lay.off_q, has_uw ? ws + lay.off_uw : nullptr, n_links};
     }
+    lbm::Reduce reduce() const
+    {
+        return lbm::Reduce{reinterpret_cast<double2 *>(ws + lay.off_wpart),
+                           reinterpret_cast<int32_t *>(ws + lay.off_wobj)};
+    }
+    lbm::BulkConfig bulk_config() const { return lbm::BulkConfig{kcfg.bulk_block_x, kcfg.bulk_store_solid}; }
     lbm::Side side() const
     {
         return lbm::Side{ws + lay.off_M, reinterpret_cast<const int32_t *>(ws + lay.off_segbase),
@@ -430,13 +441,14 @@ lbm_status enqueue_step(lbm_ctx *c, bool timed)
         hipEventRecord(e0, c->stream);
     }
     lbm_status s = c->hip(lbm::launch_link(c->p.storage, g, ph, c->cur, c->links(), c->ws + c->lay.off_M,
-                                           c->bank(c->step), c->fsum(), c->stream),
+                                           c->reduce(), c->bank(c->step), c->fsum(), c->kcfg.link_block,
+                                           c->stream),
                           "link kernel launch");
     if (s) return s;
     if (timed) hipEventRecord(e1, c->stream);
     s = c->hip(lbm::launch_bulk(c->p.storage, g, ph, c->cur, c->nxt, c->mask(),
                                 c->ws + c->lay.off_uin, c->side(), c->bank(c->step + 1),
-                                2 * c->p.n_obj, c->stream), "bulk kernel launch");
+                                2 * c->p.n_obj, c->bulk_config(), c->stream), "bulk kernel launch");
     if (s) return s;
     if (timed) hipEventRecord(e2, c->stream);
     std::swap(c->cur, c->nxt);
@@ -461,7 +473,7 @@ lbm_status collect_times(lbm_ctx *c)
     return LBM_OK;
 }
 
-// Captures GRAPH_STEPS steps on a private stream (the caller's stream may be the
+// Captures kcfg.graph_steps steps on a private stream (the caller's stream may be the
 // null stream, which cannot be captured); the graph is launched on the caller's
 // stream.
 lbm_status build_graph(lbm_ctx *c)
@@ -483,7 +495,7 @@ lbm_status build_graph(lbm_ctx *c)
         c->stream = user;
         return s;
     }
-    for (int k = 0; k < GRAPH_STEPS && !s; ++k) s = enqueue_step(c, false);
+    for (int k = 0; k < c->kcfg.graph_steps && !s; ++k) s = enqueue_step(c, false);
     hipError_t e = hipStreamEndCapture(c->stream, &graph);
     c->stream = user;
     // capture only records; restore the host-side counters
@@ -755,14 +767,15 @@ lbm_status lbm_step(lbm_ctx *c, int64_t n)
         return LBM_OK;
     }
     while (n > 0) {
-        if (n >= GRAPH_STEPS) {
+        const int gs = c->kcfg.graph_steps;
+        if (n >= gs) {
             if (!c->gexec || c->graph_cur != c->cur) {
                 if ((s = build_graph(c))) return s;
             }
             if ((s = c->hip(hipGraphLaunch(c->gexec, c->stream), "hipGraphLaunch"))) return s;
-            c->step += GRAPH_STEPS;
-            c->nsum += GRAPH_STEPS;  // GRAPH_STEPS is even: buffers return to their roles
-            n -= GRAPH_STEPS;
+            c->step += gs;
+            c->nsum += gs;  // graph_steps is even: buffers return to their roles
+            n -= gs;
         } else {
             if ((s = enqueue_step(c, false))) return s;
             --n;
@@ -993,6 +1006,89 @@ lbm_status lbm_set_profiling(lbm_ctx *c, int32_t on)
     c->prof = on != 0;
     c->link_ms = c->bulk_ms = 0;
     c->prof_steps = 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_get_kernel_config(const lbm_ctx *c, lbm_kernel_config *cfg)
+{
+    if (!c || !cfg) return LBM_E_ARG;
+    *cfg = c->kcfg;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_kernel_config(lbm_ctx *c, const lbm_kernel_config *cfg)
+{
+    if (!c || !cfg) return LBM_E_ARG;
+    const int bx = cfg->bulk_block_x;
+    if ((bx != 64 && bx != 128 && bx != 256) || (cfg->bulk_store_solid != 0 && cfg->bulk_store_solid != 1) ||
+        cfg->link_block < 64 || cfg->link_block > 1024 || cfg->link_block % 64 ||
+        cfg->graph_steps < 2 || cfg->graph_steps > 1024 || cfg->graph_steps % 2)
+        return c->fail(LBM_E_ARG, "lbm_set_kernel_config: unsupported configuration");
+    c->drop_graph();
+    c->kcfg = *cfg;
+    return LBM_OK;
+}
+
+// Times every bulk shape and link block size on the current state (steps_per_trial
+// steps each, HIP events on the context's stream), keeps the fastest and restores
+// the state, so the run continues as if no trial had been made.
+lbm_status lbm_autotune(lbm_ctx *c, int32_t steps_per_trial, lbm_kernel_config *chosen,
+                        double *best_ms_per_step)
+{
+    if (!c || steps_per_trial < 1) return LBM_E_ARG;
+    if (!c->have_geom || !c->have_init) return c->fail(LBM_E_STATE, "lbm_autotune before initialisation");
+    std::vector<char> saved(lbm_state_bytes(c));
+    lbm_status s = lbm_get_state(c, saved.data(), saved.size());
+    if (s) return s;
+    const bool prof = c->prof;
+    if ((s = lbm_set_profiling(c, 0))) return s;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return c->fail(LBM_E_DEVICE, "hipEventCreate failed");
+    const lbm_kernel_config base = c->kcfg;
+    lbm_kernel_config best = base;
+    double best_ms = 1e300;
+    auto trial = [&](const lbm_kernel_config &k, double *ms) -> lbm_status {
+        lbm_status r = lbm_set_kernel_config(c, &k);
+        if (r) return r;
+        for (int w = 0; w < 2; ++w)
+            if ((r = enqueue_step(c, false))) return r;
+        hipEventRecord(e0, c->stream);
+        for (int t = 0; t < steps_per_trial; ++t)
+            if ((r = enqueue_step(c, false))) return r;
+        hipEventRecord(e1, c->stream);
+        if ((r = c->hip(hipEventSynchronize(e1), "autotune"))) return r;
+        float f = 0;
+        hipEventElapsedTime(&f, e0, e1);
+        *ms = f / steps_per_trial;
+        return LBM_OK;
+    };
+    for (int bx : {64, 128, 256})
+        for (int ss : {0, 1}) {
+            lbm_kernel_config k = best;
+            k.bulk_block_x = bx;
+            k.bulk_store_solid = ss;
+            double ms;
+            if ((s = trial(k, &ms))) break;
+            if (ms < best_ms) best_ms = ms, best = k;
+        }
+    for (int lb : {128, 256, 512, 1024}) {
+        if (s) break;
+        lbm_kernel_config k = best;
+        k.link_block = lb;
+        double ms;
+        if ((s = trial(k, &ms))) break;
+        if (ms < best_ms) best_ms = ms, best = k;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    lbm_status r = lbm_set_kernel_config(c, s ? &base : &best);
+    if (!r) r = lbm_set_state(c, saved.data(), saved.size());
+    if (!r) r = lbm_set_profiling(c, prof ? 1 : 0);
+    if (s) return s;
+    if (r) return r;
+    if (chosen) *chosen = best;
+    if (best_ms_per_step) *best_ms_per_step = best_ms;
     return LBM_OK;
 }
 

@@ -237,3 +237,55 @@ def test_full_size_workloads_short(B, which):
     else:
         case, n = W.porous_medium(), 3
     compare(B, case, "f32", n, tol_u=1e-5, tol_f=2e-5)
+
+
+# --- launch configurations and the autotuner ------------------------------------
+
+def test_every_kernel_config_gives_the_same_result(B):
+    """Bulk shapes, solid-lane stores, link block sizes and graph lengths change
+    speed only: populations bitwise equal, forces equal up to atomic order."""
+    case = small_porous(150, 70, seed=12)
+    ref = B.Lattice(case, storage="f32")
+    ref.step(45)
+    fr = ref.populations()
+    _, sr, _ = ref.force()
+    ref.close()
+    for bx in (64, 128, 256):
+        for ss in (0, 1):
+            for lb, gs in ((64, 2), (1024, 30)):
+                lat = B.Lattice(case, storage="f32")
+                B.lbm_set_kernel_config(lat.ctx, B.lbm_kernel_config(bx, ss, lb, gs))
+                lat.step(45)
+                assert np.array_equal(lat.populations(), fr), (bx, ss, lb, gs)
+                _, s, _ = lat.force()
+                assert np.abs(s - sr).max() <= 1e-12 * np.abs(sr).max()
+                lat.close()
+
+
+def test_invalid_kernel_config_is_rejected(B):
+    lat = B.Lattice(small_cylinder(64, 32, 4.0), storage="f32")
+    for bad in ((96, 0, 256, 16), (256, 2, 256, 16), (256, 0, 100, 16), (256, 0, 256, 3)):
+        with pytest.raises(B.LbmError) as e:
+            B.lbm_set_kernel_config(lat.ctx, B.lbm_kernel_config(*bad))
+        assert e.value.status == B.LBM_E_ARG
+    assert B.lbm_get_kernel_config(lat.ctx).as_dict() == dict(bulk_block_x=256, bulk_store_solid=0,
+                                                             link_block=256, graph_steps=16)
+    lat.close()
+
+
+def test_autotune_restores_the_state(B):
+    case = small_porous(128, 96, seed=13)
+    a = B.Lattice(case, storage="f32")
+    a.step(10)
+    cfg, ms = B.lbm_autotune(a.ctx, 3)
+    assert ms > 0 and cfg.bulk_block_x in (64, 128, 256)
+    assert B.lbm_step_count(a.ctx) == 10
+    a.step(10)
+    b = B.Lattice(case, storage="f32")
+    b.step(20)
+    assert np.array_equal(a.populations(), b.populations())
+    _, sa, na = a.force()
+    _, sb, nb = b.force()
+    assert na == nb == 20 and np.abs(sa - sb).max() <= 1e-12 * np.abs(sb).max()
+    a.close()
+    b.close()
