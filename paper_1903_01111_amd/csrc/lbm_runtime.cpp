@@ -587,15 +587,19 @@ lbm_status lbm_create(const lbm_params *p, void *workspace, size_t bytes, lbm_ct
         g_thread_error = "lbm_create: workspace must be non-null and 256-byte aligned";
         return LBM_E_ARG;
     }
-    // largest link capacity the workspace holds
-    const Layout base = make_layout(*p, 0);
-    if (bytes < base.total) {
+    // largest link capacity the workspace holds (layout size is monotone in it)
+    if (bytes < make_layout(*p, 0).total) {
         g_thread_error = "lbm_create: workspace too small";
         return LBM_E_NOMEM;
     }
-    const size_t per_link = bytes_per_link(p->storage);
-    int64_t cap = (int64_t)((bytes - base.total) / per_link);
-    while (cap > 0 && make_layout(*p, cap).total > bytes) --cap;
+    int64_t lo = 0, hi = (int64_t)(bytes / bytes_per_link(p->storage)) + 1;
+    while (make_layout(*p, hi).total <= bytes) hi *= 2;
+    while (hi - lo > 1) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (make_layout(*p, mid).total <= bytes) lo = mid;
+        else hi = mid;
+    }
+    const int64_t cap = lo;
     lbm_ctx *c = new (std::nothrow) lbm_ctx;
     if (!c) {
         g_thread_error = "lbm_create: out of host memory";
