@@ -23,39 +23,53 @@ struct Phys {
     float inv_scale;  // 2^-k
 };
 
-// Mask byte of a node: bit 0 solid, bit 1 "moments wanted" (the node is x_f or
-// x_ff of some VIBB link).  The bulk kernel stores (rho - 1, ux, uy) of every
-// flagged node after collision; the link kernel of the next step reads them
-// instead of gathering the nine populations of both nodes.  The slot of a
-// flagged node is its rank in plane order: seg_base[y*pitch/64 + x/64] (flagged
-// nodes before that 64-node row segment) plus the flagged lanes below it in its
-// wavefront.
-constexpr uint8_t MASK_SOLID = 1, MASK_MOMENTS = 2;
+// Mask byte of a node: bit 0 solid, bit 1 "side record" -- the node is x_f of a
+// link or x_ff of a VIBB link.  Flagged nodes are numbered (slot) in plane order:
+// the slot of a node is seg[y*pitch/64 + x/64].flagged (flagged nodes before
+// its 64-node row segment) plus the flagged lanes below it in its wavefront.
+constexpr uint8_t MASK_SOLID = 1, MASK_SIDE = 2;
 
+// Per 64-node row segment: flagged nodes, links and deposited populations that
+// come before it in plane order.
+struct SegBase {
+    int32_t flagged, links, pops, pad;
+};
+
+// Data exchanged between the bulk kernel and the link kernel through compact
+// arrays, so that neither touches the population planes at random:
+//  - after collision the bulk kernel deposits, for every flagged node, its
+//    moments (rho - 1, ux, uy) into M and the post-collision populations the
+//    links will need (rec bits 8..15) into P;
+//  - the link kernel reads M and P and writes the value of every link into L,
+//    in (node, dir) order;
+//  - the next bulk kernel pulls direction i of a node from L instead of from the
+//    solid neighbour x - e_i (rec bits 0..7 mark the node's link directions).
 struct Side {
-    void *M;                  // real[3K]: rho - 1, ux, uy (physical velocity)
-    const int32_t *seg_base;  // [ny * pitch / 64]
-    const int32_t *mnode;     // [K] plane offset of each flagged node
+    void *M;                 // real[3K]
+    void *P;                 // storage[NP]
+    void *L;                 // storage[n_links]
+    const uint16_t *rec;     // [K] bit d-1: link in direction d; bit d+7: population d deposited
+    const SegBase *seg;      // [ny * pitch / 64]
+    const int32_t *mnode;    // [K] plane offset of each flagged node
+    const int32_t *pbase;    // [K] first P entry of each flagged node
     int64_t K;
 };
 
-// Compacted boundary links, sorted by (obj, node).  Indices are offsets inside
-// a plane.  meta = dir | (obj << 8).
+// Links in (obj, node, dir) order, so a wavefront usually serves one object.
 struct Links {
-    const int32_t *nf;   // x_f
-    const int32_t *nff;  // x_ff = x_f - e_{i'}, or -1: halfway bounce-back
-    const int32_t *ns;   // x_s = x_f + e_{i'}: its slot of plane i = opp(i')
-                         // receives f_i(x_f, t+1) for the next pull
-    const int32_t *sf;   // moment slot of x_f (VIBB links)
-    const int32_t *sff;  // moment slot of x_ff (VIBB links)
-    const uint32_t *meta;
-    const void *q;       // real[n]
-    const void *uw;      // real[2n] or nullptr (still walls)
+    const uint32_t *meta;  // dir | (obj << 8)
+    const void *q;         // real[n]
+    const void *uw;        // real[2n] or nullptr (still walls)
+    const int32_t *sf;     // moment slot of x_f
+    const int32_t *sff;    // moment slot of x_ff, or -1: halfway bounce-back
+    const int32_t *pf;     // P entry of f+_{i'}(x_f)
+    const int32_t *pff;    // P entry of f+_{i'}(x_ff) (VIBB links)
+    const int32_t *li;     // rank of the link in (node, dir) order: its L entry
     int64_t n;
 };
 
 // Wavefront partial forces of the link kernel, reduced per object by a second
-// launch: capacity one entry per 64 links of capacity, rounded up to a block.
+// launch: one entry per 64 links of capacity, plus a block of slack.
 struct Reduce {
     double2 *wpart;
     int32_t *wobj;
@@ -67,18 +81,18 @@ struct BulkConfig {
     int32_t store_solid;  // lanes of solid nodes store zeros too (full-line writes)
 };
 
-hipError_t launch_link(int storage, const Grid &g, const Phys &ph, void *A, const Links &L,
-                       const void *M, const Reduce &red, double *force_bank, double *force_sum,
-                       int block, hipStream_t s);
+hipError_t launch_link(int storage, const Grid &g, const Phys &ph, const Links &L, const Side &side,
+                       const Reduce &red, double *force_bank, double *force_sum, int block,
+                       hipStream_t s);
 
 hipError_t launch_bulk(int storage, const Grid &g, const Phys &ph, const void *A, void *B,
                        const uint8_t *mask, const void *uin, const Side &side, double *zero_bank,
                        int32_t n_zero, const BulkConfig &cf, hipStream_t s);
 
-// Recomputes the side moments of every flagged node from the populations in A
-// (after initialisation or a restored checkpoint).
+// Rebuilds the deposited populations P (and, with moments, M) of every flagged
+// node from the populations in A: after initialisation or a restored checkpoint.
 hipError_t launch_refresh(int storage, const Grid &g, const Phys &ph, const void *A,
-                          const Side &side, hipStream_t s);
+                          const Side &side, bool moments, hipStream_t s);
 
 // Equilibrium initialisation of rows [y0, y0+rows) of A from staged doubles
 // (rho, ux, uy interleaved per node, rows*nx nodes).

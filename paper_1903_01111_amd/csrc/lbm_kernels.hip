@@ -128,11 +128,10 @@ __device__ __forceinline__ R deq(R w, R eu, R dr, R usq)
 }
 
 // ---------------------------------------------------------------------------
-// Link kernel.
+// Link kernel: one lane per link, reading only compact arrays.
 // ---------------------------------------------------------------------------
 template <int ST>
-__global__ __launch_bounds__(1024) void link_kernel(Grid g, Phys ph, typename Codec<ST>::T *__restrict__ A,
-                                                    Links L, const typename Codec<ST>::R *__restrict__ M,
+__global__ __launch_bounds__(1024) void link_kernel(Grid g, Phys ph, Links L, Side side,
                                                     double2 *__restrict__ wpart, int32_t *__restrict__ wobj,
                                                     double *__restrict__ bank, double *__restrict__ fsum)
 {
@@ -144,13 +143,14 @@ __global__ __launch_bounds__(1024) void link_kernel(Grid g, Phys ph, typename Co
     double fx = 0.0, fy = 0.0;
     int obj = -1;
     if (active) {
-        const int32_t nf = L.nf[l], nff = L.nff[l], ns = L.ns[l];
         const uint32_t meta = L.meta[l];
-        const int ip = (int)(meta & 15u), i = opp_of(ip);
+        const int ip = (int)(meta & 15u);
         obj = (int)(meta >> 8);
         const int cxp = cx_of(ip), cyp = cy_of(ip);
         const R w = ip <= 4 ? R(1) / R(9) : R(1) / R(36);
         const R *qv = static_cast<const R *>(L.q);
+        const T *P = static_cast<const T *>(side.P);
+        const R *M = static_cast<const R *>(side.M);
         R uwx = R(0), uwy = R(0);
         if (L.uw) {
             const R *u = static_cast<const R *>(L.uw);
@@ -159,17 +159,17 @@ __global__ __launch_bounds__(1024) void link_kernel(Grid g, Phys ph, typename Co
         }
         // moving-wall momentum term 6 w_{i'} rho0 e_i.u_w, with e_i = -e_{i'}
         const R wall = -R(6) * w * R(ph.rho0) * (R(cxp) * uwx + R(cyp) * uwy);
-        const T *Aip = A + (int64_t)ip * g.plane;
-        const R fpf = C::ld(Aip[nf], ph.inv_scale);
+        const R fpf = C::ld(P[L.pf[l]], ph.inv_scale);
+        const int32_t sff = L.sff[l];
         R v;
-        if (nff < 0) {
+        if (sff < 0) {
             v = fpf + wall;  // halfway bounce-back
         } else {
-            // moments of f and ff at time t, stored by the previous bulk step
-            const int32_t sf = L.sf[l], sff = L.sff[l];
+            // moments of f and ff at time t, deposited by the previous bulk step
+            const int32_t sf = L.sf[l];
             const R drf = M[3 * sf], ufx = M[3 * sf + 1], ufy = M[3 * sf + 2];
             const R drff = M[3 * sff], uffx = M[3 * sff + 1], uffy = M[3 * sff + 2];
-            const R fpff = C::ld(Aip[nff], ph.inv_scale);
+            const R fpff = C::ld(P[L.pff[l]], ph.inv_scale);
             const R q = qv[l];
             const R a2q = R(2) * q, b2q = R(1) - R(2) * q;
             // density at the departure point d (extrapolated when q > 1/2)
@@ -196,7 +196,7 @@ __global__ __launch_bounds__(1024) void link_kernel(Grid g, Phys ph, typename Co
             const R udx = (usx + R(2) * ussx) / R(3), udy = (usy + R(2) * ussy) / R(3);
             v = deq(w, R(cxp) * udx + R(cyp) * udy, drd, udx * udx + udy * udy) + neqd + wall;
         }
-        A[(int64_t)i * g.plane + ns] = C::st(v, ph.scale);
+        static_cast<T *>(side.L)[L.li[l]] = C::st(v, ph.scale);
         // momentum exchange: f+_{i'}(x_f) into the wall and f_i(x_f) back, both along e_{i'}
         const double m = (double)fpf + (double)v + 2.0 * (double)w;
         fx = cxp * m;
@@ -231,17 +231,18 @@ __global__ __launch_bounds__(1024) void link_kernel(Grid g, Phys ph, typename Co
 }
 
 // Sums the wavefront partials of the link kernel per object (they are in object
-// order) into this step's force bank and the running sum.  One block; each lane
-// walks a contiguous chunk, and lanes whose open segment is the same object
+// order) into this step's force bank and the running sum.  Each lane walks
+// REDUCE_CHUNK consecutive partials; lanes whose open segment is the same object
 // combine it across the wavefront before the atomic.
-__global__ __launch_bounds__(1024) void force_reduce_kernel(const double2 *__restrict__ wpart,
-                                                            const int32_t *__restrict__ wobj, int64_t nw,
-                                                            double *__restrict__ bank,
-                                                            double *__restrict__ fsum)
+constexpr int REDUCE_CHUNK = 16;
+
+__global__ __launch_bounds__(256) void force_reduce_kernel(const double2 *__restrict__ wpart,
+                                                           const int32_t *__restrict__ wobj, int64_t nw,
+                                                           double *__restrict__ bank,
+                                                           double *__restrict__ fsum)
 {
-    const int64_t chunk = (nw + blockDim.x - 1) / blockDim.x;
-    const int64_t k0 = (int64_t)threadIdx.x * chunk;
-    const int64_t k1 = k0 + chunk < nw ? k0 + chunk : nw;
+    const int64_t k0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * REDUCE_CHUNK;
+    const int64_t k1 = k0 + REDUCE_CHUNK < nw ? k0 + REDUCE_CHUNK : nw;
     int cur = -1;
     double ax = 0.0, ay = 0.0;
     for (int64_t k = k0; k < k1; ++k) {
@@ -285,8 +286,12 @@ __global__ __launch_bounds__(1024) void force_reduce_kernel(const double2 *__res
 // Bulk kernel: pull, moments, BGK + Guo, store.  A block of BX x (256/BX) lanes
 // covers BX consecutive nodes of 256/BX rows; every 64-lane wavefront is one
 // aligned 64-node run of a row, so each population plane is read and written
-// as contiguous 256-byte (FP32) runs.
+// as contiguous runs.  Boundary nodes pull their cut directions from L and
+// deposit what the next link kernel needs into M and P; their indices into
+// those compact arrays come from per-segment bases plus wavefront prefix sums.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int popc32(uint32_t v) { return __popc(v); }
+
 template <int ST, bool OPEN, bool FORCE, int BX, bool STORE_SOLID>
 __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
                                                    const typename Codec<ST>::T *__restrict__ A,
@@ -309,25 +314,61 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
     }
     const int x = blockIdx.x * BX + threadIdx.x;
     const int y = blockIdx.y * BY + threadIdx.y;
-    const bool inside = x < g.nx && y < g.ny;
+    // a wavefront is one 64-node row segment: leave together if it lies outside
+    if (y >= g.ny || (x >> 6) >= (g.pitch >> 6)) return;
+    const bool inside = x < g.nx;
     const int32_t row = y * g.pitch;
     const uint8_t m = inside ? mask[row + x] : MASK_SOLID;
-    // moment slots of the flagged nodes of this 64-node run (all lanes vote)
-    const uint64_t flagged = __ballot((m & MASK_MOMENTS) != 0);
+    const int lane = threadIdx.x & 63;
+    const int32_t seg = __builtin_amdgcn_readfirstlane(y * (g.pitch >> 6) + (x >> 6));
+    const SegBase sb = side.seg[seg];
+    const uint64_t flagged = __ballot((m & MASK_SIDE) != 0);
+    const int32_t slot = sb.flagged + (int32_t)__popcll(flagged & ((1ull << lane) - 1ull));
+    const uint32_t rec = (m & MASK_SIDE) ? side.rec[slot] : 0u;
+    // exclusive wavefront prefix of (links, deposited populations) per node
+    const uint32_t cnt = (uint32_t)popc32(rec & 0xffu) | ((uint32_t)popc32(rec >> 8) << 16);
+    uint32_t inc = cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = __shfl_up(inc, off);
+        if (lane >= off) inc += t;
+    }
+    const uint32_t exc = inc - cnt;
+    const int32_t lbase = sb.links + (int32_t)(exc & 0xffffu);
+    const int32_t pbase = sb.pops + (int32_t)(exc >> 16);
+    // the open columns are written by their neighbour lanes: fetch their records
+    uint32_t rec_in = 0, rec_out = 0;
+    int32_t pb_in = 0, pb_out = 0, slot_out = 0;
+    if (OPEN) {
+        rec_in = __shfl(rec, 0);
+        pb_in = __shfl(pbase, 0);
+        const int xe = g.nx - 1;
+        const int le = xe & 63;
+        const uint32_t r_e = __shfl(rec, le);
+        const int32_t p_e = __shfl(pbase, le);
+        if ((xe >> 6) == (x >> 6)) {
+            rec_out = r_e;
+            pb_out = p_e;
+            slot_out = sb.flagged + (int32_t)__popcll(flagged & ((1ull << le) - 1ull));
+        } else if (x == g.nx - 2 && (mask[row + xe] & MASK_SIDE)) {
+            // x_e starts the next segment of the row
+            const SegBase sn = side.seg[seg + 1];
+            slot_out = sn.flagged;
+            rec_out = side.rec[slot_out];
+            pb_out = sn.pops;
+        }
+    }
     if (!inside) return;
     if (OPEN && (x == 0 || x == g.nx - 1)) return;
     if (m & MASK_SOLID) {
         if (STORE_SOLID) {
-            // solid slots of B are never read before the next link kernel rewrites
-            // the ones that matter; storing them keeps every cache line of B fully
-            // written (no partial-line writes at solid boundaries)
+            // solid slots of B are never read; storing them keeps every cache line
+            // of B fully written (no partial-line writes at solid boundaries)
 #pragma unroll
             for (int i = 0; i < 9; ++i) B[(int64_t)i * g.plane + row + x] = T(0);
         }
         return;
     }
-    const int lane = threadIdx.x & 63;
-    const int32_t seg = y * (g.pitch >> 6) + (x >> 6);
 
     int xm, xp;
     if (OPEN) {
@@ -341,18 +382,25 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
     const int32_t rp = (y == g.ny - 1 ? 0 : y + 1) * g.pitch;
     const int64_t P = g.plane;
     const float inv = ph.inv_scale;
+    const T *Lv = static_cast<const T *>(side.L);
 
-    // pull: f_i(x, t+1) = f+_i(x - e_i, t)
+    // pull: f_i(x, t+1) = f+_i(x - e_i, t), or the link value where x - e_i is
+    // solid (link (x, i') with i' = opp(i), bit i'-1 of rec)
+    auto pull = [&](int i, int ip, int32_t src) -> R {
+        const uint32_t bit = 1u << (ip - 1);
+        const T *p = (rec & bit) ? Lv + lbase + popc32(rec & (bit - 1u)) : A + i * P + src;
+        return C::ld(*p, inv);
+    };
     R f[9];
     f[0] = C::ld(A[row + x], inv);
-    f[1] = C::ld(A[1 * P + row + xm], inv);
-    f[2] = C::ld(A[2 * P + rm + x], inv);
-    f[3] = C::ld(A[3 * P + row + xp], inv);
-    f[4] = C::ld(A[4 * P + rp + x], inv);
-    f[5] = C::ld(A[5 * P + rm + xm], inv);
-    f[6] = C::ld(A[6 * P + rm + xp], inv);
-    f[7] = C::ld(A[7 * P + rp + xp], inv);
-    f[8] = C::ld(A[8 * P + rp + xm], inv);
+    f[1] = pull(1, 3, row + xm);
+    f[2] = pull(2, 4, rm + x);
+    f[3] = pull(3, 1, row + xp);
+    f[4] = pull(4, 2, rp + x);
+    f[5] = pull(5, 7, rm + xm);
+    f[6] = pull(6, 8, rm + xp);
+    f[7] = pull(7, 5, rp + xp);
+    f[8] = pull(8, 6, rp + xm);
 
     const R drho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
     const R jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
@@ -381,14 +429,20 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
         f[i] = v;
         B[i * P + row + x] = C::st(v, ph.scale);
     }
-    // the post-collision moments are the collision's own (rho, u): with Guo's
-    // shift the physical velocity of f+ equals the collision velocity
+    // deposits for the next link kernel.  The post-collision moments are the
+    // collision's own (rho, u): with Guo's shift the physical velocity of f+
+    // equals the collision velocity.
     R *Mv = static_cast<R *>(side.M);
-    if (m & MASK_MOMENTS) {
-        const int32_t k = side.seg_base[seg] + (int32_t)__popcll(flagged & ((1ull << lane) - 1ull));
-        Mv[3 * k] = drho;
-        Mv[3 * k + 1] = ux;
-        Mv[3 * k + 2] = uy;
+    T *Pv = static_cast<T *>(side.P);
+    if (m & MASK_SIDE) {
+        Mv[3 * slot] = drho;
+        Mv[3 * slot + 1] = ux;
+        Mv[3 * slot + 2] = uy;
+#pragma unroll
+        for (int d = 1; d < 9; ++d) {
+            const uint32_t bit = 1u << (d + 7);
+            if (rec & bit) Pv[pbase + popc32((rec >> 8) & ((1u << (d - 1)) - 1u))] = C::st(f[d], ph.scale);
+        }
     }
     if (OPEN) {
         if (x == 1 && !(mask[row] & MASK_SOLID)) {
@@ -396,20 +450,27 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
             // f+(0) = f^eq(rho_1, u_in) + f+(1) - f^eq(rho_1, u_1); its moments are (rho_1, u_in)
             const R vx = uin[2 * y], vy = uin[2 * y + 1];
             const R vsq = vx * vx + vy * vy;
+            R f0[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 const R w = wgt<R>(i);
                 const R ev = R(CX[i]) * vx + R(CY[i]) * vy;
                 const R eu = R(CX[i]) * ux + R(CY[i]) * uy;
                 const R dp = poly(ev, vsq) - poly(eu, usq);
-                const R d = w * (dp + drho * dp);
-                B[i * P + row] = C::st(f[i] + d, ph.scale);
+                f0[i] = f[i] + w * (dp + drho * dp);
+                B[i * P + row] = C::st(f0[i], ph.scale);
             }
             if (flagged & 1ull) {
-                const int32_t k = side.seg_base[y * (g.pitch >> 6)];
+                const int32_t k = sb.flagged;
                 Mv[3 * k] = drho;
                 Mv[3 * k + 1] = vx;
                 Mv[3 * k + 2] = vy;
+#pragma unroll
+                for (int d = 1; d < 9; ++d) {
+                    const uint32_t bit = 1u << (d + 7);
+                    if (rec_in & bit)
+                        Pv[pb_in + popc32((rec_in >> 8) & ((1u << (d - 1)) - 1u))] = C::st(f0[d], ph.scale);
+                }
             }
         }
         const uint8_t me = mask[row + g.nx - 1];
@@ -417,30 +478,41 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
             // zero-gradient outlet: copy every population of the last fluid column
 #pragma unroll
             for (int i = 0; i < 9; ++i) B[i * P + row + g.nx - 1] = C::st(f[i], ph.scale);
-            if (me & MASK_MOMENTS) {
-                const int xe = g.nx - 1;
-                const int32_t k = ((xe >> 6) == (x >> 6))
-                                      ? side.seg_base[seg] + (int32_t)__popcll(flagged & ((1ull << (xe & 63)) - 1ull))
-                                      : side.seg_base[seg + 1];
-                Mv[3 * k] = drho;
-                Mv[3 * k + 1] = ux;
-                Mv[3 * k + 2] = uy;
+            if (me & MASK_SIDE) {
+                Mv[3 * slot_out] = drho;
+                Mv[3 * slot_out + 1] = ux;
+                Mv[3 * slot_out + 2] = uy;
+#pragma unroll
+                for (int d = 1; d < 9; ++d) {
+                    const uint32_t bit = 1u << (d + 7);
+                    if (rec_out & bit)
+                        Pv[pb_out + popc32((rec_out >> 8) & ((1u << (d - 1)) - 1u))] = C::st(f[d], ph.scale);
+                }
             }
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Initialisation, side-moment refresh, moments and mass.
+// Initialisation, deposit refresh, moments and mass.
 // ---------------------------------------------------------------------------
 template <int ST>
-__global__ void refresh_kernel(Grid g, Phys ph, const typename Codec<ST>::T *__restrict__ A, Side side)
+__global__ void refresh_kernel(Grid g, Phys ph, const typename Codec<ST>::T *__restrict__ A, Side side,
+                               int moments)
 {
     using C = Codec<ST>;
+    using T = typename C::T;
     using R = typename C::R;
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= side.K) return;
     const int32_t n = side.mnode[k];
+    const uint32_t rec = side.rec[k];
+    T *Pv = static_cast<T *>(side.P);
+    int32_t pb = side.pbase[k];
+#pragma unroll
+    for (int d = 1; d < 9; ++d)
+        if (rec & (1u << (d + 7))) Pv[pb++] = A[(int64_t)d * g.plane + n];
+    if (!moments) return;
     R dr = R(0), jx = R(0), jy = R(0);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -538,18 +610,19 @@ __global__ __launch_bounds__(MASS_THREADS) void mass_kernel(Grid g, Phys ph,
 }
 
 template <int ST>
-hipError_t link_t(const Grid &g, const Phys &ph, void *A, const Links &L, const void *M,
-                  const Reduce &red, double *bank, double *fsum, int block, hipStream_t s)
+hipError_t link_t(const Grid &g, const Phys &ph, const Links &L, const Side &side, const Reduce &red,
+                  double *bank, double *fsum, int block, hipStream_t s)
 {
     if (L.n == 0) return hipSuccess;
     const unsigned blocks = (unsigned)((L.n + block - 1) / block);
-    hipLaunchKernelGGL(link_kernel<ST>, dim3(blocks), dim3(block), 0, s, g, ph,
-                       static_cast<typename Codec<ST>::T *>(A), L,
-                       static_cast<const typename Codec<ST>::R *>(M), red.wpart, red.wobj, bank, fsum);
+    hipLaunchKernelGGL(link_kernel<ST>, dim3(blocks), dim3(block), 0, s, g, ph, L, side, red.wpart,
+                       red.wobj, bank, fsum);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t nw = (int64_t)blocks * (block / 64);
-    hipLaunchKernelGGL(force_reduce_kernel, dim3(1), dim3(1024), 0, s, red.wpart, red.wobj, nw, bank, fsum);
+    const int64_t lanes = (nw + REDUCE_CHUNK - 1) / REDUCE_CHUNK;
+    hipLaunchKernelGGL(force_reduce_kernel, dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, s,
+                       red.wpart, red.wobj, nw, bank, fsum);
     return hipGetLastError();
 }
 
@@ -598,26 +671,26 @@ hipError_t bulk_dispatch(const Grid &g, const Phys &ph, const void *A, void *B, 
 }
 
 template <int ST>
-hipError_t refresh_t(const Grid &g, const Phys &ph, const void *A, const Side &side, hipStream_t s)
+hipError_t refresh_t(const Grid &g, const Phys &ph, const void *A, const Side &side, bool moments,
+                     hipStream_t s)
 {
     if (side.K == 0) return hipSuccess;
     hipLaunchKernelGGL(refresh_kernel<ST>, dim3((unsigned)((side.K + 255) / 256)), dim3(256), 0, s, g,
-                       ph, static_cast<const typename Codec<ST>::T *>(A), side);
+                       ph, static_cast<const typename Codec<ST>::T *>(A), side, moments ? 1 : 0);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_link(int storage, const Grid &g, const Phys &ph, void *A, const Links &L,
-                       const void *M, const Reduce &red, double *bank, double *fsum, int block,
-                       hipStream_t s)
+hipError_t launch_link(int storage, const Grid &g, const Phys &ph, const Links &L, const Side &side,
+                       const Reduce &red, double *bank, double *fsum, int block, hipStream_t s)
 {
     if (block < 64 || block > 1024 || block % 64) return hipErrorInvalidValue;
     switch (storage) {
-    case 0: return link_t<0>(g, ph, A, L, M, red, bank, fsum, block, s);
-    case 1: return link_t<1>(g, ph, A, L, M, red, bank, fsum, block, s);
-    case 2: return link_t<2>(g, ph, A, L, M, red, bank, fsum, block, s);
-    case 3: return link_t<3>(g, ph, A, L, M, red, bank, fsum, block, s);
+    case 0: return link_t<0>(g, ph, L, side, red, bank, fsum, block, s);
+    case 1: return link_t<1>(g, ph, L, side, red, bank, fsum, block, s);
+    case 2: return link_t<2>(g, ph, L, side, red, bank, fsum, block, s);
+    case 3: return link_t<3>(g, ph, L, side, red, bank, fsum, block, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -636,13 +709,13 @@ hipError_t launch_bulk(int storage, const Grid &g, const Phys &ph, const void *A
 }
 
 hipError_t launch_refresh(int storage, const Grid &g, const Phys &ph, const void *A, const Side &side,
-                          hipStream_t s)
+                          bool moments, hipStream_t s)
 {
     switch (storage) {
-    case 0: return refresh_t<0>(g, ph, A, side, s);
-    case 1: return refresh_t<1>(g, ph, A, side, s);
-    case 2: return refresh_t<2>(g, ph, A, side, s);
-    case 3: return refresh_t<3>(g, ph, A, side, s);
+    case 0: return refresh_t<0>(g, ph, A, side, moments, s);
+    case 1: return refresh_t<1>(g, ph, A, side, moments, s);
+    case 2: return refresh_t<2>(g, ph, A, side, moments, s);
+    case 3: return refresh_t<3>(g, ph, A, side, moments, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -43,15 +43,18 @@ size_t real_bytes(int storage) { return storage == LBM_F64 ? 8 : 4; }
 struct Layout {
     int32_t pitch;
     int64_t plane;  // elements per population plane
-    size_t off_A, off_B, off_mask, off_segbase, off_nf, off_nff, off_ns, off_sf, off_sff, off_meta,
-        off_q, off_uw, off_mnode, off_M, off_wpart, off_wobj, off_uin, off_force, off_partials,
-        off_stage, total;
+    size_t off_A, off_B, off_mask, off_seg, off_meta, off_q, off_uw, off_sf, off_sff, off_pf, off_pff,
+        off_li, off_L, off_rec, off_mnode, off_pbase, off_M, off_P, off_wpart, off_wobj, off_uin,
+        off_force, off_partials, off_stage, total;
     int64_t wave_cap;  // wavefront partials of the link kernel
 };
 
 // device bytes per link of capacity (link arrays, and up to two flagged nodes
 // with their side moments)
-size_t bytes_per_link(int storage) { return 25 + 3 * real_bytes(storage) + 2 * (4 + 3 * real_bytes(storage)); }
+size_t bytes_per_link(int storage)
+{
+    return 45 + 9 * real_bytes(storage) + 3 * elem_bytes(storage);
+}
 
 // Plane stride: rows padded to 64 elements; the plane size in 256-byte units is
 // kept odd so that the nine planes do not start on the same memory channel.
@@ -72,18 +75,23 @@ Layout make_layout(const lbm_params &p, int64_t max_links)
     L.off_A = take(9 * pb);
     L.off_B = take(9 * pb);
     L.off_mask = take((size_t)L.pitch * p.ny);
-    L.off_segbase = take((size_t)(L.pitch / 64) * p.ny * 4);
+    L.off_seg = take((size_t)(L.pitch / 64) * p.ny * sizeof(lbm::SegBase));
     const size_t nl = (size_t)std::max<int64_t>(max_links, 0);
-    L.off_nf = take(nl * 4);
-    L.off_nff = take(nl * 4);
-    L.off_ns = take(nl * 4);
-    L.off_sf = take(nl * 4);
-    L.off_sff = take(nl * 4);
     L.off_meta = take(nl * 4);
     L.off_q = take(nl * rb);
     L.off_uw = take(nl * 2 * rb);
+    L.off_sf = take(nl * 4);
+    L.off_sff = take(nl * 4);
+    L.off_pf = take(nl * 4);
+    L.off_pff = take(nl * 4);
+    L.off_li = take(nl * 4);
+    L.off_L = take(nl * eb);
+    // at most two flagged nodes and two deposited populations per link
+    L.off_rec = take(2 * nl * 2);
     L.off_mnode = take(2 * nl * 4);
+    L.off_pbase = take(2 * nl * 4);
     L.off_M = take(2 * nl * 3 * rb);
+    L.off_P = take(2 * nl * eb);
     L.wave_cap = (int64_t)(nl + 63) / 64 + 16;
     L.off_wpart = take((size_t)L.wave_cap * 16);
     L.off_wobj = take((size_t)L.wave_cap * 4);
@@ -149,12 +157,16 @@ bool params_ok(const lbm_params *p, std::string *why)
 }
 
 struct Prepared {
-    std::vector<int32_t> nf, nff, ns, sf, sff;
+    // per link, in (obj, node, dir) order
     std::vector<uint32_t> meta;
     std::vector<double> q, uw;
-    std::vector<uint8_t> mask;       // padded to the pitch: solid bit, moments bit
-    std::vector<int32_t> seg_base;   // flagged nodes before each 64-node row segment
-    std::vector<int32_t> mnode;      // plane offset of each flagged node, in slot order
+    std::vector<int32_t> sf, sff, pf, pff, li;
+    // per flagged node, in plane order
+    std::vector<uint16_t> rec;
+    std::vector<int32_t> mnode, pbase;
+    std::vector<uint8_t> mask;             // padded to the pitch: solid bit, side bit
+    std::vector<lbm::SegBase> seg;         // per 64-node row segment
+    int64_t n_pops = 0;
     bool has_uw = false;
     int64_t n_fallback = 0;
 };
@@ -260,6 +272,58 @@ lbm_status prepare_geometry(const lbm_params &p, const uint8_t *mask, int64_t n,
             }
         }
     if (!out) return LBM_OK;
+    // second node of each link (-1: halfway bounce-back, by scheme or because x_ff is solid)
+    std::vector<int32_t> ffo(n);  // plane offset of x_ff
+    out->n_fallback = 0;
+    for (int64_t l = 0; l < n; ++l) {
+        const int nd = node[l], d = dir[l], x = nd % nx, y = nd / nx;
+        int xf2 = x - EXR[d];
+        const int yf2 = (y - EYR[d] + ny) % ny;
+        bool ff_ok = !(open && (xf2 < 0 || xf2 >= nx));
+        xf2 = (xf2 + nx) % nx;
+        if (ff_ok && mask[(int64_t)yf2 * nx + xf2]) ff_ok = false;
+        const bool vibb = !scheme || scheme[l] == LBM_SCHEME_VIBB;
+        if (vibb && !ff_ok) ++out->n_fallback;
+        ffo[l] = (vibb && ff_ok) ? yf2 * pitch + xf2 : -1;
+    }
+    // padded mask; padding columns count as solid and are never streamed
+    const size_t plane_n = (size_t)pitch * ny;
+    out->mask.assign(plane_n, lbm::MASK_SOLID);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x)
+            out->mask[(size_t)y * pitch + x] = mask[(int64_t)y * nx + x] ? lbm::MASK_SOLID : 0;
+    // per-node record bits: link directions at x_f, deposited populations at x_f and x_ff
+    std::vector<uint16_t> bits(plane_n, 0);
+    for (int64_t l = 0; l < n; ++l) {
+        const int nd = node[l], d = dir[l];
+        const int32_t of = (nd / nx) * pitch + nd % nx;
+        bits[of] |= (uint16_t)((1u << (d - 1)) | (1u << (d + 7)));
+        if (ffo[l] >= 0) bits[ffo[l]] |= (uint16_t)(1u << (d + 7));
+    }
+    // slots, segment bases, deposit bases
+    const int64_t nseg = (int64_t)(pitch / 64) * ny;
+    out->seg.assign((size_t)nseg, lbm::SegBase{0, 0, 0, 0});
+    out->rec.clear();
+    out->mnode.clear();
+    out->pbase.clear();
+    std::vector<int32_t> slot(plane_n, -1);
+    int32_t nlinks = 0, npops = 0;
+    for (int64_t sg = 0; sg < nseg; ++sg) {
+        out->seg[sg] = lbm::SegBase{(int32_t)out->rec.size(), nlinks, npops, 0};
+        for (int64_t o = sg * 64; o < sg * 64 + 64; ++o) {
+            if (!bits[o]) continue;
+            out->mask[o] |= lbm::MASK_SIDE;
+            slot[o] = (int32_t)out->rec.size();
+            out->rec.push_back(bits[o]);
+            out->mnode.push_back((int32_t)o);
+            out->pbase.push_back(npops);
+            nlinks += __builtin_popcount(bits[o] & 0xffu);
+            npops += __builtin_popcount(bits[o] >> 8);
+        }
+    }
+    out->n_pops = npops;
+    auto rank_below = [](uint32_t set, int d) { return __builtin_popcount(set & ((1u << (d - 1)) - 1u)); };
+    // links in (obj, node, dir) order; L entry = rank in (node, dir) order
     std::vector<int64_t> order(n);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
@@ -268,69 +332,51 @@ lbm_status prepare_geometry(const lbm_params &p, const uint8_t *mask, int64_t n,
         if (node[a] != node[b]) return node[a] < node[b];
         return dir[a] < dir[b];
     });
-    out->nf.resize(n);
-    out->nff.resize(n);
-    out->ns.resize(n);
     out->meta.resize(n);
     out->q.resize(n);
+    out->sf.assign(n, -1);
+    out->sff.assign(n, -1);
+    out->pf.resize(n);
+    out->pff.assign(n, -1);
+    out->li.resize(n);
     out->has_uw = false;
     if (uw)
         for (int64_t l = 0; l < n && !out->has_uw; ++l)
             out->has_uw = uw[2 * l] != 0.0 || uw[2 * l + 1] != 0.0;
     out->uw.assign(out->has_uw ? 2 * n : 0, 0.0);
-    out->n_fallback = 0;
-    // padded mask; padding columns count as solid and are never streamed
-    out->mask.assign((size_t)pitch * ny, lbm::MASK_SOLID);
-    for (int y = 0; y < ny; ++y)
-        for (int x = 0; x < nx; ++x)
-            out->mask[(size_t)y * pitch + x] = mask[(int64_t)y * nx + x] ? lbm::MASK_SOLID : 0;
     for (int64_t k = 0; k < n; ++k) {
         const int64_t l = order[k];
-        const int nd = node[l], d = dir[l], x = nd % nx, y = nd / nx;
-        const int xs = (x + EXR[d] + nx) % nx, ys = (y + EYR[d] + ny) % ny;
-        int xf2 = x - EXR[d];
-        const int yf2 = (y - EYR[d] + ny) % ny;
-        bool ff_ok = true;
-        if (open && (xf2 < 0 || xf2 >= nx)) ff_ok = false;
-        xf2 = (xf2 + nx) % nx;
-        if (ff_ok && mask[(int64_t)yf2 * nx + xf2]) ff_ok = false;
-        const bool vibb = !scheme || scheme[l] == LBM_SCHEME_VIBB;
-        if (vibb && !ff_ok) ++out->n_fallback;
-        out->nf[k] = y * pitch + x;
-        out->nff[k] = (vibb && ff_ok) ? yf2 * pitch + xf2 : -1;
-        out->ns[k] = ys * pitch + xs;
+        const int nd = node[l], d = dir[l];
+        const int32_t of = (nd / nx) * pitch + nd % nx;
+        const int32_t sfo = slot[of];
         out->meta[k] = (uint32_t)d | ((uint32_t)(obj ? obj[l] : 0) << 8);
         out->q[k] = q[l];
         if (out->has_uw) {
             out->uw[2 * k] = uw[2 * l];
             out->uw[2 * k + 1] = uw[2 * l + 1];
         }
-        if (out->nff[k] >= 0) {
-            out->mask[out->nf[k]] |= lbm::MASK_MOMENTS;
-            out->mask[out->nff[k]] |= lbm::MASK_MOMENTS;
+        out->sf[k] = sfo;
+        out->pf[k] = out->pbase[sfo] + rank_below(out->rec[sfo] >> 8, d);
+        if (ffo[l] >= 0) {
+            const int32_t sff = slot[ffo[l]];
+            out->sff[k] = sff;
+            out->pff[k] = out->pbase[sff] + rank_below(out->rec[sff] >> 8, d);
         }
     }
-    // moment slots: rank of each flagged node in plane order
-    const int64_t nseg = (int64_t)(pitch / 64) * ny;
-    out->seg_base.assign((size_t)nseg, 0);
-    out->mnode.clear();
-    std::vector<int32_t> slot;  // plane offset -> slot, only read for flagged nodes
-    slot.assign(out->mask.size(), -1);
-    for (int64_t sgm = 0; sgm < nseg; ++sgm) {
-        out->seg_base[sgm] = (int32_t)out->mnode.size();
-        for (int64_t o = sgm * 64; o < sgm * 64 + 64; ++o)
-            if (out->mask[o] & lbm::MASK_MOMENTS) {
-                slot[o] = (int32_t)out->mnode.size();
-                out->mnode.push_back((int32_t)o);
-            }
-    }
-    out->sf.assign(n, -1);
-    out->sff.assign(n, -1);
-    for (int64_t k = 0; k < n; ++k)
-        if (out->nff[k] >= 0) {
-            out->sf[k] = slot[out->nf[k]];
-            out->sff[k] = slot[out->nff[k]];
+    // L entry of a link: links of earlier nodes plus the link's rank at its node
+    std::vector<int32_t> links_before(out->rec.size());
+    {
+        int32_t acc = 0;
+        for (size_t k = 0; k < out->rec.size(); ++k) {
+            links_before[k] = acc;
+            acc += __builtin_popcount(out->rec[k] & 0xffu);
         }
+    }
+    for (int64_t k = 0; k < n; ++k) {
+        const int d = (int)(out->meta[k] & 15u);
+        const int32_t sfo = out->sf[k];
+        out->li[k] = links_before[sfo] + rank_below(out->rec[sfo] & 0xffu, d);
+    }
     return LBM_OK;
 }
 
@@ -370,13 +416,10 @@ struct lbm_ctx {
     }
     lbm::Links links() const
     {
-        return lbm::Links{reinterpret_cast<const int32_t *>(ws + lay.off_nf),
-                          reinterpret_cast<const int32_t *>(ws + lay.off_nff),
-                          reinterpret_cast<const int32_t *>(ws + lay.off_ns),
-                          reinterpret_cast<const int32_t *>(ws + lay.off_sf),
-                          reinterpret_cast<const int32_t *>(ws + lay.off_sff),
-                          reinterpret_cast<const uint32_t *>(ws + lay.off_meta),
-                          ws + lay.off_q, has_uw ? ws + lay.off_uw : nullptr, n_links};
+        auto i32 = [&](size_t off) { return reinterpret_cast<const int32_t *>(ws + off); };
+        return lbm::Links{reinterpret_cast<const uint32_t *>(ws + lay.off_meta), ws + lay.off_q,
+                          has_uw ? ws + lay.off_uw : nullptr, i32(lay.off_sf), i32(lay.off_sff),
+                          i32(lay.off_pf), i32(lay.off_pff), i32(lay.off_li), n_links};
     }
     lbm::Reduce reduce() const
     {
@@ -386,8 +429,11 @@ struct lbm_ctx {
     lbm::BulkConfig bulk_config() const { return lbm::BulkConfig{kcfg.bulk_block_x, kcfg.bulk_store_solid}; }
     lbm::Side side() const
     {
-        return lbm::Side{ws + lay.off_M, reinterpret_cast<const int32_t *>(ws + lay.off_segbase),
-                         reinterpret_cast<const int32_t *>(ws + lay.off_mnode), n_moment_nodes};
+        return lbm::Side{ws + lay.off_M, ws + lay.off_P, ws + lay.off_L,
+                         reinterpret_cast<const uint16_t *>(ws + lay.off_rec),
+                         reinterpret_cast<const lbm::SegBase *>(ws + lay.off_seg),
+                         reinterpret_cast<const int32_t *>(ws + lay.off_mnode),
+                         reinterpret_cast<const int32_t *>(ws + lay.off_pbase), n_moment_nodes};
     }
     uint8_t *mask() const { return reinterpret_cast<uint8_t *>(ws + lay.off_mask); }
     double *force() const { return reinterpret_cast<double *>(ws + lay.off_force); }
@@ -440,9 +486,8 @@ lbm_status enqueue_step(lbm_ctx *c, bool timed)
         c->ev_used += 3;
         hipEventRecord(e0, c->stream);
     }
-    lbm_status s = c->hip(lbm::launch_link(c->p.storage, g, ph, c->cur, c->links(), c->ws + c->lay.off_M,
-                                           c->reduce(), c->bank(c->step), c->fsum(), c->kcfg.link_block,
-                                           c->stream),
+    lbm_status s = c->hip(lbm::launch_link(c->p.storage, g, ph, c->links(), c->side(), c->reduce(),
+                                           c->bank(c->step), c->fsum(), c->kcfg.link_block, c->stream),
                           "link kernel launch");
     if (s) return s;
     if (timed) hipEventRecord(e1, c->stream);
@@ -659,17 +704,23 @@ lbm_status lbm_set_geometry(lbm_ctx *c, const uint8_t *mask, int64_t n_links, co
         qsrc = qf.data();
         uwsrc = uwf.data();
     }
+    const size_t K = prep.rec.size();
     struct Up {
         size_t off;
         const void *src;
         size_t bytes;
-    } ups[] = {{c->lay.off_nf, prep.nf.data(), n * 4},   {c->lay.off_nff, prep.nff.data(), n * 4},
-               {c->lay.off_ns, prep.ns.data(), n * 4},   {c->lay.off_sf, prep.sf.data(), n * 4},
-               {c->lay.off_sff, prep.sff.data(), n * 4}, {c->lay.off_meta, prep.meta.data(), n * 4},
+    } ups[] = {{c->lay.off_meta, prep.meta.data(), n * 4},
                {c->lay.off_q, qsrc, n * rb},
                {c->lay.off_uw, uwsrc, prep.has_uw ? 2 * n * rb : 0},
-               {c->lay.off_segbase, prep.seg_base.data(), prep.seg_base.size() * 4},
-               {c->lay.off_mnode, prep.mnode.data(), prep.mnode.size() * 4}};
+               {c->lay.off_sf, prep.sf.data(), n * 4},
+               {c->lay.off_sff, prep.sff.data(), n * 4},
+               {c->lay.off_pf, prep.pf.data(), n * 4},
+               {c->lay.off_pff, prep.pff.data(), n * 4},
+               {c->lay.off_li, prep.li.data(), n * 4},
+               {c->lay.off_rec, prep.rec.data(), K * 2},
+               {c->lay.off_mnode, prep.mnode.data(), K * 4},
+               {c->lay.off_pbase, prep.pbase.data(), K * 4},
+               {c->lay.off_seg, prep.seg.data(), prep.seg.size() * sizeof(lbm::SegBase)}};
     for (const Up &u : ups)
         if (u.bytes && (s = c->hip(hipMemcpyAsync(c->ws + u.off, u.src, u.bytes,
                                                   hipMemcpyHostToDevice, st), "link upload")))
@@ -684,7 +735,7 @@ lbm_status lbm_set_geometry(lbm_ctx *c, const uint8_t *mask, int64_t n_links, co
     if ((s = c->hip(hipStreamSynchronize(st), "geometry upload")))  // host vectors die here
         return s;
     c->n_links = n_links;
-    c->n_moment_nodes = (int64_t)prep.mnode.size();
+    c->n_moment_nodes = (int64_t)prep.rec.size();
     c->has_uw = prep.has_uw;
     c->have_geom = true;
     c->have_init = false;
@@ -750,8 +801,8 @@ lbm_status lbm_init_equilibrium(lbm_ctx *c, const double *rho, const double *ux,
         if ((s = c->hip(hipStreamSynchronize(c->stream), "init")))  // h is reused
             return s;
     }
-    if ((s = c->hip(lbm::launch_refresh(c->p.storage, c->grid(), c->phys(), c->cur, c->side(), c->stream),
-                    "side-moment refresh")))
+    if ((s = c->hip(lbm::launch_refresh(c->p.storage, c->grid(), c->phys(), c->cur, c->side(), true,
+                                        c->stream), "deposit refresh")))
         return s;
     c->have_init = true;
     return LBM_OK;
@@ -995,6 +1046,10 @@ lbm_status lbm_set_state(lbm_ctx *c, const void *host, size_t bytes)
     if ((s = c->hip(hipMemcpy(c->ws + c->lay.off_M, h + sizeof hdr + pb + fb,
                               (size_t)c->n_moment_nodes * 3 * real_bytes(c->p.storage),
                               hipMemcpyHostToDevice), "state write")))
+        return s;
+    // the deposited populations are copies of stored values: rebuilt exactly
+    if ((s = c->hip(lbm::launch_refresh(c->p.storage, c->grid(), c->phys(), c->cur, c->side(), false,
+                                        c->stream), "deposit refresh")))
         return s;
     c->step = hdr[0];
     c->nsum = hdr[1];
