@@ -305,6 +305,9 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
     using T = typename C::T;
     using R = typename C::R;
     constexpr int BY = 256 / BX;
+    // per wavefront: deposits of up to 64 nodes (3 moments, up to 8 populations each)
+    __shared__ R lds_m[4][3 * 64];
+    __shared__ T lds_p[4][8 * 64];
     {
         // clear the force bank of the next step
         const int64_t gt = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * 256 +
@@ -336,20 +339,34 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
     const uint32_t exc = inc - cnt;
     const int32_t lbase = sb.links + (int32_t)(exc & 0xffffu);
     const int32_t pbase = sb.pops + (int32_t)(exc >> 16);
-    // the open columns are written by their neighbour lanes: fetch their records
+    const int wave_pops = (int)(__shfl(inc, 63) >> 16);
+    const int wave_flagged = (int)__popcll(flagged);
+    // the open columns are written by their neighbour lanes: fetch their records,
+    // and keep their deposits out of the wavefront's coalesced flush
     uint32_t rec_in = 0, rec_out = 0;
     int32_t pb_in = 0, pb_out = 0, slot_out = 0;
+    int m_lo = 0, m_hi = 3 * wave_flagged, p_lo = 0, p_hi = wave_pops;
     if (OPEN) {
         rec_in = __shfl(rec, 0);
         pb_in = __shfl(pbase, 0);
+        const uint32_t cnt_in = __shfl(cnt, 0);
+        if ((x >> 6) == 0 && (flagged & 1ull)) {
+            m_lo = 3;
+            p_lo = (int)(cnt_in >> 16);
+        }
         const int xe = g.nx - 1;
         const int le = xe & 63;
         const uint32_t r_e = __shfl(rec, le);
         const int32_t p_e = __shfl(pbase, le);
+        const uint32_t c_e = __shfl(cnt, le);
         if ((xe >> 6) == (x >> 6)) {
             rec_out = r_e;
             pb_out = p_e;
             slot_out = sb.flagged + (int32_t)__popcll(flagged & ((1ull << le) - 1ull));
+            if ((flagged >> le) & 1ull) {
+                m_hi -= 3;
+                p_hi -= (int)(c_e >> 16);
+            }
         } else if (x == g.nx - 2 && (mask[row + xe] & MASK_SIDE)) {
             // x_e starts the next segment of the row
             const SegBase sn = side.seg[seg + 1];
@@ -429,20 +446,37 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
         f[i] = v;
         B[i * P + row + x] = C::st(v, ph.scale);
     }
-    // deposits for the next link kernel.  The post-collision moments are the
-    // collision's own (rho, u): with Guo's shift the physical velocity of f+
-    // equals the collision velocity.
+    // deposits for the next link kernel, staged in LDS so that the wavefront
+    // writes its contiguous ranges of M and P in full lines.  The post-collision
+    // moments are the collision's own (rho, u): with Guo's shift the physical
+    // velocity of f+ equals the collision velocity.
     R *Mv = static_cast<R *>(side.M);
     T *Pv = static_cast<T *>(side.P);
+    const int wv = (threadIdx.y * BX + threadIdx.x) >> 6;
     if (m & MASK_SIDE) {
-        Mv[3 * slot] = drho;
-        Mv[3 * slot + 1] = ux;
-        Mv[3 * slot + 2] = uy;
+        const int ls = slot - sb.flagged;
+        lds_m[wv][3 * ls] = drho;
+        lds_m[wv][3 * ls + 1] = ux;
+        lds_m[wv][3 * ls + 2] = uy;
+        const int lp = (int)(exc >> 16);
 #pragma unroll
         for (int d = 1; d < 9; ++d) {
             const uint32_t bit = 1u << (d + 7);
-            if (rec & bit) Pv[pbase + popc32((rec >> 8) & ((1u << (d - 1)) - 1u))] = C::st(f[d], ph.scale);
+            if (rec & bit) lds_p[wv][lp + popc32((rec >> 8) & ((1u << (d - 1)) - 1u))] = C::st(f[d], ph.scale);
         }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    {
+        // lanes still running share the flush
+        const uint64_t act = __ballot(1);
+        const int arank = (int)__popcll(act & ((1ull << lane) - 1ull));
+        const int acnt = (int)__popcll(act);
+        R *Mw = Mv + 3 * (int64_t)sb.flagged;
+        for (int j = m_lo + arank; j < m_hi; j += acnt) Mw[j] = lds_m[wv][j];
+        T *Pw = Pv + sb.pops;
+        for (int j = p_lo + arank; j < p_hi; j += acnt) Pw[j] = lds_p[wv][j];
     }
     if (OPEN) {
         if (x == 1 && !(mask[row] & MASK_SOLID)) {
