@@ -322,6 +322,33 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
     const bool inside = x < g.nx;
     const int32_t row = y * g.pitch;
     const uint8_t m = inside ? mask[row + x] : MASK_SOLID;
+    const int64_t P = g.plane;
+    // The nine pulls f_i(x, t+1) = f+_i(x - e_i, t) are issued before the node
+    // type and the link records are known, so that their latency overlaps the
+    // record lookups; values of solid lanes, and those of directions whose
+    // source is solid (replaced by link values below), are discarded.
+    // Padding lanes (x >= nx) load the last column and are discarded too.
+    const int xc = inside ? x : g.nx - 1;
+    int xm, xp;
+    if (OPEN) {
+        xm = xc > 0 ? xc - 1 : 0;
+        xp = xc < g.nx - 1 ? xc + 1 : g.nx - 1;
+    } else {
+        xm = xc == 0 ? g.nx - 1 : xc - 1;
+        xp = xc == g.nx - 1 ? 0 : xc + 1;
+    }
+    const int32_t rm = (y == 0 ? g.ny - 1 : y - 1) * g.pitch;
+    const int32_t rp = (y == g.ny - 1 ? 0 : y + 1) * g.pitch;
+    T a[9];
+    a[0] = A[row + xc];
+    a[1] = A[1 * P + row + xm];
+    a[2] = A[2 * P + rm + xc];
+    a[3] = A[3 * P + row + xp];
+    a[4] = A[4 * P + rp + xc];
+    a[5] = A[5 * P + rm + xm];
+    a[6] = A[6 * P + rm + xp];
+    a[7] = A[7 * P + rp + xp];
+    a[8] = A[8 * P + rp + xm];
     const int lane = threadIdx.x & 63;
     const int32_t seg = __builtin_amdgcn_readfirstlane(y * (g.pitch >> 6) + (x >> 6));
     const SegBase sb = side.seg[seg];
@@ -387,37 +414,25 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
         return;
     }
 
-    int xm, xp;
-    if (OPEN) {
-        xm = x - 1;
-        xp = x + 1;
-    } else {
-        xm = x == 0 ? g.nx - 1 : x - 1;
-        xp = x == g.nx - 1 ? 0 : x + 1;
-    }
-    const int32_t rm = (y == 0 ? g.ny - 1 : y - 1) * g.pitch;
-    const int32_t rp = (y == g.ny - 1 ? 0 : y + 1) * g.pitch;
-    const int64_t P = g.plane;
     const float inv = ph.inv_scale;
     const T *Lv = static_cast<const T *>(side.L);
-
-    // pull: f_i(x, t+1) = f+_i(x - e_i, t), or the link value where x - e_i is
-    // solid (link (x, i') with i' = opp(i), bit i'-1 of rec)
-    auto pull = [&](int i, int ip, int32_t src) -> R {
+    // where x - e_i is solid, the link (x, i') with i' = opp(i) (bit i'-1 of rec)
+    // supplies the population instead
+    auto pull = [&](int ip, T av) -> R {
         const uint32_t bit = 1u << (ip - 1);
-        const T *p = (rec & bit) ? Lv + lbase + popc32(rec & (bit - 1u)) : A + i * P + src;
-        return C::ld(*p, inv);
+        const T v = (rec & bit) ? Lv[lbase + popc32(rec & (bit - 1u))] : av;
+        return C::ld(v, inv);
     };
     R f[9];
-    f[0] = C::ld(A[row + x], inv);
-    f[1] = pull(1, 3, row + xm);
-    f[2] = pull(2, 4, rm + x);
-    f[3] = pull(3, 1, row + xp);
-    f[4] = pull(4, 2, rp + x);
-    f[5] = pull(5, 7, rm + xm);
-    f[6] = pull(6, 8, rm + xp);
-    f[7] = pull(7, 5, rp + xp);
-    f[8] = pull(8, 6, rp + xm);
+    f[0] = C::ld(a[0], inv);
+    f[1] = pull(3, a[1]);
+    f[2] = pull(4, a[2]);
+    f[3] = pull(1, a[3]);
+    f[4] = pull(2, a[4]);
+    f[5] = pull(7, a[5]);
+    f[6] = pull(8, a[6]);
+    f[7] = pull(5, a[7]);
+    f[8] = pull(6, a[8]);
 
     const R drho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
     const R jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
