@@ -23,11 +23,14 @@ struct Phys {
     float inv_scale;  // 2^-k
 };
 
-// Mask byte of a node: bit 0 solid, bit 1 "side record" -- the node is x_f of a
-// link or x_ff of a VIBB link.  Flagged nodes are numbered (slot) in plane order:
-// the slot of a node is seg[y*pitch/64 + x/64].flagged (flagged nodes before
-// its 64-node row segment) plus the flagged lanes below it in its wavefront.
-constexpr uint8_t MASK_SOLID = 1, MASK_SIDE = 2;
+// Per-node mask word: bits 0..7 the directions d (bit d-1) of the node's links
+// (the pulls of directions opp(d) come from link values), bit 8 solid, bit 9
+// "side record" -- the node is x_f of a link or x_ff of a VIBB link.  Flagged
+// nodes are numbered (slot) in plane order: the slot of a node is
+// seg[y*pitch/64 + x/64].flagged (flagged nodes before its 64-node row segment)
+// plus the flagged lanes below it in its wavefront.
+using mask_t = uint16_t;
+constexpr mask_t MASK_LINKS = 0xff, MASK_SOLID = 0x100, MASK_SIDE = 0x200;
 
 // Per 64-node row segment: flagged nodes, links and deposited populations that
 // come before it in plane order.
@@ -86,7 +89,7 @@ hipError_t launch_link(int storage, const Grid &g, const Phys &ph, const Links &
                        hipStream_t s);
 
 hipError_t launch_bulk(int storage, const Grid &g, const Phys &ph, const void *A, void *B,
-                       const uint8_t *mask, const void *uin, const Side &side, double *zero_bank,
+                       const mask_t *mask, const void *uin, const Side &side, double *zero_bank,
                        int32_t n_zero, const BulkConfig &cf, hipStream_t s);
 
 // Rebuilds the deposited populations P (and, with moments, M) of every flagged
@@ -96,17 +99,17 @@ hipError_t launch_refresh(int storage, const Grid &g, const Phys &ph, const void
 
 // Equilibrium initialisation of rows [y0, y0+rows) of A from staged doubles
 // (rho, ux, uy interleaved per node, rows*nx nodes).
-hipError_t launch_init(int storage, const Grid &g, const Phys &ph, void *A, const uint8_t *mask,
+hipError_t launch_init(int storage, const Grid &g, const Phys &ph, void *A, const mask_t *mask,
                        const double *stage, int32_t y0, int32_t rows, hipStream_t s);
 
 // Moments of rows [y0, y0+rows) into staged doubles (rho, ux, uy per node).
 hipError_t launch_moments(int storage, const Grid &g, const Phys &ph, const void *A,
-                          const uint8_t *mask, double *stage, int32_t y0, int32_t rows,
+                          const mask_t *mask, double *stage, int32_t y0, int32_t rows,
                           hipStream_t s);
 
 // Per-block FP64 partial sums of the mass; n_partials = number of blocks used.
 hipError_t launch_mass(int storage, const Grid &g, const Phys &ph, const void *A,
-                       const uint8_t *mask, double *partials, int32_t n_partials, hipStream_t s);
+                       const mask_t *mask, double *partials, int32_t n_partials, hipStream_t s);
 
 int32_t mass_blocks(const Grid &g);
 

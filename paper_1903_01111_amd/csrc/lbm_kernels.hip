@@ -296,7 +296,7 @@ template <int ST, bool OPEN, bool FORCE, int BX, bool STORE_SOLID>
 __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
                                                    const typename Codec<ST>::T *__restrict__ A,
                                                    typename Codec<ST>::T *__restrict__ B,
-                                                   const uint8_t *__restrict__ mask,
+                                                   const mask_t *__restrict__ mask,
                                                    const typename Codec<ST>::R *__restrict__ uin,
                                                    Side side, double *__restrict__ zero_bank,
                                                    int32_t n_zero)
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
     if (y >= g.ny || (x >> 6) >= (g.pitch >> 6)) return;
     const bool inside = x < g.nx;
     const int32_t row = y * g.pitch;
-    const uint8_t m = inside ? mask[row + x] : MASK_SOLID;
+    const mask_t m = inside ? mask[row + x] : MASK_SOLID;
     const int64_t P = g.plane;
     // The nine pulls f_i(x, t+1) = f+_i(x - e_i, t) are issued before the node
     // type and the link records are known, so that their latency overlaps the
@@ -355,8 +355,29 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
     const uint64_t flagged = __ballot((m & MASK_SIDE) != 0);
     const int32_t slot = sb.flagged + (int32_t)__popcll(flagged & ((1ull << lane) - 1ull));
     const uint32_t rec = (m & MASK_SIDE) ? side.rec[slot] : 0u;
-    // exclusive wavefront prefix of (links, deposited populations) per node
-    const uint32_t cnt = (uint32_t)popc32(rec & 0xffu) | ((uint32_t)popc32(rec >> 8) << 16);
+    // links of this node (mask bits): exclusive wavefront prefix -> first L entry
+    const uint32_t lk = m & MASK_LINKS;
+    uint32_t linc = (uint32_t)popc32(lk);
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = __shfl_up(linc, off);
+        if (lane >= off) linc += t;
+    }
+    const int32_t lbase = sb.links + (int32_t)(linc - (uint32_t)popc32(lk));
+    // where x - e_i is solid, the link (x, i') with i' = opp(i) (bit i'-1 of the
+    // mask word) supplies the population: its load is issued now, while the
+    // side record is still in flight
+    {
+        const T *Lv = static_cast<const T *>(side.L);
+        constexpr int OPPI[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            const uint32_t bit = 1u << (OPPI[i] - 1);
+            if (lk & bit) a[i] = Lv[lbase + popc32(lk & (bit - 1u))];
+        }
+    }
+    // deposited populations of this node (side record): exclusive prefix -> first P entry
+    const uint32_t cnt = (uint32_t)popc32(rec >> 8) << 16;
     uint32_t inc = cnt;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -364,7 +385,6 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
         if (lane >= off) inc += t;
     }
     const uint32_t exc = inc - cnt;
-    const int32_t lbase = sb.links + (int32_t)(exc & 0xffffu);
     const int32_t pbase = sb.pops + (int32_t)(exc >> 16);
     const int wave_pops = (int)(__shfl(inc, 63) >> 16);
     const int wave_flagged = (int)__popcll(flagged);
@@ -415,24 +435,9 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
     }
 
     const float inv = ph.inv_scale;
-    const T *Lv = static_cast<const T *>(side.L);
-    // where x - e_i is solid, the link (x, i') with i' = opp(i) (bit i'-1 of rec)
-    // supplies the population instead
-    auto pull = [&](int ip, T av) -> R {
-        const uint32_t bit = 1u << (ip - 1);
-        const T v = (rec & bit) ? Lv[lbase + popc32(rec & (bit - 1u))] : av;
-        return C::ld(v, inv);
-    };
     R f[9];
-    f[0] = C::ld(a[0], inv);
-    f[1] = pull(3, a[1]);
-    f[2] = pull(4, a[2]);
-    f[3] = pull(1, a[3]);
-    f[4] = pull(2, a[4]);
-    f[5] = pull(7, a[5]);
-    f[6] = pull(8, a[6]);
-    f[7] = pull(5, a[7]);
-    f[8] = pull(6, a[8]);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = C::ld(a[i], inv);
 
     const R drho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
     const R jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
@@ -522,7 +527,7 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
                 }
             }
         }
-        const uint8_t me = mask[row + g.nx - 1];
+        const mask_t me = mask[row + g.nx - 1];
         if (x == g.nx - 2 && !(me & MASK_SOLID)) {
             // zero-gradient outlet: copy every population of the last fluid column
 #pragma unroll
@@ -579,7 +584,7 @@ __global__ void refresh_kernel(Grid g, Phys ph, const typename Codec<ST>::T *__r
 
 template <int ST>
 __global__ void init_kernel(Grid g, Phys ph, typename Codec<ST>::T *__restrict__ A,
-                            const uint8_t *__restrict__ mask, const double *__restrict__ stage,
+                            const mask_t *__restrict__ mask, const double *__restrict__ stage,
                             int32_t y0, int32_t rows)
 {
     using C = Codec<ST>;
@@ -600,7 +605,7 @@ __global__ void init_kernel(Grid g, Phys ph, typename Codec<ST>::T *__restrict__
 
 template <int ST>
 __global__ void moments_kernel(Grid g, Phys ph, const typename Codec<ST>::T *__restrict__ A,
-                               const uint8_t *__restrict__ mask, double *__restrict__ stage,
+                               const mask_t *__restrict__ mask, double *__restrict__ stage,
                                int32_t y0, int32_t rows)
 {
     using C = Codec<ST>;
@@ -631,7 +636,7 @@ constexpr int MASS_THREADS = 256;
 template <int ST>
 __global__ __launch_bounds__(MASS_THREADS) void mass_kernel(Grid g, Phys ph,
                                                            const typename Codec<ST>::T *__restrict__ A,
-                                                           const uint8_t *__restrict__ mask,
+                                                           const mask_t *__restrict__ mask,
                                                            double *__restrict__ partials)
 {
     using C = Codec<ST>;
@@ -676,7 +681,7 @@ hipError_t link_t(const Grid &g, const Phys &ph, const Links &L, const Side &sid
 }
 
 template <int ST, bool OPEN, bool FORCE, int BX, bool SS>
-hipError_t bulk_t(const Grid &g, const Phys &ph, const void *A, void *B, const uint8_t *mask,
+hipError_t bulk_t(const Grid &g, const Phys &ph, const void *A, void *B, const mask_t *mask,
                   const void *uin, const Side &side, double *zb, int32_t nz, hipStream_t s)
 {
     using C = Codec<ST>;
@@ -689,7 +694,7 @@ hipError_t bulk_t(const Grid &g, const Phys &ph, const void *A, void *B, const u
 }
 
 template <int ST, bool OPEN, bool FORCE>
-hipError_t bulk_shape(const Grid &g, const Phys &ph, const void *A, void *B, const uint8_t *mask,
+hipError_t bulk_shape(const Grid &g, const Phys &ph, const void *A, void *B, const mask_t *mask,
                       const void *uin, const Side &side, double *zb, int32_t nz, const BulkConfig &cf,
                       hipStream_t s)
 {
@@ -707,7 +712,7 @@ hipError_t bulk_shape(const Grid &g, const Phys &ph, const void *A, void *B, con
 }
 
 template <int ST>
-hipError_t bulk_dispatch(const Grid &g, const Phys &ph, const void *A, void *B, const uint8_t *mask,
+hipError_t bulk_dispatch(const Grid &g, const Phys &ph, const void *A, void *B, const mask_t *mask,
                          const void *uin, const Side &side, double *zb, int32_t nz, const BulkConfig &cf,
                          hipStream_t s)
 {
@@ -745,7 +750,7 @@ hipError_t launch_link(int storage, const Grid &g, const Phys &ph, const Links &
 }
 
 hipError_t launch_bulk(int storage, const Grid &g, const Phys &ph, const void *A, void *B,
-                       const uint8_t *mask, const void *uin, const Side &side, double *zb, int32_t nz,
+                       const mask_t *mask, const void *uin, const Side &side, double *zb, int32_t nz,
                        const BulkConfig &cf, hipStream_t s)
 {
     switch (storage) {
@@ -771,7 +776,7 @@ hipError_t launch_refresh(int storage, const Grid &g, const Phys &ph, const void
 
 namespace {
 template <int ST>
-hipError_t init_t(const Grid &g, const Phys &ph, void *A, const uint8_t *mask, const double *stage,
+hipError_t init_t(const Grid &g, const Phys &ph, void *A, const mask_t *mask, const double *stage,
                   int32_t y0, int32_t rows, hipStream_t s)
 {
     const int64_t n = (int64_t)rows * g.nx;
@@ -781,7 +786,7 @@ hipError_t init_t(const Grid &g, const Phys &ph, void *A, const uint8_t *mask, c
     return hipGetLastError();
 }
 template <int ST>
-hipError_t moments_t(const Grid &g, const Phys &ph, const void *A, const uint8_t *mask,
+hipError_t moments_t(const Grid &g, const Phys &ph, const void *A, const mask_t *mask,
                      double *stage, int32_t y0, int32_t rows, hipStream_t s)
 {
     const int64_t n = (int64_t)rows * g.nx;
@@ -791,7 +796,7 @@ hipError_t moments_t(const Grid &g, const Phys &ph, const void *A, const uint8_t
     return hipGetLastError();
 }
 template <int ST>
-hipError_t mass_t(const Grid &g, const Phys &ph, const void *A, const uint8_t *mask,
+hipError_t mass_t(const Grid &g, const Phys &ph, const void *A, const mask_t *mask,
                   double *partials, int32_t nb, hipStream_t s)
 {
     hipLaunchKernelGGL(mass_kernel<ST>, dim3(nb), dim3(MASS_THREADS), 0, s, g, ph,
@@ -800,7 +805,7 @@ hipError_t mass_t(const Grid &g, const Phys &ph, const void *A, const uint8_t *m
 }
 }  // namespace
 
-hipError_t launch_init(int storage, const Grid &g, const Phys &ph, void *A, const uint8_t *mask,
+hipError_t launch_init(int storage, const Grid &g, const Phys &ph, void *A, const mask_t *mask,
                        const double *stage, int32_t y0, int32_t rows, hipStream_t s)
 {
     switch (storage) {
@@ -813,7 +818,7 @@ hipError_t launch_init(int storage, const Grid &g, const Phys &ph, void *A, cons
 }
 
 hipError_t launch_moments(int storage, const Grid &g, const Phys &ph, const void *A,
-                          const uint8_t *mask, double *stage, int32_t y0, int32_t rows, hipStream_t s)
+                          const mask_t *mask, double *stage, int32_t y0, int32_t rows, hipStream_t s)
 {
     switch (storage) {
     case 0: return moments_t<0>(g, ph, A, mask, stage, y0, rows, s);
@@ -831,7 +836,7 @@ int32_t mass_blocks(const Grid &g)
     return (int32_t)(b < 1024 ? (b < 1 ? 1 : b) : 1024);
 }
 
-hipError_t launch_mass(int storage, const Grid &g, const Phys &ph, const void *A, const uint8_t *mask,
+hipError_t launch_mass(int storage, const Grid &g, const Phys &ph, const void *A, const mask_t *mask,
                        double *partials, int32_t nb, hipStream_t s)
 {
     switch (storage) {

@@ -74,7 +74,7 @@ Layout make_layout(const lbm_params &p, int64_t max_links)
     };
     L.off_A = take(9 * pb);
     L.off_B = take(9 * pb);
-    L.off_mask = take((size_t)L.pitch * p.ny);
+    L.off_mask = take((size_t)L.pitch * p.ny * sizeof(lbm::mask_t));
     L.off_seg = take((size_t)(L.pitch / 64) * p.ny * sizeof(lbm::SegBase));
     const size_t nl = (size_t)std::max<int64_t>(max_links, 0);
     L.off_meta = take(nl * 4);
@@ -164,7 +164,7 @@ struct Prepared {
     // per flagged node, in plane order
     std::vector<uint16_t> rec;
     std::vector<int32_t> mnode, pbase;
-    std::vector<uint8_t> mask;             // padded to the pitch: solid bit, side bit
+    std::vector<lbm::mask_t> mask;         // padded to the pitch: link bits, solid bit, side bit
     std::vector<lbm::SegBase> seg;         // per 64-node row segment
     int64_t n_pops = 0;
     bool has_uw = false;
@@ -291,7 +291,7 @@ lbm_status prepare_geometry(const lbm_params &p, const uint8_t *mask, int64_t n,
     out->mask.assign(plane_n, lbm::MASK_SOLID);
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x)
-            out->mask[(size_t)y * pitch + x] = mask[(int64_t)y * nx + x] ? lbm::MASK_SOLID : 0;
+            out->mask[(size_t)y * pitch + x] = mask[(int64_t)y * nx + x] ? lbm::MASK_SOLID : lbm::mask_t(0);
     // per-node record bits: link directions at x_f, deposited populations at x_f and x_ff
     std::vector<uint16_t> bits(plane_n, 0);
     for (int64_t l = 0; l < n; ++l) {
@@ -312,7 +312,7 @@ lbm_status prepare_geometry(const lbm_params &p, const uint8_t *mask, int64_t n,
         out->seg[sg] = lbm::SegBase{(int32_t)out->rec.size(), nlinks, npops, 0};
         for (int64_t o = sg * 64; o < sg * 64 + 64; ++o) {
             if (!bits[o]) continue;
-            out->mask[o] |= lbm::MASK_SIDE;
+            out->mask[o] |= (lbm::mask_t)(lbm::MASK_SIDE | (bits[o] & lbm::MASK_LINKS));
             slot[o] = (int32_t)out->rec.size();
             out->rec.push_back(bits[o]);
             out->mnode.push_back((int32_t)o);
@@ -435,7 +435,7 @@ struct lbm_ctx {
                          reinterpret_cast<const int32_t *>(ws + lay.off_mnode),
                          reinterpret_cast<const int32_t *>(ws + lay.off_pbase), n_moment_nodes};
     }
-    uint8_t *mask() const { return reinterpret_cast<uint8_t *>(ws + lay.off_mask); }
+    lbm::mask_t *mask() const { return reinterpret_cast<lbm::mask_t *>(ws + lay.off_mask); }
     double *force() const { return reinterpret_cast<double *>(ws + lay.off_force); }
     double *bank(int64_t t) const { return force() + (size_t)(t & 1) * 2 * p.n_obj; }
     double *fsum() const { return force() + 4 * (size_t)p.n_obj; }
@@ -691,8 +691,8 @@ lbm_status lbm_set_geometry(lbm_ctx *c, const uint8_t *mask, int64_t n_links, co
                        (long long)n_links, (long long)c->max_links);
     c->drop_graph();
     const hipStream_t st = c->stream;
-    if ((s = c->hip(hipMemcpyAsync(c->mask(), prep.mask.data(), prep.mask.size(), hipMemcpyHostToDevice,
-                                   st), "mask upload")))
+    if ((s = c->hip(hipMemcpyAsync(c->mask(), prep.mask.data(), prep.mask.size() * sizeof(lbm::mask_t),
+                                   hipMemcpyHostToDevice, st), "mask upload")))
         return s;
     const size_t n = (size_t)n_links;
     const size_t rb = real_bytes(c->p.storage);
@@ -902,10 +902,11 @@ lbm_status lbm_populations(lbm_ctx *c, double *f)
     const int nx = c->p.nx, ny = c->p.ny, pitch = c->lay.pitch;
     const size_t eb = elem_bytes(c->p.storage);
     const double inv = std::ldexp(1.0, c->p.storage >= LBM_F16_DEV ? -c->p.dev_scale_log2 : 0);
-    std::vector<uint8_t> mask((size_t)pitch * ny);
+    std::vector<lbm::mask_t> mask((size_t)pitch * ny);
     std::vector<char> plane((size_t)pitch * ny * eb);
     lbm_status s;
-    if ((s = c->hip(hipMemcpy(mask.data(), c->mask(), mask.size(), hipMemcpyDeviceToHost), "mask read")))
+    if ((s = c->hip(hipMemcpy(mask.data(), c->mask(), mask.size() * sizeof(lbm::mask_t), hipMemcpyDeviceToHost),
+                    "mask read")))
         return s;
     if ((s = c->hip(hipStreamSynchronize(c->stream), "populations"))) return s;
     for (int i = 0; i < 9; ++i) {
