@@ -189,11 +189,21 @@ lbm_status lbm_force_reset(lbm_ctx *ctx);
 /* Total mass sum over fluid nodes of sum_i f+_i, reduced in FP64.  Synchronises. */
 lbm_status lbm_mass(lbm_ctx *ctx, double *mass);
 
+/* max over fluid nodes and directions of |f+_i - w_i|, in FP64: sizes the scale
+ * 2^k of 16-bit deviation storage (largest k with 2^k * max <= 2^14 leaves a 4x
+ * margin below the FP16 maximum).  Synchronises. */
+lbm_status lbm_max_deviation(lbm_ctx *ctx, double *max_dev);
+
 /* Checkpoint: the population buffer in storage precision, the step counter, the
  * force accumulators and the stored moments of the boundary-adjacent nodes, so
  * that a restored run continues bitwise.  lbm_state_bytes gives the size of the
  * host buffer; a state only fits a context with the same params and geometry. */
 size_t lbm_state_bytes(const lbm_ctx *ctx);
+/* Checkpoint format: int64 step, int64 steps in the force sum; then plane i = 0..8
+ * of plane_elems elements of elem bytes each (storage format: (f_i - w_i)
+ * [* 2^k], node (x, y) at y*pitch + x); then 6*n_obj doubles of force
+ * accumulators; then the stored moments of the boundary-adjacent nodes. */
+lbm_status lbm_state_layout(const lbm_ctx *ctx, int32_t *pitch, int64_t *plane_elems, int32_t *elem);
 lbm_status lbm_get_state(lbm_ctx *ctx, void *host, size_t bytes);
 lbm_status lbm_set_state(lbm_ctx *ctx, const void *host, size_t bytes);
 

@@ -71,7 +71,9 @@ SIGNATURES = [
     ("lbm_force", _I32, [_P, _I32, _P, _P, _P]),
     ("lbm_force_reset", _I32, [_P]),
     ("lbm_mass", _I32, [_P, _P]),
+    ("lbm_max_deviation", _I32, [_P, _P]),
     ("lbm_state_bytes", C.c_size_t, [_P]),
+    ("lbm_state_layout", _I32, [_P, _P, _P, _P]),
     ("lbm_get_state", _I32, [_P, _P, C.c_size_t]),
     ("lbm_set_state", _I32, [_P, _P, C.c_size_t]),
     ("lbm_set_profiling", _I32, [_P, _I32]),
@@ -243,8 +245,39 @@ def lbm_mass(ctx) -> float:
     return m.value
 
 
+def lbm_max_deviation(ctx) -> float:
+    m = C.c_double(0)
+    check(lib().lbm_max_deviation(ctx, C.byref(m)), ctx)
+    return m.value
+
+
+def dev_scale_for(max_dev: float, limit_log2: int = 14) -> int:
+    """Largest k with 2^k * max_dev <= 2^limit_log2 (the 16-bit storage scale)."""
+    import math
+    if max_dev <= 0:
+        return 0
+    return int(max(-30, min(30, math.floor(limit_log2 - math.log2(max_dev)))))
+
+
 def lbm_state_bytes(ctx) -> int:
     return lib().lbm_state_bytes(ctx)
+
+
+def lbm_state_layout(ctx):
+    """(pitch, plane elements, element bytes) of the checkpoint's population planes."""
+    pitch = C.c_int32(0)
+    plane = C.c_int64(0)
+    elem = C.c_int32(0)
+    check(lib().lbm_state_layout(ctx, C.byref(pitch), C.byref(plane), C.byref(elem)), ctx)
+    return pitch.value, plane.value, elem.value
+
+
+def raw_planes(ctx, ny, nx, dtype):
+    """The nine stored population planes (ny, nx) in storage format, from a checkpoint."""
+    pitch, plane, elem = lbm_state_layout(ctx)
+    buf = lbm_get_state(ctx)
+    body = buf[16:16 + 9 * plane * elem].view(dtype).reshape(9, plane)
+    return body[:, :ny * pitch].reshape(9, ny, pitch)[:, :, :nx]
 
 
 def lbm_get_state(ctx) -> np.ndarray:

@@ -107,9 +107,11 @@ hipError_t launch_moments(int storage, const Grid &g, const Phys &ph, const void
                           const mask_t *mask, double *stage, int32_t y0, int32_t rows,
                           hipStream_t s);
 
-// Per-block FP64 partial sums of the mass; n_partials = number of blocks used.
+// Per-block FP64 partials over the fluid nodes: the mass (sum) or, with maxdev,
+// max |f_i - w_i|; n_partials = number of blocks used.
 hipError_t launch_mass(int storage, const Grid &g, const Phys &ph, const void *A,
-                       const mask_t *mask, double *partials, int32_t n_partials, hipStream_t s);
+                       const mask_t *mask, double *partials, int32_t n_partials, bool maxdev,
+                       hipStream_t s);
 
 int32_t mass_blocks(const Grid &g);
 

@@ -633,7 +633,9 @@ __global__ void moments_kernel(Grid g, Phys ph, const typename Codec<ST>::T *__r
 
 constexpr int MASS_THREADS = 256;
 
-template <int ST>
+// Per-block FP64 partials over the fluid nodes: MAXDEV = false sums the mass
+// sum_i f_i; MAXDEV = true takes max_i |f_i - w_i| (sizes the 16-bit scale).
+template <int ST, bool MAXDEV>
 __global__ __launch_bounds__(MASS_THREADS) void mass_kernel(Grid g, Phys ph,
                                                            const typename Codec<ST>::T *__restrict__ A,
                                                            const mask_t *__restrict__ mask,
@@ -649,16 +651,22 @@ __global__ __launch_bounds__(MASS_THREADS) void mass_kernel(Grid g, Phys ph,
         const int32_t n = y * g.pitch + x;
         if (mask[n] & MASK_SOLID) continue;
 #pragma unroll
-        for (int i = 0; i < 9; ++i)
-            s += (double)C::ld(A[(int64_t)i * g.plane + n], ph.inv_scale) + wgt<double>(i);
+        for (int i = 0; i < 9; ++i) {
+            const double d = (double)C::ld(A[(int64_t)i * g.plane + n], ph.inv_scale);
+            if (MAXDEV) s = fmax(s, fabs(d));
+            else s += d + wgt<double>(i);
+        }
     }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(s, off);
+        s = MAXDEV ? fmax(s, o) : s + o;
+    }
     if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
         double t = 0.0;
-        for (int k = 0; k < MASS_THREADS / 64; ++k) t += red[k];
+        for (int k = 0; k < MASS_THREADS / 64; ++k) t = MAXDEV ? fmax(t, red[k]) : t + red[k];
         partials[blockIdx.x] = t;
     }
 }
@@ -797,10 +805,14 @@ hipError_t moments_t(const Grid &g, const Phys &ph, const void *A, const mask_t 
 }
 template <int ST>
 hipError_t mass_t(const Grid &g, const Phys &ph, const void *A, const mask_t *mask,
-                  double *partials, int32_t nb, hipStream_t s)
+                  double *partials, int32_t nb, bool maxdev, hipStream_t s)
 {
-    hipLaunchKernelGGL(mass_kernel<ST>, dim3(nb), dim3(MASS_THREADS), 0, s, g, ph,
-                       static_cast<const typename Codec<ST>::T *>(A), mask, partials);
+    if (maxdev)
+        hipLaunchKernelGGL((mass_kernel<ST, true>), dim3(nb), dim3(MASS_THREADS), 0, s, g, ph,
+                           static_cast<const typename Codec<ST>::T *>(A), mask, partials);
+    else
+        hipLaunchKernelGGL((mass_kernel<ST, false>), dim3(nb), dim3(MASS_THREADS), 0, s, g, ph,
+                           static_cast<const typename Codec<ST>::T *>(A), mask, partials);
     return hipGetLastError();
 }
 }  // namespace
@@ -837,13 +849,13 @@ int32_t mass_blocks(const Grid &g)
 }
 
 hipError_t launch_mass(int storage, const Grid &g, const Phys &ph, const void *A, const mask_t *mask,
-                       double *partials, int32_t nb, hipStream_t s)
+                       double *partials, int32_t nb, bool maxdev, hipStream_t s)
 {
     switch (storage) {
-    case 0: return mass_t<0>(g, ph, A, mask, partials, nb, s);
-    case 1: return mass_t<1>(g, ph, A, mask, partials, nb, s);
-    case 2: return mass_t<2>(g, ph, A, mask, partials, nb, s);
-    case 3: return mass_t<3>(g, ph, A, mask, partials, nb, s);
+    case 0: return mass_t<0>(g, ph, A, mask, partials, nb, maxdev, s);
+    case 1: return mass_t<1>(g, ph, A, mask, partials, nb, maxdev, s);
+    case 2: return mass_t<2>(g, ph, A, mask, partials, nb, maxdev, s);
+    case 3: return mass_t<3>(g, ph, A, mask, partials, nb, maxdev, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -974,26 +974,32 @@ lbm_status lbm_force_reset(lbm_ctx *c)
     return LBM_OK;
 }
 
-lbm_status lbm_mass(lbm_ctx *c, double *m)
+namespace {
+lbm_status reduce_state(lbm_ctx *c, bool maxdev, double *out)
 {
-    if (!c || !m) return LBM_E_ARG;
-    if (!c->have_geom || !c->have_init) return c->fail(LBM_E_STATE, "lbm_mass before initialisation");
+    if (!c || !out) return LBM_E_ARG;
+    if (!c->have_geom || !c->have_init) return c->fail(LBM_E_STATE, "reduction before initialisation");
     const int nb = lbm::mass_blocks(c->grid());
     std::vector<double> h(nb);
     lbm_status s;
     if ((s = c->hip(lbm::launch_mass(c->p.storage, c->grid(), c->phys(), c->cur, c->mask(), c->partials(),
-                                     nb, c->stream), "mass kernel")))
+                                     nb, maxdev, c->stream), "reduction kernel")))
         return s;
     if ((s = c->hip(hipMemcpyAsync(h.data(), c->partials(), nb * 8, hipMemcpyDeviceToHost, c->stream),
-                    "mass read")))
+                    "reduction read")))
         return s;
-    if ((s = c->hip(hipStreamSynchronize(c->stream), "mass"))) return s;
+    if ((s = c->hip(hipStreamSynchronize(c->stream), "reduction"))) return s;
     double t = 0;
-    for (double v : h) t += v;
-    if (!std::isfinite(t)) return c->fail(LBM_E_UNSTABLE, "non-finite mass");
-    *m = t;
+    for (double v : h) t = maxdev ? std::fmax(t, v) : t + v;
+    if (!std::isfinite(t)) return c->fail(LBM_E_UNSTABLE, "non-finite populations");
+    *out = t;
     return LBM_OK;
 }
+}  // namespace
+
+lbm_status lbm_mass(lbm_ctx *c, double *m) { return reduce_state(c, false, m); }
+
+lbm_status lbm_max_deviation(lbm_ctx *c, double *d) { return reduce_state(c, true, d); }
 
 // Checkpoint layout: {step, nsum} | populations (nine planes, storage precision) |
 // force accumulators | side moments of the flagged nodes (they are part of the
@@ -1003,6 +1009,15 @@ size_t lbm_state_bytes(const lbm_ctx *c)
     if (!c) return 0;
     return 9 * (size_t)c->lay.plane * elem_bytes(c->p.storage) + 6 * (size_t)c->p.n_obj * sizeof(double) +
            2 * sizeof(int64_t) + (size_t)c->n_moment_nodes * 3 * real_bytes(c->p.storage);
+}
+
+lbm_status lbm_state_layout(const lbm_ctx *c, int32_t *pitch, int64_t *plane_elems, int32_t *elem)
+{
+    if (!c) return LBM_E_ARG;
+    if (pitch) *pitch = c->lay.pitch;
+    if (plane_elems) *plane_elems = c->lay.plane;
+    if (elem) *elem = (int32_t)elem_bytes(c->p.storage);
+    return LBM_OK;
 }
 
 lbm_status lbm_get_state(lbm_ctx *c, void *host, size_t bytes)
