@@ -234,6 +234,48 @@ lbm_status lbm_set_kernel_config(lbm_ctx *ctx, const lbm_kernel_config *cfg);
 lbm_status lbm_autotune(lbm_ctx *ctx, int32_t steps_per_trial, lbm_kernel_config *chosen,
                         double *best_ms_per_step);
 
+/* ---------------------------------------------------------------------------
+ * Batched form: n lattices of uneven size (e.g. the same flow at different
+ * obstacle offsets or Reynolds numbers) advanced together.  Each step is one
+ * link launch over the links of all instances and one bulk launch over a tile
+ * table of all instances (HIP graph replay).  Instances share storage, x_bc,
+ * rho0, dev_scale_log2, device and stream; nx, ny, tau, body force, n_obj and
+ * geometry are per instance.  The results of an instance equal those of a
+ * single-lattice context with the same arguments (bitwise for the populations).
+ * ------------------------------------------------------------------------- */
+typedef struct lbm_batch lbm_batch;
+
+const char *lbm_batch_last_error(const lbm_batch *b); /* NULL b: the thread's message */
+
+/* Device bytes for n instances with params p[n] and link capacities max_links[n];
+ * 0 if the params are invalid or do not share the common fields. */
+size_t lbm_batch_workspace_bytes(int32_t n, const lbm_params *p, const int64_t *max_links);
+
+lbm_status lbm_batch_create(int32_t n, const lbm_params *p, const int64_t *max_links, void *workspace,
+                            size_t bytes, lbm_batch **out);
+void lbm_batch_destroy(lbm_batch *b);
+
+/* Per-instance counterparts of lbm_set_geometry, lbm_set_inlet and
+ * lbm_init_equilibrium (same arguments and errors; inst in [0, n)). */
+lbm_status lbm_batch_set_geometry(lbm_batch *b, int32_t inst, const uint8_t *mask, int64_t n_links,
+                                  const int32_t *node, const int8_t *dir, const double *q, const double *uw,
+                                  const int32_t *obj, const int8_t *scheme);
+lbm_status lbm_batch_set_inlet(lbm_batch *b, int32_t inst, const double *ux, const double *uy);
+lbm_status lbm_batch_init_equilibrium(lbm_batch *b, int32_t inst, const double *rho, const double *ux,
+                                      const double *uy);
+
+/* n steps of every instance.  Errors: LBM_E_STATE if an instance lacks geometry
+ * or initialisation. */
+lbm_status lbm_batch_step(lbm_batch *b, int64_t n);
+lbm_status lbm_batch_sync(lbm_batch *b);
+int64_t lbm_batch_step_count(const lbm_batch *b);
+
+/* Per-instance read-back, as lbm_moments and lbm_force. */
+lbm_status lbm_batch_moments(lbm_batch *b, int32_t inst, double *rho, double *ux, double *uy);
+lbm_status lbm_batch_force(lbm_batch *b, int32_t inst, int32_t obj, double last[2], double sum[2],
+                           int64_t *nsum);
+lbm_status lbm_batch_force_reset(lbm_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -81,6 +81,19 @@ SIGNATURES = [
     ("lbm_get_kernel_config", _I32, [_P, _P]),
     ("lbm_set_kernel_config", _I32, [_P, _P]),
     ("lbm_autotune", _I32, [_P, _I32, _P, _P]),
+    ("lbm_batch_last_error", C.c_char_p, [_P]),
+    ("lbm_batch_workspace_bytes", C.c_size_t, [_I32, _P, _P]),
+    ("lbm_batch_create", _I32, [_I32, _P, _P, _P, C.c_size_t, _P]),
+    ("lbm_batch_destroy", _V, [_P]),
+    ("lbm_batch_set_geometry", _I32, [_P, _I32, _P, _I64, _P, _P, _P, _P, _P, _P]),
+    ("lbm_batch_set_inlet", _I32, [_P, _I32, _P, _P]),
+    ("lbm_batch_init_equilibrium", _I32, [_P, _I32, _P, _P, _P]),
+    ("lbm_batch_step", _I32, [_P, _I64]),
+    ("lbm_batch_sync", _I32, [_P]),
+    ("lbm_batch_step_count", _I64, [_P]),
+    ("lbm_batch_moments", _I32, [_P, _I32, _P, _P, _P]),
+    ("lbm_batch_force", _I32, [_P, _I32, _I32, _P, _P, _P]),
+    ("lbm_batch_force_reset", _I32, [_P]),
 ]
 
 
@@ -319,6 +332,144 @@ def lbm_autotune(ctx, steps_per_trial=20):
     ms = C.c_double(0)
     check(lib().lbm_autotune(ctx, int(steps_per_trial), C.byref(k), C.byref(ms)), ctx)
     return k, ms.value
+
+
+def _bcheck(status, b):
+    if status != LBM_OK:
+        m = lib().lbm_batch_last_error(b)
+        raise LbmError(status, m.decode() if m else "")
+
+
+def lbm_batch_workspace_bytes(params_list, max_links) -> int:
+    arr = (lbm_params * len(params_list))(*params_list)
+    ml = np.ascontiguousarray(max_links, np.int64)
+    return lib().lbm_batch_workspace_bytes(len(params_list), arr, _p(ml))
+
+
+def lbm_batch_create(params_list, max_links, workspace_ptr, nbytes):
+    arr = (lbm_params * len(params_list))(*params_list)
+    ml = np.ascontiguousarray(max_links, np.int64)
+    b = C.c_void_p()
+    _bcheck(lib().lbm_batch_create(len(params_list), arr, _p(ml), C.c_void_p(workspace_ptr), nbytes,
+                                   C.byref(b)), None)
+    return b
+
+
+def lbm_batch_destroy(b):
+    lib().lbm_batch_destroy(b)
+
+
+def lbm_batch_set_geometry(b, inst, mask, node, dir, q, uw=None, obj=None, scheme=None):
+    a = _link_arrays(mask, node, dir, q, uw, obj, scheme)
+    _bcheck(lib().lbm_batch_set_geometry(b, inst, _p(a[0]), len(a[1]), *[_p(x) for x in a[1:]]), b)
+
+
+def lbm_batch_set_inlet(b, inst, ux=None, uy=None):
+    ux = None if ux is None else np.ascontiguousarray(ux, np.float64)
+    uy = None if uy is None else np.ascontiguousarray(uy, np.float64)
+    _bcheck(lib().lbm_batch_set_inlet(b, inst, _p(ux), _p(uy)), b)
+
+
+def lbm_batch_init_equilibrium(b, inst, rho=None, ux=None, uy=None):
+    f = lambda a: None if a is None else np.ascontiguousarray(a, np.float64)
+    rho, ux, uy = f(rho), f(ux), f(uy)
+    _bcheck(lib().lbm_batch_init_equilibrium(b, inst, _p(rho), _p(ux), _p(uy)), b)
+
+
+def lbm_batch_step(b, n):
+    _bcheck(lib().lbm_batch_step(b, int(n)), b)
+
+
+def lbm_batch_sync(b):
+    _bcheck(lib().lbm_batch_sync(b), b)
+
+
+def lbm_batch_step_count(b) -> int:
+    return lib().lbm_batch_step_count(b)
+
+
+def lbm_batch_moments(b, inst, ny, nx):
+    rho = np.zeros((ny, nx))
+    ux = np.zeros((ny, nx))
+    uy = np.zeros((ny, nx))
+    _bcheck(lib().lbm_batch_moments(b, inst, _p(rho), _p(ux), _p(uy)), b)
+    return rho, ux, uy
+
+
+def lbm_batch_force(b, inst, obj=0):
+    last = np.zeros(2)
+    s = np.zeros(2)
+    n = C.c_int64(0)
+    _bcheck(lib().lbm_batch_force(b, inst, obj, _p(last), _p(s), C.byref(n)), b)
+    return last, s, n.value
+
+
+def lbm_batch_force_reset(b):
+    _bcheck(lib().lbm_batch_force_reset(b), b)
+
+
+class Batch:
+    """Many lattices on one GPU advanced together (workspace from torch)."""
+
+    def __init__(self, cases, storage="f32", dev_scale_log2=0, device=0, geometries=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise LbmError(LBM_E_DEVICE, "no GPU visible to torch")
+        self.cases = list(cases)
+        self.device = torch.device("cuda", device)
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        self.params = [make_params(c.nx, c.ny, x_open=c.x_open, storage=storage, tau=c.tau, gx=c.gx,
+                                   gy=c.gy, rho0=c.rho0, n_obj=c.n_obj, dev_scale_log2=dev_scale_log2,
+                                   device=device, stream=stream) for c in self.cases]
+        self.geoms = geometries if geometries is not None else [case_geometry(c) for c in self.cases]
+        ml = [len(g[1]) for g in self.geoms]
+        nbytes = lbm_batch_workspace_bytes(self.params, ml)
+        if nbytes == 0:
+            raise LbmError(LBM_E_ARG, "invalid batch parameters")
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = self._ws.data_ptr()
+        ptr += (-ptr) % 256
+        self.b = lbm_batch_create(self.params, ml, ptr, nbytes)
+        for i, (c, g) in enumerate(zip(self.cases, self.geoms)):
+            mask, node, d, q, uw, obj, scheme = g
+            lbm_batch_set_geometry(self.b, i, mask, node, d, q, uw, obj, scheme)
+            if c.x_open:
+                u = c.inlet()
+                lbm_batch_set_inlet(self.b, i, u[:, 0], u[:, 1])
+            lbm_batch_init_equilibrium(self.b, i, *c.init_fields())
+
+    @property
+    def n_nodes(self):
+        return sum(c.nx * c.ny for c in self.cases)
+
+    def step(self, n=1):
+        lbm_batch_step(self.b, n)
+        return self
+
+    def sync(self):
+        lbm_batch_sync(self.b)
+
+    def moments(self, i):
+        c = self.cases[i]
+        return lbm_batch_moments(self.b, i, c.ny, c.nx)
+
+    def force(self, i, obj=0):
+        return lbm_batch_force(self.b, i, obj)
+
+    def close(self):
+        if getattr(self, "b", None) is not None:
+            lbm_batch_sync(self.b)
+            lbm_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "b", None) is not None:
+                lbm_batch_destroy(self.b)
+                self.b = None
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------------------

@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "liblbm_vibb.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HIP_SOURCES = ["lbm_kernels.hip"]
-CXX_SOURCES = ["lbm_runtime.cpp", "lbm_geometry.cpp"]
+CXX_SOURCES = ["lbm_runtime.cpp", "lbm_batch.cpp", "lbm_geometry.cpp"]
 
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
                # packed FP32 instructions are kept out of the generated code
@@ -63,7 +63,8 @@ def build(verbose: bool = False) -> str:
 
 def sources():
     return [os.path.join(CSRC, s) for s in HIP_SOURCES + CXX_SOURCES] + [
-        os.path.join(CSRC, "lbm_internal.h"), os.path.join(ROOT, "include", "lbm.h")]
+        os.path.join(CSRC, "lbm_internal.h"), os.path.join(CSRC, "lbm_host.h"),
+        os.path.join(ROOT, "include", "lbm.h")]
 
 
 def is_stale() -> bool:

@@ -1,0 +1,55 @@
+// Host-side helpers shared by the lattice runtime (lbm_runtime.cpp) and the
+// batched runtime (lbm_batch.cpp): validation and preprocessing of geometries.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_internal.h"
+
+namespace lbm_host {
+
+extern thread_local std::string g_thread_error;
+
+inline constexpr int EXR[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+inline constexpr int EYR[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+inline constexpr int OPPR[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+inline constexpr double WR[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                          1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+
+inline constexpr int64_t STAGE_NODES = 1 << 20;  // nodes per read-back / init chunk
+
+
+size_t align256(size_t v);
+size_t elem_bytes(int storage);
+size_t real_bytes(int storage);
+
+// Rejects invalid lattice parameters with a reason.
+bool params_ok(const lbm_params *p, std::string *why);
+
+// Device-ready form of a validated geometry (see prepare_geometry).
+struct Prepared {
+    // per link, in (obj, node, dir) order
+    std::vector<uint32_t> meta;
+    std::vector<double> q, uw;
+    std::vector<int32_t> sf, sff, pf, pff, li;
+    // per flagged node, in plane order
+    std::vector<uint16_t> rec;
+    std::vector<int32_t> mnode, pbase;
+    std::vector<lbm::mask_t> mask;         // padded to the pitch: link bits, solid bit, side bit
+    std::vector<lbm::SegBase> seg;         // per 64-node row segment
+    int64_t n_pops = 0;
+    bool has_uw = false;
+    int64_t n_fallback = 0;
+};
+
+// Validates mask and links against p (see lbm_check_geometry); with out, also
+// builds the link arrays (object, node, direction order), the side records and
+// segment bases of the flagged nodes for a row pitch of `pitch`.
+lbm_status prepare_geometry(const lbm_params &p, const uint8_t *mask, int64_t n, const int32_t *node,
+                            const int8_t *dir, const double *q, const double *uw, const int32_t *obj,
+                            const int8_t *scheme, int32_t pitch, Prepared *out, std::string *why);
+
+}  // namespace lbm_host

@@ -92,6 +92,25 @@ hipError_t launch_bulk(int storage, const Grid &g, const Phys &ph, const void *A
                        const mask_t *mask, const void *uin, const Side &side, double *zero_bank,
                        int32_t n_zero, const BulkConfig &cf, hipStream_t s);
 
+// Batched form: per-instance descriptor and per-block tile.
+struct BatchInst {
+    Grid g;            // the instance's lattice (plane = its own plane stride)
+    int64_t pop_off;   // element offset of its plane 0 in the shared population buffers
+    int64_t mask_off;  // element offset of its mask words
+    int32_t seg_off;   // first entry of its segment table
+    int32_t uin_off;   // first inlet row
+    double omega, gx, gy;
+};
+struct BatchTile {
+    int32_t inst, y0, x0, pad;
+};
+constexpr int BATCH_BX = 256;  // lanes along x per batched block (one row)
+
+hipError_t launch_bulk_batch(int storage, const BatchInst *insts, const BatchTile *tiles, int64_t ntiles,
+                             const Phys &ph, const void *A, void *B, const mask_t *mask, const void *uin,
+                             const Side &side, double *zero_bank, int32_t n_zero, bool open, bool force,
+                             hipStream_t s);
+
 // Rebuilds the deposited populations P (and, with moments, M) of every flagged
 // node from the populations in A: after initialisation or a restored checkpoint.
 hipError_t launch_refresh(int storage, const Grid &g, const Phys &ph, const void *A,

@@ -292,31 +292,21 @@ __global__ __launch_bounds__(256) void force_reduce_kernel(const double2 *__rest
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int popc32(uint32_t v) { return __popc(v); }
 
+// One node per lane of the lattice described by (g, ph, A, B, mask, uin, side);
+// (x, y) is the lane's node, wv its wavefront within the block.
 template <int ST, bool OPEN, bool FORCE, int BX, bool STORE_SOLID>
-__global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
-                                                   const typename Codec<ST>::T *__restrict__ A,
-                                                   typename Codec<ST>::T *__restrict__ B,
-                                                   const mask_t *__restrict__ mask,
-                                                   const typename Codec<ST>::R *__restrict__ uin,
-                                                   Side side, double *__restrict__ zero_bank,
-                                                   int32_t n_zero)
+__device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
+                                          const typename Codec<ST>::T *__restrict__ A,
+                                          typename Codec<ST>::T *__restrict__ B,
+                                          const mask_t *__restrict__ mask,
+                                          const typename Codec<ST>::R *__restrict__ uin,
+                                          const Side &side, int x, int y, int wv,
+                                          typename Codec<ST>::R (*lds_m)[3 * 64],
+                                          typename Codec<ST>::T (*lds_p)[8 * 64])
 {
     using C = Codec<ST>;
     using T = typename C::T;
     using R = typename C::R;
-    constexpr int BY = 256 / BX;
-    // per wavefront: deposits of up to 64 nodes (3 moments, up to 8 populations each)
-    __shared__ R lds_m[4][3 * 64];
-    __shared__ T lds_p[4][8 * 64];
-    {
-        // clear the force bank of the next step
-        const int64_t gt = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * 256 +
-                           threadIdx.y * BX + threadIdx.x;
-        const int64_t nt = (int64_t)gridDim.x * gridDim.y * 256;
-        for (int64_t k = gt; k < n_zero; k += nt) zero_bank[k] = 0.0;
-    }
-    const int x = blockIdx.x * BX + threadIdx.x;
-    const int y = blockIdx.y * BY + threadIdx.y;
     // a wavefront is one 64-node row segment: leave together if it lies outside
     if (y >= g.ny || (x >> 6) >= (g.pitch >> 6)) return;
     const bool inside = x < g.nx;
@@ -472,7 +462,6 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
     // velocity of f+ equals the collision velocity.
     R *Mv = static_cast<R *>(side.M);
     T *Pv = static_cast<T *>(side.P);
-    const int wv = (threadIdx.y * BX + threadIdx.x) >> 6;
     if (m & MASK_SIDE) {
         const int ls = slot - sb.flagged;
         lds_m[wv][3 * ls] = drho;
@@ -545,6 +534,69 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
             }
         }
     }
+}
+
+// clears the force bank of the next step (all blocks share the work)
+__device__ __forceinline__ void zero_bank_part(double *__restrict__ zb, int32_t nz, int64_t block,
+                                               int64_t nblocks, int tid)
+{
+    for (int64_t k = block * 256 + tid; k < nz; k += nblocks * 256) zb[k] = 0.0;
+}
+
+template <int ST, bool OPEN, bool FORCE, int BX, bool STORE_SOLID>
+__global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
+                                                   const typename Codec<ST>::T *__restrict__ A,
+                                                   typename Codec<ST>::T *__restrict__ B,
+                                                   const mask_t *__restrict__ mask,
+                                                   const typename Codec<ST>::R *__restrict__ uin,
+                                                   Side side, double *__restrict__ zero_bank,
+                                                   int32_t n_zero)
+{
+    using R = typename Codec<ST>::R;
+    using T = typename Codec<ST>::T;
+    constexpr int BY = 256 / BX;
+    // per wavefront: deposits of up to 64 nodes (3 moments, up to 8 populations each)
+    __shared__ R lds_m[4][3 * 64];
+    __shared__ T lds_p[4][8 * 64];
+    const int tid = threadIdx.y * BX + threadIdx.x;
+    zero_bank_part(zero_bank, n_zero, (int64_t)blockIdx.y * gridDim.x + blockIdx.x,
+                   (int64_t)gridDim.x * gridDim.y, tid);
+    bulk_body<ST, OPEN, FORCE, BX, STORE_SOLID>(g, ph, A, B, mask, uin, side, blockIdx.x * BX + threadIdx.x,
+                                                blockIdx.y * BY + threadIdx.y, tid >> 6, lds_m, lds_p);
+}
+
+// Batched form: one launch over the tiles of many lattices.  Each block reads its
+// tile (instance, first row, first column) and the instance's descriptor; the
+// populations, masks, inlet rows and segment tables of all instances live in
+// shared arrays at per-instance offsets, while side records, deposits and link
+// values use global numbering.
+template <int ST, bool OPEN, bool FORCE, int BX, bool STORE_SOLID>
+__global__ __launch_bounds__(256) void bulk_batch_kernel(const BatchInst *__restrict__ insts,
+                                                         const BatchTile *__restrict__ tiles, Phys ph0,
+                                                         const typename Codec<ST>::T *__restrict__ A,
+                                                         typename Codec<ST>::T *__restrict__ B,
+                                                         const mask_t *__restrict__ mask,
+                                                         const typename Codec<ST>::R *__restrict__ uin,
+                                                         Side side, double *__restrict__ zero_bank,
+                                                         int32_t n_zero)
+{
+    using R = typename Codec<ST>::R;
+    using T = typename Codec<ST>::T;
+    __shared__ R lds_m[4][3 * 64];
+    __shared__ T lds_p[4][8 * 64];
+    const int tid = threadIdx.y * BX + threadIdx.x;
+    zero_bank_part(zero_bank, n_zero, blockIdx.x, gridDim.x, tid);
+    const BatchTile t = tiles[blockIdx.x];
+    const BatchInst I = insts[t.inst];
+    Phys ph = ph0;
+    ph.omega = I.omega;
+    ph.gx = I.gx;
+    ph.gy = I.gy;
+    Side sd = side;
+    sd.seg = side.seg + I.seg_off;
+    bulk_body<ST, OPEN, FORCE, BX, STORE_SOLID>(I.g, ph, A + I.pop_off, B + I.pop_off, mask + I.mask_off,
+                                                uin + 2 * (int64_t)I.uin_off, sd, t.x0 + threadIdx.x,
+                                                t.y0 + threadIdx.y, tid >> 6, lds_m, lds_p);
 }
 
 // ---------------------------------------------------------------------------
@@ -732,6 +784,33 @@ hipError_t bulk_dispatch(const Grid &g, const Phys &ph, const void *A, void *B, 
                  : bulk_shape<ST, false, false>(g, ph, A, B, mask, uin, side, zb, nz, cf, s);
 }
 
+template <int ST, bool OPEN, bool FORCE>
+hipError_t bulk_batch_t(const BatchInst *insts, const BatchTile *tiles, int64_t ntiles, const Phys &ph,
+                        const void *A, void *B, const mask_t *mask, const void *uin, const Side &side,
+                        double *zb, int32_t nz, hipStream_t s)
+{
+    using C = Codec<ST>;
+    constexpr int BX = BATCH_BX, BY = 256 / BATCH_BX;
+    hipLaunchKernelGGL((bulk_batch_kernel<ST, OPEN, FORCE, BX, true>), dim3((unsigned)ntiles), dim3(BX, BY), 0,
+                       s, insts, tiles, ph, static_cast<const typename C::T *>(A),
+                       static_cast<typename C::T *>(B), mask, static_cast<const typename C::R *>(uin), side,
+                       zb, nz);
+    return hipGetLastError();
+}
+
+template <int ST>
+hipError_t bulk_batch_dispatch(const BatchInst *insts, const BatchTile *tiles, int64_t ntiles,
+                               const Phys &ph, const void *A, void *B, const mask_t *mask, const void *uin,
+                               const Side &side, double *zb, int32_t nz, bool open, bool force,
+                               hipStream_t s)
+{
+    if (open)
+        return force ? bulk_batch_t<ST, true, true>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, s)
+                     : bulk_batch_t<ST, true, false>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, s);
+    return force ? bulk_batch_t<ST, false, true>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, s)
+                 : bulk_batch_t<ST, false, false>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, s);
+}
+
 template <int ST>
 hipError_t refresh_t(const Grid &g, const Phys &ph, const void *A, const Side &side, bool moments,
                      hipStream_t s)
@@ -766,6 +845,20 @@ hipError_t launch_bulk(int storage, const Grid &g, const Phys &ph, const void *A
     case 1: return bulk_dispatch<1>(g, ph, A, B, mask, uin, side, zb, nz, cf, s);
     case 2: return bulk_dispatch<2>(g, ph, A, B, mask, uin, side, zb, nz, cf, s);
     case 3: return bulk_dispatch<3>(g, ph, A, B, mask, uin, side, zb, nz, cf, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_bulk_batch(int storage, const BatchInst *insts, const BatchTile *tiles, int64_t ntiles,
+                             const Phys &ph, const void *A, void *B, const mask_t *mask, const void *uin,
+                             const Side &side, double *zb, int32_t nz, bool open, bool force, hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    switch (storage) {
+    case 0: return bulk_batch_dispatch<0>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, open, force, s);
+    case 1: return bulk_batch_dispatch<1>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, open, force, s);
+    case 2: return bulk_batch_dispatch<2>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, open, force, s);
+    case 3: return bulk_batch_dispatch<3>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, open, force, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -14,19 +14,12 @@
 #include <vector>
 
 #include "lbm.h"
+#include "lbm_host.h"
 #include "lbm_internal.h"
 
-namespace {
+namespace lbm_host {
 
 thread_local std::string g_thread_error = "no error";
-
-constexpr int EXR[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-constexpr int EYR[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-constexpr int OPPR[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
-constexpr double WR[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
-                          1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
-
-constexpr int64_t STAGE_NODES = 1 << 20;  // nodes per read-back / init chunk
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -156,20 +149,7 @@ bool params_ok(const lbm_params *p, std::string *why)
     return true;
 }
 
-struct Prepared {
-    // per link, in (obj, node, dir) order
-    std::vector<uint32_t> meta;
-    std::vector<double> q, uw;
-    std::vector<int32_t> sf, sff, pf, pff, li;
-    // per flagged node, in plane order
-    std::vector<uint16_t> rec;
-    std::vector<int32_t> mnode, pbase;
-    std::vector<lbm::mask_t> mask;         // padded to the pitch: link bits, solid bit, side bit
-    std::vector<lbm::SegBase> seg;         // per 64-node row segment
-    int64_t n_pops = 0;
-    bool has_uw = false;
-    int64_t n_fallback = 0;
-};
+
 
 // Validates mask and links; on success fills the device-ready link arrays
 // (sorted by object, then node, then direction).
@@ -380,7 +360,9 @@ lbm_status prepare_geometry(const lbm_params &p, const uint8_t *mask, int64_t n,
     return LBM_OK;
 }
 
-}  // namespace
+}  // namespace lbm_host
+
+using namespace lbm_host;
 
 struct lbm_ctx {
     lbm_params p{};

@@ -1,0 +1,102 @@
+"""Batched form on the GPU: many lattices of uneven size in one link launch and one
+bulk launch per step must give every instance exactly what a single-lattice
+context gives it (populations and moments bitwise; forces to the summation order
+of FP64 atomics), and hence the oracle's result within the stated tolerances."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1903_01111_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1903_01111_amd import binding
+    binding.lib()
+    return binding
+
+
+def _walled(seed, n):
+    """Walled cylinder channels of uneven size; Re in [10, 20] keeps tau >= 0.56
+    at these resolutions."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        nx = int(rng.integers(70, 330))
+        re = float(10 + 10 * rng.random())
+        r1, r2 = rng.random(2)
+        out.append(W.walled_cylinder(nx, re, r1, r2))
+    return out
+
+
+def _equal_to_single(B, cases, storage, nsteps):
+    bt = B.Batch(cases, storage=storage)
+    print(f"[batch] {len(cases)} instances, {bt.n_nodes} nodes, {storage}, {nsteps} steps", flush=True)
+    bt.step(nsteps)
+    for i, c in enumerate(cases):
+        rb, uxb, uyb = bt.moments(i)
+        lat = B.Lattice(c, storage=storage)
+        lat.step(nsteps)
+        rs, uxs, uys = lat.moments()
+        assert np.array_equal(rb, rs) and np.array_equal(uxb, uxs) and np.array_equal(uyb, uys), i
+        for o in range(c.n_obj):
+            lb, sb, nb = bt.force(i, o)
+            ls, ss, ns = lat.force(o)
+            assert nb == ns == nsteps
+            scale = max(np.abs(ss).max(), 1e-30)
+            assert np.abs(sb - ss).max() <= 1e-12 * scale, (i, o)
+            assert np.abs(lb - ls).max() <= 1e-12 * max(np.abs(ls).max(), 1e-30), (i, o)
+        lat.close()
+    bt.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64", "f16"])
+def test_batch_equals_single_open_channels(B, storage):
+    _equal_to_single(B, _walled(1, 7), storage, 53)
+
+
+def test_batch_equals_single_periodic_with_body_force(B):
+    cases = [W.porous_medium(nx=nx, ny=ny, rmin=3, rmax=6, seed=s, g=1e-5)
+             for s, (nx, ny) in enumerate([(128, 64), (100, 37), (64, 90), (257, 50)])]
+    cases[1].gx = 0.0  # an instance without force in a forced batch
+    _equal_to_single(B, cases, "f32", 41)
+
+
+def test_batch_instance_matches_oracle(B):
+    cases = _walled(2, 3)
+    bt = B.Batch(cases, storage="f64")
+    bt.step(200)
+    for i, c in enumerate(cases):
+        _, ux, uy = bt.moments(i)
+        fp, g, fs, _, _ = oracle.run_case(c, nsteps=200)
+        _, uxr, uyr = oracle.moments(fp, g.solid)
+        ref = max(np.abs(uxr).max(), np.abs(uyr).max())
+        assert max(np.abs(ux - uxr).max(), np.abs(uy - uyr).max()) / ref <= 1e-11
+        _, s, _ = bt.force(i, 0)
+        assert np.abs(s - fs[0]).max() <= 1e-10 * np.abs(fs[0]).max()
+    bt.close()
+
+
+def test_batch_errors(B):
+    cases = _walled(3, 2)
+    p = [B.make_params(c.nx, c.ny, x_open=True, tau=c.tau) for c in cases]
+    p[1].storage = B.LBM_F64
+    assert B.lbm_batch_workspace_bytes(p, [10, 10]) == 0
+    p[1].storage = B.LBM_F32
+    import torch
+    n = B.lbm_batch_workspace_bytes(p, [2000, 2000])
+    ws = torch.empty(n + 256, dtype=torch.uint8, device="cuda")
+    ptr = ws.data_ptr() + (-ws.data_ptr()) % 256
+    b = B.lbm_batch_create(p, [2000, 2000], ptr, n)
+    with pytest.raises(B.LbmError) as e:
+        B.lbm_batch_step(b, 1)
+    assert e.value.status == B.LBM_E_STATE
+    with pytest.raises(B.LbmError) as e:
+        B.lbm_batch_moments(b, 5, 4, 4)
+    assert e.value.status == B.LBM_E_ARG
+    B.lbm_batch_destroy(b)
