@@ -87,6 +87,121 @@ def algorithmic_bytes(case, mask, n_links, n_vibb, storage):
     return bulk, link
 
 
+def timed(B, lat, steps):
+    """steps with every launch bracketed by HIP events; (ms total, link ms, bulk ms)."""
+    import torch
+    B.lbm_set_profiling(lat.ctx, True)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    lat.step(steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    link_ms, bulk_ms, n = B.lbm_kernel_times(lat.ctx)
+    B.lbm_set_profiling(lat.ctx, False)
+    return ev0.elapsed_time(ev1), link_ms, bulk_ms
+
+
+def e_u(a, b):
+    import numpy as np
+    ref = max(np.abs(b[0]).max(), np.abs(b[1]).max())
+    return float(max(np.abs(a[0] - b[0]).max(), np.abs(a[1] - b[1]).max()) / ref)
+
+
+def form_precision(B, case, steps_err, steps_time):
+    """16-bit deviation storage against FP32 on the same workload: velocity error
+    after steps_err steps from the same initial state, and throughput."""
+    f32 = B.Lattice(case, storage="f32")
+    f32.step(steps_err)
+    _, u32, v32 = f32.moments()
+    k = B.dev_scale_for(B.lbm_max_deviation(f32.ctx))
+    _, fs32, _ = f32.force(0)
+    f32.close()
+    out = {}
+    for st, kk in (("f16", k), ("bf16", 0)):
+        lat = B.Lattice(case, storage=st, dev_scale_log2=kk)
+        lat.step(steps_err)
+        try:
+            _, u, v = lat.moments()
+            err = e_u((u, v), (u32, v32))
+            _, fs, _ = lat.force(0)
+            ferr = float(abs(fs[0] - fs32[0]) / abs(fs32[0]))
+        except B.LbmError as e:
+            err, ferr = f"unstable ({e})", None
+        B.lbm_autotune(lat.ctx, 10)
+        ms, link_ms, bulk_ms = timed(B, lat, steps_time)
+        nfb = B.lbm_check_geometry(lat.params, lat.mask, lat.node, lat.dir, lat.q, lat.uw, lat.obj,
+                                   lat.scheme)
+        bulk_bytes, _ = algorithmic_bytes(case, lat.mask, lat.n_links, lat.n_links - nfb, st)
+        out[st] = {"scale_log2": kk, "e_u_vs_f32": err, "drag_err_vs_f32": ferr, "steps": steps_err,
+                   "mlups": round(case.nx * case.ny * steps_time / (ms * 1e-3) / 1e6, 1),
+                   "bulk_GBps_algorithmic": round(bulk_bytes / (bulk_ms * 1e-3 / steps_time) / 1e9, 1)}
+        lat.close()
+        print(f"[bench] {st}: {out[st]}", file=sys.stderr, flush=True)
+    return out
+
+
+def form_batched(B, n_inst, steps, warmup):
+    """The batched workload (uneven walled-cylinder channels) in one batch, against
+    a loop over single-lattice contexts of the same instances."""
+    import numpy as np
+    import torch
+    from paper_1903_01111_amd import workloads as W
+    cases = W.batched_cylinders(n_inst)
+    geoms = [B.case_geometry(c) for c in cases]
+    bt = B.Batch(cases, storage="f32", geometries=geoms)
+    bt.step(warmup)
+    bt.sync()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    bt.step(steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    finite = 0
+    for i in range(len(cases)):
+        try:
+            bt.moments(i)
+            finite += 1
+        except B.LbmError:
+            pass
+    bt.close()
+    lats = [B.Lattice(c, storage="f32", geometry=g) for c, g in zip(cases, geoms)]
+    for lat in lats:
+        lat.step(warmup)
+    torch.cuda.synchronize()
+    ev0.record()
+    for lat in lats:
+        lat.step(steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_loop = ev0.elapsed_time(ev1)
+    for lat in lats:
+        lat.close()
+    n_nodes = sum(c.nx * c.ny for c in cases)
+    taus = [c.tau for c in cases]
+    out = {"workload": f"{n_inst} walled-cylinder channels, nx U{{256..1024}}, ny = nx/4, Re U[20,100]",
+           "nodes": n_nodes, "steps": steps, "mlups": round(n_nodes * steps / (ms * 1e-3) / 1e6, 1),
+           "single_context_loop_mlups": round(n_nodes * steps / (ms_loop * 1e-3) / 1e6, 1),
+           "speedup_vs_loop": round(ms_loop / ms, 2), "instances_finite_after": finite,
+           "tau_range": [round(min(taus), 4), round(max(taus), 4)]}
+    print(f"[bench] batched: {out}", file=sys.stderr, flush=True)
+    return out
+
+
+def form_single(B, case, steps, warmup):
+    lat = B.Lattice(case, storage="f32")
+    lat.step(warmup)
+    B.lbm_autotune(lat.ctx, 10)
+    ms, link_ms, bulk_ms = timed(B, lat, steps)
+    lat.moments()
+    lat.close()
+    return {"mlups": round(case.nx * case.ny * steps / (ms * 1e-3) / 1e6, 1),
+            "bulk_us": round(bulk_ms * 1e3 / steps, 2), "link_us": round(link_ms * 1e3 / steps, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +213,8 @@ def main():
                     help="oracle steps on the full lattice for the CPU baseline (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 1 GiB device copy (counter calibration under rocprofv3)")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the FP16/BF16 storage, batched and cylinder measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part "
@@ -225,6 +342,15 @@ def main():
         out["error_vs_oracle"] = {"e_u": float(err), "steps": args.cpu_steps,
                                   "definition": "max|u_gpu - u_oracle| / max|u_oracle|"}
     lat.close()
+    if not args.no_forms:
+        from paper_1903_01111_amd import workloads as W
+        forms = {}
+        forms["storage_16bit"] = form_precision(B, case, 1000, 500)
+        forms["batched"] = form_batched(B, 256, 300, 20)
+        forms["cylinder_2048x512_f32"] = form_single(B, W.cylinder_channel(), 2000, 100)
+        forms["cylinder_2048x512_f32"]["note"] = ("75 MB working set: resident in the 256 MB "
+                                                  "last-level cache, not an HBM figure")
+        out["forms"] = forms
     print(json.dumps(out), flush=True)
 
 
