@@ -72,15 +72,15 @@ def workload(name):
 def algorithmic_bytes(case, mask, n_links, n_vibb, storage):
     """Bytes the method must move per launch (no cache reuse assumed beyond one
     read of every input and one write of every output):
-    bulk: 9 loads + 9 stores per fluid node, 1 mask byte per node, plus the two
-          open columns written again; link: per link 16 B of indices, q (and u_w),
+    bulk: 9 loads + 9 stores per fluid node, a 2-byte mask word per node, plus the
+          two open columns written again; link: per link 16 B of indices, q (and u_w),
           the populations of f and ff (9 + 9 for VIBB, 1 for halfway bounce-back)
           and one store."""
     s = BYTES[storage]
     rb = 8 if storage == "f64" else 4
     n = case.nx * case.ny
     nf = int((mask == 0).sum())
-    bulk = nf * 18 * s + n
+    bulk = nf * 18 * s + 2 * n
     if case.x_open:
         bulk += 2 * case.ny * 9 * s
     link = n_links * (16 + rb + s) + n_vibb * 18 * s + (n_links - n_vibb) * s
