@@ -116,6 +116,16 @@ lbm_status lbm_geometry(int32_t nx, int32_t ny, int32_t x_bc, int32_t n_prim, co
                         uint8_t *mask_out, int64_t max_links, int32_t *node, int8_t *dir,
                         double *q, double *uw, int32_t *obj, int64_t *n_links_out);
 
+/* lbm_geometry plus, per link (either may be NULL): prim[k], the primitive that
+ * sets its q, and dq[3k..3k+2] = dq/d(cx, cy, r) of that primitive with the node
+ * classification held fixed (circles: from |x_f + q e - c| = r, so with
+ * p = x_w - c, dq/dc = p/(p.e) and dq/dr = r/(p.e); lines: dq/dcy = 1/e_y). */
+lbm_status lbm_geometry_ex(int32_t nx, int32_t ny, int32_t x_bc, int32_t n_prim, const int32_t *kind,
+                           const double *geo, const double *motion, const int32_t *prim_obj,
+                           uint8_t *mask_out, int64_t max_links, int32_t *node, int8_t *dir,
+                           double *q, double *uw, int32_t *obj, int32_t *prim, double *dq,
+                           int64_t *n_links_out);
+
 /* Validates a mask and link list against params without touching a device:
  * sizes, q in (0,1], every link from a streamed fluid node into a solid node,
  * no duplicate (node, dir), every pull from a solid node covered by a link, obj

@@ -56,6 +56,8 @@ _P, _V, _I64, _I32, _D = C.c_void_p, None, C.c_int64, C.c_int32, C.c_double
 SIGNATURES = [
     ("lbm_last_error", C.c_char_p, [_P]),
     ("lbm_geometry", _I32, [_I32, _I32, _I32, _I32, _P, _P, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P]),
+    ("lbm_geometry_ex", _I32, [_I32, _I32, _I32, _I32, _P, _P, _P, _P, _P, _I64, _P, _P, _P, _P, _P,
+                               _P, _P, _P]),
     ("lbm_check_geometry", _I32, [_P, _P, _I64, _P, _P, _P, _P, _P, _P, _P]),
     ("lbm_workspace_bytes", C.c_size_t, [_P, _I64]),
     ("lbm_create", _I32, [_P, _P, C.c_size_t, _P]),
@@ -161,6 +163,29 @@ def lbm_geometry(nx, ny, x_bc, kind, geo, motion, prim_obj):
     obj = np.zeros(k, np.int32)
     check(lib().lbm_geometry(*args, k, _p(node), _p(d), _p(q), _p(uw), _p(obj), C.byref(n)))
     return mask, node, d, q, uw, obj
+
+
+def lbm_geometry_ex(nx, ny, x_bc, kind, geo, motion, prim_obj):
+    """lbm_geometry plus the primitive of each link and dq/d(cx, cy, r) (n, 3)."""
+    kind = np.ascontiguousarray(kind, np.int32)
+    geo = np.ascontiguousarray(geo, np.float64).reshape(-1, 3)
+    motion = np.ascontiguousarray(motion, np.float64).reshape(-1, 3)
+    prim_obj = np.ascontiguousarray(prim_obj, np.int32)
+    mask = np.zeros((ny, nx), np.uint8)
+    n = C.c_int64(0)
+    args = [nx, ny, x_bc, len(kind), _p(kind), _p(geo), _p(motion), _p(prim_obj), _p(mask)]
+    check(lib().lbm_geometry_ex(*args, 0, None, None, None, None, None, None, None, C.byref(n)))
+    k = n.value
+    node = np.zeros(k, np.int32)
+    d = np.zeros(k, np.int8)
+    q = np.zeros(k)
+    uw = np.zeros((k, 2))
+    obj = np.zeros(k, np.int32)
+    prim = np.zeros(k, np.int32)
+    dq = np.zeros((k, 3))
+    check(lib().lbm_geometry_ex(*args, k, _p(node), _p(d), _p(q), _p(uw), _p(obj), _p(prim), _p(dq),
+                                C.byref(n)))
+    return mask, node, d, q, uw, obj, prim, dq
 
 
 def lbm_check_geometry(params, mask, node, dir, q, uw=None, obj=None, scheme=None):

@@ -83,6 +83,16 @@ extern "C" lbm_status lbm_geometry(int32_t nx, int32_t ny, int32_t x_bc, int32_t
                                    int32_t *node, int8_t *dir, double *q, double *uw, int32_t *obj,
                                    int64_t *n_links_out)
 {
+    return lbm_geometry_ex(nx, ny, x_bc, n_prim, kind, geo, motion, prim_obj, mask_out, max_links, node,
+                           dir, q, uw, obj, nullptr, nullptr, n_links_out);
+}
+
+extern "C" lbm_status lbm_geometry_ex(int32_t nx, int32_t ny, int32_t x_bc, int32_t n_prim,
+                                      const int32_t *kind, const double *geo, const double *motion,
+                                      const int32_t *prim_obj, uint8_t *mask_out, int64_t max_links,
+                                      int32_t *node, int8_t *dir, double *q, double *uw, int32_t *obj,
+                                      int32_t *prim, double *dq, int64_t *n_links_out)
+{
     if (nx < 1 || ny < 1 || (int64_t)nx * ny > ((int64_t)1 << 31) - 1 || n_prim < 0 ||
         (n_prim > 0 && (!kind || !geo)) || !mask_out || !n_links_out ||
         (x_bc != LBM_X_PERIODIC && x_bc != LBM_X_OPEN)) {
@@ -168,6 +178,23 @@ extern "C" lbm_status lbm_geometry(int32_t nx, int32_t ny, int32_t x_bc, int32_t
                     uw[2 * count] = p.ux - p.om * bry;
                     uw[2 * count + 1] = p.uy + p.om * brx;
                     obj[count] = p.obj;
+                    if (prim) prim[count] = bp;
+                    if (dq) {
+                        // derivatives of q with respect to (cx, cy, r) of the primitive, from
+                        // |x_f + q e - c| = r (circles: with p = x_w - c, dq/dc = p/(p.e),
+                        // dq/dr = +-r/(p.e)) or x_f.y + q e.y = cy (lines: dq/dcy = 1/e.y)
+                        double *d = dq + 3 * count;
+                        if (p.kind == LBM_PRIM_DISC || p.kind == LBM_PRIM_RING) {
+                            const double pe = brx * EXG[ip] + bry * EYG[ip];
+                            d[0] = brx / pe;
+                            d[1] = bry / pe;
+                            d[2] = p.r / pe;
+                        } else {
+                            d[0] = 0.0;
+                            d[1] = 1.0 / EYG[ip];
+                            d[2] = 0.0;
+                        }
+                    }
                 }
                 ++count;
             }

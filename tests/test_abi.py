@@ -174,3 +174,25 @@ def test_fallback_count_matches_oracle():
     fp = oracle.init_equilibrium(g.solid, *case.init_fields())
     _, _, nfb_oracle = oracle.run(fp, g, tau=0.7, nsteps=1)
     assert nfb == nfb_oracle > 0
+
+
+def test_geometry_fraction_derivatives_match_oracle_complex_step():
+    """dq/d(cx, cy, R) of the library's geometry against the oracle's complex-step
+    evaluation of its own q (an exact derivative of an independent routine)."""
+    base = [(20.37, 11.21, 5.3), (41.6, 17.9, 4.05)]
+    kind = np.array([W.PRIM_DISC, W.PRIM_DISC], np.int32)
+    mot = np.zeros((2, 3))
+    pobj = np.array([0, 1], np.int32)
+    mask, node, d, q, uw, obj, prim, dq = B.lbm_geometry_ex(60, 30, B.LBM_X_OPEN, kind,
+                                                            np.array(base), mot, pobj)
+    h = 1e-30
+    for p_ in range(2):
+        for k in range(3):
+            geo = np.array(base, dtype=np.complex128)
+            geo[p_, k] += 1j * h
+            g = oracle.geometry(60, 30, True, kind, geo, mot, pobj, complex_step=True)
+            assert np.array_equal(g.node, node) and np.array_equal(g.dir, d)
+            cs = g.q.imag / h
+            sel = prim == p_
+            assert np.abs(dq[sel, k] - cs[sel]).max() < 1e-9 * max(1.0, np.abs(cs[sel]).max())
+            assert np.abs(cs[~sel]).max() == 0.0
