@@ -286,6 +286,50 @@ lbm_status lbm_batch_force(lbm_batch *b, int32_t inst, int32_t obj, double last[
                            int64_t *nsum);
 lbm_status lbm_batch_force_reset(lbm_batch *b);
 
+/* ---------------------------------------------------------------------------
+ * Adjoint form: gradients of a time-averaged force by the discrete adjoint of
+ * the step (the reverse of the link update of Section 3.1, of the pull streaming
+ * and BGK/Guo collision of Section 2 and of the open columns of Section 4.3).
+ *
+ * Objective, for the nsteps steps that follow the context's current state S_0:
+ *     J = (1/nsteps) sum_{t=0}^{nsteps-1} (d_x F_x(t) + d_y F_y(t)),
+ * F(t) the momentum-exchange force on object obj during step t (what lbm_force
+ * accumulates) and d = (dir_x, dir_y) (d = (1, 0): the mean drag).
+ *
+ * Method: a forward sweep of nsteps steps keeps the state every ckpt_every steps;
+ * the reverse sweep recomputes each segment of ckpt_every steps from its
+ * checkpoint and runs the adjoint step backwards through it.  The gradients are
+ * derivatives of the discrete map with the node classification held fixed; at
+ * q = 1/2 the VIBB velocity branch of the forward (q <= 1/2) is differentiated.
+ * Adjoint arithmetic is in the storage's precision; gradients with respect to the
+ * parameters are accumulated in FP64.  FP64 and FP32 storage only.
+ *
+ * lbm_adjoint_workspace_bytes: device bytes the call needs for this context
+ * (checkpoints, the recomputed segment, adjoint fields); 0 on invalid arguments.
+ *
+ * lbm_adjoint_force: ws is a caller-owned device buffer, 256-byte aligned, of at
+ * least lbm_adjoint_workspace_bytes; nothing is retained after the call.  On
+ * return the context has advanced by nsteps exactly as lbm_step(nsteps) advances
+ * it (state, step count, force accumulators).  Outputs (host, each may be NULL):
+ *   J           the objective;
+ *   dJ_duin     [2*ny]   dJ/d(u_in,x, u_in,y) of every inlet row (open lattices);
+ *   dJ_dq       [n_links] dJ/dq of every link, in the order given to lbm_set_geometry;
+ *   dJ_duw      [2*n_links] dJ/du_w of every link, same order;
+ *   dJ_dstate   [nx*ny*9] dJ/df+_i(x, 0) of the initial post-collision state,
+ *               node-major (index (y*nx + x)*9 + i), zero at solid nodes;
+ *   dJ_dinit    [nx*ny*3] dJ/d(rho, ux, uy) of the initial fields, reading the
+ *               initial state as f+ = f^eq(rho, u) of its own (rho, u) (the state
+ *               lbm_init_equilibrium writes), node-major, zero at solid nodes.
+ * Errors: LBM_E_ARG (nsteps < 1, ckpt_every < 1, obj out of range, 16-bit
+ * storage, workspace null, misaligned or too small), LBM_E_STATE (no geometry or
+ * initialisation), LBM_E_DEVICE, LBM_E_UNSTABLE (non-finite objective or
+ * gradient). */
+size_t lbm_adjoint_workspace_bytes(const lbm_ctx *ctx, int64_t nsteps, int32_t ckpt_every);
+lbm_status lbm_adjoint_force(lbm_ctx *ctx, void *ws, size_t ws_bytes, int64_t nsteps,
+                             int32_t ckpt_every, int32_t obj, double dir_x, double dir_y, double *J,
+                             double *dJ_duin, double *dJ_dq, double *dJ_duw, double *dJ_dstate,
+                             double *dJ_dinit);
+
 #ifdef __cplusplus
 }
 #endif

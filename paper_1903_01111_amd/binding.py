@@ -96,6 +96,8 @@ SIGNATURES = [
     ("lbm_batch_moments", _I32, [_P, _I32, _P, _P, _P]),
     ("lbm_batch_force", _I32, [_P, _I32, _I32, _P, _P, _P]),
     ("lbm_batch_force_reset", _I32, [_P]),
+    ("lbm_adjoint_workspace_bytes", C.c_size_t, [_P, _I64, _I32]),
+    ("lbm_adjoint_force", _I32, [_P, _P, C.c_size_t, _I64, _I32, _I32, _D, _D, _P, _P, _P, _P, _P, _P]),
 ]
 
 
@@ -359,6 +361,26 @@ def lbm_autotune(ctx, steps_per_trial=20):
     return k, ms.value
 
 
+def lbm_adjoint_workspace_bytes(ctx, nsteps, ckpt_every) -> int:
+    return int(lib().lbm_adjoint_workspace_bytes(ctx, nsteps, ckpt_every))
+
+
+def lbm_adjoint_force(ctx, workspace_ptr, nbytes, nsteps, ckpt_every, obj, dir_x, dir_y, *, ny, nx,
+                      n_links, want_state=False, want_init=False):
+    """Runs lbm_adjoint_force; returns dict(J, duin (ny,2), dq (n_links,), duw
+    (n_links,2), dstate (ny,nx,9) or None, dinit (ny,nx,3) or None)."""
+    J = C.c_double(0.0)
+    duin = np.zeros((ny, 2))
+    dq = np.zeros(max(n_links, 0))
+    duw = np.zeros((max(n_links, 0), 2))
+    dstate = np.zeros((ny, nx, 9)) if want_state else None
+    dinit = np.zeros((ny, nx, 3)) if want_init else None
+    check(lib().lbm_adjoint_force(ctx, workspace_ptr, nbytes, nsteps, ckpt_every, obj, float(dir_x),
+                                  float(dir_y), C.byref(J), _p(duin), _p(dq), _p(duw), _p(dstate),
+                                  _p(dinit)), ctx)
+    return dict(J=J.value, duin=duin, dq=dq, duw=duw, dstate=dstate, dinit=dinit)
+
+
 def _bcheck(status, b):
     if status != LBM_OK:
         m = lib().lbm_batch_last_error(b)
@@ -571,6 +593,25 @@ class Lattice:
 
     def mass(self):
         return lbm_mass(self.ctx)
+
+    def adjoint_force(self, nsteps, ckpt_every=100, obj=0, direction=(1.0, 0.0), want_state=False,
+                      want_init=False):
+        """Time-averaged force along `direction` over the next nsteps steps and its
+        gradients (lbm_adjoint_force); advances the lattice by nsteps.  dq and duw
+        are in the order of self.q."""
+        import torch
+
+        nbytes = lbm_adjoint_workspace_bytes(self.ctx, nsteps, ckpt_every)
+        if nbytes == 0:
+            raise LbmError(LBM_E_ARG, "adjoint: invalid arguments or storage")
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = ws.data_ptr()
+        ptr += (-ptr) % 256
+        out = lbm_adjoint_force(self.ctx, ptr, nbytes, nsteps, ckpt_every, obj, direction[0],
+                                direction[1], ny=self.case.ny, nx=self.case.nx, n_links=self.n_links,
+                                want_state=want_state, want_init=want_init)
+        del ws
+        return out
 
     @property
     def n_links(self):

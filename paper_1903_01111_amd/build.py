@@ -15,8 +15,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "liblbm_vibb.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-HIP_SOURCES = ["lbm_kernels.hip"]
-CXX_SOURCES = ["lbm_runtime.cpp", "lbm_batch.cpp", "lbm_geometry.cpp"]
+HIP_SOURCES = ["lbm_kernels.hip", "lbm_adjoint.hip"]
+CXX_SOURCES = ["lbm_runtime.cpp", "lbm_batch.cpp", "lbm_geometry.cpp", "lbm_adjoint.cpp"]
 
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
                # packed FP32 instructions are kept out of the generated code
@@ -62,8 +62,8 @@ def build(verbose: bool = False) -> str:
 
 
 def sources():
-    return [os.path.join(CSRC, s) for s in HIP_SOURCES + CXX_SOURCES] + [
-        os.path.join(CSRC, "lbm_internal.h"), os.path.join(CSRC, "lbm_host.h"),
+    headers = sorted(os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h"))
+    return [os.path.join(CSRC, s) for s in HIP_SOURCES + CXX_SOURCES] + headers + [
         os.path.join(ROOT, "include", "lbm.h")]
 
 

@@ -35,6 +35,7 @@ struct Prepared {
     std::vector<uint32_t> meta;
     std::vector<double> q, uw;
     std::vector<int32_t> sf, sff, pf, pff, li;
+    std::vector<int64_t> order;  // caller's index of each link
     // per flagged node, in plane order
     std::vector<uint16_t> rec;
     std::vector<int32_t> mnode, pbase;

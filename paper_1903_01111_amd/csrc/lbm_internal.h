@@ -134,4 +134,35 @@ hipError_t launch_mass(int storage, const Grid &g, const Phys &ph, const void *A
 
 int32_t mass_blocks(const Grid &g);
 
+// ---------------------------------------------------------------------------
+// Adjoint kernels (lbm_adjoint.hip); FP64 and FP32 storage only.  Side records
+// hold 12 doubles per flagged node.
+// ---------------------------------------------------------------------------
+
+// One lane per link.  With Sn (state of step t+1): back-propagates the adjoint
+// Lbar of every link value of step t+1 (plus the force weight (djx, djy) for
+// links of object obj) into the side records of x_f and x_ff and into the FP64
+// accumulators dq[l] and duw[2l..2l+1]; with Sc (state of step t): writes the
+// link values of step t into Lf.  Either state may be null.
+hipError_t launch_adj_link(int storage, const Grid &g, const Phys &ph, const Links &L, const int32_t *mnode,
+                           const void *Sn, const void *Sc, void *Lf, const void *Lbar, double *sig, double *dq,
+                           double *duw, int32_t obj, double djx, double djy, hipStream_t s);
+
+// One lane per node: from the adjoint Cin of the pre-collision populations of
+// step t+1 and the side records (consumed and cleared), the adjoint Cout of the
+// pre-collision populations of step t (state S of step t, link values Lf) and
+// its link entries Lbar; inlet rows add to duin (2 doubles per row).  colslot:
+// side slots of the inlet and outlet column nodes (open lattices).
+hipError_t launch_adj_bulk(int storage, const Grid &g, const Phys &ph, const void *S, const void *Lf,
+                           const void *Cin, void *Cout, void *Lbar, double *sig, const mask_t *mask,
+                           const SegBase *seg, const int32_t *colslot, const void *uin, double *duin,
+                           hipStream_t s);
+
+// dJ/dS_0 (nine planes of dplane doubles) and dJ/d(rho, ux, uy) of an
+// equilibrium initial state (three planes) from Cin and the side records of
+// step 0.
+hipError_t launch_adj_final(int storage, const Grid &g, const Phys &ph, const void *S, const void *Cin,
+                            const double *sig, const mask_t *mask, const SegBase *seg, double *dstate,
+                            double *dinit, int64_t dplane, hipStream_t s);
+
 }  // namespace lbm

@@ -13,9 +13,7 @@
 #include <string>
 #include <vector>
 
-#include "lbm.h"
-#include "lbm_host.h"
-#include "lbm_internal.h"
+#include "lbm_ctx.h"
 
 namespace lbm_host {
 
@@ -33,14 +31,6 @@ size_t elem_bytes(int storage)
 }
 size_t real_bytes(int storage) { return storage == LBM_F64 ? 8 : 4; }
 
-struct Layout {
-    int32_t pitch;
-    int64_t plane;  // elements per population plane
-    size_t off_A, off_B, off_mask, off_seg, off_meta, off_q, off_uw, off_sf, off_sff, off_pf, off_pff,
-        off_li, off_L, off_rec, off_mnode, off_pbase, off_M, off_P, off_wpart, off_wobj, off_uin,
-        off_force, off_partials, off_stage, total;
-    int64_t wave_cap;  // wavefront partials of the link kernel
-};
 
 // device bytes per link of capacity (link arrays, and up to two flagged nodes
 // with their side moments)
@@ -312,6 +302,7 @@ lbm_status prepare_geometry(const lbm_params &p, const uint8_t *mask, int64_t n,
         if (node[a] != node[b]) return node[a] < node[b];
         return dir[a] < dir[b];
     });
+    out->order = order;
     out->meta.resize(n);
     out->q.resize(n);
     out->sf.assign(n, -1);
@@ -364,94 +355,10 @@ lbm_status prepare_geometry(const lbm_params &p, const uint8_t *mask, int64_t n,
 
 using namespace lbm_host;
 
-struct lbm_ctx {
-    lbm_params p{};
-    Layout lay{};
-    hipStream_t stream = nullptr;
-    hipStream_t cap_stream = nullptr;  // private stream the step graph is captured on
-    std::string err = "no error";
-    char *ws = nullptr;
-    size_t ws_bytes = 0;
-    int64_t max_links = 0, n_links = 0, n_moment_nodes = 0;
-    bool has_uw = false, have_geom = false, have_init = false;
-    void *cur = nullptr, *nxt = nullptr;
-    int64_t step = 0, nsum = 0;
-    lbm_kernel_config kcfg{256, 0, 256, 16};
-    // graph of kcfg.graph_steps steps starting from buffer `graph_cur`
-    hipGraphExec_t gexec = nullptr;
-    void *graph_cur = nullptr;
-    // profiling
-    bool prof = false;
-    std::vector<hipEvent_t> events;
-    size_t ev_used = 0;
-    double link_ms = 0, bulk_ms = 0;
-    int64_t prof_steps = 0;
-
-    lbm::Grid grid() const
-    {
-        return lbm::Grid{p.nx, p.ny, lay.pitch, p.x_bc == LBM_X_OPEN ? 1 : 0, lay.plane};
-    }
-    lbm::Phys phys() const
-    {
-        const float sc = std::ldexp(1.0f, p.storage >= LBM_F16_DEV ? p.dev_scale_log2 : 0);
-        return lbm::Phys{1.0 / p.tau, p.gx, p.gy, p.rho0, sc, 1.0f / sc};
-    }
-    lbm::Links links() const
-    {
-        auto i32 = [&](size_t off) { return reinterpret_cast<const int32_t *>(ws + off); };
-        return lbm::Links{reinterpret_cast<const uint32_t *>(ws + lay.off_meta), ws + lay.off_q,
-                          has_uw ? ws + lay.off_uw : nullptr, i32(lay.off_sf), i32(lay.off_sff),
-                          i32(lay.off_pf), i32(lay.off_pff), i32(lay.off_li), n_links};
-    }
-    lbm::Reduce reduce() const
-    {
-        return lbm::Reduce{reinterpret_cast<double2 *>(ws + lay.off_wpart),
-                           reinterpret_cast<int32_t *>(ws + lay.off_wobj)};
-    }
-    lbm::BulkConfig bulk_config() const { return lbm::BulkConfig{kcfg.bulk_block_x, kcfg.bulk_store_solid}; }
-    lbm::Side side() const
-    {
-        return lbm::Side{ws + lay.off_M, ws + lay.off_P, ws + lay.off_L,
-                         reinterpret_cast<const uint16_t *>(ws + lay.off_rec),
-                         reinterpret_cast<const lbm::SegBase *>(ws + lay.off_seg),
-                         reinterpret_cast<const int32_t *>(ws + lay.off_mnode),
-                         reinterpret_cast<const int32_t *>(ws + lay.off_pbase), n_moment_nodes};
-    }
-    lbm::mask_t *mask() const { return reinterpret_cast<lbm::mask_t *>(ws + lay.off_mask); }
-    double *force() const { return reinterpret_cast<double *>(ws + lay.off_force); }
-    double *bank(int64_t t) const { return force() + (size_t)(t & 1) * 2 * p.n_obj; }
-    double *fsum() const { return force() + 4 * (size_t)p.n_obj; }
-    double *stage() const { return reinterpret_cast<double *>(ws + lay.off_stage); }
-    double *partials() const { return reinterpret_cast<double *>(ws + lay.off_partials); }
-
-    lbm_status fail(lbm_status s, const char *fmt, ...)
-    {
-        char m[512];
-        va_list ap;
-        va_start(ap, fmt);
-        std::vsnprintf(m, sizeof m, fmt, ap);
-        va_end(ap);
-        err = m;
-        return s;
-    }
-    lbm_status hip(hipError_t e, const char *what)
-    {
-        if (e == hipSuccess) return LBM_OK;
-        return fail(LBM_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
-    }
-    void drop_graph()
-    {
-        if (gexec) hipGraphExecDestroy(gexec);
-        gexec = nullptr;
-        graph_cur = nullptr;
-    }
-};
 
 extern "C" void lbm_set_thread_error(const char *msg) { g_thread_error = msg; }
 
-namespace {
-
-lbm_status enqueue_step(lbm_ctx *c, bool timed)
+lbm_status lbm_host::enqueue_step(lbm_ctx *c, bool timed)
 {
     const lbm::Grid g = c->grid();
     const lbm::Phys ph = c->phys();
@@ -483,6 +390,8 @@ lbm_status enqueue_step(lbm_ctx *c, bool timed)
     ++c->nsum;
     return LBM_OK;
 }
+
+namespace {
 
 lbm_status collect_times(lbm_ctx *c)
 {
@@ -717,6 +626,16 @@ lbm_status lbm_set_geometry(lbm_ctx *c, const uint8_t *mask, int64_t n_links, co
     if ((s = c->hip(hipStreamSynchronize(st), "geometry upload")))  // host vectors die here
         return s;
     c->n_links = n_links;
+    c->link_order = prep.order;
+    c->colslot.assign(c->p.x_bc == LBM_X_OPEN ? 2 * (size_t)c->p.ny : 0, -1);
+    if (c->p.x_bc == LBM_X_OPEN)
+        for (int y = 0; y < c->p.ny; ++y)
+            for (int side = 0; side < 2; ++side) {
+                const int32_t o = y * c->lay.pitch + (side ? c->p.nx - 1 : 0);
+                auto it = std::lower_bound(prep.mnode.begin(), prep.mnode.end(), o);
+                if (it != prep.mnode.end() && *it == o)
+                    c->colslot[(size_t)side * c->p.ny + y] = (int32_t)(it - prep.mnode.begin());
+            }
     c->n_moment_nodes = (int64_t)prep.rec.size();
     c->has_uw = prep.has_uw;
     c->have_geom = true;
