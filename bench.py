@@ -202,6 +202,56 @@ def form_single(B, case, steps, warmup):
             "bulk_us": round(bulk_ms * 1e3 / steps, 2), "link_us": round(link_ms * 1e3 / steps, 2)}
 
 
+def form_adjoint(B, steps=2000, ckpt=100):
+    """Drag gradient of the uniform-inlet cylinder 1024x256 (R = 12.4, Re = 100):
+    wall time of the adjoint call (forward sweep with checkpoints, recomputation,
+    reverse sweep) against the plain FP32 forward over the same steps, and the
+    FP32 gradient dJ/d(U, cx, cy, R) against the FP64 one."""
+    import numpy as np
+    import torch
+    from paper_1903_01111_amd import workloads as W
+    from paper_1903_01111_amd.autograd import drag_and_gradient, with_parameters
+    base = W.adjoint_cylinder(nsteps=steps)
+    p0 = [0.05, base.prims[0].cx, base.prims[0].cy, base.prims[0].r]
+    case = with_parameters(base, *p0)
+    # plain forward, FP32, same steps from the same initial state
+    lat = B.Lattice(case, storage="f32")
+    lat.step(64)
+    rho, ux, uy = case.init_fields()
+    B.lbm_init_equilibrium(lat.ctx, rho, ux, uy)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    lat.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1)
+    # adjoint call (one short call first loads its kernels)
+    B.lbm_init_equilibrium(lat.ctx, rho, ux, uy)
+    lat.adjoint_force(2 * ckpt, ckpt)
+    B.lbm_init_equilibrium(lat.ctx, rho, ux, uy)
+    B.lbm_force_reset(lat.ctx)
+    torch.cuda.synchronize()
+    e0.record()
+    lat.adjoint_force(steps, ckpt)
+    e1.record()
+    torch.cuda.synchronize()
+    adj_ms = e0.elapsed_time(e1)
+    ws = B.lbm_adjoint_workspace_bytes(lat.ctx, steps, ckpt)
+    lat.close()
+    J32, g32 = drag_and_gradient(base, p0, steps, ckpt, "f32")
+    J64, g64 = drag_and_gradient(base, p0, steps, ckpt, "f64")
+    err = np.abs(g32 - g64) / np.abs(g64)
+    return {"workload": f"adjoint_cylinder_{case.nx}x{case.ny}_R{case.prims[0].r}_Re100",
+            "steps": steps, "ckpt_every": ckpt, "forward_ms": round(fwd_ms, 2),
+            "adjoint_ms": round(adj_ms, 2), "adjoint_over_forward": round(adj_ms / fwd_ms, 2),
+            "algorithmic_ratio": 3.5, "workspace_mb": round(ws / 2 ** 20, 1),
+            "J_f32": J32, "J_f64": J64, "grad_f32": [float(v) for v in g32],
+            "grad_f64": [float(v) for v in g64],
+            "grad_rel_err_f32_vs_f64": [float(v) for v in err],
+            "params": "(U, cx, cy, R); tau fixed"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,7 +264,9 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 1 GiB device copy (counter calibration under rocprofv3)")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the FP16/BF16 storage, batched and cylinder measurements")
+                    help="skip the FP16/BF16 storage, batched, cylinder and adjoint measurements")
+    ap.add_argument("--form", choices=["storage_16bit", "batched", "cylinder", "adjoint"],
+                    help="run only this form and print its JSON object")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part "
@@ -229,6 +281,19 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+    if args.form:
+        from paper_1903_01111_amd import workloads as W
+        B.lib()
+        if args.form == "storage_16bit":
+            res = form_precision(B, workload(args.workload), 1000, 500)
+        elif args.form == "batched":
+            res = form_batched(B, 256, 300, 20)
+        elif args.form == "cylinder":
+            res = form_single(B, W.cylinder_channel(), 2000, 100)
+        else:
+            res = form_adjoint(B)
+        print(json.dumps({"form": args.form, **res}), flush=True)
+        return
     t_setup = time.perf_counter()
     case = workload(args.workload)
     lat = B.Lattice(case, storage=args.storage)
@@ -350,6 +415,7 @@ def main():
         forms["cylinder_2048x512_f32"] = form_single(B, W.cylinder_channel(), 2000, 100)
         forms["cylinder_2048x512_f32"]["note"] = ("75 MB working set: resident in the 256 MB "
                                                   "last-level cache, not an HBM figure")
+        forms["adjoint"] = form_adjoint(B)
         out["forms"] = forms
     print(json.dumps(out), flush=True)
 

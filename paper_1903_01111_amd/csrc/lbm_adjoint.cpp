@@ -23,8 +23,8 @@ struct AdjLayout {
     int64_t n_tape;   // recomputed states of a segment besides its checkpoint
     int64_t dplane;   // doubles per plane of the gradient fields
     size_t mbytes;    // bytes of one copy of the side moments
-    size_t off_ck, off_ckM, off_tape, off_C0, off_C1, off_Lf, off_Lb, off_sig, off_dq, off_duw, off_duin,
-        off_colslot, off_bank, off_dstate, off_dinit, total;
+    size_t off_ck, off_ckM, off_tape, off_C0, off_C1, off_lrec, off_sig, off_dq, off_duw, off_duin,
+        off_colslot, off_dstate, off_dinit, total;
 };
 
 bool adj_layout(const lbm_ctx *c, int64_t nsteps, int32_t k, AdjLayout *L)
@@ -50,14 +50,12 @@ bool adj_layout(const lbm_ctx *c, int64_t nsteps, int32_t k, AdjLayout *L)
     L->off_tape = take((size_t)L->n_tape * L->state);
     L->off_C0 = take(L->state);
     L->off_C1 = take(L->state);
-    L->off_Lf = take(nl * eb);
-    L->off_Lb = take(nl * eb);
-    L->off_sig = take(K * SIG * sizeof(double));
+    L->off_lrec = take(nl * lbm::adj_link_record_bytes(c->p.storage));
+    L->off_sig = take(2 * K * SIG * sizeof(double));  // steps of even / odd parity
     L->off_dq = take(nl * sizeof(double));
     L->off_duw = take(2 * nl * sizeof(double));
     L->off_duin = take(2 * (size_t)c->p.ny * sizeof(double));
     L->off_colslot = take(2 * (size_t)c->p.ny * sizeof(int32_t));
-    L->off_bank = take((size_t)c->p.n_obj * 6 * sizeof(double));
     L->off_dstate = take(9 * (size_t)L->dplane * sizeof(double));
     L->off_dinit = take(3 * (size_t)L->dplane * sizeof(double));
     L->total = o;
@@ -106,11 +104,12 @@ lbm_status lbm_adjoint_force(lbm_ctx *c, void *wsv, size_t ws_bytes, int64_t nst
     const size_t mb = (size_t)c->n_moment_nodes * 3 * real_bytes(storage);
     auto tape = [&](int64_t j) -> void * { return ws + L.off_tape + (size_t)j * L.state; };
     auto state = [&](int64_t t) -> void * { return t % k == 0 ? ck(t / k) : tape(t % k - 1); };
+    const int64_t K = std::max<int64_t>(c->n_moment_nodes, 1);
     double *sig = reinterpret_cast<double *>(ws + L.off_sig);
+    double *sigp[2] = {sig, sig + K * SIG};  // side records of steps of even / odd parity
     double *dq = reinterpret_cast<double *>(ws + L.off_dq);
     double *duw = reinterpret_cast<double *>(ws + L.off_duw);
     double *duin = reinterpret_cast<double *>(ws + L.off_duin);
-    double *bank = reinterpret_cast<double *>(ws + L.off_bank);
     int32_t *colslot = reinterpret_cast<int32_t *>(ws + L.off_colslot);
     void *Cb[2] = {ws + L.off_C0, ws + L.off_C1};
 
@@ -126,7 +125,18 @@ lbm_status lbm_adjoint_force(lbm_ctx *c, void *wsv, size_t ws_bytes, int64_t nst
         if (mb && (s = c->hip(hipMemcpyAsync(ckM(j), c->side().M, mb, hipMemcpyDeviceToDevice, st),
                               "checkpoint copy")))
             return s;
-        if ((s = lbm_step(c, std::min<int64_t>(k, nsteps - j * k)))) return s;
+        if (j + 1 < L.n_ck) {
+            if ((s = lbm_step(c, k))) return s;
+            continue;
+        }
+        // the last segment is written straight into the tape: the reverse sweep
+        // starts on it without recomputing it
+        for (int64_t t = j * k; t < nsteps; ++t) {
+            const void *A = t == j * k ? c->cur : state(t);
+            void *Bn = t + 1 < nsteps ? state(t + 1) : c->nxt;
+            if ((s = enqueue_step_to(c, A, Bn, false))) return s;
+        }
+        std::swap(c->cur, c->nxt);
     }
     if (mb && (s = c->hip(hipMemcpyAsync(ckM(L.n_ck), c->side().M, mb, hipMemcpyDeviceToDevice, st),
                           "checkpoint copy")))
@@ -138,10 +148,9 @@ lbm_status lbm_adjoint_force(lbm_ctx *c, void *wsv, size_t ws_bytes, int64_t nst
     struct Z {
         void *p;
         size_t n;
-    } zs[] = {{Cb[0], L.state}, {Cb[1], L.state}, {ws + L.off_Lb, nl * elem_bytes(storage)},
-              {sig, (size_t)c->n_moment_nodes * SIG * sizeof(double)}, {dq, nl * sizeof(double)},
-              {duw, 2 * nl * sizeof(double)}, {duin, 2 * (size_t)c->p.ny * sizeof(double)},
-              {bank, (size_t)c->p.n_obj * 6 * sizeof(double)}};
+    } zs[] = {{Cb[0], L.state}, {Cb[1], L.state}, {sig, 2 * (size_t)K * SIG * sizeof(double)},
+              {dq, nl * sizeof(double)},
+              {duw, 2 * nl * sizeof(double)}, {duin, 2 * (size_t)c->p.ny * sizeof(double)}};
     for (const Z &z : zs)
         if (z.n && (s = c->hip(hipMemsetAsync(z.p, 0, z.n, st), "adjoint clear"))) return s;
     if (!c->colslot.empty() &&
@@ -152,10 +161,12 @@ lbm_status lbm_adjoint_force(lbm_ctx *c, void *wsv, size_t ws_bytes, int64_t nst
     const lbm::Side side = c->side();
     const int32_t *mnode = side.mnode;
     const lbm::SegBase *seg = side.seg;
+    if ((s = c->hip(lbm::launch_adj_setup(storage, links, mnode, ws + L.off_lrec, st), "adjoint setup")))
+        return s;
     const double djx = dir_x / (double)nsteps, djy = dir_y / (double)nsteps;
     for (int64_t sgm = L.n_ck - 1; sgm >= 0; --sgm) {
         const int64_t t0 = sgm * k, t1 = std::min<int64_t>(t0 + k, nsteps);
-        if (t1 - t0 > 1) {
+        if (t1 - t0 > 1 && sgm + 1 < L.n_ck) {
             // recompute the segment's states from its checkpoint: same kernels, launch
             // shapes and side data as the forward sweep, so bitwise the same states
             if (mb && (s = c->hip(hipMemcpyAsync(side.M, ckM(sgm), mb, hipMemcpyDeviceToDevice, st),
@@ -164,33 +175,26 @@ lbm_status lbm_adjoint_force(lbm_ctx *c, void *wsv, size_t ws_bytes, int64_t nst
             if ((s = c->hip(lbm::launch_refresh(storage, g, ph, ck(sgm), side, false, st), "refresh")))
                 return s;
             for (int64_t t = t0; t + 1 < t1; ++t) {
-                if ((s = c->hip(lbm::launch_link(storage, g, ph, links, side, c->reduce(), bank, bank + 4 * c->p.n_obj,
+                // no force: only the states are wanted
+                if ((s = c->hip(lbm::launch_link(storage, g, ph, links, side, c->reduce(), nullptr, nullptr,
                                                  c->kcfg.link_block, st), "link kernel")))
                     return s;
                 if ((s = c->hip(lbm::launch_bulk(storage, g, ph, state(t), state(t + 1), c->mask(),
-                                                 c->ws + c->lay.off_uin, side, bank + 2 * c->p.n_obj,
-                                                 2 * c->p.n_obj, c->bulk_config(), st), "bulk kernel")))
+                                                 c->ws + c->lay.off_uin, side, nullptr, 0, c->bulk_config(),
+                                                 st), "bulk kernel")))
                     return s;
             }
         }
-        for (int64_t t = t1 - 1; t >= t0; --t) {
-            if ((s = c->hip(lbm::launch_adj_link(storage, g, ph, links, mnode, t + 1 < nsteps ? state(t + 1) : nullptr,
-                                                 state(t), ws + L.off_Lf, ws + L.off_Lb, sig, dq, duw, obj, djx,
-                                                 djy, st), "adjoint link kernel")))
+        for (int64_t t = t1 - 1; t >= t0; --t)
+            if ((s = c->hip(lbm::launch_adj_step(storage, g, ph, state(t), Cb[(t + 1) & 1], Cb[t & 1],
+                                                 sigp[(t + 1) & 1], sigp[t & 1], ws + L.off_lrec, c->mask(), seg,
+                                                 c->colslot.empty() ? nullptr : colslot, c->ws + c->lay.off_uin,
+                                                 duin, dq, duw, obj, djx, djy, st), "adjoint step kernel")))
                 return s;
-            if ((s = c->hip(lbm::launch_adj_bulk(storage, g, ph, state(t), ws + L.off_Lf, Cb[(t + 1) & 1], Cb[t & 1],
-                                                 ws + L.off_Lb, sig, c->mask(), seg,
-                                                 c->colslot.empty() ? nullptr : colslot,
-                                                 c->ws + c->lay.off_uin, duin, st), "adjoint bulk kernel")))
-                return s;
-        }
     }
-    if ((s = c->hip(lbm::launch_adj_link(storage, g, ph, links, mnode, state(0), nullptr, ws + L.off_Lf,
-                                         ws + L.off_Lb, sig, dq, duw, obj, djx, djy, st), "adjoint link kernel")))
-        return s;
     double *dstate = reinterpret_cast<double *>(ws + L.off_dstate);
     double *dinit = reinterpret_cast<double *>(ws + L.off_dinit);
-    if ((s = c->hip(lbm::launch_adj_final(storage, g, ph, state(0), Cb[0], sig, c->mask(), seg, dstate, dinit,
+    if ((s = c->hip(lbm::launch_adj_final(storage, g, ph, state(0), Cb[0], sigp[0], c->mask(), seg, dstate, dinit,
                                           L.dplane, st), "adjoint final kernel")))
         return s;
     // the recomputation overwrote the context's deposits: restore them for its

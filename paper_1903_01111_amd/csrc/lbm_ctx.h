@@ -123,4 +123,7 @@ namespace lbm_host {
 // One forward step on the context's own buffers (link + bulk launches); with
 // timed, HIP events bracket both launches for lbm_kernel_times.
 lbm_status enqueue_step(lbm_ctx *c, bool timed);
+// The same step from state A into B (any buffers of the context's layout); the
+// context's own buffers are left as they are.
+lbm_status enqueue_step_to(lbm_ctx *c, const void *A, void *B, bool timed);
 }  // namespace lbm_host

@@ -84,6 +84,8 @@ struct BulkConfig {
     int32_t store_solid;  // lanes of solid nodes store zeros too (full-line writes)
 };
 
+// Link values of one step into side.L and, unless force_bank is null, the force
+// of every object added to force_bank and force_sum.
 hipError_t launch_link(int storage, const Grid &g, const Phys &ph, const Links &L, const Side &side,
                        const Reduce &red, double *force_bank, double *force_sum, int block,
                        hipStream_t s);
@@ -139,24 +141,23 @@ int32_t mass_blocks(const Grid &g);
 // hold 12 doubles per flagged node.
 // ---------------------------------------------------------------------------
 
-// One lane per link.  With Sn (state of step t+1): back-propagates the adjoint
-// Lbar of every link value of step t+1 (plus the force weight (djx, djy) for
-// links of object obj) into the side records of x_f and x_ff and into the FP64
-// accumulators dq[l] and duw[2l..2l+1]; with Sc (state of step t): writes the
-// link values of step t into Lf.  Either state may be null.
-hipError_t launch_adj_link(int storage, const Grid &g, const Phys &ph, const Links &L, const int32_t *mnode,
-                           const void *Sn, const void *Sc, void *Lf, const void *Lbar, double *sig, double *dq,
-                           double *duw, int32_t obj, double djx, double djy, hipStream_t s);
+// Bytes of one per-link record of the adjoint.
+size_t adj_link_record_bytes(int storage);
 
-// One lane per node: from the adjoint Cin of the pre-collision populations of
-// step t+1 and the side records (consumed and cleared), the adjoint Cout of the
-// pre-collision populations of step t (state S of step t, link values Lf) and
-// its link entries Lbar; inlet rows add to duin (2 doubles per row).  colslot:
-// side slots of the inlet and outlet column nodes (open lattices).
-hipError_t launch_adj_bulk(int storage, const Grid &g, const Phys &ph, const void *S, const void *Lf,
-                           const void *Cin, void *Cout, void *Lbar, double *sig, const mask_t *mask,
-                           const SegBase *seg, const int32_t *colslot, const void *uin, double *duin,
-                           hipStream_t s);
+// Per-link records of the adjoint, in (node, dir) order, from the link arrays.
+hipError_t launch_adj_setup(int storage, const Links &L, const int32_t *mnode, void *lrec, hipStream_t s);
+
+// One reverse step t, one lane per node: from the adjoint Cin of the
+// pre-collision populations of step t+1 and the side records sig_in of step t+1
+// (consumed and cleared), the adjoint Cout of the pre-collision populations of
+// step t (state S of step t), the side records sig_out of step t (added to) and
+// the FP64 accumulators dq, duw (per link) and duin (per inlet row).  The force
+// weight (djx, djy) applies to the links of object obj.  colslot: side slots of
+// the inlet and outlet column nodes (open lattices).
+hipError_t launch_adj_step(int storage, const Grid &g, const Phys &ph, const void *S, const void *Cin, void *Cout,
+                           double *sig_in, double *sig_out, const void *lrec, const mask_t *mask,
+                           const SegBase *seg, const int32_t *colslot, const void *uin, double *duin, double *dq,
+                           double *duw, int32_t obj, double djx, double djy, hipStream_t s);
 
 // dJ/dS_0 (nine planes of dplane doubles) and dJ/d(rho, ux, uy) of an
 // equilibrium initial state (three planes) from Cin and the side records of

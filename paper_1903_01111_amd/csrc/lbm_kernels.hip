@@ -99,6 +99,7 @@ __global__ __launch_bounds__(1024) void link_kernel(Grid g, Phys ph, Links L, Si
         fx = cxp * m;
         fy = cyp * m;
     }
+    if (!bank) return;  // link values only: no force wanted (uniform over the grid)
     // FP64 wavefront reduction.  Links are sorted by object, so a wavefront
     // usually holds one object: it leaves one partial sum for force_reduce_kernel
     // (no atomics: thousands of wavefronts adding into the same address would
@@ -629,7 +630,7 @@ hipError_t link_t(const Grid &g, const Phys &ph, const Links &L, const Side &sid
     hipLaunchKernelGGL(link_kernel<ST>, dim3(blocks), dim3(block), 0, s, g, ph, L, side, red.wpart,
                        red.wobj, bank, fsum);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || !bank) return e;
     const int64_t nw = (int64_t)blocks * (block / 64);
     const int64_t lanes = (nw + REDUCE_CHUNK - 1) / REDUCE_CHUNK;
     hipLaunchKernelGGL(force_reduce_kernel, dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, s,

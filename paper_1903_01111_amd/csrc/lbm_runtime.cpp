@@ -360,6 +360,14 @@ extern "C" void lbm_set_thread_error(const char *msg) { g_thread_error = msg; }
 
 lbm_status lbm_host::enqueue_step(lbm_ctx *c, bool timed)
 {
+    lbm_status s = enqueue_step_to(c, c->cur, c->nxt, timed);
+    if (s) return s;
+    std::swap(c->cur, c->nxt);
+    return LBM_OK;
+}
+
+lbm_status lbm_host::enqueue_step_to(lbm_ctx *c, const void *A, void *B, bool timed)
+{
     const lbm::Grid g = c->grid();
     const lbm::Phys ph = c->phys();
     hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
@@ -380,12 +388,11 @@ lbm_status lbm_host::enqueue_step(lbm_ctx *c, bool timed)
                           "link kernel launch");
     if (s) return s;
     if (timed) hipEventRecord(e1, c->stream);
-    s = c->hip(lbm::launch_bulk(c->p.storage, g, ph, c->cur, c->nxt, c->mask(),
+    s = c->hip(lbm::launch_bulk(c->p.storage, g, ph, A, B, c->mask(),
                                 c->ws + c->lay.off_uin, c->side(), c->bank(c->step + 1),
                                 2 * c->p.n_obj, c->bulk_config(), c->stream), "bulk kernel launch");
     if (s) return s;
     if (timed) hipEventRecord(e2, c->stream);
-    std::swap(c->cur, c->nxt);
     ++c->step;
     ++c->nsum;
     return LBM_OK;

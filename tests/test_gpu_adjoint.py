@@ -241,3 +241,41 @@ def test_adjoint_errors(B):
         assert e.value.status == B.LBM_E_ARG
     assert B.lbm_step_count(lat.ctx) == 0
     lat.close()
+
+
+def test_full_size_drag_gradient(B):
+    """The drag-gradient workload at full size: cylinder 1024x256, R = 12.4,
+    Re = 100, 2000 steps, checkpoints every 100 steps.  FP64 adjoint against FP64
+    central differences of the GPU forward, and FP32 against FP64 within 1e-3
+    relative per component."""
+    from paper_1903_01111_amd.autograd import drag_and_gradient, with_parameters
+    base = W.adjoint_cylinder()
+    n = 2000
+    p0 = np.array([0.05, base.prims[0].cx, base.prims[0].cy, base.prims[0].r])
+    print(f"[adjoint] full size {base.nx}x{base.ny} n={n} f64", flush=True)
+    J64, g64 = drag_and_gradient(base, p0, n, 100, "f64")
+    ref_mask = B.case_geometry(with_parameters(base, *p0))[0]
+
+    def fwd(pp):
+        c = with_parameters(base, *pp)
+        lat = B.Lattice(c, storage="f64")
+        assert np.array_equal(lat.mask, ref_mask)
+        lat.step(n)
+        _, s, _ = lat.force(0)
+        lat.close()
+        return s[0] / n
+
+    hs = [1e-7, 1e-6, 1e-6, 1e-6]
+    for k in range(4):
+        e = np.zeros(4)
+        e[k] = hs[k]
+        fd = (fwd(p0 + e) - fwd(p0 - e)) / (2 * hs[k])
+        print(f"[adjoint] full size dJ/dp[{k}]: adjoint {g64[k]:.10e} central difference {fd:.10e}",
+              flush=True)
+        assert abs(g64[k] - fd) <= 1e-6 * abs(fd) + 1e-12 * abs(J64) / hs[k]
+    print(f"[adjoint] full size f32", flush=True)
+    J32, g32 = drag_and_gradient(base, p0, n, 100, "f32")
+    err = np.abs(g32 - g64) / np.abs(g64)
+    print(f"[adjoint] full size fp32 vs fp64: J {abs(J32 - J64) / abs(J64):.2e}, gradient {err}", flush=True)
+    assert abs(J32 - J64) <= 1e-4 * abs(J64)
+    assert err.max() <= 1e-3
