@@ -245,7 +245,10 @@ def form_adjoint(B, steps=2000, ckpt=100):
     return {"workload": f"adjoint_cylinder_{case.nx}x{case.ny}_R{case.prims[0].r}_Re100",
             "steps": steps, "ckpt_every": ckpt, "forward_ms": round(fwd_ms, 2),
             "adjoint_ms": round(adj_ms, 2), "adjoint_over_forward": round(adj_ms / fwd_ms, 2),
-            "algorithmic_ratio": 3.5, "workspace_mb": round(ws / 2 ** 20, 1),
+            # bytes per fluid node and step against the forward's 18 values: forward sweep
+            # 18, recompute 18 (1 - k/n) (the last segment is taped by the sweep), reverse 27
+            "algorithmic_ratio": round((18 + 18 * (1 - ckpt / steps) + 27) / 18, 2),
+            "workspace_mb": round(ws / 2 ** 20, 1),
             "J_f32": J32, "J_f64": J64, "grad_f32": [float(v) for v in g32],
             "grad_f64": [float(v) for v in g64],
             "grad_rel_err_f32_vs_f64": [float(v) for v in err],
