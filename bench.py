@@ -262,6 +262,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="porous", choices=["porous", "cylinder", "dense"])
     ap.add_argument("--storage", default="f32", choices=list(BYTES))
+    ap.add_argument("--layout", default="dense", choices=["dense", "compact"],
+                    help="population layout: every node, or the fluid nodes only")
     ap.add_argument("--cpu-steps", type=int, default=4,
                     help="oracle steps on the full lattice for the CPU baseline (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -299,7 +301,7 @@ def main():
         return
     t_setup = time.perf_counter()
     case = workload(args.workload)
-    lat = B.Lattice(case, storage=args.storage)
+    lat = B.Lattice(case, storage=args.storage, layout=args.layout)
     n_nodes = case.nx * case.ny
     n_fluid = int((lat.mask == 0).sum())
     nfb = B.lbm_check_geometry(lat.params, lat.mask, lat.node, lat.dir, lat.q, lat.uw, lat.obj,
@@ -369,7 +371,7 @@ def main():
                    "body_force": case.gx, "n_discs": len(case.prims), "fluid_nodes": n_fluid,
                    "links": lat.n_links, "hbb_fallback_links": nfb,
                    "boundary": "VIBB (velocity-interpolation bounce-back)",
-                   "collision": "BGK + Guo forcing", "storage": args.storage,
+                   "collision": "BGK + Guo forcing", "storage": args.storage, "layout": args.layout,
                    "kernel_config": cfg.as_dict()},
         "mflups_fluid": round(n_fluid * args.steps / (ms * 1e-3) / 1e6, 1),
         "step_algorithmic_GBps": round((bulk_bytes + link_bytes) / (ms * 1e-3 / args.steps) / 1e9, 1),

@@ -62,6 +62,10 @@ typedef int32_t lbm_status;
 #define LBM_F16_DEV 2
 #define LBM_BF16_DEV 3
 
+/* population layout in device memory */
+#define LBM_LAYOUT_DENSE 0   /* every node of the padded lattice, node (x, y) at y*pitch + x */
+#define LBM_LAYOUT_COMPACT 1 /* fluid nodes only, numbered in (y, x) order */
+
 #define LBM_X_PERIODIC 0
 #define LBM_X_OPEN 1 /* inlet at x = 0, outlet at x = nx-1 */
 
@@ -84,7 +88,7 @@ typedef struct {
     int32_t n_obj;          /* number of force accumulators, >= 1 */
     int32_t dev_scale_log2; /* 16-bit storage scale exponent k, |k| <= 30 */
     int32_t device;         /* HIP device ordinal */
-    int32_t reserved;       /* must be 0 */
+    int32_t layout;         /* LBM_LAYOUT_DENSE or LBM_LAYOUT_COMPACT (single lattices) */
     void *stream;           /* hipStream_t the work is enqueued on; NULL = null stream */
 } lbm_params;
 
@@ -211,7 +215,8 @@ lbm_status lbm_max_deviation(lbm_ctx *ctx, double *max_dev);
 size_t lbm_state_bytes(const lbm_ctx *ctx);
 /* Checkpoint format: int64 step, int64 steps in the force sum; then plane i = 0..8
  * of plane_elems elements of elem bytes each (storage format: (f_i - w_i)
- * [* 2^k], node (x, y) at y*pitch + x); then 6*n_obj doubles of force
+ * [* 2^k]; dense layout: node (x, y) at y*pitch + x; compact layout: the k-th
+ * fluid node in (y, x) order at k); then 6*n_obj doubles of force
  * accumulators; then the stored moments of the boundary-adjacent nodes. */
 lbm_status lbm_state_layout(const lbm_ctx *ctx, int32_t *pitch, int64_t *plane_elems, int32_t *elem);
 lbm_status lbm_get_state(lbm_ctx *ctx, void *host, size_t bytes);
@@ -231,13 +236,16 @@ typedef struct {
     int32_t bulk_store_solid; /* 1: lanes of solid nodes store too, so rows are written in full lines */
     int32_t link_block;       /* link kernel lanes per block: 64..1024, a multiple of 64 */
     int32_t graph_steps;      /* steps per captured HIP graph: even, 2..1024 */
+    int32_t bulk_xcd;         /* 1: each XCD takes a contiguous run of the bulk blocks (workgroups
+                                 go to the 8 XCDs round robin), so neighbouring rows and shared
+                                 cache lines stay in one L2; 0: hardware order */
 } lbm_kernel_config;
 
 lbm_status lbm_get_kernel_config(const lbm_ctx *ctx, lbm_kernel_config *cfg);
 /* Errors: LBM_E_ARG for an unsupported configuration (the previous one stays). */
 lbm_status lbm_set_kernel_config(lbm_ctx *ctx, const lbm_kernel_config *cfg);
 
-/* Autotuner: times every bulk shape and link block size for steps_per_trial steps
+/* Autotuner: times every bulk shape (block, solid stores, XCD order) and link block size for steps_per_trial steps
  * on the current state, keeps the fastest, and restores the state (populations,
  * step counter, forces), so results do not depend on having tuned.  Needs host
  * memory for one checkpoint.  chosen and best_ms_per_step may be NULL. */
@@ -249,8 +257,8 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t steps_per_trial, lbm_kernel_config
  * obstacle offsets or Reynolds numbers) advanced together.  Each step is one
  * link launch over the links of all instances and one bulk launch over a tile
  * table of all instances (HIP graph replay).  Instances share storage, x_bc,
- * rho0, dev_scale_log2, device and stream; nx, ny, tau, body force, n_obj and
- * geometry are per instance.  The results of an instance equal those of a
+ * rho0, dev_scale_log2, device and stream, and use the dense layout; nx, ny,
+ * tau, body force, n_obj and geometry are per instance.  The results of an instance equal those of a
  * single-lattice context with the same arguments (bitwise for the populations).
  * ------------------------------------------------------------------------- */
 typedef struct lbm_batch lbm_batch;
@@ -302,7 +310,7 @@ lbm_status lbm_batch_force_reset(lbm_batch *b);
  * derivatives of the discrete map with the node classification held fixed; at
  * q = 1/2 the VIBB velocity branch of the forward (q <= 1/2) is differentiated.
  * Adjoint arithmetic is in the storage's precision; gradients with respect to the
- * parameters are accumulated in FP64.  FP64 and FP32 storage only.
+ * parameters are accumulated in FP64.  FP64 and FP32 storage, dense layout only.
  *
  * lbm_adjoint_workspace_bytes: device bytes the call needs for this context
  * (checkpoints, the recomputed segment, adjoint fields); 0 on invalid arguments.
@@ -321,7 +329,7 @@ lbm_status lbm_batch_force_reset(lbm_batch *b);
  *               initial state as f+ = f^eq(rho, u) of its own (rho, u) (the state
  *               lbm_init_equilibrium writes), node-major, zero at solid nodes.
  * Errors: LBM_E_ARG (nsteps < 1, ckpt_every < 1, obj out of range, 16-bit
- * storage, workspace null, misaligned or too small), LBM_E_STATE (no geometry or
+ * storage, compact layout, workspace null, misaligned or too small), LBM_E_STATE (no geometry or
  * initialisation), LBM_E_DEVICE, LBM_E_UNSTABLE (non-finite objective or
  * gradient). */
 size_t lbm_adjoint_workspace_bytes(const lbm_ctx *ctx, int64_t nsteps, int32_t ckpt_every);

@@ -22,6 +22,8 @@ LBM_OK, LBM_E_ARG, LBM_E_GEOM, LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_STATE, LBM_E_UNS
     0, -1, -2, -3, -4, -5, -6)
 LBM_F64, LBM_F32, LBM_F16_DEV, LBM_BF16_DEV = 0, 1, 2, 3
 LBM_X_PERIODIC, LBM_X_OPEN = 0, 1
+LBM_LAYOUT_DENSE, LBM_LAYOUT_COMPACT = 0, 1
+LAYOUT = {"dense": LBM_LAYOUT_DENSE, "compact": LBM_LAYOUT_COMPACT}
 STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16": LBM_F16_DEV, "bf16": LBM_BF16_DEV}
 STATUS_NAMES = {0: "LBM_OK", -1: "LBM_E_ARG", -2: "LBM_E_GEOM", -3: "LBM_E_NOMEM",
                 -4: "LBM_E_DEVICE", -5: "LBM_E_STATE", -6: "LBM_E_UNSTABLE"}
@@ -32,12 +34,12 @@ class lbm_params(C.Structure):
                 ("storage", C.c_int32), ("tau", C.c_double), ("gx", C.c_double),
                 ("gy", C.c_double), ("rho0", C.c_double), ("n_obj", C.c_int32),
                 ("dev_scale_log2", C.c_int32), ("device", C.c_int32),
-                ("reserved", C.c_int32), ("stream", C.c_void_p)]
+                ("layout", C.c_int32), ("stream", C.c_void_p)]
 
 
 class lbm_kernel_config(C.Structure):
     _fields_ = [("bulk_block_x", C.c_int32), ("bulk_store_solid", C.c_int32),
-                ("link_block", C.c_int32), ("graph_steps", C.c_int32)]
+                ("link_block", C.c_int32), ("graph_steps", C.c_int32), ("bulk_xcd", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -524,9 +526,10 @@ class Batch:
 # ---------------------------------------------------------------------------
 
 def make_params(nx, ny, *, x_open=False, storage="f32", tau=0.8, gx=0.0, gy=0.0, rho0=1.0,
-                n_obj=1, dev_scale_log2=0, device=0, stream=None) -> lbm_params:
+                n_obj=1, dev_scale_log2=0, device=0, stream=None, layout="dense") -> lbm_params:
     return lbm_params(nx, ny, LBM_X_OPEN if x_open else LBM_X_PERIODIC, STORAGE.get(storage, storage),
-                      tau, gx, gy, rho0, n_obj, dev_scale_log2, device, 0, stream)
+                      tau, gx, gy, rho0, n_obj, dev_scale_log2, device, LAYOUT.get(layout, layout),
+                      stream)
 
 
 def case_geometry(case: W.Case):
@@ -546,7 +549,7 @@ class Lattice:
     """One lattice on one GPU: workspace from torch, work on torch's current stream."""
 
     def __init__(self, case: W.Case, storage="f32", dev_scale_log2=0, device=0, geometry=None,
-                 max_links=None):
+                 max_links=None, layout="dense"):
         import torch
 
         if not torch.cuda.is_available():
@@ -556,7 +559,8 @@ class Lattice:
         stream = torch.cuda.current_stream(self.device).cuda_stream
         self.params = make_params(case.nx, case.ny, x_open=case.x_open, storage=storage, tau=case.tau,
                                   gx=case.gx, gy=case.gy, rho0=case.rho0, n_obj=case.n_obj,
-                                  dev_scale_log2=dev_scale_log2, device=device, stream=stream)
+                                  dev_scale_log2=dev_scale_log2, device=device, stream=stream,
+                                  layout=layout)
         geo = geometry if geometry is not None else case_geometry(case)
         self.mask, self.node, self.dir, self.q, self.uw, self.obj, self.scheme = geo
         nl = len(self.node) if max_links is None else max_links

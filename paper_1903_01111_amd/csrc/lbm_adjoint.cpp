@@ -69,7 +69,9 @@ extern "C" {
 size_t lbm_adjoint_workspace_bytes(const lbm_ctx *c, int64_t nsteps, int32_t ckpt_every)
 {
     AdjLayout L;
-    if (!c || !c->have_geom || (c->p.storage != LBM_F64 && c->p.storage != LBM_F32)) return 0;
+    if (!c || !c->have_geom || (c->p.storage != LBM_F64 && c->p.storage != LBM_F32) ||
+        c->p.layout != LBM_LAYOUT_DENSE)
+        return 0;
     if (!adj_layout(c, nsteps, ckpt_every, &L)) return 0;
     return L.total;
 }
@@ -83,6 +85,7 @@ lbm_status lbm_adjoint_force(lbm_ctx *c, void *wsv, size_t ws_bytes, int64_t nst
         return c->fail(LBM_E_STATE, "lbm_adjoint_force before lbm_set_geometry and initialisation");
     if (c->p.storage != LBM_F64 && c->p.storage != LBM_F32)
         return c->fail(LBM_E_ARG, "lbm_adjoint_force: FP64 or FP32 storage only");
+    if (c->p.layout != LBM_LAYOUT_DENSE) return c->fail(LBM_E_ARG, "lbm_adjoint_force: dense layout only");
     if (nsteps < 1 || k < 1) return c->fail(LBM_E_ARG, "lbm_adjoint_force: nsteps and ckpt_every must be >= 1");
     if (obj < 0 || obj >= c->p.n_obj) return c->fail(LBM_E_ARG, "lbm_adjoint_force: obj out of range");
     if (!std::isfinite(dir_x) || !std::isfinite(dir_y))

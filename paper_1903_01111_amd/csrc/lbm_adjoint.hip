@@ -260,12 +260,7 @@ __device__ __forceinline__ bool adj_lane(const Grid &g, const mask_t *__restrict
     const uint64_t flagged = __ballot((a.m & MASK_SIDE) != 0);
     a.slot = sb.flagged + (int32_t)__popcll(flagged & ((1ull << a.lane) - 1ull));
     const uint32_t lk = a.m & MASK_LINKS;
-    uint32_t linc = (uint32_t)__popc(lk);
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t t = __shfl_up(linc, off);
-        if (a.lane >= off) linc += t;
-    }
+    const uint32_t linc = wave_inclusive_scan((uint32_t)__popc(lk));
     a.lbase = sb.links + (int32_t)(linc - (uint32_t)__popc(lk));
     return true;
 }

@@ -99,7 +99,8 @@ struct lbm_batch {
     }
     lbm::Grid grid(int i) const
     {
-        return lbm::Grid{p[i].nx, p[i].ny, il[i].pitch, x_bc == LBM_X_OPEN ? 1 : 0, il[i].plane};
+        return lbm::Grid{p[i].nx, p[i].ny, il[i].pitch, x_bc == LBM_X_OPEN ? 1 : 0, il[i].plane, 0, 0, nullptr,
+                         nullptr};
     }
     size_t eb() const { return elem_bytes(storage); }
     size_t rb() const { return real_bytes(storage); }
@@ -219,6 +220,10 @@ bool batch_params_ok(int32_t n, const lbm_params *p, const int64_t *max_links, s
         }
         if (max_links[i] < 0) {
             *why = "instance " + std::to_string(i) + ": negative link capacity";
+            return false;
+        }
+        if (p[i].layout != LBM_LAYOUT_DENSE) {
+            *why = "instance " + std::to_string(i) + ": the batched form uses the dense layout";
             return false;
         }
         if (p[i].storage != p[0].storage || p[i].x_bc != p[0].x_bc || p[i].rho0 != p[0].rho0 ||

@@ -20,7 +20,7 @@ namespace lbm_host {
 struct Layout {
     int32_t pitch;
     int64_t plane;  // elements per population plane
-    size_t off_A, off_B, off_mask, off_seg, off_meta, off_q, off_uw, off_sf, off_sff, off_pf, off_pff,
+    size_t off_A, off_B, off_mask, off_seg, off_fmask, off_meta, off_q, off_uw, off_sf, off_sff, off_pf, off_pff,
         off_li, off_L, off_rec, off_mnode, off_pbase, off_M, off_P, off_wpart, off_wobj, off_uin,
         off_force, off_partials, off_stage, total;
     int64_t wave_cap;  // wavefront partials of the link kernel
@@ -48,7 +48,7 @@ struct lbm_ctx {
     std::vector<int32_t> colslot;
     void *cur = nullptr, *nxt = nullptr;
     int64_t step = 0, nsum = 0;
-    lbm_kernel_config kcfg{256, 0, 256, 16};
+    lbm_kernel_config kcfg{256, 0, 256, 16, 0};
     // graph of kcfg.graph_steps steps starting from buffer `graph_cur`
     hipGraphExec_t gexec = nullptr;
     void *graph_cur = nullptr;
@@ -61,7 +61,10 @@ struct lbm_ctx {
 
     lbm::Grid grid() const
     {
-        return lbm::Grid{p.nx, p.ny, lay.pitch, p.x_bc == LBM_X_OPEN ? 1 : 0, lay.plane};
+        return lbm::Grid{p.nx, p.ny, lay.pitch, p.x_bc == LBM_X_OPEN ? 1 : 0, lay.plane,
+                         p.layout == LBM_LAYOUT_COMPACT ? 1 : 0, 0,
+                         reinterpret_cast<const lbm::SegBase *>(ws + lay.off_seg),
+                         reinterpret_cast<const uint64_t *>(ws + lay.off_fmask)};
     }
     lbm::Phys phys() const
     {
@@ -80,7 +83,10 @@ struct lbm_ctx {
         return lbm::Reduce{reinterpret_cast<double2 *>(ws + lay.off_wpart),
                            reinterpret_cast<int32_t *>(ws + lay.off_wobj)};
     }
-    lbm::BulkConfig bulk_config() const { return lbm::BulkConfig{kcfg.bulk_block_x, kcfg.bulk_store_solid}; }
+    lbm::BulkConfig bulk_config() const
+    {
+        return lbm::BulkConfig{kcfg.bulk_block_x, kcfg.bulk_store_solid, kcfg.bulk_xcd};
+    }
     lbm::Side side() const
     {
         return lbm::Side{ws + lay.off_M, ws + lay.off_P, ws + lay.off_L,

@@ -111,5 +111,46 @@ __device__ __forceinline__ R deq(R w, R eu, R dr, R usq)
     return w * (dr + P + dr * P);
 }
 
+// 1/rho - 1 with the hardware reciprocal (about 1 ulp), for the bulk kernel's
+// velocity; the error is a relative 1e-7 of u (dr / (1 + dr) times 1 ulp).
+__device__ __forceinline__ float inv_rho_m1_fast(float dr) { return -dr * __builtin_amdgcn_rcpf(1.0f + dr); }
+__device__ __forceinline__ double inv_rho_m1_fast(double dr) { return -dr / (1.0 + dr); }
+
+// Element e of a population plane at base.  A plane is smaller than 4 GiB (the
+// runtime checks it), so the byte offset fits 32 bits and the access takes the
+// scalar-base + 32-bit vector-offset form.
+template <class T>
+__device__ __forceinline__ T ld_el(const T *__restrict__ base, int32_t e)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) +
+                                        (uint64_t)((uint32_t)e * (uint32_t)sizeof(T)));
+}
+template <class T>
+__device__ __forceinline__ void st_el(T *__restrict__ base, int32_t e, T v)
+{
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + (uint64_t)((uint32_t)e * (uint32_t)sizeof(T))) = v;
+}
+
+// Inclusive prefix sum over the 64 lanes of a wavefront with DPP row shifts and
+// row broadcasts (all lanes must be active).
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v)
+{
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return v;
+}
+
+// Offset of node (x, y) in a population plane (see Grid).
+__device__ __forceinline__ int32_t node_offset(const Grid &g, int x, int y)
+{
+    if (!g.compact) return y * g.pitch + x;
+    const int32_t s = y * (g.pitch >> 6) + (x >> 6);
+    return g.fseg[s].fluid + (int32_t)__popcll(g.fmask[s] & ((1ull << (x & 63)) - 1ull));
+}
+
 }  // namespace
 }  // namespace lbm

@@ -41,6 +41,7 @@ struct Prepared {
     std::vector<int32_t> mnode, pbase;
     std::vector<lbm::mask_t> mask;         // padded to the pitch: link bits, solid bit, side bit
     std::vector<lbm::SegBase> seg;         // per 64-node row segment
+    std::vector<uint64_t> fmask;           // per segment: its fluid nodes (bit = lane)
     int64_t n_pops = 0;
     bool has_uw = false;
     int64_t n_fallback = 0;

@@ -10,9 +10,18 @@ namespace lbm {
 // Device population layout: nine planes of `plane` elements, plane i holding
 // f_i - w_i of node (x, y) at offset y*pitch + x.  pitch >= nx is a multiple of
 // 64 elements, so a 64-lane wavefront reads one aligned run of a row.
+struct SegBase;
+
+// With compact set, plane i holds only the fluid nodes, the k-th fluid node in
+// (y, x) order at offset k: a node's offset is the fluid count before its
+// 64-node row segment (fseg[s].fluid) plus the fluid nodes below it in the
+// segment (popcount of the segment's fluid bitmask fmask[s]).
 struct Grid {
     int32_t nx, ny, pitch, x_open;
     int64_t plane;
+    int32_t compact, pad;
+    const SegBase *fseg;    // [ny * pitch / 64] (compact layout)
+    const uint64_t *fmask;  // [ny * pitch / 64] (compact layout)
 };
 
 struct Phys {
@@ -35,7 +44,7 @@ constexpr mask_t MASK_LINKS = 0xff, MASK_SOLID = 0x100, MASK_SIDE = 0x200;
 // Per 64-node row segment: flagged nodes, links and deposited populations that
 // come before it in plane order.
 struct SegBase {
-    int32_t flagged, links, pops, pad;
+    int32_t flagged, links, pops, fluid;
 };
 
 // Data exchanged between the bulk kernel and the link kernel through compact
@@ -82,6 +91,7 @@ struct Reduce {
 struct BulkConfig {
     int32_t block_x;      // 64, 128 or 256 lanes along x; 256/block_x rows
     int32_t store_solid;  // lanes of solid nodes store zeros too (full-line writes)
+    int32_t xcd;          // contiguous runs of blocks per XCD (see bulk_kernel)
 };
 
 // Link values of one step into side.L and, unless force_bank is null, the force

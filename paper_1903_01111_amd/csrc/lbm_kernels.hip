@@ -192,7 +192,7 @@ __device__ __forceinline__ int popc32(uint32_t v) { return __popc(v); }
 
 // One node per lane of the lattice described by (g, ph, A, B, mask, uin, side);
 // (x, y) is the lane's node, wv its wavefront within the block.
-template <int ST, bool OPEN, bool FORCE, int BX, bool STORE_SOLID>
+template <int ST, bool OPEN, bool FORCE, int BX, bool STORE_SOLID, bool CMP = false>
 __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
                                           const typename Codec<ST>::T *__restrict__ A,
                                           typename Codec<ST>::T *__restrict__ B,
@@ -225,19 +225,77 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
         xm = xc == 0 ? g.nx - 1 : xc - 1;
         xp = xc == g.nx - 1 ? 0 : xc + 1;
     }
-    const int32_t rm = (y == 0 ? g.ny - 1 : y - 1) * g.pitch;
-    const int32_t rp = (y == g.ny - 1 ? 0 : y + 1) * g.pitch;
-    T a[9];
-    a[0] = A[row + xc];
-    a[1] = A[1 * P + row + xm];
-    a[2] = A[2 * P + rm + xc];
-    a[3] = A[3 * P + row + xp];
-    a[4] = A[4 * P + rp + xc];
-    a[5] = A[5 * P + rm + xm];
-    a[6] = A[6 * P + rm + xp];
-    a[7] = A[7 * P + rp + xp];
-    a[8] = A[8 * P + rp + xm];
+    const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
+    const int32_t rm = ym * g.pitch;
+    const int32_t rp = yp * g.pitch;
     const int lane = threadIdx.x & 63;
+    // element offsets of the nine pull sources and of the node itself (own)
+    int32_t o[9], own, own_in = row, own_out = row + g.nx - 1;
+    if (CMP) {
+        // compact layout: the fluid rank of (x, r) for the rows r = y-1, y, y+1 is the
+        // fluid base of the wavefront's segment in that row plus the fluid lanes below
+        // this one (v_mbcnt over the segment's bitmask).  In plane order a fluid
+        // source at x-1 then has rank rk - 1 and one at x+1 rank rk + fluid(x); solid
+        // sources are discarded, their offsets only kept in bounds.
+        const int nsr = g.pitch >> 6;
+        const int sx = __builtin_amdgcn_readfirstlane(x >> 6);
+        const int yu = __builtin_amdgcn_readfirstlane(y);
+        const int rows3[3] = {yu == 0 ? g.ny - 1 : yu - 1, yu, yu == g.ny - 1 ? 0 : yu + 1};
+        const int32_t last = (int32_t)(P - 1);
+        int32_t rk[3], lf[3], rt[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const int32_t sg = rows3[r] * nsr + sx;
+            const uint64_t fm = g.fmask[sg];
+            rk[r] = (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(fm >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)fm, (uint32_t)g.fseg[sg].fluid));
+            lf[r] = rk[r] > 0 ? rk[r] - 1 : 0;
+            const int32_t q = rk[r] + (int32_t)((fm >> lane) & 1ull);
+            rt[r] = q < last ? q : last;
+        }
+        if (!OPEN) {
+            // periodic wrap in x: x = 0 pulls its e_x > 0 directions from x = nx-1 and
+            // x = nx-1 its e_x < 0 directions from x = 0
+            if (sx == 0 && lane == 0) {
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const int32_t sg = rows3[r] * nsr + nsr - 1;
+                    lf[r] = g.fseg[sg].fluid + (int32_t)__popcll(g.fmask[sg] & ((1ull << ((g.nx - 1) & 63)) - 1ull));
+                }
+            }
+            if (sx == nsr - 1 && lane == ((g.nx - 1) & 63)) {
+#pragma unroll
+                for (int r = 0; r < 3; ++r) rt[r] = g.fseg[rows3[r] * nsr].fluid;
+            }
+        } else {
+            own_in = lf[1];   // (0, y), written by the lane x = 1 (both fluid)
+            own_out = rt[1];  // (nx-1, y), written by the lane x = nx-2 (both fluid)
+        }
+        own = rk[1];
+        o[0] = rk[1];
+        o[1] = lf[1];
+        o[2] = rk[0];
+        o[3] = rt[1];
+        o[4] = rk[2];
+        o[5] = lf[0];
+        o[6] = rt[0];
+        o[7] = rt[2];
+        o[8] = lf[2];
+    } else {
+        own = row + x;
+        o[0] = row + xc;
+        o[1] = row + xm;
+        o[2] = rm + xc;
+        o[3] = row + xp;
+        o[4] = rp + xc;
+        o[5] = rm + xm;
+        o[6] = rm + xp;
+        o[7] = rp + xp;
+        o[8] = rp + xm;
+    }
+    T a[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) a[i] = ld_el(A + i * P, o[i]);
     const int32_t seg = __builtin_amdgcn_readfirstlane(y * (g.pitch >> 6) + (x >> 6));
     const SegBase sb = side.seg[seg];
     const uint64_t flagged = __ballot((m & MASK_SIDE) != 0);
@@ -245,12 +303,7 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
     const uint32_t rec = (m & MASK_SIDE) ? side.rec[slot] : 0u;
     // links of this node (mask bits): exclusive wavefront prefix -> first L entry
     const uint32_t lk = m & MASK_LINKS;
-    uint32_t linc = (uint32_t)popc32(lk);
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t t = __shfl_up(linc, off);
-        if (lane >= off) linc += t;
-    }
+    const uint32_t linc = wave_inclusive_scan((uint32_t)popc32(lk));
     const int32_t lbase = sb.links + (int32_t)(linc - (uint32_t)popc32(lk));
     // where x - e_i is solid, the link (x, i') with i' = opp(i) (bit i'-1 of the
     // mask word) supplies the population: its load is issued now, while the
@@ -266,12 +319,7 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
     }
     // deposited populations of this node (side record): exclusive prefix -> first P entry
     const uint32_t cnt = (uint32_t)popc32(rec >> 8) << 16;
-    uint32_t inc = cnt;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t t = __shfl_up(inc, off);
-        if (lane >= off) inc += t;
-    }
+    const uint32_t inc = wave_inclusive_scan(cnt);
     const uint32_t exc = inc - cnt;
     const int32_t pbase = sb.pops + (int32_t)(exc >> 16);
     const int wave_pops = (int)(__shfl(inc, 63) >> 16);
@@ -313,11 +361,11 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
     if (!inside) return;
     if (OPEN && (x == 0 || x == g.nx - 1)) return;
     if (m & MASK_SOLID) {
-        if (STORE_SOLID) {
+        if (STORE_SOLID && !CMP) {
             // solid slots of B are never read; storing them keeps every cache line
             // of B fully written (no partial-line writes at solid boundaries)
 #pragma unroll
-            for (int i = 0; i < 9; ++i) B[(int64_t)i * g.plane + row + x] = T(0);
+            for (int i = 0; i < 9; ++i) st_el(B + i * P, own, T(0));
         }
         return;
     }
@@ -330,7 +378,7 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
     const R drho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
     const R jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
     const R jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
-    const R ir = inv_rho_m1(drho);
+    const R ir = inv_rho_m1_fast(drho);
     R ux = jx + jx * ir, uy = jy + jy * ir;
     R Fx = R(0), Fy = R(0);
     if (FORCE) {
@@ -343,17 +391,45 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
     const R usq = ux * ux + uy * uy;
     const R om = R(ph.omega);
     const R cf = R(1) - R(0.5) * om;
+    // BGK + Guo, direction pairs (i, opp(i)) sharing e.u up to its sign:
+    //   f^eq - w = w (rho P + dr),  P = A +- B,  A = 9/2 (e.u)^2 - 3/2 u.u,  B = 3 e.u,
+    // so f^eq_{i,opp} - w = w (rho A + dr) +- w rho B, with rho A = A + dr A kept in
+    // deviation form; Guo's source (1 - omega/2) w [3 (e - u).F + 9 (e.u)(e.F)]
+    // splits the same way into (1 - omega/2) w (9 (e.u)(e.F) - 3 u.F) +- 3 (1 - omega/2) w e.F.
+    const R h15 = R(1.5) * usq;
+    const R uF = FORCE ? ux * Fx + uy * Fy : R(0);
+    {
+        // rest population: e.u = 0
+        const R w = wgt<R>(0);
+        R v = f[0] + om * (w * (drho - (h15 + drho * h15)) - f[0]);
+        if (FORCE) v -= R(3) * cf * w * uF;
+        f[0] = v;
+    }
+    constexpr int PLUS[4] = {1, 2, 5, 6}, MINUS[4] = {3, 4, 7, 8};
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
+    for (int k = 0; k < 4; ++k) {
+        const int i = PLUS[k], j = MINUS[k];
         const R w = wgt<R>(i);
         const R eu = R(CX[i]) * ux + R(CY[i]) * uy;
-        R v = f[i] - om * (f[i] - deq(w, eu, drho, usq));
-        if (FORCE)
-            v += cf * w * ((R(3) * (R(CX[i]) - ux) + R(9) * eu * R(CX[i])) * Fx +
-                           (R(3) * (R(CY[i]) - uy) + R(9) * eu * R(CY[i])) * Fy);
-        f[i] = v;
-        B[i * P + row + x] = C::st(v, ph.scale);
+        const R A2 = R(4.5) * eu * eu - h15;
+        const R B3 = R(3) * eu;
+        const R sa = w * ((A2 + drho * A2) + drho);
+        const R sb = w * (B3 + drho * B3);
+        R vi = f[i] + om * ((sa + sb) - f[i]);
+        R vj = f[j] + om * ((sa - sb) - f[j]);
+        if (FORCE) {
+            const R eF = R(CX[i]) * Fx + R(CY[i]) * Fy;
+            const R cw = cf * w;
+            const R s0 = cw * (R(9) * eu * eF - R(3) * uF);
+            const R s1 = R(3) * cw * eF;
+            vi += s0 + s1;
+            vj += s0 - s1;
+        }
+        f[i] = vi;
+        f[j] = vj;
     }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) st_el(B + i * P, own, C::st(f[i], ph.scale));
     // deposits for the next link kernel, staged in LDS so that the wavefront
     // writes its contiguous ranges of M and P in full lines.  The post-collision
     // moments are the collision's own (rho, u): with Guo's shift the physical
@@ -399,7 +475,7 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
                 const R eu = R(CX[i]) * ux + R(CY[i]) * uy;
                 const R dp = poly(ev, vsq) - poly(eu, usq);
                 f0[i] = f[i] + w * (dp + drho * dp);
-                B[i * P + row] = C::st(f0[i], ph.scale);
+                st_el(B + i * P, own_in, C::st(f0[i], ph.scale));
             }
             if (flagged & 1ull) {
                 const int32_t k = sb.flagged;
@@ -418,7 +494,7 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
         if (x == g.nx - 2 && !(me & MASK_SOLID)) {
             // zero-gradient outlet: copy every population of the last fluid column
 #pragma unroll
-            for (int i = 0; i < 9; ++i) B[i * P + row + g.nx - 1] = C::st(f[i], ph.scale);
+            for (int i = 0; i < 9; ++i) st_el(B + i * P, own_out, C::st(f[i], ph.scale));
             if (me & MASK_SIDE) {
                 Mv[3 * slot_out] = drho;
                 Mv[3 * slot_out + 1] = ux;
@@ -441,14 +517,14 @@ __device__ __forceinline__ void zero_bank_part(double *__restrict__ zb, int32_t 
     for (int64_t k = block * 256 + tid; k < nz; k += nblocks * 256) zb[k] = 0.0;
 }
 
-template <int ST, bool OPEN, bool FORCE, int BX, bool STORE_SOLID>
+template <int ST, bool OPEN, bool FORCE, int BX, bool STORE_SOLID, bool CMP>
 __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
                                                    const typename Codec<ST>::T *__restrict__ A,
                                                    typename Codec<ST>::T *__restrict__ B,
                                                    const mask_t *__restrict__ mask,
                                                    const typename Codec<ST>::R *__restrict__ uin,
                                                    Side side, double *__restrict__ zero_bank,
-                                                   int32_t n_zero)
+                                                   int32_t n_zero, int32_t xcd)
 {
     using R = typename Codec<ST>::R;
     using T = typename Codec<ST>::T;
@@ -457,10 +533,21 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
     __shared__ R lds_m[4][3 * 64];
     __shared__ T lds_p[4][8 * 64];
     const int tid = threadIdx.y * BX + threadIdx.x;
-    zero_bank_part(zero_bank, n_zero, (int64_t)blockIdx.y * gridDim.x + blockIdx.x,
-                   (int64_t)gridDim.x * gridDim.y, tid);
-    bulk_body<ST, OPEN, FORCE, BX, STORE_SOLID>(g, ph, A, B, mask, uin, side, blockIdx.x * BX + threadIdx.x,
-                                                blockIdx.y * BY + threadIdx.y, tid >> 6, lds_m, lds_p);
+    const int64_t nb = (int64_t)gridDim.x * gridDim.y;
+    const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    zero_bank_part(zero_bank, n_zero, b, nb, tid);
+    // Workgroups go to the 8 XCDs round robin (block b to XCD b mod 8).  With xcd,
+    // XCD k takes the k-th contiguous run of tiles in row-major order instead, so
+    // the rows a tile pulls from, and the cache lines it shares with the tiles
+    // beside it, were mostly touched by the same XCD and sit in its L2.
+    int64_t tile = b;
+    if (xcd) {
+        const int64_t q = nb >> 3, r = nb & 7, k = b & 7;
+        tile = k * q + (k < r ? k : r) + (b >> 3);
+    }
+    const int tx = (int)(tile % gridDim.x), ty = (int)(tile / gridDim.x);
+    bulk_body<ST, OPEN, FORCE, BX, STORE_SOLID, CMP>(g, ph, A, B, mask, uin, side, tx * BX + threadIdx.x,
+                                                     ty * BY + threadIdx.y, tid >> 6, lds_m, lds_p);
 }
 
 // Batched form: one launch over the tiles of many lattices.  Each block reads its
@@ -509,7 +596,8 @@ __global__ void refresh_kernel(Grid g, Phys ph, const typename Codec<ST>::T *__r
     using R = typename C::R;
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= side.K) return;
-    const int32_t n = side.mnode[k];
+    const int32_t nd = side.mnode[k];
+    const int32_t n = node_offset(g, nd % g.pitch, nd / g.pitch);
     const uint32_t rec = side.rec[k];
     T *Pv = static_cast<T *>(side.P);
     int32_t pb = side.pbase[k];
@@ -541,8 +629,9 @@ __global__ void init_kernel(Grid g, Phys ph, typename Codec<ST>::T *__restrict__
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= (int64_t)rows * g.nx) return;
     const int y = y0 + (int)(k / g.nx), x = (int)(k % g.nx);
-    const int32_t n = y * g.pitch + x;
-    const bool solid = (mask[n] & MASK_SOLID) != 0;
+    const bool solid = (mask[y * g.pitch + x] & MASK_SOLID) != 0;
+    if (solid && g.compact) return;  // no slot
+    const int32_t n = node_offset(g, x, y);
     const double rho = stage[3 * k], ux = stage[3 * k + 1], uy = stage[3 * k + 2];
     const double usq = ux * ux + uy * uy;
 #pragma unroll
@@ -562,11 +651,11 @@ __global__ void moments_kernel(Grid g, Phys ph, const typename Codec<ST>::T *__r
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= (int64_t)rows * g.nx) return;
     const int y = y0 + (int)(k / g.nx), x = (int)(k % g.nx);
-    const int32_t n = y * g.pitch + x;
-    if (mask[n] & MASK_SOLID) {
+    if (mask[y * g.pitch + x] & MASK_SOLID) {
         stage[3 * k] = stage[3 * k + 1] = stage[3 * k + 2] = 0.0;
         return;
     }
+    const int32_t n = node_offset(g, x, y);
     double dr = 0, jx = 0, jy = 0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -598,8 +687,8 @@ __global__ __launch_bounds__(MASS_THREADS) void mass_kernel(Grid g, Phys ph,
     for (int64_t k = (int64_t)blockIdx.x * MASS_THREADS + threadIdx.x; k < N;
          k += (int64_t)gridDim.x * MASS_THREADS) {
         const int y = (int)(k / g.nx), x = (int)(k % g.nx);
-        const int32_t n = y * g.pitch + x;
-        if (mask[n] & MASK_SOLID) continue;
+        if (mask[y * g.pitch + x] & MASK_SOLID) continue;
+        const int32_t n = node_offset(g, x, y);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             const double d = (double)C::ld(A[(int64_t)i * g.plane + n], ph.inv_scale);
@@ -638,16 +727,16 @@ hipError_t link_t(const Grid &g, const Phys &ph, const Links &L, const Side &sid
     return hipGetLastError();
 }
 
-template <int ST, bool OPEN, bool FORCE, int BX, bool SS>
+template <int ST, bool OPEN, bool FORCE, int BX, bool SS, bool CMP>
 hipError_t bulk_t(const Grid &g, const Phys &ph, const void *A, void *B, const mask_t *mask,
-                  const void *uin, const Side &side, double *zb, int32_t nz, hipStream_t s)
+                  const void *uin, const Side &side, double *zb, int32_t nz, int32_t xcd, hipStream_t s)
 {
     using C = Codec<ST>;
     constexpr int BY = 256 / BX;
     dim3 grid((g.nx + BX - 1) / BX, (g.ny + BY - 1) / BY);
-    hipLaunchKernelGGL((bulk_kernel<ST, OPEN, FORCE, BX, SS>), grid, dim3(BX, BY), 0, s, g, ph,
+    hipLaunchKernelGGL((bulk_kernel<ST, OPEN, FORCE, BX, SS, CMP>), grid, dim3(BX, BY), 0, s, g, ph,
                        static_cast<const typename C::T *>(A), static_cast<typename C::T *>(B), mask,
-                       static_cast<const typename C::R *>(uin), side, zb, nz);
+                       static_cast<const typename C::R *>(uin), side, zb, nz, xcd);
     return hipGetLastError();
 }
 
@@ -656,9 +745,16 @@ hipError_t bulk_shape(const Grid &g, const Phys &ph, const void *A, void *B, con
                       const void *uin, const Side &side, double *zb, int32_t nz, const BulkConfig &cf,
                       hipStream_t s)
 {
+    if (g.compact) {
+        // no solid slots to store in the compact layout
+        if (cf.block_x == 64) return bulk_t<ST, OPEN, FORCE, 64, false, true>(g, ph, A, B, mask, uin, side, zb, nz, cf.xcd, s);
+        if (cf.block_x == 128) return bulk_t<ST, OPEN, FORCE, 128, false, true>(g, ph, A, B, mask, uin, side, zb, nz, cf.xcd, s);
+        if (cf.block_x == 256) return bulk_t<ST, OPEN, FORCE, 256, false, true>(g, ph, A, B, mask, uin, side, zb, nz, cf.xcd, s);
+        return hipErrorInvalidValue;
+    }
 #define LBM_BULK_SHAPE(BXV, SSV)                                                                  \
     if (cf.block_x == BXV && cf.store_solid == SSV)                                              \
-        return bulk_t<ST, OPEN, FORCE, BXV, SSV>(g, ph, A, B, mask, uin, side, zb, nz, s);
+        return bulk_t<ST, OPEN, FORCE, BXV, SSV, false>(g, ph, A, B, mask, uin, side, zb, nz, cf.xcd, s);
     LBM_BULK_SHAPE(64, false)
     LBM_BULK_SHAPE(64, true)
     LBM_BULK_SHAPE(128, false)

@@ -59,6 +59,7 @@ Layout make_layout(const lbm_params &p, int64_t max_links)
     L.off_B = take(9 * pb);
     L.off_mask = take((size_t)L.pitch * p.ny * sizeof(lbm::mask_t));
     L.off_seg = take((size_t)(L.pitch / 64) * p.ny * sizeof(lbm::SegBase));
+    L.off_fmask = take((size_t)(L.pitch / 64) * p.ny * sizeof(uint64_t));
     const size_t nl = (size_t)std::max<int64_t>(max_links, 0);
     L.off_meta = take(nl * 4);
     L.off_q = take(nl * rb);
@@ -115,6 +116,10 @@ bool params_ok(const lbm_params *p, std::string *why)
         *why = "unknown storage";
         return false;
     }
+    if ((pitch * p->ny * (int64_t)elem_bytes(p->storage) + 512) >= ((int64_t)1 << 32)) {
+        *why = "a population plane must be smaller than 4 GiB (the kernels use 32-bit byte offsets)";
+        return false;
+    }
     if (!(p->tau > 0.5) || !std::isfinite(p->tau)) {
         std::snprintf(m, sizeof m, "tau must be finite and > 1/2 (got %g)", p->tau);
         *why = m;
@@ -132,8 +137,8 @@ bool params_ok(const lbm_params *p, std::string *why)
         *why = "dev_scale_log2 must be in [-30, 30]";
         return false;
     }
-    if (p->reserved != 0) {
-        *why = "reserved must be 0";
+    if (p->layout != LBM_LAYOUT_DENSE && p->layout != LBM_LAYOUT_COMPACT) {
+        *why = "layout must be LBM_LAYOUT_DENSE or LBM_LAYOUT_COMPACT";
         return false;
     }
     return true;
@@ -278,8 +283,13 @@ lbm_status prepare_geometry(const lbm_params &p, const uint8_t *mask, int64_t n,
     out->pbase.clear();
     std::vector<int32_t> slot(plane_n, -1);
     int32_t nlinks = 0, npops = 0;
+    out->fmask.assign((size_t)nseg, 0);
+    int32_t nfluid = 0;
     for (int64_t sg = 0; sg < nseg; ++sg) {
-        out->seg[sg] = lbm::SegBase{(int32_t)out->rec.size(), nlinks, npops, 0};
+        out->seg[sg] = lbm::SegBase{(int32_t)out->rec.size(), nlinks, npops, nfluid};
+        for (int b = 0; b < 64; ++b)
+            if (!(out->mask[sg * 64 + b] & lbm::MASK_SOLID)) out->fmask[sg] |= 1ull << b;
+        nfluid += __builtin_popcountll(out->fmask[sg]);
         for (int64_t o = sg * 64; o < sg * 64 + 64; ++o) {
             if (!bits[o]) continue;
             out->mask[o] |= (lbm::mask_t)(lbm::MASK_SIDE | (bits[o] & lbm::MASK_LINKS));
@@ -618,7 +628,8 @@ lbm_status lbm_set_geometry(lbm_ctx *c, const uint8_t *mask, int64_t n_links, co
                {c->lay.off_rec, prep.rec.data(), K * 2},
                {c->lay.off_mnode, prep.mnode.data(), K * 4},
                {c->lay.off_pbase, prep.pbase.data(), K * 4},
-               {c->lay.off_seg, prep.seg.data(), prep.seg.size() * sizeof(lbm::SegBase)}};
+               {c->lay.off_seg, prep.seg.data(), prep.seg.size() * sizeof(lbm::SegBase)},
+               {c->lay.off_fmask, prep.fmask.data(), prep.fmask.size() * sizeof(uint64_t)}};
     for (const Up &u : ups)
         if (u.bytes && (s = c->hip(hipMemcpyAsync(c->ws + u.off, u.src, u.bytes,
                                                   hipMemcpyHostToDevice, st), "link upload")))
@@ -817,13 +828,22 @@ lbm_status lbm_populations(lbm_ctx *c, double *f)
                     "mask read")))
         return s;
     if ((s = c->hip(hipStreamSynchronize(c->stream), "populations"))) return s;
+    // plane offset of every node: y*pitch + x, or its fluid rank in the compact layout
+    std::vector<int64_t> off((size_t)pitch * ny);
+    {
+        int64_t r = 0;
+        for (size_t k = 0; k < off.size(); ++k) {
+            off[k] = c->p.layout == LBM_LAYOUT_COMPACT ? r : (int64_t)k;
+            if (!(mask[k] & lbm::MASK_SOLID)) ++r;
+        }
+    }
     for (int i = 0; i < 9; ++i) {
         const char *src = static_cast<const char *>(c->cur) + (size_t)i * c->lay.plane * eb;
         if ((s = c->hip(hipMemcpy(plane.data(), src, plane.size(), hipMemcpyDeviceToHost), "plane read")))
             return s;
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
-                const size_t k = (size_t)y * pitch + x;
+                const size_t k = (size_t)off[(size_t)y * pitch + x];
                 double d;
                 switch (c->p.storage) {
                 case LBM_F64: std::memcpy(&d, &plane[k * 8], 8); break;
@@ -845,7 +865,8 @@ lbm_status lbm_populations(lbm_ctx *c, double *f)
                     d = bf16_to_double(v) * inv;
                 }
                 }
-                f[((size_t)y * nx + x) * 9 + i] = (mask[k] & lbm::MASK_SOLID) ? 0.0 : d + WR[i];
+                f[((size_t)y * nx + x) * 9 + i] =
+                    (mask[(size_t)y * pitch + x] & lbm::MASK_SOLID) ? 0.0 : d + WR[i];
             }
     }
     return LBM_OK;
@@ -1004,6 +1025,7 @@ lbm_status lbm_set_kernel_config(lbm_ctx *c, const lbm_kernel_config *cfg)
     if (!c || !cfg) return LBM_E_ARG;
     const int bx = cfg->bulk_block_x;
     if ((bx != 64 && bx != 128 && bx != 256) || (cfg->bulk_store_solid != 0 && cfg->bulk_store_solid != 1) ||
+        (cfg->bulk_xcd != 0 && cfg->bulk_xcd != 1) ||
         cfg->link_block < 64 || cfg->link_block > 1024 || cfg->link_block % 64 ||
         cfg->graph_steps < 2 || cfg->graph_steps > 1024 || cfg->graph_steps % 2)
         return c->fail(LBM_E_ARG, "lbm_set_kernel_config: unsupported configuration");
@@ -1047,14 +1069,17 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps_per_trial, lbm_kernel_config *
         return LBM_OK;
     };
     for (int bx : {64, 128, 256})
-        for (int ss : {0, 1}) {
-            lbm_kernel_config k = best;
-            k.bulk_block_x = bx;
-            k.bulk_store_solid = ss;
-            double ms;
-            if ((s = trial(k, &ms))) break;
-            if (ms < best_ms) best_ms = ms, best = k;
-        }
+        for (int ss : {0, 1})
+            for (int xo : {0, 1}) {
+                if (s || (ss && c->p.layout == LBM_LAYOUT_COMPACT)) continue;  // no solid slots there
+                lbm_kernel_config k = best;
+                k.bulk_block_x = bx;
+                k.bulk_store_solid = ss;
+                k.bulk_xcd = xo;
+                double ms;
+                if ((s = trial(k, &ms))) break;
+                if (ms < best_ms) best_ms = ms, best = k;
+            }
     for (int lb : {128, 256, 512, 1024}) {
         if (s) break;
         lbm_kernel_config k = best;

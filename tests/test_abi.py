@@ -50,7 +50,8 @@ def test_create_without_gpu_reports_device_error():
 
 
 @pytest.mark.parametrize("kw", [dict(tau=0.5), dict(tau=float("nan")), dict(x_open=True, nx=2),
-                                dict(nx=0), dict(storage=7), dict(n_obj=0), dict(dev_scale_log2=40)])
+                                dict(nx=0), dict(storage=7), dict(n_obj=0), dict(dev_scale_log2=40),
+                                dict(layout=2)])
 def test_invalid_params_have_no_workspace(kw):
     nx = kw.pop("nx", 16)
     p = B.make_params(nx, 8, **kw)

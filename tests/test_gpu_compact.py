@@ -1,0 +1,121 @@
+"""Compact population layout on the GPU: planes that hold only the fluid nodes
+(in (y, x) order) must give bitwise the populations and moments of the dense
+layout for every storage, boundary type, lattice width (one to several 64-node
+segments per row, with the periodic wrap across them) and launch shape; forces
+agree to the summation order of FP64 atomics."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1903_01111_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1903_01111_amd import binding
+    binding.lib()
+    return binding
+
+
+def _porous(nx, ny, seed, g=1e-5):
+    return W.perturb(W.porous_medium(nx=nx, ny=ny, rmin=3.0, rmax=7.0, gap=1.0, seed=seed, g=g), seed=seed,
+                     amp_rho=1e-3, amp_u=2e-3)
+
+
+CASES = {
+    "porous_48x40": lambda: _porous(48, 40, 1),      # one segment per row
+    "porous_100x37": lambda: _porous(100, 37, 2),    # two, the second partly padding
+    "porous_200x64": lambda: _porous(200, 64, 3),    # four
+    "cylinder_open": lambda: W.cylinder_channel(nx=150, ny=40, radius=6.2, centre=(40.0, 20.0), re=30.0, seed=2),
+    "walled_open": lambda: W.walled_cylinder(140, 20.0, 0.3, 0.6),
+}
+
+
+def _run(B, case, storage, layout, n, k=0, cfg=None):
+    lat = B.Lattice(case, storage=storage, layout=layout, dev_scale_log2=k)
+    if cfg is not None:
+        B.lbm_set_kernel_config(lat.ctx, cfg)
+    lat.step(n)
+    f = lat.populations()
+    rho, ux, uy = lat.moments()
+    forces = [lat.force(o) for o in range(case.n_obj)]
+    mass = lat.mass()
+    lat.close()
+    return f, (rho, ux, uy), forces, mass
+
+
+def _same(a, b):
+    fa, ma, Fa, mass_a = a
+    fb, mb, Fb, mass_b = b
+    assert np.array_equal(fa, fb)
+    for x, y in zip(ma, mb):
+        assert np.array_equal(x, y)
+    for (la, sa, na), (lb, sb, nb) in zip(Fa, Fb):
+        assert na == nb
+        assert np.abs(sa - sb).max() <= 1e-12 * max(np.abs(sb).max(), 1e-30)
+    assert abs(mass_a - mass_b) <= 1e-12 * abs(mass_b)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("storage", ["f32", "f64", "f16", "bf16"])
+def test_compact_equals_dense(B, name, storage):
+    case = CASES[name]()
+    k = 12 if storage == "f16" else 0
+    print(f"[compact] {name} {storage}", flush=True)
+    _same(_run(B, case, storage, "compact", 37, k), _run(B, case, storage, "dense", 37, k))
+
+
+@pytest.mark.parametrize("bx", [64, 128, 256])
+@pytest.mark.parametrize("xcd", [0, 1])
+def test_compact_launch_shapes(B, bx, xcd):
+    case = CASES["porous_200x64"]()
+    cfg = B.lbm_kernel_config(bx, 0, 256, 16, xcd)
+    _same(_run(B, case, "f32", "compact", 40, cfg=cfg), _run(B, case, "f32", "dense", 40))
+
+
+def test_compact_checkpoint_resume(B):
+    case = CASES["walled_open"]()
+    a = B.Lattice(case, storage="f32", layout="compact")
+    a.step(20)
+    st = B.lbm_get_state(a.ctx)
+    a.step(15)
+    fa = a.populations()
+    b = B.Lattice(case, storage="f32", layout="compact")
+    B.lbm_set_state(b.ctx, st)
+    b.step(15)
+    assert np.array_equal(fa, b.populations())
+    assert B.lbm_max_deviation(a.ctx) == B.lbm_max_deviation(b.ctx)
+    a.close()
+    b.close()
+
+
+def test_compact_matches_oracle(B):
+    case = CASES["porous_100x37"]()
+    lat = B.Lattice(case, storage="f64", layout="compact")
+    lat.step(200)
+    _, ux, uy = lat.moments()
+    _, s, _ = lat.force(0)
+    lat.close()
+    fp, g, fs, _, _ = oracle.run_case(case, nsteps=200)
+    _, uxr, uyr = oracle.moments(fp, g.solid, (case.gx, case.gy))
+    ref = max(np.abs(uxr).max(), np.abs(uyr).max())
+    assert max(np.abs(ux - uxr).max(), np.abs(uy - uyr).max()) <= 1e-11 * ref
+    assert np.abs(s - fs[0]).max() <= 1e-10 * np.abs(fs[0]).max()
+
+
+def test_compact_is_refused_where_unsupported(B):
+    case = CASES["cylinder_open"]()
+    lat = B.Lattice(case, storage="f32", layout="compact")
+    assert B.lbm_adjoint_workspace_bytes(lat.ctx, 10, 5) == 0
+    with pytest.raises(B.LbmError) as e:
+        B.lbm_adjoint_force(lat.ctx, 256, 1 << 20, 10, 5, 0, 1.0, 0.0, ny=case.ny, nx=case.nx,
+                            n_links=lat.n_links)
+    assert e.value.status == B.LBM_E_ARG
+    lat.close()
+    p = [B.make_params(case.nx, case.ny, x_open=True, tau=case.tau, layout="compact")]
+    assert B.lbm_batch_workspace_bytes(p, [100]) == 0

@@ -252,11 +252,11 @@ def test_every_kernel_config_gives_the_same_result(B):
     ref.close()
     for bx in (64, 128, 256):
         for ss in (0, 1):
-            for lb, gs in ((64, 2), (1024, 30)):
+            for lb, gs, xo in ((64, 2, 0), (1024, 30, 1)):
                 lat = B.Lattice(case, storage="f32")
-                B.lbm_set_kernel_config(lat.ctx, B.lbm_kernel_config(bx, ss, lb, gs))
+                B.lbm_set_kernel_config(lat.ctx, B.lbm_kernel_config(bx, ss, lb, gs, xo))
                 lat.step(45)
-                assert np.array_equal(lat.populations(), fr), (bx, ss, lb, gs)
+                assert np.array_equal(lat.populations(), fr), (bx, ss, lb, gs, xo)
                 _, s, _ = lat.force()
                 assert np.abs(s - sr).max() <= 1e-12 * np.abs(sr).max()
                 lat.close()
@@ -264,12 +264,12 @@ def test_every_kernel_config_gives_the_same_result(B):
 
 def test_invalid_kernel_config_is_rejected(B):
     lat = B.Lattice(small_cylinder(64, 32, 4.0), storage="f32")
-    for bad in ((96, 0, 256, 16), (256, 2, 256, 16), (256, 0, 100, 16), (256, 0, 256, 3)):
+    for bad in ((96, 0, 256, 16), (256, 2, 256, 16), (256, 0, 100, 16), (256, 0, 256, 3), (256, 0, 256, 16, 2)):
         with pytest.raises(B.LbmError) as e:
             B.lbm_set_kernel_config(lat.ctx, B.lbm_kernel_config(*bad))
         assert e.value.status == B.LBM_E_ARG
     assert B.lbm_get_kernel_config(lat.ctx).as_dict() == dict(bulk_block_x=256, bulk_store_solid=0,
-                                                             link_block=256, graph_steps=16)
+                                                             link_block=256, graph_steps=16, bulk_xcd=0)
     lat.close()
 
 
