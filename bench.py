@@ -38,14 +38,14 @@ def kernel_hash():
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:12]
 
 
-def counter_traffic():
+def counter_traffic(layout):
     """HBM bytes per bulk launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+    was taken on the current kernel source and population layout; else None."""
     if not os.path.exists(COUNTER_SUMMARY):
         return None
     txt = open(COUNTER_SUMMARY).read()
     m = dict(re.findall(r"^(\w+):\s*(\S+)", txt, flags=re.M))
-    if m.get("kernel_source_sha256_12") != kernel_hash():
+    if m.get("kernel_source_sha256_12") != kernel_hash() or m.get("layout") != layout:
         return None
     try:
         return float(m["hbm_bytes_per_bulk_launch"])
@@ -109,10 +109,10 @@ def e_u(a, b):
     return float(max(np.abs(a[0] - b[0]).max(), np.abs(a[1] - b[1]).max()) / ref)
 
 
-def form_precision(B, case, steps_err, steps_time):
+def form_precision(B, case, steps_err, steps_time, layout="compact"):
     """16-bit deviation storage against FP32 on the same workload: velocity error
     after steps_err steps from the same initial state, and throughput."""
-    f32 = B.Lattice(case, storage="f32")
+    f32 = B.Lattice(case, storage="f32", layout=layout)
     f32.step(steps_err)
     _, u32, v32 = f32.moments()
     k = B.dev_scale_for(B.lbm_max_deviation(f32.ctx))
@@ -120,7 +120,7 @@ def form_precision(B, case, steps_err, steps_time):
     f32.close()
     out = {}
     for st, kk in (("f16", k), ("bf16", 0)):
-        lat = B.Lattice(case, storage=st, dev_scale_log2=kk)
+        lat = B.Lattice(case, storage=st, dev_scale_log2=kk, layout=layout)
         lat.step(steps_err)
         try:
             _, u, v = lat.moments()
@@ -191,8 +191,8 @@ def form_batched(B, n_inst, steps, warmup):
     return out
 
 
-def form_single(B, case, steps, warmup):
-    lat = B.Lattice(case, storage="f32")
+def form_single(B, case, steps, warmup, layout="dense"):
+    lat = B.Lattice(case, storage="f32", layout=layout)
     lat.step(warmup)
     B.lbm_autotune(lat.ctx, 10)
     ms, link_ms, bulk_ms = timed(B, lat, steps)
@@ -262,7 +262,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="porous", choices=["porous", "cylinder", "dense"])
     ap.add_argument("--storage", default="f32", choices=list(BYTES))
-    ap.add_argument("--layout", default="dense", choices=["dense", "compact"],
+    ap.add_argument("--layout", default="compact", choices=["dense", "compact"],
                     help="population layout: every node, or the fluid nodes only")
     ap.add_argument("--cpu-steps", type=int, default=4,
                     help="oracle steps on the full lattice for the CPU baseline (0: skip)")
@@ -270,7 +270,7 @@ def main():
                     help="also run one 1 GiB device copy (counter calibration under rocprofv3)")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the FP16/BF16 storage, batched, cylinder and adjoint measurements")
-    ap.add_argument("--form", choices=["storage_16bit", "batched", "cylinder", "adjoint"],
+    ap.add_argument("--form", choices=["storage_16bit", "batched", "cylinder", "dense_layout", "adjoint"],
                     help="run only this form and print its JSON object")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -295,6 +295,8 @@ def main():
             res = form_batched(B, 256, 300, 20)
         elif args.form == "cylinder":
             res = form_single(B, W.cylinder_channel(), 2000, 100)
+        elif args.form == "dense_layout":
+            res = form_single(B, workload(args.workload), 1000, 100, layout="dense")
         else:
             res = form_adjoint(B)
         print(json.dumps({"form": args.form, **res}), flush=True)
@@ -378,7 +380,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "bulk (pull + BGK collision)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": counter_traffic(),
+                     "traffic": counter_traffic(args.layout),
                      "algorithmic_bytes_per_launch": bulk_bytes,
                      "avg_launch_us": round(bulk_avg_s * 1e6, 2)},
         "link_kernel": {"avg_launch_us": round(link_avg_s * 1e6, 2),
@@ -420,6 +422,9 @@ def main():
         forms["cylinder_2048x512_f32"] = form_single(B, W.cylinder_channel(), 2000, 100)
         forms["cylinder_2048x512_f32"]["note"] = ("75 MB working set: resident in the 256 MB "
                                                   "last-level cache, not an HBM figure")
+        forms["porous_dense_layout_f32"] = form_single(B, case, 1000, 100, layout="dense")
+        forms["porous_dense_layout_f32"]["note"] = ("the same porous step with every node of the padded "
+                                                    "lattice stored (solid nodes included)")
         forms["adjoint"] = form_adjoint(B)
         out["forms"] = forms
     print(json.dumps(out), flush=True)

@@ -514,6 +514,7 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
 __device__ __forceinline__ void zero_bank_part(double *__restrict__ zb, int32_t nz, int64_t block,
                                                int64_t nblocks, int tid)
 {
+    if (block * 256 >= nz) return;  // most blocks: nothing to clear (uniform)
     for (int64_t k = block * 256 + tid; k < nz; k += nblocks * 256) zb[k] = 0.0;
 }
 
@@ -524,7 +525,7 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
                                                    const mask_t *__restrict__ mask,
                                                    const typename Codec<ST>::R *__restrict__ uin,
                                                    Side side, double *__restrict__ zero_bank,
-                                                   int32_t n_zero, int32_t xcd)
+                                                   int32_t n_zero, int32_t xcd, double inv_nbx)
 {
     using R = typename Codec<ST>::R;
     using T = typename Codec<ST>::T;
@@ -540,12 +541,16 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
     // XCD k takes the k-th contiguous run of tiles in row-major order instead, so
     // the rows a tile pulls from, and the cache lines it shares with the tiles
     // beside it, were mostly touched by the same XCD and sit in its L2.
-    int64_t tile = b;
+    int tx = blockIdx.x, ty = blockIdx.y;
     if (xcd) {
-        const int64_t q = nb >> 3, r = nb & 7, k = b & 7;
-        tile = k * q + (k < r ? k : r) + (b >> 3);
+        const int32_t n = (int32_t)nb, q = n >> 3, r = n & 7, k = (int32_t)b & 7;
+        const int32_t tile = k * q + (k < r ? k : r) + ((int32_t)b >> 3);
+        // tile / gridDim.x in double: exact for tile < 2^31 (no integer divide)
+        ty = (int)((tile + 0.5) * inv_nbx);
+        tx = tile - ty * (int)gridDim.x;
+        if (tx < 0) tx += gridDim.x, --ty;
+        if (tx >= (int)gridDim.x) tx -= gridDim.x, ++ty;
     }
-    const int tx = (int)(tile % gridDim.x), ty = (int)(tile / gridDim.x);
     bulk_body<ST, OPEN, FORCE, BX, STORE_SOLID, CMP>(g, ph, A, B, mask, uin, side, tx * BX + threadIdx.x,
                                                      ty * BY + threadIdx.y, tid >> 6, lds_m, lds_p);
 }
@@ -736,7 +741,7 @@ hipError_t bulk_t(const Grid &g, const Phys &ph, const void *A, void *B, const m
     dim3 grid((g.nx + BX - 1) / BX, (g.ny + BY - 1) / BY);
     hipLaunchKernelGGL((bulk_kernel<ST, OPEN, FORCE, BX, SS, CMP>), grid, dim3(BX, BY), 0, s, g, ph,
                        static_cast<const typename C::T *>(A), static_cast<typename C::T *>(B), mask,
-                       static_cast<const typename C::R *>(uin), side, zb, nz, xcd);
+                       static_cast<const typename C::R *>(uin), side, zb, nz, xcd, 1.0 / grid.x);
     return hipGetLastError();
 }
 
