@@ -239,13 +239,16 @@ typedef struct {
     int32_t bulk_xcd;         /* 1: each XCD takes a contiguous run of the bulk blocks (workgroups
                                  go to the 8 XCDs round robin), so neighbouring rows and shared
                                  cache lines stay in one L2; 0: hardware order */
+    int32_t bulk_fused;       /* 1: the bulk kernel evaluates the links of its own nodes (one
+                                 launch per step plus the force reduction); needs bulk_block_x
+                                 256; 0: a separate link kernel */
 } lbm_kernel_config;
 
 lbm_status lbm_get_kernel_config(const lbm_ctx *ctx, lbm_kernel_config *cfg);
 /* Errors: LBM_E_ARG for an unsupported configuration (the previous one stays). */
 lbm_status lbm_set_kernel_config(lbm_ctx *ctx, const lbm_kernel_config *cfg);
 
-/* Autotuner: times every bulk shape (block, solid stores, XCD order) and link block size for steps_per_trial steps
+/* Autotuner: times every bulk shape (block, solid stores, XCD order, fused links) and link block size for steps_per_trial steps
  * on the current state, keeps the fastest, and restores the state (populations,
  * step counter, forces), so results do not depend on having tuned.  Needs host
  * memory for one checkpoint.  chosen and best_ms_per_step may be NULL. */

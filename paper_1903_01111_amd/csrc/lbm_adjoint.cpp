@@ -161,7 +161,11 @@ lbm_status lbm_adjoint_force(lbm_ctx *c, void *wsv, size_t ws_bytes, int64_t nst
                                    hipMemcpyHostToDevice, st), "column slots")))
         return s;
     const lbm::Links links = c->links();
-    const lbm::Side side = c->side();
+    // the recomputation reads and deposits in the current state's pair (the link
+    // kernel of a step reads before the bulk kernel overwrites)
+    lbm::Side side = c->side();
+    side.Mw = side.M;
+    side.Pw = side.P;
     const int32_t *mnode = side.mnode;
     const lbm::SegBase *seg = side.seg;
     if ((s = c->hip(lbm::launch_adj_setup(storage, links, mnode, ws + L.off_lrec, st), "adjoint setup")))

@@ -115,7 +115,7 @@ struct lbm_batch {
         return lbm::Side{ws + off_M, ws + off_P, ws + off_L, reinterpret_cast<const uint16_t *>(ws + off_rec),
                          reinterpret_cast<const lbm::SegBase *>(ws + off_seg),
                          reinterpret_cast<const int32_t *>(ws + off_mnode),
-                         reinterpret_cast<const int32_t *>(ws + off_pbase), n_flagged};
+                         reinterpret_cast<const int32_t *>(ws + off_pbase), n_flagged, ws + off_M, ws + off_P};
     }
     // the flagged nodes of instance i alone (its records, deposits and local node offsets)
     lbm::Side side_of(int i) const
@@ -126,14 +126,15 @@ struct lbm_batch {
                          reinterpret_cast<const lbm::SegBase *>(ws + off_seg) + il[i].seg_off,
                          reinterpret_cast<const int32_t *>(ws + off_mnode) + so,
                          reinterpret_cast<const int32_t *>(ws + off_pbase) + so,
-                         (int64_t)prep[i].rec.size()};
+                         (int64_t)prep[i].rec.size(), ws + off_M + (size_t)so * 3 * rb(),
+                         ws + off_P + (size_t)pop_base[i] * eb()};
     }
     lbm::Links links() const
     {
         auto i32 = [&](size_t off) { return reinterpret_cast<const int32_t *>(ws + off); };
         return lbm::Links{reinterpret_cast<const uint32_t *>(ws + off_meta), ws + off_q,
                           has_uw ? ws + off_uw : nullptr, i32(off_sf), i32(off_sff), i32(off_pf), i32(off_pff),
-                          i32(off_li), n_links};
+                          i32(off_li), n_links, 0, 0, nullptr};
     }
 };
 
@@ -289,7 +290,10 @@ lbm_status assemble(lbm_batch *b)
         rec.insert(rec.end(), P.rec.begin(), P.rec.end());
         mnode.insert(mnode.end(), P.mnode.begin(), P.mnode.end());
         pbase.insert(pbase.end(), P.pbase.begin(), P.pbase.end());
-        for (const lbm::SegBase &sb : P.seg) seg.push_back(lbm::SegBase{sb.flagged + so, sb.links + lo, sb.pops + po, 0});
+        for (size_t k = 0; k + 1 < P.seg.size(); ++k) {  // the instance's sentinel is not copied
+            const lbm::SegBase &sb = P.seg[k];
+            seg.push_back(lbm::SegBase{sb.flagged + so, sb.links + lo, sb.pops + po, 0});
+        }
     }
     std::vector<lbm::BatchInst> insts(b->n);
     std::vector<lbm::BatchTile> tiles;

@@ -21,7 +21,8 @@ struct Layout {
     int32_t pitch;
     int64_t plane;  // elements per population plane
     size_t off_A, off_B, off_mask, off_seg, off_fmask, off_meta, off_q, off_uw, off_sf, off_sff, off_pf, off_pff,
-        off_li, off_L, off_rec, off_mnode, off_pbase, off_M, off_P, off_wpart, off_wobj, off_uin,
+        off_li, off_kof, off_L, off_rec, off_mnode, off_pbase, off_M, off_P, off_M2, off_P2, off_wpart,
+        off_wobj, off_uin,
         off_force, off_partials, off_stage, total;
     int64_t wave_cap;  // wavefront partials of the link kernel
 };
@@ -41,6 +42,7 @@ struct lbm_ctx {
     size_t ws_bytes = 0;
     int64_t max_links = 0, n_links = 0, n_moment_nodes = 0;
     bool has_uw = false, have_geom = false, have_init = false;
+    bool li_ident = false;  // links in (node, dir) order: L entry = link index
     // caller's index of each device link (links are kept in (obj, node, dir) order)
     std::vector<int64_t> link_order;
     // flagged slot of the inlet node (0, y) at [y] and of the outlet node
@@ -48,10 +50,15 @@ struct lbm_ctx {
     std::vector<int32_t> colslot;
     void *cur = nullptr, *nxt = nullptr;
     int64_t step = 0, nsum = 0;
-    lbm_kernel_config kcfg{256, 0, 256, 16, 0};
-    // graph of kcfg.graph_steps steps starting from buffer `graph_cur`
+    lbm_kernel_config kcfg{256, 0, 256, 16, 0, 0};
+    // deposits (M, P) are double-buffered: dpar selects the pair the links of the
+    // next step read; the bulk kernel deposits into the other one
+    int dpar = 0;
+    // graph of kcfg.graph_steps steps starting from buffer `graph_cur` and deposit
+    // parity `graph_dpar`
     hipGraphExec_t gexec = nullptr;
     void *graph_cur = nullptr;
+    int graph_dpar = 0;
     // profiling
     bool prof = false;
     std::vector<hipEvent_t> events;
@@ -76,7 +83,8 @@ struct lbm_ctx {
         auto i32 = [&](size_t off) { return reinterpret_cast<const int32_t *>(ws + off); };
         return lbm::Links{reinterpret_cast<const uint32_t *>(ws + lay.off_meta), ws + lay.off_q,
                           has_uw ? ws + lay.off_uw : nullptr, i32(lay.off_sf), i32(lay.off_sff),
-                          i32(lay.off_pf), i32(lay.off_pff), i32(lay.off_li), n_links};
+                          i32(lay.off_pf), i32(lay.off_pff), i32(lay.off_li), n_links, li_ident ? 1 : 0, 0,
+                          li_ident ? nullptr : i32(lay.off_kof)};
     }
     lbm::Reduce reduce() const
     {
@@ -85,16 +93,21 @@ struct lbm_ctx {
     }
     lbm::BulkConfig bulk_config() const
     {
-        return lbm::BulkConfig{kcfg.bulk_block_x, kcfg.bulk_store_solid, kcfg.bulk_xcd};
+        return lbm::BulkConfig{kcfg.bulk_block_x, kcfg.bulk_store_solid, kcfg.bulk_xcd, kcfg.bulk_fused};
     }
-    lbm::Side side() const
+    // deposits read with parity p (and written into the other pair)
+    lbm::Side side_par(int p) const
     {
-        return lbm::Side{ws + lay.off_M, ws + lay.off_P, ws + lay.off_L,
+        char *Mr = ws + (p ? lay.off_M2 : lay.off_M), *Pr = ws + (p ? lay.off_P2 : lay.off_P);
+        char *Mw = ws + (p ? lay.off_M : lay.off_M2), *Pw = ws + (p ? lay.off_P : lay.off_P2);
+        return lbm::Side{Mr, Pr, ws + lay.off_L,
                          reinterpret_cast<const uint16_t *>(ws + lay.off_rec),
                          reinterpret_cast<const lbm::SegBase *>(ws + lay.off_seg),
                          reinterpret_cast<const int32_t *>(ws + lay.off_mnode),
-                         reinterpret_cast<const int32_t *>(ws + lay.off_pbase), n_moment_nodes};
+                         reinterpret_cast<const int32_t *>(ws + lay.off_pbase), n_moment_nodes, Mw, Pw};
     }
+    // the deposits of the current state
+    lbm::Side side() const { return side_par(dpar); }
     lbm::mask_t *mask() const { return reinterpret_cast<lbm::mask_t *>(ws + lay.off_mask); }
     double *force() const { return reinterpret_cast<double *>(ws + lay.off_force); }
     double *bank(int64_t t) const { return force() + (size_t)(t & 1) * 2 * p.n_obj; }

@@ -40,7 +40,7 @@ struct Prepared {
     std::vector<uint16_t> rec;
     std::vector<int32_t> mnode, pbase;
     std::vector<lbm::mask_t> mask;         // padded to the pitch: link bits, solid bit, side bit
-    std::vector<lbm::SegBase> seg;         // per 64-node row segment
+    std::vector<lbm::SegBase> seg;         // per 64-node row segment, plus a sentinel with the totals
     std::vector<uint64_t> fmask;           // per segment: its fluid nodes (bit = lane)
     int64_t n_pops = 0;
     bool has_uw = false;

@@ -56,6 +56,9 @@ struct SegBase {
 //    in (node, dir) order;
 //  - the next bulk kernel pulls direction i of a node from L instead of from the
 //    solid neighbour x - e_i (rec bits 0..7 mark the node's link directions).
+//  M and P are what the links read this step; the bulk kernel deposits into Mw
+//  and Pw (the same arrays, or the other of a double-buffered pair when the bulk
+//  kernel evaluates the links of its own nodes).
 struct Side {
     void *M;                 // real[3K]
     void *P;                 // storage[NP]
@@ -65,6 +68,8 @@ struct Side {
     const int32_t *mnode;    // [K] plane offset of each flagged node
     const int32_t *pbase;    // [K] first P entry of each flagged node
     int64_t K;
+    void *Mw;                // deposits of this step: real[3K]
+    void *Pw;                // storage[NP]
 };
 
 // Links in (obj, node, dir) order, so a wavefront usually serves one object.
@@ -78,6 +83,9 @@ struct Links {
     const int32_t *pff;    // P entry of f+_{i'}(x_ff) (VIBB links)
     const int32_t *li;     // rank of the link in (node, dir) order: its L entry
     int64_t n;
+    int32_t li_ident;      // 1: li[l] == l for every link (one object), li is not read
+    int32_t pad;
+    const int32_t *kof;    // inverse of li (null when li_ident)
 };
 
 // Wavefront partial forces of the link kernel, reduced per object by a second
@@ -92,6 +100,18 @@ struct BulkConfig {
     int32_t block_x;      // 64, 128 or 256 lanes along x; 256/block_x rows
     int32_t store_solid;  // lanes of solid nodes store zeros too (full-line writes)
     int32_t xcd;          // contiguous runs of blocks per XCD (see bulk_kernel)
+    int32_t fused;        // the bulk kernel evaluates the links of its nodes (no link kernel)
+};
+
+// What the fused bulk kernel needs for the links: link arrays, the per-segment
+// force partials (one per 64-node row segment, reduced by force_reduce_kernel
+// into force_bank and force_sum) and the banks for wavefronts that mix objects.
+struct FuseArgs {
+    Links L;
+    double2 *wpart;
+    int32_t *wobj;
+    double *bank;
+    double *fsum;
 };
 
 // Link values of one step into side.L and, unless force_bank is null, the force
@@ -103,6 +123,13 @@ hipError_t launch_link(int storage, const Grid &g, const Phys &ph, const Links &
 hipError_t launch_bulk(int storage, const Grid &g, const Phys &ph, const void *A, void *B,
                        const mask_t *mask, const void *uin, const Side &side, double *zero_bank,
                        int32_t n_zero, const BulkConfig &cf, hipStream_t s);
+
+// One whole step with the links evaluated inside the bulk kernel (cf.fused): the
+// bulk launch, then the force reduction over its segment partials.  side.M/P
+// must hold this step's deposits and side.Mw/Pw other arrays.
+hipError_t launch_bulk_fused(int storage, const Grid &g, const Phys &ph, const void *A, void *B,
+                             const mask_t *mask, const void *uin, const Side &side, const FuseArgs &fa,
+                             double *zero_bank, int32_t n_zero, const BulkConfig &cf, hipStream_t s);
 
 // Batched form: per-instance descriptor and per-block tile.
 struct BatchInst {

@@ -27,6 +27,78 @@ namespace {
 // ---------------------------------------------------------------------------
 // Link kernel: one lane per link, reading only compact arrays.
 // ---------------------------------------------------------------------------
+
+// Value of link k (decoded, before storage rounding) from the moments M and the
+// populations P deposited by the previous bulk step (Section 3.1, or halfway
+// bounce-back where x_ff is unusable), and its momentum-exchange force: the
+// population f+_{i'}(x_f) into the wall and f_i(x_f) back, both along e_{i'}.
+template <int ST>
+__device__ __forceinline__ typename Codec<ST>::R link_eval(const Phys &ph, const Links &L, const void *Mv,
+                                                           const void *Pv, int64_t k, double &fx, double &fy,
+                                                           int &obj)
+{
+    using C = Codec<ST>;
+    using T = typename C::T;
+    using R = typename C::R;
+    const uint32_t meta = L.meta[k];
+    const int ip = (int)(meta & 15u);
+    obj = (int)(meta >> 8);
+    const int cxp = cx_of(ip), cyp = cy_of(ip);
+    const R w = ip <= 4 ? R(1) / R(9) : R(1) / R(36);
+    const R *qv = static_cast<const R *>(L.q);
+    const T *P = static_cast<const T *>(Pv);
+    const R *M = static_cast<const R *>(Mv);
+    R uwx = R(0), uwy = R(0);
+    if (L.uw) {
+        const R *u = static_cast<const R *>(L.uw);
+        uwx = u[2 * k];
+        uwy = u[2 * k + 1];
+    }
+    // moving-wall momentum term 6 w_{i'} rho0 e_i.u_w, with e_i = -e_{i'}
+    const R wall = -R(6) * w * R(ph.rho0) * (R(cxp) * uwx + R(cyp) * uwy);
+    const R fpf = C::ld(P[L.pf[k]], ph.inv_scale);
+    const int32_t sff = L.sff[k];
+    R v;
+    if (sff < 0) {
+        v = fpf + wall;  // halfway bounce-back
+    } else {
+        // moments of f and ff at time t, deposited by the previous bulk step
+        const int32_t sf = L.sf[k];
+        const R drf = M[3 * sf], ufx = M[3 * sf + 1], ufy = M[3 * sf + 2];
+        const R drff = M[3 * sff], uffx = M[3 * sff + 1], uffy = M[3 * sff + 2];
+        const R fpff = C::ld(P[L.pff[k]], ph.inv_scale);
+        const R q = qv[k];
+        const R a2q = R(2) * q, b2q = R(1) - R(2) * q;
+        // density at the departure point d (extrapolated when q > 1/2)
+        const R drd = a2q * drf + b2q * drff;
+        // non-equilibrium parts at f and ff, interpolated per unit density and
+        // rescaled by rho_d: rho_d/rho_f = 1 + (dr_d - dr_f)/(1 + dr_f)
+        const R neqf = fpf - deq(w, R(cxp) * ufx + R(cyp) * ufy, drf, ufx * ufx + ufy * ufy);
+        const R neqff = fpff - deq(w, R(cxp) * uffx + R(cyp) * uffy, drff, uffx * uffx + uffy * uffy);
+        const R neqd = a2q * (neqf + neqf * ((drd - drf) / (R(1) + drf))) +
+                       b2q * (neqff + neqff * ((drd - drff) / (R(1) + drff)));
+        // velocity at d: u*_d from (f, ff) or (f, wall), u**_d from (ff, wall)
+        R usx, usy;
+        if (q <= R(0.5)) {
+            usx = a2q * ufx + b2q * uffx;
+            usy = a2q * ufy + b2q * uffy;
+        } else {
+            const R cf = (R(1) - q) / q, cw = (R(2) * q - R(1)) / q;
+            usx = cf * ufx + cw * uwx;
+            usy = cf * ufy + cw * uwy;
+        }
+        const R inv1q = R(1) / (R(1) + q);
+        const R cff = (R(1) - q) * inv1q, cww = a2q * inv1q;
+        const R ussx = cff * uffx + cww * uwx, ussy = cff * uffy + cww * uwy;
+        const R udx = (usx + R(2) * ussx) / R(3), udy = (usy + R(2) * ussy) / R(3);
+        v = deq(w, R(cxp) * udx + R(cyp) * udy, drd, udx * udx + udy * udy) + neqd + wall;
+    }
+    const double m = (double)fpf + (double)v + 2.0 * (double)w;
+    fx = cxp * m;
+    fy = cyp * m;
+    return v;
+}
+
 template <int ST>
 __global__ __launch_bounds__(1024) void link_kernel(Grid g, Phys ph, Links L, Side side,
                                                     double2 *__restrict__ wpart, int32_t *__restrict__ wobj,
@@ -34,70 +106,13 @@ __global__ __launch_bounds__(1024) void link_kernel(Grid g, Phys ph, Links L, Si
 {
     using C = Codec<ST>;
     using T = typename C::T;
-    using R = typename C::R;
     const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = l < L.n;
     double fx = 0.0, fy = 0.0;
     int obj = -1;
     if (active) {
-        const uint32_t meta = L.meta[l];
-        const int ip = (int)(meta & 15u);
-        obj = (int)(meta >> 8);
-        const int cxp = cx_of(ip), cyp = cy_of(ip);
-        const R w = ip <= 4 ? R(1) / R(9) : R(1) / R(36);
-        const R *qv = static_cast<const R *>(L.q);
-        const T *P = static_cast<const T *>(side.P);
-        const R *M = static_cast<const R *>(side.M);
-        R uwx = R(0), uwy = R(0);
-        if (L.uw) {
-            const R *u = static_cast<const R *>(L.uw);
-            uwx = u[2 * l];
-            uwy = u[2 * l + 1];
-        }
-        // moving-wall momentum term 6 w_{i'} rho0 e_i.u_w, with e_i = -e_{i'}
-        const R wall = -R(6) * w * R(ph.rho0) * (R(cxp) * uwx + R(cyp) * uwy);
-        const R fpf = C::ld(P[L.pf[l]], ph.inv_scale);
-        const int32_t sff = L.sff[l];
-        R v;
-        if (sff < 0) {
-            v = fpf + wall;  // halfway bounce-back
-        } else {
-            // moments of f and ff at time t, deposited by the previous bulk step
-            const int32_t sf = L.sf[l];
-            const R drf = M[3 * sf], ufx = M[3 * sf + 1], ufy = M[3 * sf + 2];
-            const R drff = M[3 * sff], uffx = M[3 * sff + 1], uffy = M[3 * sff + 2];
-            const R fpff = C::ld(P[L.pff[l]], ph.inv_scale);
-            const R q = qv[l];
-            const R a2q = R(2) * q, b2q = R(1) - R(2) * q;
-            // density at the departure point d (extrapolated when q > 1/2)
-            const R drd = a2q * drf + b2q * drff;
-            // non-equilibrium parts at f and ff, interpolated per unit density and
-            // rescaled by rho_d: rho_d/rho_f = 1 + (dr_d - dr_f)/(1 + dr_f)
-            const R neqf = fpf - deq(w, R(cxp) * ufx + R(cyp) * ufy, drf, ufx * ufx + ufy * ufy);
-            const R neqff = fpff - deq(w, R(cxp) * uffx + R(cyp) * uffy, drff, uffx * uffx + uffy * uffy);
-            const R neqd = a2q * (neqf + neqf * ((drd - drf) / (R(1) + drf))) +
-                           b2q * (neqff + neqff * ((drd - drff) / (R(1) + drff)));
-            // velocity at d: u*_d from (f, ff) or (f, wall), u**_d from (ff, wall)
-            R usx, usy;
-            if (q <= R(0.5)) {
-                usx = a2q * ufx + b2q * uffx;
-                usy = a2q * ufy + b2q * uffy;
-            } else {
-                const R cf = (R(1) - q) / q, cw = (R(2) * q - R(1)) / q;
-                usx = cf * ufx + cw * uwx;
-                usy = cf * ufy + cw * uwy;
-            }
-            const R inv1q = R(1) / (R(1) + q);
-            const R cff = (R(1) - q) * inv1q, cww = a2q * inv1q;
-            const R ussx = cff * uffx + cww * uwx, ussy = cff * uffy + cww * uwy;
-            const R udx = (usx + R(2) * ussx) / R(3), udy = (usy + R(2) * ussy) / R(3);
-            v = deq(w, R(cxp) * udx + R(cyp) * udy, drd, udx * udx + udy * udy) + neqd + wall;
-        }
-        static_cast<T *>(side.L)[L.li[l]] = C::st(v, ph.scale);
-        // momentum exchange: f+_{i'}(x_f) into the wall and f_i(x_f) back, both along e_{i'}
-        const double m = (double)fpf + (double)v + 2.0 * (double)w;
-        fx = cxp * m;
-        fy = cyp * m;
+        const auto v = link_eval<ST>(ph, L, side.M, side.P, l, fx, fy, obj);
+        static_cast<T *>(side.L)[L.li_ident ? (int32_t)l : L.li[l]] = C::st(v, ph.scale);
     }
     if (!bank) return;  // link values only: no force wanted (uniform over the grid)
     // FP64 wavefront reduction.  Links are sorted by object, so a wavefront
@@ -140,11 +155,20 @@ __global__ __launch_bounds__(256) void force_reduce_kernel(const double2 *__rest
                                                            double *__restrict__ fsum)
 {
     const int64_t k0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * REDUCE_CHUNK;
-    const int64_t k1 = k0 + REDUCE_CHUNK < nw ? k0 + REDUCE_CHUNK : nw;
+    // all loads of the chunk first (one round trip), then the segmented sum
+    int ob[REDUCE_CHUNK];
+    double2 pv[REDUCE_CHUNK];
+#pragma unroll
+    for (int k = 0; k < REDUCE_CHUNK; ++k) {
+        const bool in = k0 + k < nw;
+        ob[k] = in ? wobj[k0 + k] : -1;
+        pv[k] = in ? wpart[k0 + k] : make_double2(0.0, 0.0);
+    }
     int cur = -1;
     double ax = 0.0, ay = 0.0;
-    for (int64_t k = k0; k < k1; ++k) {
-        const int o = wobj[k];
+#pragma unroll
+    for (int k = 0; k < REDUCE_CHUNK; ++k) {
+        const int o = ob[k];
         if (o < 0) continue;
         if (o != cur) {
             if (cur >= 0) {
@@ -156,9 +180,8 @@ __global__ __launch_bounds__(256) void force_reduce_kernel(const double2 *__rest
             cur = o;
             ax = ay = 0.0;
         }
-        const double2 v = wpart[k];
-        ax += v.x;
-        ay += v.y;
+        ax += pv[k].x;
+        ay += pv[k].y;
     }
     int top = cur;
 #pragma unroll
@@ -192,7 +215,7 @@ __device__ __forceinline__ int popc32(uint32_t v) { return __popc(v); }
 
 // One node per lane of the lattice described by (g, ph, A, B, mask, uin, side);
 // (x, y) is the lane's node, wv its wavefront within the block.
-template <int ST, bool OPEN, bool FORCE, int BX, bool STORE_SOLID, bool CMP = false>
+template <int ST, bool OPEN, bool FORCE, int BX, bool STORE_SOLID, bool CMP = false, bool FUSE = false>
 __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
                                           const typename Codec<ST>::T *__restrict__ A,
                                           typename Codec<ST>::T *__restrict__ B,
@@ -200,7 +223,9 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
                                           const typename Codec<ST>::R *__restrict__ uin,
                                           const Side &side, int x, int y, int wv,
                                           typename Codec<ST>::R (*lds_m)[3 * 64],
-                                          typename Codec<ST>::T (*lds_p)[8 * 64])
+                                          typename Codec<ST>::T (*lds_p)[8 * 64],
+                                          const FuseArgs *fa = nullptr,
+                                          typename Codec<ST>::T (*lds_l)[8 * 64] = nullptr)
 {
     using C = Codec<ST>;
     using T = typename C::T;
@@ -298,6 +323,57 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
     for (int i = 0; i < 9; ++i) a[i] = ld_el(A + i * P, o[i]);
     const int32_t seg = __builtin_amdgcn_readfirstlane(y * (g.pitch >> 6) + (x >> 6));
     const SegBase sb = side.seg[seg];
+    if (FUSE) {
+        // the wavefront's links are entries [lw, lw + nl) of the (node, dir) order
+        // (segment bases; no need to wait for the mask words): one per lane,
+        // evaluated from the previous step's deposits while the pulls are in
+        // flight, handed to the node lanes through LDS; their force goes to the
+        // segment's partial
+        const int32_t lw = sb.links;
+        const int nl = side.seg[seg + 1].links - lw;
+        const Links &L = fa->L;
+        double fx = 0.0, fy = 0.0;
+        int obj = -1;
+        for (int j = lane; j < nl; j += 64) {
+            const int64_t k = L.li_ident ? (int64_t)(lw + j) : (int64_t)L.kof[lw + j];
+            double lfx, lfy;
+            int o;
+            const R v = link_eval<ST>(ph, L, side.M, side.P, k, lfx, lfy, o);
+            lds_l[wv][j] = C::st(v, ph.scale);
+            if (obj < 0 || o == obj) {
+                obj = o;
+                fx += lfx;
+                fy += lfy;
+            } else {
+                unsafeAtomicAdd(&fa->bank[2 * o], lfx);
+                unsafeAtomicAdd(&fa->bank[2 * o + 1], lfy);
+                unsafeAtomicAdd(&fa->fsum[2 * o], lfx);
+                unsafeAtomicAdd(&fa->fsum[2 * o + 1], lfy);
+            }
+        }
+        int top = obj;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) top = max(top, __shfl_xor(top, off));
+        if (__all(obj == top || obj < 0)) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                fx += __shfl_xor(fx, off);
+                fy += __shfl_xor(fy, off);
+            }
+            if (lane == 0) {
+                fa->wpart[seg] = make_double2(fx, fy);
+                fa->wobj[seg] = top;
+            }
+        } else {
+            if (obj >= 0) {
+                unsafeAtomicAdd(&fa->bank[2 * obj], fx);
+                unsafeAtomicAdd(&fa->bank[2 * obj + 1], fy);
+                unsafeAtomicAdd(&fa->fsum[2 * obj], fx);
+                unsafeAtomicAdd(&fa->fsum[2 * obj + 1], fy);
+            }
+            if (lane == 0) fa->wobj[seg] = -1;
+        }
+    }
     const uint64_t flagged = __ballot((m & MASK_SIDE) != 0);
     const int32_t slot = sb.flagged + (int32_t)__popcll(flagged & ((1ull << lane) - 1ull));
     const uint32_t rec = (m & MASK_SIDE) ? side.rec[slot] : 0u;
@@ -308,7 +384,19 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
     // where x - e_i is solid, the link (x, i') with i' = opp(i) (bit i'-1 of the
     // mask word) supplies the population: its load is issued now, while the
     // side record is still in flight
-    {
+    if (FUSE) {
+        const int32_t lw = sb.links;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        constexpr int OPPI[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+        const int lo = lbase - lw;
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            const uint32_t bit = 1u << (OPPI[i] - 1);
+            if (lk & bit) a[i] = lds_l[wv][lo + popc32(lk & (bit - 1u))];
+        }
+    } else {
         const T *Lv = static_cast<const T *>(side.L);
         constexpr int OPPI[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 #pragma unroll
@@ -434,8 +522,8 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
     // writes its contiguous ranges of M and P in full lines.  The post-collision
     // moments are the collision's own (rho, u): with Guo's shift the physical
     // velocity of f+ equals the collision velocity.
-    R *Mv = static_cast<R *>(side.M);
-    T *Pv = static_cast<T *>(side.P);
+    R *Mv = static_cast<R *>(side.Mw);
+    T *Pv = static_cast<T *>(side.Pw);
     if (m & MASK_SIDE) {
         const int ls = slot - sb.flagged;
         lds_m[wv][3 * ls] = drho;
@@ -553,6 +641,39 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
     }
     bulk_body<ST, OPEN, FORCE, BX, STORE_SOLID, CMP>(g, ph, A, B, mask, uin, side, tx * BX + threadIdx.x,
                                                      ty * BY + threadIdx.y, tid >> 6, lds_m, lds_p);
+}
+
+// The same step with the links of each wavefront's nodes evaluated in the
+// wavefront itself (FUSE): 256 lanes along x per block.
+template <int ST, bool OPEN, bool FORCE, bool STORE_SOLID, bool CMP>
+__global__ __launch_bounds__(256) void bulk_fused_kernel(Grid g, Phys ph,
+                                                         const typename Codec<ST>::T *__restrict__ A,
+                                                         typename Codec<ST>::T *__restrict__ B,
+                                                         const mask_t *__restrict__ mask,
+                                                         const typename Codec<ST>::R *__restrict__ uin,
+                                                         Side side, FuseArgs fa, double *__restrict__ zero_bank,
+                                                         int32_t n_zero, int32_t xcd, double inv_nbx)
+{
+    using R = typename Codec<ST>::R;
+    using T = typename Codec<ST>::T;
+    __shared__ R lds_m[4][3 * 64];
+    __shared__ T lds_p[4][8 * 64];
+    __shared__ T lds_l[4][8 * 64];
+    const int tid = threadIdx.x;
+    const int64_t nb = (int64_t)gridDim.x * gridDim.y;
+    const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    zero_bank_part(zero_bank, n_zero, b, nb, tid);
+    int tx = blockIdx.x, ty = blockIdx.y;
+    if (xcd) {
+        const int32_t n = (int32_t)nb, q = n >> 3, r = n & 7, k = (int32_t)b & 7;
+        const int32_t tile = k * q + (k < r ? k : r) + ((int32_t)b >> 3);
+        ty = (int)((tile + 0.5) * inv_nbx);
+        tx = tile - ty * (int)gridDim.x;
+        if (tx < 0) tx += gridDim.x, --ty;
+        if (tx >= (int)gridDim.x) tx -= gridDim.x, ++ty;
+    }
+    bulk_body<ST, OPEN, FORCE, 256, STORE_SOLID, CMP, true>(g, ph, A, B, mask, uin, side, tx * 256 + threadIdx.x,
+                                                            ty, tid >> 6, lds_m, lds_p, &fa, lds_l);
 }
 
 // Batched form: one launch over the tiles of many lattices.  Each block reads its
@@ -732,6 +853,50 @@ hipError_t link_t(const Grid &g, const Phys &ph, const Links &L, const Side &sid
     return hipGetLastError();
 }
 
+template <int ST, bool OPEN, bool FORCE, bool SS, bool CMP>
+hipError_t bulk_fused_t(const Grid &g, const Phys &ph, const void *A, void *B, const mask_t *mask,
+                        const void *uin, const Side &side, const FuseArgs &fa, double *zb, int32_t nz,
+                        int32_t xcd, hipStream_t s)
+{
+    using C = Codec<ST>;
+    dim3 grid((g.nx + 255) / 256, g.ny);
+    hipLaunchKernelGGL((bulk_fused_kernel<ST, OPEN, FORCE, SS, CMP>), grid, dim3(256), 0, s, g, ph,
+                       static_cast<const typename C::T *>(A), static_cast<typename C::T *>(B), mask,
+                       static_cast<const typename C::R *>(uin), side, fa, zb, nz, xcd, 1.0 / grid.x);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // one force partial per 64-node row segment
+    const int64_t nw = (int64_t)(g.pitch / 64) * g.ny;
+    const int64_t lanes = (nw + REDUCE_CHUNK - 1) / REDUCE_CHUNK;
+    hipLaunchKernelGGL(force_reduce_kernel, dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, s, fa.wpart,
+                       fa.wobj, nw, fa.bank, fa.fsum);
+    return hipGetLastError();
+}
+
+template <int ST, bool OPEN, bool FORCE>
+hipError_t bulk_fused_shape(const Grid &g, const Phys &ph, const void *A, void *B, const mask_t *mask,
+                            const void *uin, const Side &side, const FuseArgs &fa, double *zb, int32_t nz,
+                            const BulkConfig &cf, hipStream_t s)
+{
+    if (cf.block_x != 256) return hipErrorInvalidValue;
+    if (g.compact) return bulk_fused_t<ST, OPEN, FORCE, false, true>(g, ph, A, B, mask, uin, side, fa, zb, nz, cf.xcd, s);
+    if (cf.store_solid) return bulk_fused_t<ST, OPEN, FORCE, true, false>(g, ph, A, B, mask, uin, side, fa, zb, nz, cf.xcd, s);
+    return bulk_fused_t<ST, OPEN, FORCE, false, false>(g, ph, A, B, mask, uin, side, fa, zb, nz, cf.xcd, s);
+}
+
+template <int ST>
+hipError_t bulk_fused_dispatch(const Grid &g, const Phys &ph, const void *A, void *B, const mask_t *mask,
+                               const void *uin, const Side &side, const FuseArgs &fa, double *zb, int32_t nz,
+                               const BulkConfig &cf, hipStream_t s)
+{
+    const bool force = ph.gx != 0.0 || ph.gy != 0.0;
+    if (g.x_open)
+        return force ? bulk_fused_shape<ST, true, true>(g, ph, A, B, mask, uin, side, fa, zb, nz, cf, s)
+                     : bulk_fused_shape<ST, true, false>(g, ph, A, B, mask, uin, side, fa, zb, nz, cf, s);
+    return force ? bulk_fused_shape<ST, false, true>(g, ph, A, B, mask, uin, side, fa, zb, nz, cf, s)
+                 : bulk_fused_shape<ST, false, false>(g, ph, A, B, mask, uin, side, fa, zb, nz, cf, s);
+}
+
 template <int ST, bool OPEN, bool FORCE, int BX, bool SS, bool CMP>
 hipError_t bulk_t(const Grid &g, const Phys &ph, const void *A, void *B, const mask_t *mask,
                   const void *uin, const Side &side, double *zb, int32_t nz, int32_t xcd, hipStream_t s)
@@ -831,6 +996,19 @@ hipError_t launch_link(int storage, const Grid &g, const Phys &ph, const Links &
     case 1: return link_t<1>(g, ph, L, side, red, bank, fsum, block, s);
     case 2: return link_t<2>(g, ph, L, side, red, bank, fsum, block, s);
     case 3: return link_t<3>(g, ph, L, side, red, bank, fsum, block, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_bulk_fused(int storage, const Grid &g, const Phys &ph, const void *A, void *B,
+                             const mask_t *mask, const void *uin, const Side &side, const FuseArgs &fa,
+                             double *zb, int32_t nz, const BulkConfig &cf, hipStream_t s)
+{
+    switch (storage) {
+    case 0: return bulk_fused_dispatch<0>(g, ph, A, B, mask, uin, side, fa, zb, nz, cf, s);
+    case 1: return bulk_fused_dispatch<1>(g, ph, A, B, mask, uin, side, fa, zb, nz, cf, s);
+    case 2: return bulk_fused_dispatch<2>(g, ph, A, B, mask, uin, side, fa, zb, nz, cf, s);
+    case 3: return bulk_fused_dispatch<3>(g, ph, A, B, mask, uin, side, fa, zb, nz, cf, s);
     default: return hipErrorInvalidValue;
     }
 }

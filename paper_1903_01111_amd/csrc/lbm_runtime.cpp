@@ -36,7 +36,7 @@ size_t real_bytes(int storage) { return storage == LBM_F64 ? 8 : 4; }
 // with their side moments)
 size_t bytes_per_link(int storage)
 {
-    return 45 + 9 * real_bytes(storage) + 3 * elem_bytes(storage);
+    return 49 + 15 * real_bytes(storage) + 5 * elem_bytes(storage);
 }
 
 // Plane stride: rows padded to 64 elements; the plane size in 256-byte units is
@@ -58,7 +58,7 @@ Layout make_layout(const lbm_params &p, int64_t max_links)
     L.off_A = take(9 * pb);
     L.off_B = take(9 * pb);
     L.off_mask = take((size_t)L.pitch * p.ny * sizeof(lbm::mask_t));
-    L.off_seg = take((size_t)(L.pitch / 64) * p.ny * sizeof(lbm::SegBase));
+    L.off_seg = take(((size_t)(L.pitch / 64) * p.ny + 1) * sizeof(lbm::SegBase));
     L.off_fmask = take((size_t)(L.pitch / 64) * p.ny * sizeof(uint64_t));
     const size_t nl = (size_t)std::max<int64_t>(max_links, 0);
     L.off_meta = take(nl * 4);
@@ -69,6 +69,7 @@ Layout make_layout(const lbm_params &p, int64_t max_links)
     L.off_pf = take(nl * 4);
     L.off_pff = take(nl * 4);
     L.off_li = take(nl * 4);
+    L.off_kof = take(nl * 4);
     L.off_L = take(nl * eb);
     // at most two flagged nodes and two deposited populations per link
     L.off_rec = take(2 * nl * 2);
@@ -76,7 +77,10 @@ Layout make_layout(const lbm_params &p, int64_t max_links)
     L.off_pbase = take(2 * nl * 4);
     L.off_M = take(2 * nl * 3 * rb);
     L.off_P = take(2 * nl * eb);
-    L.wave_cap = (int64_t)(nl + 63) / 64 + 16;
+    L.off_M2 = take(2 * nl * 3 * rb);
+    L.off_P2 = take(2 * nl * eb);
+    // force partials: one per 64 links (link kernel) or per row segment (fused bulk)
+    L.wave_cap = std::max<int64_t>((int64_t)(nl + 63) / 64, (int64_t)(L.pitch / 64) * p.ny) + 16;
     L.off_wpart = take((size_t)L.wave_cap * 16);
     L.off_wobj = take((size_t)L.wave_cap * 4);
     L.off_uin = take((size_t)p.ny * 2 * rb);
@@ -301,6 +305,8 @@ lbm_status prepare_geometry(const lbm_params &p, const uint8_t *mask, int64_t n,
             npops += __builtin_popcount(bits[o] >> 8);
         }
     }
+    // sentinel after the last segment: the totals
+    out->seg.push_back(lbm::SegBase{(int32_t)out->rec.size(), nlinks, npops, nfluid});
     out->n_pops = npops;
     auto rank_below = [](uint32_t set, int d) { return __builtin_popcount(set & ((1u << (d - 1)) - 1u)); };
     // links in (obj, node, dir) order; L entry = rank in (node, dir) order
@@ -393,16 +399,30 @@ lbm_status lbm_host::enqueue_step_to(lbm_ctx *c, const void *A, void *B, bool ti
         c->ev_used += 3;
         hipEventRecord(e0, c->stream);
     }
-    lbm_status s = c->hip(lbm::launch_link(c->p.storage, g, ph, c->links(), c->side(), c->reduce(),
-                                           c->bank(c->step), c->fsum(), c->kcfg.link_block, c->stream),
-                          "link kernel launch");
-    if (s) return s;
-    if (timed) hipEventRecord(e1, c->stream);
-    s = c->hip(lbm::launch_bulk(c->p.storage, g, ph, A, B, c->mask(),
-                                c->ws + c->lay.off_uin, c->side(), c->bank(c->step + 1),
-                                2 * c->p.n_obj, c->bulk_config(), c->stream), "bulk kernel launch");
-    if (s) return s;
+    const lbm::Side sd = c->side_par(c->dpar);
+    lbm_status s;
+    if (c->kcfg.bulk_fused) {
+        // links inside the bulk kernel: the link interval of the timing is empty
+        if (timed) hipEventRecord(e1, c->stream);
+        const lbm::Reduce red = c->reduce();
+        const lbm::FuseArgs fa{c->links(), red.wpart, red.wobj, c->bank(c->step), c->fsum()};
+        s = c->hip(lbm::launch_bulk_fused(c->p.storage, g, ph, A, B, c->mask(), c->ws + c->lay.off_uin, sd, fa,
+                                          c->bank(c->step + 1), 2 * c->p.n_obj, c->bulk_config(), c->stream),
+                   "fused bulk kernel launch");
+        if (s) return s;
+    } else {
+        s = c->hip(lbm::launch_link(c->p.storage, g, ph, c->links(), sd, c->reduce(), c->bank(c->step), c->fsum(),
+                                    c->kcfg.link_block, c->stream),
+                   "link kernel launch");
+        if (s) return s;
+        if (timed) hipEventRecord(e1, c->stream);
+        s = c->hip(lbm::launch_bulk(c->p.storage, g, ph, A, B, c->mask(), c->ws + c->lay.off_uin, sd,
+                                    c->bank(c->step + 1), 2 * c->p.n_obj, c->bulk_config(), c->stream),
+                   "bulk kernel launch");
+        if (s) return s;
+    }
     if (timed) hipEventRecord(e2, c->stream);
+    c->dpar ^= 1;
     ++c->step;
     ++c->nsum;
     return LBM_OK;
@@ -439,6 +459,7 @@ lbm_status build_graph(lbm_ctx *c)
     }
     void *start = c->cur;
     const int64_t step0 = c->step, nsum0 = c->nsum;
+    const int dpar0 = c->dpar;
     hipGraph_t graph = nullptr;
     hipStream_t user = c->stream;
     c->stream = c->cap_stream;
@@ -454,6 +475,7 @@ lbm_status build_graph(lbm_ctx *c)
     // capture only records; restore the host-side counters
     c->step = step0;
     c->nsum = nsum0;
+    c->dpar = dpar0;
     if (c->cur != start) std::swap(c->cur, c->nxt);
     if (s) {
         if (graph) hipGraphDestroy(graph);
@@ -467,6 +489,7 @@ lbm_status build_graph(lbm_ctx *c)
         return s;
     }
     c->graph_cur = start;
+    c->graph_dpar = dpar0;
     return LBM_OK;
 }
 
@@ -613,6 +636,9 @@ lbm_status lbm_set_geometry(lbm_ctx *c, const uint8_t *mask, int64_t n_links, co
         uwsrc = uwf.data();
     }
     const size_t K = prep.rec.size();
+    // link index of each (node, dir) rank, for the fused bulk kernel
+    std::vector<int32_t> kof(n);
+    for (size_t k = 0; k < n; ++k) kof[prep.li[k]] = (int32_t)k;
     struct Up {
         size_t off;
         const void *src;
@@ -625,6 +651,7 @@ lbm_status lbm_set_geometry(lbm_ctx *c, const uint8_t *mask, int64_t n_links, co
                {c->lay.off_pf, prep.pf.data(), n * 4},
                {c->lay.off_pff, prep.pff.data(), n * 4},
                {c->lay.off_li, prep.li.data(), n * 4},
+               {c->lay.off_kof, kof.data(), kof.size() * 4},
                {c->lay.off_rec, prep.rec.data(), K * 2},
                {c->lay.off_mnode, prep.mnode.data(), K * 4},
                {c->lay.off_pbase, prep.pbase.data(), K * 4},
@@ -645,6 +672,8 @@ lbm_status lbm_set_geometry(lbm_ctx *c, const uint8_t *mask, int64_t n_links, co
         return s;
     c->n_links = n_links;
     c->link_order = prep.order;
+    c->li_ident = true;
+    for (int64_t k = 0; k < n_links && c->li_ident; ++k) c->li_ident = prep.li[k] == k;
     c->colslot.assign(c->p.x_bc == LBM_X_OPEN ? 2 * (size_t)c->p.ny : 0, -1);
     if (c->p.x_bc == LBM_X_OPEN)
         for (int y = 0; y < c->p.ny; ++y)
@@ -660,6 +689,7 @@ lbm_status lbm_set_geometry(lbm_ctx *c, const uint8_t *mask, int64_t n_links, co
     c->have_init = false;
     c->cur = c->ws + c->lay.off_A;
     c->nxt = c->ws + c->lay.off_B;
+    c->dpar = 0;
     c->step = 0;
     c->nsum = 0;
     return LBM_OK;
@@ -743,7 +773,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t n)
     while (n > 0) {
         const int gs = c->kcfg.graph_steps;
         if (n >= gs) {
-            if (!c->gexec || c->graph_cur != c->cur) {
+            if (!c->gexec || c->graph_cur != c->cur || c->graph_dpar != c->dpar) {
                 if ((s = build_graph(c))) return s;
             }
             if ((s = c->hip(hipGraphLaunch(c->gexec, c->stream), "hipGraphLaunch"))) return s;
@@ -964,7 +994,7 @@ lbm_status lbm_get_state(lbm_ctx *c, void *host, size_t bytes)
     const size_t fb = 6 * (size_t)c->p.n_obj * 8;
     if ((s = c->hip(hipMemcpy(h + sizeof hdr + pb, c->force(), fb, hipMemcpyDeviceToHost), "state read")))
         return s;
-    return c->hip(hipMemcpy(h + sizeof hdr + pb + fb, c->ws + c->lay.off_M,
+    return c->hip(hipMemcpy(h + sizeof hdr + pb + fb, c->side().M,
                             (size_t)c->n_moment_nodes * 3 * real_bytes(c->p.storage),
                             hipMemcpyDeviceToHost), "state read");
 }
@@ -988,7 +1018,7 @@ lbm_status lbm_set_state(lbm_ctx *c, const void *host, size_t bytes)
     const size_t fb = 6 * (size_t)c->p.n_obj * 8;
     if ((s = c->hip(hipMemcpy(c->force(), h + sizeof hdr + pb, fb, hipMemcpyHostToDevice), "state write")))
         return s;
-    if ((s = c->hip(hipMemcpy(c->ws + c->lay.off_M, h + sizeof hdr + pb + fb,
+    if ((s = c->hip(hipMemcpy(c->side().M, h + sizeof hdr + pb + fb,
                               (size_t)c->n_moment_nodes * 3 * real_bytes(c->p.storage),
                               hipMemcpyHostToDevice), "state write")))
         return s;
@@ -1025,7 +1055,8 @@ lbm_status lbm_set_kernel_config(lbm_ctx *c, const lbm_kernel_config *cfg)
     if (!c || !cfg) return LBM_E_ARG;
     const int bx = cfg->bulk_block_x;
     if ((bx != 64 && bx != 128 && bx != 256) || (cfg->bulk_store_solid != 0 && cfg->bulk_store_solid != 1) ||
-        (cfg->bulk_xcd != 0 && cfg->bulk_xcd != 1) ||
+        (cfg->bulk_xcd != 0 && cfg->bulk_xcd != 1) || (cfg->bulk_fused != 0 && cfg->bulk_fused != 1) ||
+        (cfg->bulk_fused && bx != 256) ||
         cfg->link_block < 64 || cfg->link_block > 1024 || cfg->link_block % 64 ||
         cfg->graph_steps < 2 || cfg->graph_steps > 1024 || cfg->graph_steps % 2)
         return c->fail(LBM_E_ARG, "lbm_set_kernel_config: unsupported configuration");
@@ -1076,6 +1107,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps_per_trial, lbm_kernel_config *
                 k.bulk_block_x = bx;
                 k.bulk_store_solid = ss;
                 k.bulk_xcd = xo;
+                k.bulk_fused = 0;
                 double ms;
                 if ((s = trial(k, &ms))) break;
                 if (ms < best_ms) best_ms = ms, best = k;
@@ -1088,6 +1120,20 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps_per_trial, lbm_kernel_config *
         if ((s = trial(k, &ms))) break;
         if (ms < best_ms) best_ms = ms, best = k;
     }
+    // links evaluated inside the bulk kernel (256-lane blocks)
+    const lbm_kernel_config unfused = best;
+    for (int ss : {0, 1})
+        for (int xo : {0, 1}) {
+            if (s || (ss && c->p.layout == LBM_LAYOUT_COMPACT)) continue;
+            lbm_kernel_config k = unfused;
+            k.bulk_fused = 1;
+            k.bulk_block_x = 256;
+            k.bulk_store_solid = ss;
+            k.bulk_xcd = xo;
+            double ms;
+            if ((s = trial(k, &ms))) break;
+            if (ms < best_ms) best_ms = ms, best = k;
+        }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     lbm_status r = lbm_set_kernel_config(c, s ? &base : &best);

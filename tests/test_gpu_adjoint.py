@@ -131,6 +131,21 @@ def test_gradient_matches_oracle_complex_step(runs, name, what):
     assert abs(adj - cs) <= 1e-11 * abs(cs)
 
 
+def test_adjoint_under_fused_forward(B):
+    """The forward sweep may run with the links inside the bulk kernel while the
+    recomputation uses the separate link kernel: same trajectory, same gradient."""
+    case = _walled()
+    res = []
+    for fused in (0, 1):
+        lat = B.Lattice(case, storage="f64")
+        B.lbm_set_kernel_config(lat.ctx, B.lbm_kernel_config(256, 0, 256, 16, 0, fused))
+        res.append(lat.adjoint_force(33, 10, 0, (0.3, 1.0), want_state=True))
+        lat.close()
+    assert abs(res[1]["J"] - res[0]["J"]) <= 1e-13 * abs(res[0]["J"])
+    for key in ("dq", "duw", "duin", "dstate"):
+        assert np.abs(res[1][key] - res[0][key]).max() <= 1e-13 * np.abs(res[0][key]).max(), key
+
+
 def test_checkpoint_interval_does_not_change_the_result(B):
     case = _cyl()
     res = []

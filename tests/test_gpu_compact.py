@@ -33,6 +33,12 @@ CASES = {
     "porous_200x64": lambda: _porous(200, 64, 3),    # four
     "cylinder_open": lambda: W.cylinder_channel(nx=150, ny=40, radius=6.2, centre=(40.0, 20.0), re=30.0, seed=2),
     "walled_open": lambda: W.walled_cylinder(140, 20.0, 0.3, 0.6),
+    # no solid node at all (every slot fluid, width a multiple of 64)
+    "no_walls_128x40": lambda: W.Case("wave", 128, 40, False, 0.9,
+                                      init_ux=1e-3 * np.sin(2 * np.pi * np.arange(40)[:, None] / 40 *
+                                                            np.ones((1, 128)))),
+    # one column wide
+    "column_1x42": lambda: W.perturb(W.poiseuille_channel(nx=1, ny_fluid=40, q=0.77, u_top=0.01), seed=2),
 }
 
 
@@ -70,11 +76,11 @@ def test_compact_equals_dense(B, name, storage):
     _same(_run(B, case, storage, "compact", 37, k), _run(B, case, storage, "dense", 37, k))
 
 
-@pytest.mark.parametrize("bx", [64, 128, 256])
+@pytest.mark.parametrize("bx,fused", [(64, 0), (128, 0), (256, 0), (256, 1)])
 @pytest.mark.parametrize("xcd", [0, 1])
-def test_compact_launch_shapes(B, bx, xcd):
+def test_compact_launch_shapes(B, bx, fused, xcd):
     case = CASES["porous_200x64"]()
-    cfg = B.lbm_kernel_config(bx, 0, 256, 16, xcd)
+    cfg = B.lbm_kernel_config(bx, 0, 256, 16, xcd, fused)
     _same(_run(B, case, "f32", "compact", 40, cfg=cfg), _run(B, case, "f32", "dense", 40))
 
 

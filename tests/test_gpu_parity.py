@@ -48,9 +48,12 @@ def force_scale(case, u_ref, nsteps):
     return out
 
 
-def compare(B, case, storage, nsteps, tol_u, tol_f=None, tol_pop=None, chunks=None):
-    lat = B.Lattice(case, storage=storage)
-    print(f"[parity] {case.name} {storage} {nsteps} steps links={lat.n_links}", flush=True)
+def compare(B, case, storage, nsteps, tol_u, tol_f=None, tol_pop=None, chunks=None, layout="dense",
+            autotune=False):
+    lat = B.Lattice(case, storage=storage, layout=layout)
+    if autotune:
+        B.lbm_autotune(lat.ctx, 3)
+    print(f"[parity] {case.name} {storage} {layout} {nsteps} steps links={lat.n_links}", flush=True)
     if chunks:
         for c in chunks:
             lat.step(c)
@@ -116,7 +119,9 @@ def spinning(nx=100, ny=37):
     lambda: small_porous(),
     lambda: spinning(),
     lambda: W.walled_cylinder(160, 15.0, 0.37, 0.61),
-], ids=["channel", "column", "cylinder", "porous", "spinning_ragged", "walled_cylinder"])
+    lambda: small_channel(q=0.5),                 # VIBB at q = 1/2 (branch boundary)
+    lambda: small_channel(q=1.0),                 # wall on the solid node
+], ids=["channel", "column", "cylinder", "porous", "spinning_ragged", "walled_cylinder", "q_half", "q_one"])
 def test_fp64_matches_oracle(B, case):
     compare(B, case(), "f64", 300, tol_u=1e-11, tol_f=1e-10, tol_pop=1e-13)
 
@@ -230,13 +235,18 @@ def test_state_errors_through_abi(B):
 
 # --- full-size workloads, a few steps against the oracle at full size -----------
 
-@pytest.mark.parametrize("which", ["cylinder_2048x512", "porous_8192x2048"])
+@pytest.mark.parametrize("which", ["cylinder_2048x512", "porous_8192x2048", "porous_8192x2048_compact"])
 def test_full_size_workloads_short(B, which):
+    """Full size against the oracle; the compact porous case runs in the layout and
+    the autotuned launch configuration of the benchmark."""
     if which.startswith("cylinder"):
         case, n = W.cylinder_channel(), 20
     else:
         case, n = W.porous_medium(), 3
-    compare(B, case, "f32", n, tol_u=1e-5, tol_f=2e-5)
+    if which.endswith("compact"):
+        compare(B, case, "f32", n, tol_u=1e-5, tol_f=2e-5, layout="compact", autotune=True)
+    else:
+        compare(B, case, "f32", n, tol_u=1e-5, tol_f=2e-5)
 
 
 # --- launch configurations and the autotuner ------------------------------------
@@ -250,26 +260,53 @@ def test_every_kernel_config_gives_the_same_result(B):
     fr = ref.populations()
     _, sr, _ = ref.force()
     ref.close()
-    for bx in (64, 128, 256):
-        for ss in (0, 1):
-            for lb, gs, xo in ((64, 2, 0), (1024, 30, 1)):
-                lat = B.Lattice(case, storage="f32")
-                B.lbm_set_kernel_config(lat.ctx, B.lbm_kernel_config(bx, ss, lb, gs, xo))
-                lat.step(45)
-                assert np.array_equal(lat.populations(), fr), (bx, ss, lb, gs, xo)
-                _, s, _ = lat.force()
-                assert np.abs(s - sr).max() <= 1e-12 * np.abs(sr).max()
-                lat.close()
+    cfgs = [(bx, ss, lb, gs, xo, 0) for bx in (64, 128, 256) for ss in (0, 1)
+            for lb, gs, xo in ((64, 2, 0), (1024, 30, 1))]
+    cfgs += [(256, ss, 256, gs, xo, 1) for ss in (0, 1) for gs, xo in ((2, 0), (16, 1))]
+    for cfg in cfgs:
+        lat = B.Lattice(case, storage="f32")
+        B.lbm_set_kernel_config(lat.ctx, B.lbm_kernel_config(*cfg))
+        lat.step(45)
+        assert np.array_equal(lat.populations(), fr), cfg
+        _, s, _ = lat.force()
+        assert np.abs(s - sr).max() <= 1e-12 * np.abs(sr).max()
+        lat.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_fused_links_with_several_objects(B, storage):
+    """Links evaluated inside the bulk kernel: a walled channel (disc object 0,
+    halfway bounce-back walls object 1; links not in (node, dir) order) gives
+    bitwise the populations of the separate link kernel, every object its force."""
+    case = W.walled_cylinder(200, 20.0, 0.41, 0.27)
+    k = 14 if storage == "f16" else 0
+    ref = B.Lattice(case, storage=storage, dev_scale_log2=k)
+    ref.step(61)
+    for xo in (0, 1):
+        lat = B.Lattice(case, storage=storage, dev_scale_log2=k)
+        B.lbm_set_kernel_config(lat.ctx, B.lbm_kernel_config(256, 1, 256, 16, xo, 1))
+        lat.step(61)
+        assert np.array_equal(lat.populations(), ref.populations())
+        for o in range(case.n_obj):
+            la, sa, na = lat.force(o)
+            lb_, sb, nb = ref.force(o)
+            assert na == nb == 61
+            assert np.abs(sa - sb).max() <= 1e-12 * np.abs(sb).max()
+            assert np.abs(la - lb_).max() <= 1e-12 * np.abs(lb_).max()
+        lat.close()
+    ref.close()
 
 
 def test_invalid_kernel_config_is_rejected(B):
     lat = B.Lattice(small_cylinder(64, 32, 4.0), storage="f32")
-    for bad in ((96, 0, 256, 16), (256, 2, 256, 16), (256, 0, 100, 16), (256, 0, 256, 3), (256, 0, 256, 16, 2)):
+    for bad in ((96, 0, 256, 16), (256, 2, 256, 16), (256, 0, 100, 16), (256, 0, 256, 3), (256, 0, 256, 16, 2),
+                (128, 0, 256, 16, 0, 1), (256, 0, 256, 16, 0, 2)):
         with pytest.raises(B.LbmError) as e:
             B.lbm_set_kernel_config(lat.ctx, B.lbm_kernel_config(*bad))
         assert e.value.status == B.LBM_E_ARG
     assert B.lbm_get_kernel_config(lat.ctx).as_dict() == dict(bulk_block_x=256, bulk_store_solid=0,
-                                                             link_block=256, graph_steps=16, bulk_xcd=0)
+                                                             link_block=256, graph_steps=16, bulk_xcd=0,
+                                                             bulk_fused=0)
     lat.close()
 
 
