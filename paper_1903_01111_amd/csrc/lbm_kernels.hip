@@ -397,13 +397,13 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
             if (lk & bit) a[i] = lds_l[wv][lo + popc32(lk & (bit - 1u))];
         }
     } else {
+        // a node's links are consecutive L entries in direction order: walk them
         const T *Lv = static_cast<const T *>(side.L);
-        constexpr int OPPI[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+        constexpr int OPPD[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+        int32_t li = lbase;
 #pragma unroll
-        for (int i = 1; i < 9; ++i) {
-            const uint32_t bit = 1u << (OPPI[i] - 1);
-            if (lk & bit) a[i] = Lv[lbase + popc32(lk & (bit - 1u))];
-        }
+        for (int d = 1; d < 9; ++d)
+            if (lk & (1u << (d - 1))) a[OPPD[d]] = Lv[li++];
     }
     // deposited populations of this node (side record): exclusive prefix -> first P entry
     const uint32_t cnt = (uint32_t)popc32(rec >> 8) << 16;
@@ -529,12 +529,10 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
         lds_m[wv][3 * ls] = drho;
         lds_m[wv][3 * ls + 1] = ux;
         lds_m[wv][3 * ls + 2] = uy;
-        const int lp = (int)(exc >> 16);
+        int lp = (int)(exc >> 16);
 #pragma unroll
-        for (int d = 1; d < 9; ++d) {
-            const uint32_t bit = 1u << (d + 7);
-            if (rec & bit) lds_p[wv][lp + popc32((rec >> 8) & ((1u << (d - 1)) - 1u))] = C::st(f[d], ph.scale);
-        }
+        for (int d = 1; d < 9; ++d)
+            if (rec & (1u << (d + 7))) lds_p[wv][lp++] = C::st(f[d], ph.scale);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
