@@ -326,3 +326,78 @@ def test_autotune_restores_the_state(B):
     assert na == nb == 20 and np.abs(sa - sb).max() <= 1e-12 * np.abs(sb).max()
     a.close()
     b.close()
+
+
+# --- curved walls: cylindrical Couette convergence on the GPU -------------------
+
+def test_cylindrical_couette_second_order_on_gpu(B):
+    """FP64 library against u_theta(r) of circular Couette flow at L = 48 .. 384,
+    1.5 diffusive times (see the oracle's test of the same flow): second order.
+    Diffusive scaling, wall speed U = 0.48 / L: at a fixed U the compressibility
+    error (order Ma^2) and the slow mass drift of VIBB on curved walls do not shrink
+    with L and flatten the error near 1e-4 from L = 192 on."""
+    errs = []
+    for L in (48, 96, 192, 384):
+        cx, cy, r1, r2, U = L / 2 + 0.13, L / 2 - 0.41, L / 4.8, L / 2.4, 0.48 / L
+        om = U / r1
+        case = W.Case("cyl_couette", L, L, False, 0.8, n_obj=2,
+                      prims=[W.Prim(W.PRIM_DISC, cx=cx, cy=cy, r=r1, omega=om, obj=0),
+                             W.Prim(W.PRIM_RING, cx=cx, cy=cy, r=r2, obj=1)])
+        lat = B.Lattice(case, storage="f64")
+        n = int(round(1.5 * (r2 - r1) ** 2 / ((case.tau - 0.5) / 3)))
+        lat.step(n)
+        _, ux, uy = lat.moments()
+        fl = lat.mask == 0
+        lat.close()
+        yy, xx = np.mgrid[0:L, 0:L]
+        dx, dy = xx - cx, yy - cy
+        r = np.hypot(dx, dy)
+        ut = om * r1 ** 2 * (r2 ** 2 / r - r) / (r2 ** 2 - r1 ** 2)
+        ex, ey = -dy / r * ut, dx / r * ut
+        errs.append(float(np.sqrt(((ux - ex) ** 2 + (uy - ey) ** 2)[fl].sum() / (ex ** 2 + ey ** 2)[fl].sum())))
+    orders = [float(np.log2(errs[k] / errs[k + 1])) for k in range(3)]
+    print(f"[couette] errors {errs} orders {orders}", flush=True)
+    assert min(orders) >= 1.8, (errs, orders)
+
+
+# --- the kernels never read a solid slot of the populations ----------------------
+
+@pytest.mark.parametrize("ss", [0, 1])
+def test_solid_slots_are_never_read(B, ss):
+    """NaN in every solid (and padding) slot of the state: the run must stay finite
+    and equal bitwise to the run with zeros there (links feed the cut directions)."""
+    case = small_porous(150, 70, seed=9)
+    runs = []
+    for poison in (False, True):
+        lat = B.Lattice(case, storage="f32")
+        B.lbm_set_kernel_config(lat.ctx, B.lbm_kernel_config(256, ss, 256, 16, 0, 0))
+        if poison:
+            pitch, plane, elem = B.lbm_state_layout(lat.ctx)
+            buf = B.lbm_get_state(lat.ctx)
+            planes = buf[16:16 + 9 * plane * elem].view(np.float32).reshape(9, plane)
+            solid = np.ones((case.ny, pitch), bool)
+            solid[:, :case.nx] = lat.mask != 0
+            planes[:, :case.ny * pitch][:, solid.ravel()] = np.nan
+            B.lbm_set_state(lat.ctx, buf)
+        lat.step(40)
+        runs.append(lat.populations())
+        lat.close()
+    assert np.isfinite(runs[1]).all()
+    assert np.array_equal(runs[0], runs[1])
+
+
+def test_host_arrays_are_not_retained(B):
+    """lbm_set_geometry copies its inputs: scribbling over the caller's arrays after
+    the call changes nothing."""
+    case = small_cylinder(96, 48, 6.1)
+    ref = B.Lattice(case, storage="f32")
+    ref.step(30)
+    lat = B.Lattice(case, storage="f32")
+    rng = np.random.default_rng(0)
+    for a in (lat.mask, lat.node, lat.dir, lat.q, lat.uw, lat.obj):
+        if a is not None:
+            a[...] = rng.integers(0, 7, a.shape).astype(a.dtype)
+    lat.step(30)
+    assert np.array_equal(lat.populations(), ref.populations())
+    lat.close()
+    ref.close()
