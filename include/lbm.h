@@ -146,13 +146,17 @@ lbm_status lbm_check_geometry(const lbm_params *p, const uint8_t *mask, int64_t 
  * Lattice context.
  * ------------------------------------------------------------------------- */
 
+/* Most links one lattice (or one batch, summed over its instances) can hold: the
+ * bulk kernel addresses the link values with 32-bit byte offsets. */
+#define LBM_MAX_LINKS ((int64_t)1 << 28)
+
 /* Device bytes the context needs for params and up to max_links links, or 0 if
- * params are invalid. */
+ * params are invalid or max_links is outside [0, LBM_MAX_LINKS]. */
 size_t lbm_workspace_bytes(const lbm_params *p, int64_t max_links);
 
 /* Creates a context over a device workspace of at least
  * lbm_workspace_bytes(p, max_links) bytes (256-byte aligned; the caller owns it).
- * max_links is read from the workspace size.  Launches nothing.
+ * max_links is read from the workspace size (at most LBM_MAX_LINKS).  Launches nothing.
  * Errors: LBM_E_ARG, LBM_E_NOMEM, LBM_E_DEVICE (no GPU). */
 lbm_status lbm_create(const lbm_params *p, void *workspace, size_t bytes, lbm_ctx **out);
 

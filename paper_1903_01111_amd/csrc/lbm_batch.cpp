@@ -213,6 +213,14 @@ bool batch_params_ok(int32_t n, const lbm_params *p, const int64_t *max_links, s
         *why = "need n >= 1 instances, params and link capacities";
         return false;
     }
+    int64_t total_links = 0;
+    for (int i = 0; i < n; ++i) {
+        if (max_links[i] >= 0) total_links += max_links[i];
+        if (total_links > LBM_MAX_LINKS) {
+            *why = "the link capacities sum to more than LBM_MAX_LINKS";
+            return false;
+        }
+    }
     for (int i = 0; i < n; ++i) {
         std::string w;
         if (!params_ok(&p[i], &w)) {
@@ -352,15 +360,17 @@ lbm_status enqueue_batch_step(lbm_batch *b)
 {
     const lbm::Side side = b->side_global();
     lbm::Reduce red{reinterpret_cast<double2 *>(b->ws + b->off_wpart), reinterpret_cast<int32_t *>(b->ws + b->off_wobj)};
+    // the force reduction over the link kernel's partials runs in the bulk launch
+    lbm::ForceReduce fr{};
     lbm_status s = b->hip(lbm::launch_link(b->storage, b->grid(0), b->phys(0), b->links(), side, red,
-                                           b->bank(b->step), b->fsum(), 256, b->stream),
+                                           b->bank(b->step), b->fsum(), 256, b->stream, &fr),
                           "batch link launch");
     if (s) return s;
     s = b->hip(lbm::launch_bulk_batch(b->storage, reinterpret_cast<const lbm::BatchInst *>(b->ws + b->off_insts),
                                       reinterpret_cast<const lbm::BatchTile *>(b->ws + b->off_tiles), b->ntiles,
                                       b->phys(0), b->cur, b->nxt, reinterpret_cast<const lbm::mask_t *>(b->ws + b->off_mask),
                                       b->ws + b->off_uin, side, b->bank(b->step + 1), (int32_t)(2 * b->n_obj),
-                                      b->x_bc == LBM_X_OPEN, b->forced, b->stream),
+                                      b->x_bc == LBM_X_OPEN, b->forced, b->stream, fr),
                "batch bulk launch");
     if (s) return s;
     std::swap(b->cur, b->nxt);

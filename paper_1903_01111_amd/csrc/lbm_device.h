@@ -130,6 +130,55 @@ __device__ __forceinline__ void st_el(T *__restrict__ base, int32_t e, T v)
 {
     *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + (uint64_t)((uint32_t)e * (uint32_t)sizeof(T))) = v;
 }
+// The same with the byte offset given (an array smaller than 4 GiB at a
+// wavefront-uniform base).
+template <class T>
+__device__ __forceinline__ T ld_at(const T *__restrict__ base, uint32_t byte_off)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + (uint64_t)byte_off);
+}
+
+// A population plane as a raw buffer resource (base and size in scalar
+// registers; 32-bit data format, the gfx9 encoding of the fourth word).  Stores
+// through it take a 32-bit vector byte offset and need no vector address
+// arithmetic per plane; offsets at or past `bytes` are dropped by the hardware.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)bytes, 0x00020000);
+}
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void st_buf(__amdgpu_buffer_rsrc_t r, uint32_t off, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void st_buf(__amdgpu_buffer_rsrc_t r, uint32_t off, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void st_buf(__amdgpu_buffer_rsrc_t r, uint32_t off, __half v)
+{
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void st_buf(__amdgpu_buffer_rsrc_t r, uint32_t off, uint16_t v)
+{
+    __builtin_amdgcn_raw_buffer_store_b16(v, r, (int)off, 0, 0);
+}
+
+// Load of a wavefront-uniform element of a table that no kernel writes while it
+// runs (segment bases, fluid masks): read through the constant address space it
+// always takes the scalar cache, whatever stores, atomics or barriers come
+// before it in the kernel.
+template <class T>
+__device__ __forceinline__ T ld_const(const T *p)
+{
+    return *(const __attribute__((address_space(4))) T *)p;
+}
+// A segment-base record field by field (a record load of only the fields used
+// can become 12 bytes wide, which the scalar unit has no form for).
+__device__ __forceinline__ SegBase ld_seg(const SegBase *p)
+{
+    return SegBase{ld_const(&p->flagged), ld_const(&p->links), ld_const(&p->pops), ld_const(&p->fluid)};
+}
 
 // Inclusive prefix sum over the 64 lanes of a wavefront with DPP row shifts and
 // row broadcasts (all lanes must be active).

@@ -95,6 +95,16 @@ struct Reduce {
     int32_t *wobj;
 };
 
+// A pending force reduction: nw wavefront partials (wpart, wobj) summed per object
+// into bank and fsum.  nw = 0: nothing to do.
+struct ForceReduce {
+    const double2 *wpart;
+    const int32_t *wobj;
+    int64_t nw;
+    double *bank;
+    double *fsum;
+};
+
 // Launch shape of the bulk kernel (chosen by the autotuner).
 struct BulkConfig {
     int32_t block_x;      // 64, 128 or 256 lanes along x; 256/block_x rows
@@ -115,14 +125,19 @@ struct FuseArgs {
 };
 
 // Link values of one step into side.L and, unless force_bank is null, the force
-// of every object added to force_bank and force_sum.
+// of every object added to force_bank and force_sum.  With defer non-null the
+// reduction of the per-wavefront partials is not launched but described in
+// *defer, for the bulk launch that follows (nw = 0 when there is none).
 hipError_t launch_link(int storage, const Grid &g, const Phys &ph, const Links &L, const Side &side,
                        const Reduce &red, double *force_bank, double *force_sum, int block,
-                       hipStream_t s);
+                       hipStream_t s, ForceReduce *defer = nullptr);
 
+// One bulk step; fr is a reduction deferred by launch_link, done by the first
+// blocks of the launch.
 hipError_t launch_bulk(int storage, const Grid &g, const Phys &ph, const void *A, void *B,
                        const mask_t *mask, const void *uin, const Side &side, double *zero_bank,
-                       int32_t n_zero, const BulkConfig &cf, hipStream_t s);
+                       int32_t n_zero, const BulkConfig &cf, hipStream_t s,
+                       const ForceReduce &fr = ForceReduce{nullptr, nullptr, 0, nullptr, nullptr});
 
 // One whole step with the links evaluated inside the bulk kernel (cf.fused): the
 // bulk launch, then the force reduction over its segment partials.  side.M/P
@@ -148,7 +163,7 @@ constexpr int BATCH_BX = 256;  // lanes along x per batched block (one row)
 hipError_t launch_bulk_batch(int storage, const BatchInst *insts, const BatchTile *tiles, int64_t ntiles,
                              const Phys &ph, const void *A, void *B, const mask_t *mask, const void *uin,
                              const Side &side, double *zero_bank, int32_t n_zero, bool open, bool force,
-                             hipStream_t s);
+                             hipStream_t s, const ForceReduce &fr);
 
 // Rebuilds the deposited populations P (and, with moments, M) of every flagged
 // node from the populations in A: after initialisation or a restored checkpoint.

@@ -144,22 +144,41 @@ __global__ __launch_bounds__(1024) void link_kernel(Grid g, Phys ph, Links L, Si
 }
 
 // Sums the wavefront partials of the link kernel per object (they are in object
-// order) into this step's force bank and the running sum.  Each lane walks
-// REDUCE_CHUNK consecutive partials; lanes whose open segment is the same object
-// combine it across the wavefront before the atomic.
+// order) into this step's force bank and the running sum.  A block of 256 lanes
+// takes 256 * CHUNK consecutive partials: each lane sums its chunk per object,
+// a wavefront whose lanes end on one object adds them up across its lanes, and a
+// block whose four wavefronts end on one object adds them up in LDS, so that the
+// common case costs one atomic per block and address (thousands of atomics on
+// the same address would serialise).  Runs of other objects are added where
+// they close.  The pointers come from distinct __restrict__ kernel arguments:
+// the atomics then provably leave the rest of a kernel's inputs untouched, so
+// that its wavefront-uniform loads can still use the scalar cache.
 constexpr int REDUCE_CHUNK = 16;
 
-__global__ __launch_bounds__(256) void force_reduce_kernel(const double2 *__restrict__ wpart,
-                                                           const int32_t *__restrict__ wobj, int64_t nw,
-                                                           double *__restrict__ bank,
-                                                           double *__restrict__ fsum)
+__device__ __forceinline__ void add_force(double *__restrict__ bank, double *__restrict__ fsum, int o,
+                                          double ax, double ay)
 {
-    const int64_t k0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * REDUCE_CHUNK;
+    unsafeAtomicAdd(&bank[2 * o], ax);
+    unsafeAtomicAdd(&bank[2 * o + 1], ay);
+    unsafeAtomicAdd(&fsum[2 * o], ax);
+    unsafeAtomicAdd(&fsum[2 * o + 1], ay);
+}
+
+// Every thread of the 256-thread block calls it (it synchronises the block).
+template <int CHUNK>
+__device__ __forceinline__ void force_reduce_block(const double2 *__restrict__ wpart,
+                                                   const int32_t *__restrict__ wobj, int64_t nw,
+                                                   double *__restrict__ bank, double *__restrict__ fsum,
+                                                   int64_t block, int tid)
+{
+    __shared__ int s_obj[4];
+    __shared__ double s_f[4][2];
+    const int64_t k0 = (block * 256 + tid) * CHUNK;
     // all loads of the chunk first (one round trip), then the segmented sum
-    int ob[REDUCE_CHUNK];
-    double2 pv[REDUCE_CHUNK];
+    int ob[CHUNK];
+    double2 pv[CHUNK];
 #pragma unroll
-    for (int k = 0; k < REDUCE_CHUNK; ++k) {
+    for (int k = 0; k < CHUNK; ++k) {
         const bool in = k0 + k < nw;
         ob[k] = in ? wobj[k0 + k] : -1;
         pv[k] = in ? wpart[k0 + k] : make_double2(0.0, 0.0);
@@ -167,16 +186,11 @@ __global__ __launch_bounds__(256) void force_reduce_kernel(const double2 *__rest
     int cur = -1;
     double ax = 0.0, ay = 0.0;
 #pragma unroll
-    for (int k = 0; k < REDUCE_CHUNK; ++k) {
+    for (int k = 0; k < CHUNK; ++k) {
         const int o = ob[k];
         if (o < 0) continue;
         if (o != cur) {
-            if (cur >= 0) {
-                unsafeAtomicAdd(&bank[2 * cur], ax);
-                unsafeAtomicAdd(&bank[2 * cur + 1], ay);
-                unsafeAtomicAdd(&fsum[2 * cur], ax);
-                unsafeAtomicAdd(&fsum[2 * cur + 1], ay);
-            }
+            if (cur >= 0) add_force(bank, fsum, cur, ax, ay);
             cur = o;
             ax = ay = 0.0;
         }
@@ -186,21 +200,67 @@ __global__ __launch_bounds__(256) void force_reduce_kernel(const double2 *__rest
     int top = cur;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) top = max(top, __shfl_xor(top, off));
-    if (__all(cur == top || cur < 0)) {
+    const bool uni = __all(cur == top || cur < 0);
+    if (uni) {
+        // top < 0: the wavefront holds nothing
         if (cur < 0) ax = ay = 0.0;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
             ax += __shfl_xor(ax, off);
             ay += __shfl_xor(ay, off);
         }
-        cur = (threadIdx.x & 63) == 0 ? top : -1;
+    } else if (cur >= 0) {
+        add_force(bank, fsum, cur, ax, ay);
     }
-    if (cur >= 0) {
-        unsafeAtomicAdd(&bank[2 * cur], ax);
-        unsafeAtomicAdd(&bank[2 * cur + 1], ay);
-        unsafeAtomicAdd(&fsum[2 * cur], ax);
-        unsafeAtomicAdd(&fsum[2 * cur + 1], ay);
+    const int wv = tid >> 6;
+    if ((tid & 63) == 0) {
+        s_obj[wv] = uni ? top : -1;
+        s_f[wv][0] = ax;
+        s_f[wv][1] = ay;
     }
+    __syncthreads();
+    if (tid == 0) {
+        int o0 = -1;
+        bool same = true;
+        for (int w = 0; w < 4; ++w) {
+            const int o = s_obj[w];
+            if (o < 0) continue;
+            if (o0 < 0) o0 = o;
+            same = same && o == o0;
+        }
+        if (same && o0 >= 0) {
+            double sx = 0.0, sy = 0.0;
+            for (int w = 0; w < 4; ++w)
+                if (s_obj[w] >= 0) sx += s_f[w][0], sy += s_f[w][1];
+            add_force(bank, fsum, o0, sx, sy);
+        } else if (!same) {
+            for (int w = 0; w < 4; ++w)
+                if (s_obj[w] >= 0) add_force(bank, fsum, s_obj[w], s_f[w][0], s_f[w][1]);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void force_reduce_kernel(const double2 *__restrict__ wpart,
+                                                           const int32_t *__restrict__ wobj, int64_t nw,
+                                                           double *__restrict__ bank,
+                                                           double *__restrict__ fsum)
+{
+    force_reduce_block<REDUCE_CHUNK>(wpart, wobj, nw, bank, fsum, blockIdx.x, threadIdx.x);
+}
+
+// The reduction folded into the first blocks of the bulk kernel that follows the
+// link kernel (block b, thread tid of 256; uniform per block).  A chunk of four
+// partials per lane keeps the bulk kernel's register count (and occupancy) as
+// it is; a longer one would raise it for every block.
+constexpr int FOLD_CHUNK = 4;
+
+__device__ __forceinline__ void force_reduce_part(const double2 *__restrict__ wpart,
+                                                  const int32_t *__restrict__ wobj, int64_t nw,
+                                                  double *__restrict__ bank, double *__restrict__ fsum,
+                                                  int64_t b, int tid)
+{
+    if (nw <= 0 || b * 256 * FOLD_CHUNK >= nw) return;
+    force_reduce_block<FOLD_CHUNK>(wpart, wobj, nw, bank, fsum, b, tid);
 }
 
 // ---------------------------------------------------------------------------
@@ -234,8 +294,11 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
     if (y >= g.ny || (x >> 6) >= (g.pitch >> 6)) return;
     const bool inside = x < g.nx;
     const int32_t row = y * g.pitch;
-    const mask_t m = inside ? mask[row + x] : MASK_SOLID;
+    const mask_t m = inside ? ld_el(mask, row + x) : MASK_SOLID;
     const int64_t P = g.plane;
+    constexpr uint32_t S = sizeof(T);
+    // the planes of B are written through buffer resources (plane < 4 GiB)
+    const uint32_t pbytes = (uint32_t)(P * S);
     // The nine pulls f_i(x, t+1) = f+_i(x - e_i, t) are issued before the node
     // type and the link records are known, so that their latency overlaps the
     // record lookups; values of solid lanes, and those of directions whose
@@ -254,8 +317,8 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
     const int32_t rm = ym * g.pitch;
     const int32_t rp = yp * g.pitch;
     const int lane = threadIdx.x & 63;
-    // element offsets of the nine pull sources and of the node itself (own)
-    int32_t o[9], own, own_in = row, own_out = row + g.nx - 1;
+    // byte offsets in a plane of the nine pull sources and of the node itself (own)
+    uint32_t o[9], own, own_in = (uint32_t)row * S, own_out = (uint32_t)(row + g.nx - 1) * S;
     if (CMP) {
         // compact layout: the fluid rank of (x, r) for the rows r = y-1, y, y+1 is the
         // fluid base of the wavefront's segment in that row plus the fluid lanes below
@@ -266,16 +329,16 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
         const int sx = __builtin_amdgcn_readfirstlane(x >> 6);
         const int yu = __builtin_amdgcn_readfirstlane(y);
         const int rows3[3] = {yu == 0 ? g.ny - 1 : yu - 1, yu, yu == g.ny - 1 ? 0 : yu + 1};
-        const int32_t last = (int32_t)(P - 1);
-        int32_t rk[3], lf[3], rt[3];
+        const uint32_t last = (uint32_t)(P - 1) * S;
+        uint32_t rk[3], lf[3], rt[3];
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             const int32_t sg = rows3[r] * nsr + sx;
-            const uint64_t fm = g.fmask[sg];
-            rk[r] = (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(fm >> 32),
-                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)fm, (uint32_t)g.fseg[sg].fluid));
-            lf[r] = rk[r] > 0 ? rk[r] - 1 : 0;
-            const int32_t q = rk[r] + (int32_t)((fm >> lane) & 1ull);
+            const uint64_t fm = ld_const(g.fmask + sg);
+            rk[r] = S * __builtin_amdgcn_mbcnt_hi((uint32_t)(fm >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)fm, (uint32_t)ld_const(&g.fseg[sg].fluid)));
+            lf[r] = (rk[r] > S ? rk[r] : S) - S;
+            const uint32_t q = rk[r] + S * (uint32_t)((fm >> lane) & 1ull);
             rt[r] = q < last ? q : last;
         }
         if (!OPEN) {
@@ -285,12 +348,13 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
 #pragma unroll
                 for (int r = 0; r < 3; ++r) {
                     const int32_t sg = rows3[r] * nsr + nsr - 1;
-                    lf[r] = g.fseg[sg].fluid + (int32_t)__popcll(g.fmask[sg] & ((1ull << ((g.nx - 1) & 63)) - 1ull));
+                    lf[r] = S * (uint32_t)(ld_const(&g.fseg[sg].fluid) +
+                                            (int32_t)__popcll(ld_const(g.fmask + sg) & ((1ull << ((g.nx - 1) & 63)) - 1ull)));
                 }
             }
             if (sx == nsr - 1 && lane == ((g.nx - 1) & 63)) {
 #pragma unroll
-                for (int r = 0; r < 3; ++r) rt[r] = g.fseg[rows3[r] * nsr].fluid;
+                for (int r = 0; r < 3; ++r) rt[r] = S * (uint32_t)ld_const(&g.fseg[rows3[r] * nsr].fluid);
             }
         } else {
             own_in = lf[1];   // (0, y), written by the lane x = 1 (both fluid)
@@ -307,22 +371,25 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
         o[7] = rt[2];
         o[8] = lf[2];
     } else {
-        own = row + x;
-        o[0] = row + xc;
-        o[1] = row + xm;
-        o[2] = rm + xc;
-        o[3] = row + xp;
-        o[4] = rp + xc;
-        o[5] = rm + xm;
-        o[6] = rm + xp;
-        o[7] = rp + xp;
-        o[8] = rp + xm;
+        own = (uint32_t)(row + x) * S;
+        o[0] = (uint32_t)(row + xc) * S;
+        o[1] = (uint32_t)(row + xm) * S;
+        o[2] = (uint32_t)(rm + xc) * S;
+        o[3] = (uint32_t)(row + xp) * S;
+        o[4] = (uint32_t)(rp + xc) * S;
+        o[5] = (uint32_t)(rm + xm) * S;
+        o[6] = (uint32_t)(rm + xp) * S;
+        o[7] = (uint32_t)(rp + xp) * S;
+        o[8] = (uint32_t)(rp + xm) * S;
     }
     T a[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) a[i] = ld_el(A + i * P, o[i]);
+    for (int i = 0; i < 9; ++i) a[i] = ld_at(A + i * P, o[i]);
+    // keep the pulls ahead of everything that waits for the mask word (the
+    // scheduler would otherwise hoist the ballot below and expose its latency)
+    __builtin_amdgcn_sched_barrier(0);
     const int32_t seg = __builtin_amdgcn_readfirstlane(y * (g.pitch >> 6) + (x >> 6));
-    const SegBase sb = side.seg[seg];
+    const SegBase sb = ld_seg(side.seg + seg);
     if (FUSE) {
         // the wavefront's links are entries [lw, lw + nl) of the (node, dir) order
         // (segment bases; no need to wait for the mask words): one per lane,
@@ -330,7 +397,7 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
         // flight, handed to the node lanes through LDS; their force goes to the
         // segment's partial
         const int32_t lw = sb.links;
-        const int nl = side.seg[seg + 1].links - lw;
+        const int nl = ld_const(&side.seg[seg + 1].links) - lw;
         const Links &L = fa->L;
         double fx = 0.0, fy = 0.0;
         int obj = -1;
@@ -376,7 +443,7 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
     }
     const uint64_t flagged = __ballot((m & MASK_SIDE) != 0);
     const int32_t slot = sb.flagged + (int32_t)__popcll(flagged & ((1ull << lane) - 1ull));
-    const uint32_t rec = (m & MASK_SIDE) ? side.rec[slot] : 0u;
+    const uint32_t rec = (m & MASK_SIDE) ? ld_el(side.rec, slot) : 0u;
     // links of this node (mask bits): exclusive wavefront prefix -> first L entry
     const uint32_t lk = m & MASK_LINKS;
     const uint32_t linc = wave_inclusive_scan((uint32_t)popc32(lk));
@@ -398,12 +465,16 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
         }
     } else {
         // a node's links are consecutive L entries in direction order: walk them
+        // (byte offsets: the link array is smaller than 4 GiB)
         const T *Lv = static_cast<const T *>(side.L);
         constexpr int OPPD[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
-        int32_t li = lbase;
+        uint32_t lb = (uint32_t)lbase * S;
 #pragma unroll
         for (int d = 1; d < 9; ++d)
-            if (lk & (1u << (d - 1))) a[OPPD[d]] = Lv[li++];
+            if (lk & (1u << (d - 1))) {
+                a[OPPD[d]] = ld_at(Lv, lb);
+                lb += S;
+            }
     }
     // deposited populations of this node (side record): exclusive prefix -> first P entry
     const uint32_t cnt = (uint32_t)popc32(rec >> 8) << 16;
@@ -440,7 +511,7 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
             }
         } else if (x == g.nx - 2 && (mask[row + xe] & MASK_SIDE)) {
             // x_e starts the next segment of the row
-            const SegBase sn = side.seg[seg + 1];
+            const SegBase sn = ld_seg(side.seg + seg + 1);
             slot_out = sn.flagged;
             rec_out = side.rec[slot_out];
             pb_out = sn.pops;
@@ -453,7 +524,7 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
             // solid slots of B are never read; storing them keeps every cache line
             // of B fully written (no partial-line writes at solid boundaries)
 #pragma unroll
-            for (int i = 0; i < 9; ++i) st_el(B + i * P, own, T(0));
+            for (int i = 0; i < 9; ++i) st_buf(plane_rsrc(B + i * P, pbytes), own, T(0));
         }
         return;
     }
@@ -517,7 +588,7 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
         f[j] = vj;
     }
 #pragma unroll
-    for (int i = 0; i < 9; ++i) st_el(B + i * P, own, C::st(f[i], ph.scale));
+    for (int i = 0; i < 9; ++i) st_buf(plane_rsrc(B + i * P, pbytes), own, C::st(f[i], ph.scale));
     // deposits for the next link kernel, staged in LDS so that the wavefront
     // writes its contiguous ranges of M and P in full lines.  The post-collision
     // moments are the collision's own (rho, u): with Guo's shift the physical
@@ -561,7 +632,7 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
                 const R eu = R(CX[i]) * ux + R(CY[i]) * uy;
                 const R dp = poly(ev, vsq) - poly(eu, usq);
                 f0[i] = f[i] + w * (dp + drho * dp);
-                st_el(B + i * P, own_in, C::st(f0[i], ph.scale));
+                st_buf(plane_rsrc(B + i * P, pbytes), own_in, C::st(f0[i], ph.scale));
             }
             if (flagged & 1ull) {
                 const int32_t k = sb.flagged;
@@ -580,7 +651,7 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
         if (x == g.nx - 2 && !(me & MASK_SOLID)) {
             // zero-gradient outlet: copy every population of the last fluid column
 #pragma unroll
-            for (int i = 0; i < 9; ++i) st_el(B + i * P, own_out, C::st(f[i], ph.scale));
+            for (int i = 0; i < 9; ++i) st_buf(plane_rsrc(B + i * P, pbytes), own_out, C::st(f[i], ph.scale));
             if (me & MASK_SIDE) {
                 Mv[3 * slot_out] = drho;
                 Mv[3 * slot_out + 1] = ux;
@@ -611,7 +682,10 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
                                                    const mask_t *__restrict__ mask,
                                                    const typename Codec<ST>::R *__restrict__ uin,
                                                    Side side, double *__restrict__ zero_bank,
-                                                   int32_t n_zero, int32_t xcd, double inv_nbx)
+                                                   int32_t n_zero, int32_t xcd, double inv_nbx,
+                                                   const double2 *__restrict__ red_part,
+                                                   const int32_t *__restrict__ red_obj, int64_t red_n,
+                                                   double *__restrict__ red_bank, double *__restrict__ red_sum)
 {
     using R = typename Codec<ST>::R;
     using T = typename Codec<ST>::T;
@@ -623,6 +697,7 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
     const int64_t nb = (int64_t)gridDim.x * gridDim.y;
     const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
     zero_bank_part(zero_bank, n_zero, b, nb, tid);
+    force_reduce_part(red_part, red_obj, red_n, red_bank, red_sum, b, tid);
     // Workgroups go to the 8 XCDs round robin (block b to XCD b mod 8).  With xcd,
     // XCD k takes the k-th contiguous run of tiles in row-major order instead, so
     // the rows a tile pulls from, and the cache lines it shares with the tiles
@@ -687,7 +762,10 @@ __global__ __launch_bounds__(256) void bulk_batch_kernel(const BatchInst *__rest
                                                          const mask_t *__restrict__ mask,
                                                          const typename Codec<ST>::R *__restrict__ uin,
                                                          Side side, double *__restrict__ zero_bank,
-                                                         int32_t n_zero)
+                                                         int32_t n_zero, const double2 *__restrict__ red_part,
+                                                         const int32_t *__restrict__ red_obj, int64_t red_n,
+                                                         double *__restrict__ red_bank,
+                                                         double *__restrict__ red_sum)
 {
     using R = typename Codec<ST>::R;
     using T = typename Codec<ST>::T;
@@ -695,6 +773,7 @@ __global__ __launch_bounds__(256) void bulk_batch_kernel(const BatchInst *__rest
     __shared__ T lds_p[4][8 * 64];
     const int tid = threadIdx.y * BX + threadIdx.x;
     zero_bank_part(zero_bank, n_zero, blockIdx.x, gridDim.x, tid);
+    force_reduce_part(red_part, red_obj, red_n, red_bank, red_sum, blockIdx.x, tid);
     const BatchTile t = tiles[blockIdx.x];
     const BatchInst I = insts[t.inst];
     Phys ph = ph0;
@@ -836,18 +915,23 @@ __global__ __launch_bounds__(MASS_THREADS) void mass_kernel(Grid g, Phys ph,
 
 template <int ST>
 hipError_t link_t(const Grid &g, const Phys &ph, const Links &L, const Side &side, const Reduce &red,
-                  double *bank, double *fsum, int block, hipStream_t s)
+                  double *bank, double *fsum, int block, hipStream_t s, ForceReduce *defer)
 {
+    if (defer) *defer = ForceReduce{red.wpart, red.wobj, 0, bank, fsum};
     if (L.n == 0) return hipSuccess;
     const unsigned blocks = (unsigned)((L.n + block - 1) / block);
     hipLaunchKernelGGL(link_kernel<ST>, dim3(blocks), dim3(block), 0, s, g, ph, L, side, red.wpart,
                        red.wobj, bank, fsum);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !bank) return e;
-    const int64_t nw = (int64_t)blocks * (block / 64);
-    const int64_t lanes = (nw + REDUCE_CHUNK - 1) / REDUCE_CHUNK;
-    hipLaunchKernelGGL(force_reduce_kernel, dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, s,
-                       red.wpart, red.wobj, nw, bank, fsum);
+    const ForceReduce fr{red.wpart, red.wobj, (int64_t)blocks * (block / 64), bank, fsum};
+    if (defer) {
+        *defer = fr;
+        return hipSuccess;
+    }
+    const int64_t lanes = (fr.nw + REDUCE_CHUNK - 1) / REDUCE_CHUNK;
+    hipLaunchKernelGGL(force_reduce_kernel, dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, s, fr.wpart,
+                       fr.wobj, fr.nw, fr.bank, fr.fsum);
     return hipGetLastError();
 }
 
@@ -897,32 +981,36 @@ hipError_t bulk_fused_dispatch(const Grid &g, const Phys &ph, const void *A, voi
 
 template <int ST, bool OPEN, bool FORCE, int BX, bool SS, bool CMP>
 hipError_t bulk_t(const Grid &g, const Phys &ph, const void *A, void *B, const mask_t *mask,
-                  const void *uin, const Side &side, double *zb, int32_t nz, int32_t xcd, hipStream_t s)
+                  const void *uin, const Side &side, double *zb, int32_t nz, int32_t xcd, hipStream_t s,
+                  const ForceReduce &fr)
 {
     using C = Codec<ST>;
     constexpr int BY = 256 / BX;
     dim3 grid((g.nx + BX - 1) / BX, (g.ny + BY - 1) / BY);
+    const int64_t nb = (int64_t)grid.x * grid.y;
+    if (fr.nw > nb * 256 * FOLD_CHUNK) return hipErrorInvalidValue;  // more partials than lanes
     hipLaunchKernelGGL((bulk_kernel<ST, OPEN, FORCE, BX, SS, CMP>), grid, dim3(BX, BY), 0, s, g, ph,
                        static_cast<const typename C::T *>(A), static_cast<typename C::T *>(B), mask,
-                       static_cast<const typename C::R *>(uin), side, zb, nz, xcd, 1.0 / grid.x);
+                       static_cast<const typename C::R *>(uin), side, zb, nz, xcd, 1.0 / grid.x, fr.wpart,
+                       fr.wobj, fr.nw, fr.bank, fr.fsum);
     return hipGetLastError();
 }
 
 template <int ST, bool OPEN, bool FORCE>
 hipError_t bulk_shape(const Grid &g, const Phys &ph, const void *A, void *B, const mask_t *mask,
                       const void *uin, const Side &side, double *zb, int32_t nz, const BulkConfig &cf,
-                      hipStream_t s)
+                      hipStream_t s, const ForceReduce &fr)
 {
     if (g.compact) {
         // no solid slots to store in the compact layout
-        if (cf.block_x == 64) return bulk_t<ST, OPEN, FORCE, 64, false, true>(g, ph, A, B, mask, uin, side, zb, nz, cf.xcd, s);
-        if (cf.block_x == 128) return bulk_t<ST, OPEN, FORCE, 128, false, true>(g, ph, A, B, mask, uin, side, zb, nz, cf.xcd, s);
-        if (cf.block_x == 256) return bulk_t<ST, OPEN, FORCE, 256, false, true>(g, ph, A, B, mask, uin, side, zb, nz, cf.xcd, s);
+        if (cf.block_x == 64) return bulk_t<ST, OPEN, FORCE, 64, false, true>(g, ph, A, B, mask, uin, side, zb, nz, cf.xcd, s, fr);
+        if (cf.block_x == 128) return bulk_t<ST, OPEN, FORCE, 128, false, true>(g, ph, A, B, mask, uin, side, zb, nz, cf.xcd, s, fr);
+        if (cf.block_x == 256) return bulk_t<ST, OPEN, FORCE, 256, false, true>(g, ph, A, B, mask, uin, side, zb, nz, cf.xcd, s, fr);
         return hipErrorInvalidValue;
     }
 #define LBM_BULK_SHAPE(BXV, SSV)                                                                  \
     if (cf.block_x == BXV && cf.store_solid == SSV)                                              \
-        return bulk_t<ST, OPEN, FORCE, BXV, SSV, false>(g, ph, A, B, mask, uin, side, zb, nz, cf.xcd, s);
+        return bulk_t<ST, OPEN, FORCE, BXV, SSV, false>(g, ph, A, B, mask, uin, side, zb, nz, cf.xcd, s, fr);
     LBM_BULK_SHAPE(64, false)
     LBM_BULK_SHAPE(64, true)
     LBM_BULK_SHAPE(128, false)
@@ -936,27 +1024,28 @@ hipError_t bulk_shape(const Grid &g, const Phys &ph, const void *A, void *B, con
 template <int ST>
 hipError_t bulk_dispatch(const Grid &g, const Phys &ph, const void *A, void *B, const mask_t *mask,
                          const void *uin, const Side &side, double *zb, int32_t nz, const BulkConfig &cf,
-                         hipStream_t s)
+                         hipStream_t s, const ForceReduce &fr)
 {
     const bool force = ph.gx != 0.0 || ph.gy != 0.0;
     if (g.x_open)
-        return force ? bulk_shape<ST, true, true>(g, ph, A, B, mask, uin, side, zb, nz, cf, s)
-                     : bulk_shape<ST, true, false>(g, ph, A, B, mask, uin, side, zb, nz, cf, s);
-    return force ? bulk_shape<ST, false, true>(g, ph, A, B, mask, uin, side, zb, nz, cf, s)
-                 : bulk_shape<ST, false, false>(g, ph, A, B, mask, uin, side, zb, nz, cf, s);
+        return force ? bulk_shape<ST, true, true>(g, ph, A, B, mask, uin, side, zb, nz, cf, s, fr)
+                     : bulk_shape<ST, true, false>(g, ph, A, B, mask, uin, side, zb, nz, cf, s, fr);
+    return force ? bulk_shape<ST, false, true>(g, ph, A, B, mask, uin, side, zb, nz, cf, s, fr)
+                 : bulk_shape<ST, false, false>(g, ph, A, B, mask, uin, side, zb, nz, cf, s, fr);
 }
 
 template <int ST, bool OPEN, bool FORCE>
 hipError_t bulk_batch_t(const BatchInst *insts, const BatchTile *tiles, int64_t ntiles, const Phys &ph,
                         const void *A, void *B, const mask_t *mask, const void *uin, const Side &side,
-                        double *zb, int32_t nz, hipStream_t s)
+                        double *zb, int32_t nz, hipStream_t s, const ForceReduce &fr)
 {
     using C = Codec<ST>;
     constexpr int BX = BATCH_BX, BY = 256 / BATCH_BX;
+    if (fr.nw > ntiles * 256 * FOLD_CHUNK) return hipErrorInvalidValue;  // more partials than lanes
     hipLaunchKernelGGL((bulk_batch_kernel<ST, OPEN, FORCE, BX, true>), dim3((unsigned)ntiles), dim3(BX, BY), 0,
                        s, insts, tiles, ph, static_cast<const typename C::T *>(A),
                        static_cast<typename C::T *>(B), mask, static_cast<const typename C::R *>(uin), side,
-                       zb, nz);
+                       zb, nz, fr.wpart, fr.wobj, fr.nw, fr.bank, fr.fsum);
     return hipGetLastError();
 }
 
@@ -964,13 +1053,13 @@ template <int ST>
 hipError_t bulk_batch_dispatch(const BatchInst *insts, const BatchTile *tiles, int64_t ntiles,
                                const Phys &ph, const void *A, void *B, const mask_t *mask, const void *uin,
                                const Side &side, double *zb, int32_t nz, bool open, bool force,
-                               hipStream_t s)
+                               hipStream_t s, const ForceReduce &fr)
 {
     if (open)
-        return force ? bulk_batch_t<ST, true, true>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, s)
-                     : bulk_batch_t<ST, true, false>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, s);
-    return force ? bulk_batch_t<ST, false, true>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, s)
-                 : bulk_batch_t<ST, false, false>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, s);
+        return force ? bulk_batch_t<ST, true, true>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, s, fr)
+                     : bulk_batch_t<ST, true, false>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, s, fr);
+    return force ? bulk_batch_t<ST, false, true>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, s, fr)
+                 : bulk_batch_t<ST, false, false>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, s, fr);
 }
 
 template <int ST>
@@ -986,14 +1075,15 @@ hipError_t refresh_t(const Grid &g, const Phys &ph, const void *A, const Side &s
 }  // namespace
 
 hipError_t launch_link(int storage, const Grid &g, const Phys &ph, const Links &L, const Side &side,
-                       const Reduce &red, double *bank, double *fsum, int block, hipStream_t s)
+                       const Reduce &red, double *bank, double *fsum, int block, hipStream_t s,
+                       ForceReduce *defer)
 {
     if (block < 64 || block > 1024 || block % 64) return hipErrorInvalidValue;
     switch (storage) {
-    case 0: return link_t<0>(g, ph, L, side, red, bank, fsum, block, s);
-    case 1: return link_t<1>(g, ph, L, side, red, bank, fsum, block, s);
-    case 2: return link_t<2>(g, ph, L, side, red, bank, fsum, block, s);
-    case 3: return link_t<3>(g, ph, L, side, red, bank, fsum, block, s);
+    case 0: return link_t<0>(g, ph, L, side, red, bank, fsum, block, s, defer);
+    case 1: return link_t<1>(g, ph, L, side, red, bank, fsum, block, s, defer);
+    case 2: return link_t<2>(g, ph, L, side, red, bank, fsum, block, s, defer);
+    case 3: return link_t<3>(g, ph, L, side, red, bank, fsum, block, s, defer);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1013,27 +1103,28 @@ hipError_t launch_bulk_fused(int storage, const Grid &g, const Phys &ph, const v
 
 hipError_t launch_bulk(int storage, const Grid &g, const Phys &ph, const void *A, void *B,
                        const mask_t *mask, const void *uin, const Side &side, double *zb, int32_t nz,
-                       const BulkConfig &cf, hipStream_t s)
+                       const BulkConfig &cf, hipStream_t s, const ForceReduce &fr)
 {
     switch (storage) {
-    case 0: return bulk_dispatch<0>(g, ph, A, B, mask, uin, side, zb, nz, cf, s);
-    case 1: return bulk_dispatch<1>(g, ph, A, B, mask, uin, side, zb, nz, cf, s);
-    case 2: return bulk_dispatch<2>(g, ph, A, B, mask, uin, side, zb, nz, cf, s);
-    case 3: return bulk_dispatch<3>(g, ph, A, B, mask, uin, side, zb, nz, cf, s);
+    case 0: return bulk_dispatch<0>(g, ph, A, B, mask, uin, side, zb, nz, cf, s, fr);
+    case 1: return bulk_dispatch<1>(g, ph, A, B, mask, uin, side, zb, nz, cf, s, fr);
+    case 2: return bulk_dispatch<2>(g, ph, A, B, mask, uin, side, zb, nz, cf, s, fr);
+    case 3: return bulk_dispatch<3>(g, ph, A, B, mask, uin, side, zb, nz, cf, s, fr);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_bulk_batch(int storage, const BatchInst *insts, const BatchTile *tiles, int64_t ntiles,
                              const Phys &ph, const void *A, void *B, const mask_t *mask, const void *uin,
-                             const Side &side, double *zb, int32_t nz, bool open, bool force, hipStream_t s)
+                             const Side &side, double *zb, int32_t nz, bool open, bool force, hipStream_t s,
+                             const ForceReduce &fr)
 {
-    if (ntiles <= 0) return hipSuccess;
+    if (ntiles <= 0) return fr.nw > 0 ? hipErrorInvalidValue : hipSuccess;
     switch (storage) {
-    case 0: return bulk_batch_dispatch<0>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, open, force, s);
-    case 1: return bulk_batch_dispatch<1>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, open, force, s);
-    case 2: return bulk_batch_dispatch<2>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, open, force, s);
-    case 3: return bulk_batch_dispatch<3>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, open, force, s);
+    case 0: return bulk_batch_dispatch<0>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, open, force, s, fr);
+    case 1: return bulk_batch_dispatch<1>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, open, force, s, fr);
+    case 2: return bulk_batch_dispatch<2>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, open, force, s, fr);
+    case 3: return bulk_batch_dispatch<3>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, open, force, s, fr);
     default: return hipErrorInvalidValue;
     }
 }

@@ -411,13 +411,15 @@ lbm_status lbm_host::enqueue_step_to(lbm_ctx *c, const void *A, void *B, bool ti
                    "fused bulk kernel launch");
         if (s) return s;
     } else {
+        // the force reduction over the link kernel's partials runs in the bulk launch
+        lbm::ForceReduce fr{};
         s = c->hip(lbm::launch_link(c->p.storage, g, ph, c->links(), sd, c->reduce(), c->bank(c->step), c->fsum(),
-                                    c->kcfg.link_block, c->stream),
+                                    c->kcfg.link_block, c->stream, &fr),
                    "link kernel launch");
         if (s) return s;
         if (timed) hipEventRecord(e1, c->stream);
         s = c->hip(lbm::launch_bulk(c->p.storage, g, ph, A, B, c->mask(), c->ws + c->lay.off_uin, sd,
-                                    c->bank(c->step + 1), 2 * c->p.n_obj, c->bulk_config(), c->stream),
+                                    c->bank(c->step + 1), 2 * c->p.n_obj, c->bulk_config(), c->stream, fr),
                    "bulk kernel launch");
         if (s) return s;
     }
@@ -534,7 +536,7 @@ lbm_status lbm_check_geometry(const lbm_params *p, const uint8_t *mask, int64_t 
 size_t lbm_workspace_bytes(const lbm_params *p, int64_t max_links)
 {
     std::string why;
-    if (!params_ok(p, &why) || max_links < 0) return 0;
+    if (!params_ok(p, &why) || max_links < 0 || max_links > LBM_MAX_LINKS) return 0;
     return make_layout(*p, max_links).total;
 }
 
@@ -575,7 +577,7 @@ lbm_status lbm_create(const lbm_params *p, void *workspace, size_t bytes, lbm_ct
         if (make_layout(*p, mid).total <= bytes) lo = mid;
         else hi = mid;
     }
-    const int64_t cap = lo;
+    const int64_t cap = std::min<int64_t>(lo, LBM_MAX_LINKS);
     lbm_ctx *c = new (std::nothrow) lbm_ctx;
     if (!c) {
         g_thread_error = "lbm_create: out of host memory";

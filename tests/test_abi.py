@@ -71,6 +71,16 @@ def test_workspace_grows_with_links_and_precision():
     assert B.lbm_workspace_bytes(p32, 0) >= 2 * 9 * 128 * 37 * 4
 
 
+def test_link_capacity_is_bounded():
+    """The link values are addressed with 32-bit byte offsets: at most
+    LBM_MAX_LINKS links per lattice, and per batch in total."""
+    p = B.make_params(100, 37, storage="f64")
+    assert B.lbm_workspace_bytes(p, B.LBM_MAX_LINKS) > 0
+    assert B.lbm_workspace_bytes(p, B.LBM_MAX_LINKS + 1) == 0
+    assert B.lbm_batch_workspace_bytes([p, p], [B.LBM_MAX_LINKS // 2, B.LBM_MAX_LINKS // 2]) > 0
+    assert B.lbm_batch_workspace_bytes([p, p], [B.LBM_MAX_LINKS // 2, B.LBM_MAX_LINKS // 2 + 1]) == 0
+
+
 def _disc_case(x_open=False):
     return W.Case("d", 24, 20, x_open, 0.7, prims=[W.Prim(W.PRIM_DISC, cx=11.3, cy=9.6, r=4.2)])
 
