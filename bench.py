@@ -38,19 +38,36 @@ def kernel_hash():
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:12]
 
 
-def counter_traffic(layout):
-    """HBM bytes per bulk launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source and population layout; else None."""
+def bulk_kernel_name(kcfg, layout, storage):
+    """Template name of the periodic forced bulk kernel (the porous workload) that a
+    launch configuration runs (None for the fused form)."""
+    if kcfg["bulk_fused"]:
+        return None
+    b = lambda v: "true" if v else "false"
+    st = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}[storage]
+    return (f"void bulk_kernel<{st}, false, true, {kcfg['bulk_block_x']}, {b(kcfg['bulk_store_solid'])}, "
+            f"{b(layout == 'compact')}, {max(kcfg.get('bulk_rows', 1), 1)}>")
+
+
+def counter_traffic(layout, kcfg, storage="f32"):
+    """HBM bytes per launch of the bulk kernel shape kcfg from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source and
+    population layout and holds that shape; else None."""
     if not os.path.exists(COUNTER_SUMMARY):
         return None
     txt = open(COUNTER_SUMMARY).read()
     m = dict(re.findall(r"^(\w+):\s*(\S+)", txt, flags=re.M))
     if m.get("kernel_source_sha256_12") != kernel_hash() or m.get("layout") != layout:
         return None
-    try:
-        return float(m["hbm_bytes_per_bulk_launch"])
-    except (KeyError, ValueError):
-        return None
+    name = bulk_kernel_name(kcfg, layout, storage)
+    for line in txt.splitlines():
+        parts = [p.strip() for p in line[len("variant:"):].split("|")] if line.startswith("variant:") else []
+        if len(parts) >= 4 and parts[0] == name:
+            try:
+                return float(parts[3])
+            except ValueError:
+                return None
+    return None
 
 
 def workload(name):
@@ -380,7 +397,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "bulk (pull + BGK collision)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": counter_traffic(args.layout),
+                     "traffic": counter_traffic(args.layout, cfg.as_dict(), args.storage),
                      "algorithmic_bytes_per_launch": bulk_bytes,
                      "avg_launch_us": round(bulk_avg_s * 1e6, 2)},
         "link_kernel": {"avg_launch_us": round(link_avg_s * 1e6, 2),

@@ -50,7 +50,7 @@ struct lbm_ctx {
     std::vector<int32_t> colslot;
     void *cur = nullptr, *nxt = nullptr;
     int64_t step = 0, nsum = 0;
-    lbm_kernel_config kcfg{256, 0, 256, 16, 0, 0};
+    lbm_kernel_config kcfg{256, 0, 256, 16, 0, 0, 1};
     // deposits (M, P) are double-buffered: dpar selects the pair the links of the
     // next step read; the bulk kernel deposits into the other one
     int dpar = 0;
@@ -93,7 +93,8 @@ struct lbm_ctx {
     }
     lbm::BulkConfig bulk_config() const
     {
-        return lbm::BulkConfig{kcfg.bulk_block_x, kcfg.bulk_store_solid, kcfg.bulk_xcd, kcfg.bulk_fused};
+        return lbm::BulkConfig{kcfg.bulk_block_x, kcfg.bulk_store_solid, kcfg.bulk_xcd, kcfg.bulk_fused,
+                               kcfg.bulk_rows == 2 ? 2 : 1};
     }
     // deposits read with parity p (and written into the other pair)
     lbm::Side side_par(int p) const

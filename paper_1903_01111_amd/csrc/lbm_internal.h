@@ -111,6 +111,7 @@ struct BulkConfig {
     int32_t store_solid;  // lanes of solid nodes store zeros too (full-line writes)
     int32_t xcd;          // contiguous runs of blocks per XCD (see bulk_kernel)
     int32_t fused;        // the bulk kernel evaluates the links of its nodes (no link kernel)
+    int32_t rows;         // row segments per wavefront: 1, or 2 (block_x 256, not fused)
 };
 
 // What the fused bulk kernel needs for the links: link arrays, the per-segment

@@ -273,32 +273,32 @@ __device__ __forceinline__ void force_reduce_part(const double2 *__restrict__ wp
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int popc32(uint32_t v) { return __popc(v); }
 
-// One node per lane of the lattice described by (g, ph, A, B, mask, uin, side);
-// (x, y) is the lane's node, wv its wavefront within the block.
-template <int ST, bool OPEN, bool FORCE, int BX, bool STORE_SOLID, bool CMP = false, bool FUSE = false>
-__device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
-                                          const typename Codec<ST>::T *__restrict__ A,
-                                          typename Codec<ST>::T *__restrict__ B,
-                                          const mask_t *__restrict__ mask,
-                                          const typename Codec<ST>::R *__restrict__ uin,
-                                          const Side &side, int x, int y, int wv,
-                                          typename Codec<ST>::R (*lds_m)[3 * 64],
-                                          typename Codec<ST>::T (*lds_p)[8 * 64],
-                                          const FuseArgs *fa = nullptr,
-                                          typename Codec<ST>::T (*lds_l)[8 * 64] = nullptr)
+// One node per lane of the lattice described by (g, A, mask), in two halves:
+// bulk_issue loads the node's mask word and issues its nine pulls; bulk_finish
+// (with ph, B, uin, side) does the rest once they have arrived.  A wavefront can
+// issue the pulls of a second row segment before it finishes the first.
+template <int ST>
+struct Pulled {
+    typename Codec<ST>::T a[9];  // the pulled populations (stored form)
+    uint32_t own, own_in, own_out;  // byte offsets in a plane: the node, the open columns
+    mask_t m;
+    bool live;  // the wavefront's row segment lies in the lattice (uniform)
+};
+
+template <int ST, bool OPEN, bool CMP>
+__device__ __forceinline__ void bulk_issue(const Grid &g, const typename Codec<ST>::T *__restrict__ A,
+                                           const mask_t *__restrict__ mask, int x, int y, Pulled<ST> &pl)
 {
-    using C = Codec<ST>;
-    using T = typename C::T;
-    using R = typename C::R;
+    using T = typename Codec<ST>::T;
     // a wavefront is one 64-node row segment: leave together if it lies outside
-    if (y >= g.ny || (x >> 6) >= (g.pitch >> 6)) return;
+    pl.live = !(y >= g.ny || (x >> 6) >= (g.pitch >> 6));
+    if (!pl.live) return;
     const bool inside = x < g.nx;
     const int32_t row = y * g.pitch;
     const mask_t m = inside ? ld_el(mask, row + x) : MASK_SOLID;
+    pl.m = m;
     const int64_t P = g.plane;
     constexpr uint32_t S = sizeof(T);
-    // the planes of B are written through buffer resources (plane < 4 GiB)
-    const uint32_t pbytes = (uint32_t)(P * S);
     // The nine pulls f_i(x, t+1) = f+_i(x - e_i, t) are issued before the node
     // type and the link records are known, so that their latency overlaps the
     // record lookups; values of solid lanes, and those of directions whose
@@ -382,12 +382,40 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
         o[7] = (uint32_t)(rp + xp) * S;
         o[8] = (uint32_t)(rp + xm) * S;
     }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) pl.a[i] = ld_at(A + i * P, o[i]);
+    pl.own = own;
+    pl.own_in = own_in;
+    pl.own_out = own_out;
+}
+
+template <int ST, bool OPEN, bool FORCE, int BX, bool STORE_SOLID, bool CMP = false, bool FUSE = false>
+__device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
+                                            typename Codec<ST>::T *__restrict__ B,
+                                            const mask_t *__restrict__ mask,
+                                            const typename Codec<ST>::R *__restrict__ uin,
+                                            const Side &side, int x, int y, int wv,
+                                            typename Codec<ST>::R (*lds_m)[3 * 64],
+                                            typename Codec<ST>::T (*lds_p)[8 * 64], const Pulled<ST> &pl,
+                                            const FuseArgs *fa = nullptr,
+                                            typename Codec<ST>::T (*lds_l)[8 * 64] = nullptr)
+{
+    using C = Codec<ST>;
+    using T = typename C::T;
+    using R = typename C::R;
+    if (!pl.live) return;
+    const bool inside = x < g.nx;
+    const int32_t row = y * g.pitch;
+    const mask_t m = pl.m;
+    const int64_t P = g.plane;
+    constexpr uint32_t S = sizeof(T);
+    // the planes of B are written through buffer resources (plane < 4 GiB)
+    const uint32_t pbytes = (uint32_t)(P * S);
+    const int lane = threadIdx.x & 63;
+    const uint32_t own = pl.own, own_in = pl.own_in, own_out = pl.own_out;
     T a[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) a[i] = ld_at(A + i * P, o[i]);
-    // keep the pulls ahead of everything that waits for the mask word (the
-    // scheduler would otherwise hoist the ballot below and expose its latency)
-    __builtin_amdgcn_sched_barrier(0);
+    for (int i = 0; i < 9; ++i) a[i] = pl.a[i];
     const int32_t seg = __builtin_amdgcn_readfirstlane(y * (g.pitch >> 6) + (x >> 6));
     const SegBase sb = ld_seg(side.seg + seg);
     if (FUSE) {
@@ -667,6 +695,29 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
     }
 }
 
+// Both halves back to back: one row segment per wavefront.
+template <int ST, bool OPEN, bool FORCE, int BX, bool STORE_SOLID, bool CMP = false, bool FUSE = false>
+__device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
+                                          const typename Codec<ST>::T *__restrict__ A,
+                                          typename Codec<ST>::T *__restrict__ B,
+                                          const mask_t *__restrict__ mask,
+                                          const typename Codec<ST>::R *__restrict__ uin,
+                                          const Side &side, int x, int y, int wv,
+                                          typename Codec<ST>::R (*lds_m)[3 * 64],
+                                          typename Codec<ST>::T (*lds_p)[8 * 64],
+                                          const FuseArgs *fa = nullptr,
+                                          typename Codec<ST>::T (*lds_l)[8 * 64] = nullptr)
+{
+    Pulled<ST> pl;
+    bulk_issue<ST, OPEN, CMP>(g, A, mask, x, y, pl);
+    // keep the pulls ahead of everything that waits for the mask word (the
+    // scheduler would otherwise hoist the ballot of bulk_finish above them and
+    // expose the mask's latency)
+    __builtin_amdgcn_sched_barrier(0);
+    bulk_finish<ST, OPEN, FORCE, BX, STORE_SOLID, CMP, FUSE>(g, ph, B, mask, uin, side, x, y, wv, lds_m, lds_p,
+                                                              pl, fa, lds_l);
+}
+
 // clears the force bank of the next step (all blocks share the work)
 __device__ __forceinline__ void zero_bank_part(double *__restrict__ zb, int32_t nz, int64_t block,
                                                int64_t nblocks, int tid)
@@ -675,7 +726,7 @@ __device__ __forceinline__ void zero_bank_part(double *__restrict__ zb, int32_t 
     for (int64_t k = block * 256 + tid; k < nz; k += nblocks * 256) zb[k] = 0.0;
 }
 
-template <int ST, bool OPEN, bool FORCE, int BX, bool STORE_SOLID, bool CMP>
+template <int ST, bool OPEN, bool FORCE, int BX, bool STORE_SOLID, bool CMP, int ROWS>
 __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
                                                    const typename Codec<ST>::T *__restrict__ A,
                                                    typename Codec<ST>::T *__restrict__ B,
@@ -712,8 +763,27 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
         if (tx < 0) tx += gridDim.x, --ty;
         if (tx >= (int)gridDim.x) tx -= gridDim.x, ++ty;
     }
-    bulk_body<ST, OPEN, FORCE, BX, STORE_SOLID, CMP>(g, ph, A, B, mask, uin, side, tx * BX + threadIdx.x,
-                                                     ty * BY + threadIdx.y, tid >> 6, lds_m, lds_p);
+    const int x = tx * BX + threadIdx.x;
+    if (ROWS == 1) {
+        bulk_body<ST, OPEN, FORCE, BX, STORE_SOLID, CMP>(g, ph, A, B, mask, uin, side, x, ty * BY + threadIdx.y,
+                                                         tid >> 6, lds_m, lds_p);
+    } else {
+        // two row segments per wavefront (rows y and y + BY of a BX x 2BY tile):
+        // the second one's pulls are in flight while the first is finished
+        const int y0 = ty * 2 * BY + threadIdx.y, y1 = y0 + BY;
+        Pulled<ST> p0, p1;
+        bulk_issue<ST, OPEN, CMP>(g, A, mask, x, y0, p0);
+        bulk_issue<ST, OPEN, CMP>(g, A, mask, x, y1, p1);
+        __builtin_amdgcn_sched_barrier(0);
+        bulk_finish<ST, OPEN, FORCE, BX, STORE_SOLID, CMP>(g, ph, B, mask, uin, side, x, y0, tid >> 6, lds_m, lds_p,
+                                                           p0);
+        // the first segment's deposit flush has read the wavefront's LDS staging
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        bulk_finish<ST, OPEN, FORCE, BX, STORE_SOLID, CMP>(g, ph, B, mask, uin, side, x, y1, tid >> 6, lds_m, lds_p,
+                                                           p1);
+    }
 }
 
 // The same step with the links of each wavefront's nodes evaluated in the
@@ -979,17 +1049,17 @@ hipError_t bulk_fused_dispatch(const Grid &g, const Phys &ph, const void *A, voi
                  : bulk_fused_shape<ST, false, false>(g, ph, A, B, mask, uin, side, fa, zb, nz, cf, s);
 }
 
-template <int ST, bool OPEN, bool FORCE, int BX, bool SS, bool CMP>
+template <int ST, bool OPEN, bool FORCE, int BX, bool SS, bool CMP, int ROWS = 1>
 hipError_t bulk_t(const Grid &g, const Phys &ph, const void *A, void *B, const mask_t *mask,
                   const void *uin, const Side &side, double *zb, int32_t nz, int32_t xcd, hipStream_t s,
                   const ForceReduce &fr)
 {
     using C = Codec<ST>;
     constexpr int BY = 256 / BX;
-    dim3 grid((g.nx + BX - 1) / BX, (g.ny + BY - 1) / BY);
+    dim3 grid((g.nx + BX - 1) / BX, (g.ny + ROWS * BY - 1) / (ROWS * BY));
     const int64_t nb = (int64_t)grid.x * grid.y;
     if (fr.nw > nb * 256 * FOLD_CHUNK) return hipErrorInvalidValue;  // more partials than lanes
-    hipLaunchKernelGGL((bulk_kernel<ST, OPEN, FORCE, BX, SS, CMP>), grid, dim3(BX, BY), 0, s, g, ph,
+    hipLaunchKernelGGL((bulk_kernel<ST, OPEN, FORCE, BX, SS, CMP, ROWS>), grid, dim3(BX, BY), 0, s, g, ph,
                        static_cast<const typename C::T *>(A), static_cast<typename C::T *>(B), mask,
                        static_cast<const typename C::R *>(uin), side, zb, nz, xcd, 1.0 / grid.x, fr.wpart,
                        fr.wobj, fr.nw, fr.bank, fr.fsum);
@@ -1003,10 +1073,18 @@ hipError_t bulk_shape(const Grid &g, const Phys &ph, const void *A, void *B, con
 {
     if (g.compact) {
         // no solid slots to store in the compact layout
+        if (cf.rows == 2)
+            return cf.block_x == 256 ? bulk_t<ST, OPEN, FORCE, 256, false, true, 2>(g, ph, A, B, mask, uin, side, zb, nz, cf.xcd, s, fr)
+                                     : hipErrorInvalidValue;
         if (cf.block_x == 64) return bulk_t<ST, OPEN, FORCE, 64, false, true>(g, ph, A, B, mask, uin, side, zb, nz, cf.xcd, s, fr);
         if (cf.block_x == 128) return bulk_t<ST, OPEN, FORCE, 128, false, true>(g, ph, A, B, mask, uin, side, zb, nz, cf.xcd, s, fr);
         if (cf.block_x == 256) return bulk_t<ST, OPEN, FORCE, 256, false, true>(g, ph, A, B, mask, uin, side, zb, nz, cf.xcd, s, fr);
         return hipErrorInvalidValue;
+    }
+    if (cf.rows == 2) {
+        if (cf.block_x != 256) return hipErrorInvalidValue;
+        return cf.store_solid ? bulk_t<ST, OPEN, FORCE, 256, true, false, 2>(g, ph, A, B, mask, uin, side, zb, nz, cf.xcd, s, fr)
+                              : bulk_t<ST, OPEN, FORCE, 256, false, false, 2>(g, ph, A, B, mask, uin, side, zb, nz, cf.xcd, s, fr);
     }
 #define LBM_BULK_SHAPE(BXV, SSV)                                                                  \
     if (cf.block_x == BXV && cf.store_solid == SSV)                                              \

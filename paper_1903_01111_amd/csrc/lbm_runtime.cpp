@@ -1058,7 +1058,8 @@ lbm_status lbm_set_kernel_config(lbm_ctx *c, const lbm_kernel_config *cfg)
     const int bx = cfg->bulk_block_x;
     if ((bx != 64 && bx != 128 && bx != 256) || (cfg->bulk_store_solid != 0 && cfg->bulk_store_solid != 1) ||
         (cfg->bulk_xcd != 0 && cfg->bulk_xcd != 1) || (cfg->bulk_fused != 0 && cfg->bulk_fused != 1) ||
-        (cfg->bulk_fused && bx != 256) ||
+        (cfg->bulk_fused && bx != 256) || cfg->bulk_rows < 0 || cfg->bulk_rows > 2 ||
+        (cfg->bulk_rows == 2 && (bx != 256 || cfg->bulk_fused)) ||
         cfg->link_block < 64 || cfg->link_block > 1024 || cfg->link_block % 64 ||
         cfg->graph_steps < 2 || cfg->graph_steps > 1024 || cfg->graph_steps % 2)
         return c->fail(LBM_E_ARG, "lbm_set_kernel_config: unsupported configuration");
@@ -1103,17 +1104,20 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps_per_trial, lbm_kernel_config *
     };
     for (int bx : {64, 128, 256})
         for (int ss : {0, 1})
-            for (int xo : {0, 1}) {
-                if (s || (ss && c->p.layout == LBM_LAYOUT_COMPACT)) continue;  // no solid slots there
-                lbm_kernel_config k = best;
-                k.bulk_block_x = bx;
-                k.bulk_store_solid = ss;
-                k.bulk_xcd = xo;
-                k.bulk_fused = 0;
-                double ms;
-                if ((s = trial(k, &ms))) break;
-                if (ms < best_ms) best_ms = ms, best = k;
-            }
+            for (int xo : {0, 1})
+                for (int rows : {1, 2}) {
+                    if (s || (ss && c->p.layout == LBM_LAYOUT_COMPACT)) continue;  // no solid slots there
+                    if (rows == 2 && bx != 256) continue;
+                    lbm_kernel_config k = best;
+                    k.bulk_block_x = bx;
+                    k.bulk_store_solid = ss;
+                    k.bulk_xcd = xo;
+                    k.bulk_fused = 0;
+                    k.bulk_rows = rows;
+                    double ms;
+                    if ((s = trial(k, &ms))) break;
+                    if (ms < best_ms) best_ms = ms, best = k;
+                }
     for (int lb : {128, 256, 512, 1024}) {
         if (s) break;
         lbm_kernel_config k = best;
@@ -1129,6 +1133,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps_per_trial, lbm_kernel_config *
             if (s || (ss && c->p.layout == LBM_LAYOUT_COMPACT)) continue;
             lbm_kernel_config k = unfused;
             k.bulk_fused = 1;
+            k.bulk_rows = 1;
             k.bulk_block_x = 256;
             k.bulk_store_solid = ss;
             k.bulk_xcd = xo;

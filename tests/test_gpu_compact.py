@@ -76,11 +76,11 @@ def test_compact_equals_dense(B, name, storage):
     _same(_run(B, case, storage, "compact", 37, k), _run(B, case, storage, "dense", 37, k))
 
 
-@pytest.mark.parametrize("bx,fused", [(64, 0), (128, 0), (256, 0), (256, 1)])
+@pytest.mark.parametrize("bx,fused,rows", [(64, 0, 1), (128, 0, 1), (256, 0, 1), (256, 1, 1), (256, 0, 2)])
 @pytest.mark.parametrize("xcd", [0, 1])
-def test_compact_launch_shapes(B, bx, fused, xcd):
+def test_compact_launch_shapes(B, bx, fused, rows, xcd):
     case = CASES["porous_200x64"]()
-    cfg = B.lbm_kernel_config(bx, 0, 256, 16, xcd, fused)
+    cfg = B.lbm_kernel_config(bx, 0, 256, 16, xcd, fused, rows)
     _same(_run(B, case, "f32", "compact", 40, cfg=cfg), _run(B, case, "f32", "dense", 40))
 
 

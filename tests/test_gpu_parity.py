@@ -263,6 +263,7 @@ def test_every_kernel_config_gives_the_same_result(B):
     cfgs = [(bx, ss, lb, gs, xo, 0) for bx in (64, 128, 256) for ss in (0, 1)
             for lb, gs, xo in ((64, 2, 0), (1024, 30, 1))]
     cfgs += [(256, ss, 256, gs, xo, 1) for ss in (0, 1) for gs, xo in ((2, 0), (16, 1))]
+    cfgs += [(256, ss, lb, gs, xo, 0, 2) for ss in (0, 1) for lb, gs, xo in ((64, 2, 0), (1024, 30, 1))]
     for cfg in cfgs:
         lat = B.Lattice(case, storage="f32")
         B.lbm_set_kernel_config(lat.ctx, B.lbm_kernel_config(*cfg))
@@ -297,16 +298,44 @@ def test_fused_links_with_several_objects(B, storage):
     ref.close()
 
 
+@pytest.mark.parametrize("storage", ["f32", "f64", "f16", "bf16"])
+def test_two_rows_per_wavefront(B, storage):
+    """Two row segments per bulk wavefront change speed only: bitwise the same
+    populations on an open channel with an odd row count (the last tile's second
+    segment lies outside) and on a periodic porous lattice, in both layouts."""
+    k = 12 if storage == "f16" else 0
+    for case in (W.walled_cylinder(204, 20.0, 0.41, 0.27), small_porous(150, 71, seed=5)):
+        assert case.ny % 2 == 1  # the last 2-row tile is half outside
+        for layout in ("dense", "compact"):
+            ref = B.Lattice(case, storage=storage, dev_scale_log2=k, layout=layout)
+            ref.step(33)
+            for ss, xo in ((0, 0), (1, 1)):
+                if ss and layout == "compact":
+                    continue
+                lat = B.Lattice(case, storage=storage, dev_scale_log2=k, layout=layout)
+                B.lbm_set_kernel_config(lat.ctx, B.lbm_kernel_config(256, ss, 256, 16, xo, 0, 2))
+                lat.step(33)
+                print(f"[rows2] {case.name} {storage} {layout} ss={ss} xcd={xo}", flush=True)
+                assert np.array_equal(lat.populations(), ref.populations())
+                for o in range(case.n_obj):
+                    _, sa, _ = lat.force(o)
+                    _, sb, _ = ref.force(o)
+                    assert np.abs(sa - sb).max() <= 1e-12 * max(np.abs(sb).max(), 1e-300)
+                lat.close()
+            ref.close()
+
+
 def test_invalid_kernel_config_is_rejected(B):
     lat = B.Lattice(small_cylinder(64, 32, 4.0), storage="f32")
     for bad in ((96, 0, 256, 16), (256, 2, 256, 16), (256, 0, 100, 16), (256, 0, 256, 3), (256, 0, 256, 16, 2),
-                (128, 0, 256, 16, 0, 1), (256, 0, 256, 16, 0, 2)):
+                (128, 0, 256, 16, 0, 1), (256, 0, 256, 16, 0, 2), (256, 0, 256, 16, 0, 0, 3),
+                (128, 0, 256, 16, 0, 0, 2), (256, 0, 256, 16, 0, 1, 2), (256, 0, 256, 16, 0, 0, -1)):
         with pytest.raises(B.LbmError) as e:
             B.lbm_set_kernel_config(lat.ctx, B.lbm_kernel_config(*bad))
         assert e.value.status == B.LBM_E_ARG
     assert B.lbm_get_kernel_config(lat.ctx).as_dict() == dict(bulk_block_x=256, bulk_store_solid=0,
                                                              link_block=256, graph_steps=16, bulk_xcd=0,
-                                                             bulk_fused=0)
+                                                             bulk_fused=0, bulk_rows=1)
     lat.close()
 
 
