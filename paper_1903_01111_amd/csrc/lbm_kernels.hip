@@ -40,34 +40,38 @@ __device__ __forceinline__ typename Codec<ST>::R link_eval(const Phys &ph, const
     using C = Codec<ST>;
     using T = typename C::T;
     using R = typename C::R;
-    const uint32_t meta = L.meta[k];
-    const int ip = (int)(meta & 15u);
-    obj = (int)(meta >> 8);
-    const int cxp = cx_of(ip), cyp = cy_of(ip);
-    const R w = ip <= 4 ? R(1) / R(9) : R(1) / R(36);
+    // Two round trips: every per-link record first, then every deposit it points
+    // to.  The deposits of ff are fetched for halfway bounce-back links too (from
+    // f's slots, in bounds) and not used, so that no load waits on a branch.
     const R *qv = static_cast<const R *>(L.q);
     const T *P = static_cast<const T *>(Pv);
     const R *M = static_cast<const R *>(Mv);
+    const uint32_t meta = L.meta[k];
+    const int32_t pf = L.pf[k], sf = L.sf[k], sff = L.sff[k], pff = L.pff[k];
+    const R q = qv[k];
     R uwx = R(0), uwy = R(0);
     if (L.uw) {
         const R *u = static_cast<const R *>(L.uw);
         uwx = u[2 * k];
         uwy = u[2 * k + 1];
     }
+    const int32_t sffc = sff < 0 ? sf : sff, pffc = sff < 0 ? pf : pff;
+    const T pfv = P[pf], pffv = P[pffc];
+    const R drf = M[3 * sf], ufx = M[3 * sf + 1], ufy = M[3 * sf + 2];
+    const R drff = M[3 * sffc], uffx = M[3 * sffc + 1], uffy = M[3 * sffc + 2];
+    const int ip = (int)(meta & 15u);
+    obj = (int)(meta >> 8);
+    const int cxp = cx_of(ip), cyp = cy_of(ip);
+    const R w = ip <= 4 ? R(1) / R(9) : R(1) / R(36);
     // moving-wall momentum term 6 w_{i'} rho0 e_i.u_w, with e_i = -e_{i'}
     const R wall = -R(6) * w * R(ph.rho0) * (R(cxp) * uwx + R(cyp) * uwy);
-    const R fpf = C::ld(P[L.pf[k]], ph.inv_scale);
-    const int32_t sff = L.sff[k];
+    const R fpf = C::ld(pfv, ph.inv_scale);
     R v;
-    if (sff < 0) {
-        v = fpf + wall;  // halfway bounce-back
-    } else {
-        // moments of f and ff at time t, deposited by the previous bulk step
-        const int32_t sf = L.sf[k];
-        const R drf = M[3 * sf], ufx = M[3 * sf + 1], ufy = M[3 * sf + 2];
-        const R drff = M[3 * sff], uffx = M[3 * sff + 1], uffy = M[3 * sff + 2];
-        const R fpff = C::ld(P[L.pff[k]], ph.inv_scale);
-        const R q = qv[k];
+    {
+        // VIBB from the moments of f and ff at time t, deposited by the previous
+        // bulk step; evaluated for every link (no load may sink into a branch),
+        // halfway bounce-back links take fpf + wall below instead
+        const R fpff = C::ld(pffv, ph.inv_scale);
         const R a2q = R(2) * q, b2q = R(1) - R(2) * q;
         // density at the departure point d (extrapolated when q > 1/2)
         const R drd = a2q * drf + b2q * drff;
@@ -93,6 +97,7 @@ __device__ __forceinline__ typename Codec<ST>::R link_eval(const Phys &ph, const
         const R udx = (usx + R(2) * ussx) / R(3), udy = (usy + R(2) * ussy) / R(3);
         v = deq(w, R(cxp) * udx + R(cyp) * udy, drd, udx * udx + udy * udy) + neqd + wall;
     }
+    if (sff < 0) v = fpf + wall;  // halfway bounce-back
     const double m = (double)fpf + (double)v + 2.0 * (double)w;
     fx = cxp * m;
     fy = cyp * m;
