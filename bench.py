@@ -311,9 +311,9 @@ def main():
                     help="run only this form and print its JSON object")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part "
-                                   "of it (the lattice would be split into y-slabs with halo "
-                                   "exchange, which is not implemented)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; a run over several GPUs "
+                                   "would split the lattice into y-slabs with halo exchange, "
+                                   "which is not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import numpy as np
