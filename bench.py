@@ -239,6 +239,51 @@ def form_single(B, case, steps, warmup, layout="dense"):
             "kernel_config": cfg}
 
 
+def upward_crossings(t, y):
+    """Times at which y crosses zero upwards (linear interpolation between samples)."""
+    import numpy as np
+    k = np.nonzero((y[:-1] < 0) & (y[1:] >= 0))[0]
+    return t[k] + (t[k + 1] - t[k]) * (-y[k]) / (y[k + 1] - y[k])
+
+
+def form_cylinder_flow(B, steps=100000, window=16, tail=40000, storage="f32"):
+    """Flow past the disc of the 2048x512 channel at Re = 100 (uniform inlet U = 0.05,
+    R = 20): mean drag coefficient, rms lift coefficient and Strouhal number of
+    the vortex shedding over the last `tail` steps, from the force averaged over
+    windows of `window` steps.  C_D = 2 F_x / (rho0 U^2 D) and C_L = 2 F_y /
+    (rho0 U^2 D) with the momentum-exchange force on the disc; St = f D / U with f
+    from the mean spacing of the lift's upward zero crossings."""
+    import numpy as np
+    from paper_1903_01111_amd import workloads as W
+    case = W.cylinder_channel()
+    U, D = 0.05, 2.0 * case.prims[0].r
+    lat = B.Lattice(case, storage=storage)
+    prev = np.zeros(2)
+    samples = []
+    w0 = time.perf_counter()
+    for _ in range(steps // window):
+        lat.step(window)
+        _, s, _ = lat.force(0)
+        samples.append((s - prev) / window)
+        prev = s.copy()
+    wall = time.perf_counter() - w0
+    lat.moments()  # raises on a non-finite state
+    lat.close()
+    f = np.array(samples)
+    nt = tail // window
+    t = (np.arange(len(f)) + 0.5) * window
+    cd = 2.0 * f[-nt:, 0] / (U * U * D)
+    cl = 2.0 * f[-nt:, 1] / (U * U * D)
+    up = upward_crossings(t[-nt:], cl - cl.mean())
+    st = float(D / U / np.diff(up).mean()) if len(up) >= 2 else None
+    return {"workload": f"{case.name}, Re = 100, U = {U}, D = {D:g}", "storage": storage,
+            "steps": steps, "tail": tail,
+            "window": window, "C_D_mean": round(float(cd.mean()), 4),
+            "C_L_rms": round(float(np.sqrt(np.mean((cl - cl.mean()) ** 2))), 4),
+            "C_L_mean": round(float(cl.mean()), 5), "St": round(st, 4) if st else None,
+            "shedding_periods_in_tail": max(len(up) - 1, 0), "wall_s": round(wall, 2)}
+
+
 def form_adjoint(B, steps=2000, ckpt=100):
     """Drag gradient of the uniform-inlet cylinder 1024x256 (R = 12.4, Re = 100):
     wall time of the adjoint call (forward sweep with checkpoints, recomputation,
@@ -307,7 +352,8 @@ def main():
                     help="also run one 1 GiB device copy (counter calibration under rocprofv3)")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the FP16/BF16 storage, batched, cylinder and adjoint measurements")
-    ap.add_argument("--form", choices=["storage_16bit", "batched", "cylinder", "dense_layout", "adjoint"],
+    ap.add_argument("--form", choices=["storage_16bit", "batched", "cylinder", "cylinder_flow", "dense_layout",
+                                       "adjoint"],
                     help="run only this form and print its JSON object")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -332,6 +378,8 @@ def main():
             res = form_batched(B, 256, 300, 20)
         elif args.form == "cylinder":
             res = form_single(B, W.cylinder_channel(), 2000, 100)
+        elif args.form == "cylinder_flow":
+            res = form_cylinder_flow(B)
         elif args.form == "dense_layout":
             res = form_single(B, workload(args.workload), 1000, 100, layout="dense")
         else:
@@ -459,6 +507,8 @@ def main():
         forms["cylinder_2048x512_f32"] = form_single(B, W.cylinder_channel(), 2000, 100)
         forms["cylinder_2048x512_f32"]["note"] = ("75 MB working set: resident in the 256 MB "
                                                   "last-level cache, not an HBM figure")
+        forms["cylinder_flow_re100"] = form_cylinder_flow(B)
+        print(f"[bench] cylinder flow: {forms['cylinder_flow_re100']}", file=sys.stderr, flush=True)
         forms["porous_dense_layout_f32"] = form_single(B, case, 1000, 100, layout="dense")
         forms["porous_dense_layout_f32"]["note"] = ("the same porous step with every node of the padded "
                                                     "lattice stored (solid nodes included)")
