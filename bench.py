@@ -141,36 +141,55 @@ def e_u(a, b):
     return float(max(np.abs(a[0] - b[0]).max(), np.abs(a[1] - b[1]).max()) / ref)
 
 
-def form_precision(B, case, steps_err, steps_time, layout="compact"):
-    """16-bit deviation storage against FP32 on the same workload: velocity error
-    after steps_err steps from the same initial state, and throughput."""
+def form_precision(B, case, steps_err, steps_time, layout="compact", steps_long=20000):
+    """16-bit deviation storage against FP32 and FP64 on the same workload, from the
+    same initial state: velocity error e_u and drag error after steps_err steps
+    against FP64 storage (the FP64 path equals the oracle to 1e-11 at every tested
+    size, so it stands in for the oracle at full size) and against FP32; e_u and the
+    error of the mean u_x (the superficial velocity) against FP32 after steps_long
+    steps; then throughput."""
+    import numpy as np
+    ref = B.Lattice(case, storage="f64", layout=layout)
+    ref.step(steps_err)
+    _, u64, v64 = ref.moments()
+    _, fs64, _ = ref.force(0)
+    ref.close()
     f32 = B.Lattice(case, storage="f32", layout=layout)
     f32.step(steps_err)
     _, u32, v32 = f32.moments()
     k = B.dev_scale_for(B.lbm_max_deviation(f32.ctx))
     _, fs32, _ = f32.force(0)
+    out = {"f32": {"e_u_vs_f64": e_u((u32, v32), (u64, v64)),
+                   "drag_err_vs_f64": float(abs(fs32[0] - fs64[0]) / abs(fs64[0])), "steps": steps_err}}
+    f32.step(steps_long - steps_err)
+    _, u32l, v32l = f32.moments()
     f32.close()
-    out = {}
     for st, kk in (("f16", k), ("bf16", 0)):
         lat = B.Lattice(case, storage=st, dev_scale_log2=kk, layout=layout)
         lat.step(steps_err)
+        r = {"scale_log2": kk, "steps": steps_err, "steps_long": steps_long}
         try:
             _, u, v = lat.moments()
-            err = e_u((u, v), (u32, v32))
             _, fs, _ = lat.force(0)
-            ferr = float(abs(fs[0] - fs32[0]) / abs(fs32[0]))
+            r.update(e_u_vs_f32=e_u((u, v), (u32, v32)), e_u_vs_f64=e_u((u, v), (u64, v64)),
+                     drag_err_vs_f32=float(abs(fs[0] - fs32[0]) / abs(fs32[0])),
+                     drag_err_vs_f64=float(abs(fs[0] - fs64[0]) / abs(fs64[0])))
+            lat.step(steps_long - steps_err)
+            _, u, v = lat.moments()
+            r.update(e_u_vs_f32_long=e_u((u, v), (u32l, v32l)),
+                     mean_ux_err_vs_f32_long=float(abs(u.mean() - u32l.mean()) / abs(u32l.mean())))
         except B.LbmError as e:
-            err, ferr = f"unstable ({e})", None
+            r["error"] = f"unstable ({e})"
         B.lbm_autotune(lat.ctx, 10)
         ms, link_ms, bulk_ms, ksteps = replay_then_timed(B, lat, steps_time)
         nfb = B.lbm_check_geometry(lat.params, lat.mask, lat.node, lat.dir, lat.q, lat.uw, lat.obj,
                                    lat.scheme)
         bulk_bytes, _ = algorithmic_bytes(case, lat.mask, lat.n_links, lat.n_links - nfb, st)
-        out[st] = {"scale_log2": kk, "e_u_vs_f32": err, "drag_err_vs_f32": ferr, "steps": steps_err,
-                   "mlups": round(case.nx * case.ny * steps_time / (ms * 1e-3) / 1e6, 1),
-                   "bulk_GBps_algorithmic": round(bulk_bytes / (bulk_ms * 1e-3 / ksteps) / 1e9, 1)}
+        r.update(mlups=round(case.nx * case.ny * steps_time / (ms * 1e-3) / 1e6, 1),
+                 bulk_GBps_algorithmic=round(bulk_bytes / (bulk_ms * 1e-3 / ksteps) / 1e9, 1))
+        out[st] = r
         lat.close()
-        print(f"[bench] {st}: {out[st]}", file=sys.stderr, flush=True)
+        print(f"[bench] {st}: {r}", file=sys.stderr, flush=True)
     return out
 
 
