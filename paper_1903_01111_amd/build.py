@@ -21,6 +21,10 @@ CXX_SOURCES = ["lbm_runtime.cpp", "lbm_batch.cpp", "lbm_geometry.cpp", "lbm_adjo
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
                # packed FP32 instructions are kept out of the generated code
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+               # multiply-adds fused within a source expression only: every kernel
+               # instantiation (launch shape, rows per wavefront, batch) then rounds
+               # the same way, which keeps their results bitwise equal
+               "-ffp-contract=on",
                "-Wall", "-Wno-unused-function"]
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-D__HIP_PLATFORM_AMD__"]
 

@@ -115,6 +115,13 @@ __device__ __forceinline__ R deq(R w, R eu, R dr, R usq)
 // velocity; the error is a relative 1e-7 of u (dr / (1 + dr) times 1 ulp).
 __device__ __forceinline__ float inv_rho_m1_fast(float dr) { return -dr * __builtin_amdgcn_rcpf(1.0f + dr); }
 __device__ __forceinline__ double inv_rho_m1_fast(double dr) { return -dr / (1.0 + dr); }
+// Arithmetic type of the bulk collision: the storage's own arithmetic type (FP64
+// for FP64 storage, FP32 otherwise).  Kept as a separate name so that a storage
+// form can collide wider than it stores.
+template <int ST>
+struct Collide {
+    using A = typename Codec<ST>::R;
+};
 
 // Element e of a population plane at base.  A plane is smaller than 4 GiB (the
 // runtime checks it), so the byte offset fits 32 bits and the access takes the

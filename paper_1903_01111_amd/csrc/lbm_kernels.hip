@@ -563,65 +563,82 @@ __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
     }
 
     const float inv = ph.inv_scale;
-    R f[9];
+    using A = typename Collide<ST>::A;
+    A f[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = C::ld(a[i], inv);
+    for (int i = 0; i < 9; ++i) f[i] = A(C::ld(a[i], inv));
 
-    const R drho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
-    const R jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
-    const R jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
-    const R ir = inv_rho_m1_fast(drho);
-    R ux = jx + jx * ir, uy = jy + jy * ir;
-    R Fx = R(0), Fy = R(0);
+    const A drho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+    const A jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+    const A jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    const A ir = inv_rho_m1_fast(drho);
+    A ux = jx + jx * ir, uy = jy + jy * ir;
+    A Fx = A(0), Fy = A(0);
     if (FORCE) {
         // force density F = rho g; velocity shifted by half the force (Guo)
-        Fx = R(ph.gx) + drho * R(ph.gx);
-        Fy = R(ph.gy) + drho * R(ph.gy);
-        ux += R(0.5) * R(ph.gx);
-        uy += R(0.5) * R(ph.gy);
+        Fx = A(ph.gx) + drho * A(ph.gx);
+        Fy = A(ph.gy) + drho * A(ph.gy);
+        ux += A(0.5) * A(ph.gx);
+        uy += A(0.5) * A(ph.gy);
     }
-    const R usq = ux * ux + uy * uy;
-    const R om = R(ph.omega);
-    const R cf = R(1) - R(0.5) * om;
-    // BGK + Guo, direction pairs (i, opp(i)) sharing e.u up to its sign:
+    const A usq = ux * ux + uy * uy;
+    const A om = A(ph.omega);
+    const A cf = A(1) - A(0.5) * om;
+    // BGK + Guo in direction pairs (i, opp(i)), which share e.u up to its sign:
     //   f^eq - w = w (rho P + dr),  P = A +- B,  A = 9/2 (e.u)^2 - 3/2 u.u,  B = 3 e.u,
-    // so f^eq_{i,opp} - w = w (rho A + dr) +- w rho B, with rho A = A + dr A kept in
-    // deviation form; Guo's source (1 - omega/2) w [3 (e - u).F + 9 (e.u)(e.F)]
-    // splits the same way into (1 - omega/2) w (9 (e.u)(e.F) - 3 u.F) +- 3 (1 - omega/2) w e.F.
-    const R h15 = R(1.5) * usq;
-    const R uF = FORCE ? ux * Fx + uy * Fy : R(0);
-    {
-        // rest population: e.u = 0
-        const R w = wgt<R>(0);
-        R v = f[0] + om * (w * (drho - (h15 + drho * h15)) - f[0]);
-        if (FORCE) v -= R(3) * cf * w * uF;
-        f[0] = v;
+    // so f^eq_{i,opp} - w = ev +- od with the even part ev = w (rho A + dr) (rho A =
+    // A + dr A in deviation form) and the odd part od = w rho B.  Guo's source
+    // (1 - omega/2) w [3 (e - u).F + 9 (e.u)(e.F)] splits into gs +- gd with
+    // gs = (1 - omega/2) w (9 (e.u)(e.F) - 3 u.F) and gd = 3 (1 - omega/2) w e.F.
+    // Mass and momentum are conserved by construction, not through the weights
+    // (1/9 and 1/36 are inexact in binary): the odd parts of the two axis pairs are
+    // what the diagonal pairs leave of the equilibrium momentum rho u = j + F/2 (and
+    // of the source's (1 - omega/2) F), and the rest population takes what the pairs
+    // leave of the mass.  With rounded weights every collision would add the same
+    // small momentum wherever the flow is steady: a spurious body force of about
+    // 1e-9 per step at |u| = 0.05 in FP32, which shifted the velocity by 1e-5 within
+    // 1000 steps in a forced channel.
+    const A h15 = A(1.5) * usq;
+    const A uF = FORCE ? ux * Fx + uy * Fy : A(0);
+    constexpr int PLUS[4] = {1, 2, 5, 6}, MINUS[4] = {3, 4, 7, 8};  // x axis, y axis, two diagonals
+    A ev[4], od[4], gs[4], gd[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int i = PLUS[k];
+        const A w = wgt<A>(i);
+        const A eu = A(CX[i]) * ux + A(CY[i]) * uy;
+        const A A2 = A(4.5) * eu * eu - h15;
+        ev[k] = w * ((A2 + drho * A2) + drho);
+        if (k >= 2) od[k] = (A(3) * w) * (eu + drho * eu);
+        if (FORCE) {
+            const A eF = A(CX[i]) * Fx + A(CY[i]) * Fy;
+            const A cw = cf * w;
+            gs[k] = cw * (A(9) * eu * eF - A(3) * uF);
+            if (k >= 2) gd[k] = (A(3) * cw) * eF;
+        }
     }
-    constexpr int PLUS[4] = {1, 2, 5, 6}, MINUS[4] = {3, 4, 7, 8};
+    const A Px = FORCE ? jx + A(0.5) * Fx : jx, Py = FORCE ? jy + A(0.5) * Fy : jy;
+    od[0] = A(0.5) * Px - (od[2] - od[3]);
+    od[1] = A(0.5) * Py - (od[2] + od[3]);
+    const A ev0 = drho - A(2) * ((ev[0] + ev[1]) + (ev[2] + ev[3]));
+    A gs0 = A(0);
+    if (FORCE) {
+        const A hcf = A(0.5) * cf;
+        gd[0] = hcf * Fx - (gd[2] - gd[3]);
+        gd[1] = hcf * Fy - (gd[2] + gd[3]);
+        gs0 = A(-2) * ((gs[0] + gs[1]) + (gs[2] + gs[3]));
+    }
+    // each population changes by one rounded addition of its (small) increment
+    f[0] = f[0] + (om * (ev0 - f[0]) + gs0);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int i = PLUS[k], j = MINUS[k];
-        const R w = wgt<R>(i);
-        const R eu = R(CX[i]) * ux + R(CY[i]) * uy;
-        const R A2 = R(4.5) * eu * eu - h15;
-        const R B3 = R(3) * eu;
-        const R sa = w * ((A2 + drho * A2) + drho);
-        const R sb = w * (B3 + drho * B3);
-        R vi = f[i] + om * ((sa + sb) - f[i]);
-        R vj = f[j] + om * ((sa - sb) - f[j]);
-        if (FORCE) {
-            const R eF = R(CX[i]) * Fx + R(CY[i]) * Fy;
-            const R cw = cf * w;
-            const R s0 = cw * (R(9) * eu * eF - R(3) * uF);
-            const R s1 = R(3) * cw * eF;
-            vi += s0 + s1;
-            vj += s0 - s1;
-        }
-        f[i] = vi;
-        f[j] = vj;
+        const A si = FORCE ? gs[k] + gd[k] : A(0), sj = FORCE ? gs[k] - gd[k] : A(0);
+        f[i] = f[i] + (om * ((ev[k] + od[k]) - f[i]) + si);
+        f[j] = f[j] + (om * ((ev[k] - od[k]) - f[j]) + sj);
     }
 #pragma unroll
-    for (int i = 0; i < 9; ++i) st_buf(plane_rsrc(B + i * P, pbytes), own, C::st(f[i], ph.scale));
+    for (int i = 0; i < 9; ++i) st_buf(plane_rsrc(B + i * P, pbytes), own, C::st(R(f[i]), ph.scale));
     // deposits for the next link kernel, staged in LDS so that the wavefront
     // writes its contiguous ranges of M and P in full lines.  The post-collision
     // moments are the collision's own (rho, u): with Guo's shift the physical
@@ -630,13 +647,13 @@ __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
     T *Pv = static_cast<T *>(side.Pw);
     if (m & MASK_SIDE) {
         const int ls = slot - sb.flagged;
-        lds_m[wv][3 * ls] = drho;
-        lds_m[wv][3 * ls + 1] = ux;
-        lds_m[wv][3 * ls + 2] = uy;
+        lds_m[wv][3 * ls] = R(drho);
+        lds_m[wv][3 * ls + 1] = R(ux);
+        lds_m[wv][3 * ls + 2] = R(uy);
         int lp = (int)(exc >> 16);
 #pragma unroll
         for (int d = 1; d < 9; ++d)
-            if (rec & (1u << (d + 7))) lds_p[wv][lp++] = C::st(f[d], ph.scale);
+            if (rec & (1u << (d + 7))) lds_p[wv][lp++] = C::st(R(f[d]), ph.scale);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -655,28 +672,28 @@ __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
         if (x == 1 && !(mask[row] & MASK_SOLID)) {
             // velocity inlet by non-equilibrium extrapolation:
             // f+(0) = f^eq(rho_1, u_in) + f+(1) - f^eq(rho_1, u_1); its moments are (rho_1, u_in)
-            const R vx = uin[2 * y], vy = uin[2 * y + 1];
-            const R vsq = vx * vx + vy * vy;
-            R f0[9];
+            const A vx = A(uin[2 * y]), vy = A(uin[2 * y + 1]);
+            const A vsq = vx * vx + vy * vy;
+            A f0[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
-                const R w = wgt<R>(i);
-                const R ev = R(CX[i]) * vx + R(CY[i]) * vy;
-                const R eu = R(CX[i]) * ux + R(CY[i]) * uy;
-                const R dp = poly(ev, vsq) - poly(eu, usq);
+                const A w = wgt<A>(i);
+                const A ev = A(CX[i]) * vx + A(CY[i]) * vy;
+                const A eu = A(CX[i]) * ux + A(CY[i]) * uy;
+                const A dp = poly(ev, vsq) - poly(eu, usq);
                 f0[i] = f[i] + w * (dp + drho * dp);
-                st_buf(plane_rsrc(B + i * P, pbytes), own_in, C::st(f0[i], ph.scale));
+                st_buf(plane_rsrc(B + i * P, pbytes), own_in, C::st(R(f0[i]), ph.scale));
             }
             if (flagged & 1ull) {
                 const int32_t k = sb.flagged;
-                Mv[3 * k] = drho;
-                Mv[3 * k + 1] = vx;
-                Mv[3 * k + 2] = vy;
+                Mv[3 * k] = R(drho);
+                Mv[3 * k + 1] = R(vx);
+                Mv[3 * k + 2] = R(vy);
 #pragma unroll
                 for (int d = 1; d < 9; ++d) {
                     const uint32_t bit = 1u << (d + 7);
                     if (rec_in & bit)
-                        Pv[pb_in + popc32((rec_in >> 8) & ((1u << (d - 1)) - 1u))] = C::st(f0[d], ph.scale);
+                        Pv[pb_in + popc32((rec_in >> 8) & ((1u << (d - 1)) - 1u))] = C::st(R(f0[d]), ph.scale);
                 }
             }
         }
@@ -684,16 +701,16 @@ __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
         if (x == g.nx - 2 && !(me & MASK_SOLID)) {
             // zero-gradient outlet: copy every population of the last fluid column
 #pragma unroll
-            for (int i = 0; i < 9; ++i) st_buf(plane_rsrc(B + i * P, pbytes), own_out, C::st(f[i], ph.scale));
+            for (int i = 0; i < 9; ++i) st_buf(plane_rsrc(B + i * P, pbytes), own_out, C::st(R(f[i]), ph.scale));
             if (me & MASK_SIDE) {
-                Mv[3 * slot_out] = drho;
-                Mv[3 * slot_out + 1] = ux;
-                Mv[3 * slot_out + 2] = uy;
+                Mv[3 * slot_out] = R(drho);
+                Mv[3 * slot_out + 1] = R(ux);
+                Mv[3 * slot_out + 2] = R(uy);
 #pragma unroll
                 for (int d = 1; d < 9; ++d) {
                     const uint32_t bit = 1u << (d + 7);
                     if (rec_out & bit)
-                        Pv[pb_out + popc32((rec_out >> 8) & ((1u << (d - 1)) - 1u))] = C::st(f[d], ph.scale);
+                        Pv[pb_out + popc32((rec_out >> 8) & ((1u << (d - 1)) - 1u))] = C::st(R(f[d]), ph.scale);
                 }
             }
         }

@@ -100,3 +100,52 @@ def test_batch_errors(B):
         B.lbm_batch_moments(b, 5, 4, 4)
     assert e.value.status == B.LBM_E_ARG
     B.lbm_batch_destroy(b)
+
+
+def test_benchmark_recipe_instances_match_oracle(B):
+    """Eight instances of the batched benchmark's own recipe (seed 0; nx capped at
+    320 so the oracle finishes in seconds; Re up to 100, tau down to 0.526), 1000
+    steps in one batch: per-instance velocity and mean drag coefficient against the
+    oracle, in FP64 (to rounding) and in FP32 (the stated FP32 bound).  BGK with
+    VIBB is unstable as tau -> 1/2: the oracle's run of instance 6 (256x64,
+    tau = 0.526) blows up after about 700 steps (|u| far above the speed of
+    sound; the GPU in FP64 tracks it to 1e-11 up to step 750), and the batch must
+    show that instance blown up too, and only that one."""
+    def blown_up(ux, uy):
+        return not (np.isfinite(ux).all() and np.isfinite(uy).all()) or max(np.abs(ux).max(), np.abs(uy).max()) > 1.0
+
+    cases = W.batched_cylinders(n=8, nx_min=256, nx_max=320, seed=0)
+    n = 1000
+    refs = []
+    for c in cases:
+        fp, g, fs, _, _ = oracle.run_case(c, nsteps=n)
+        with np.errstate(all="ignore"):
+            _, uxr, uyr = oracle.moments(fp, g.solid)
+            refs.append(None if blown_up(uxr, uyr) or not np.isfinite(fs).all() else (uxr, uyr, fs))
+    assert [i for i, r in enumerate(refs) if r is None] == [6]
+    bad = []
+    for storage, tol_u, tol_f in (("f64", 1e-11, 1e-10), ("f32", 1e-5, 2e-5)):
+        bt = B.Batch(cases, storage=storage)
+        bt.step(n)
+        for i, (c, ref_i) in enumerate(zip(cases, refs)):
+            if ref_i is None:
+                try:
+                    _, ux, uy = bt.moments(i)
+                    assert blown_up(ux, uy), i
+                except B.LbmError as e:
+                    assert e.status == B.LBM_E_UNSTABLE
+                continue
+            uxr, uyr, fs = ref_i
+            _, ux, uy = bt.moments(i)
+            ref = max(np.abs(uxr).max(), np.abs(uyr).max())
+            eu = max(np.abs(ux - uxr).max(), np.abs(uy - uyr).max()) / ref
+            _, s, nsum = bt.force(i, 0)
+            # mean drag coefficient over the n steps: 2 <F_x> / (rho0 U^2 D)
+            d = 2.0 * c.prims[0].r
+            cd, cd_ref = 2 * s[0] / nsum / (0.05 ** 2 * d), 2 * fs[0][0] / n / (0.05 ** 2 * d)
+            print(f"[batch-oracle] {storage} inst {i} {c.nx}x{c.ny} tau {c.tau:.4f}: e_u {eu:.2e} "
+                  f"C_D {cd:.6f} vs {cd_ref:.6f}", flush=True)
+            if eu > tol_u or abs(cd - cd_ref) > tol_f * abs(cd_ref):
+                bad.append((storage, i, eu, cd, cd_ref))
+        bt.close()
+    assert not bad, bad
