@@ -203,6 +203,7 @@ def form_batched(B, n_inst, steps, warmup):
     geoms = [B.case_geometry(c) for c in cases]
     bt = B.Batch(cases, storage="f32", geometries=geoms)
     bt.step(warmup)
+    cfg, tuned_ms = B.lbm_batch_autotune(bt.b, 10)  # keeps the fastest configuration, restores the state
     bt.sync()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -237,6 +238,7 @@ def form_batched(B, n_inst, steps, warmup):
            "nodes": n_nodes, "steps": steps, "mlups": round(n_nodes * steps / (ms * 1e-3) / 1e6, 1),
            "single_context_loop_mlups": round(n_nodes * steps / (ms_loop * 1e-3) / 1e6, 1),
            "speedup_vs_loop": round(ms_loop / ms, 2), "instances_finite_after": finite,
+           "autotuned": cfg.as_dict(),
            "tau_range": [round(min(taus), 4), round(max(taus), 4)]}
     print(f"[bench] batched: {out}", file=sys.stderr, flush=True)
     return out

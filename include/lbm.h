@@ -298,6 +298,29 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t n);
 lbm_status lbm_batch_sync(lbm_batch *b);
 int64_t lbm_batch_step_count(const lbm_batch *b);
 
+/* Launch configuration of the batched step.  Every configuration computes the same
+ * result; they differ in speed only. */
+typedef struct {
+    int32_t bulk_store_solid; /* 1: lanes of solid nodes store too (rows written in full lines) */
+    int32_t bulk_rows;        /* tile-table entries per bulk wavefront: 2 issues the second one's
+                                 loads before the first is finished; 1 (or 0): one */
+    int32_t link_block;       /* link kernel lanes per block: 64..1024, a multiple of 64 */
+    int32_t graph_steps;      /* steps per captured HIP graph: even, 2..1024 */
+} lbm_batch_kernel_config;
+
+lbm_status lbm_batch_get_kernel_config(const lbm_batch *b, lbm_batch_kernel_config *cfg);
+/* Errors: LBM_E_ARG for an unsupported configuration (the previous one stays). */
+lbm_status lbm_batch_set_kernel_config(lbm_batch *b, const lbm_batch_kernel_config *cfg);
+
+/* Autotuner of the batched step: times every configuration (solid stores, rows per
+ * wavefront, link block size) for steps_per_trial steps on the current state, keeps
+ * the fastest and restores the state (populations, deposits, step count, forces),
+ * so results do not depend on having tuned.  Needs host memory for one copy of the
+ * populations and deposits.  Errors: LBM_E_STATE before every instance has geometry
+ * and initialisation.  chosen and best_ms_per_step may be NULL. */
+lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps_per_trial, lbm_batch_kernel_config *chosen,
+                              double *best_ms_per_step);
+
 /* Per-instance read-back, as lbm_moments and lbm_force. */
 lbm_status lbm_batch_moments(lbm_batch *b, int32_t inst, double *rho, double *ux, double *uy);
 lbm_status lbm_batch_force(lbm_batch *b, int32_t inst, int32_t obj, double last[2], double sum[2],

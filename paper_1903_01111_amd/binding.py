@@ -47,6 +47,14 @@ class lbm_kernel_config(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class lbm_batch_kernel_config(C.Structure):
+    _fields_ = [("bulk_store_solid", C.c_int32), ("bulk_rows", C.c_int32), ("link_block", C.c_int32),
+                ("graph_steps", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class LbmError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
@@ -100,6 +108,9 @@ SIGNATURES = [
     ("lbm_batch_moments", _I32, [_P, _I32, _P, _P, _P]),
     ("lbm_batch_force", _I32, [_P, _I32, _I32, _P, _P, _P]),
     ("lbm_batch_force_reset", _I32, [_P]),
+    ("lbm_batch_get_kernel_config", _I32, [_P, _P]),
+    ("lbm_batch_set_kernel_config", _I32, [_P, _P]),
+    ("lbm_batch_autotune", _I32, [_P, _I32, _P, _P]),
     ("lbm_adjoint_workspace_bytes", C.c_size_t, [_P, _I64, _I32]),
     ("lbm_adjoint_force", _I32, [_P, _P, C.c_size_t, _I64, _I32, _I32, _D, _D, _P, _P, _P, _P, _P, _P]),
 ]
@@ -457,6 +468,24 @@ def lbm_batch_force(b, inst, obj=0):
 
 def lbm_batch_force_reset(b):
     _bcheck(lib().lbm_batch_force_reset(b), b)
+
+
+def lbm_batch_get_kernel_config(b) -> lbm_batch_kernel_config:
+    k = lbm_batch_kernel_config()
+    _bcheck(lib().lbm_batch_get_kernel_config(b, C.byref(k)), b)
+    return k
+
+
+def lbm_batch_set_kernel_config(b, cfg: lbm_batch_kernel_config):
+    _bcheck(lib().lbm_batch_set_kernel_config(b, C.byref(cfg)), b)
+
+
+def lbm_batch_autotune(b, steps_per_trial=10):
+    """Returns (chosen lbm_batch_kernel_config, ms per step)."""
+    k = lbm_batch_kernel_config()
+    ms = C.c_double(0)
+    _bcheck(lib().lbm_batch_autotune(b, int(steps_per_trial), C.byref(k), C.byref(ms)), b)
+    return k, ms.value
 
 
 class Batch:

@@ -67,7 +67,7 @@ struct lbm_batch {
     bool has_uw = false;
     void *cur = nullptr, *nxt = nullptr;
     int64_t step = 0, nsum = 0;
-    int graph_steps = 16;
+    lbm_batch_kernel_config kcfg{1, 1, 256, 16};
     hipGraphExec_t gexec = nullptr;
     void *graph_cur = nullptr;
 
@@ -363,14 +363,15 @@ lbm_status enqueue_batch_step(lbm_batch *b)
     // the force reduction over the link kernel's partials runs in the bulk launch
     lbm::ForceReduce fr{};
     lbm_status s = b->hip(lbm::launch_link(b->storage, b->grid(0), b->phys(0), b->links(), side, red,
-                                           b->bank(b->step), b->fsum(), 256, b->stream, &fr),
+                                           b->bank(b->step), b->fsum(), b->kcfg.link_block, b->stream, &fr),
                           "batch link launch");
     if (s) return s;
     s = b->hip(lbm::launch_bulk_batch(b->storage, reinterpret_cast<const lbm::BatchInst *>(b->ws + b->off_insts),
                                       reinterpret_cast<const lbm::BatchTile *>(b->ws + b->off_tiles), b->ntiles,
                                       b->phys(0), b->cur, b->nxt, reinterpret_cast<const lbm::mask_t *>(b->ws + b->off_mask),
                                       b->ws + b->off_uin, side, b->bank(b->step + 1), (int32_t)(2 * b->n_obj),
-                                      b->x_bc == LBM_X_OPEN, b->forced, b->stream, fr),
+                                      b->x_bc == LBM_X_OPEN, b->forced, b->kcfg.bulk_store_solid != 0,
+                                      b->kcfg.bulk_rows == 2 ? 2 : 1, b->stream, fr),
                "batch bulk launch");
     if (s) return s;
     std::swap(b->cur, b->nxt);
@@ -396,7 +397,7 @@ lbm_status build_batch_graph(lbm_batch *b)
         b->stream = user;
         return s;
     }
-    for (int k = 0; k < b->graph_steps && !s; ++k) s = enqueue_batch_step(b);
+    for (int k = 0; k < b->kcfg.graph_steps && !s; ++k) s = enqueue_batch_step(b);
     hipError_t e = hipStreamEndCapture(b->stream, &graph);
     b->stream = user;
     b->step = step0;
@@ -615,13 +616,13 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t n)
             return b->fail(LBM_E_STATE, "lbm_batch_step: instance %d lacks geometry or initialisation", i);
     if (!b->assembled && (s = assemble(b))) return s;
     while (n > 0) {
-        if (n >= b->graph_steps) {
+        if (n >= b->kcfg.graph_steps) {
             if (!b->gexec || b->graph_cur != b->cur)
                 if ((s = build_batch_graph(b))) return s;
             if ((s = b->hip(hipGraphLaunch(b->gexec, b->stream), "hipGraphLaunch"))) return s;
-            b->step += b->graph_steps;
-            b->nsum += b->graph_steps;
-            n -= b->graph_steps;
+            b->step += b->kcfg.graph_steps;
+            b->nsum += b->kcfg.graph_steps;
+            n -= b->kcfg.graph_steps;
         } else {
             if ((s = enqueue_batch_step(b))) return s;
             --n;
@@ -698,5 +699,118 @@ lbm_status lbm_batch_force_reset(lbm_batch *b)
 }
 
 int64_t lbm_batch_step_count(const lbm_batch *b) { return b ? b->step : -1; }
+
+lbm_status lbm_batch_get_kernel_config(const lbm_batch *b, lbm_batch_kernel_config *cfg)
+{
+    if (!b || !cfg) return LBM_E_ARG;
+    *cfg = b->kcfg;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_set_kernel_config(lbm_batch *b, const lbm_batch_kernel_config *cfg)
+{
+    if (!b || !cfg) return LBM_E_ARG;
+    if ((cfg->bulk_store_solid != 0 && cfg->bulk_store_solid != 1) || cfg->bulk_rows < 0 || cfg->bulk_rows > 2 ||
+        cfg->link_block < 64 || cfg->link_block > 1024 || cfg->link_block % 64 || cfg->graph_steps < 2 ||
+        cfg->graph_steps > 1024 || cfg->graph_steps % 2)
+        return b->fail(LBM_E_ARG, "lbm_batch_set_kernel_config: unsupported configuration");
+    b->drop_graph();
+    b->kcfg = *cfg;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps_per_trial, lbm_batch_kernel_config *chosen,
+                              double *best_ms_per_step)
+{
+    if (!b || steps_per_trial < 1) return LBM_E_ARG;
+    for (int i = 0; i < b->n; ++i)
+        if (!b->has_geom[i] || !b->has_init[i])
+            return b->fail(LBM_E_STATE, "lbm_batch_autotune: instance %d lacks geometry or initialisation", i);
+    lbm_status s;
+    if (!b->assembled && (s = assemble(b))) return s;
+    // the state the trials start from: populations, deposits, forces and counters
+    const size_t pop_bytes = (size_t)b->pop_elems * b->eb();
+    const size_t m_bytes = (size_t)b->n_flagged * 3 * b->rb(), p_bytes = (size_t)b->n_pops * b->eb();
+    const size_t f_bytes = (size_t)b->n_obj * 6 * sizeof(double);
+    std::vector<char> saved;
+    try {
+        saved.resize(pop_bytes + m_bytes + p_bytes + f_bytes);
+    } catch (const std::bad_alloc &) {
+        return b->fail(LBM_E_NOMEM, "lbm_batch_autotune: no host memory for the saved state");
+    }
+    char *h = saved.data();
+    const struct {
+        size_t host_off;
+        char *dev;
+        size_t bytes;
+    } parts[4] = {{0, static_cast<char *>(b->cur), pop_bytes},
+                  {pop_bytes, b->ws + b->off_M, m_bytes},
+                  {pop_bytes + m_bytes, b->ws + b->off_P, p_bytes},
+                  {pop_bytes + m_bytes + p_bytes, b->ws + b->off_force, f_bytes}};
+    for (const auto &pt : parts)
+        if (pt.bytes && (s = b->hip(hipMemcpyAsync(h + pt.host_off, pt.dev, pt.bytes, hipMemcpyDeviceToHost,
+                                                   b->stream), "autotune save")))
+            return s;
+    if ((s = b->hip(hipStreamSynchronize(b->stream), "autotune save"))) return s;
+    const int64_t step0 = b->step, nsum0 = b->nsum;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return b->fail(LBM_E_DEVICE, "hipEventCreate failed");
+    const lbm_batch_kernel_config base = b->kcfg;
+    lbm_batch_kernel_config best = base;
+    double best_ms = 1e300;
+    auto trial = [&](const lbm_batch_kernel_config &k, double *ms) -> lbm_status {
+        lbm_status r = lbm_batch_set_kernel_config(b, &k);
+        if (r) return r;
+        for (int w = 0; w < 2; ++w)
+            if ((r = enqueue_batch_step(b))) return r;
+        hipEventRecord(e0, b->stream);
+        for (int t = 0; t < steps_per_trial; ++t)
+            if ((r = enqueue_batch_step(b))) return r;
+        hipEventRecord(e1, b->stream);
+        if ((r = b->hip(hipEventSynchronize(e1), "autotune"))) return r;
+        float f = 0;
+        hipEventElapsedTime(&f, e0, e1);
+        *ms = f / steps_per_trial;
+        return LBM_OK;
+    };
+    s = LBM_OK;
+    for (int ss : {0, 1})
+        for (int rows : {1, 2}) {
+            if (s) break;
+            lbm_batch_kernel_config k = best;
+            k.bulk_store_solid = ss;
+            k.bulk_rows = rows;
+            double ms;
+            if ((s = trial(k, &ms))) break;
+            if (ms < best_ms) best_ms = ms, best = k;
+        }
+    for (int lb : {128, 256, 512, 1024}) {
+        if (s) break;
+        lbm_batch_kernel_config k = best;
+        k.link_block = lb;
+        double ms;
+        if ((s = trial(k, &ms))) break;
+        if (ms < best_ms) best_ms = ms, best = k;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    // back to the saved state (whichever buffer is current now)
+    lbm_status r = lbm_batch_set_kernel_config(b, s ? &base : &best);
+    const char *devs[4] = {static_cast<char *>(b->cur), b->ws + b->off_M, b->ws + b->off_P, b->ws + b->off_force};
+    for (int k = 0; k < 4 && !r; ++k)
+        if (parts[k].bytes)
+            r = b->hip(hipMemcpyAsync(const_cast<char *>(devs[k]), h + parts[k].host_off, parts[k].bytes,
+                                      hipMemcpyHostToDevice, b->stream), "autotune restore");
+    if (!r) r = b->hip(hipStreamSynchronize(b->stream), "autotune restore");
+    b->step = step0;
+    b->nsum = nsum0;
+    b->drop_graph();
+    if (s) return s;
+    if (r) return r;
+    if (chosen) *chosen = best;
+    if (best_ms_per_step) *best_ms_per_step = best_ms;
+    return LBM_OK;
+}
 
 }  // extern "C"

@@ -180,6 +180,18 @@ __device__ __forceinline__ T ld_const(const T *p)
 {
     return *(const __attribute__((address_space(4))) T *)p;
 }
+// A trivially copyable record through the constant address space, word by word.
+template <class T>
+__device__ __forceinline__ T ld_const_record(const T *p)
+{
+    static_assert(sizeof(T) % 4 == 0, "record of whole words");
+    T v;
+    const __attribute__((address_space(4))) uint32_t *q = (const __attribute__((address_space(4))) uint32_t *)p;
+    uint32_t *d = reinterpret_cast<uint32_t *>(&v);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) d[i] = q[i];
+    return v;
+}
 // A segment-base record field by field (a record load of only the fields used
 // can become 12 bytes wide, which the scalar unit has no form for).
 __device__ __forceinline__ SegBase ld_seg(const SegBase *p)

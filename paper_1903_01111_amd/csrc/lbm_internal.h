@@ -164,7 +164,7 @@ constexpr int BATCH_BX = 256;  // lanes along x per batched block (one row)
 hipError_t launch_bulk_batch(int storage, const BatchInst *insts, const BatchTile *tiles, int64_t ntiles,
                              const Phys &ph, const void *A, void *B, const mask_t *mask, const void *uin,
                              const Side &side, double *zero_bank, int32_t n_zero, bool open, bool force,
-                             hipStream_t s, const ForceReduce &fr);
+                             bool store_solid, int rows, hipStream_t s, const ForceReduce &fr);
 
 // Rebuilds the deposited populations P (and, with moments, M) of every flagged
 // node from the populations in A: after initialisation or a restored checkpoint.

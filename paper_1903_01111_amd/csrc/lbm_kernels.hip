@@ -846,9 +846,10 @@ __global__ __launch_bounds__(256) void bulk_fused_kernel(Grid g, Phys ph,
 // populations, masks, inlet rows and segment tables of all instances live in
 // shared arrays at per-instance offsets, while side records, deposits and link
 // values use global numbering.
-template <int ST, bool OPEN, bool FORCE, int BX, bool STORE_SOLID>
+template <int ST, bool OPEN, bool FORCE, int BX, bool STORE_SOLID, int ROWS>
 __global__ __launch_bounds__(256) void bulk_batch_kernel(const BatchInst *__restrict__ insts,
-                                                         const BatchTile *__restrict__ tiles, Phys ph0,
+                                                         const BatchTile *__restrict__ tiles, int64_t ntiles,
+                                                         Phys ph0,
                                                          const typename Codec<ST>::T *__restrict__ A,
                                                          typename Codec<ST>::T *__restrict__ B,
                                                          const mask_t *__restrict__ mask,
@@ -866,17 +867,49 @@ __global__ __launch_bounds__(256) void bulk_batch_kernel(const BatchInst *__rest
     const int tid = threadIdx.y * BX + threadIdx.x;
     zero_bank_part(zero_bank, n_zero, blockIdx.x, gridDim.x, tid);
     force_reduce_part(red_part, red_obj, red_n, red_bank, red_sum, blockIdx.x, tid);
-    const BatchTile t = tiles[blockIdx.x];
-    const BatchInst I = insts[t.inst];
-    Phys ph = ph0;
-    ph.omega = I.omega;
-    ph.gx = I.gx;
-    ph.gy = I.gy;
-    Side sd = side;
-    sd.seg = side.seg + I.seg_off;
-    bulk_body<ST, OPEN, FORCE, BX, STORE_SOLID>(I.g, ph, A + I.pop_off, B + I.pop_off, mask + I.mask_off,
-                                                uin + 2 * (int64_t)I.uin_off, sd, t.x0 + threadIdx.x,
-                                                t.y0 + threadIdx.y, tid >> 6, lds_m, lds_p);
+    // the tile table and instance records are read through the scalar cache
+    auto finish = [&](const BatchTile &t, const BatchInst &I, const Pulled<ST> &pl) {
+        Phys ph = ph0;
+        ph.omega = I.omega;
+        ph.gx = I.gx;
+        ph.gy = I.gy;
+        Side sd = side;
+        sd.seg = side.seg + I.seg_off;
+        bulk_finish<ST, OPEN, FORCE, BX, STORE_SOLID>(I.g, ph, B + I.pop_off, mask + I.mask_off,
+                                                      uin + 2 * (int64_t)I.uin_off, sd, t.x0 + threadIdx.x,
+                                                      t.y0 + threadIdx.y, tid >> 6, lds_m, lds_p, pl);
+    };
+    if (ROWS == 1) {
+        const BatchTile t = ld_const_record(tiles + blockIdx.x);
+        const BatchInst I = ld_const_record(insts + t.inst);
+        Pulled<ST> pl;
+        bulk_issue<ST, OPEN, false>(I.g, A + I.pop_off, mask + I.mask_off, t.x0 + threadIdx.x, t.y0 + threadIdx.y,
+                                    pl);
+        __builtin_amdgcn_sched_barrier(0);
+        finish(t, I, pl);
+    } else {
+        // two tile-table entries per block: the second one's pulls are in flight
+        // while the first is finished
+        const int64_t k0 = 2 * (int64_t)blockIdx.x;
+        const bool has1 = k0 + 1 < ntiles;
+        const BatchTile t0 = ld_const_record(tiles + k0), t1 = ld_const_record(tiles + (has1 ? k0 + 1 : k0));
+        const BatchInst I0 = ld_const_record(insts + t0.inst), I1 = ld_const_record(insts + t1.inst);
+        Pulled<ST> p0, p1;
+        bulk_issue<ST, OPEN, false>(I0.g, A + I0.pop_off, mask + I0.mask_off, t0.x0 + threadIdx.x,
+                                    t0.y0 + threadIdx.y, p0);
+        if (has1)
+            bulk_issue<ST, OPEN, false>(I1.g, A + I1.pop_off, mask + I1.mask_off, t1.x0 + threadIdx.x,
+                                        t1.y0 + threadIdx.y, p1);
+        __builtin_amdgcn_sched_barrier(0);
+        finish(t0, I0, p0);
+        if (has1) {
+            // the first tile's deposit flush has read the wavefront's LDS staging
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            finish(t1, I1, p1);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1134,32 +1167,45 @@ hipError_t bulk_dispatch(const Grid &g, const Phys &ph, const void *A, void *B, 
                  : bulk_shape<ST, false, false>(g, ph, A, B, mask, uin, side, zb, nz, cf, s, fr);
 }
 
-template <int ST, bool OPEN, bool FORCE>
+template <int ST, bool OPEN, bool FORCE, bool SS, int ROWS>
 hipError_t bulk_batch_t(const BatchInst *insts, const BatchTile *tiles, int64_t ntiles, const Phys &ph,
                         const void *A, void *B, const mask_t *mask, const void *uin, const Side &side,
                         double *zb, int32_t nz, hipStream_t s, const ForceReduce &fr)
 {
     using C = Codec<ST>;
     constexpr int BX = BATCH_BX, BY = 256 / BATCH_BX;
-    if (fr.nw > ntiles * 256 * FOLD_CHUNK) return hipErrorInvalidValue;  // more partials than lanes
-    hipLaunchKernelGGL((bulk_batch_kernel<ST, OPEN, FORCE, BX, true>), dim3((unsigned)ntiles), dim3(BX, BY), 0,
-                       s, insts, tiles, ph, static_cast<const typename C::T *>(A),
+    const int64_t nb = (ntiles + ROWS - 1) / ROWS;
+    if (fr.nw > nb * 256 * FOLD_CHUNK) return hipErrorInvalidValue;  // more partials than lanes
+    hipLaunchKernelGGL((bulk_batch_kernel<ST, OPEN, FORCE, BX, SS, ROWS>), dim3((unsigned)nb), dim3(BX, BY), 0,
+                       s, insts, tiles, ntiles, ph, static_cast<const typename C::T *>(A),
                        static_cast<typename C::T *>(B), mask, static_cast<const typename C::R *>(uin), side,
                        zb, nz, fr.wpart, fr.wobj, fr.nw, fr.bank, fr.fsum);
     return hipGetLastError();
 }
 
+template <int ST, bool OPEN, bool FORCE>
+hipError_t bulk_batch_shape(const BatchInst *insts, const BatchTile *tiles, int64_t ntiles, const Phys &ph,
+                            const void *A, void *B, const mask_t *mask, const void *uin, const Side &side,
+                            double *zb, int32_t nz, bool ss, int rows, hipStream_t s, const ForceReduce &fr)
+{
+    if (rows == 2)
+        return ss ? bulk_batch_t<ST, OPEN, FORCE, true, 2>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, s, fr)
+                  : bulk_batch_t<ST, OPEN, FORCE, false, 2>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, s, fr);
+    return ss ? bulk_batch_t<ST, OPEN, FORCE, true, 1>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, s, fr)
+              : bulk_batch_t<ST, OPEN, FORCE, false, 1>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, s, fr);
+}
+
 template <int ST>
 hipError_t bulk_batch_dispatch(const BatchInst *insts, const BatchTile *tiles, int64_t ntiles,
                                const Phys &ph, const void *A, void *B, const mask_t *mask, const void *uin,
-                               const Side &side, double *zb, int32_t nz, bool open, bool force,
-                               hipStream_t s, const ForceReduce &fr)
+                               const Side &side, double *zb, int32_t nz, bool open, bool force, bool ss,
+                               int rows, hipStream_t s, const ForceReduce &fr)
 {
     if (open)
-        return force ? bulk_batch_t<ST, true, true>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, s, fr)
-                     : bulk_batch_t<ST, true, false>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, s, fr);
-    return force ? bulk_batch_t<ST, false, true>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, s, fr)
-                 : bulk_batch_t<ST, false, false>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, s, fr);
+        return force ? bulk_batch_shape<ST, true, true>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, ss, rows, s, fr)
+                     : bulk_batch_shape<ST, true, false>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, ss, rows, s, fr);
+    return force ? bulk_batch_shape<ST, false, true>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, ss, rows, s, fr)
+                 : bulk_batch_shape<ST, false, false>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, ss, rows, s, fr);
 }
 
 template <int ST>
@@ -1216,15 +1262,16 @@ hipError_t launch_bulk(int storage, const Grid &g, const Phys &ph, const void *A
 
 hipError_t launch_bulk_batch(int storage, const BatchInst *insts, const BatchTile *tiles, int64_t ntiles,
                              const Phys &ph, const void *A, void *B, const mask_t *mask, const void *uin,
-                             const Side &side, double *zb, int32_t nz, bool open, bool force, hipStream_t s,
-                             const ForceReduce &fr)
+                             const Side &side, double *zb, int32_t nz, bool open, bool force, bool store_solid,
+                             int rows, hipStream_t s, const ForceReduce &fr)
 {
     if (ntiles <= 0) return fr.nw > 0 ? hipErrorInvalidValue : hipSuccess;
+    if (rows != 1 && rows != 2) return hipErrorInvalidValue;
     switch (storage) {
-    case 0: return bulk_batch_dispatch<0>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, open, force, s, fr);
-    case 1: return bulk_batch_dispatch<1>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, open, force, s, fr);
-    case 2: return bulk_batch_dispatch<2>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, open, force, s, fr);
-    case 3: return bulk_batch_dispatch<3>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, open, force, s, fr);
+    case 0: return bulk_batch_dispatch<0>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, open, force, store_solid, rows, s, fr);
+    case 1: return bulk_batch_dispatch<1>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, open, force, store_solid, rows, s, fr);
+    case 2: return bulk_batch_dispatch<2>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, open, force, store_solid, rows, s, fr);
+    case 3: return bulk_batch_dispatch<3>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, open, force, store_solid, rows, s, fr);
     default: return hipErrorInvalidValue;
     }
 }

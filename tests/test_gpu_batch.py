@@ -149,3 +149,69 @@ def test_benchmark_recipe_instances_match_oracle(B):
                 bad.append((storage, i, eu, cd, cd_ref))
         bt.close()
     assert not bad, bad
+
+
+def _pops_and_forces(B, bt, cases):
+    out = []
+    for i, c in enumerate(cases):
+        r, ux, uy = bt.moments(i)
+        out.append((r, ux, uy, [bt.force(i, o) for o in range(c.n_obj)]))
+    return out
+
+
+def _same_results(a, b):
+    for (ra, ua, va, fa), (rb, ub, vb, fb) in zip(a, b):
+        assert np.array_equal(ra, rb) and np.array_equal(ua, ub) and np.array_equal(va, vb)
+        for (la, sa, na), (lb, sb, nb) in zip(fa, fb):
+            assert na == nb
+            assert np.abs(sa - sb).max() <= 1e-12 * max(np.abs(sb).max(), 1e-30)
+            assert np.abs(la - lb).max() <= 1e-12 * max(np.abs(lb).max(), 1e-30)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64", "bf16"])
+def test_batch_kernel_configs_give_the_same_result(B, storage):
+    """Solid stores, one or two tile-table entries per wavefront (an odd tile count
+    leaves the last block half empty), link block sizes and graph lengths change
+    speed only: bitwise the same moments, forces up to the order of FP64 atomics."""
+    cases = _walled(18, 5)  # 507 tiles
+    n = 37
+    ref = B.Batch(cases, storage=storage)
+    ref.step(n)
+    r0 = _pops_and_forces(B, ref, cases)
+    assert B.lbm_batch_get_kernel_config(ref.b).as_dict() == dict(bulk_store_solid=1, bulk_rows=1,
+                                                                   link_block=256, graph_steps=16)
+    ref.close()
+    for cfg in ((0, 1, 64, 2), (1, 2, 1024, 30), (0, 2, 128, 16), (1, 0, 512, 4)):
+        bt = B.Batch(cases, storage=storage)
+        B.lbm_batch_set_kernel_config(bt.b, B.lbm_batch_kernel_config(*cfg))
+        bt.step(n)
+        print(f"[batch-cfg] {storage} {cfg}", flush=True)
+        _same_results(_pops_and_forces(B, bt, cases), r0)
+        bt.close()
+
+
+def test_batch_autotune_restores_the_state(B):
+    cases = _walled(12, 4)
+    a = B.Batch(cases, storage="f32")
+    a.step(20)
+    cfg, ms = B.lbm_batch_autotune(a.b, 5)
+    assert ms > 0 and B.lbm_batch_step_count(a.b) == 20
+    assert B.lbm_batch_get_kernel_config(a.b).as_dict() == cfg.as_dict()
+    a.step(17)
+    b = B.Batch(cases, storage="f32")
+    b.step(37)
+    _same_results(_pops_and_forces(B, a, cases), _pops_and_forces(B, b, cases))
+    a.close()
+    b.close()
+
+
+def test_invalid_batch_kernel_config_is_rejected(B):
+    bt = B.Batch(_walled(13, 2), storage="f32")
+    for bad in ((2, 1, 256, 16), (0, 3, 256, 16), (0, -1, 256, 16), (0, 1, 100, 16), (0, 1, 2048, 16),
+                (0, 1, 256, 3), (0, 1, 256, 0)):
+        with pytest.raises(B.LbmError) as e:
+            B.lbm_batch_set_kernel_config(bt.b, B.lbm_batch_kernel_config(*bad))
+        assert e.value.status == B.LBM_E_ARG
+    assert B.lbm_batch_get_kernel_config(bt.b).as_dict() == dict(bulk_store_solid=1, bulk_rows=1, link_block=256,
+                                                                  graph_steps=16)
+    bt.close()
