@@ -31,7 +31,7 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1903_01111_amd", "csrc", "lbm_kernels.hip
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "bulk_kernel_porous_8192x2048_f32_counters.txt")
 METRIC = ("MLUPS + % HBM roofline at stated drag/velocity error; "
           "FP16-store & adjoint vs FP32")
-BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "f32w": 4}
 
 
 def kernel_hash():
@@ -44,7 +44,7 @@ def bulk_kernel_name(kcfg, layout, storage):
     if kcfg["bulk_fused"]:
         return None
     b = lambda v: "true" if v else "false"
-    st = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}[storage]
+    st = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3, "f32w": 4}[storage]
     return (f"void bulk_kernel<{st}, false, true, {kcfg['bulk_block_x']}, {b(kcfg['bulk_store_solid'])}, "
             f"{b(layout == 'compact')}, {max(kcfg.get('bulk_rows', 1), 1)}>")
 
@@ -164,6 +164,19 @@ def form_precision(B, case, steps_err, steps_time, layout="compact", steps_long=
     f32.step(steps_long - steps_err)
     _, u32l, v32l = f32.moments()
     f32.close()
+    # FP32 storage with the bulk collision in FP64
+    wide = B.Lattice(case, storage="f32w", layout=layout)
+    wide.step(steps_err)
+    _, uw_, vw_ = wide.moments()
+    _, fsw, _ = wide.force(0)
+    B.lbm_autotune(wide.ctx, 10)
+    ms, link_ms, bulk_ms, ksteps = replay_then_timed(B, wide, steps_time)
+    out["f32w"] = {"e_u_vs_f64": e_u((uw_, vw_), (u64, v64)),
+                   "drag_err_vs_f64": float(abs(fsw[0] - fs64[0]) / abs(fs64[0])), "steps": steps_err,
+                   "mlups": round(case.nx * case.ny * steps_time / (ms * 1e-3) / 1e6, 1),
+                   "bulk_us": round(bulk_ms * 1e3 / ksteps, 2)}
+    wide.close()
+    print(f"[bench] f32w: {out['f32w']}", file=sys.stderr, flush=True)
     for st, kk in (("f16", k), ("bf16", 0)):
         lat = B.Lattice(case, storage=st, dev_scale_log2=kk, layout=layout)
         lat.step(steps_err)

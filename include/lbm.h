@@ -55,12 +55,14 @@ typedef int32_t lbm_status;
 #define LBM_E_UNSTABLE (-6) /* a non-finite value was read back */
 
 /* storage of the populations in device memory.  All store f_i - w_i (deviation
- * from the rest state); F64 computes in FP64, the others in FP32.  The 16-bit
- * forms store (f_i - w_i) * 2^dev_scale_log2 rounded to nearest even. */
+ * from the rest state); F64 computes in FP64, the others in FP32, except that
+ * F32_WIDE runs the bulk collision in FP64 (the boundary links stay FP32).  The
+ * 16-bit forms store (f_i - w_i) * 2^dev_scale_log2 rounded to nearest even. */
 #define LBM_F64 0
 #define LBM_F32 1
 #define LBM_F16_DEV 2
 #define LBM_BF16_DEV 3
+#define LBM_F32_WIDE 4 /* FP32 storage, FP64 collision: no drift from coherent FP32 rounding in steady flows */
 
 /* population layout in device memory */
 #define LBM_LAYOUT_DENSE 0   /* every node of the padded lattice, node (x, y) at y*pitch + x */

@@ -20,12 +20,12 @@ LIB_PATH = os.path.join(HERE, "liblbm_vibb.so")
 
 LBM_OK, LBM_E_ARG, LBM_E_GEOM, LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_STATE, LBM_E_UNSTABLE = (
     0, -1, -2, -3, -4, -5, -6)
-LBM_F64, LBM_F32, LBM_F16_DEV, LBM_BF16_DEV = 0, 1, 2, 3
+LBM_F64, LBM_F32, LBM_F16_DEV, LBM_BF16_DEV, LBM_F32_WIDE = 0, 1, 2, 3, 4
 LBM_X_PERIODIC, LBM_X_OPEN = 0, 1
 LBM_LAYOUT_DENSE, LBM_LAYOUT_COMPACT = 0, 1
 LBM_MAX_LINKS = 1 << 28
 LAYOUT = {"dense": LBM_LAYOUT_DENSE, "compact": LBM_LAYOUT_COMPACT}
-STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16": LBM_F16_DEV, "bf16": LBM_BF16_DEV}
+STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16": LBM_F16_DEV, "bf16": LBM_BF16_DEV, "f32w": LBM_F32_WIDE}
 STATUS_NAMES = {0: "LBM_OK", -1: "LBM_E_ARG", -2: "LBM_E_GEOM", -3: "LBM_E_NOMEM",
                 -4: "LBM_E_DEVICE", -5: "LBM_E_STATE", -6: "LBM_E_UNSTABLE"}
 

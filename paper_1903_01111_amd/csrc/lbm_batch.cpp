@@ -94,7 +94,7 @@ struct lbm_batch {
     }
     lbm::Phys phys(int i) const
     {
-        const float sc = std::ldexp(1.0f, storage >= LBM_F16_DEV ? p[0].dev_scale_log2 : 0);
+        const float sc = std::ldexp(1.0f, lbm_host::storage_is_16bit(storage) ? p[0].dev_scale_log2 : 0);
         return lbm::Phys{1.0 / p[i].tau, p[i].gx, p[i].gy, p[0].rho0, sc, 1.0f / sc};
     }
     lbm::Grid grid(int i) const

@@ -75,7 +75,7 @@ struct lbm_ctx {
     }
     lbm::Phys phys() const
     {
-        const float sc = std::ldexp(1.0f, p.storage >= LBM_F16_DEV ? p.dev_scale_log2 : 0);
+        const float sc = std::ldexp(1.0f, lbm_host::storage_is_16bit(p.storage) ? p.dev_scale_log2 : 0);
         return lbm::Phys{1.0 / p.tau, p.gx, p.gy, p.rho0, sc, 1.0f / sc};
     }
     lbm::Links links() const

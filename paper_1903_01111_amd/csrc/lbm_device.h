@@ -62,6 +62,10 @@ struct Codec<1> {  // LBM_F32
 };
 
 template <>
+struct Codec<4> : Codec<1> {  // LBM_F32_WIDE: stored as LBM_F32
+};
+
+template <>
 struct Codec<2> {  // LBM_F16_DEV
     using T = __half;
     using R = float;
@@ -116,11 +120,18 @@ __device__ __forceinline__ R deq(R w, R eu, R dr, R usq)
 __device__ __forceinline__ float inv_rho_m1_fast(float dr) { return -dr * __builtin_amdgcn_rcpf(1.0f + dr); }
 __device__ __forceinline__ double inv_rho_m1_fast(double dr) { return -dr / (1.0 + dr); }
 // Arithmetic type of the bulk collision: the storage's own arithmetic type (FP64
-// for FP64 storage, FP32 otherwise).  Kept as a separate name so that a storage
-// form can collide wider than it stores.
+// for FP64 storage, FP32 otherwise), and FP64 for the wide FP32 form.  FP32
+// feq and f^eq - f carry absolute rounding errors near 1e-9 (the ulp of the
+// O(1e-2) deviations); wherever the flow is steady the same error recurs every
+// step and adds up like a body force.  FP64 vector FMAs issue at the rate of
+// unpacked FP32 ones on this chip; the cost is the wider registers.
 template <int ST>
 struct Collide {
     using A = typename Codec<ST>::R;
+};
+template <>
+struct Collide<4> {
+    using A = double;
 };
 
 // Element e of a population plane at base.  A plane is smaller than 4 GiB (the

@@ -25,6 +25,7 @@ inline constexpr int64_t STAGE_NODES = 1 << 20;  // nodes per read-back / init c
 size_t align256(size_t v);
 size_t elem_bytes(int storage);
 size_t real_bytes(int storage);
+bool storage_is_16bit(int storage);  // FP16 or BF16 deviations scaled by 2^dev_scale_log2
 
 // Rejects invalid lattice parameters with a reason.
 bool params_ok(const lbm_params *p, std::string *why);

@@ -1227,7 +1227,8 @@ hipError_t launch_link(int storage, const Grid &g, const Phys &ph, const Links &
     if (block < 64 || block > 1024 || block % 64) return hipErrorInvalidValue;
     switch (storage) {
     case 0: return link_t<0>(g, ph, L, side, red, bank, fsum, block, s, defer);
-    case 1: return link_t<1>(g, ph, L, side, red, bank, fsum, block, s, defer);
+    case 1:
+    case 4: return link_t<1>(g, ph, L, side, red, bank, fsum, block, s, defer);
     case 2: return link_t<2>(g, ph, L, side, red, bank, fsum, block, s, defer);
     case 3: return link_t<3>(g, ph, L, side, red, bank, fsum, block, s, defer);
     default: return hipErrorInvalidValue;
@@ -1243,6 +1244,7 @@ hipError_t launch_bulk_fused(int storage, const Grid &g, const Phys &ph, const v
     case 1: return bulk_fused_dispatch<1>(g, ph, A, B, mask, uin, side, fa, zb, nz, cf, s);
     case 2: return bulk_fused_dispatch<2>(g, ph, A, B, mask, uin, side, fa, zb, nz, cf, s);
     case 3: return bulk_fused_dispatch<3>(g, ph, A, B, mask, uin, side, fa, zb, nz, cf, s);
+    case 4: return bulk_fused_dispatch<4>(g, ph, A, B, mask, uin, side, fa, zb, nz, cf, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1256,6 +1258,7 @@ hipError_t launch_bulk(int storage, const Grid &g, const Phys &ph, const void *A
     case 1: return bulk_dispatch<1>(g, ph, A, B, mask, uin, side, zb, nz, cf, s, fr);
     case 2: return bulk_dispatch<2>(g, ph, A, B, mask, uin, side, zb, nz, cf, s, fr);
     case 3: return bulk_dispatch<3>(g, ph, A, B, mask, uin, side, zb, nz, cf, s, fr);
+    case 4: return bulk_dispatch<4>(g, ph, A, B, mask, uin, side, zb, nz, cf, s, fr);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1272,6 +1275,7 @@ hipError_t launch_bulk_batch(int storage, const BatchInst *insts, const BatchTil
     case 1: return bulk_batch_dispatch<1>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, open, force, store_solid, rows, s, fr);
     case 2: return bulk_batch_dispatch<2>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, open, force, store_solid, rows, s, fr);
     case 3: return bulk_batch_dispatch<3>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, open, force, store_solid, rows, s, fr);
+    case 4: return bulk_batch_dispatch<4>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, open, force, store_solid, rows, s, fr);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1281,7 +1285,8 @@ hipError_t launch_refresh(int storage, const Grid &g, const Phys &ph, const void
 {
     switch (storage) {
     case 0: return refresh_t<0>(g, ph, A, side, moments, s);
-    case 1: return refresh_t<1>(g, ph, A, side, moments, s);
+    case 1:
+    case 4: return refresh_t<1>(g, ph, A, side, moments, s);
     case 2: return refresh_t<2>(g, ph, A, side, moments, s);
     case 3: return refresh_t<3>(g, ph, A, side, moments, s);
     default: return hipErrorInvalidValue;
@@ -1328,7 +1333,8 @@ hipError_t launch_init(int storage, const Grid &g, const Phys &ph, void *A, cons
 {
     switch (storage) {
     case 0: return init_t<0>(g, ph, A, mask, stage, y0, rows, s);
-    case 1: return init_t<1>(g, ph, A, mask, stage, y0, rows, s);
+    case 1:
+    case 4: return init_t<1>(g, ph, A, mask, stage, y0, rows, s);
     case 2: return init_t<2>(g, ph, A, mask, stage, y0, rows, s);
     case 3: return init_t<3>(g, ph, A, mask, stage, y0, rows, s);
     default: return hipErrorInvalidValue;
@@ -1340,7 +1346,8 @@ hipError_t launch_moments(int storage, const Grid &g, const Phys &ph, const void
 {
     switch (storage) {
     case 0: return moments_t<0>(g, ph, A, mask, stage, y0, rows, s);
-    case 1: return moments_t<1>(g, ph, A, mask, stage, y0, rows, s);
+    case 1:
+    case 4: return moments_t<1>(g, ph, A, mask, stage, y0, rows, s);
     case 2: return moments_t<2>(g, ph, A, mask, stage, y0, rows, s);
     case 3: return moments_t<3>(g, ph, A, mask, stage, y0, rows, s);
     default: return hipErrorInvalidValue;
@@ -1359,7 +1366,8 @@ hipError_t launch_mass(int storage, const Grid &g, const Phys &ph, const void *A
 {
     switch (storage) {
     case 0: return mass_t<0>(g, ph, A, mask, partials, nb, maxdev, s);
-    case 1: return mass_t<1>(g, ph, A, mask, partials, nb, maxdev, s);
+    case 1:
+    case 4: return mass_t<1>(g, ph, A, mask, partials, nb, maxdev, s);
     case 2: return mass_t<2>(g, ph, A, mask, partials, nb, maxdev, s);
     case 3: return mass_t<3>(g, ph, A, mask, partials, nb, maxdev, s);
     default: return hipErrorInvalidValue;

@@ -25,11 +25,13 @@ size_t elem_bytes(int storage)
 {
     switch (storage) {
     case LBM_F64: return 8;
-    case LBM_F32: return 4;
+    case LBM_F32:
+    case LBM_F32_WIDE: return 4;
     default: return 2;
     }
 }
 size_t real_bytes(int storage) { return storage == LBM_F64 ? 8 : 4; }
+bool storage_is_16bit(int storage) { return storage == LBM_F16_DEV || storage == LBM_BF16_DEV; }
 
 
 // device bytes per link of capacity (link arrays, and up to two flagged nodes
@@ -116,7 +118,7 @@ bool params_ok(const lbm_params *p, std::string *why)
         *why = "an open lattice needs nx >= 3";
         return false;
     }
-    if (p->storage < LBM_F64 || p->storage > LBM_BF16_DEV) {
+    if (p->storage < LBM_F64 || p->storage > LBM_F32_WIDE) {
         *why = "unknown storage";
         return false;
     }
@@ -852,7 +854,7 @@ lbm_status lbm_populations(lbm_ctx *c, double *f)
     if (!c->have_geom || !c->have_init) return c->fail(LBM_E_STATE, "lbm_populations before initialisation");
     const int nx = c->p.nx, ny = c->p.ny, pitch = c->lay.pitch;
     const size_t eb = elem_bytes(c->p.storage);
-    const double inv = std::ldexp(1.0, c->p.storage >= LBM_F16_DEV ? -c->p.dev_scale_log2 : 0);
+    const double inv = std::ldexp(1.0, storage_is_16bit(c->p.storage) ? -c->p.dev_scale_log2 : 0);
     std::vector<lbm::mask_t> mask((size_t)pitch * ny);
     std::vector<char> plane((size_t)pitch * ny * eb);
     lbm_status s;
@@ -879,7 +881,8 @@ lbm_status lbm_populations(lbm_ctx *c, double *f)
                 double d;
                 switch (c->p.storage) {
                 case LBM_F64: std::memcpy(&d, &plane[k * 8], 8); break;
-                case LBM_F32: {
+                case LBM_F32:
+                case LBM_F32_WIDE: {
                     float v;
                     std::memcpy(&v, &plane[k * 4], 4);
                     d = v;

@@ -55,7 +55,7 @@ def _equal_to_single(B, cases, storage, nsteps):
     bt.close()
 
 
-@pytest.mark.parametrize("storage", ["f32", "f64", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "f64", "f16", "f32w"])
 def test_batch_equals_single_open_channels(B, storage):
     _equal_to_single(B, _walled(1, 7), storage, 53)
 

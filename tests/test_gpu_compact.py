@@ -68,7 +68,7 @@ def _same(a, b):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("storage", ["f32", "f64", "f16", "bf16"])
+@pytest.mark.parametrize("storage", ["f32", "f64", "f16", "bf16", "f32w"])
 def test_compact_equals_dense(B, name, storage):
     case = CASES[name]()
     k = 12 if storage == "f16" else 0
