@@ -50,7 +50,7 @@ def test_create_without_gpu_reports_device_error():
 
 
 @pytest.mark.parametrize("kw", [dict(tau=0.5), dict(tau=float("nan")), dict(x_open=True, nx=2),
-                                dict(nx=0), dict(storage=7), dict(n_obj=0), dict(dev_scale_log2=40),
+                                dict(nx=0), dict(storage=5), dict(storage=-1), dict(n_obj=0), dict(dev_scale_log2=40),
                                 dict(layout=2)])
 def test_invalid_params_have_no_workspace(kw):
     nx = kw.pop("nx", 16)
@@ -59,6 +59,12 @@ def test_invalid_params_have_no_workspace(kw):
     with pytest.raises(B.LbmError) as e:
         B.lbm_check_geometry(p, np.zeros((8, max(nx, 1)), np.uint8), [], [], [])
     assert e.value.status == B.LBM_E_ARG
+
+
+def test_wide_fp32_storage_has_the_fp32_footprint():
+    """LBM_F32_WIDE stores FP32 populations (only the collision arithmetic is FP64)."""
+    assert B.lbm_workspace_bytes(B.make_params(100, 37, storage="f32w"), 500) == \
+        B.lbm_workspace_bytes(B.make_params(100, 37), 500)
 
 
 def test_workspace_grows_with_links_and_precision():
