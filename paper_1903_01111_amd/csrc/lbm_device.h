@@ -127,11 +127,18 @@ __device__ __forceinline__ double inv_rho_m1_fast(double dr) { return -dr / (1.0
 // unpacked FP32 ones on this chip; the cost is the wider registers.
 template <int ST>
 struct Collide {
-    using A = typename Codec<ST>::R;
+    using A = typename Codec<ST>::R;  // the collision's arithmetic
+    using D = A;                      // its moments and odd (momentum) parts
+};
+template <>
+struct Collide<1> {
+    using A = float;
+    using D = double;
 };
 template <>
 struct Collide<4> {
     using A = double;
+    using D = double;
 };
 
 // Element e of a population plane at base.  A plane is smaller than 4 GiB (the

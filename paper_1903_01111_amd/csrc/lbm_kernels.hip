@@ -564,13 +564,18 @@ __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
 
     const float inv = ph.inv_scale;
     using A = typename Collide<ST>::A;
+    // the moments and the momentum-carrying (odd) parts of the collision in D
+    using D = typename Collide<ST>::D;
     A f[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) f[i] = A(C::ld(a[i], inv));
 
-    const A drho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
-    const A jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
-    const A jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    // In D, these sums of stored values are exact (FP32 inputs in FP64)
+    const D drho_d = ((D(f[0]) + D(f[1])) + (D(f[2]) + D(f[3]))) + ((D(f[4]) + D(f[5])) + (D(f[6]) + D(f[7]))) +
+                     D(f[8]);
+    const D jx_d = (D(f[1]) - D(f[3])) + (D(f[5]) - D(f[6])) + (D(f[8]) - D(f[7]));
+    const D jy_d = (D(f[2]) - D(f[4])) + (D(f[5]) + D(f[6])) - (D(f[7]) + D(f[8]));
+    const A drho = A(drho_d), jx = A(jx_d), jy = A(jy_d);
     const A ir = inv_rho_m1_fast(drho);
     A ux = jx + jx * ir, uy = jy + jy * ir;
     A Fx = A(0), Fy = A(0);
@@ -594,14 +599,19 @@ __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
     // (1/9 and 1/36 are inexact in binary): the odd parts of the two axis pairs are
     // what the diagonal pairs leave of the equilibrium momentum rho u = j + F/2 (and
     // of the source's (1 - omega/2) F), and the rest population takes what the pairs
-    // leave of the mass.  With rounded weights every collision would add the same
-    // small momentum wherever the flow is steady: a spurious body force of about
-    // 1e-9 per step at |u| = 0.05 in FP32, which shifted the velocity by 1e-5 within
-    // 1000 steps in a forced channel.
+    // leave of the mass.
+    // A population changes by -omega f^neq + source with f^neq = f - f^eq split the
+    // same way: (f_i + f_opp)/2 - ev (small terms, exact sum) +- ((f_i - f_opp)/2 - od).
+    // The odd part subtracts two O(|u|) numbers; done in FP32, its rounding (the ulp
+    // of the O(1e-2) deviations, about 1e-9) recurs every step wherever the flow is
+    // steady and adds up like a body force, so the momenta, od and that difference
+    // are formed in D (FP64 for FP32 storage); each population then changes by one
+    // rounded addition of its small increment.
     const A h15 = A(1.5) * usq;
     const A uF = FORCE ? ux * Fx + uy * Fy : A(0);
     constexpr int PLUS[4] = {1, 2, 5, 6}, MINUS[4] = {3, 4, 7, 8};  // x axis, y axis, two diagonals
-    A ev[4], od[4], gs[4], gd[4];
+    A ev[4], gs[4], gd[4];
+    D od[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int i = PLUS[k];
@@ -609,7 +619,6 @@ __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
         const A eu = A(CX[i]) * ux + A(CY[i]) * uy;
         const A A2 = A(4.5) * eu * eu - h15;
         ev[k] = w * ((A2 + drho * A2) + drho);
-        if (k >= 2) od[k] = (A(3) * w) * (eu + drho * eu);
         if (FORCE) {
             const A eF = A(CX[i]) * Fx + A(CY[i]) * Fy;
             const A cw = cf * w;
@@ -617,9 +626,15 @@ __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
             if (k >= 2) gd[k] = (A(3) * cw) * eF;
         }
     }
-    const A Px = FORCE ? jx + A(0.5) * Fx : jx, Py = FORCE ? jy + A(0.5) * Fy : jy;
-    od[0] = A(0.5) * Px - (od[2] - od[3]);
-    od[1] = A(0.5) * Py - (od[2] + od[3]);
+    {
+        // diagonal odd parts w rho B = (1/12) rho (e.u), from the exact momenta
+        const D Px = FORCE ? jx_d + D(0.5) * D(Fx) : jx_d, Py = FORCE ? jy_d + D(0.5) * D(Fy) : jy_d;
+        const D ru2 = Px + Py, ru3 = Py - Px;  // rho e.u of the diagonals (1,1) and (-1,1)
+        od[2] = ru2 * D(1.0 / 12.0);
+        od[3] = ru3 * D(1.0 / 12.0);
+        od[0] = D(0.5) * Px - (od[2] - od[3]);
+        od[1] = D(0.5) * Py - (od[2] + od[3]);
+    }
     const A ev0 = drho - A(2) * ((ev[0] + ev[1]) + (ev[2] + ev[3]));
     A gs0 = A(0);
     if (FORCE) {
@@ -628,14 +643,15 @@ __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
         gd[1] = hcf * Fy - (gd[2] + gd[3]);
         gs0 = A(-2) * ((gs[0] + gs[1]) + (gs[2] + gs[3]));
     }
-    // each population changes by one rounded addition of its (small) increment
     f[0] = f[0] + (om * (ev0 - f[0]) + gs0);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int i = PLUS[k], j = MINUS[k];
+        const A ne = A(0.5) * (f[i] + f[j]) - ev[k];                    // even part of f^neq
+        const A no = A(D(0.5) * (D(f[i]) - D(f[j])) - od[k]);           // odd part of f^neq
         const A si = FORCE ? gs[k] + gd[k] : A(0), sj = FORCE ? gs[k] - gd[k] : A(0);
-        f[i] = f[i] + (om * ((ev[k] + od[k]) - f[i]) + si);
-        f[j] = f[j] + (om * ((ev[k] - od[k]) - f[j]) + sj);
+        f[i] = f[i] + (si - om * (ne + no));
+        f[j] = f[j] + (sj - om * (ne - no));
     }
 #pragma unroll
     for (int i = 0; i < 9; ++i) st_buf(plane_rsrc(B + i * P, pbytes), own, C::st(R(f[i]), ph.scale));
