@@ -106,7 +106,7 @@ def test_benchmark_recipe_instances_match_oracle(B):
     """Eight instances of the batched benchmark's own recipe (seed 0; nx capped at
     320 so the oracle finishes in seconds; Re up to 100, tau down to 0.526), 1000
     steps in one batch: per-instance velocity and mean drag coefficient against the
-    oracle, in FP64 (to rounding) and in FP32 (the stated FP32 bound).  BGK with
+    oracle, in FP64 (to rounding) and in FP32 (a tenth of the stated bound).  BGK with
     VIBB is unstable as tau -> 1/2: the oracle's run of instance 6 (256x64,
     tau = 0.526) blows up after about 700 steps (|u| far above the speed of
     sound; the GPU in FP64 tracks it to 1e-11 up to step 750), and the batch must
@@ -124,7 +124,7 @@ def test_benchmark_recipe_instances_match_oracle(B):
             refs.append(None if blown_up(uxr, uyr) or not np.isfinite(fs).all() else (uxr, uyr, fs))
     assert [i for i, r in enumerate(refs) if r is None] == [6]
     bad = []
-    for storage, tol_u, tol_f in (("f64", 1e-11, 1e-10), ("f32", 1e-5, 2e-5)):
+    for storage, tol_u, tol_f in (("f64", 1e-11, 1e-10), ("f32", 1e-6, 1e-6)):
         bt = B.Batch(cases, storage=storage)
         bt.step(n)
         for i, (c, ref_i) in enumerate(zip(cases, refs)):
