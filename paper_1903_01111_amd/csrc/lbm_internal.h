@@ -88,8 +88,9 @@ struct Links {
     const int32_t *kof;    // inverse of li (null when li_ident)
 };
 
-// Wavefront partial forces of the link kernel, reduced per object by a second
-// launch: one entry per 64 links of capacity, plus a block of slack.
+// Wavefront partial forces of the link kernel, reduced per object by the first
+// blocks of the next bulk launch (or by force_reduce_kernel): one entry per 64
+// links of capacity, plus a block of slack.
 struct Reduce {
     double2 *wpart;
     int32_t *wobj;

@@ -121,7 +121,7 @@ __global__ __launch_bounds__(1024) void link_kernel(Grid g, Phys ph, Links L, Si
     }
     if (!bank) return;  // link values only: no force wanted (uniform over the grid)
     // FP64 wavefront reduction.  Links are sorted by object, so a wavefront
-    // usually holds one object: it leaves one partial sum for force_reduce_kernel
+    // usually holds one object: it leaves one partial sum for the reduction
     // (no atomics: thousands of wavefronts adding into the same address would
     // serialise).  A wavefront spanning several objects adds per lane.
     const int64_t wave = l >> 6;
