@@ -119,6 +119,9 @@ __device__ __forceinline__ R deq(R w, R eu, R dr, R usq)
 // velocity; the error is a relative 1e-7 of u (dr / (1 + dr) times 1 ulp).
 __device__ __forceinline__ float inv_rho_m1_fast(float dr) { return -dr * __builtin_amdgcn_rcpf(1.0f + dr); }
 __device__ __forceinline__ double inv_rho_m1_fast(double dr) { return -dr / (1.0 + dr); }
+// 1/x: the hardware reciprocal in FP32 (about 1 ulp), a true division in FP64.
+__device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_fast(double x) { return 1.0 / x; }
 // Arithmetic type of the bulk collision: the storage's own arithmetic type (FP64
 // for FP64 storage, FP32 otherwise), and FP64 for the wide FP32 form.  FP32
 // feq and f^eq - f carry absolute rounding errors near 1e-9 (the ulp of the
@@ -227,6 +230,39 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v)
     v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
     v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
     v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return v;
+}
+
+// Sum over the 64 lanes of a wavefront in FP64 with DPP moves of both halves
+// (all lanes must be active): pairs, quads, half-rows, rows, then row 1 += row 0
+// and row 3 += row 2, then row 3 += row 1.  Lane 63 holds the total (the order
+// of the additions is fixed, so the result is deterministic).
+// Permutations within a row (every source lane valid): a plain DPP move.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xf, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+// Row broadcasts into the rows of ROWS; the other rows read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64_rows(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROWS, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROWS, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double wave_sum_to_last(double v)
+{
+    v += dpp_f64<0xb1>(v);             // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4e>(v);             // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);            // row_half_mirror
+    v += dpp_f64<0x140>(v);            // row_mirror
+    v += dpp_f64_rows<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_f64_rows<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
     return v;
 }
 

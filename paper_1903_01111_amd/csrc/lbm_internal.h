@@ -88,9 +88,9 @@ struct Links {
     const int32_t *kof;    // inverse of li (null when li_ident)
 };
 
-// Wavefront partial forces of the link kernel, reduced per object by the first
-// blocks of the next bulk launch (or by force_reduce_kernel): one entry per 64
-// links of capacity, plus a block of slack.
+// Partial forces of the link kernel, one per run of 64 links, reduced per object
+// by the first blocks of the next bulk launch (or by force_reduce_kernel): one
+// entry per 64 links of capacity.
 struct Reduce {
     double2 *wpart;
     int32_t *wobj;
@@ -128,7 +128,7 @@ struct FuseArgs {
 
 // Link values of one step into side.L and, unless force_bank is null, the force
 // of every object added to force_bank and force_sum.  With defer non-null the
-// reduction of the per-wavefront partials is not launched but described in
+// reduction of the per-64-link partials is not launched but described in
 // *defer, for the bulk launch that follows (nw = 0 when there is none).
 hipError_t launch_link(int storage, const Grid &g, const Phys &ph, const Links &L, const Side &side,
                        const Reduce &red, double *force_bank, double *force_sum, int block,

@@ -28,50 +28,87 @@ namespace {
 // Link kernel: one lane per link, reading only compact arrays.
 // ---------------------------------------------------------------------------
 
-// Value of link k (decoded, before storage rounding) from the moments M and the
+// What the evaluation of one link reads: its record and the deposits it
+// points to.
+template <int ST>
+struct LinkIn {
+    using R = typename Codec<ST>::R;
+    using T = typename Codec<ST>::T;
+    uint32_t meta;
+    int32_t sf, sff, pf, pff;
+    R q, uwx, uwy;
+    T pfv, pffv;
+    R drf, ufx, ufy, drff, uffx, uffy;
+};
+
+// First round trip: the per-link record of link k.  The per-link arrays hold at
+// most 2^28 entries of at most 8 bytes, so byte offsets fit 32 bits (scalar base
+// + 32-bit vector offset).
+template <int ST>
+__device__ __forceinline__ void link_load_record(const Links &L, int32_t k, LinkIn<ST> &a)
+{
+    using R = typename Codec<ST>::R;
+    const uint32_t o4 = (uint32_t)k * 4u;
+    a.meta = ld_at(L.meta, o4);
+    a.pf = ld_at(L.pf, o4);
+    a.sf = ld_at(L.sf, o4);
+    a.sff = ld_at(L.sff, o4);
+    a.pff = ld_at(L.pff, o4);
+    a.q = ld_at(static_cast<const R *>(L.q), (uint32_t)k * (uint32_t)sizeof(R));
+    a.uwx = a.uwy = R(0);
+    if (L.uw) {
+        const R *u = static_cast<const R *>(L.uw);
+        a.uwx = u[2 * (int64_t)k];
+        a.uwy = u[2 * (int64_t)k + 1];
+    }
+}
+
+// Second round trip: the deposits of x_f and x_ff the record points to.  Those
+// of ff are fetched for halfway bounce-back links too (from f's slots, in
+// bounds) and not used, so that no load waits on a branch.
+template <int ST>
+__device__ __forceinline__ void link_load_deposits(const void *Mv, const void *Pv, LinkIn<ST> &a)
+{
+    using R = typename Codec<ST>::R;
+    using T = typename Codec<ST>::T;
+    const T *P = static_cast<const T *>(Pv);
+    const R *M = static_cast<const R *>(Mv);
+    const int32_t sffc = a.sff < 0 ? a.sf : a.sff, pffc = a.sff < 0 ? a.pf : a.pff;
+    a.pfv = P[a.pf];
+    a.pffv = P[pffc];
+    a.drf = M[3 * (int64_t)a.sf];
+    a.ufx = M[3 * (int64_t)a.sf + 1];
+    a.ufy = M[3 * (int64_t)a.sf + 2];
+    a.drff = M[3 * (int64_t)sffc];
+    a.uffx = M[3 * (int64_t)sffc + 1];
+    a.uffy = M[3 * (int64_t)sffc + 2];
+}
+
+// Value of a link (decoded, before storage rounding) from the moments M and the
 // populations P deposited by the previous bulk step (Section 3.1, or halfway
 // bounce-back where x_ff is unusable), and its momentum-exchange force: the
 // population f+_{i'}(x_f) into the wall and f_i(x_f) back, both along e_{i'}.
 template <int ST>
-__device__ __forceinline__ typename Codec<ST>::R link_eval(const Phys &ph, const Links &L, const void *Mv,
-                                                           const void *Pv, int64_t k, double &fx, double &fy,
-                                                           int &obj)
+__device__ __forceinline__ typename Codec<ST>::R link_value(const Phys &ph, const LinkIn<ST> &a, double &fx,
+                                                            double &fy, int &obj)
 {
     using C = Codec<ST>;
-    using T = typename C::T;
     using R = typename C::R;
-    // Two round trips: every per-link record first, then every deposit it points
-    // to.  The deposits of ff are fetched for halfway bounce-back links too (from
-    // f's slots, in bounds) and not used, so that no load waits on a branch.
-    const R *qv = static_cast<const R *>(L.q);
-    const T *P = static_cast<const T *>(Pv);
-    const R *M = static_cast<const R *>(Mv);
-    const uint32_t meta = L.meta[k];
-    const int32_t pf = L.pf[k], sf = L.sf[k], sff = L.sff[k], pff = L.pff[k];
-    const R q = qv[k];
-    R uwx = R(0), uwy = R(0);
-    if (L.uw) {
-        const R *u = static_cast<const R *>(L.uw);
-        uwx = u[2 * k];
-        uwy = u[2 * k + 1];
-    }
-    const int32_t sffc = sff < 0 ? sf : sff, pffc = sff < 0 ? pf : pff;
-    const T pfv = P[pf], pffv = P[pffc];
-    const R drf = M[3 * sf], ufx = M[3 * sf + 1], ufy = M[3 * sf + 2];
-    const R drff = M[3 * sffc], uffx = M[3 * sffc + 1], uffy = M[3 * sffc + 2];
-    const int ip = (int)(meta & 15u);
-    obj = (int)(meta >> 8);
+    const R q = a.q, uwx = a.uwx, uwy = a.uwy;
+    const R drf = a.drf, ufx = a.ufx, ufy = a.ufy, drff = a.drff, uffx = a.uffx, uffy = a.uffy;
+    const int ip = (int)(a.meta & 15u);
+    obj = (int)(a.meta >> 8);
     const int cxp = cx_of(ip), cyp = cy_of(ip);
     const R w = ip <= 4 ? R(1) / R(9) : R(1) / R(36);
     // moving-wall momentum term 6 w_{i'} rho0 e_i.u_w, with e_i = -e_{i'}
     const R wall = -R(6) * w * R(ph.rho0) * (R(cxp) * uwx + R(cyp) * uwy);
-    const R fpf = C::ld(pfv, ph.inv_scale);
+    const R fpf = C::ld(a.pfv, ph.inv_scale);
     R v;
     {
         // VIBB from the moments of f and ff at time t, deposited by the previous
         // bulk step; evaluated for every link (no load may sink into a branch),
         // halfway bounce-back links take fpf + wall below instead
-        const R fpff = C::ld(pffv, ph.inv_scale);
+        const R fpff = C::ld(a.pffv, ph.inv_scale);
         const R a2q = R(2) * q, b2q = R(1) - R(2) * q;
         // density at the departure point d (extrapolated when q > 1/2)
         const R drd = a2q * drf + b2q * drff;
@@ -79,31 +116,47 @@ __device__ __forceinline__ typename Codec<ST>::R link_eval(const Phys &ph, const
         // rescaled by rho_d: rho_d/rho_f = 1 + (dr_d - dr_f)/(1 + dr_f)
         const R neqf = fpf - deq(w, R(cxp) * ufx + R(cyp) * ufy, drf, ufx * ufx + ufy * ufy);
         const R neqff = fpff - deq(w, R(cxp) * uffx + R(cyp) * uffy, drff, uffx * uffx + uffy * uffy);
-        const R neqd = a2q * (neqf + neqf * ((drd - drf) / (R(1) + drf))) +
-                       b2q * (neqff + neqff * ((drd - drff) / (R(1) + drff)));
+        const R neqd = a2q * (neqf + neqf * ((drd - drf) * rcp_fast(R(1) + drf))) +
+                       b2q * (neqff + neqff * ((drd - drff) * rcp_fast(R(1) + drff)));
         // velocity at d: u*_d from (f, ff) or (f, wall), u**_d from (ff, wall)
         R usx, usy;
         if (q <= R(0.5)) {
             usx = a2q * ufx + b2q * uffx;
             usy = a2q * ufy + b2q * uffy;
         } else {
-            const R cf = (R(1) - q) / q, cw = (R(2) * q - R(1)) / q;
+            const R iq = rcp_fast(q), cf = (R(1) - q) * iq, cw = (R(2) * q - R(1)) * iq;
             usx = cf * ufx + cw * uwx;
             usy = cf * ufy + cw * uwy;
         }
-        const R inv1q = R(1) / (R(1) + q);
+        const R inv1q = rcp_fast(R(1) + q);
         const R cff = (R(1) - q) * inv1q, cww = a2q * inv1q;
         const R ussx = cff * uffx + cww * uwx, ussy = cff * uffy + cww * uwy;
-        const R udx = (usx + R(2) * ussx) / R(3), udy = (usy + R(2) * ussy) / R(3);
+        const R third = R(1) / R(3);
+        const R udx = (usx + R(2) * ussx) * third, udy = (usy + R(2) * ussy) * third;
         v = deq(w, R(cxp) * udx + R(cyp) * udy, drd, udx * udx + udy * udy) + neqd + wall;
     }
-    if (sff < 0) v = fpf + wall;  // halfway bounce-back
+    if (a.sff < 0) v = fpf + wall;  // halfway bounce-back
     const double m = (double)fpf + (double)v + 2.0 * (double)w;
     fx = cxp * m;
     fy = cyp * m;
     return v;
 }
 
+// One link start to finish (two round trips).
+template <int ST>
+__device__ __forceinline__ typename Codec<ST>::R link_eval(const Phys &ph, const Links &L, const void *Mv,
+                                                           const void *Pv, int32_t k, double &fx, double &fy,
+                                                           int &obj)
+{
+    LinkIn<ST> a;
+    link_load_record<ST>(L, k, a);
+    link_load_deposits<ST>(Mv, Pv, a);
+    return link_value<ST>(ph, a, fx, fy, obj);
+}
+
+// Link kernel: one lane per link.  The kernel is bound by the request stream
+// between the compute units' L1 caches and L2 (the per-link records and the
+// deposit gathers), not by HBM bandwidth, arithmetic or wave count.
 template <int ST>
 __global__ __launch_bounds__(1024) void link_kernel(Grid g, Phys ph, Links L, Side side,
                                                     double2 *__restrict__ wpart, int32_t *__restrict__ wobj,
@@ -111,31 +164,36 @@ __global__ __launch_bounds__(1024) void link_kernel(Grid g, Phys ph, Links L, Si
 {
     using C = Codec<ST>;
     using T = typename C::T;
-    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool active = l < L.n;
+    // XCD k (which gets hardware blocks k, k+8, ...) takes the k-th contiguous
+    // run of link blocks: the links of neighbouring rows gather the same lines of
+    // M and P, which then sit in one L2 instead of being fetched by all eight.
+    const int32_t nb = (int32_t)gridDim.x, q8 = nb >> 3, r8 = nb & 7, k8 = (int32_t)blockIdx.x & 7;
+    const int32_t blk = k8 * q8 + (k8 < r8 ? k8 : r8) + ((int32_t)blockIdx.x >> 3);
+    const int lane = threadIdx.x & 63;
+    // links number below 2^28
+    const int32_t n = (int32_t)L.n;
+    const int32_t k = blk * (int32_t)blockDim.x + (int32_t)threadIdx.x;
     double fx = 0.0, fy = 0.0;
     int obj = -1;
-    if (active) {
-        const auto v = link_eval<ST>(ph, L, side.M, side.P, l, fx, fy, obj);
-        static_cast<T *>(side.L)[L.li_ident ? (int32_t)l : L.li[l]] = C::st(v, ph.scale);
+    if (k < n) {
+        const auto v = link_eval<ST>(ph, L, side.M, side.P, k, fx, fy, obj);
+        st_el(static_cast<T *>(side.L), L.li_ident ? k : ld_at(L.li, (uint32_t)k * 4u), C::st(v, ph.scale));
     }
     if (!bank) return;  // link values only: no force wanted (uniform over the grid)
-    // FP64 wavefront reduction.  Links are sorted by object, so a wavefront
-    // usually holds one object: it leaves one partial sum for the reduction
-    // (no atomics: thousands of wavefronts adding into the same address would
-    // serialise).  A wavefront spanning several objects adds per lane.
-    const int64_t wave = l >> 6;
-    const int obj0 = __shfl(obj, 0);
-    const bool uniform = __all(obj == obj0 || obj < 0);
-    if (uniform) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            fx += __shfl_xor(fx, off);
-            fy += __shfl_xor(fy, off);
-        }
-        if ((threadIdx.x & 63) == 0) {
-            wpart[wave] = make_double2(fx, fy);
-            wobj[wave] = obj0;
+    // FP64 reduction per run of 64 links (entry k/64 of the partials; runs past
+    // the last link write none).  Links are sorted by object, so a run usually
+    // holds one object: it leaves one partial sum for the reduction (no atomics:
+    // thousands of wavefronts adding into the same address would serialise).  A
+    // run spanning several objects adds per lane.
+    const int32_t r0 = k - lane;
+    if (r0 >= n) return;  // wavefront-uniform
+    const int32_t run = r0 >> 6;
+    const int obj0 = __builtin_amdgcn_readlane(obj, 0);
+    if (__all(obj == obj0 || obj < 0)) {
+        const double sx = wave_sum_to_last(fx), sy = wave_sum_to_last(fy);
+        if (lane == 63) {
+            wpart[run] = make_double2(sx, sy);
+            wobj[run] = obj0;
         }
     } else {
         if (obj >= 0) {
@@ -144,7 +202,7 @@ __global__ __launch_bounds__(1024) void link_kernel(Grid g, Phys ph, Links L, Si
             unsafeAtomicAdd(&fsum[2 * obj], fx);
             unsafeAtomicAdd(&fsum[2 * obj + 1], fy);
         }
-        if ((threadIdx.x & 63) == 0) wobj[wave] = -1;
+        if (lane == 0) wobj[run] = -1;
     }
 }
 
@@ -435,7 +493,7 @@ __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
         double fx = 0.0, fy = 0.0;
         int obj = -1;
         for (int j = lane; j < nl; j += 64) {
-            const int64_t k = L.li_ident ? (int64_t)(lw + j) : (int64_t)L.kof[lw + j];
+            const int32_t k = L.li_ident ? lw + j : L.kof[lw + j];
             double lfx, lfy;
             int o;
             const R v = link_eval<ST>(ph, L, side.M, side.P, k, lfx, lfy, o);
@@ -514,7 +572,7 @@ __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
     const uint32_t inc = wave_inclusive_scan(cnt);
     const uint32_t exc = inc - cnt;
     const int32_t pbase = sb.pops + (int32_t)(exc >> 16);
-    const int wave_pops = (int)(__shfl(inc, 63) >> 16);
+    const int wave_pops = (int)((uint32_t)__builtin_amdgcn_readlane((int)inc, 63) >> 16);
     const int wave_flagged = (int)__popcll(flagged);
     // the open columns are written by their neighbour lanes: fetch their records,
     // and keep their deposits out of the wavefront's coalesced flush
@@ -522,18 +580,18 @@ __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
     int32_t pb_in = 0, pb_out = 0, slot_out = 0;
     int m_lo = 0, m_hi = 3 * wave_flagged, p_lo = 0, p_hi = wave_pops;
     if (OPEN) {
-        rec_in = __shfl(rec, 0);
-        pb_in = __shfl(pbase, 0);
-        const uint32_t cnt_in = __shfl(cnt, 0);
+        rec_in = (uint32_t)__builtin_amdgcn_readlane((int)rec, 0);
+        pb_in = __builtin_amdgcn_readlane(pbase, 0);
+        const uint32_t cnt_in = (uint32_t)__builtin_amdgcn_readlane((int)cnt, 0);
         if ((x >> 6) == 0 && (flagged & 1ull)) {
             m_lo = 3;
             p_lo = (int)(cnt_in >> 16);
         }
         const int xe = g.nx - 1;
         const int le = xe & 63;
-        const uint32_t r_e = __shfl(rec, le);
-        const int32_t p_e = __shfl(pbase, le);
-        const uint32_t c_e = __shfl(cnt, le);
+        const uint32_t r_e = (uint32_t)__builtin_amdgcn_readlane((int)rec, le);
+        const int32_t p_e = __builtin_amdgcn_readlane(pbase, le);
+        const uint32_t c_e = (uint32_t)__builtin_amdgcn_readlane((int)cnt, le);
         if ((xe >> 6) == (x >> 6)) {
             rec_out = r_e;
             pb_out = p_e;
@@ -1065,7 +1123,8 @@ hipError_t link_t(const Grid &g, const Phys &ph, const Links &L, const Side &sid
                        red.wobj, bank, fsum);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !bank) return e;
-    const ForceReduce fr{red.wpart, red.wobj, (int64_t)blocks * (block / 64), bank, fsum};
+    // one partial per run of 64 links
+    const ForceReduce fr{red.wpart, red.wobj, (L.n + 63) / 64, bank, fsum};
     if (defer) {
         *defer = fr;
         return hipSuccess;

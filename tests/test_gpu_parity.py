@@ -337,6 +337,32 @@ def test_fused_links_with_several_objects(B, storage):
     ref.close()
 
 
+@pytest.mark.parametrize("storage", ["f32", "f64", "f16"])
+def test_link_blocks_with_several_objects(B, storage):
+    """Link block sizes change speed only, also where runs of 64 links hold two
+    objects (disc object 0, halfway bounce-back walls object 1) and where the
+    last block's wavefronts lie past the last link: bitwise the same
+    populations, every object's force equal up to the order of FP64 atomics."""
+    case = W.walled_cylinder(200, 20.0, 0.41, 0.27)
+    k = 14 if storage == "f16" else 0
+    ref = B.Lattice(case, storage=storage, dev_scale_log2=k)
+    ref.step(29)
+    for lb in (64, 1024):
+        lat = B.Lattice(case, storage=storage, dev_scale_log2=k)
+        B.lbm_set_kernel_config(lat.ctx, B.lbm_kernel_config(256, 1, lb, 16, 1, 0))
+        lat.step(29)
+        print(f"[link-block] {storage} block={lb}", flush=True)
+        assert np.array_equal(lat.populations(), ref.populations())
+        for o in range(case.n_obj):
+            la, sa, na = lat.force(o)
+            lb_, sb, nb = ref.force(o)
+            assert na == nb == 29
+            assert np.abs(sa - sb).max() <= 1e-12 * np.abs(sb).max()
+            assert np.abs(la - lb_).max() <= 1e-12 * np.abs(lb_).max()
+        lat.close()
+    ref.close()
+
+
 @pytest.mark.parametrize("storage", ["f32", "f64", "f16", "bf16", "f32w"])
 def test_two_rows_per_wavefront(B, storage):
     """Two row segments per bulk wavefront change speed only: bitwise the same
