@@ -154,9 +154,10 @@ __device__ __forceinline__ typename Codec<ST>::R link_eval(const Phys &ph, const
     return link_value<ST>(ph, a, fx, fy, obj);
 }
 
-// Link kernel: one lane per link.  The kernel is bound by the request stream
-// between the compute units' L1 caches and L2 (the per-link records and the
-// deposit gathers), not by HBM bandwidth, arithmetic or wave count.
+// Link kernel: one lane per link.  The kernel is bound by its four deposit
+// gathers per link (a wavefront's lanes hit scattered and repeated entries of M
+// and P, served from L2), not by HBM bandwidth, record bytes, arithmetic or wave
+// count.
 template <int ST>
 __global__ __launch_bounds__(1024) void link_kernel(Grid g, Phys ph, Links L, Side side,
                                                     double2 *__restrict__ wpart, int32_t *__restrict__ wobj,
