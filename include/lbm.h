@@ -195,6 +195,15 @@ int64_t lbm_step_count(const lbm_ctx *ctx); /* steps since geometry / set_state 
  * (non-finite value found). */
 lbm_status lbm_moments(lbm_ctx *ctx, double *rho, double *ux, double *uy);
 
+/* The same moments into device arrays of ny*nx values each, index y*nx + x (FP64
+ * when fp64 is nonzero, else rounded to FP32; any may be NULL), enqueued on the
+ * context's stream without waiting.  The arrays are the caller's (e.g. torch
+ * tensors on the context's device) and must hold ny*nx values and stay valid until
+ * the stream has run the kernel.  FP64 values equal those of lbm_moments bitwise.
+ * No finiteness check (lbm_moments does one).  Errors: LBM_E_STATE before
+ * initialisation, LBM_E_DEVICE. */
+lbm_status lbm_moments_device(lbm_ctx *ctx, void *rho, void *ux, void *uy, int32_t fp64);
+
 /* Raw post-collision populations f+_i (including w_i) into a host array of
  * 9*ny*nx doubles, node-major: f[(y*nx + x)*9 + i]; solid nodes read 0. */
 lbm_status lbm_populations(lbm_ctx *ctx, double *f);

@@ -81,6 +81,7 @@ SIGNATURES = [
     ("lbm_sync", _I32, [_P]),
     ("lbm_step_count", _I64, [_P]),
     ("lbm_moments", _I32, [_P, _P, _P, _P]),
+    ("lbm_moments_device", _I32, [_P, _P, _P, _P, C.c_int32]),
     ("lbm_populations", _I32, [_P, _P]),
     ("lbm_force", _I32, [_P, _I32, _P, _P, _P]),
     ("lbm_force_reset", _I32, [_P]),
@@ -274,6 +275,24 @@ def lbm_moments(ctx, ny, nx):
     uy = np.zeros((ny, nx))
     check(lib().lbm_moments(ctx, _p(rho), _p(ux), _p(uy)), ctx)
     return rho, ux, uy
+
+
+def lbm_moments_device(ctx, rho, ux, uy):
+    """lbm_moments into torch tensors on the context's device (any may be None):
+    float64 or float32, all of one dtype, contiguous, ny*nx elements each; enqueued
+    on the context's stream (torch's current stream for a Lattice)."""
+    import torch
+    ts = [t for t in (rho, ux, uy) if t is not None]
+    if not ts:
+        return
+    dt = ts[0].dtype
+    if dt not in (torch.float64, torch.float32) or any(t.dtype != dt for t in ts):
+        raise TypeError("lbm_moments_device: tensors must all be float64 or all float32")
+    n = ts[0].numel()
+    if any(not t.is_cuda or not t.is_contiguous() or t.numel() != n for t in ts):
+        raise ValueError("lbm_moments_device: contiguous device tensors of ny*nx elements expected")
+    ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
+    check(lib().lbm_moments_device(ctx, ptr(rho), ptr(ux), ptr(uy), 1 if dt == torch.float64 else 0), ctx)
 
 
 def lbm_populations(ctx, ny, nx):
@@ -619,6 +638,15 @@ class Lattice:
 
     def moments(self):
         return lbm_moments(self.ctx, self.case.ny, self.case.nx)
+
+    def moments_device(self, dtype=None):
+        """(rho, ux, uy) as (ny, nx) torch tensors on the lattice's device, computed
+        by the GPU on torch's current stream (no host round trip)."""
+        import torch
+        dtype = dtype or torch.float64
+        out = [torch.empty((self.case.ny, self.case.nx), dtype=dtype, device=self.device) for _ in range(3)]
+        lbm_moments_device(self.ctx, *out)
+        return tuple(out)
 
     def populations(self):
         return lbm_populations(self.ctx, self.case.ny, self.case.nx)

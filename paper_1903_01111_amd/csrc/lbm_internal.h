@@ -182,6 +182,11 @@ hipError_t launch_moments(int storage, const Grid &g, const Phys &ph, const void
                           const mask_t *mask, double *stage, int32_t y0, int32_t rows,
                           hipStream_t s);
 
+// Moments of every node into three device arrays of ny*nx values (y*nx + x), FP64
+// or FP32; null arrays are skipped.
+hipError_t launch_moments_out(int storage, const Grid &g, const Phys &ph, const void *A, const mask_t *mask,
+                              void *rho, void *ux, void *uy, bool fp64, hipStream_t s);
+
 // Per-block FP64 partials over the fluid nodes: the mass (sum) or, with maxdev,
 // max |f_i - w_i|; n_partials = number of blocks used.
 hipError_t launch_mass(int storage, const Grid &g, const Phys &ph, const void *A,

@@ -1045,17 +1045,16 @@ __global__ void init_kernel(Grid g, Phys ph, typename Codec<ST>::T *__restrict__
     }
 }
 
+// Density and physical velocity (Guo's half-force shift) of fluid node (x, y) in
+// FP64; 0 for solid nodes.
 template <int ST>
-__global__ void moments_kernel(Grid g, Phys ph, const typename Codec<ST>::T *__restrict__ A,
-                               const mask_t *__restrict__ mask, double *__restrict__ stage,
-                               int32_t y0, int32_t rows)
+__device__ __forceinline__ void node_moments(const Grid &g, const Phys &ph, const typename Codec<ST>::T *__restrict__ A,
+                                             const mask_t *__restrict__ mask, int x, int y, double &rho, double &ux,
+                                             double &uy)
 {
     using C = Codec<ST>;
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= (int64_t)rows * g.nx) return;
-    const int y = y0 + (int)(k / g.nx), x = (int)(k % g.nx);
     if (mask[y * g.pitch + x] & MASK_SOLID) {
-        stage[3 * k] = stage[3 * k + 1] = stage[3 * k + 2] = 0.0;
+        rho = ux = uy = 0.0;
         return;
     }
     const int32_t n = node_offset(g, x, y);
@@ -1067,10 +1066,37 @@ __global__ void moments_kernel(Grid g, Phys ph, const typename Codec<ST>::T *__r
         jx += CX[i] * v;
         jy += CY[i] * v;
     }
-    const double rho = 1.0 + dr;
-    stage[3 * k] = rho;
-    stage[3 * k + 1] = jx / rho - 0.5 * ph.gx;
-    stage[3 * k + 2] = jy / rho - 0.5 * ph.gy;
+    rho = 1.0 + dr;
+    ux = jx / rho - 0.5 * ph.gx;
+    uy = jy / rho - 0.5 * ph.gy;
+}
+
+template <int ST>
+__global__ void moments_kernel(Grid g, Phys ph, const typename Codec<ST>::T *__restrict__ A,
+                               const mask_t *__restrict__ mask, double *__restrict__ stage,
+                               int32_t y0, int32_t rows)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)rows * g.nx) return;
+    const int y = y0 + (int)(k / g.nx), x = (int)(k % g.nx);
+    node_moments<ST>(g, ph, A, mask, x, y, stage[3 * k], stage[3 * k + 1], stage[3 * k + 2]);
+}
+
+// The moments of every node into three caller arrays of ny*nx values (y*nx + x),
+// rounded to OT; a null array is skipped.
+template <int ST, class OT>
+__global__ void moments_out_kernel(Grid g, Phys ph, const typename Codec<ST>::T *__restrict__ A,
+                                   const mask_t *__restrict__ mask, OT *__restrict__ rho, OT *__restrict__ ux,
+                                   OT *__restrict__ uy)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)g.ny * g.nx) return;
+    const int y = (int)(k / g.nx), x = (int)(k % g.nx);
+    double r, vx, vy;
+    node_moments<ST>(g, ph, A, mask, x, y, r, vx, vy);
+    if (rho) rho[k] = (OT)r;
+    if (ux) ux[k] = (OT)vx;
+    if (uy) uy[k] = (OT)vy;
 }
 
 constexpr int MASS_THREADS = 256;
@@ -1391,6 +1417,22 @@ hipError_t moments_t(const Grid &g, const Phys &ph, const void *A, const mask_t 
     return hipGetLastError();
 }
 template <int ST>
+hipError_t moments_out_t(const Grid &g, const Phys &ph, const void *A, const mask_t *mask, void *rho, void *ux,
+                         void *uy, bool fp64, hipStream_t s)
+{
+    const int64_t n = (int64_t)g.ny * g.nx;
+    if (n == 0 || (!rho && !ux && !uy)) return hipSuccess;
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    const auto *a = static_cast<const typename Codec<ST>::T *>(A);
+    if (fp64)
+        hipLaunchKernelGGL((moments_out_kernel<ST, double>), grid, block, 0, s, g, ph, a, mask,
+                           static_cast<double *>(rho), static_cast<double *>(ux), static_cast<double *>(uy));
+    else
+        hipLaunchKernelGGL((moments_out_kernel<ST, float>), grid, block, 0, s, g, ph, a, mask,
+                           static_cast<float *>(rho), static_cast<float *>(ux), static_cast<float *>(uy));
+    return hipGetLastError();
+}
+template <int ST>
 hipError_t mass_t(const Grid &g, const Phys &ph, const void *A, const mask_t *mask,
                   double *partials, int32_t nb, bool maxdev, hipStream_t s)
 {
@@ -1413,6 +1455,19 @@ hipError_t launch_init(int storage, const Grid &g, const Phys &ph, void *A, cons
     case 4: return init_t<1>(g, ph, A, mask, stage, y0, rows, s);
     case 2: return init_t<2>(g, ph, A, mask, stage, y0, rows, s);
     case 3: return init_t<3>(g, ph, A, mask, stage, y0, rows, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_moments_out(int storage, const Grid &g, const Phys &ph, const void *A, const mask_t *mask,
+                              void *rho, void *ux, void *uy, bool fp64, hipStream_t s)
+{
+    switch (storage) {
+    case 0: return moments_out_t<0>(g, ph, A, mask, rho, ux, uy, fp64, s);
+    case 1:
+    case 4: return moments_out_t<1>(g, ph, A, mask, rho, ux, uy, fp64, s);
+    case 2: return moments_out_t<2>(g, ph, A, mask, rho, ux, uy, fp64, s);
+    case 3: return moments_out_t<3>(g, ph, A, mask, rho, ux, uy, fp64, s);
     default: return hipErrorInvalidValue;
     }
 }

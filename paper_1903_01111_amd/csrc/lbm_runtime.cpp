@@ -829,6 +829,16 @@ lbm_status lbm_moments(lbm_ctx *c, double *rho, double *ux, double *uy)
     return LBM_OK;
 }
 
+lbm_status lbm_moments_device(lbm_ctx *c, void *rho, void *ux, void *uy, int32_t fp64)
+{
+    if (!c) return LBM_E_ARG;
+    if (!c->have_geom || !c->have_init)
+        return c->fail(LBM_E_STATE, "lbm_moments_device before initialisation");
+    return c->hip(lbm::launch_moments_out(c->p.storage, c->grid(), c->phys(), c->cur, c->mask(), rho, ux, uy,
+                                          fp64 != 0, c->stream),
+                  "moments kernel");
+}
+
 namespace {
 double half_to_double(uint16_t h)
 {

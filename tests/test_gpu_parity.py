@@ -390,6 +390,44 @@ def test_two_rows_per_wavefront(B, storage):
             ref.close()
 
 
+@pytest.mark.parametrize("storage,layout", [("f64", "dense"), ("f32", "compact"), ("f16", "dense"),
+                                            ("bf16", "compact")])
+def test_moments_device_equal_host_moments(B, storage, layout):
+    """lbm_moments_device writes the moments of lbm_moments into torch tensors on
+    the GPU: bitwise in FP64, the same values rounded in FP32, solid nodes 0, null
+    arrays skipped; before initialisation it is a state error."""
+    import torch
+    k = 12 if storage == "f16" else 0
+    for case in (small_porous(150, 70, seed=9), W.walled_cylinder(204, 20.0, 0.41, 0.27)):
+        lat = B.Lattice(case, storage=storage, dev_scale_log2=k, layout=layout)
+        lat.step(17)
+        rho, ux, uy = lat.moments()
+        d64 = lat.moments_device()
+        d32 = lat.moments_device(torch.float32)
+        torch.cuda.synchronize()
+        print(f"[moments-device] {case.name} {storage} {layout}", flush=True)
+        for dev, host in zip(d64, (rho, ux, uy)):
+            assert np.array_equal(dev.cpu().numpy(), host)
+        for dev, host in zip(d32, (rho, ux, uy)):
+            assert np.array_equal(dev.cpu().numpy(), host.astype(np.float32))
+        only = torch.full((case.ny, case.nx), -7.0, dtype=torch.float64, device=lat.device)
+        B.lbm_moments_device(lat.ctx, None, only, None)
+        torch.cuda.synchronize()
+        assert np.array_equal(only.cpu().numpy(), ux)
+        with pytest.raises(TypeError):
+            B.lbm_moments_device(lat.ctx, d64[0], d32[1], None)
+        lat.close()
+    p = B.make_params(64, 32)
+    n = B.lbm_workspace_bytes(p, 10)
+    ws = torch.empty(n + 256, dtype=torch.uint8, device="cuda")
+    ctx = B.lbm_create(p, ws.data_ptr() + (-ws.data_ptr()) % 256, n)
+    out = torch.empty(64 * 32, dtype=torch.float64, device="cuda")
+    with pytest.raises(B.LbmError) as e:
+        B.lbm_moments_device(ctx, out, None, None)
+    assert e.value.status == B.LBM_E_STATE
+    B.lbm_destroy(ctx)
+
+
 def test_invalid_kernel_config_is_rejected(B):
     lat = B.Lattice(small_cylinder(64, 32, 4.0), storage="f32")
     for bad in ((96, 0, 256, 16), (256, 2, 256, 16), (256, 0, 100, 16), (256, 0, 256, 3), (256, 0, 256, 16, 2),
