@@ -41,20 +41,20 @@ struct LinkIn {
     R drf, ufx, ufy, drff, uffx, uffy;
 };
 
-// First round trip: the per-link record of link k.  The per-link arrays hold at
-// most 2^28 entries of at most 8 bytes, so byte offsets fit 32 bits (scalar base
-// + 32-bit vector offset).
+// First round trip: the per-link record of link k, read once per step through
+// the non-temporal path.  The per-link arrays hold at most 2^28 entries of at most
+// 8 bytes, so byte offsets fit 32 bits (scalar base + 32-bit vector offset).
 template <int ST>
 __device__ __forceinline__ void link_load_record(const Links &L, int32_t k, LinkIn<ST> &a)
 {
     using R = typename Codec<ST>::R;
     const uint32_t o4 = (uint32_t)k * 4u;
-    a.meta = ld_at(L.meta, o4);
-    a.pf = ld_at(L.pf, o4);
-    a.sf = ld_at(L.sf, o4);
-    a.sff = ld_at(L.sff, o4);
-    a.pff = ld_at(L.pff, o4);
-    a.q = ld_at(static_cast<const R *>(L.q), (uint32_t)k * (uint32_t)sizeof(R));
+    a.meta = ld_at_nt(L.meta, o4);
+    a.pf = ld_at_nt(L.pf, o4);
+    a.sf = ld_at_nt(L.sf, o4);
+    a.sff = ld_at_nt(L.sff, o4);
+    a.pff = ld_at_nt(L.pff, o4);
+    a.q = ld_at_nt(static_cast<const R *>(L.q), (uint32_t)k * (uint32_t)sizeof(R));
     a.uwx = a.uwy = R(0);
     if (L.uw) {
         const R *u = static_cast<const R *>(L.uw);
@@ -447,7 +447,13 @@ __device__ __forceinline__ void bulk_issue(const Grid &g, const typename Codec<S
         o[8] = (uint32_t)(rp + xm) * S;
     }
 #pragma unroll
-    for (int i = 0; i < 9; ++i) pl.a[i] = ld_at(A + i * P, o[i]);
+    for (int i = 0; i < 9; ++i) {
+        // compact layout: streamed through once, non-temporal so that the deposits
+        // stay cached for the link kernel; dense layout: neighbouring rows reuse the
+        // lines, which the non-temporal path would drop (all-fluid lattice 4% slower)
+        if (CMP) pl.a[i] = ld_at_nt(A + i * P, o[i]);
+        else pl.a[i] = ld_at(A + i * P, o[i]);
+    }
     pl.own = own;
     pl.own_in = own_in;
     pl.own_out = own_out;
