@@ -156,8 +156,9 @@ __device__ __forceinline__ typename Codec<ST>::R link_eval(const Phys &ph, const
 
 // Link kernel: one lane per link.  The kernel is bound by its four deposit
 // gathers per link (a wavefront's lanes hit scattered and repeated entries of M
-// and P, served from L2), not by HBM bandwidth, record bytes, arithmetic or wave
-// count.
+// and P), not by record bytes, arithmetic or wave count; it runs faster the more
+// of the deposits the Infinity Cache still holds when it starts (hence the
+// non-temporal streaming loads here and in the bulk kernel).
 template <int ST>
 __global__ __launch_bounds__(1024) void link_kernel(Grid g, Phys ph, Links L, Side side,
                                                     double2 *__restrict__ wpart, int32_t *__restrict__ wobj,
