@@ -380,7 +380,7 @@ def main():
     ap.add_argument("--storage", default="f32", choices=list(BYTES))
     ap.add_argument("--layout", default="compact", choices=["dense", "compact"],
                     help="population layout: every node, or the fluid nodes only")
-    ap.add_argument("--cpu-steps", type=int, default=4,
+    ap.add_argument("--cpu-steps", type=int, default=8,
                     help="oracle steps on the full lattice for the CPU baseline (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 1 GiB device copy (counter calibration under rocprofv3)")
