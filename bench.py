@@ -27,7 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_1903_01111_amd", "csrc", "lbm_kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1903_01111_amd", "csrc", f)
+               for f in ("lbm_step_kernels.h", "lbm_device.h", "lbm_kernels.hip", "lbm_internal.h")]
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "bulk_kernel_porous_8192x2048_f32_counters.txt")
 METRIC = ("MLUPS + % HBM roofline at stated drag/velocity error; "
           "FP16-store & adjoint vs FP32")
@@ -35,7 +36,11 @@ BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "f32w": 4}
 
 
 def kernel_hash():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:12]
+    """Hash of the step kernels' sources (a counter summary is valid only for it)."""
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:12]
 
 
 def bulk_kernel_name(kcfg, layout, storage):

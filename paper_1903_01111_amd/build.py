@@ -15,8 +15,13 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "liblbm_vibb.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-HIP_SOURCES = ["lbm_kernels.hip", "lbm_adjoint.hip"]
-CXX_SOURCES = ["lbm_runtime.cpp", "lbm_batch.cpp", "lbm_geometry.cpp", "lbm_adjoint.cpp"]
+# (source, extra flags, object tag): the step kernels are compiled once per storage
+# format (LBM_ST), so that the formats build in parallel
+STORAGE_FORMATS = (0, 1, 2, 3, 4)
+HIP_UNITS = [("lbm_kernels.hip", [f"-DLBM_ST={k}"], f"st{k}") for k in STORAGE_FORMATS] + [
+    ("lbm_adjoint.hip", [], "")]
+CXX_SOURCES = ["lbm_runtime.cpp", "lbm_batch.cpp", "lbm_geometry.cpp", "lbm_adjoint.cpp", "lbm_dispatch.cpp"]
+HIP_SOURCES = sorted({u[0] for u in HIP_UNITS})
 
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
                # packed FP32 instructions are kept out of the generated code
@@ -33,11 +38,12 @@ def _inc():
     return ["-I", os.path.join(ROOT, "include"), "-I", CSRC, "-I", os.path.join(ROCM, "include")]
 
 
-def _compile(src, verbose):
+def _compile(unit, verbose):
+    src, extra, tag = unit if isinstance(unit, tuple) else (unit, [], "")
     path = os.path.join(CSRC, src)
-    obj = os.path.join(BUILD, src + ".o")
+    obj = os.path.join(BUILD, src + (f".{tag}" if tag else "") + ".o")
     if src.endswith(".hip"):
-        cmd = [os.path.join(ROCM, "bin", "hipcc"), *HIPCC_FLAGS, *_inc(), "-c", path, "-o", obj]
+        cmd = [os.path.join(ROCM, "bin", "hipcc"), *HIPCC_FLAGS, *extra, *_inc(), "-c", path, "-o", obj]
     else:
         cmd = ["g++", *CXX_FLAGS, *_inc(), "-c", path, "-o", obj]
     if verbose:
@@ -50,7 +56,7 @@ def _compile(src, verbose):
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    srcs = HIP_SOURCES + CXX_SOURCES
+    srcs = HIP_UNITS + CXX_SOURCES
     with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
     tmp = LIB + ".tmp"

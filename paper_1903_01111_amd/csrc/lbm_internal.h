@@ -194,6 +194,39 @@ hipError_t launch_mass(int storage, const Grid &g, const Phys &ph, const void *A
                        hipStream_t s);
 
 int32_t mass_blocks(const Grid &g);
+constexpr int MASS_THREADS = 256;  // lanes per block of the mass / deviation reduction
+
+// The launch helpers of one storage format, defined by lbm_kernels.hip compiled
+// with LBM_ST = 0..4 (one object per format, so that the formats build in
+// parallel); the launch_* functions above dispatch on the storage.  Format 4
+// (FP32 storage, FP64 collision) defines only the bulk launches and shares the
+// others with format 1.
+#define LBM_ST_DECLS(K)                                                                                       \
+    hipError_t launch_link_st##K(const Grid &, const Phys &, const Links &, const Side &, const Reduce &,      \
+                                 double *, double *, int, hipStream_t, ForceReduce *);                         \
+    hipError_t launch_bulk_st##K(const Grid &, const Phys &, const void *, void *, const mask_t *, const void *, \
+                                 const Side &, double *, int32_t, const BulkConfig &, hipStream_t,             \
+                                 const ForceReduce &);                                                         \
+    hipError_t launch_bulk_fused_st##K(const Grid &, const Phys &, const void *, void *, const mask_t *,         \
+                                       const void *, const Side &, const FuseArgs &, double *, int32_t,          \
+                                       const BulkConfig &, hipStream_t);                                       \
+    hipError_t launch_bulk_batch_st##K(const BatchInst *, const BatchTile *, int64_t, const Phys &, const void *, \
+                                       void *, const mask_t *, const void *, const Side &, double *, int32_t,   \
+                                       bool, bool, bool, int, hipStream_t, const ForceReduce &);               \
+    hipError_t launch_refresh_st##K(const Grid &, const Phys &, const void *, const Side &, bool, hipStream_t); \
+    hipError_t launch_init_st##K(const Grid &, const Phys &, void *, const mask_t *, const double *, int32_t,  \
+                                 int32_t, hipStream_t);                                                        \
+    hipError_t launch_moments_st##K(const Grid &, const Phys &, const void *, const mask_t *, double *, int32_t, \
+                                    int32_t, hipStream_t);                                                     \
+    hipError_t launch_moments_out_st##K(const Grid &, const Phys &, const void *, const mask_t *, void *, void *, \
+                                        void *, bool, hipStream_t);                                            \
+    hipError_t launch_mass_st##K(const Grid &, const Phys &, const void *, const mask_t *, double *, int32_t,   \
+                                 bool, hipStream_t);
+LBM_ST_DECLS(0)
+LBM_ST_DECLS(1)
+LBM_ST_DECLS(2)
+LBM_ST_DECLS(3)
+LBM_ST_DECLS(4)
 
 // ---------------------------------------------------------------------------
 // Adjoint kernels (lbm_adjoint.hip); FP64 and FP32 storage only.  Side records
