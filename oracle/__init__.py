@@ -8,6 +8,10 @@ arrays through ctypes.  Populations are node-major arrays of shape
 
 Pass ``complex_step=True`` to the functions that take it to run the same
 arithmetic on complex128 inputs (exact derivatives by complex step).
+
+``threads=n`` runs the per-node loops of a run on n threads through the OpenMP
+build of the same source (bitwise the serial results); it is used to time the
+oracle on all host cores and to run it on full-size workloads.
 """
 from __future__ import annotations
 
@@ -20,12 +24,20 @@ import numpy as np
 from . import build as _build
 
 _lib = None
+_lib_omp = None
+
+# boundary schemes of the link list (Section 3)
+SCHEME_VIBB, SCHEME_HBB, SCHEME_BOUZIDI, SCHEME_YU = 0, 1, 2, 3
+# relaxation rates of the conserved moments rho, j_x, j_y as printed in Section 2
+# (they do not change the result: those moments are conserved)
+MRT_S_CONSERVED = 0.3
 
 
 class _Params(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("x_open", C.c_int32),
                 ("n_obj", C.c_int32), ("tau", C.c_double), ("gx", C.c_double),
-                ("gy", C.c_double), ("rho0", C.c_double)]
+                ("gy", C.c_double), ("rho0", C.c_double), ("collision", C.c_int32),
+                ("gi_mea", C.c_int32), ("s", C.c_double * 9)]
 
 
 class _Cplx(C.Structure):
@@ -33,19 +45,40 @@ class _Cplx(C.Structure):
     _fields_ = [("re", C.c_double), ("im", C.c_double)]
 
 
+def _load(omp):
+    h = C.CDLL(_build.ensure_built(omp))
+    for pre, cplx in (("orc_", False), ("orc_cs_", True)):
+        for name in ("equilibrium", "vibb", "hbb", "bouzidi", "yu", "mass"):
+            getattr(h, pre + name).restype = _Cplx if cplx else C.c_double
+        getattr(h, pre + "geometry").restype = C.c_int64
+        getattr(h, pre + "step").restype = C.c_int
+        getattr(h, pre + "run").restype = C.c_int
+    h.orc_threads.restype = C.c_int
+    h.orc_threads.argtypes = [C.c_int]
+    return h
+
+
 def lib():
     global _lib
     if _lib is None:
-        _lib = C.CDLL(_build.ensure_built())
-        for pre, cplx in (("orc_", False), ("orc_cs_", True)):
-            getattr(_lib, pre + "equilibrium").restype = _Cplx if cplx else C.c_double
-            getattr(_lib, pre + "vibb").restype = _Cplx if cplx else C.c_double
-            getattr(_lib, pre + "hbb").restype = _Cplx if cplx else C.c_double
-            getattr(_lib, pre + "mass").restype = _Cplx if cplx else C.c_double
-            getattr(_lib, pre + "geometry").restype = C.c_int64
-            getattr(_lib, pre + "step").restype = C.c_int
-            getattr(_lib, pre + "run").restype = C.c_int
+        _lib = _load(False)
     return _lib
+
+
+def lib_omp():
+    """The OpenMP build (same source; per-node loops over rows in parallel)."""
+    global _lib_omp
+    if _lib_omp is None:
+        _lib_omp = _load(True)
+    return _lib_omp
+
+
+def threads_for(threads):
+    """Library and thread count for a run: the serial build for None or 1."""
+    if threads is None or threads <= 1:
+        return lib(), 1
+    h = lib_omp()
+    return h, h.orc_threads(int(threads))
 
 
 def _p(a):
@@ -111,6 +144,61 @@ def vibb(ip, fp_f, fp_ff, q, uw=(0.0, 0.0), rho0=1.0, g=(0.0, 0.0), complex_step
     return _out(r, cs)
 
 
+def bouzidi(ip, fp_f, fp_ff, q, uw=(0.0, 0.0), rho0=1.0, complex_step=False):
+    """Missing population of one link by Bouzidi's interpolated bounce-back."""
+    cs = complex_step
+    t = _Cplx if cs else C.c_double
+    a = np.ascontiguousarray(fp_f, dtype=_real(cs))
+    b = np.ascontiguousarray(fp_ff, dtype=_real(cs))
+    r = _call_scalar_fn("bouzidi", cs, [C.c_int, C.c_void_p, C.c_void_p, t, t, t, C.c_double],
+                        int(ip), _p(a), _p(b), _cval(q, cs), _cval(uw[0], cs), _cval(uw[1], cs),
+                        C.c_double(rho0))
+    return _out(r, cs)
+
+
+def yu(ip, fp_f, fp_ff, q, uw=(0.0, 0.0), rho0=1.0, complex_step=False):
+    """Missing population of one link by Yu's unified interpolated bounce-back."""
+    cs = complex_step
+    t = _Cplx if cs else C.c_double
+    a = np.ascontiguousarray(fp_f, dtype=_real(cs))
+    b = np.ascontiguousarray(fp_ff, dtype=_real(cs))
+    r = _call_scalar_fn("yu", cs, [C.c_int, C.c_void_p, C.c_void_p, t, t, t, C.c_double],
+                        int(ip), _p(a), _p(b), _cval(q, cs), _cval(uw[0], cs), _cval(uw[1], cs),
+                        C.c_double(rho0))
+    return _out(r, cs)
+
+
+def mrt_matrix():
+    """The oracle's MRT transform matrix M (9x9 integers)."""
+    m = np.zeros(81, np.int32)
+    lib().orc_mrt_matrix(_p(m))
+    return m.reshape(9, 9)
+
+
+def mrt_inverse():
+    """The oracle's M^-1 (Gauss-Jordan)."""
+    m = np.zeros(81)
+    lib().orc_mrt_inverse(_p(m))
+    return m.reshape(9, 9)
+
+
+def mrt_meq(rho, ux, uy):
+    """Equilibrium moments m^eq(rho, u) as the oracle takes them."""
+    out = np.zeros(9)
+    fn = lib().orc_mrt_meq
+    fn.argtypes = [C.c_double, C.c_double, C.c_double, C.c_void_p]
+    fn(rho, ux, uy, _p(out))
+    return out
+
+
+def collide_node(f, *, tau, g=(0.0, 0.0), collision="bgk", mrt_s=None):
+    """One node's collision (pre-collision f, 9 values) as the oracle's step does it."""
+    a = np.ascontiguousarray(f, dtype=np.float64).copy()
+    p = _params(1, 1, False, tau, g[0], g[1], 1.0, 1, collision, mrt_s, False)
+    lib().orc_collide_node(C.byref(p), _p(a))
+    return a
+
+
 def hbb(ip, fp_f, uw=(0.0, 0.0), rho0=1.0, complex_step=False):
     cs = complex_step
     t = _Cplx if cs else C.c_double
@@ -160,8 +248,21 @@ def geometry(nx, ny, x_open, kind, geo, mot, obj, complex_step=False) -> Geometr
     return Geometry(solid, node, d, q, uw, ob)
 
 
-def _params(nx, ny, x_open, tau, gx, gy, rho0, n_obj):
-    return _Params(nx, ny, int(x_open), n_obj, tau, gx, gy, rho0)
+def mrt_rates(tau, mrt_s=None):
+    """The nine rates of S (Section 2): the conserved moments at the printed 0.3,
+    (s_e, s_eps, s_q) = mrt_s (the printed 1.5, 1.5, 1.2 by default) and
+    s_7 = s_8 = 1/tau."""
+    se, seps, sq = (1.5, 1.5, 1.2) if mrt_s is None else mrt_s
+    c = MRT_S_CONSERVED
+    return (c, se, seps, c, sq, c, sq, 1.0 / tau, 1.0 / tau)
+
+
+def _params(nx, ny, x_open, tau, gx, gy, rho0, n_obj, collision="bgk", mrt_s=None, gi_mea=False):
+    if collision not in ("bgk", "mrt"):
+        raise ValueError(f"unknown collision {collision!r}")
+    s = (C.c_double * 9)(*mrt_rates(tau, mrt_s))
+    return _Params(nx, ny, int(x_open), n_obj, tau, gx, gy, rho0, 1 if collision == "mrt" else 0,
+                   1 if gi_mea else 0, s)
 
 
 def init_equilibrium(solid, rho, ux, uy, complex_step=False):
@@ -182,19 +283,22 @@ class OracleError(RuntimeError):
 
 
 def run(fp, geom: Geometry, *, tau, gx=0.0, gy=0.0, rho0=1.0, x_open=False, n_obj=1,
-        nsteps=1, u_in=None, scheme=None, history=False, complex_step=False):
+        nsteps=1, u_in=None, scheme=None, history=False, complex_step=False, collision="bgk",
+        mrt_s=None, gi_mea=False, threads=None):
     """Advances fp (modified in place) by nsteps.  Returns (force_sum (n_obj,2),
-    force_hist (nsteps,n_obj,2) or None, n_fallback)."""
+    force_hist (nsteps,n_obj,2) or None, n_fallback).  n_fallback counts the links
+    whose scheme needs x_ff where it is unusable (halfway bounce-back instead)."""
     cs = complex_step
     ny, nx, _ = fp.shape
     assert fp.dtype == _real(cs) and fp.flags.c_contiguous
-    p = _params(nx, ny, x_open, tau, gx, gy, rho0, n_obj)
+    p = _params(nx, ny, x_open, tau, gx, gy, rho0, n_obj, collision, mrt_s, gi_mea)
+    h, _ = threads_for(threads)
     uin = np.zeros((ny, 2), _real(cs)) if u_in is None else np.ascontiguousarray(u_in, _real(cs))
     fsum = np.zeros((n_obj, 2), _real(cs))
     fh = np.zeros((nsteps, n_obj, 2), _real(cs)) if history else None
     nfb = C.c_int64(0)
     sch = None if scheme is None else np.ascontiguousarray(scheme, np.int8)
-    st = getattr(lib(), _pre(cs) + "run")(
+    st = getattr(h, _pre(cs) + "run")(
         C.byref(p), _p(geom.solid), C.c_int64(len(geom.node)), _p(geom.node), _p(geom.dir),
         _p(np.ascontiguousarray(geom.q, _real(cs))), _p(np.ascontiguousarray(geom.uw, _real(cs))),
         _p(geom.obj), _p(sch), _p(uin), _p(fp), C.c_int64(nsteps), _p(fh), _p(fsum),
@@ -205,11 +309,11 @@ def run(fp, geom: Geometry, *, tau, gx=0.0, gy=0.0, rho0=1.0, x_open=False, n_ob
 
 
 def step_links(fp, geom: Geometry, *, tau, gx=0.0, gy=0.0, rho0=1.0, x_open=False, n_obj=1,
-               u_in=None, scheme=None):
+               u_in=None, scheme=None, collision="bgk", mrt_s=None, gi_mea=False):
     """One step in place; returns (force (n_obj,2), missing population of every link)."""
     ny, nx, _ = fp.shape
     assert fp.dtype == np.float64 and fp.flags.c_contiguous
-    p = _params(nx, ny, x_open, tau, gx, gy, rho0, n_obj)
+    p = _params(nx, ny, x_open, tau, gx, gy, rho0, n_obj, collision, mrt_s, gi_mea)
     uin = np.zeros((ny, 2)) if u_in is None else np.ascontiguousarray(u_in, np.float64)
     force = np.zeros((n_obj, 2))
     lo = np.zeros(len(geom.node))
@@ -223,14 +327,16 @@ def step_links(fp, geom: Geometry, *, tau, gx=0.0, gy=0.0, rho0=1.0, x_open=Fals
     return force, lo
 
 
-def moments(fp, solid, g=(0.0, 0.0)):
+def moments(fp, solid, g=(0.0, 0.0), threads=None):
     ny, nx, _ = fp.shape
     cs = fp.dtype == np.complex128
     p = _params(nx, ny, 0, 1.0, g[0], g[1], 1.0, 1)
     rho = np.zeros((ny, nx), fp.dtype)
     ux = np.zeros((ny, nx), fp.dtype)
     uy = np.zeros((ny, nx), fp.dtype)
-    getattr(lib(), _pre(cs) + "moments")(C.byref(p), _p(solid), _p(fp), _p(rho), _p(ux), _p(uy))
+    h, _ = threads_for(threads)
+    getattr(h, _pre(cs) + "moments")(C.byref(p), _p(np.ascontiguousarray(solid, np.uint8)), _p(fp),
+                                     _p(rho), _p(ux), _p(uy))
     return rho, ux, uy
 
 
@@ -255,7 +361,13 @@ def case_scheme(case, geom: Geometry) -> Optional[np.ndarray]:
     return np.asarray(case.scheme_of_obj, np.int8)[geom.obj]
 
 
-def run_case(case, nsteps=None, history=False, geom: Optional[Geometry] = None):
+def case_kwargs(case):
+    """Collision, rates and force form of a workloads.Case as run() keywords."""
+    return dict(collision=getattr(case, "collision", "bgk"), mrt_s=getattr(case, "mrt_s", None),
+                gi_mea=getattr(case, "gi_mea", False))
+
+
+def run_case(case, nsteps=None, history=False, geom: Optional[Geometry] = None, threads=None):
     """Initialises a workloads.Case at equilibrium and runs it; returns
     (fp, geom, force_sum, force_hist, n_fallback)."""
     g = geom if geom is not None else case_geometry(case)
@@ -264,5 +376,6 @@ def run_case(case, nsteps=None, history=False, geom: Optional[Geometry] = None):
     n = case.nsteps if nsteps is None else nsteps
     fs, fh, nfb = run(fp, g, tau=case.tau, gx=case.gx, gy=case.gy, rho0=case.rho0,
                       x_open=case.x_open, n_obj=case.n_obj, nsteps=n, u_in=case.inlet(),
-                      scheme=case_scheme(case, g), history=history)
+                      scheme=case_scheme(case, g), history=history, threads=threads,
+                      **case_kwargs(case))
     return fp, g, fs, fh, nfb

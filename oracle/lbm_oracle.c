@@ -22,12 +22,21 @@
  *
  * Readings of the paper that this file takes where the text is silent or
  * ambiguous are marked "reading:".
+ *
+ * Built with -fopenmp (a separate library used only to time the oracle and to
+ * compare large workloads), the per-node loops of streaming, collision, the
+ * open columns and the moments run over rows in parallel; every node's
+ * arithmetic is the same, so the results are bitwise those of the serial build.
+ * The link loop and the force sums stay serial.
  */
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
 #include <complex.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #ifdef ORC_COMPLEX
 typedef double _Complex real_t;
@@ -158,6 +167,41 @@ real_t ORC(hbb)(int ip, const real_t *fp_f, real_t uwx, real_t uwy, double rho0)
 {
     int i = opposite(ip);
     return fp_f[ip] + 6.0 * weight(ip) * rho0 * (EX[i] * uwx + EY[i] * uwy);
+}
+
+/* Bouzidi's linear interpolated bounce-back (Section 3, the two equations for
+ * q <= 1/2 and q > 1/2), with the same moving-wall term:
+ *   q <= 1/2:  f_i(x_f,t+1) = 2q f+_{i'}(x_f) + (1-2q) f+_{i'}(x_ff) + wall
+ *   q >  1/2:  f_i(x_f,t+1) = (f+_{i'}(x_f) + wall)/(2q) + (2q-1)/(2q) f+_i(x_f)
+ * reading: the last term of the q > 1/2 equation, printed as f_i(x_f, t), is
+ * the post-collision population f+_i(x_f, t) of the outgoing direction i (the
+ * value that streams to x_ff at t+1).  For q > 1/2 the node ff is not used. */
+real_t ORC(bouzidi)(int ip, const real_t *fp_f, const real_t *fp_ff, real_t q, real_t uwx, real_t uwy,
+                    double rho0)
+{
+    int i = opposite(ip);
+    real_t wall = 6.0 * weight(ip) * rho0 * (EX[i] * uwx + EY[i] * uwy);
+    if (RE(q) <= 0.5) return 2.0 * q * fp_f[ip] + (1.0 - 2.0 * q) * fp_ff[ip] + wall;
+    return (fp_f[ip] + wall) / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * fp_f[i];
+}
+
+/* Yu's unified interpolated bounce-back (Section 3): the population at the
+ * wall point first, by linear interpolation of f+_{i'} between x_f and x_ff and
+ * bounce-back with the moving-wall term,
+ *   f_i(x_w, t+1) = q f+_{i'}(x_f) + (1-q) f+_{i'}(x_ff) + wall,
+ * then the unknown at x_f by interpolation between x_w and x_ff,
+ *   f_i(x_f, t+1) = [f_i(x_w, t+1) + q f_i(x_ff, t+1)] / (1+q).
+ * reading: the second equation has an unbalanced parenthesis as printed; it is
+ * read as the linear interpolation above (x_w at distance q from x_f on one
+ * side, x_ff at distance 1 on the other).  f_i(x_ff, t+1) is what streams into
+ * x_ff from x_f, i.e. f+_i(x_f, t). */
+real_t ORC(yu)(int ip, const real_t *fp_f, const real_t *fp_ff, real_t q, real_t uwx, real_t uwy, double rho0)
+{
+    int i = opposite(ip);
+    real_t wall = 6.0 * weight(ip) * rho0 * (EX[i] * uwx + EY[i] * uwy);
+    real_t fw = q * fp_f[ip] + (1.0 - q) * fp_ff[ip] + wall;
+    real_t fff = fp_f[i];
+    return (fw + q * fff) / (1.0 + q);
 }
 
 /* ---------------------------------------------------------------------------
@@ -302,13 +346,31 @@ int64_t ORC(geometry)(int nx, int ny, int x_open, int nprim, const int32_t *ptyp
  * Time stepping.
  * ------------------------------------------------------------------------- */
 typedef struct {
-    int32_t nx, ny;  /* node index y*nx + x */
-    int32_t x_open;  /* 0: periodic in x; 1: inlet at x = 0 and outlet at x = nx-1 */
-    int32_t n_obj;   /* number of force accumulators */
-    double tau;      /* BGK relaxation time, tau = 3 nu + 1/2 (Section 2) */
-    double gx, gy;   /* body acceleration (force density F = rho g) */
-    double rho0;     /* reference density of the moving-wall term */
+    int32_t nx, ny;     /* node index y*nx + x */
+    int32_t x_open;     /* 0: periodic in x; 1: inlet at x = 0 and outlet at x = nx-1 */
+    int32_t n_obj;      /* number of force accumulators */
+    double tau;         /* BGK relaxation time, tau = 3 nu + 1/2 (Section 2) */
+    double gx, gy;      /* body acceleration (force density F = rho g) */
+    double rho0;        /* reference density of the moving-wall term */
+    int32_t collision;  /* 0: BGK; 1: MRT with the rates s[] (Section 2) */
+    int32_t gi_mea;     /* 0: plain momentum exchange; 1: its Galilean-invariant form */
+    double s[9];        /* MRT relaxation rates, one per moment of M (collision == 1) */
 } orc_params;
+
+/* threads of the OpenMP build (ignored by the serial build); returns the count
+ * the parallel loops will use (1 in the serial build) */
+#ifndef ORC_COMPLEX
+int orc_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+#endif
 
 /* f+ = f^eq(rho, u) at every fluid node; solid nodes hold zeros */
 void ORC(init_equilibrium)(int nx, int ny, const uint8_t *solid, const real_t *rho,
@@ -322,12 +384,128 @@ void ORC(init_equilibrium)(int nx, int ny, const uint8_t *solid, const real_t *r
 void ORC(moments)(const orc_params *p, const uint8_t *solid, const real_t *fp,
                   real_t *rho, real_t *ux, real_t *uy)
 {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
     for (int n = 0; n < p->nx * p->ny; ++n) {
         if (solid[n]) {
             rho[n] = ux[n] = uy[n] = 0;
             continue;
         }
         moments_post(fp + 9 * n, p->gx, p->gy, &rho[n], &ux[n], &uy[n]);
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * MRT collision (Section 2): Omega = M^-1 S (m^eq - m), m = M f, with the
+ * transform matrix M as printed (moments rho, e, epsilon, j_x, q_x, j_y, q_y,
+ * p_xx, p_xy) and the diagonal relaxation matrix S.
+ * ------------------------------------------------------------------------- */
+static const int MRT_M[9][9] = {
+    {1, 1, 1, 1, 1, 1, 1, 1, 1},       {-4, -1, -1, -1, -1, 2, 2, 2, 2}, {4, -2, -2, -2, -2, 1, 1, 1, 1},
+    {0, 1, 0, -1, 0, 1, -1, -1, 1},    {0, -2, 0, 2, 0, 1, -1, -1, 1},   {0, 0, 1, 0, -1, 1, 1, -1, -1},
+    {0, 0, -2, 0, 2, 1, 1, -1, -1},    {0, 1, -1, 1, -1, 0, 0, 0, 0},    {0, 0, 0, 0, 0, 1, -1, 1, -1}};
+
+#ifndef ORC_COMPLEX
+void orc_mrt_matrix(int32_t *out81)
+{
+    for (int k = 0; k < 81; ++k) out81[k] = MRT_M[k / 9][k % 9];
+}
+#endif
+
+/* M^-1 by Gauss-Jordan elimination with partial pivoting (computed once) */
+static double MRT_MINV[9][9];
+static int mrt_minv_ready = 0;
+
+static void mrt_inverse(void)
+{
+    if (mrt_minv_ready) return;
+    double a[9][18];
+    for (int r = 0; r < 9; ++r)
+        for (int c = 0; c < 18; ++c) a[r][c] = c < 9 ? MRT_M[r][c] : (c - 9 == r ? 1.0 : 0.0);
+    for (int c = 0; c < 9; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 9; ++r)
+            if (fabs(a[r][c]) > fabs(a[piv][c])) piv = r;
+        for (int k = 0; k < 18; ++k) {
+            double tmp = a[c][k];
+            a[c][k] = a[piv][k];
+            a[piv][k] = tmp;
+        }
+        double d = a[c][c];
+        for (int k = 0; k < 18; ++k) a[c][k] /= d;
+        for (int r = 0; r < 9; ++r) {
+            if (r == c) continue;
+            double m = a[r][c];
+            for (int k = 0; k < 18; ++k) a[r][k] -= m * a[c][k];
+        }
+    }
+    for (int r = 0; r < 9; ++r)
+        for (int c = 0; c < 9; ++c) MRT_MINV[r][c] = a[r][c + 9];
+    mrt_minv_ready = 1;
+}
+
+#ifndef ORC_COMPLEX
+void orc_mrt_inverse(double *out81)
+{
+    mrt_inverse();
+    for (int k = 0; k < 81; ++k) out81[k] = MRT_MINV[k / 9][k % 9];
+}
+#endif
+
+/* Equilibrium moments.  reading: the printed e^eq and epsilon^eq, rho(-2 + 3 j.j)
+ * and rho(1 - 3 j.j), mix j = rho u with rho; they are taken as the moments of
+ * the second-order equilibrium of Section 2, rho(-2 + 3 u.u) and rho(1 - 3 u.u);
+ * likewise q^eq = -j, p_xx^eq = (j_x^2 - j_y^2)/rho, p_xy^eq = j_x j_y/rho. */
+void ORC(mrt_meq)(real_t rho, real_t ux, real_t uy, real_t *m)
+{
+    real_t uu = ux * ux + uy * uy;
+    m[0] = rho;
+    m[1] = rho * (-2.0 + 3.0 * uu);
+    m[2] = rho * (1.0 - 3.0 * uu);
+    m[3] = rho * ux;
+    m[4] = -rho * ux;
+    m[5] = rho * uy;
+    m[6] = -rho * uy;
+    m[7] = rho * (ux * ux - uy * uy);
+    m[8] = rho * ux * uy;
+}
+
+/* MRT collision with a body force.  reading: the paper names no forcing scheme;
+ * Guo, Zheng & Shi's source term F_i = w_i [3(e_i - u) + 9 (e_i.u) e_i].F is
+ * applied in moment space with the factor (I - S/2), the MRT form of Guo's
+ * forcing, and u carries the half-force shift as in the BGK collision.  With
+ * every s_k = 1/tau this is the BGK collision below. */
+static void collide_mrt(real_t *f, const double *s, double gx, double gy)
+{
+    mrt_inverse();
+    real_t rho = 0, jx = 0, jy = 0;
+    for (int i = 0; i < 9; ++i) {
+        rho += f[i];
+        jx += f[i] * EX[i];
+        jy += f[i] * EY[i];
+    }
+    real_t Fx = rho * gx, Fy = rho * gy;
+    real_t ux = (jx + 0.5 * Fx) / rho, uy = (jy + 0.5 * Fy) / rho;
+    real_t meq[9], src[9], ms[9];
+    ORC(mrt_meq)(rho, ux, uy, meq);
+    for (int i = 0; i < 9; ++i) {
+        real_t eu = EX[i] * ux + EY[i] * uy;
+        src[i] = weight(i) * ((3.0 * (EX[i] - ux) + 9.0 * eu * EX[i]) * Fx +
+                              (3.0 * (EY[i] - uy) + 9.0 * eu * EY[i]) * Fy);
+    }
+    for (int k = 0; k < 9; ++k) {
+        real_t mk = 0, sk = 0;
+        for (int i = 0; i < 9; ++i) {
+            mk += MRT_M[k][i] * f[i];
+            sk += MRT_M[k][i] * src[i];
+        }
+        ms[k] = mk - s[k] * (mk - meq[k]) + (1.0 - 0.5 * s[k]) * sk;
+    }
+    for (int i = 0; i < 9; ++i) {
+        real_t v = 0;
+        for (int k = 0; k < 9; ++k) v += MRT_MINV[i][k] * ms[k];
+        f[i] = v;
     }
 }
 
@@ -355,6 +533,15 @@ static void collide(real_t *f, double tau, double gx, double gy)
     }
 }
 
+static void collide_node(const orc_params *p, real_t *f)
+{
+    if (p->collision == 1) collide_mrt(f, p->s, p->gx, p->gy);
+    else collide(f, p->tau, p->gx, p->gy);
+}
+
+/* one node's collision in place (pre-collision f in, post-collision out) */
+void ORC(collide_node)(const orc_params *p, real_t *f) { collide_node(p, f); }
+
 /* One time step t -> t+1 in place on fp.  force[2*obj] accumulates (+=) the
  * momentum-exchange force of the fluid on each object during this step;
  * link_out (may be NULL) receives the missing population of every link.
@@ -381,29 +568,53 @@ int ORC(step)(const orc_params *p, const uint8_t *solid, int64_t nl, const int32
         int nff = yff * nx + xff;
         if (solid[nff]) ff_ok = 0;
         real_t uwx = luw ? luw[2 * l] : 0.0, uwy = luw ? luw[2 * l + 1] : 0.0;
-        real_t v;
-        if (ff_ok && (!lscheme || lscheme[l] == 0)) {
-            v = ORC(vibb)(ip, fp + 9 * nf, fp + 9 * nff, lq[l], uwx, uwy, p->rho0, p->gx, p->gy);
-        } else {
-            /* reading: with no second fluid node behind f the link falls back to
-             * halfway bounce-back */
-            v = ORC(hbb)(ip, fp + 9 * nf, uwx, uwy, p->rho0);
-            if (n_fallback && (!lscheme || lscheme[l] == 0)) ++*n_fallback;
+        /* scheme: 0 VIBB (Section 3.1), 1 halfway bounce-back, 2 Bouzidi, 3 Yu */
+        int sch = lscheme ? lscheme[l] : 0;
+        /* reading: a scheme that needs the second fluid node falls back to halfway
+         * bounce-back where x_ff is solid or off an open edge (Bouzidi needs it only
+         * for q <= 1/2) */
+        int needs_ff = sch == 0 || sch == 3 || (sch == 2 && RE(lq[l]) <= 0.5);
+        if (needs_ff && !ff_ok) {
+            if (n_fallback) ++*n_fallback;
+            sch = 1;
         }
+        real_t v;
+        if (sch == 0)
+            v = ORC(vibb)(ip, fp + 9 * nf, fp + 9 * nff, lq[l], uwx, uwy, p->rho0, p->gx, p->gy);
+        else if (sch == 2)
+            v = ORC(bouzidi)(ip, fp + 9 * nf, fp + 9 * nff, lq[l], uwx, uwy, p->rho0);
+        else if (sch == 3)
+            v = ORC(yu)(ip, fp + 9 * nf, fp + 9 * nff, lq[l], uwx, uwy, p->rho0);
+        else
+            v = ORC(hbb)(ip, fp + 9 * nf, uwx, uwy, p->rho0);
         fbc[9 * nf + i] = v;
         have[9 * nf + i] = 1;
         if (link_out) link_out[l] = v;
         /* momentum exchange: the population f+_{i'} carried into the wall and the
-         * returning f_i both push the solid along e_{i'} */
+         * returning f_i both push the solid along e_{i'}.  With gi_mea, the
+         * Galilean-invariant form of Wen, Zhang, Tu, Wang & Fang (J. Comput. Phys.
+         * 266, 2014): the momenta are taken relative to the wall,
+         * (e_{i'} - u_w) f+_{i'} - (e_i - u_w) f_i, which adds
+         * -u_w (f+_{i'} - f_i) to the plain form. */
         int o = lobj ? lobj[l] : 0;
         if (force) {
-            force[2 * o] += EX[ip] * (fp[9 * nf + ip] + v);
-            force[2 * o + 1] += EY[ip] * (fp[9 * nf + ip] + v);
+            real_t fin = fp[9 * nf + ip];
+            real_t fx = EX[ip] * (fin + v), fy = EY[ip] * (fin + v);
+            if (p->gi_mea) {
+                fx -= uwx * (fin - v);
+                fy -= uwy * (fin - v);
+            }
+            force[2 * o] += fx;
+            force[2 * o + 1] += fy;
         }
     }
 
     /* 3-4. pull streaming then collision at every interior fluid node */
     int status = 0;
+    if (p->collision == 1) mrt_inverse(); /* before the parallel loop */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) reduction(min : status)
+#endif
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             int n = y * nx + x;
@@ -422,9 +633,12 @@ int ORC(step)(const orc_params *p, const uint8_t *solid, int64_t nl, const int32
                     status = -2;
                 }
             }
-            collide(f, p->tau, p->gx, p->gy);
+            collide_node(p, f);
             for (int i = 0; i < 9; ++i) fnew[9 * n + i] = f[i];
         }
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
     for (int n = 0; n < N; ++n) {
         int x = n % nx;
         if (solid[n] || (p->x_open && (x == 0 || x == nx - 1))) continue;
@@ -437,6 +651,9 @@ int ORC(step)(const orc_params *p, const uint8_t *solid, int64_t nl, const int32
      * post-collision populations of the new time level; a column node is updated
      * only if it and its neighbour column node are fluid. */
     if (p->x_open) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
         for (int y = 0; y < ny; ++y) {
             int n0 = y * nx, n1 = y * nx + 1;
             if (!solid[n0] && !solid[n1]) {

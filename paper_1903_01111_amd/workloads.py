@@ -27,7 +27,10 @@ from typing import List, Optional
 import numpy as np
 
 PRIM_DISC, PRIM_RING, PRIM_BELOW, PRIM_ABOVE = 0, 1, 2, 3
-SCHEME_VIBB, SCHEME_HBB = 0, 1
+SCHEME_VIBB, SCHEME_HBB, SCHEME_BOUZIDI, SCHEME_YU = 0, 1, 2, 3
+# MRT rates (s_e, s_eps, s_q) of the energy, energy-square and heat-flux moments as
+# printed in Section 2; the shear rates are 1/tau
+MRT_S_PAPER = (1.5, 1.5, 1.2)
 
 
 @dataclasses.dataclass
@@ -62,6 +65,9 @@ class Case:
     init_ux: Optional[np.ndarray] = None  # (ny, nx); None -> 0
     init_uy: Optional[np.ndarray] = None
     nsteps: int = 0
+    collision: str = "bgk"  # "bgk" or "mrt"
+    mrt_s: tuple = MRT_S_PAPER  # (s_e, s_eps, s_q) for "mrt"
+    gi_mea: bool = False  # Galilean-invariant momentum exchange for the force
 
     def init_fields(self):
         shape = (self.ny, self.nx)
