@@ -7,12 +7,14 @@
  *   1. for every fluid->solid link (x_f, i', q, u_w): the population f_i(x_f, t+1)
  *      that would stream out of the solid, by VIBB (Section 3.1: bounce-back from
  *      the departure point d, whose density, non-equilibrium part and velocity
- *      are interpolated along the link) or by halfway bounce-back; plus the
- *      momentum-exchange force on the solid;
+ *      are interpolated along the link), by halfway bounce-back, or by the
+ *      interpolated bounce-back of Bouzidi or of Yu (Section 3) that the paper
+ *      compares VIBB with; plus the momentum-exchange force on the solid;
  *   2. pull streaming f_i(x, t+1) = f+_i(x - e_i, t) at every fluid node
  *      (Section 2, the evolution equation);
- *   3. BGK collision f+ = f - (f - f^eq)/tau (Section 2), with a body force by
- *      Guo's scheme;
+ *   3. collision (Section 2): BGK, f+ = f - (f - f^eq)/tau, or the paper's MRT
+ *      operator f+ = f + M^-1 S (m^eq - m), each with a body force by Guo's
+ *      scheme;
  *   4. optional open columns (Section 4.3): a non-equilibrium extrapolation
  *      velocity inlet at x = 0 and a zero-gradient (copy) outlet at x = nx-1.
  *
@@ -71,8 +73,23 @@ typedef int32_t lbm_status;
 #define LBM_X_PERIODIC 0
 #define LBM_X_OPEN 1 /* inlet at x = 0, outlet at x = nx-1 */
 
-#define LBM_SCHEME_VIBB 0 /* Section 3.1 */
-#define LBM_SCHEME_HBB 1  /* halfway bounce-back (Section 3) */
+/* per-link wall closure (Section 3).  A scheme that needs the second fluid node
+ * x_ff = x_f - e_{i'} (VIBB, Yu, Bouzidi with q <= 1/2) falls back to halfway
+ * bounce-back where x_ff is solid or outside an open lattice. */
+#define LBM_SCHEME_VIBB 0    /* velocity-interpolation bounce-back, Section 3.1 */
+#define LBM_SCHEME_HBB 1     /* halfway bounce-back (Section 3) */
+#define LBM_SCHEME_BOUZIDI 2 /* Bouzidi's linear interpolated bounce-back (Section 3, two branches in q) */
+#define LBM_SCHEME_YU 3      /* Yu's unified interpolated bounce-back (Section 3) */
+
+/* collision operator (Section 2) */
+#define LBM_COLLISION_BGK 0 /* single relaxation time tau */
+#define LBM_COLLISION_MRT 1 /* moments m = M f relaxed at the rates S: s_e, s_eps, s_q as given,
+                               s_nu = 1/tau for p_xx and p_xy; rho and j are conserved */
+
+/* momentum-exchange force on the solid (Section 4.3 uses it for the lift) */
+#define LBM_FORCE_PLAIN 0    /* sum over links of e_{i'} (f+_{i'}(x_f) + f_i(x_f, t+1)) */
+#define LBM_FORCE_GALILEAN 1 /* the Galilean-invariant form (Wen et al., J. Comput. Phys. 266, 2014):
+                                momenta relative to the wall, which adds -u_w (f+_{i'} - f_i) per link */
 
 /* obstacle primitives of lbm_geometry; geo = (cx, cy, r) */
 #define LBM_PRIM_DISC 0  /* solid where |x - c| <= r */
@@ -92,6 +109,10 @@ typedef struct {
     int32_t device;         /* HIP device ordinal */
     int32_t layout;         /* LBM_LAYOUT_DENSE or LBM_LAYOUT_COMPACT (single lattices) */
     void *stream;           /* hipStream_t the work is enqueued on; NULL = null stream */
+    int32_t collision;      /* LBM_COLLISION_BGK (0) or LBM_COLLISION_MRT */
+    int32_t force_form;     /* LBM_FORCE_PLAIN (0) or LBM_FORCE_GALILEAN */
+    double s_e, s_eps, s_q; /* MRT rates of the moments e, epsilon and q_x, q_y, each in (0, 2)
+                               (Section 2 prints 1.5, 1.5, 1.2); read only with LBM_COLLISION_MRT */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx;
@@ -135,10 +156,12 @@ lbm_status lbm_geometry_ex(int32_t nx, int32_t ny, int32_t x_bc, int32_t n_prim,
 /* Validates a mask and link list against params without touching a device:
  * sizes, q in (0,1], every link from a streamed fluid node into a solid node,
  * no duplicate (node, dir), every pull from a solid node covered by a link, obj
- * in [0, n_obj), open columns backed by a fluid neighbour column.  uw, obj and
- * scheme may be NULL (0, 0, VIBB).  *n_fallback (may be NULL) receives the number
- * of VIBB links whose second node x_ff = x_f - e_{i'} is solid: they fall back to
- * halfway bounce-back.  Errors: LBM_E_ARG, LBM_E_GEOM (message names the index). */
+ * in [0, n_obj), scheme in LBM_SCHEME_VIBB .. LBM_SCHEME_YU, open columns backed
+ * by a fluid neighbour column.  uw, obj and scheme may be NULL (0, 0, VIBB).
+ * *n_fallback (may be NULL) receives the number of links whose scheme needs the
+ * second node x_ff = x_f - e_{i'} where it is solid or off an open edge: they fall
+ * back to halfway bounce-back.  Errors: LBM_E_ARG, LBM_E_GEOM (message names the
+ * index). */
 lbm_status lbm_check_geometry(const lbm_params *p, const uint8_t *mask, int64_t n_links,
                               const int32_t *node, const int8_t *dir, const double *q,
                               const double *uw, const int32_t *obj, const int8_t *scheme,
@@ -164,6 +187,10 @@ lbm_status lbm_create(const lbm_params *p, void *workspace, size_t bytes, lbm_ct
 
 void lbm_destroy(lbm_ctx *ctx); /* frees host-side state only */
 
+/* The parameters the context was created with (e.g. to size the arrays of
+ * lbm_moments_device).  Errors: LBM_E_ARG (null pointer). */
+lbm_status lbm_get_params(const lbm_ctx *ctx, lbm_params *out);
+
 /* Uploads the geometry (validated as lbm_check_geometry; nothing on the device
  * changes if it fails), resets the force accumulators and the step counter.
  * The populations must then be initialised.  Errors: LBM_E_GEOM, LBM_E_NOMEM
@@ -181,7 +208,11 @@ lbm_status lbm_set_inlet(lbm_ctx *ctx, const double *ux, const double *uy);
 lbm_status lbm_init_equilibrium(lbm_ctx *ctx, const double *rho, const double *ux,
                                 const double *uy);
 
-/* Enqueues n >= 0 time steps; returns without waiting.  Errors: LBM_E_STATE. */
+/* Enqueues n >= 0 time steps; returns without waiting.  One step is the
+ * evolution equation of Section 2, f_i(x + e_i, t+1) = f_i(x, t) + Omega, with the
+ * collision of params.collision and the boundary values of Section 3 for the
+ * populations that would stream out of the solid (see the top of this file).
+ * Errors: LBM_E_STATE. */
 lbm_status lbm_step(lbm_ctx *ctx, int64_t n);
 
 /* Waits for the context's stream. */
@@ -208,14 +239,19 @@ lbm_status lbm_moments_device(lbm_ctx *ctx, void *rho, void *ux, void *uy, int32
  * 9*ny*nx doubles, node-major: f[(y*nx + x)*9 + i]; solid nodes read 0. */
 lbm_status lbm_populations(lbm_ctx *ctx, double *f);
 
-/* Momentum-exchange force of the fluid on object obj: last = the latest step,
- * sum = accumulated since geometry / lbm_force_reset over *nsum steps (any output
- * may be NULL).  Accumulated in FP64 on the device.  Synchronises.
+/* Force of the fluid on object obj by momentum exchange over its links (the
+ * force whose y component gives the lift coefficient of Section 4.3; the paper
+ * does not name the method, params.force_form selects the plain or the
+ * Galilean-invariant form): last = the latest step, sum = accumulated since
+ * geometry / lbm_force_reset over *nsum steps (any output may be NULL).
+ * Accumulated in FP64 on the device.  Synchronises.
  * Errors: LBM_E_ARG (obj range), LBM_E_UNSTABLE (non-finite). */
 lbm_status lbm_force(lbm_ctx *ctx, int32_t obj, double last[2], double sum[2], int64_t *nsum);
 lbm_status lbm_force_reset(lbm_ctx *ctx);
 
-/* Total mass sum over fluid nodes of sum_i f+_i, reduced in FP64.  Synchronises. */
+/* Total mass: the zeroth moment rho = sum_i f_i of Section 2 summed over the
+ * fluid nodes (post-collision populations), reduced in FP64.  Synchronises.
+ * Errors: LBM_E_STATE, LBM_E_UNSTABLE (non-finite). */
 lbm_status lbm_mass(lbm_ctx *ctx, double *mass);
 
 /* max over fluid nodes and directions of |f+_i - w_i|, in FP64: sizes the scale
@@ -278,7 +314,8 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t steps_per_trial, lbm_kernel_config
  * obstacle offsets or Reynolds numbers) advanced together.  Each step is one
  * link launch over the links of all instances and one bulk launch over a tile
  * table of all instances (HIP graph replay).  Instances share storage, x_bc,
- * rho0, dev_scale_log2, device and stream, and use the dense layout; nx, ny,
+ * rho0, dev_scale_log2, device, stream, collision, force_form and the MRT rates
+ * s_e, s_eps, s_q, and use the dense layout; nx, ny,
  * tau, body force, n_obj and geometry are per instance.  The results of an instance equal those of a
  * single-lattice context with the same arguments (bitwise for the populations).
  * ------------------------------------------------------------------------- */
@@ -354,7 +391,8 @@ lbm_status lbm_batch_force_reset(lbm_batch *b);
  * derivatives of the discrete map with the node classification held fixed; at
  * q = 1/2 the VIBB velocity branch of the forward (q <= 1/2) is differentiated.
  * Adjoint arithmetic is in the storage's precision; gradients with respect to the
- * parameters are accumulated in FP64.  FP64 and FP32 storage, dense layout only.
+ * parameters are accumulated in FP64.  FP64 and FP32 storage, dense layout, BGK
+ * collision, the plain force and VIBB / halfway bounce-back links only.
  *
  * lbm_adjoint_workspace_bytes: device bytes the call needs for this context
  * (checkpoints, the recomputed segment, adjoint fields); 0 on invalid arguments.
@@ -373,7 +411,8 @@ lbm_status lbm_batch_force_reset(lbm_batch *b);
  *               initial state as f+ = f^eq(rho, u) of its own (rho, u) (the state
  *               lbm_init_equilibrium writes), node-major, zero at solid nodes.
  * Errors: LBM_E_ARG (nsteps < 1, ckpt_every < 1, obj out of range, 16-bit
- * storage, compact layout, workspace null, misaligned or too small), LBM_E_STATE (no geometry or
+ * storage, compact layout, MRT, Galilean-invariant force, Bouzidi or Yu links,
+ * workspace null, misaligned or too small), LBM_E_STATE (no geometry or
  * initialisation), LBM_E_DEVICE, LBM_E_UNSTABLE (non-finite objective or
  * gradient). */
 size_t lbm_adjoint_workspace_bytes(const lbm_ctx *ctx, int64_t nsteps, int32_t ckpt_every);

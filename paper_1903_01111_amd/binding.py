@@ -22,6 +22,10 @@ LBM_OK, LBM_E_ARG, LBM_E_GEOM, LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_STATE, LBM_E_UNS
     0, -1, -2, -3, -4, -5, -6)
 LBM_F64, LBM_F32, LBM_F16_DEV, LBM_BF16_DEV, LBM_F32_WIDE = 0, 1, 2, 3, 4
 LBM_X_PERIODIC, LBM_X_OPEN = 0, 1
+LBM_SCHEME_VIBB, LBM_SCHEME_HBB, LBM_SCHEME_BOUZIDI, LBM_SCHEME_YU = 0, 1, 2, 3
+LBM_COLLISION_BGK, LBM_COLLISION_MRT = 0, 1
+LBM_FORCE_PLAIN, LBM_FORCE_GALILEAN = 0, 1
+COLLISION = {"bgk": LBM_COLLISION_BGK, "mrt": LBM_COLLISION_MRT}
 LBM_LAYOUT_DENSE, LBM_LAYOUT_COMPACT = 0, 1
 LBM_MAX_LINKS = 1 << 28
 LAYOUT = {"dense": LBM_LAYOUT_DENSE, "compact": LBM_LAYOUT_COMPACT}
@@ -35,7 +39,9 @@ class lbm_params(C.Structure):
                 ("storage", C.c_int32), ("tau", C.c_double), ("gx", C.c_double),
                 ("gy", C.c_double), ("rho0", C.c_double), ("n_obj", C.c_int32),
                 ("dev_scale_log2", C.c_int32), ("device", C.c_int32),
-                ("layout", C.c_int32), ("stream", C.c_void_p)]
+                ("layout", C.c_int32), ("stream", C.c_void_p), ("collision", C.c_int32),
+                ("force_form", C.c_int32), ("s_e", C.c_double), ("s_eps", C.c_double),
+                ("s_q", C.c_double)]
 
 
 class lbm_kernel_config(C.Structure):
@@ -74,6 +80,7 @@ SIGNATURES = [
     ("lbm_workspace_bytes", C.c_size_t, [_P, _I64]),
     ("lbm_create", _I32, [_P, _P, C.c_size_t, _P]),
     ("lbm_destroy", _V, [_P]),
+    ("lbm_get_params", _I32, [_P, _P]),
     ("lbm_set_geometry", _I32, [_P, _P, _I64, _P, _P, _P, _P, _P, _P]),
     ("lbm_set_inlet", _I32, [_P, _P, _P]),
     ("lbm_init_equilibrium", _I32, [_P, _P, _P, _P]),
@@ -240,6 +247,12 @@ def lbm_destroy(ctx):
     lib().lbm_destroy(ctx)
 
 
+def lbm_get_params(ctx) -> lbm_params:
+    p = lbm_params()
+    check(lib().lbm_get_params(ctx, C.byref(p)), ctx)
+    return p
+
+
 def lbm_set_geometry(ctx, mask, node, dir, q, uw=None, obj=None, scheme=None):
     a = _link_arrays(mask, node, dir, q, uw, obj, scheme)
     check(lib().lbm_set_geometry(ctx, _p(a[0]), len(a[1]), *[_p(x) for x in a[1:]]), ctx)
@@ -279,8 +292,10 @@ def lbm_moments(ctx, ny, nx):
 
 def lbm_moments_device(ctx, rho, ux, uy):
     """lbm_moments into torch tensors on the context's device (any may be None):
-    float64 or float32, all of one dtype, contiguous, ny*nx elements each; enqueued
-    on the context's stream (torch's current stream for a Lattice)."""
+    float64 or float32, all of one dtype, contiguous, exactly ny*nx elements each
+    (checked against the context's parameters before anything is launched);
+    enqueued on the context's stream (torch's current stream for a Lattice).  No
+    finiteness check is made (lbm_moments makes one)."""
     import torch
     ts = [t for t in (rho, ux, uy) if t is not None]
     if not ts:
@@ -288,9 +303,14 @@ def lbm_moments_device(ctx, rho, ux, uy):
     dt = ts[0].dtype
     if dt not in (torch.float64, torch.float32) or any(t.dtype != dt for t in ts):
         raise TypeError("lbm_moments_device: tensors must all be float64 or all float32")
-    n = ts[0].numel()
-    if any(not t.is_cuda or not t.is_contiguous() or t.numel() != n for t in ts):
-        raise ValueError("lbm_moments_device: contiguous device tensors of ny*nx elements expected")
+    p = lbm_get_params(ctx)
+    n = p.nx * p.ny
+    for t in ts:
+        if not t.is_cuda or t.device.index != p.device:
+            raise ValueError(f"lbm_moments_device: tensors must live on the context's device cuda:{p.device}")
+        if not t.is_contiguous() or t.numel() != n:
+            raise ValueError(f"lbm_moments_device: contiguous tensors of ny*nx = {n} elements expected, "
+                             f"got {t.numel()}")
     ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
     check(lib().lbm_moments_device(ctx, ptr(rho), ptr(ux), ptr(uy), 1 if dt == torch.float64 else 0), ctx)
 
@@ -518,9 +538,8 @@ class Batch:
         self.cases = list(cases)
         self.device = torch.device("cuda", device)
         stream = torch.cuda.current_stream(self.device).cuda_stream
-        self.params = [make_params(c.nx, c.ny, x_open=c.x_open, storage=storage, tau=c.tau, gx=c.gx,
-                                   gy=c.gy, rho0=c.rho0, n_obj=c.n_obj, dev_scale_log2=dev_scale_log2,
-                                   device=device, stream=stream) for c in self.cases]
+        self.params = [case_params(c, storage=storage, dev_scale_log2=dev_scale_log2, device=device,
+                                   stream=stream) for c in self.cases]
         self.geoms = geometries if geometries is not None else [case_geometry(c) for c in self.cases]
         ml = [len(g[1]) for g in self.geoms]
         nbytes = lbm_batch_workspace_bytes(self.params, ml)
@@ -576,10 +595,21 @@ class Batch:
 # ---------------------------------------------------------------------------
 
 def make_params(nx, ny, *, x_open=False, storage="f32", tau=0.8, gx=0.0, gy=0.0, rho0=1.0,
-                n_obj=1, dev_scale_log2=0, device=0, stream=None, layout="dense") -> lbm_params:
+                n_obj=1, dev_scale_log2=0, device=0, stream=None, layout="dense", collision="bgk",
+                mrt_s=W.MRT_S_PAPER, gi_mea=False) -> lbm_params:
+    se, seps, sq = mrt_s
     return lbm_params(nx, ny, LBM_X_OPEN if x_open else LBM_X_PERIODIC, STORAGE.get(storage, storage),
                       tau, gx, gy, rho0, n_obj, dev_scale_log2, device, LAYOUT.get(layout, layout),
-                      stream)
+                      stream, COLLISION.get(collision, collision),
+                      LBM_FORCE_GALILEAN if gi_mea else LBM_FORCE_PLAIN, se, seps, sq)
+
+
+def case_params(case: W.Case, **kw) -> lbm_params:
+    """lbm_params of a workloads.Case (its lattice, physics, collision and force
+    form); kw adds storage, layout, device, stream and dev_scale_log2."""
+    return make_params(case.nx, case.ny, x_open=case.x_open, tau=case.tau, gx=case.gx, gy=case.gy,
+                       rho0=case.rho0, n_obj=case.n_obj, collision=case.collision, mrt_s=case.mrt_s,
+                       gi_mea=case.gi_mea, **kw)
 
 
 def case_geometry(case: W.Case):
@@ -607,10 +637,8 @@ class Lattice:
         self.case = case
         self.device = torch.device("cuda", device)
         stream = torch.cuda.current_stream(self.device).cuda_stream
-        self.params = make_params(case.nx, case.ny, x_open=case.x_open, storage=storage, tau=case.tau,
-                                  gx=case.gx, gy=case.gy, rho0=case.rho0, n_obj=case.n_obj,
-                                  dev_scale_log2=dev_scale_log2, device=device, stream=stream,
-                                  layout=layout)
+        self.params = case_params(case, storage=storage, dev_scale_log2=dev_scale_log2, device=device,
+                                  stream=stream, layout=layout)
         geo = geometry if geometry is not None else case_geometry(case)
         self.mask, self.node, self.dir, self.q, self.uw, self.obj, self.scheme = geo
         nl = len(self.node) if max_links is None else max_links

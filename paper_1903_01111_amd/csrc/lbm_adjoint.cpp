@@ -70,7 +70,8 @@ size_t lbm_adjoint_workspace_bytes(const lbm_ctx *c, int64_t nsteps, int32_t ckp
 {
     AdjLayout L;
     if (!c || !c->have_geom || (c->p.storage != LBM_F64 && c->p.storage != LBM_F32) ||
-        c->p.layout != LBM_LAYOUT_DENSE)
+        c->p.layout != LBM_LAYOUT_DENSE || c->p.collision != LBM_COLLISION_BGK ||
+        c->p.force_form != LBM_FORCE_PLAIN || c->has_ext_scheme)
         return 0;
     if (!adj_layout(c, nsteps, ckpt_every, &L)) return 0;
     return L.total;
@@ -86,6 +87,11 @@ lbm_status lbm_adjoint_force(lbm_ctx *c, void *wsv, size_t ws_bytes, int64_t nst
     if (c->p.storage != LBM_F64 && c->p.storage != LBM_F32)
         return c->fail(LBM_E_ARG, "lbm_adjoint_force: FP64 or FP32 storage only");
     if (c->p.layout != LBM_LAYOUT_DENSE) return c->fail(LBM_E_ARG, "lbm_adjoint_force: dense layout only");
+    if (c->p.collision != LBM_COLLISION_BGK) return c->fail(LBM_E_ARG, "lbm_adjoint_force: BGK collision only");
+    if (c->p.force_form != LBM_FORCE_PLAIN)
+        return c->fail(LBM_E_ARG, "lbm_adjoint_force: the plain momentum exchange only");
+    if (c->has_ext_scheme)
+        return c->fail(LBM_E_ARG, "lbm_adjoint_force: VIBB and halfway bounce-back links only");
     if (nsteps < 1 || k < 1) return c->fail(LBM_E_ARG, "lbm_adjoint_force: nsteps and ckpt_every must be >= 1");
     if (obj < 0 || obj >= c->p.n_obj) return c->fail(LBM_E_ARG, "lbm_adjoint_force: obj out of range");
     if (!std::isfinite(dir_x) || !std::isfinite(dir_y))

@@ -54,7 +54,7 @@ struct lbm_batch {
     size_t bytes = 0;
     // workspace offsets
     size_t off_A = 0, off_B = 0, off_mask = 0, off_seg = 0, off_meta = 0, off_q = 0, off_uw = 0, off_sf = 0,
-           off_sff = 0, off_pf = 0, off_pff = 0, off_li = 0, off_L = 0, off_rec = 0, off_mnode = 0,
+           off_sff = 0, off_pf = 0, off_pff = 0, off_pfi = 0, off_li = 0, off_L = 0, off_rec = 0, off_mnode = 0,
            off_pbase = 0, off_M = 0, off_P = 0, off_wpart = 0, off_wobj = 0, off_uin = 0, off_force = 0,
            off_insts = 0, off_tiles = 0, off_partials = 0, off_stage = 0, total = 0;
     // geometry, per instance until the batch is assembled
@@ -64,7 +64,7 @@ struct lbm_batch {
     // global numbering after assembly
     std::vector<int64_t> slot_off, pop_base, link_off;
     int64_t n_links = 0, n_flagged = 0, n_pops = 0;
-    bool has_uw = false;
+    bool has_uw = false, has_pfi = false;
     void *cur = nullptr, *nxt = nullptr;
     int64_t step = 0, nsum = 0;
     lbm_batch_kernel_config kcfg{1, 1, 256, 16};
@@ -95,7 +95,8 @@ struct lbm_batch {
     lbm::Phys phys(int i) const
     {
         const float sc = std::ldexp(1.0f, lbm_host::storage_is_16bit(storage) ? p[0].dev_scale_log2 : 0);
-        return lbm::Phys{1.0 / p[i].tau, p[i].gx, p[i].gy, p[0].rho0, sc, 1.0f / sc};
+        return lbm::Phys{1.0 / p[i].tau, p[i].gx, p[i].gy, p[0].rho0, sc, 1.0f / sc, p[0].s_e, p[0].s_eps,
+                         p[0].s_q, p[0].force_form == LBM_FORCE_GALILEAN ? 1 : 0, p[0].collision};
     }
     lbm::Grid grid(int i) const
     {
@@ -134,7 +135,7 @@ struct lbm_batch {
         auto i32 = [&](size_t off) { return reinterpret_cast<const int32_t *>(ws + off); };
         return lbm::Links{reinterpret_cast<const uint32_t *>(ws + off_meta), ws + off_q,
                           has_uw ? ws + off_uw : nullptr, i32(off_sf), i32(off_sff), i32(off_pf), i32(off_pff),
-                          i32(off_li), n_links, 0, 0, nullptr};
+                          i32(off_li), n_links, 0, 0, nullptr, has_pfi ? i32(off_pfi) : nullptr};
     }
 };
 
@@ -187,13 +188,14 @@ size_t layout(lbm_batch *b)
     b->off_sff = take(nl * 4);
     b->off_pf = take(nl * 4);
     b->off_pff = take(nl * 4);
+    b->off_pfi = take(nl * 4);
     b->off_li = take(nl * 4);
     b->off_L = take(nl * eb);
     b->off_rec = take(2 * nl * 2);
     b->off_mnode = take(2 * nl * 4);
     b->off_pbase = take(2 * nl * 4);
     b->off_M = take(2 * nl * 3 * rb);
-    b->off_P = take(2 * nl * eb);
+    b->off_P = take(3 * nl * eb);
     const size_t waves = (nl + 63) / 64 + 16;
     b->off_wpart = take(waves * 16);
     b->off_wobj = take(waves * 4);
@@ -237,9 +239,13 @@ bool batch_params_ok(int32_t n, const lbm_params *p, const int64_t *max_links, s
         }
         if (p[i].storage != p[0].storage || p[i].x_bc != p[0].x_bc || p[i].rho0 != p[0].rho0 ||
             p[i].dev_scale_log2 != p[0].dev_scale_log2 || p[i].device != p[0].device ||
-            p[i].stream != p[0].stream) {
+            p[i].stream != p[0].stream || p[i].collision != p[0].collision ||
+            p[i].force_form != p[0].force_form ||
+            (p[0].collision == LBM_COLLISION_MRT &&
+             (p[i].s_e != p[0].s_e || p[i].s_eps != p[0].s_eps || p[i].s_q != p[0].s_q))) {
             *why = "instance " + std::to_string(i) +
-                   ": storage, x_bc, rho0, dev_scale_log2, device and stream must match instance 0";
+                   ": storage, x_bc, rho0, dev_scale_log2, device, stream, collision, force_form and the MRT "
+                   "rates must match instance 0";
             return false;
         }
     }
@@ -257,7 +263,7 @@ lbm_status assemble(lbm_batch *b)
     b->pop_base.assign(b->n, 0);
     b->link_off.assign(b->n, 0);
     int64_t slots = 0, pops = 0, links = 0;
-    b->has_uw = false;
+    b->has_uw = b->has_pfi = false;
     for (int i = 0; i < b->n; ++i) {
         b->slot_off[i] = slots;
         b->pop_base[i] = pops;
@@ -266,6 +272,7 @@ lbm_status assemble(lbm_batch *b)
         pops += b->prep[i].n_pops;
         links += (int64_t)b->prep[i].meta.size();
         b->has_uw |= b->prep[i].has_uw;
+        b->has_pfi |= b->prep[i].has_pfi;
     }
     if (slots >= INT32_MAX || pops >= INT32_MAX || links >= INT32_MAX)
         return b->fail(LBM_E_NOMEM, "batch too large for 32-bit link numbering");
@@ -274,7 +281,7 @@ lbm_status assemble(lbm_batch *b)
     b->n_pops = pops;
     std::vector<uint32_t> meta;
     std::vector<double> q, uw;
-    std::vector<int32_t> sf, sff, pf, pff, li, mnode, pbase;
+    std::vector<int32_t> sf, sff, pf, pff, pfi, li, mnode, pbase;
     std::vector<uint16_t> rec;
     std::vector<lbm::SegBase> seg;
     meta.reserve(links);
@@ -283,7 +290,7 @@ lbm_status assemble(lbm_batch *b)
         const int32_t so = (int32_t)b->slot_off[i], po = (int32_t)b->pop_base[i], lo = (int32_t)b->link_off[i];
         const uint32_t oo = (uint32_t)b->il[i].obj_off;
         for (size_t k = 0; k < P.meta.size(); ++k) {
-            meta.push_back((P.meta[k] & 15u) | (((P.meta[k] >> 8) + oo) << 8));
+            meta.push_back((P.meta[k] & 255u) | (((P.meta[k] >> 8) + oo) << 8));
             q.push_back(P.q[k]);
             if (b->has_uw) {
                 uw.push_back(P.has_uw ? P.uw[2 * k] : 0.0);
@@ -293,6 +300,7 @@ lbm_status assemble(lbm_batch *b)
             sff.push_back(P.sff[k] >= 0 ? P.sff[k] + so : -1);
             pf.push_back(P.pf[k] + po);
             pff.push_back(P.pff[k] >= 0 ? P.pff[k] + po : -1);
+            if (b->has_pfi) pfi.push_back((P.has_pfi ? P.pfi[k] : P.pf[k]) + po);
             li.push_back(P.li[k] + lo);
         }
         rec.insert(rec.end(), P.rec.begin(), P.rec.end());
@@ -333,6 +341,7 @@ lbm_status assemble(lbm_batch *b)
                {b->off_sff, sff.data(), n * 4},
                {b->off_pf, pf.data(), n * 4},
                {b->off_pff, pff.data(), n * 4},
+               {b->off_pfi, pfi.data(), b->has_pfi ? n * 4 : 0},
                {b->off_li, li.data(), n * 4},
                {b->off_rec, rec.data(), rec.size() * 2},
                {b->off_mnode, mnode.data(), mnode.size() * 4},

@@ -21,7 +21,7 @@ struct Layout {
     int32_t pitch;
     int64_t plane;  // elements per population plane
     size_t off_A, off_B, off_mask, off_seg, off_fmask, off_meta, off_q, off_uw, off_sf, off_sff, off_pf, off_pff,
-        off_li, off_kof, off_L, off_rec, off_mnode, off_pbase, off_M, off_P, off_M2, off_P2, off_wpart,
+        off_pfi, off_li, off_kof, off_L, off_rec, off_mnode, off_pbase, off_M, off_P, off_M2, off_P2, off_wpart,
         off_wobj, off_uin,
         off_force, off_partials, off_stage, total;
     int64_t wave_cap;  // wavefront partials of the link kernel
@@ -42,6 +42,8 @@ struct lbm_ctx {
     size_t ws_bytes = 0;
     int64_t max_links = 0, n_links = 0, n_moment_nodes = 0;
     bool has_uw = false, have_geom = false, have_init = false;
+    bool has_pfi = false;       // some link needs f+_i(x_f) (Bouzidi, Yu)
+    bool has_ext_scheme = false;  // some link uses Bouzidi or Yu
     bool li_ident = false;  // links in (node, dir) order: L entry = link index
     // caller's index of each device link (links are kept in (obj, node, dir) order)
     std::vector<int64_t> link_order;
@@ -76,7 +78,8 @@ struct lbm_ctx {
     lbm::Phys phys() const
     {
         const float sc = std::ldexp(1.0f, lbm_host::storage_is_16bit(p.storage) ? p.dev_scale_log2 : 0);
-        return lbm::Phys{1.0 / p.tau, p.gx, p.gy, p.rho0, sc, 1.0f / sc};
+        return lbm::Phys{1.0 / p.tau, p.gx, p.gy, p.rho0, sc, 1.0f / sc, p.s_e, p.s_eps, p.s_q,
+                         p.force_form == LBM_FORCE_GALILEAN ? 1 : 0, p.collision};
     }
     lbm::Links links() const
     {
@@ -84,7 +87,7 @@ struct lbm_ctx {
         return lbm::Links{reinterpret_cast<const uint32_t *>(ws + lay.off_meta), ws + lay.off_q,
                           has_uw ? ws + lay.off_uw : nullptr, i32(lay.off_sf), i32(lay.off_sff),
                           i32(lay.off_pf), i32(lay.off_pff), i32(lay.off_li), n_links, li_ident ? 1 : 0, 0,
-                          li_ident ? nullptr : i32(lay.off_kof)};
+                          li_ident ? nullptr : i32(lay.off_kof), has_pfi ? i32(lay.off_pfi) : nullptr};
     }
     lbm::Reduce reduce() const
     {

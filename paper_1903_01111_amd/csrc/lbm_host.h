@@ -35,7 +35,7 @@ struct Prepared {
     // per link, in (obj, node, dir) order
     std::vector<uint32_t> meta;
     std::vector<double> q, uw;
-    std::vector<int32_t> sf, sff, pf, pff, li;
+    std::vector<int32_t> sf, sff, pf, pff, pfi, li;
     std::vector<int64_t> order;  // caller's index of each link
     // per flagged node, in plane order
     std::vector<uint16_t> rec;
@@ -45,6 +45,8 @@ struct Prepared {
     std::vector<uint64_t> fmask;           // per segment: its fluid nodes (bit = lane)
     int64_t n_pops = 0;
     bool has_uw = false;
+    bool has_pfi = false;       // some link reads f+_i(x_f) (Bouzidi, Yu): pfi is filled
+    bool has_ext_scheme = false;  // some link uses Bouzidi or Yu
     int64_t n_fallback = 0;
 };
 

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
 
+#include "lbm.h"
+
 namespace lbm {
 
 // Device population layout: nine planes of `plane` elements, plane i holding
@@ -25,11 +27,14 @@ struct Grid {
 };
 
 struct Phys {
-    double omega;     // 1/tau
+    double omega;     // 1/tau (BGK rate; MRT rate of p_xx and p_xy)
     double gx, gy;    // body acceleration
     double rho0;      // reference density of the moving-wall term
     float scale;      // 2^k for 16-bit storage (1 otherwise)
     float inv_scale;  // 2^-k
+    double s_e, s_eps, s_q;  // MRT rates of e, epsilon and q_x, q_y
+    int32_t gi_force;        // Galilean-invariant momentum exchange
+    int32_t coll;            // LBM_COLLISION_BGK or LBM_COLLISION_MRT
 };
 
 // Per-node mask word: bits 0..7 the directions d (bit d-1) of the node's links
@@ -73,8 +78,10 @@ struct Side {
 };
 
 // Links in (obj, node, dir) order, so a wavefront usually serves one object.
+// The scheme in bits 4..7 of meta is the one evaluated: LBM_SCHEME_HBB also for a
+// link whose scheme needs x_ff where x_ff is unusable (then sff = -1).
 struct Links {
-    const uint32_t *meta;  // dir | (obj << 8)
+    const uint32_t *meta;  // dir | (scheme << 4) | (obj << 8)
     const void *q;         // real[n]
     const void *uw;        // real[2n] or nullptr (still walls)
     const int32_t *sf;     // moment slot of x_f
@@ -86,6 +93,8 @@ struct Links {
     int32_t li_ident;      // 1: li[l] == l for every link (one object), li is not read
     int32_t pad;
     const int32_t *kof;    // inverse of li (null when li_ident)
+    const int32_t *pfi;    // P entry of f+_i(x_f), i = opp(dir) (Bouzidi and Yu links; others
+                           // repeat pf), or null when no link needs it
 };
 
 // Partial forces of the link kernel, one per run of 64 links, reduced per object

@@ -38,7 +38,7 @@ bool storage_is_16bit(int storage) { return storage == LBM_F16_DEV || storage ==
 // with their side moments)
 size_t bytes_per_link(int storage)
 {
-    return 49 + 15 * real_bytes(storage) + 5 * elem_bytes(storage);
+    return 53 + 15 * real_bytes(storage) + 7 * elem_bytes(storage);
 }
 
 // Plane stride: rows padded to 64 elements; the plane size in 256-byte units is
@@ -70,17 +70,18 @@ Layout make_layout(const lbm_params &p, int64_t max_links)
     L.off_sff = take(nl * 4);
     L.off_pf = take(nl * 4);
     L.off_pff = take(nl * 4);
+    L.off_pfi = take(nl * 4);
     L.off_li = take(nl * 4);
     L.off_kof = take(nl * 4);
     L.off_L = take(nl * eb);
-    // at most two flagged nodes and two deposited populations per link
+    // at most two flagged nodes and three deposited populations per link
     L.off_rec = take(2 * nl * 2);
     L.off_mnode = take(2 * nl * 4);
     L.off_pbase = take(2 * nl * 4);
     L.off_M = take(2 * nl * 3 * rb);
-    L.off_P = take(2 * nl * eb);
+    L.off_P = take(3 * nl * eb);
     L.off_M2 = take(2 * nl * 3 * rb);
-    L.off_P2 = take(2 * nl * eb);
+    L.off_P2 = take(3 * nl * eb);
     // force partials: one per 64 links (link kernel) or per row segment (fused bulk)
     L.wave_cap = std::max<int64_t>((int64_t)(nl + 63) / 64, (int64_t)(L.pitch / 64) * p.ny) + 16;
     L.off_wpart = take((size_t)L.wave_cap * 16);
@@ -145,6 +146,23 @@ bool params_ok(const lbm_params *p, std::string *why)
     }
     if (p->layout != LBM_LAYOUT_DENSE && p->layout != LBM_LAYOUT_COMPACT) {
         *why = "layout must be LBM_LAYOUT_DENSE or LBM_LAYOUT_COMPACT";
+        return false;
+    }
+    if (p->collision != LBM_COLLISION_BGK && p->collision != LBM_COLLISION_MRT) {
+        *why = "collision must be LBM_COLLISION_BGK or LBM_COLLISION_MRT";
+        return false;
+    }
+    if (p->collision == LBM_COLLISION_MRT) {
+        for (double s : {p->s_e, p->s_eps, p->s_q})
+            if (!(s > 0.0 && s < 2.0)) {
+                std::snprintf(m, sizeof m, "MRT rates s_e, s_eps, s_q must lie in (0, 2) (got %g, %g, %g)",
+                              p->s_e, p->s_eps, p->s_q);
+                *why = m;
+                return false;
+            }
+    }
+    if (p->force_form != LBM_FORCE_PLAIN && p->force_form != LBM_FORCE_GALILEAN) {
+        *why = "force_form must be LBM_FORCE_PLAIN or LBM_FORCE_GALILEAN";
         return false;
     }
     return true;
@@ -225,7 +243,7 @@ lbm_status prepare_geometry(const lbm_params &p, const uint8_t *mask, int64_t n,
             *why = m;
             return LBM_E_GEOM;
         }
-        if (scheme && scheme[l] != LBM_SCHEME_VIBB && scheme[l] != LBM_SCHEME_HBB) {
+        if (scheme && (scheme[l] < LBM_SCHEME_VIBB || scheme[l] > LBM_SCHEME_YU)) {
             std::snprintf(m, sizeof m, "link %lld: unknown scheme %d", (long long)l, scheme[l]);
             *why = m;
             return LBM_E_GEOM;
@@ -253,9 +271,14 @@ lbm_status prepare_geometry(const lbm_params &p, const uint8_t *mask, int64_t n,
             }
         }
     if (!out) return LBM_OK;
-    // second node of each link (-1: halfway bounce-back, by scheme or because x_ff is solid)
+    // scheme evaluated per link and its second node (-1: not read).  A scheme that
+    // needs x_ff (VIBB, Yu, Bouzidi for q <= 1/2) falls back to halfway bounce-back
+    // where x_ff is solid or off an open edge; Bouzidi for q > 1/2 and Yu also read
+    // f+_i(x_f) of the outgoing direction i = opp(dir).
     std::vector<int32_t> ffo(n);  // plane offset of x_ff
+    std::vector<uint8_t> eff(n);  // scheme evaluated
     out->n_fallback = 0;
+    out->has_pfi = out->has_ext_scheme = false;
     for (int64_t l = 0; l < n; ++l) {
         const int nd = node[l], d = dir[l], x = nd % nx, y = nd / nx;
         int xf2 = x - EXR[d];
@@ -263,10 +286,20 @@ lbm_status prepare_geometry(const lbm_params &p, const uint8_t *mask, int64_t n,
         bool ff_ok = !(open && (xf2 < 0 || xf2 >= nx));
         xf2 = (xf2 + nx) % nx;
         if (ff_ok && mask[(int64_t)yf2 * nx + xf2]) ff_ok = false;
-        const bool vibb = !scheme || scheme[l] == LBM_SCHEME_VIBB;
-        if (vibb && !ff_ok) ++out->n_fallback;
-        ffo[l] = (vibb && ff_ok) ? yf2 * pitch + xf2 : -1;
+        int sch = scheme ? scheme[l] : LBM_SCHEME_VIBB;
+        out->has_ext_scheme |= sch == LBM_SCHEME_BOUZIDI || sch == LBM_SCHEME_YU;
+        const bool needs_ff = sch == LBM_SCHEME_VIBB || sch == LBM_SCHEME_YU ||
+                              (sch == LBM_SCHEME_BOUZIDI && q[l] <= 0.5);
+        if (needs_ff && !ff_ok) {
+            ++out->n_fallback;
+            sch = LBM_SCHEME_HBB;
+        }
+        eff[l] = (uint8_t)sch;
+        ffo[l] = (needs_ff && ff_ok) ? yf2 * pitch + xf2 : -1;
     }
+    auto needs_pfi = [&](int64_t l) {
+        return eff[l] == LBM_SCHEME_YU || (eff[l] == LBM_SCHEME_BOUZIDI && q[l] > 0.5);
+    };
     // padded mask; padding columns count as solid and are never streamed
     const size_t plane_n = (size_t)pitch * ny;
     out->mask.assign(plane_n, lbm::MASK_SOLID);
@@ -280,6 +313,7 @@ lbm_status prepare_geometry(const lbm_params &p, const uint8_t *mask, int64_t n,
         const int32_t of = (nd / nx) * pitch + nd % nx;
         bits[of] |= (uint16_t)((1u << (d - 1)) | (1u << (d + 7)));
         if (ffo[l] >= 0) bits[ffo[l]] |= (uint16_t)(1u << (d + 7));
+        if (needs_pfi(l)) bits[of] |= (uint16_t)(1u << (OPPR[d] + 7));
     }
     // slots, segment bases, deposit bases
     const int64_t nseg = (int64_t)(pitch / 64) * ny;
@@ -327,6 +361,7 @@ lbm_status prepare_geometry(const lbm_params &p, const uint8_t *mask, int64_t n,
     out->sff.assign(n, -1);
     out->pf.resize(n);
     out->pff.assign(n, -1);
+    out->pfi.resize(n);
     out->li.resize(n);
     out->has_uw = false;
     if (uw)
@@ -338,7 +373,7 @@ lbm_status prepare_geometry(const lbm_params &p, const uint8_t *mask, int64_t n,
         const int nd = node[l], d = dir[l];
         const int32_t of = (nd / nx) * pitch + nd % nx;
         const int32_t sfo = slot[of];
-        out->meta[k] = (uint32_t)d | ((uint32_t)(obj ? obj[l] : 0) << 8);
+        out->meta[k] = (uint32_t)d | ((uint32_t)eff[l] << 4) | ((uint32_t)(obj ? obj[l] : 0) << 8);
         out->q[k] = q[l];
         if (out->has_uw) {
             out->uw[2 * k] = uw[2 * l];
@@ -346,6 +381,11 @@ lbm_status prepare_geometry(const lbm_params &p, const uint8_t *mask, int64_t n,
         }
         out->sf[k] = sfo;
         out->pf[k] = out->pbase[sfo] + rank_below(out->rec[sfo] >> 8, d);
+        out->pfi[k] = out->pf[k];
+        if (needs_pfi(l)) {
+            out->pfi[k] = out->pbase[sfo] + rank_below(out->rec[sfo] >> 8, OPPR[d]);
+            out->has_pfi = true;
+        }
         if (ffo[l] >= 0) {
             const int32_t sff = slot[ffo[l]];
             out->sff[k] = sff;
@@ -602,6 +642,13 @@ lbm_status lbm_create(const lbm_params *p, void *workspace, size_t bytes, lbm_ct
     return LBM_OK;
 }
 
+lbm_status lbm_get_params(const lbm_ctx *c, lbm_params *out)
+{
+    if (!c || !out) return LBM_E_ARG;
+    *out = c->p;
+    return LBM_OK;
+}
+
 void lbm_destroy(lbm_ctx *c)
 {
     if (!c) return;
@@ -654,6 +701,7 @@ lbm_status lbm_set_geometry(lbm_ctx *c, const uint8_t *mask, int64_t n_links, co
                {c->lay.off_sff, prep.sff.data(), n * 4},
                {c->lay.off_pf, prep.pf.data(), n * 4},
                {c->lay.off_pff, prep.pff.data(), n * 4},
+               {c->lay.off_pfi, prep.pfi.data(), prep.has_pfi ? n * 4 : 0},
                {c->lay.off_li, prep.li.data(), n * 4},
                {c->lay.off_kof, kof.data(), kof.size() * 4},
                {c->lay.off_rec, prep.rec.data(), K * 2},
@@ -689,6 +737,8 @@ lbm_status lbm_set_geometry(lbm_ctx *c, const uint8_t *mask, int64_t n_links, co
             }
     c->n_moment_nodes = (int64_t)prep.rec.size();
     c->has_uw = prep.has_uw;
+    c->has_pfi = prep.has_pfi;
+    c->has_ext_scheme = prep.has_ext_scheme;
     c->have_geom = true;
     c->have_init = false;
     c->cur = c->ws + c->lay.off_A;
@@ -1076,6 +1126,8 @@ lbm_status lbm_set_kernel_config(lbm_ctx *c, const lbm_kernel_config *cfg)
         cfg->link_block < 64 || cfg->link_block > 1024 || cfg->link_block % 64 ||
         cfg->graph_steps < 2 || cfg->graph_steps > 1024 || cfg->graph_steps % 2)
         return c->fail(LBM_E_ARG, "lbm_set_kernel_config: unsupported configuration");
+    if (c->p.collision == LBM_COLLISION_MRT && (bx != 256 || cfg->bulk_fused))
+        return c->fail(LBM_E_ARG, "lbm_set_kernel_config: MRT runs with bulk_block_x 256 and bulk_fused 0");
     c->drop_graph();
     c->kcfg = *cfg;
     return LBM_OK;
@@ -1121,6 +1173,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps_per_trial, lbm_kernel_config *
                 for (int rows : {1, 2}) {
                     if (s || (ss && c->p.layout == LBM_LAYOUT_COMPACT)) continue;  // no solid slots there
                     if (rows == 2 && bx != 256) continue;
+                    if (c->p.collision == LBM_COLLISION_MRT && bx != 256) continue;
                     lbm_kernel_config k = best;
                     k.bulk_block_x = bx;
                     k.bulk_store_solid = ss;
@@ -1143,7 +1196,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps_per_trial, lbm_kernel_config *
     const lbm_kernel_config unfused = best;
     for (int ss : {0, 1})
         for (int xo : {0, 1}) {
-            if (s || (ss && c->p.layout == LBM_LAYOUT_COMPACT)) continue;
+            if (s || (ss && c->p.layout == LBM_LAYOUT_COMPACT) || c->p.collision != LBM_COLLISION_BGK) continue;
             lbm_kernel_config k = unfused;
             k.bulk_fused = 1;
             k.bulk_rows = 1;

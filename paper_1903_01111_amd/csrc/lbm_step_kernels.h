@@ -39,9 +39,9 @@ struct LinkIn {
     using R = typename Codec<ST>::R;
     using T = typename Codec<ST>::T;
     uint32_t meta;
-    int32_t sf, sff, pf, pff;
+    int32_t sf, sff, pf, pff, pfi;
     R q, uwx, uwy;
-    T pfv, pffv;
+    T pfv, pffv, pfiv;
     R drf, ufx, ufy, drff, uffx, uffy;
 };
 
@@ -58,6 +58,8 @@ __device__ __forceinline__ void link_load_record(const Links &L, int32_t k, Link
     a.sf = ld_at_nt(L.sf, o4);
     a.sff = ld_at_nt(L.sff, o4);
     a.pff = ld_at_nt(L.pff, o4);
+    // f+_i(x_f) of the outgoing direction: Bouzidi (q > 1/2) and Yu links only
+    a.pfi = L.pfi ? ld_at_nt(L.pfi, o4) : a.pf;
     a.q = ld_at_nt(static_cast<const R *>(L.q), (uint32_t)k * (uint32_t)sizeof(R));
     a.uwx = a.uwy = R(0);
     if (L.uw) {
@@ -80,6 +82,7 @@ __device__ __forceinline__ void link_load_deposits(const void *Mv, const void *P
     const int32_t sffc = a.sff < 0 ? a.sf : a.sff, pffc = a.sff < 0 ? a.pf : a.pff;
     a.pfv = P[a.pf];
     a.pffv = P[pffc];
+    a.pfiv = P[a.pfi];
     a.drf = M[3 * (int64_t)a.sf];
     a.ufx = M[3 * (int64_t)a.sf + 1];
     a.ufy = M[3 * (int64_t)a.sf + 2];
@@ -89,9 +92,11 @@ __device__ __forceinline__ void link_load_deposits(const void *Mv, const void *P
 }
 
 // Value of a link (decoded, before storage rounding) from the moments M and the
-// populations P deposited by the previous bulk step (Section 3.1, or halfway
-// bounce-back where x_ff is unusable), and its momentum-exchange force: the
-// population f+_{i'}(x_f) into the wall and f_i(x_f) back, both along e_{i'}.
+// populations P deposited by the previous bulk step, by the link's scheme
+// (Section 3.1 VIBB; halfway bounce-back, also where x_ff is unusable; Bouzidi;
+// Yu), and its momentum-exchange force: the population f+_{i'}(x_f) into the wall
+// and f_i(x_f) back, both along e_{i'}, with Galilean-invariant momentum
+// exchange (momenta relative to the wall) the term -u_w (f+_{i'} - f_i) added.
 template <int ST>
 __device__ __forceinline__ typename Codec<ST>::R link_value(const Phys &ph, const LinkIn<ST> &a, double &fx,
                                                             double &fy, int &obj)
@@ -139,10 +144,31 @@ __device__ __forceinline__ typename Codec<ST>::R link_value(const Phys &ph, cons
         const R udx = (usx + R(2) * ussx) * third, udy = (usy + R(2) * ussy) * third;
         v = deq(w, R(cxp) * udx + R(cyp) * udy, drd, udx * udx + udy * udy) + neqd + wall;
     }
-    if (a.sff < 0) v = fpf + wall;  // halfway bounce-back
+    // the other schemes from the same deposits (deviation form: their weights sum
+    // to one, so the rest-state weights cancel)
+    const int sch = (int)((a.meta >> 4) & 15u);
+    if (sch == LBM_SCHEME_HBB) {
+        v = fpf + wall;
+    } else if (sch == LBM_SCHEME_BOUZIDI) {
+        const R fpff = C::ld(a.pffv, ph.inv_scale), fpi = C::ld(a.pfiv, ph.inv_scale);
+        if (q <= R(0.5))
+            v = R(2) * q * fpf + (R(1) - R(2) * q) * fpff + wall;
+        else
+            v = (fpf + wall + (R(2) * q - R(1)) * fpi) * rcp_fast(R(2) * q);
+    } else if (sch == LBM_SCHEME_YU) {
+        // wall value by interpolation between x_f and x_ff, then the value at x_f
+        // between the wall point and x_ff (which receives f+_i(x_f) at t+1)
+        const R fpff = C::ld(a.pffv, ph.inv_scale), fpi = C::ld(a.pfiv, ph.inv_scale);
+        v = (q * fpf + (R(1) - q) * fpff + wall + q * fpi) * rcp_fast(R(1) + q);
+    }
     const double m = (double)fpf + (double)v + 2.0 * (double)w;
     fx = cxp * m;
     fy = cyp * m;
+    if (ph.gi_force) {
+        const double dm = (double)fpf - (double)v;
+        fx -= (double)uwx * dm;
+        fy -= (double)uwy * dm;
+    }
     return v;
 }
 
@@ -342,6 +368,67 @@ __device__ __forceinline__ void force_reduce_part(const double2 *__restrict__ wp
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int popc32(uint32_t v) { return __popc(v); }
 
+// MRT collision (Section 2) of one node in deviation form: the six non-conserved
+// moments of the paper's M (e, epsilon, q_x, q_y, p_xx, p_xy) relax towards the
+// moments of the second-order equilibrium at their own rates (s_e, s_eps, s_q and
+// omega = 1/tau for the stresses); rho and j are conserved, and the body force
+// enters as Guo's source taken to moment space with the factor (1 - s/2):
+// e: 6 u.F, epsilon: -6 u.F, q: -F, p_xx: 2 (u_x F_x - u_y F_y), p_xy: u_x F_y +
+// u_y F_x, j: F.  The moment changes return to the populations through
+// M^-1 = M^T diag(9, 36, 36, 6, 12, 6, 12, 4, 4)^-1 (M's rows are orthogonal),
+// in the same direction pairs as the BGK collision: f_i, f_opp change by ev +- od.
+// Mass and momentum are conserved by construction (the axis odd parts take what
+// the diagonals leave of F/2, the rest population what the pairs leave of the
+// mass), and the momentum-carrying parts (q_x, q_y and the odd parts) are formed
+// in D from the exact sums of the inputs, for the reason given in the BGK code.
+template <class A, class D, bool FORCE>
+__device__ __forceinline__ void collide_mrt(A (&f)[9], const Phys &ph, A drho, D jx_d, D jy_d, A ux, A uy, A usq,
+                                            A Fx, A Fy)
+{
+    const A rho = A(1) + drho;
+    const A ru2 = usq + drho * usq;  // rho u.u
+    const A sax = (f[1] + f[3]) + (f[2] + f[4]), sdg = (f[5] + f[7]) + (f[6] + f[8]);
+    // deviations of the moments from those of the rest state, minus the equilibrium's
+    const A ne_e = ((sdg + sdg) - sax - A(4) * f[0]) + (drho + drho) - A(3) * ru2;
+    const A ne_eps = ((sdg - (sax + sax)) + A(4) * f[0]) - drho + A(3) * ru2;
+    const A ne_pxx = ((f[1] + f[3]) - (f[2] + f[4])) - rho * (ux * ux - uy * uy);
+    const A ne_pxy = ((f[5] + f[7]) - (f[6] + f[8])) - rho * (ux * uy);
+    const D Px = FORCE ? jx_d + D(0.5) * D(Fx) : jx_d, Py = FORCE ? jy_d + D(0.5) * D(Fy) : jy_d;
+    const D ne_qx = (D(-2) * (D(f[1]) - D(f[3])) + ((D(f[5]) - D(f[6])) - (D(f[7]) - D(f[8])))) + Px;
+    const D ne_qy = (D(-2) * (D(f[2]) - D(f[4])) + ((D(f[5]) + D(f[6])) - (D(f[7]) + D(f[8])))) + Py;
+    const A se = A(ph.s_e), seps = A(ph.s_eps), om = A(ph.omega);
+    const D sq = D(ph.s_q);
+    A de = -se * ne_e, deps = -seps * ne_eps, dpxx = -om * ne_pxx, dpxy = -om * ne_pxy;
+    D dqx = -sq * ne_qx, dqy = -sq * ne_qy;
+    if (FORCE) {
+        const A uF = ux * Fx + uy * Fy;
+        de += (A(1) - A(0.5) * se) * (A(6) * uF);
+        deps -= (A(1) - A(0.5) * seps) * (A(6) * uF);
+        dpxx += (A(1) - A(0.5) * om) * (A(2) * (ux * Fx - uy * Fy));
+        dpxy += (A(1) - A(0.5) * om) * (ux * Fy + uy * Fx);
+        dqx -= (D(1) - D(0.5) * sq) * D(Fx);
+        dqy -= (D(1) - D(0.5) * sq) * D(Fy);
+    }
+    const A a = de * A(1.0 / 36.0), b = deps * A(1.0 / 36.0), pp = dpxx * A(0.25), rr = dpxy * A(0.25);
+    const A ev13 = (pp - a) - (b + b), ev24 = (-pp - a) - (b + b);
+    const A ev57 = (a + a) + b + rr, ev68 = (a + a) + b - rr;
+    const D cx = FORCE ? D(Fx) * D(1.0 / 6.0) : D(0), cy = FORCE ? D(Fy) * D(1.0 / 6.0) : D(0);
+    const D dx = dqx * D(1.0 / 12.0), dy = dqy * D(1.0 / 12.0);
+    const D od57 = (cx + dx) + (cy + dy), od68 = (cy + dy) - (cx + dx);
+    const D hFx = FORCE ? D(0.5) * D(Fx) : D(0), hFy = FORCE ? D(0.5) * D(Fy) : D(0);
+    const D od13 = hFx - (od57 - od68), od24 = hFy - (od57 + od68);
+    const A o13 = A(od13), o24 = A(od24), o57 = A(od57), o68 = A(od68);
+    f[0] = f[0] - A(2) * ((ev13 + ev24) + (ev57 + ev68));
+    f[1] = f[1] + (ev13 + o13);
+    f[3] = f[3] + (ev13 - o13);
+    f[2] = f[2] + (ev24 + o24);
+    f[4] = f[4] + (ev24 - o24);
+    f[5] = f[5] + (ev57 + o57);
+    f[7] = f[7] + (ev57 - o57);
+    f[6] = f[6] + (ev68 + o68);
+    f[8] = f[8] + (ev68 - o68);
+}
+
 // One node per lane of the lattice described by (g, A, mask), in two halves:
 // bulk_issue loads the node's mask word and issues its nine pulls; bulk_finish
 // (with ph, B, uin, side) does the rest once they have arrived.  A wavefront can
@@ -464,7 +551,8 @@ __device__ __forceinline__ void bulk_issue(const Grid &g, const typename Codec<S
     pl.own_out = own_out;
 }
 
-template <int ST, bool OPEN, bool FORCE, int BX, bool STORE_SOLID, bool CMP = false, bool FUSE = false>
+template <int ST, bool OPEN, bool FORCE, int BX, bool STORE_SOLID, bool CMP = false, bool FUSE = false,
+          int COLL = 0>
 __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
                                             typename Codec<ST>::T *__restrict__ B,
                                             const mask_t *__restrict__ mask,
@@ -657,6 +745,9 @@ __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
         uy += A(0.5) * A(ph.gy);
     }
     const A usq = ux * ux + uy * uy;
+    if constexpr (COLL == 1) {
+        collide_mrt<A, D, FORCE>(f, ph, drho, jx_d, jy_d, ux, uy, usq, Fx, Fy);
+    } else {
     const A om = A(ph.omega);
     const A cf = A(1) - A(0.5) * om;
     // BGK + Guo in direction pairs (i, opp(i)), which share e.u up to its sign:
@@ -723,6 +814,7 @@ __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
         f[i] = f[i] + (si - om * (ne + no));
         f[j] = f[j] + (sj - om * (ne - no));
     }
+    }  // BGK
 #pragma unroll
     for (int i = 0; i < 9; ++i) st_buf(plane_rsrc(B + i * P, pbytes), own, C::st(R(f[i]), ph.scale));
     // deposits for the next link kernel, staged in LDS so that the wavefront
@@ -804,7 +896,8 @@ __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
 }
 
 // Both halves back to back: one row segment per wavefront.
-template <int ST, bool OPEN, bool FORCE, int BX, bool STORE_SOLID, bool CMP = false, bool FUSE = false>
+template <int ST, bool OPEN, bool FORCE, int BX, bool STORE_SOLID, bool CMP = false, bool FUSE = false,
+          int COLL = 0>
 __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
                                           const typename Codec<ST>::T *__restrict__ A,
                                           typename Codec<ST>::T *__restrict__ B,
@@ -822,8 +915,8 @@ __device__ __forceinline__ void bulk_body(const Grid &g, const Phys &ph,
     // scheduler would otherwise hoist the ballot of bulk_finish above them and
     // expose the mask's latency)
     __builtin_amdgcn_sched_barrier(0);
-    bulk_finish<ST, OPEN, FORCE, BX, STORE_SOLID, CMP, FUSE>(g, ph, B, mask, uin, side, x, y, wv, lds_m, lds_p,
-                                                              pl, fa, lds_l);
+    bulk_finish<ST, OPEN, FORCE, BX, STORE_SOLID, CMP, FUSE, COLL>(g, ph, B, mask, uin, side, x, y, wv, lds_m,
+                                                                    lds_p, pl, fa, lds_l);
 }
 
 // clears the force bank of the next step (all blocks share the work)
@@ -834,7 +927,7 @@ __device__ __forceinline__ void zero_bank_part(double *__restrict__ zb, int32_t 
     for (int64_t k = block * 256 + tid; k < nz; k += nblocks * 256) zb[k] = 0.0;
 }
 
-template <int ST, bool OPEN, bool FORCE, int BX, bool STORE_SOLID, bool CMP, int ROWS>
+template <int ST, bool OPEN, bool FORCE, int BX, bool STORE_SOLID, bool CMP, int ROWS, int COLL>
 __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
                                                    const typename Codec<ST>::T *__restrict__ A,
                                                    typename Codec<ST>::T *__restrict__ B,
@@ -873,8 +966,8 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
     }
     const int x = tx * BX + threadIdx.x;
     if (ROWS == 1) {
-        bulk_body<ST, OPEN, FORCE, BX, STORE_SOLID, CMP>(g, ph, A, B, mask, uin, side, x, ty * BY + threadIdx.y,
-                                                         tid >> 6, lds_m, lds_p);
+        bulk_body<ST, OPEN, FORCE, BX, STORE_SOLID, CMP, false, COLL>(g, ph, A, B, mask, uin, side, x,
+                                                                      ty * BY + threadIdx.y, tid >> 6, lds_m, lds_p);
     } else {
         // two row segments per wavefront (rows y and y + BY of a BX x 2BY tile):
         // the second one's pulls are in flight while the first is finished
@@ -883,20 +976,20 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
         bulk_issue<ST, OPEN, CMP>(g, A, mask, x, y0, p0);
         bulk_issue<ST, OPEN, CMP>(g, A, mask, x, y1, p1);
         __builtin_amdgcn_sched_barrier(0);
-        bulk_finish<ST, OPEN, FORCE, BX, STORE_SOLID, CMP>(g, ph, B, mask, uin, side, x, y0, tid >> 6, lds_m, lds_p,
-                                                           p0);
+        bulk_finish<ST, OPEN, FORCE, BX, STORE_SOLID, CMP, false, COLL>(g, ph, B, mask, uin, side, x, y0, tid >> 6,
+                                                                        lds_m, lds_p, p0);
         // the first segment's deposit flush has read the wavefront's LDS staging
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        bulk_finish<ST, OPEN, FORCE, BX, STORE_SOLID, CMP>(g, ph, B, mask, uin, side, x, y1, tid >> 6, lds_m, lds_p,
-                                                           p1);
+        bulk_finish<ST, OPEN, FORCE, BX, STORE_SOLID, CMP, false, COLL>(g, ph, B, mask, uin, side, x, y1, tid >> 6,
+                                                                        lds_m, lds_p, p1);
     }
 }
 
 // The same step with the links of each wavefront's nodes evaluated in the
 // wavefront itself (FUSE): 256 lanes along x per block.
-template <int ST, bool OPEN, bool FORCE, bool STORE_SOLID, bool CMP>
+template <int ST, bool OPEN, bool FORCE, bool STORE_SOLID, bool CMP, int COLL>
 __global__ __launch_bounds__(256) void bulk_fused_kernel(Grid g, Phys ph,
                                                          const typename Codec<ST>::T *__restrict__ A,
                                                          typename Codec<ST>::T *__restrict__ B,
@@ -923,8 +1016,9 @@ __global__ __launch_bounds__(256) void bulk_fused_kernel(Grid g, Phys ph,
         if (tx < 0) tx += gridDim.x, --ty;
         if (tx >= (int)gridDim.x) tx -= gridDim.x, ++ty;
     }
-    bulk_body<ST, OPEN, FORCE, 256, STORE_SOLID, CMP, true>(g, ph, A, B, mask, uin, side, tx * 256 + threadIdx.x,
-                                                            ty, tid >> 6, lds_m, lds_p, &fa, lds_l);
+    bulk_body<ST, OPEN, FORCE, 256, STORE_SOLID, CMP, true, COLL>(g, ph, A, B, mask, uin, side,
+                                                                  tx * 256 + threadIdx.x, ty, tid >> 6, lds_m, lds_p,
+                                                                  &fa, lds_l);
 }
 
 // Batched form: one launch over the tiles of many lattices.  Each block reads its
@@ -932,7 +1026,7 @@ __global__ __launch_bounds__(256) void bulk_fused_kernel(Grid g, Phys ph,
 // populations, masks, inlet rows and segment tables of all instances live in
 // shared arrays at per-instance offsets, while side records, deposits and link
 // values use global numbering.
-template <int ST, bool OPEN, bool FORCE, int BX, bool STORE_SOLID, int ROWS>
+template <int ST, bool OPEN, bool FORCE, int BX, bool STORE_SOLID, int ROWS, int COLL>
 __global__ __launch_bounds__(256) void bulk_batch_kernel(const BatchInst *__restrict__ insts,
                                                          const BatchTile *__restrict__ tiles, int64_t ntiles,
                                                          Phys ph0,
@@ -961,7 +1055,7 @@ __global__ __launch_bounds__(256) void bulk_batch_kernel(const BatchInst *__rest
         ph.gy = I.gy;
         Side sd = side;
         sd.seg = side.seg + I.seg_off;
-        bulk_finish<ST, OPEN, FORCE, BX, STORE_SOLID>(I.g, ph, B + I.pop_off, mask + I.mask_off,
+        bulk_finish<ST, OPEN, FORCE, BX, STORE_SOLID, false, false, COLL>(I.g, ph, B + I.pop_off, mask + I.mask_off,
                                                       uin + 2 * (int64_t)I.uin_off, sd, t.x0 + threadIdx.x,
                                                       t.y0 + threadIdx.y, tid >> 6, lds_m, lds_p, pl);
     };
@@ -1179,7 +1273,7 @@ hipError_t bulk_fused_t(const Grid &g, const Phys &ph, const void *A, void *B, c
 {
     using C = Codec<ST>;
     dim3 grid((g.nx + 255) / 256, g.ny);
-    hipLaunchKernelGGL((bulk_fused_kernel<ST, OPEN, FORCE, SS, CMP>), grid, dim3(256), 0, s, g, ph,
+    hipLaunchKernelGGL((bulk_fused_kernel<ST, OPEN, FORCE, SS, CMP, 0>), grid, dim3(256), 0, s, g, ph,
                        static_cast<const typename C::T *>(A), static_cast<typename C::T *>(B), mask,
                        static_cast<const typename C::R *>(uin), side, fa, zb, nz, xcd, 1.0 / grid.x);
     hipError_t e = hipGetLastError();
@@ -1203,11 +1297,13 @@ hipError_t bulk_fused_shape(const Grid &g, const Phys &ph, const void *A, void *
     return bulk_fused_t<ST, OPEN, FORCE, false, false>(g, ph, A, B, mask, uin, side, fa, zb, nz, cf.xcd, s);
 }
 
+// The fused form (links inside the bulk kernel) runs the BGK collision only.
 template <int ST>
 hipError_t bulk_fused_dispatch(const Grid &g, const Phys &ph, const void *A, void *B, const mask_t *mask,
                                const void *uin, const Side &side, const FuseArgs &fa, double *zb, int32_t nz,
                                const BulkConfig &cf, hipStream_t s)
 {
+    if (ph.coll != LBM_COLLISION_BGK) return hipErrorInvalidValue;
     const bool force = ph.gx != 0.0 || ph.gy != 0.0;
     if (g.x_open)
         return force ? bulk_fused_shape<ST, true, true>(g, ph, A, B, mask, uin, side, fa, zb, nz, cf, s)
@@ -1216,7 +1312,7 @@ hipError_t bulk_fused_dispatch(const Grid &g, const Phys &ph, const void *A, voi
                  : bulk_fused_shape<ST, false, false>(g, ph, A, B, mask, uin, side, fa, zb, nz, cf, s);
 }
 
-template <int ST, bool OPEN, bool FORCE, int BX, bool SS, bool CMP, int ROWS = 1>
+template <int ST, bool OPEN, bool FORCE, int BX, bool SS, bool CMP, int ROWS, int COLL>
 hipError_t bulk_t(const Grid &g, const Phys &ph, const void *A, void *B, const mask_t *mask,
                   const void *uin, const Side &side, double *zb, int32_t nz, int32_t xcd, hipStream_t s,
                   const ForceReduce &fr)
@@ -1226,44 +1322,55 @@ hipError_t bulk_t(const Grid &g, const Phys &ph, const void *A, void *B, const m
     dim3 grid((g.nx + BX - 1) / BX, (g.ny + ROWS * BY - 1) / (ROWS * BY));
     const int64_t nb = (int64_t)grid.x * grid.y;
     if (fr.nw > nb * 256 * FOLD_CHUNK) return hipErrorInvalidValue;  // more partials than lanes
-    hipLaunchKernelGGL((bulk_kernel<ST, OPEN, FORCE, BX, SS, CMP, ROWS>), grid, dim3(BX, BY), 0, s, g, ph,
+    hipLaunchKernelGGL((bulk_kernel<ST, OPEN, FORCE, BX, SS, CMP, ROWS, COLL>), grid, dim3(BX, BY), 0, s, g, ph,
                        static_cast<const typename C::T *>(A), static_cast<typename C::T *>(B), mask,
                        static_cast<const typename C::R *>(uin), side, zb, nz, xcd, 1.0 / grid.x, fr.wpart,
                        fr.wobj, fr.nw, fr.bank, fr.fsum);
     return hipGetLastError();
 }
 
-template <int ST, bool OPEN, bool FORCE>
+// Launch shapes: BGK in every shape; MRT with 256-lane rows (one or two row
+// segments per wavefront, both layouts, with or without solid stores).
+template <int ST, bool OPEN, bool FORCE, int COLL>
 hipError_t bulk_shape(const Grid &g, const Phys &ph, const void *A, void *B, const mask_t *mask,
                       const void *uin, const Side &side, double *zb, int32_t nz, const BulkConfig &cf,
                       hipStream_t s, const ForceReduce &fr)
 {
-    if (g.compact) {
-        // no solid slots to store in the compact layout
-        if (cf.rows == 2)
-            return cf.block_x == 256 ? bulk_t<ST, OPEN, FORCE, 256, false, true, 2>(g, ph, A, B, mask, uin, side, zb, nz, cf.xcd, s, fr)
-                                     : hipErrorInvalidValue;
-        if (cf.block_x == 64) return bulk_t<ST, OPEN, FORCE, 64, false, true>(g, ph, A, B, mask, uin, side, zb, nz, cf.xcd, s, fr);
-        if (cf.block_x == 128) return bulk_t<ST, OPEN, FORCE, 128, false, true>(g, ph, A, B, mask, uin, side, zb, nz, cf.xcd, s, fr);
-        if (cf.block_x == 256) return bulk_t<ST, OPEN, FORCE, 256, false, true>(g, ph, A, B, mask, uin, side, zb, nz, cf.xcd, s, fr);
-        return hipErrorInvalidValue;
-    }
-    if (cf.rows == 2) {
+#define LBM_BULK(BXV, SSV, CMPV, ROWSV) \
+    bulk_t<ST, OPEN, FORCE, BXV, SSV, CMPV, ROWSV, COLL>(g, ph, A, B, mask, uin, side, zb, nz, cf.xcd, s, fr)
+    if (cf.rows == 2 || COLL != LBM_COLLISION_BGK) {
         if (cf.block_x != 256) return hipErrorInvalidValue;
-        return cf.store_solid ? bulk_t<ST, OPEN, FORCE, 256, true, false, 2>(g, ph, A, B, mask, uin, side, zb, nz, cf.xcd, s, fr)
-                              : bulk_t<ST, OPEN, FORCE, 256, false, false, 2>(g, ph, A, B, mask, uin, side, zb, nz, cf.xcd, s, fr);
+        // no solid slots to store in the compact layout
+        if (g.compact) return cf.rows == 2 ? LBM_BULK(256, false, true, 2) : LBM_BULK(256, false, true, 1);
+        if (cf.rows == 2) return cf.store_solid ? LBM_BULK(256, true, false, 2) : LBM_BULK(256, false, false, 2);
+        return cf.store_solid ? LBM_BULK(256, true, false, 1) : LBM_BULK(256, false, false, 1);
     }
-#define LBM_BULK_SHAPE(BXV, SSV)                                                                  \
-    if (cf.block_x == BXV && cf.store_solid == SSV)                                              \
-        return bulk_t<ST, OPEN, FORCE, BXV, SSV, false>(g, ph, A, B, mask, uin, side, zb, nz, cf.xcd, s, fr);
-    LBM_BULK_SHAPE(64, false)
-    LBM_BULK_SHAPE(64, true)
-    LBM_BULK_SHAPE(128, false)
-    LBM_BULK_SHAPE(128, true)
-    LBM_BULK_SHAPE(256, false)
-    LBM_BULK_SHAPE(256, true)
-#undef LBM_BULK_SHAPE
+    if constexpr (COLL == LBM_COLLISION_BGK) {
+        if (g.compact) {
+            if (cf.block_x == 64) return LBM_BULK(64, false, true, 1);
+            if (cf.block_x == 128) return LBM_BULK(128, false, true, 1);
+            if (cf.block_x == 256) return LBM_BULK(256, false, true, 1);
+            return hipErrorInvalidValue;
+        }
+        if (cf.block_x == 64) return cf.store_solid ? LBM_BULK(64, true, false, 1) : LBM_BULK(64, false, false, 1);
+        if (cf.block_x == 128) return cf.store_solid ? LBM_BULK(128, true, false, 1) : LBM_BULK(128, false, false, 1);
+        if (cf.block_x == 256) return cf.store_solid ? LBM_BULK(256, true, false, 1) : LBM_BULK(256, false, false, 1);
+    }
+#undef LBM_BULK
     return hipErrorInvalidValue;
+}
+
+template <int ST, int COLL>
+hipError_t bulk_coll(const Grid &g, const Phys &ph, const void *A, void *B, const mask_t *mask,
+                     const void *uin, const Side &side, double *zb, int32_t nz, const BulkConfig &cf,
+                     hipStream_t s, const ForceReduce &fr)
+{
+    const bool force = ph.gx != 0.0 || ph.gy != 0.0;
+    if (g.x_open)
+        return force ? bulk_shape<ST, true, true, COLL>(g, ph, A, B, mask, uin, side, zb, nz, cf, s, fr)
+                     : bulk_shape<ST, true, false, COLL>(g, ph, A, B, mask, uin, side, zb, nz, cf, s, fr);
+    return force ? bulk_shape<ST, false, true, COLL>(g, ph, A, B, mask, uin, side, zb, nz, cf, s, fr)
+                 : bulk_shape<ST, false, false, COLL>(g, ph, A, B, mask, uin, side, zb, nz, cf, s, fr);
 }
 
 template <int ST>
@@ -1271,15 +1378,14 @@ hipError_t bulk_dispatch(const Grid &g, const Phys &ph, const void *A, void *B, 
                          const void *uin, const Side &side, double *zb, int32_t nz, const BulkConfig &cf,
                          hipStream_t s, const ForceReduce &fr)
 {
-    const bool force = ph.gx != 0.0 || ph.gy != 0.0;
-    if (g.x_open)
-        return force ? bulk_shape<ST, true, true>(g, ph, A, B, mask, uin, side, zb, nz, cf, s, fr)
-                     : bulk_shape<ST, true, false>(g, ph, A, B, mask, uin, side, zb, nz, cf, s, fr);
-    return force ? bulk_shape<ST, false, true>(g, ph, A, B, mask, uin, side, zb, nz, cf, s, fr)
-                 : bulk_shape<ST, false, false>(g, ph, A, B, mask, uin, side, zb, nz, cf, s, fr);
+    if (ph.coll == LBM_COLLISION_MRT)
+        return bulk_coll<ST, LBM_COLLISION_MRT>(g, ph, A, B, mask, uin, side, zb, nz, cf, s, fr);
+    if (ph.coll == LBM_COLLISION_BGK)
+        return bulk_coll<ST, LBM_COLLISION_BGK>(g, ph, A, B, mask, uin, side, zb, nz, cf, s, fr);
+    return hipErrorInvalidValue;
 }
 
-template <int ST, bool OPEN, bool FORCE, bool SS, int ROWS>
+template <int ST, bool OPEN, bool FORCE, bool SS, int ROWS, int COLL>
 hipError_t bulk_batch_t(const BatchInst *insts, const BatchTile *tiles, int64_t ntiles, const Phys &ph,
                         const void *A, void *B, const mask_t *mask, const void *uin, const Side &side,
                         double *zb, int32_t nz, hipStream_t s, const ForceReduce &fr)
@@ -1288,23 +1394,36 @@ hipError_t bulk_batch_t(const BatchInst *insts, const BatchTile *tiles, int64_t 
     constexpr int BX = BATCH_BX, BY = 256 / BATCH_BX;
     const int64_t nb = (ntiles + ROWS - 1) / ROWS;
     if (fr.nw > nb * 256 * FOLD_CHUNK) return hipErrorInvalidValue;  // more partials than lanes
-    hipLaunchKernelGGL((bulk_batch_kernel<ST, OPEN, FORCE, BX, SS, ROWS>), dim3((unsigned)nb), dim3(BX, BY), 0,
-                       s, insts, tiles, ntiles, ph, static_cast<const typename C::T *>(A),
+    hipLaunchKernelGGL((bulk_batch_kernel<ST, OPEN, FORCE, BX, SS, ROWS, COLL>), dim3((unsigned)nb), dim3(BX, BY),
+                       0, s, insts, tiles, ntiles, ph, static_cast<const typename C::T *>(A),
                        static_cast<typename C::T *>(B), mask, static_cast<const typename C::R *>(uin), side,
                        zb, nz, fr.wpart, fr.wobj, fr.nw, fr.bank, fr.fsum);
     return hipGetLastError();
 }
 
-template <int ST, bool OPEN, bool FORCE>
+template <int ST, bool OPEN, bool FORCE, int COLL>
 hipError_t bulk_batch_shape(const BatchInst *insts, const BatchTile *tiles, int64_t ntiles, const Phys &ph,
                             const void *A, void *B, const mask_t *mask, const void *uin, const Side &side,
                             double *zb, int32_t nz, bool ss, int rows, hipStream_t s, const ForceReduce &fr)
 {
-    if (rows == 2)
-        return ss ? bulk_batch_t<ST, OPEN, FORCE, true, 2>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, s, fr)
-                  : bulk_batch_t<ST, OPEN, FORCE, false, 2>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, s, fr);
-    return ss ? bulk_batch_t<ST, OPEN, FORCE, true, 1>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, s, fr)
-              : bulk_batch_t<ST, OPEN, FORCE, false, 1>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, s, fr);
+#define LBM_BATCH(SSV, ROWSV) \
+    bulk_batch_t<ST, OPEN, FORCE, SSV, ROWSV, COLL>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, s, fr)
+    if (rows == 2) return ss ? LBM_BATCH(true, 2) : LBM_BATCH(false, 2);
+    return ss ? LBM_BATCH(true, 1) : LBM_BATCH(false, 1);
+#undef LBM_BATCH
+}
+
+template <int ST, int COLL>
+hipError_t bulk_batch_coll(const BatchInst *insts, const BatchTile *tiles, int64_t ntiles, const Phys &ph,
+                           const void *A, void *B, const mask_t *mask, const void *uin, const Side &side,
+                           double *zb, int32_t nz, bool open, bool force, bool ss, int rows, hipStream_t s,
+                           const ForceReduce &fr)
+{
+    if (open)
+        return force ? bulk_batch_shape<ST, true, true, COLL>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, ss, rows, s, fr)
+                     : bulk_batch_shape<ST, true, false, COLL>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, ss, rows, s, fr);
+    return force ? bulk_batch_shape<ST, false, true, COLL>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, ss, rows, s, fr)
+                 : bulk_batch_shape<ST, false, false, COLL>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, ss, rows, s, fr);
 }
 
 template <int ST>
@@ -1313,11 +1432,13 @@ hipError_t bulk_batch_dispatch(const BatchInst *insts, const BatchTile *tiles, i
                                const Side &side, double *zb, int32_t nz, bool open, bool force, bool ss,
                                int rows, hipStream_t s, const ForceReduce &fr)
 {
-    if (open)
-        return force ? bulk_batch_shape<ST, true, true>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, ss, rows, s, fr)
-                     : bulk_batch_shape<ST, true, false>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, ss, rows, s, fr);
-    return force ? bulk_batch_shape<ST, false, true>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, ss, rows, s, fr)
-                 : bulk_batch_shape<ST, false, false>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, ss, rows, s, fr);
+    if (ph.coll == LBM_COLLISION_MRT)
+        return bulk_batch_coll<ST, LBM_COLLISION_MRT>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, open,
+                                                      force, ss, rows, s, fr);
+    if (ph.coll == LBM_COLLISION_BGK)
+        return bulk_batch_coll<ST, LBM_COLLISION_BGK>(insts, tiles, ntiles, ph, A, B, mask, uin, side, zb, nz, open,
+                                                      force, ss, rows, s, fr);
+    return hipErrorInvalidValue;
 }
 
 template <int ST>
