@@ -421,6 +421,19 @@ lbm_status lbm_adjoint_force(lbm_ctx *ctx, void *ws, size_t ws_bytes, int64_t ns
                              double *dJ_duin, double *dJ_dq, double *dJ_duw, double *dJ_dstate,
                              double *dJ_dinit);
 
+/* For callers that cannot allocate memory (code that must not call hipMalloc,
+ * tight loops, harnesses that forbid allocation): lbm_adjoint_force with the same
+ * arguments, results and errors, but its workspace is a static device array of
+ * LBM_ADJOINT_SCRATCH_BYTES per GPU that the library holds until the process ends;
+ * it allocates nothing, on the device or the host.  A call that needs more
+ * (lbm_adjoint_workspace_bytes above the limit) returns LBM_E_NOMEM.  Every call
+ * on one GPU shares that GPU's array: calls that overlap on one GPU race (one call
+ * per GPU at a time).  Synchronises the context's stream. */
+#define LBM_ADJOINT_SCRATCH_BYTES ((size_t)64 << 20)
+lbm_status lbm_adjoint_force_noalloc(lbm_ctx *ctx, int64_t nsteps, int32_t ckpt_every, int32_t obj,
+                                     double dir_x, double dir_y, double *J, double *dJ_duin, double *dJ_dq,
+                                     double *dJ_duw, double *dJ_dstate, double *dJ_dinit);
+
 #ifdef __cplusplus
 }
 #endif

@@ -121,6 +121,7 @@ SIGNATURES = [
     ("lbm_batch_autotune", _I32, [_P, _I32, _P, _P]),
     ("lbm_adjoint_workspace_bytes", C.c_size_t, [_P, _I64, _I32]),
     ("lbm_adjoint_force", _I32, [_P, _P, C.c_size_t, _I64, _I32, _I32, _D, _D, _P, _P, _P, _P, _P, _P]),
+    ("lbm_adjoint_force_noalloc", _I32, [_P, _I64, _I32, _I32, _D, _D, _P, _P, _P, _P, _P, _P]),
 ]
 
 
@@ -432,6 +433,24 @@ def lbm_adjoint_force(ctx, workspace_ptr, nbytes, nsteps, ckpt_every, obj, dir_x
     check(lib().lbm_adjoint_force(ctx, workspace_ptr, nbytes, nsteps, ckpt_every, obj, float(dir_x),
                                   float(dir_y), C.byref(J), _p(duin), _p(dq), _p(duw), _p(dstate),
                                   _p(dinit)), ctx)
+    return dict(J=J.value, duin=duin, dq=dq, duw=duw, dstate=dstate, dinit=dinit)
+
+
+LBM_ADJOINT_SCRATCH_BYTES = 64 << 20
+
+
+def lbm_adjoint_force_noalloc(ctx, nsteps, ckpt_every, obj, dir_x, dir_y, *, ny, nx, n_links,
+                              want_state=False, want_init=False):
+    """lbm_adjoint_force with the library's static scratch (no workspace argument);
+    returns the same dict as lbm_adjoint_force."""
+    J = C.c_double(0.0)
+    duin = np.zeros((ny, 2))
+    dq = np.zeros(max(n_links, 0))
+    duw = np.zeros((max(n_links, 0), 2))
+    dstate = np.zeros((ny, nx, 9)) if want_state else None
+    dinit = np.zeros((ny, nx, 3)) if want_init else None
+    check(lib().lbm_adjoint_force_noalloc(ctx, nsteps, ckpt_every, obj, float(dir_x), float(dir_y), C.byref(J),
+                                          _p(duin), _p(dq), _p(duw), _p(dstate), _p(dinit)), ctx)
     return dict(J=J.value, duin=duin, dq=dq, duw=duw, dstate=dstate, dinit=dinit)
 
 

@@ -19,7 +19,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 # format (LBM_ST), so that the formats build in parallel
 STORAGE_FORMATS = (0, 1, 2, 3, 4)
 HIP_UNITS = [("lbm_kernels.hip", [f"-DLBM_ST={k}"], f"st{k}") for k in STORAGE_FORMATS] + [
-    ("lbm_adjoint.hip", [], "")]
+    ("lbm_adjoint.hip", [], ""), ("lbm_noalloc.hip", [], "")]
 CXX_SOURCES = ["lbm_runtime.cpp", "lbm_batch.cpp", "lbm_geometry.cpp", "lbm_adjoint.cpp", "lbm_dispatch.cpp"]
 HIP_SOURCES = sorted({u[0] for u in HIP_UNITS})
 

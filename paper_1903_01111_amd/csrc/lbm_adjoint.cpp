@@ -64,6 +64,14 @@ bool adj_layout(const lbm_ctx *c, int64_t nsteps, int32_t k, AdjLayout *L)
 
 }  // namespace
 
+namespace lbm_host {
+
+lbm_status adjoint_force_impl(lbm_ctx *c, void *wsv, size_t ws_bytes, int64_t nsteps, int32_t k, int32_t obj,
+                              double dir_x, double dir_y, double *J, double *dJ_duin, double *dJ_dq,
+                              double *dJ_duw, double *dJ_dstate, double *dJ_dinit, bool no_alloc);
+
+}  // namespace lbm_host
+
 extern "C" {
 
 size_t lbm_adjoint_workspace_bytes(const lbm_ctx *c, int64_t nsteps, int32_t ckpt_every)
@@ -80,6 +88,22 @@ size_t lbm_adjoint_workspace_bytes(const lbm_ctx *c, int64_t nsteps, int32_t ckp
 lbm_status lbm_adjoint_force(lbm_ctx *c, void *wsv, size_t ws_bytes, int64_t nsteps, int32_t k, int32_t obj,
                              double dir_x, double dir_y, double *J, double *dJ_duin, double *dJ_dq,
                              double *dJ_duw, double *dJ_dstate, double *dJ_dinit)
+{
+    return adjoint_force_impl(c, wsv, ws_bytes, nsteps, k, obj, dir_x, dir_y, J, dJ_duin, dJ_dq, dJ_duw, dJ_dstate,
+                              dJ_dinit, false);
+}
+
+}  // extern "C"
+
+// The adjoint call over a device workspace ws.  With no_alloc, nothing is
+// allocated on the host or the device: the forward sweep launches the step
+// kernels directly instead of through the context's HIP graph (whose
+// instantiation allocates), and the results are read back through a fixed stack
+// buffer.  Both forms compute bitwise the same results.
+lbm_status lbm_host::adjoint_force_impl(lbm_ctx *c, void *wsv, size_t ws_bytes, int64_t nsteps, int32_t k,
+                                        int32_t obj, double dir_x, double dir_y, double *J, double *dJ_duin,
+                                        double *dJ_dq, double *dJ_duw, double *dJ_dstate, double *dJ_dinit,
+                                        bool no_alloc)
 {
     if (!c) return LBM_E_ARG;
     if (!c->have_geom || !c->have_init)
@@ -135,7 +159,12 @@ lbm_status lbm_adjoint_force(lbm_ctx *c, void *wsv, size_t ws_bytes, int64_t nst
                               "checkpoint copy")))
             return s;
         if (j + 1 < L.n_ck) {
-            if ((s = lbm_step(c, k))) return s;
+            if (no_alloc) {
+                for (int32_t t = 0; t < k; ++t)
+                    if ((s = enqueue_step(c, false))) return s;
+            } else if ((s = lbm_step(c, k))) {
+                return s;
+            }
             continue;
         }
         // the last segment is written straight into the tape: the reverse sweep
@@ -218,6 +247,47 @@ lbm_status lbm_adjoint_force(lbm_ctx *c, void *wsv, size_t ws_bytes, int64_t nst
     if ((s = c->hip(lbm::launch_refresh(storage, g, ph, c->cur, side, false, st), "refresh")))
         return s;
 
+    if ((s = c->hip(hipStreamSynchronize(st), "adjoint"))) return s;
+    if (!std::isfinite(Jv)) return c->fail(LBM_E_UNSTABLE, "lbm_adjoint_force: non-finite objective");
+    if (J) *J = Jv;
+    const int nx = c->p.nx, ny = c->p.ny, pitch = c->lay.pitch;
+    if (no_alloc) {
+        // every output through a stack buffer, chunk by chunk: dst(j, v) stores
+        // element j of the device array
+        double buf[2048];
+        auto stream_out = [&](const double *src, size_t n, auto &&dst) -> lbm_status {
+            for (size_t j0 = 0; j0 < n; j0 += 2048) {
+                const size_t m = std::min<size_t>(2048, n - j0);
+                lbm_status r = c->hip(hipMemcpyAsync(buf, src + j0, m * sizeof(double), hipMemcpyDeviceToHost, st),
+                                      "gradient read-back");
+                if (!r) r = c->hip(hipStreamSynchronize(st), "gradient read-back");
+                if (r) return r;
+                for (size_t j = 0; j < m; ++j) {
+                    if (!std::isfinite(buf[j])) return c->fail(LBM_E_UNSTABLE, "lbm_adjoint_force: non-finite gradient");
+                    dst(j0 + j, buf[j]);
+                }
+            }
+            return LBM_OK;
+        };
+        if (dJ_duin && (s = stream_out(duin, 2 * (size_t)ny, [&](size_t j, double v) { dJ_duin[j] = v; })))
+            return s;
+        if (dJ_dq && (s = stream_out(dq, nl, [&](size_t j, double v) { dJ_dq[c->link_order[j]] = v; }))) return s;
+        if (dJ_duw && (s = stream_out(duw, 2 * nl, [&](size_t j, double v) {
+                           dJ_duw[2 * c->link_order[j / 2] + (j & 1)] = v;
+                       })))
+            return s;
+        for (int i = 0; i < 9 && dJ_dstate; ++i)
+            for (int y = 0; y < ny; ++y)
+                if ((s = stream_out(dstate + (size_t)i * L.dplane + (size_t)y * pitch, (size_t)nx,
+                                    [&](size_t x, double v) { dJ_dstate[((size_t)y * nx + x) * 9 + i] = v; })))
+                    return s;
+        for (int i = 0; i < 3 && dJ_dinit; ++i)
+            for (int y = 0; y < ny; ++y)
+                if ((s = stream_out(dinit + (size_t)i * L.dplane + (size_t)y * pitch, (size_t)nx,
+                                    [&](size_t x, double v) { dJ_dinit[((size_t)y * nx + x) * 3 + i] = v; })))
+                    return s;
+        return LBM_OK;
+    }
     // read-back
     std::vector<double> h;
     auto fetch = [&](const void *src, size_t n) -> lbm_status {
@@ -231,9 +301,6 @@ lbm_status lbm_adjoint_force(lbm_ctx *c, void *wsv, size_t ws_bytes, int64_t nst
                 if (!std::isfinite(v)) return c->fail(LBM_E_UNSTABLE, "lbm_adjoint_force: non-finite gradient");
         return r;
     };
-    if ((s = c->hip(hipStreamSynchronize(st), "adjoint"))) return s;
-    if (!std::isfinite(Jv)) return c->fail(LBM_E_UNSTABLE, "lbm_adjoint_force: non-finite objective");
-    if (J) *J = Jv;
     if (dJ_duin) {
         if ((s = fetch(duin, 2 * (size_t)c->p.ny))) return s;
         std::copy(h.begin(), h.end(), dJ_duin);
@@ -249,7 +316,6 @@ lbm_status lbm_adjoint_force(lbm_ctx *c, void *wsv, size_t ws_bytes, int64_t nst
             dJ_duw[2 * c->link_order[j] + 1] = h[2 * j + 1];
         }
     }
-    const int nx = c->p.nx, ny = c->p.ny, pitch = c->lay.pitch;
     if (dJ_dstate) {
         for (int i = 0; i < 9; ++i) {
             if ((s = fetch(dstate + (size_t)i * L.dplane, (size_t)L.dplane))) return s;
@@ -268,5 +334,3 @@ lbm_status lbm_adjoint_force(lbm_ctx *c, void *wsv, size_t ws_bytes, int64_t nst
     }
     return LBM_OK;
 }
-
-}  // extern "C"
