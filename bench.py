@@ -376,6 +376,271 @@ def form_adjoint(B, steps=2000, ckpt=100):
             "params": "(U, cx, cy, R); tau fixed"}
 
 
+SCHEME_NAMES = {0: "vibb", 1: "hbb", 2: "bouzidi", 3: "yu"}
+
+
+def _batch_read_at(B, cases, targets, storage="f64", read=None, chunk=None):
+    """One batch of the cases; instance i is read by read(bt, i) once the batch
+    has run targets[i] steps (rounded up to whole graphs).  Returns the readings
+    and the steps run."""
+    import numpy as np
+    bt = B.Batch(cases, storage=storage)
+    order = np.argsort(targets, kind="stable")
+    done = 0
+    out = [None] * len(cases)
+    for i in order:
+        t = int(-(-int(targets[i]) // 16) * 16)
+        if t > done:
+            bt.step(t - done)
+            done = t
+        out[i] = read(bt, int(i))
+    bt.close()
+    return out, done
+
+
+def form_wall_sweep(B, qs=(0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9), res=(6.0, 60.0),
+                    taus=(0.51, 0.55, 0.6, 0.7, 0.8, 0.9, 1.0), schemes=(0, 2, 3), storage="f64",
+                    decay=4.0):
+    """Section 4.1 in one batched launch: Poiseuille flow with a moving top wall
+    (L = 60, g = 1e-6, u_top = 0.01, bottom wall halfway bounce-back, top wall at q
+    by the scheme under test), MRT collision.  Error vs q at Re = 6 and 60, and vs
+    tau at q = 0.8: the paper's |(u_s - u_e)/u_e| after each instance has run
+    `decay` slowest-mode decay times from the exact profile.  Reading: the paper
+    plots this error against the top wall's q without saying where it is taken;
+    it is reported at the boundary node next to the moving wall ("top_node", the
+    node the closure acts on) and as its maximum over the fluid rows ("max_rows",
+    which the fixed halfway bounce-back bottom wall dominates: with MRT at these
+    rates its slip error is the same for every top-wall scheme).  The paper's
+    statements about the three schemes are evaluated on the top-node error as
+    inequalities and reported, true or false."""
+    import numpy as np
+    from paper_1903_01111_amd import workloads as W
+    cases, tags = [], []
+    for re in res:
+        for q in qs:
+            for s in schemes:
+                cases.append(W.moving_wall_poiseuille(q, re, s))
+                tags.append(("re", re, q, s))
+    for tau in taus:
+        for s in schemes:
+            cases.append(W.moving_wall_poiseuille(0.8, 0.0, s, tau=tau))
+            tags.append(("tau", tau, 0.8, s))
+    L, g, ut = 60, 1e-6, 0.01
+
+    def err(bt, i):
+        c, tag = cases[i], tags[i]
+        q = tag[2]
+        nu = (c.tau - 0.5) / 3.0
+        yb, H = 0.5, L - 0.5 + q
+        _, ux, _ = bt.moments(i)
+        y = np.arange(1, L + 1) - yb
+        ue = -g / (2 * nu) * y ** 2 + (g * H / (2 * nu) + ut / H) * y
+        e = np.abs((ux[1:L + 1, 0] - ue) / ue)
+        return float(e[-1]), float(e.max())
+
+    targets = []
+    for c, tag in zip(cases, tags):
+        nu = (c.tau - 0.5) / 3.0
+        H = L - 0.5 + tag[2]
+        targets.append(decay * H * H / (np.pi ** 2 * nu))
+    t0 = time.perf_counter()
+    errs, steps = _batch_read_at(B, cases, targets, storage, err)
+    wall = time.perf_counter() - t0
+    out = {"workload": "Section 4.1 moving-wall Poiseuille, L = 60, g = 1e-6, u_top = 0.01, MRT, "
+                       f"{len(cases)} instances in one batch ({storage})",
+           "error": "max over fluid rows of |(u_s - u_e)/u_e| (the paper's metric)",
+           "q": list(qs), "tau": list(taus), "steps": steps, "wall_s": round(wall, 2)}
+    for m, name in ((0, "top_node"), (1, "max_rows")):
+        d = {}
+        for re in res:
+            d[f"re{re:g}"] = {SCHEME_NAMES[s]: [errs[k][m] for k, tg in enumerate(tags)
+                                                if tg[0] == "re" and tg[1] == re and tg[3] == s] for s in schemes}
+        d["tau_q0.8"] = {SCHEME_NAMES[s]: [errs[k][m] for k, tg in enumerate(tags) if tg[0] == "tau" and tg[3] == s]
+                         for s in schemes}
+        out[name] = d
+    if set(schemes) >= {0, 2, 3} and 60.0 in res and 6.0 in res:
+        hi = [k for k, q in enumerate(qs) if q > 0.5]
+        lo = [k for k, q in enumerate(qs) if q < 0.5]
+        r60, r6, tt = (out["top_node"][k] for k in ("re60", "re6", "tau_q0.8"))
+        best_other60 = [min(r60["bouzidi"][k], r60["yu"][k]) for k in hi]
+        spread = {n: max(v) / min(v) for n, v in tt.items()}
+        out["paper_statements"] = {
+            "re60: VIBB error falls as q grows beyond 1/2":
+                all(r60["vibb"][a] >= r60["vibb"][b] for a, b in zip(hi, hi[1:])),
+            "re60: VIBB below both other schemes for every q > 1/2":
+                all(r60["vibb"][k] < o for k, o in zip(hi, best_other60)),
+            "re60: smallest ratio other/VIBB for q > 1/2": round(min(o / r60["vibb"][k]
+                                                                      for k, o in zip(hi, best_other60)), 2),
+            "re6: VIBB not above the others for q > 1/2":
+                all(r6["vibb"][k] <= min(r6["bouzidi"][k], r6["yu"][k]) for k in hi),
+            "re6: largest ratio between schemes for q < 1/2": round(max(
+                max(r6[a][k] for a in r6) / min(r6[a][k] for a in r6) for k in lo), 2),
+            "tau sweep: max/min error over tau per scheme": {n: round(v, 2) for n, v in spread.items()},
+            "tau sweep: VIBB depends least on tau": spread["vibb"] < min(spread["bouzidi"], spread["yu"]),
+        }
+    return out
+
+
+def _couette_error(ux, uy, solid, case):
+    """Relative L2 error of the fluid velocity against Section 4.2's exact profile
+    u_theta(r) = u_w R1 (R2/r - r/R2) / (R2/R1 - R1/R2) about the cylinders' centre."""
+    import numpy as np
+    inner = case.prims[0]
+    cx, cy, r1, om = inner.cx, inner.cy, inner.r, inner.omega
+    r2 = case.prims[1].r
+    L = solid.shape[0]
+    yy, xx = np.mgrid[0:L, 0:L]
+    dx, dy = xx - cx, yy - cy
+    r = np.hypot(dx, dy)
+    fl = solid == 0
+    ut = om * r1 ** 2 * (r2 ** 2 / r - r) / (r2 ** 2 - r1 ** 2)
+    ex, ey = -dy / r * ut, dx / r * ut
+    return float(np.sqrt(((ux - ex) ** 2 + (uy - ey) ** 2)[fl].sum() / (ex ** 2 + ey ** 2)[fl].sum()))
+
+
+def form_couette(B, Ls=(20, 40, 80, 160), res=(6.0, 60.0), res_at_160=(6.0, 12.0, 24.0, 36.0, 48.0, 60.0),
+                 schemes=(0, 3), storage="f64", diffusive=1.5):
+    """Section 4.2: cylindrical Couette flow, R1 = L/4.8, R2 = L/2.4, L = 20..160 at
+    Re = 6 and 60 (Re = u_w L / nu at tau = 0.55, readings), VIBB against Yu's
+    scheme, MRT, one batched launch.  Each instance is read after `diffusive` diffusion times
+    (R2 - R1)^2 / nu (VIBB and Yu do not conserve mass on curved walls, so there is
+    no exact steady state: the start-up transient has then decayed and the drift
+    is still negligible).  Error: relative L2 over the fluid nodes; order from
+    successive resolutions; the error against Re at L = 160."""
+    import numpy as np
+    from paper_1903_01111_amd import workloads as W
+    cases, tags = [], []
+    for re in res:
+        for L in Ls:
+            for s in schemes:
+                cases.append(W.cylindrical_couette(L, re, s))
+                tags.append(("L", re, L, s))
+    for re in (res_at_160 if 160 in Ls else ()):
+        if re in res:
+            continue
+        for s in schemes:
+            cases.append(W.cylindrical_couette(160, re, s))
+            tags.append(("L", re, 160, s))
+    geoms = [B.case_geometry(c) for c in cases]
+
+    def err(bt, i):
+        _, ux, uy = bt.moments(i)
+        return _couette_error(ux, uy, geoms[i][0], cases[i])
+
+    targets = [diffusive * (c.prims[1].r - c.prims[0].r) ** 2 / ((c.tau - 0.5) / 3.0) for c in cases]
+    t0 = time.perf_counter()
+    errs, steps = _batch_read_at(B, cases, targets, storage, err)
+    wall = time.perf_counter() - t0
+    out = {"workload": f"Section 4.2 cylindrical Couette, MRT, {len(cases)} instances in one batch ({storage})",
+           "L": list(Ls), "steps_max": steps, "wall_s": round(wall, 2)}
+    for re in res:
+        d = {}
+        for s in schemes:
+            e = [errs[k] for k, tg in enumerate(tags) if tg[1] == re and tg[3] == s and tg[2] in Ls]
+            d[SCHEME_NAMES[s]] = {"error": e, "order": [round(float(np.log2(e[k] / e[k + 1])), 3)
+                                                         for k in range(len(e) - 1)]}
+        out[f"re{re:g}"] = d
+    if 160 in Ls:
+        res_all = sorted(set(res) | set(res_at_160))
+        out["L160_vs_re"] = {"re": res_all, **{SCHEME_NAMES[s]: [
+            next(errs[k] for k, tg in enumerate(tags) if tg[1] == re and tg[2] == 160 and tg[3] == s)
+            for re in res_all] for s in schemes}}
+    if set(schemes) >= {0, 3} and 160 in Ls:
+        st = {}
+        for re in res:
+            v, y = out[f"re{re:g}"]["vibb"], out[f"re{re:g}"]["yu"]
+            st[f"re{re:g}: VIBB below Yu at every L"] = all(a < b for a, b in zip(v["error"], y["error"]))
+            st[f"re{re:g}: VIBB order, finest pair"] = v["order"][-1]
+        ev, ey = out["L160_vs_re"]["vibb"], out["L160_vs_re"]["yu"]
+        st["L=160: error grows with Re (VIBB)"] = all(a <= b for a, b in zip(ev, ev[1:]))
+        st["L=160: VIBB error at Re 60 over Re 6"] = round(ev[-1] / ev[0], 2)
+        st["L=160: Yu error at Re 60 over Re 6"] = round(ey[-1] / ey[0], 2)
+        out["paper_statements"] = st
+    return out
+
+
+def form_magnus(B, spins=(0.0, 0.5, 1.0, 1.5, 2.0), steps=40000, window=2000, storage="f64", L=400):
+    """Section 4.3: lift on a particle spinning at S_pa = omega R / U in a walled
+    Poiseuille channel (L = 400, R = 10, U = 0.05, Re = 2UR/nu = 20), MRT, the
+    Galilean-invariant momentum exchange, all spin numbers in one batched launch.
+    C_L = F_y / (rho0 U^2 R) and C_D = F_x / (rho0 U^2 R) averaged over the last
+    window; the change between the last two windows shows how steady it is.  The
+    paper compares with literature values that are not available here: these
+    coefficients are parity-unpinned (the kernels match the oracle on the same
+    flow at small size in the GPU tests)."""
+    import numpy as np
+    from paper_1903_01111_amd import workloads as W
+    cases = [W.magnus_channel(s, L=L) for s in spins]
+    U, R = 0.05, cases[0].prims[0].r
+    bt = B.Batch(cases, storage=storage)
+    t0 = time.perf_counter()
+    bt.step(steps - 2 * window)
+    s0 = [bt.force(i, 0)[1].copy() for i in range(len(cases))]
+    bt.step(window)
+    s1 = [bt.force(i, 0)[1].copy() for i in range(len(cases))]
+    bt.step(window)
+    s2 = [bt.force(i, 0)[1].copy() for i in range(len(cases))]
+    for i in range(len(cases)):
+        bt.moments(i)  # finite check
+    bt.close()
+    wall = time.perf_counter() - t0
+    f1 = [(b - a) / window for a, b in zip(s0, s1)]
+    f2 = [(b - a) / window for a, b in zip(s1, s2)]
+    cl = [float(f[1] / (U * U * R)) for f in f2]
+    cd = [float(f[0] / (U * U * R)) for f in f2]
+    drift = [float(abs(b[1] - a[1]) / (U * U * R)) for a, b in zip(f1, f2)]
+    out = {"workload": f"Section 4.3 Magnus flow, {cases[0].nx}x{cases[0].ny}, R = {R:g}, U = {U}, Re = 20 "
+                       f"(nu = {(cases[0].tau - 0.5) / 3:.4g}), MRT, Galilean-invariant momentum exchange, "
+                       f"{len(cases)} spin numbers in one batch ({storage})",
+           "S_pa": list(spins), "C_L": cl, "C_D": cd, "C_L_change_between_last_windows": drift,
+           "steps": steps, "window": window, "wall_s": round(wall, 2),
+           "sign": "C_L = F_y/(rho0 U^2 R); a counter-clockwise spin (omega > 0) in a +x stream lifts towards -y"}
+    out["checks"] = {"C_L(0) ~ 0 (symmetric channel)": abs(cl[0]) < 1e-3,
+                     "|C_L| grows with S_pa": all(abs(a) < abs(b) for a, b in zip(cl, cl[1:])),
+                     "C_L < 0 for S_pa > 0": all(c < 0 for c in cl[1:])}
+    return out
+
+
+def form_position(B, n_offsets=64, nx=512, re=20.0, steps=24000, window=2000, storage="f32", schemes=(0, 2, 1)):
+    """The solid-position dependency (abstract, Section 5) in one batched launch:
+    the walled-cylinder channel at one size and Re with n_offsets sub-grid disc
+    offsets, per disc closure (VIBB, Bouzidi, halfway bounce-back; walls halfway
+    bounce-back), MRT.  C_D = 2 F_x / (rho0 U_max^2 D) averaged over the last
+    window; reported: std(C_D)/mean(C_D) over the offsets for each closure."""
+    import numpy as np
+    from paper_1903_01111_amd import workloads as W
+    cases = W.position_study(n_offsets, nx, re, schemes=schemes)
+    D = 2.0 * cases[0].prims[0].r
+    U = 0.05
+    bt = B.Batch(cases, storage=storage)
+    t0 = time.perf_counter()
+    bt.step(steps - window)
+    a = [bt.force(i, 0)[1].copy() for i in range(len(cases))]
+    bt.step(window)
+    b = [bt.force(i, 0)[1].copy() for i in range(len(cases))]
+    for i in range(len(cases)):
+        bt.moments(i)
+    bt.close()
+    wall = time.perf_counter() - t0
+    cd = np.array([2.0 * (y[0] - x[0]) / window / (U * U * D) for x, y in zip(a, b)])
+    cl = np.array([2.0 * (y[1] - x[1]) / window / (U * U * D) for x, y in zip(a, b)])
+    ns = len(schemes)
+    out = {"workload": f"{n_offsets} sub-grid disc offsets x {ns} closures, walled cylinder {nx}x{nx // 4}, "
+                       f"Re = {re:g}, R = {cases[0].prims[0].r:g}, MRT, one batch ({storage})",
+           "steps": steps, "window": window, "wall_s": round(wall, 2), "nodes": sum(c.nx * c.ny for c in cases)}
+    for j, s in enumerate(schemes):
+        v, l = cd[j::ns], cl[j::ns]
+        out[SCHEME_NAMES[s]] = {"C_D_mean": round(float(v.mean()), 5),
+                                "C_D_std_over_mean": float(v.std() / v.mean()),
+                                "C_D_range_over_mean": float((v.max() - v.min()) / v.mean()),
+                                "C_L_std": float(l.std())}
+    if set(schemes) >= {0, 2, 1}:
+        out["paper_statement: VIBB depends least on the disc position"] = (
+            out["vibb"]["C_D_std_over_mean"] < min(out["bouzidi"]["C_D_std_over_mean"],
+                                                   out["hbb"]["C_D_std_over_mean"]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -392,7 +657,7 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the FP16/BF16 storage, batched, cylinder and adjoint measurements")
     ap.add_argument("--form", choices=["storage_16bit", "batched", "cylinder", "cylinder_flow", "dense_layout",
-                                       "adjoint"],
+                                       "adjoint", "wall_sweep", "couette", "magnus", "position"],
                     help="run only this form and print its JSON object")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -421,6 +686,14 @@ def main():
             res = form_cylinder_flow(B)
         elif args.form == "dense_layout":
             res = form_single(B, workload(args.workload), 1000, 100, layout="dense")
+        elif args.form == "wall_sweep":
+            res = form_wall_sweep(B)
+        elif args.form == "couette":
+            res = form_couette(B)
+        elif args.form == "magnus":
+            res = form_magnus(B)
+        elif args.form == "position":
+            res = form_position(B)
         else:
             res = form_adjoint(B)
         print(json.dumps({"form": args.form, **res}), flush=True)
@@ -552,6 +825,11 @@ def main():
         forms["porous_dense_layout_f32"]["note"] = ("the same porous step with every node of the padded "
                                                     "lattice stored (solid nodes included)")
         forms["adjoint"] = form_adjoint(B)
+        for name, fn in (("wall_sweep", form_wall_sweep), ("couette", form_couette), ("magnus", form_magnus),
+                         ("position", form_position)):
+            forms[name] = fn(B)
+            print(f"[bench] {name}: {forms[name].get('paper_statements', forms[name].get('checks'))}",
+                  file=sys.stderr, flush=True)
         out["forms"] = forms
     print(json.dumps(out), flush=True)
 
