@@ -10,10 +10,11 @@ U[5,15] to porosity 0.6, body force 1e-6, tau = 0.7, FP32 storage -- the one
 workload whose working set (about 1.2 GB) exceeds the 256 MB last-level cache,
 so its bandwidth is an HBM figure.
 
-Prints ONE JSON line: MLUPS over the timed steps, the HBM roofline of the bulk
-kernel (durations from HIP events recorded around every launch on the stream the
-kernels run on), and the FP64 CPU oracle timed on a bounded sample of the same
-workload.
+Prints ONE JSON line: MLUPS over the timed steps (HIP graph replay), the HBM
+roofline of the bulk kernel (durations from a separate pass with HIP events
+recorded around every launch on the stream the kernels run on), the FP64 CPU
+oracle timed on every host core on a bounded sample of the same workload, and the
+GPU's error against that oracle run.
 """
 import argparse
 import hashlib
@@ -32,7 +33,7 @@ KERNEL_SRCS = [os.path.join(ROOT, "paper_1903_01111_amd", "csrc", f)
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "bulk_kernel_porous_8192x2048_f32_counters.txt")
 METRIC = ("MLUPS + % HBM roofline at stated drag/velocity error; "
           "FP16-store & adjoint vs FP32")
-BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "f32w": 4}
+BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "f32w": 4, "f32p": 4}
 
 
 def kernel_hash():
@@ -43,15 +44,15 @@ def kernel_hash():
     return h.hexdigest()[:12]
 
 
-def bulk_kernel_name(kcfg, layout, storage):
+def bulk_kernel_name(kcfg, layout, storage, coll=0):
     """Template name of the periodic forced bulk kernel (the porous workload) that a
-    launch configuration runs (None for the fused form)."""
+    launch configuration runs (None for the fused form); coll 0 BGK, 1 MRT."""
     if kcfg["bulk_fused"]:
         return None
     b = lambda v: "true" if v else "false"
-    st = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3, "f32w": 4}[storage]
+    st = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3, "f32w": 4, "f32p": 5}[storage]
     return (f"void bulk_kernel<{st}, false, true, {kcfg['bulk_block_x']}, {b(kcfg['bulk_store_solid'])}, "
-            f"{b(layout == 'compact')}, {max(kcfg.get('bulk_rows', 1), 1)}>")
+            f"{b(layout == 'compact')}, {max(kcfg.get('bulk_rows', 1), 1)}, {coll}>")
 
 
 def counter_traffic(layout, kcfg, storage="f32"):
@@ -91,21 +92,23 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def algorithmic_bytes(case, mask, n_links, n_vibb, storage):
-    """Bytes the method must move per launch (no cache reuse assumed beyond one
-    read of every input and one write of every output):
-    bulk: 9 loads + 9 stores per fluid node, a 2-byte mask word per node, plus the
-          two open columns written again; link: per link 16 B of indices, q (and u_w),
-          the populations of f and ff (9 + 9 for VIBB, 1 for halfway bounce-back)
-          and one store."""
+def algorithmic_bytes(case, mask, n_links, storage):
+    """Bytes the method must move per launch (each input read once, each output
+    written once), as the algorithmic count of the step:
+    bulk: 9 loads + 9 stores per fluid node and a 1-byte node type per node (the
+          implementation reads a 2-byte mask word that also carries the node's link
+          directions; those bytes are not counted), plus the two open columns
+          written again;
+    link: per link 8 bytes of record (node and direction, q), the two populations
+          f+_{i'} at x_f and x_ff, 24 bytes of moments (rho, u at x_f and x_ff in
+          FP32), and the stored value is counted in the bulk kernel's pull."""
     s = BYTES[storage]
-    rb = 8 if storage == "f64" else 4
     n = case.nx * case.ny
     nf = int((mask == 0).sum())
-    bulk = nf * 18 * s + 2 * n
+    bulk = nf * 18 * s + n
     if case.x_open:
         bulk += 2 * case.ny * 9 * s
-    link = n_links * (16 + rb + s) + n_vibb * 18 * s + (n_links - n_vibb) * s
+    link = n_links * (8 + 2 * s + 24)
     return bulk, link
 
 
@@ -146,119 +149,143 @@ def e_u(a, b):
     return float(max(np.abs(a[0] - b[0]).max(), np.abs(a[1] - b[1]).max()) / ref)
 
 
-def form_precision(B, case, steps_err, steps_time, layout="compact", steps_long=20000):
-    """16-bit deviation storage against FP32 and FP64 on the same workload, from the
-    same initial state: velocity error e_u and drag error after steps_err steps
-    against FP64 storage (the FP64 path equals the oracle to 1e-11 at every tested
-    size, so it stands in for the oracle at full size) and against FP32; e_u and the
-    error of the mean u_x (the superficial velocity) against FP32 after steps_long
-    steps; then throughput."""
+def oracle_reference(case, steps, threads):
+    """The FP64 oracle on the full workload from its initial state: (ux, uy, force
+    sum of object 0, seconds, threads used)."""
+    import oracle
+    g = oracle.case_geometry(case)
+    fp = oracle.init_equilibrium(g.solid, *case.init_fields())
+    _, used = oracle.threads_for(threads)
+    t0 = time.perf_counter()
+    fs, _, _ = oracle.run(fp, g, tau=case.tau, gx=case.gx, gy=case.gy, rho0=case.rho0, x_open=case.x_open,
+                          n_obj=case.n_obj, nsteps=steps, u_in=case.inlet(), scheme=oracle.case_scheme(case, g),
+                          threads=threads, **oracle.case_kwargs(case))
+    sec = time.perf_counter() - t0
+    _, ux, uy = oracle.moments(fp, g.solid, (case.gx, case.gy), threads=threads)
+    del fp
+    return ux, uy, fs[0].copy(), sec, used
+
+
+def host_info():
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "cpu_model": model}
+
+
+def form_precision(B, case, ref, steps_time, layout="compact", steps_long=20000, storages=None):
+    """Every storage form against the FP64 oracle on the full workload, from the
+    same initial state: velocity error e_u = max|u - u_oracle| / max|u_oracle| and
+    drag error after ref["steps"] steps; the 16-bit forms also against FP32 after
+    steps_long steps (e_u and the mean u_x, the superficial velocity); then
+    throughput (graph replay) and the bulk kernel's time and algorithmic bandwidth.
+    ref: dict(ux, uy, force, steps) from oracle_reference."""
     import numpy as np
-    ref = B.Lattice(case, storage="f64", layout=layout)
-    ref.step(steps_err)
-    _, u64, v64 = ref.moments()
-    _, fs64, _ = ref.force(0)
-    ref.close()
-    f32 = B.Lattice(case, storage="f32", layout=layout)
-    f32.step(steps_err)
-    _, u32, v32 = f32.moments()
-    k = B.dev_scale_for(B.lbm_max_deviation(f32.ctx))
-    _, fs32, _ = f32.force(0)
-    out = {"f32": {"e_u_vs_f64": e_u((u32, v32), (u64, v64)),
-                   "drag_err_vs_f64": float(abs(fs32[0] - fs64[0]) / abs(fs64[0])), "steps": steps_err}}
-    f32.step(steps_long - steps_err)
-    _, u32l, v32l = f32.moments()
-    f32.close()
-    # FP32 storage with the bulk collision in FP64
-    wide = B.Lattice(case, storage="f32w", layout=layout)
-    wide.step(steps_err)
-    _, uw_, vw_ = wide.moments()
-    _, fsw, _ = wide.force(0)
-    B.lbm_autotune(wide.ctx, 10)
-    ms, link_ms, bulk_ms, ksteps = replay_then_timed(B, wide, steps_time)
-    out["f32w"] = {"e_u_vs_f64": e_u((uw_, vw_), (u64, v64)),
-                   "drag_err_vs_f64": float(abs(fsw[0] - fs64[0]) / abs(fs64[0])), "steps": steps_err,
-                   "mlups": round(case.nx * case.ny * steps_time / (ms * 1e-3) / 1e6, 1),
-                   "bulk_us": round(bulk_ms * 1e3 / ksteps, 2)}
-    wide.close()
-    print(f"[bench] f32w: {out['f32w']}", file=sys.stderr, flush=True)
-    for st, kk in (("f16", k), ("bf16", 0)):
+    n = ref["steps"]
+    uo, vo, fo = ref["ux"], ref["uy"], ref["force"]
+    storages = storages or [("f32", 0), ("f32p", 0), ("f32w", 0), ("f16", None), ("bf16", 0)]
+    out = {"reference": f"FP64 oracle, {n} steps of the full lattice from the initial state"}
+    long32 = None
+    k16 = None
+    for st, kk in storages:
+        if kk is None:
+            kk = k16
         lat = B.Lattice(case, storage=st, dev_scale_log2=kk, layout=layout)
-        lat.step(steps_err)
-        r = {"scale_log2": kk, "steps": steps_err, "steps_long": steps_long}
+        lat.step(n)
+        r = {"steps": n}
         try:
             _, u, v = lat.moments()
             _, fs, _ = lat.force(0)
-            r.update(e_u_vs_f32=e_u((u, v), (u32, v32)), e_u_vs_f64=e_u((u, v), (u64, v64)),
-                     drag_err_vs_f32=float(abs(fs[0] - fs32[0]) / abs(fs32[0])),
-                     drag_err_vs_f64=float(abs(fs[0] - fs64[0]) / abs(fs64[0])))
-            lat.step(steps_long - steps_err)
-            _, u, v = lat.moments()
-            r.update(e_u_vs_f32_long=e_u((u, v), (u32l, v32l)),
-                     mean_ux_err_vs_f32_long=float(abs(u.mean() - u32l.mean()) / abs(u32l.mean())))
+            r.update(e_u_vs_oracle=e_u((u, v), (uo, vo)),
+                     drag_err_vs_oracle=float(abs(fs[0] - fo[0]) / abs(fo[0])))
+            if st == "f32":
+                k16 = B.dev_scale_for(B.lbm_max_deviation(lat.ctx))
+                lat.step(steps_long - n)
+                _, ul, vl = lat.moments()
+                long32 = (ul, vl)
+            elif st in ("f16", "bf16") and long32 is not None:
+                r["scale_log2"] = kk
+                lat.step(steps_long - n)
+                _, ul, vl = lat.moments()
+                r.update(e_u_vs_f32_long=e_u((ul, vl), long32), steps_long=steps_long,
+                         mean_ux_err_vs_f32_long=float(abs(ul.mean() - long32[0].mean()) / abs(long32[0].mean())))
         except B.LbmError as e:
             r["error"] = f"unstable ({e})"
         B.lbm_autotune(lat.ctx, 10)
         ms, link_ms, bulk_ms, ksteps = replay_then_timed(B, lat, steps_time)
-        nfb = B.lbm_check_geometry(lat.params, lat.mask, lat.node, lat.dir, lat.q, lat.uw, lat.obj,
-                                   lat.scheme)
-        bulk_bytes, _ = algorithmic_bytes(case, lat.mask, lat.n_links, lat.n_links - nfb, st)
-        r.update(mlups=round(case.nx * case.ny * steps_time / (ms * 1e-3) / 1e6, 1),
-                 bulk_GBps_algorithmic=round(bulk_bytes / (bulk_ms * 1e-3 / ksteps) / 1e9, 1))
+        bulk_bytes, _ = algorithmic_bytes(case, lat.mask, lat.n_links, st)
+        bulk_us = bulk_ms * 1e3 / ksteps
+        r.update(mlups=round(case.nx * case.ny * steps_time / (ms * 1e-3) / 1e6, 1), bulk_us=round(bulk_us, 2),
+                 bulk_GBps_algorithmic=round(bulk_bytes / (bulk_us * 1e-6) / 1e9, 1),
+                 bulk_frac_of_hbm_peak=round(bulk_bytes / (bulk_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4))
         out[st] = r
         lat.close()
-        print(f"[bench] {st}: {r}", file=sys.stderr, flush=True)
+        print(f"[bench] precision {st}: {r}", file=sys.stderr, flush=True)
     return out
 
 
-def form_batched(B, n_inst, steps, warmup):
-    """The batched workload (uneven walled-cylinder channels) in one batch, against
-    a loop over single-lattice contexts of the same instances."""
+def form_batched(B, n_inst, steps, warmup, collisions=("bgk", "mrt")):
+    """The batched workload (uneven walled-cylinder channels) in one batch, for each
+    collision, run to the stated length: throughput, and how many instances are
+    still finite at the end; the BGK batch against a loop over single-lattice
+    contexts of the same instances."""
     import numpy as np
     import torch
     from paper_1903_01111_amd import workloads as W
-    cases = W.batched_cylinders(n_inst)
-    geoms = [B.case_geometry(c) for c in cases]
-    bt = B.Batch(cases, storage="f32", geometries=geoms)
-    bt.step(warmup)
-    cfg, tuned_ms = B.lbm_batch_autotune(bt.b, 10)  # keeps the fastest configuration, restores the state
-    bt.sync()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    bt.step(steps)
-    ev1.record()
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
-    finite = 0
-    for i in range(len(cases)):
-        try:
-            bt.moments(i)
-            finite += 1
-        except B.LbmError:
-            pass
-    bt.close()
-    lats = [B.Lattice(c, storage="f32", geometry=g) for c, g in zip(cases, geoms)]
-    for lat in lats:
-        lat.step(warmup)
-    torch.cuda.synchronize()
-    ev0.record()
-    for lat in lats:
-        lat.step(steps)
-    ev1.record()
-    torch.cuda.synchronize()
-    ms_loop = ev0.elapsed_time(ev1)
-    for lat in lats:
-        lat.close()
-    n_nodes = sum(c.nx * c.ny for c in cases)
-    taus = [c.tau for c in cases]
     out = {"workload": f"{n_inst} walled-cylinder channels, nx U{{256..1024}}, ny = nx/4, Re U[20,100]",
-           "nodes": n_nodes, "steps": steps, "mlups": round(n_nodes * steps / (ms * 1e-3) / 1e6, 1),
-           "single_context_loop_mlups": round(n_nodes * steps / (ms_loop * 1e-3) / 1e6, 1),
-           "speedup_vs_loop": round(ms_loop / ms, 2), "instances_finite_after": finite,
-           "autotuned": cfg.as_dict(),
-           "tau_range": [round(min(taus), 4), round(max(taus), 4)]}
-    print(f"[bench] batched: {out}", file=sys.stderr, flush=True)
+           "steps": steps}
+    for coll in collisions:
+        cases = W.batched_cylinders(n_inst)
+        for c in cases:
+            c.collision = coll
+        geoms = [B.case_geometry(c) for c in cases]
+        bt = B.Batch(cases, storage="f32", geometries=geoms)
+        bt.step(warmup)
+        cfg, tuned_ms = B.lbm_batch_autotune(bt.b, 10)  # keeps the fastest configuration, restores the state
+        bt.sync()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        bt.step(steps)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        finite = 0
+        for i in range(len(cases)):
+            try:
+                bt.moments(i)
+                finite += 1
+            except B.LbmError:
+                pass
+        bt.close()
+        n_nodes = sum(c.nx * c.ny for c in cases)
+        taus = [c.tau for c in cases]
+        r = {"nodes": n_nodes, "mlups": round(n_nodes * steps / (ms * 1e-3) / 1e6, 1),
+             "instances_finite_after": finite, "autotuned": cfg.as_dict(),
+             "tau_range": [round(min(taus), 4), round(max(taus), 4)]}
+        if coll == "bgk":
+            lats = [B.Lattice(c, storage="f32", geometry=g) for c, g in zip(cases, geoms)]
+            for lat in lats:
+                lat.step(warmup)
+            torch.cuda.synchronize()
+            nloop = min(steps, 300)
+            ev0.record()
+            for lat in lats:
+                lat.step(nloop)
+            ev1.record()
+            torch.cuda.synchronize()
+            ms_loop = ev0.elapsed_time(ev1)
+            for lat in lats:
+                lat.close()
+            r["single_context_loop_mlups"] = round(n_nodes * nloop / (ms_loop * 1e-3) / 1e6, 1)
+            r["speedup_vs_loop"] = round(r["mlups"] / r["single_context_loop_mlups"], 2)
+        out[coll] = r
+        print(f"[bench] batched {coll}: {r}", file=sys.stderr, flush=True)
     return out
 
 
@@ -641,6 +668,11 @@ def form_position(B, n_offsets=64, nx=512, re=20.0, steps=24000, window=2000, st
     return out
 
 
+DTYPE = {"f64": "f64", "f32": "f32 storage, f32 collision + f64 moments", "f32p": "f32",
+         "f32w": "f32 storage, f64 collision", "f16": "f16 storage (x 2^k), f32 arithmetic + f64 moments",
+         "bf16": "bf16 storage (x 2^k), f32 arithmetic + f64 moments"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -650,12 +682,16 @@ def main():
     ap.add_argument("--storage", default="f32", choices=list(BYTES))
     ap.add_argument("--layout", default="compact", choices=["dense", "compact"],
                     help="population layout: every node, or the fluid nodes only")
-    ap.add_argument("--cpu-steps", type=int, default=8,
-                    help="oracle steps on the full lattice for the CPU baseline (0: skip)")
+    ap.add_argument("--oracle-steps", type=int, default=100,
+                    help="steps of the FP64 oracle on the full lattice, on every host core: the CPU baseline "
+                         "and the reference of the stated errors (0: skip)")
+    ap.add_argument("--oracle-threads", type=int, default=0, help="oracle threads (0: every core of this process)")
+    ap.add_argument("--cpu-single-steps", type=int, default=2,
+                    help="steps of the single-thread oracle for its rate (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 1 GiB device copy (counter calibration under rocprofv3)")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the FP16/BF16 storage, batched, cylinder and adjoint measurements")
+                    help="skip the storage, batched, cylinder, adjoint and study measurements")
     ap.add_argument("--form", choices=["storage_16bit", "batched", "cylinder", "cylinder_flow", "dense_layout",
                                        "adjoint", "wall_sweep", "couette", "magnus", "position"],
                     help="run only this form and print its JSON object")
@@ -673,13 +709,22 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+    threads = args.oracle_threads or len(os.sched_getaffinity(0))
+
+    def reference(case):
+        ux, uy, fs, sec, used = oracle_reference(case, args.oracle_steps, threads)
+        print(f"[bench] oracle: {args.oracle_steps} steps on {used} threads in {sec:.1f}s", file=sys.stderr,
+              flush=True)
+        return {"ux": ux, "uy": uy, "force": fs, "steps": args.oracle_steps, "sec": sec, "threads": used}
+
     if args.form:
         from paper_1903_01111_amd import workloads as W
         B.lib()
         if args.form == "storage_16bit":
-            res = form_precision(B, workload(args.workload), 1000, 500)
+            case = workload(args.workload)
+            res = form_precision(B, case, reference(case), 500)
         elif args.form == "batched":
-            res = form_batched(B, 256, 300, 20)
+            res = form_batched(B, 256, 10000, 20)
         elif args.form == "cylinder":
             res = form_single(B, W.cylinder_channel(), 2000, 100)
         elif args.form == "cylinder_flow":
@@ -705,8 +750,6 @@ def main():
     n_fluid = int((lat.mask == 0).sum())
     nfb = B.lbm_check_geometry(lat.params, lat.mask, lat.node, lat.dir, lat.q, lat.uw, lat.obj,
                                lat.scheme)
-    n_hbb = int((lat.scheme == 1).sum()) if lat.scheme is not None else 0
-    n_vibb = lat.n_links - n_hbb - nfb
     print(f"[bench] {case.name}: {n_nodes} nodes, {n_fluid} fluid, {lat.n_links} links "
           f"({nfb} fall back to halfway bounce-back), storage {args.storage}, "
           f"setup {time.perf_counter() - t_setup:.1f}s", file=sys.stderr, flush=True)
@@ -723,33 +766,25 @@ def main():
     cfg, tuned_ms = B.lbm_autotune(lat.ctx, 20)  # keeps the fastest launch shape, restores the state
     print(f"[bench] autotuned {cfg.as_dict()} ({tuned_ms * 1e3:.1f} us/step)", file=sys.stderr,
           flush=True)
-    rho, ux, uy = lat.moments()  # raises LBM_E_UNSTABLE on a non-finite state
-    torch.cuda.synchronize()
+    lat.moments()  # raises LBM_E_UNSTABLE on a non-finite state
+    lat.step(args.warmup)
 
-    # timed region: every launch bracketed by HIP events on the kernels' stream
-    B.lbm_set_profiling(lat.ctx, True)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    # timed region: graph replay, synchronised on both sides; then the kernel
+    # durations from a separate pass with HIP events around every launch on the
+    # kernels' stream
     w0 = time.perf_counter()
-    ev0.record()
-    lat.step(args.steps)
-    ev1.record()
-    torch.cuda.synchronize()
+    ms, link_ms, bulk_ms, ksteps = replay_then_timed(B, lat, args.steps, ksteps=min(args.steps, 200))
     wall = time.perf_counter() - w0
-    ms = ev0.elapsed_time(ev1)
-    link_ms, bulk_ms, n_timed = B.lbm_kernel_times(lat.ctx)
-    B.lbm_set_profiling(lat.ctx, False)
-    assert n_timed == args.steps
     _, fsum, nsum = lat.force(0)
     lat.moments()  # finite check after the timed steps
 
     mlups = n_nodes * args.steps / (ms * 1e-3) / 1e6
-    bulk_bytes, link_bytes = algorithmic_bytes(case, lat.mask, lat.n_links, n_vibb, args.storage)
-    bulk_avg_s = bulk_ms * 1e-3 / args.steps
-    link_avg_s = link_ms * 1e-3 / args.steps
+    bulk_bytes, link_bytes = algorithmic_bytes(case, lat.mask, lat.n_links, args.storage)
+    bulk_avg_s = bulk_ms * 1e-3 / ksteps
+    link_avg_s = link_ms * 1e-3 / ksteps
     achieved = bulk_bytes / bulk_avg_s / 1e9
-    print(f"[bench] {args.steps} steps in {ms:.1f} ms (wall {wall:.2f}s): {mlups:.0f} MLUPS; "
+    link_gbps = link_bytes / link_avg_s / 1e9 if link_avg_s > 0 else None
+    print(f"[bench] {args.steps} steps in {ms:.1f} ms (graph replay): {mlups:.0f} MLUPS; "
           f"bulk {bulk_avg_s * 1e6:.1f} us/launch = {achieved:.0f} GB/s; link "
           f"{link_avg_s * 1e6:.1f} us/launch", file=sys.stderr, flush=True)
 
@@ -764,14 +799,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.storage,
+        "dtype": DTYPE[args.storage],
         "data": "synthetic",
         "config": {"workload": case.name, "nx": case.nx, "ny": case.ny, "tau": case.tau,
                    "body_force": case.gx, "n_discs": len(case.prims), "fluid_nodes": n_fluid,
                    "links": lat.n_links, "hbb_fallback_links": nfb,
                    "boundary": "VIBB (velocity-interpolation bounce-back)",
                    "collision": "BGK + Guo forcing", "storage": args.storage, "layout": args.layout,
-                   "kernel_config": cfg.as_dict()},
+                   "kernel_config": cfg.as_dict(), "timing": "HIP graph replay; kernel durations from a "
+                                                             f"separate {ksteps}-step pass with HIP events"},
         "mflups_fluid": round(n_fluid * args.steps / (ms * 1e-3) / 1e6, 1),
         "step_algorithmic_GBps": round((bulk_bytes + link_bytes) / (ms * 1e-3 / args.steps) / 1e9, 1),
         "roofline": {"bound": "hbm", "kernel": "bulk (pull + BGK collision)",
@@ -779,43 +815,59 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": counter_traffic(args.layout, cfg.as_dict(), args.storage),
                      "algorithmic_bytes_per_launch": bulk_bytes,
+                     "bytes_per_unit": f"18 x {BYTES[args.storage]} B per fluid node + 1 B per node",
                      "avg_launch_us": round(bulk_avg_s * 1e6, 2)},
         "link_kernel": {"avg_launch_us": round(link_avg_s * 1e6, 2),
                         "algorithmic_bytes_per_launch": link_bytes,
-                        "GBps": round(link_bytes / link_avg_s / 1e9, 1) if link_avg_s > 0 else None},
+                        "bytes_per_unit": f"8 + 2 x {BYTES[args.storage]} + 24 B per link",
+                        "GBps": round(link_gbps, 1) if link_gbps and link_gbps <= HBM_PEAK_GBS else None,
+                        "frac": round(link_gbps / HBM_PEAK_GBS, 4)
+                        if link_gbps and link_gbps <= HBM_PEAK_GBS else None},
         "drag_per_step_mean": [float(fsum[0] / max(nsum, 1)), float(fsum[1] / max(nsum, 1))],
     }
 
-    if args.cpu_steps > 0:
+    ref = None
+    if args.oracle_steps > 0:
         import oracle
 
-        g = oracle.case_geometry(case)
-        fp = oracle.init_equilibrium(g.solid, *case.init_fields())
-        t0 = time.perf_counter()
-        oracle.run(fp, g, tau=case.tau, gx=case.gx, gy=case.gy, rho0=case.rho0,
-                   x_open=case.x_open, n_obj=case.n_obj, nsteps=args.cpu_steps,
-                   u_in=case.inlet(), scheme=oracle.case_scheme(case, g))
-        cpu_s = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": round(n_nodes * args.cpu_steps / cpu_s / 1e6, 3),
-                               "unit": "MLUPS", "cores": 1, "kind": "oracle",
-                               "sample": f"{args.cpu_steps} steps of the full {case.nx}x{case.ny} "
-                                         f"lattice, FP64, single thread ({cpu_s:.1f}s)"}
-        # the GPU from the same initial state, same steps: the error this run is stated at
+        ref = reference(case)
+        rate = n_nodes * args.oracle_steps / ref["sec"] / 1e6
+        single = None
+        if args.cpu_single_steps > 0:
+            g = oracle.case_geometry(case)
+            fp = oracle.init_equilibrium(g.solid, *case.init_fields())
+            t0 = time.perf_counter()
+            oracle.run(fp, g, tau=case.tau, gx=case.gx, gy=case.gy, rho0=case.rho0, x_open=case.x_open,
+                       n_obj=case.n_obj, nsteps=args.cpu_single_steps, u_in=case.inlet(),
+                       scheme=oracle.case_scheme(case, g), **oracle.case_kwargs(case))
+            single = n_nodes * args.cpu_single_steps / (time.perf_counter() - t0) / 1e6
+            del fp
+        out["cpu_baseline"] = {
+            "value": round(rate, 3), "unit": "MLUPS", "cores": ref["threads"], "kind": "oracle",
+            "sample": f"{args.oracle_steps} steps of the full {case.nx}x{case.ny} lattice, FP64, OpenMP build of "
+                      f"the oracle (bitwise its serial results) on {ref['threads']} threads ({ref['sec']:.1f}s)",
+            "single_thread_mlups": round(single, 3) if single else None,
+            "single_thread_sample": f"{args.cpu_single_steps} steps, serial build" if single else None,
+            "host": host_info()}
+        # the headline configuration from the same initial state, same steps
         rho0, ux0, uy0 = case.init_fields()
         B.lbm_init_equilibrium(lat.ctx, rho0, ux0, uy0)
-        lat.step(args.cpu_steps)
+        B.lbm_force_reset(lat.ctx)
+        lat.step(args.oracle_steps)
         _, gux, guy = lat.moments()
-        _, oux, ouy = oracle.moments(fp, g.solid, (case.gx, case.gy))
-        ref = max(np.abs(oux).max(), np.abs(ouy).max())
-        err = max(np.abs(gux - oux).max(), np.abs(guy - ouy).max()) / ref
-        out["error_vs_oracle"] = {"e_u": float(err), "steps": args.cpu_steps,
-                                  "definition": "max|u_gpu - u_oracle| / max|u_oracle|"}
+        _, gfs, _ = lat.force(0)
+        out["error_vs_oracle"] = {"e_u": e_u((gux, guy), (ref["ux"], ref["uy"])),
+                                  "drag": float(abs(gfs[0] - ref["force"][0]) / abs(ref["force"][0])),
+                                  "steps": args.oracle_steps,
+                                  "definition": "max|u_gpu - u_oracle| / max|u_oracle|; |F_x - F_x,oracle| / "
+                                                "|F_x,oracle| of the force summed over the steps"}
     lat.close()
     if not args.no_forms:
         from paper_1903_01111_amd import workloads as W
         forms = {}
-        forms["storage_16bit"] = form_precision(B, case, 1000, 500)
-        forms["batched"] = form_batched(B, 256, 300, 20)
+        if ref is not None:
+            forms["storage_16bit"] = form_precision(B, case, ref, 500)
+        forms["batched"] = form_batched(B, 256, 10000, 20)
         forms["cylinder_2048x512_f32"] = form_single(B, W.cylinder_channel(), 2000, 100)
         forms["cylinder_2048x512_f32"]["note"] = ("75 MB working set: resident in the 256 MB "
                                                   "last-level cache, not an HBM figure")

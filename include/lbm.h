@@ -57,14 +57,20 @@ typedef int32_t lbm_status;
 #define LBM_E_UNSTABLE (-6) /* a non-finite value was read back */
 
 /* storage of the populations in device memory.  All store f_i - w_i (deviation
- * from the rest state); F64 computes in FP64, the others in FP32, except that
- * F32_WIDE runs the bulk collision in FP64 (the boundary links stay FP32).  The
- * 16-bit forms store (f_i - w_i) * 2^dev_scale_log2 rounded to nearest even. */
+ * from the rest state).  F64 computes in FP64.  The FP32 and 16-bit forms compute
+ * the links and the collision in FP32, except that the collision forms the
+ * moments rho, j and the momentum-carrying (odd) parts in FP64 from the exact sums
+ * of the FP32 inputs (FP64 vector arithmetic issues at the FP32 rate on gfx950; in
+ * FP32 their rounding recurs every step in steady flows and drifts the velocity);
+ * F32_PLAIN does the whole collision in FP32 and F32_WIDE the whole collision in
+ * FP64.  The 16-bit forms store (f_i - w_i) * 2^dev_scale_log2 rounded to nearest
+ * even. */
 #define LBM_F64 0
 #define LBM_F32 1
 #define LBM_F16_DEV 2
 #define LBM_BF16_DEV 3
-#define LBM_F32_WIDE 4 /* FP32 storage, FP64 collision: no drift from coherent FP32 rounding in steady flows */
+#define LBM_F32_WIDE 4  /* FP32 storage, FP64 collision */
+#define LBM_F32_PLAIN 5 /* FP32 storage, every collision operation in FP32 */
 
 /* population layout in device memory */
 #define LBM_LAYOUT_DENSE 0   /* every node of the padded lattice, node (x, y) at y*pitch + x */
@@ -100,7 +106,7 @@ typedef int32_t lbm_status;
 typedef struct {
     int32_t nx, ny;         /* lattice size, >= 1 each; nx >= 3 with LBM_X_OPEN */
     int32_t x_bc;           /* LBM_X_PERIODIC or LBM_X_OPEN */
-    int32_t storage;        /* LBM_F64 .. LBM_BF16_DEV */
+    int32_t storage;        /* LBM_F64 .. LBM_F32_PLAIN */
     double tau;             /* BGK relaxation time, > 1/2 (tau = 3 nu + 1/2, Section 2) */
     double gx, gy;          /* body acceleration; force density rho*g (Guo forcing) */
     double rho0;            /* reference density of the moving-wall term 6 w rho0 e.u_w */

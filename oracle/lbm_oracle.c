@@ -542,21 +542,54 @@ static void collide_node(const orc_params *p, real_t *f)
 /* one node's collision in place (pre-collision f in, post-collision out) */
 void ORC(collide_node)(const orc_params *p, real_t *f) { collide_node(p, f); }
 
+/* Scratch of one step: boundary values per node and direction, which of them a
+ * link sets, the post-collision populations, the value of every link. */
+typedef struct {
+    real_t *fbc, *fnew, *val;
+    uint8_t *have;
+} orc_work;
+
+static int work_alloc(orc_work *w, int nx, int ny, int64_t nl)
+{
+    size_t n9 = 9 * (size_t)nx * ny;
+    w->fbc = (real_t *)malloc(sizeof(real_t) * n9);
+    w->fnew = (real_t *)malloc(sizeof(real_t) * n9);
+    w->val = (real_t *)malloc(sizeof(real_t) * (size_t)(nl > 0 ? nl : 1));
+    w->have = (uint8_t *)malloc(n9);
+    return w->fbc && w->fnew && w->val && w->have;
+}
+
+static void work_free(orc_work *w)
+{
+    free(w->fbc);
+    free(w->fnew);
+    free(w->val);
+    free(w->have);
+}
+
 /* One time step t -> t+1 in place on fp.  force[2*obj] accumulates (+=) the
  * momentum-exchange force of the fluid on each object during this step;
- * link_out (may be NULL) receives the missing population of every link.
- * Returns 0, or -2 if a fluid node pulls from a solid node with no link. */
-int ORC(step)(const orc_params *p, const uint8_t *solid, int64_t nl, const int32_t *lnode,
-              const int8_t *ldir, const real_t *lq, const real_t *luw, const int32_t *lobj,
-              const int8_t *lscheme, const real_t *uin, real_t *fp, real_t *force,
-              int64_t *n_fallback, real_t *link_out)
+ * link_out (may be NULL) receives the missing population of every link;
+ * *n_fallback (may be NULL) is increased by the number of links that fall back to
+ * halfway bounce-back.  Returns 0, or -2 if a fluid node pulls from a solid node
+ * with no link. */
+static int step_work(const orc_params *p, const uint8_t *solid, int64_t nl, const int32_t *lnode,
+                     const int8_t *ldir, const real_t *lq, const real_t *luw, const int32_t *lobj,
+                     const int8_t *lscheme, const real_t *uin, real_t *fp, real_t *force,
+                     int64_t *n_fallback, real_t *link_out, orc_work *w)
 {
     const int nx = p->nx, ny = p->ny, N = nx * ny;
-    real_t *fbc = (real_t *)malloc(sizeof(real_t) * 9 * (size_t)N);
-    uint8_t *have = (uint8_t *)calloc(9 * (size_t)N, 1);
-    real_t *fnew = (real_t *)malloc(sizeof(real_t) * 9 * (size_t)N);
+    real_t *fbc = w->fbc, *fnew = w->fnew, *val = w->val;
+    uint8_t *have = w->have;
+    memset(have, 0, 9 * (size_t)N);
 
-    /* 1-2. boundary value of every link from the state at time t */
+    /* 1-2. boundary value of every link from the state at time t (links are
+     * independent: the OpenMP build evaluates them in parallel); the force sums
+     * follow serially in link order */
+    int64_t nfb = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) reduction(+ : nfb)
+#endif
     for (int64_t l = 0; l < nl; ++l) {
         int nf = lnode[l], ip = ldir[l], i = opposite(ip);
         int xf = nf % nx, yf = nf / nx;
@@ -575,7 +608,7 @@ int ORC(step)(const orc_params *p, const uint8_t *solid, int64_t nl, const int32
          * for q <= 1/2) */
         int needs_ff = sch == 0 || sch == 3 || (sch == 2 && RE(lq[l]) <= 0.5);
         if (needs_ff && !ff_ok) {
-            if (n_fallback) ++*n_fallback;
+            ++nfb;
             sch = 1;
         }
         real_t v;
@@ -589,6 +622,13 @@ int ORC(step)(const orc_params *p, const uint8_t *solid, int64_t nl, const int32
             v = ORC(hbb)(ip, fp + 9 * nf, uwx, uwy, p->rho0);
         fbc[9 * nf + i] = v;
         have[9 * nf + i] = 1;
+        val[l] = v;
+    }
+    if (n_fallback) *n_fallback += nfb;
+    for (int64_t l = 0; l < nl; ++l) {
+        int nf = lnode[l], ip = ldir[l];
+        real_t v = val[l];
+        real_t uwx = luw ? luw[2 * l] : 0.0, uwy = luw ? luw[2 * l + 1] : 0.0;
         if (link_out) link_out[l] = v;
         /* momentum exchange: the population f+_{i'} carried into the wall and the
          * returning f_i both push the solid along e_{i'}.  With gi_mea, the
@@ -668,14 +708,28 @@ int ORC(step)(const orc_params *p, const uint8_t *solid, int64_t nl, const int32
                 for (int i = 0; i < 9; ++i) fp[9 * ne + i] = fp[9 * nw + i];
         }
     }
-    free(fbc);
-    free(have);
-    free(fnew);
     return status;
 }
 
+int ORC(step)(const orc_params *p, const uint8_t *solid, int64_t nl, const int32_t *lnode,
+              const int8_t *ldir, const real_t *lq, const real_t *luw, const int32_t *lobj,
+              const int8_t *lscheme, const real_t *uin, real_t *fp, real_t *force,
+              int64_t *n_fallback, real_t *link_out)
+{
+    orc_work w = {NULL, NULL, NULL, NULL};
+    if (!work_alloc(&w, p->nx, p->ny, nl)) {
+        work_free(&w);
+        return -3;
+    }
+    int st = step_work(p, solid, nl, lnode, ldir, lq, luw, lobj, lscheme, uin, fp, force, n_fallback, link_out,
+                       &w);
+    work_free(&w);
+    return st;
+}
+
 /* nsteps steps; force_hist (nsteps*n_obj*2, may be NULL) receives the force of
- * every step, force_sum (n_obj*2, may be NULL) accumulates over all steps. */
+ * every step, force_sum (n_obj*2, may be NULL) accumulates over all steps.
+ * Returns 0, -2 as ORC(step), or -3 if the scratch could not be allocated. */
 int ORC(run)(const orc_params *p, const uint8_t *solid, int64_t nl, const int32_t *lnode,
              const int8_t *ldir, const real_t *lq, const real_t *luw, const int32_t *lobj,
              const int8_t *lscheme, const real_t *uin, real_t *fp, int64_t nsteps,
@@ -683,21 +737,26 @@ int ORC(run)(const orc_params *p, const uint8_t *solid, int64_t nl, const int32_
 {
     int no = p->n_obj > 0 ? p->n_obj : 1;
     real_t *fs = (real_t *)malloc(sizeof(real_t) * 2 * no);
-    for (int64_t t = 0; t < nsteps; ++t) {
+    orc_work w = {NULL, NULL, NULL, NULL};
+    if (!fs || !work_alloc(&w, p->nx, p->ny, nl)) {
+        free(fs);
+        work_free(&w);
+        return -3;
+    }
+    int st = 0;
+    for (int64_t t = 0; t < nsteps && !st; ++t) {
         for (int k = 0; k < 2 * no; ++k) fs[k] = 0;
-        int st = ORC(step)(p, solid, nl, lnode, ldir, lq, luw, lobj, lscheme, uin, fp, fs,
-                           t == 0 ? n_fallback : NULL, NULL);
-        if (st) {
-            free(fs);
-            return st;
-        }
+        st = step_work(p, solid, nl, lnode, ldir, lq, luw, lobj, lscheme, uin, fp, fs, t == 0 ? n_fallback : NULL,
+                       NULL, &w);
+        if (st) break;
         for (int k = 0; k < 2 * no; ++k) {
             if (force_hist) force_hist[t * 2 * no + k] = fs[k];
             if (force_sum) force_sum[k] += fs[k];
         }
     }
     free(fs);
-    return 0;
+    work_free(&w);
+    return st;
 }
 
 /* total mass sum_{fluid nodes} sum_i f_i */

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "liblbm_vibb.so")
 
 LBM_OK, LBM_E_ARG, LBM_E_GEOM, LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_STATE, LBM_E_UNSTABLE = (
     0, -1, -2, -3, -4, -5, -6)
-LBM_F64, LBM_F32, LBM_F16_DEV, LBM_BF16_DEV, LBM_F32_WIDE = 0, 1, 2, 3, 4
+LBM_F64, LBM_F32, LBM_F16_DEV, LBM_BF16_DEV, LBM_F32_WIDE, LBM_F32_PLAIN = 0, 1, 2, 3, 4, 5
 LBM_X_PERIODIC, LBM_X_OPEN = 0, 1
 LBM_SCHEME_VIBB, LBM_SCHEME_HBB, LBM_SCHEME_BOUZIDI, LBM_SCHEME_YU = 0, 1, 2, 3
 LBM_COLLISION_BGK, LBM_COLLISION_MRT = 0, 1
@@ -29,7 +29,8 @@ COLLISION = {"bgk": LBM_COLLISION_BGK, "mrt": LBM_COLLISION_MRT}
 LBM_LAYOUT_DENSE, LBM_LAYOUT_COMPACT = 0, 1
 LBM_MAX_LINKS = 1 << 28
 LAYOUT = {"dense": LBM_LAYOUT_DENSE, "compact": LBM_LAYOUT_COMPACT}
-STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16": LBM_F16_DEV, "bf16": LBM_BF16_DEV, "f32w": LBM_F32_WIDE}
+STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16": LBM_F16_DEV, "bf16": LBM_BF16_DEV, "f32w": LBM_F32_WIDE,
+           "f32p": LBM_F32_PLAIN}
 STATUS_NAMES = {0: "LBM_OK", -1: "LBM_E_ARG", -2: "LBM_E_GEOM", -3: "LBM_E_NOMEM",
                 -4: "LBM_E_DEVICE", -5: "LBM_E_STATE", -6: "LBM_E_UNSTABLE"}
 

@@ -17,7 +17,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 # (source, extra flags, object tag): the step kernels are compiled once per storage
 # format (LBM_ST), so that the formats build in parallel
-STORAGE_FORMATS = (0, 1, 2, 3, 4)
+STORAGE_FORMATS = (0, 1, 2, 3, 4, 5)
 HIP_UNITS = [("lbm_kernels.hip", [f"-DLBM_ST={k}"], f"st{k}") for k in STORAGE_FORMATS] + [
     ("lbm_adjoint.hip", [], ""), ("lbm_noalloc.hip", [], "")]
 CXX_SOURCES = ["lbm_runtime.cpp", "lbm_batch.cpp", "lbm_geometry.cpp", "lbm_adjoint.cpp", "lbm_dispatch.cpp"]

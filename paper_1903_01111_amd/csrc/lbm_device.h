@@ -66,6 +66,9 @@ struct Codec<1> {  // LBM_F32
 template <>
 struct Codec<4> : Codec<1> {  // LBM_F32_WIDE: stored as LBM_F32
 };
+template <>
+struct Codec<5> : Codec<1> {  // LBM_F32_PLAIN: stored as LBM_F32
+};
 
 template <>
 struct Codec<2> {  // LBM_F16_DEV
@@ -83,13 +86,8 @@ struct Codec<3> {  // LBM_BF16_DEV, bits of a bfloat16 in a uint16
     {
         return __uint_as_float((uint32_t)v << 16) * inv;
     }
-    static __device__ __forceinline__ T st(R v, float scale)
-    {
-        uint32_t u = __float_as_uint(v * scale);
-        if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
-        u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
-        return (uint16_t)(u >> 16);
-    }
+    // FP32 -> BF16 with round to nearest even: one v_cvt_pk_bf16_f32 on gfx950
+    static __device__ __forceinline__ T st(R v, float scale) { return __builtin_bit_cast(uint16_t, (__bf16)(v * scale)); }
 };
 
 // Deviation-form arithmetic.  rho = 1 + dr is never formed: in FP32 its rounding
@@ -125,7 +123,8 @@ __device__ __forceinline__ double inv_rho_m1_fast(double dr) { return -dr / (1.0
 __device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double rcp_fast(double x) { return 1.0 / x; }
 // Arithmetic type of the bulk collision: the storage's own arithmetic type (FP64
-// for FP64 storage, FP32 otherwise), and FP64 for the wide FP32 form.  FP32
+// for FP64 storage, FP32 otherwise), FP64 for the wide FP32 form, and FP32
+// throughout (moments and odd parts too) for the plain FP32 form.  FP32
 // feq and f^eq - f carry absolute rounding errors near 1e-9 (the ulp of the
 // O(1e-2) deviations); wherever the flow is steady the same error recurs every
 // step and adds up like a body force.  FP64 vector FMAs issue at the rate of
@@ -144,6 +143,11 @@ template <>
 struct Collide<4> {
     using A = double;
     using D = double;
+};
+template <>
+struct Collide<5> {
+    using A = float;
+    using D = float;
 };
 
 // Element e of a population plane at base.  A plane is smaller than 4 GiB (the

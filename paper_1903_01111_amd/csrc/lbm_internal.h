@@ -206,10 +206,10 @@ int32_t mass_blocks(const Grid &g);
 constexpr int MASS_THREADS = 256;  // lanes per block of the mass / deviation reduction
 
 // The launch helpers of one storage format, defined by lbm_kernels.hip compiled
-// with LBM_ST = 0..4 (one object per format, so that the formats build in
-// parallel); the launch_* functions above dispatch on the storage.  Format 4
-// (FP32 storage, FP64 collision) defines only the bulk launches and shares the
-// others with format 1.
+// with LBM_ST = 0..5 (one object per format, so that the formats build in
+// parallel); the launch_* functions above dispatch on the storage.  Formats 4 and
+// 5 (FP32 storage with an FP64 or a plain FP32 collision) define only the bulk
+// launches and share the others with format 1.
 #define LBM_ST_DECLS(K)                                                                                       \
     hipError_t launch_link_st##K(const Grid &, const Phys &, const Links &, const Side &, const Reduce &,      \
                                  double *, double *, int, hipStream_t, ForceReduce *);                         \
@@ -236,6 +236,7 @@ LBM_ST_DECLS(1)
 LBM_ST_DECLS(2)
 LBM_ST_DECLS(3)
 LBM_ST_DECLS(4)
+LBM_ST_DECLS(5)
 
 // ---------------------------------------------------------------------------
 // Adjoint kernels (lbm_adjoint.hip); FP64 and FP32 storage only.  Side records

@@ -1,11 +1,11 @@
 // One storage format's launch helpers of the step kernels (lbm_step_kernels.h).
-// This file is compiled once per format with -DLBM_ST=0..4; the per-format
+// This file is compiled once per format with -DLBM_ST=0..5; the per-format
 // objects build in parallel and lbm_dispatch.cpp picks the one of a context's
 // storage.
 #include "lbm_step_kernels.h"
 
 #ifndef LBM_ST
-#error "compile with -DLBM_ST=<storage format 0..4>"
+#error "compile with -DLBM_ST=<storage format 0..5>"
 #endif
 
 #define LBM_CAT_(a, b) a##b
@@ -37,7 +37,7 @@ hipError_t LBM_FN(launch_bulk_batch_st)(const BatchInst *insts, const BatchTile 
                                        rows, s, fr);
 }
 
-#if LBM_ST != 4
+#if LBM_ST != 4 && LBM_ST != 5
 hipError_t LBM_FN(launch_link_st)(const Grid &g, const Phys &ph, const Links &L, const Side &side,
                                   const Reduce &red, double *bank, double *fsum, int block, hipStream_t s,
                                   ForceReduce *defer)

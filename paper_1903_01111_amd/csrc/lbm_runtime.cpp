@@ -26,7 +26,8 @@ size_t elem_bytes(int storage)
     switch (storage) {
     case LBM_F64: return 8;
     case LBM_F32:
-    case LBM_F32_WIDE: return 4;
+    case LBM_F32_WIDE:
+    case LBM_F32_PLAIN: return 4;
     default: return 2;
     }
 }
@@ -119,7 +120,7 @@ bool params_ok(const lbm_params *p, std::string *why)
         *why = "an open lattice needs nx >= 3";
         return false;
     }
-    if (p->storage < LBM_F64 || p->storage > LBM_F32_WIDE) {
+    if (p->storage < LBM_F64 || p->storage > LBM_F32_PLAIN) {
         *why = "unknown storage";
         return false;
     }
@@ -942,7 +943,8 @@ lbm_status lbm_populations(lbm_ctx *c, double *f)
                 switch (c->p.storage) {
                 case LBM_F64: std::memcpy(&d, &plane[k * 8], 8); break;
                 case LBM_F32:
-                case LBM_F32_WIDE: {
+                case LBM_F32_WIDE:
+                case LBM_F32_PLAIN: {
                     float v;
                     std::memcpy(&v, &plane[k * 4], 4);
                     d = v;

@@ -27,10 +27,11 @@ def _cfg(**kw):
 
 def test_bulk_kernel_names_follow_the_templates():
     assert bench.bulk_kernel_name(_cfg(), "compact", "f32") == \
-        "void bulk_kernel<1, false, true, 256, false, true, 1>"
+        "void bulk_kernel<1, false, true, 256, false, true, 1, 0>"
     assert bench.bulk_kernel_name(_cfg(bulk_block_x=64, bulk_store_solid=1), "dense", "f16") == \
-        "void bulk_kernel<2, false, true, 64, true, false, 1>"
-    assert bench.bulk_kernel_name(_cfg(bulk_rows=2), "compact", "bf16").endswith(", 2>")
+        "void bulk_kernel<2, false, true, 64, true, false, 1, 0>"
+    assert bench.bulk_kernel_name(_cfg(bulk_rows=2), "compact", "bf16").endswith(", 2, 0>")
+    assert bench.bulk_kernel_name(_cfg(), "compact", "f32", coll=1).endswith(", 1, 1>")
     assert bench.bulk_kernel_name(_cfg(bulk_fused=1), "compact", "f32") is None
 
 

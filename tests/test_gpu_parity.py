@@ -7,7 +7,9 @@ Tolerances:
 * FP32 storage: e_u = max|u_gpu - u_ref| / max|u_ref| after 1000 steps within
   1e-6, a tenth of the stated bound of the method's FP32 form (1e-5): the
   collision forms the moments and the odd parts of f^neq in FP64, and measures
-  1e-7 to 3e-7 on these workloads; the force summed over the steps within 1e-6,
+  1e-7 to 3e-7 on these workloads; with every collision operation in FP32
+  (LBM_F32_PLAIN) within the stated 1e-5, except on a steady channel uniform along
+  x, where the same rounding recurs everywhere (its own test states that bound); the force summed over the steps within 1e-6,
   relative to the larger of the reference force and the dynamic-pressure scale
   rho0 U^2 D / 2 per step (a drag/lift-coefficient error).  The force is a sum of
   the momentum fluxes of the wall populations, so its FP32 error follows the
@@ -173,6 +175,29 @@ def test_fp32_wide_matches_oracle_after_1000_steps(B, case):
     """FP32 storage with the bulk collision in FP64 (LBM_F32_WIDE): 1e-6 after 1000
     steps, also on the steady forced channel."""
     compare(B, case(), "f32w", 1000, tol_u=1e-6, tol_f=2e-6)
+
+
+@pytest.mark.parametrize("case", [
+    lambda: small_cylinder(),
+    lambda: small_porous(),
+    lambda: spinning(),
+    lambda: W.walled_cylinder(160, 15.0, 0.37, 0.61),
+], ids=["cylinder", "porous", "spinning_ragged", "walled_cylinder"])
+def test_fp32_plain_collision_matches_oracle_after_1000_steps(B, case):
+    """FP32 storage with every collision operation in FP32 (LBM_F32_PLAIN): within
+    the stated FP32 bound of 1e-5 after 1000 steps on these flows."""
+    out = compare(B, case(), "f32p", 1000, tol_u=1e-5, tol_f=1e-5)
+    print(f"[plain-fp32] {out}", flush=True)
+
+
+def test_fp32_plain_collision_on_the_steady_forced_channel(B):
+    """The all-FP32 collision on the steady channel that is uniform along x: the
+    same rounding recurs at every node of a row and every step and drifts the
+    velocity past the 1e-5 bound within 1000 steps.  The bound stated here is the
+    measured limitation of the plain FP32 method (the mixed form stays at 3e-7)."""
+    out = compare(B, forced_channel(), "f32p", 1000, tol_u=1e-4, tol_f=1e-4)
+    print(f"[forced-channel] f32p {out}", flush=True)
+    assert out["e_u"] > 1e-6
 
 
 def test_fp32_on_the_steady_forced_channel(B):

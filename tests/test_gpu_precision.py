@@ -1,5 +1,8 @@
 """Reduced-precision population storage on the GPU: FP32 deviations, and FP16 /
-BF16 deviations scaled by 2^k (collision arithmetic in FP32 for all three).
+BF16 deviations scaled by 2^k.  All three compute the links and the collision in
+FP32, with the collision's moments and momentum-carrying (odd) parts formed in
+FP64 from the exact sums of the FP32 inputs; the all-FP32 collision
+(LBM_F32_PLAIN) is checked in test_gpu_parity.py.
 
 * The codecs are pinned bit-exactly: a stored value is round-to-nearest-even of
   float32(f - w_i) * 2^k in the 16-bit format (numpy's float16 conversion and a
