@@ -47,20 +47,28 @@ __device__ __forceinline__ int opp_of(int i)
 template <int ST>
 struct Codec;
 
+// Reg is how the bulk kernel holds a loaded value until it decodes it (T itself,
+// except BF16 below); reg() makes one from a stored value, ldr() decodes it.
 template <>
 struct Codec<0> {  // LBM_F64
     using T = double;
     using R = double;
+    using Reg = T;
     static __device__ __forceinline__ R ld(T v, float) { return v; }
     static __device__ __forceinline__ T st(R v, float) { return v; }
+    static __device__ __forceinline__ Reg reg(T v) { return v; }
+    static __device__ __forceinline__ R ldr(Reg v, float inv) { return ld(v, inv); }
 };
 
 template <>
 struct Codec<1> {  // LBM_F32
     using T = float;
     using R = float;
+    using Reg = T;
     static __device__ __forceinline__ R ld(T v, float) { return v; }
     static __device__ __forceinline__ T st(R v, float) { return v; }
+    static __device__ __forceinline__ Reg reg(T v) { return v; }
+    static __device__ __forceinline__ R ldr(Reg v, float inv) { return ld(v, inv); }
 };
 
 template <>
@@ -74,20 +82,30 @@ template <>
 struct Codec<2> {  // LBM_F16_DEV
     using T = __half;
     using R = float;
+    // held zero-extended in 32 bits, as BF16 below
+    using Reg = uint32_t;
     static __device__ __forceinline__ R ld(T v, float inv) { return __half2float(v) * inv; }
     static __device__ __forceinline__ T st(R v, float scale) { return __float2half_rn(v * scale); }
+    static __device__ __forceinline__ Reg reg(T v) { return (uint32_t)__builtin_bit_cast(uint16_t, v); }
+    static __device__ __forceinline__ R ldr(Reg v, float inv)
+    {
+        return __half2float(__builtin_bit_cast(__half, (uint16_t)v)) * inv;
+    }
 };
 
 template <>
-struct Codec<3> {  // LBM_BF16_DEV, bits of a bfloat16 in a uint16
-    using T = uint16_t;
+struct Codec<3> {  // LBM_BF16_DEV
+    using T = __bf16;
     using R = float;
-    static __device__ __forceinline__ R ld(T v, float inv)
-    {
-        return __uint_as_float((uint32_t)v << 16) * inv;
-    }
+    // Held zero-extended in 32 bits: as 16-bit values the nine pulled populations
+    // were packed in pairs right after their loads, which made the kernel wait
+    // for the loads there instead of behind the node lookups.
+    using Reg = uint32_t;
+    static __device__ __forceinline__ R ld(T v, float inv) { return (float)v * inv; }
     // FP32 -> BF16 with round to nearest even: one v_cvt_pk_bf16_f32 on gfx950
-    static __device__ __forceinline__ T st(R v, float scale) { return __builtin_bit_cast(uint16_t, (__bf16)(v * scale)); }
+    static __device__ __forceinline__ T st(R v, float scale) { return (__bf16)(v * scale); }
+    static __device__ __forceinline__ Reg reg(T v) { return (uint32_t)__builtin_bit_cast(uint16_t, v); }
+    static __device__ __forceinline__ R ldr(Reg v, float inv) { return __uint_as_float(v << 16) * inv; }
 };
 
 // Deviation-form arithmetic.  rho = 1 + dr is never formed: in FP32 its rounding
@@ -211,6 +229,10 @@ __device__ __forceinline__ void st_buf(__amdgpu_buffer_rsrc_t r, uint32_t off, _
 __device__ __forceinline__ void st_buf(__amdgpu_buffer_rsrc_t r, uint32_t off, uint16_t v)
 {
     __builtin_amdgcn_raw_buffer_store_b16(v, r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void st_buf(__amdgpu_buffer_rsrc_t r, uint32_t off, __bf16 v)
+{
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)off, 0, 0);
 }
 
 // Load of a wavefront-uniform element of a table that no kernel writes while it

@@ -435,7 +435,7 @@ __device__ __forceinline__ void collide_mrt(A (&f)[9], const Phys &ph, A drho, D
 // issue the pulls of a second row segment before it finishes the first.
 template <int ST>
 struct Pulled {
-    typename Codec<ST>::T a[9];  // the pulled populations (stored form)
+    typename Codec<ST>::Reg a[9];  // the pulled populations (stored form, register holding)
     uint32_t own, own_in, own_out;  // byte offsets in a plane: the node, the open columns
     mask_t m;
     bool live;  // the wavefront's row segment lies in the lattice (uniform)
@@ -543,8 +543,8 @@ __device__ __forceinline__ void bulk_issue(const Grid &g, const typename Codec<S
         // compact layout: streamed through once, non-temporal so that the deposits
         // stay cached for the link kernel; dense layout: neighbouring rows reuse the
         // lines, which the non-temporal path would drop (all-fluid lattice 4% slower)
-        if (CMP) pl.a[i] = ld_at_nt(A + i * P, o[i]);
-        else pl.a[i] = ld_at(A + i * P, o[i]);
+        if (CMP) pl.a[i] = Codec<ST>::reg(ld_at_nt(A + i * P, o[i]));
+        else pl.a[i] = Codec<ST>::reg(ld_at(A + i * P, o[i]));
     }
     pl.own = own;
     pl.own_in = own_in;
@@ -576,7 +576,7 @@ __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
     const uint32_t pbytes = (uint32_t)(P * S);
     const int lane = threadIdx.x & 63;
     const uint32_t own = pl.own, own_in = pl.own_in, own_out = pl.own_out;
-    T a[9];
+    typename C::Reg a[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) a[i] = pl.a[i];
     const int32_t seg = __builtin_amdgcn_readfirstlane(y * (g.pitch >> 6) + (x >> 6));
@@ -652,7 +652,7 @@ __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
             const uint32_t bit = 1u << (OPPI[i] - 1);
-            if (lk & bit) a[i] = lds_l[wv][lo + popc32(lk & (bit - 1u))];
+            if (lk & bit) a[i] = C::reg(lds_l[wv][lo + popc32(lk & (bit - 1u))]);
         }
     } else {
         // a node's links are consecutive L entries in direction order: walk them
@@ -663,7 +663,7 @@ __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
 #pragma unroll
         for (int d = 1; d < 9; ++d)
             if (lk & (1u << (d - 1))) {
-                a[OPPD[d]] = ld_at(Lv, lb);
+                a[OPPD[d]] = C::reg(ld_at(Lv, lb));
                 lb += S;
             }
     }
@@ -726,7 +726,7 @@ __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
     using D = typename Collide<ST>::D;
     A f[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = A(C::ld(a[i], inv));
+    for (int i = 0; i < 9; ++i) f[i] = A(C::ldr(a[i], inv));
 
     // In D, these sums of stored values are exact (FP32 inputs in FP64)
     const D drho_d = ((D(f[0]) + D(f[1])) + (D(f[2]) + D(f[3]))) + ((D(f[4]) + D(f[5])) + (D(f[6]) + D(f[7]))) +
