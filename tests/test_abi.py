@@ -50,8 +50,9 @@ def test_create_without_gpu_reports_device_error():
 
 
 @pytest.mark.parametrize("kw", [dict(tau=0.5), dict(tau=float("nan")), dict(x_open=True, nx=2),
-                                dict(nx=0), dict(storage=5), dict(storage=-1), dict(n_obj=0), dict(dev_scale_log2=40),
-                                dict(layout=2)])
+                                dict(nx=0), dict(storage=6), dict(storage=-1), dict(n_obj=0), dict(dev_scale_log2=40),
+                                dict(layout=2), dict(collision=2), dict(collision="mrt", mrt_s=(0.0, 1.5, 1.2)),
+                                dict(collision="mrt", mrt_s=(1.5, 2.0, 1.2))])
 def test_invalid_params_have_no_workspace(kw):
     nx = kw.pop("nx", 16)
     p = B.make_params(nx, 8, **kw)
@@ -62,9 +63,11 @@ def test_invalid_params_have_no_workspace(kw):
 
 
 def test_wide_fp32_storage_has_the_fp32_footprint():
-    """LBM_F32_WIDE stores FP32 populations (only the collision arithmetic is FP64)."""
-    assert B.lbm_workspace_bytes(B.make_params(100, 37, storage="f32w"), 500) == \
-        B.lbm_workspace_bytes(B.make_params(100, 37), 500)
+    """LBM_F32_WIDE and LBM_F32_PLAIN store FP32 populations (only the collision
+    arithmetic differs)."""
+    for st in ("f32w", "f32p"):
+        assert B.lbm_workspace_bytes(B.make_params(100, 37, storage=st), 500) == \
+            B.lbm_workspace_bytes(B.make_params(100, 37), 500)
 
 
 def test_workspace_grows_with_links_and_precision():
