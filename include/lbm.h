@@ -427,6 +427,21 @@ lbm_status lbm_adjoint_force(lbm_ctx *ctx, void *ws, size_t ws_bytes, int64_t ns
                              double *dJ_duin, double *dJ_dq, double *dJ_duw, double *dJ_dstate,
                              double *dJ_dinit);
 
+/* lbm_adjoint_force in two halves, for callers that need J before they know
+ * whether the gradient is wanted (a torch.autograd.Function: forward, then
+ * backward): lbm_adjoint_forward runs the forward sweep (the context advances by
+ * nsteps, checkpoints go into ws) and returns J; lbm_adjoint_backward, on the same
+ * workspace, runs the recomputation and the reverse sweep and returns the
+ * gradients (outputs as lbm_adjoint_force; any may be NULL).  The workspace must
+ * be left as it is between the two calls; stepping the context, a new geometry,
+ * initialisation or a restored checkpoint in between void the forward half
+ * (lbm_adjoint_backward then returns LBM_E_STATE).  The two halves compute what
+ * lbm_adjoint_force computes. */
+lbm_status lbm_adjoint_forward(lbm_ctx *ctx, void *ws, size_t ws_bytes, int64_t nsteps, int32_t ckpt_every,
+                               int32_t obj, double dir_x, double dir_y, double *J);
+lbm_status lbm_adjoint_backward(lbm_ctx *ctx, void *ws, size_t ws_bytes, double *dJ_duin, double *dJ_dq,
+                                double *dJ_duw, double *dJ_dstate, double *dJ_dinit);
+
 /* For callers that cannot allocate memory (code that must not call hipMalloc,
  * tight loops, harnesses that forbid allocation): lbm_adjoint_force with the same
  * arguments, results and errors, but its workspace is a static device array of

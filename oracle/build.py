@@ -15,22 +15,27 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lbm_oracle.c")
 LIB = os.path.join(HERE, "liblbm_oracle.so")
 LIB_OMP = os.path.join(HERE, "liblbm_oracle_omp.so")
+# both builds under AddressSanitizer and UBSan, loaded instead of LIB and LIB_OMP
+# when LBM_SANITIZE is set (CPU tests only)
+LIB_SAN = os.path.join(HERE, "liblbm_oracle_san.so")
+LIB_SAN_OMP = os.path.join(HERE, "liblbm_oracle_omp_san.so")
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-fno-sanitize-recover=undefined"]
 
 CFLAGS = ["-O2", "-std=c11", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall"]
 
 
-def _build_one(lib, omp, verbose):
+def _build_one(lib, omp, verbose, san=False):
     objs = []
-    flags = CFLAGS + (["-fopenmp"] if omp else [])
+    flags = CFLAGS + (["-fopenmp"] if omp else []) + (SAN_FLAGS if san else [])
     for tag, extra in (("real", []), ("cplx", ["-DORC_COMPLEX"])):
-        obj = os.path.join(HERE, f"_lbm_oracle_{tag}{'_omp' if omp else ''}.o")
+        obj = os.path.join(HERE, f"_lbm_oracle_{tag}{'_omp' if omp else ''}{'_san' if san else ''}.o")
         cmd = ["gcc", *flags, *extra, "-c", SRC, "-o", obj]
         if verbose:
             print(" ".join(cmd))
         subprocess.run(cmd, check=True)
         objs.append(obj)
     tmp = lib + ".tmp"
-    cmd = ["gcc", "-shared", *(["-fopenmp"] if omp else []), "-o", tmp, *objs, "-lm"]
+    cmd = ["gcc", "-shared", *(["-fopenmp"] if omp else []), *(SAN_FLAGS if san else []), "-o", tmp, *objs, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
@@ -45,8 +50,19 @@ def build(verbose: bool = False) -> str:
     return _build_one(LIB, False, verbose)
 
 
+def build_sanitized(verbose: bool = False) -> str:
+    _build_one(LIB_SAN_OMP, True, verbose, san=True)
+    return _build_one(LIB_SAN, False, verbose, san=True)
+
+
 def ensure_built(omp: bool = False) -> str:
-    """Builds only if the library is missing or older than its source."""
+    """Builds only if the library is missing or older than its source (the
+    sanitized builds with LBM_SANITIZE set)."""
+    if os.environ.get("LBM_SANITIZE"):
+        lib = LIB_SAN_OMP if omp else LIB_SAN
+        if not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(SRC):
+            build_sanitized()
+        return lib
     lib = LIB_OMP if omp else LIB
     if not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(SRC):
         build()
@@ -54,4 +70,4 @@ def ensure_built(omp: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build_sanitized(verbose="-v" in sys.argv) if "--sanitize" in sys.argv else build(verbose="-v" in sys.argv))

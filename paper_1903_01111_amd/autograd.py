@@ -42,9 +42,9 @@ def with_parameters(base: W.Case, U: float, cx: float, cy: float, R: float, prim
     return c
 
 
-def drag_and_gradient(base: W.Case, p, nsteps: int, ckpt_every: int = 100, storage: str = "f32",
-                      direction=(1.0, 0.0), prim: int = 0):
-    """J and dJ/d(U, cx, cy, R) (numpy, float64) for the parameters p."""
+def _parameterised_lattice(base: W.Case, p, storage: str, prim: int):
+    """The lattice of the parameters p with the library's geometry, and the
+    per-link primitive and dq/d(cx, cy, R) the chain rule needs."""
     U, cx, cy, R = (float(v) for v in p)
     case = with_parameters(base, U, cx, cy, R, prim)
     kind, geo, mot, pobj = W.prim_arrays(case.prims)
@@ -54,34 +54,59 @@ def drag_and_gradient(base: W.Case, p, nsteps: int, ckpt_every: int = 100, stora
     if case.scheme_of_obj is not None:
         scheme = np.asarray(case.scheme_of_obj, np.int8)[lobj]
     lat = B.Lattice(case, storage=storage, geometry=(mask, node, d, q, uw, lobj, scheme))
+    return case, lat, mask, lprim, dq
+
+
+def _chain(out, mask, lprim, dq, prim):
+    """dJ/d(U, cx, cy, R) from the library's dJ/du_in, dJ/d(initial fields) and dJ/dq."""
+    sel = lprim == prim
+    g_u = out["duin"][:, 0].sum() + out["dinit"][..., 1][mask == 0].sum()
+    g_c = (out["dq"][sel, None] * dq[sel]).sum(axis=0)
+    return np.array([g_u, g_c[0], g_c[1], g_c[2]])
+
+
+def drag_and_gradient(base: W.Case, p, nsteps: int, ckpt_every: int = 100, storage: str = "f32",
+                      direction=(1.0, 0.0), prim: int = 0):
+    """J and dJ/d(U, cx, cy, R) (numpy, float64) for the parameters p, in one
+    adjoint call."""
+    case, lat, mask, lprim, dq = _parameterised_lattice(base, p, storage, prim)
     try:
         out = lat.adjoint_force(nsteps, ckpt_every, obj=case.prims[prim].obj, direction=direction,
                                 want_init=True)
     finally:
         lat.close()
-    sel = lprim == prim
-    g_u = out["duin"][:, 0].sum() + out["dinit"][..., 1][mask == 0].sum()
-    g_c = (out["dq"][sel, None] * dq[sel]).sum(axis=0)
-    return out["J"], np.array([g_u, g_c[0], g_c[1], g_c[2]])
+    return out["J"], _chain(out, mask, lprim, dq, prim)
 
 
 class DragFunction(torch.autograd.Function):
     """J(p) for p = (U, cx, cy, R), a float64 tensor of four entries.
 
     Usage: ``J = DragFunction.apply(p, base_case, nsteps, ckpt_every, storage)``.
-    The forward pass runs the simulation and the adjoint together (the adjoint
-    needs the forward trajectory, which it checkpoints); backward scales the
-    stored gradient by the incoming one.
+    The forward pass runs the simulation with checkpoints every ckpt_every steps
+    (the forward half of the adjoint, lbm_adjoint_forward) and keeps the lattice and
+    its checkpoints; backward runs the recomputation and the reverse sweep
+    (lbm_adjoint_backward) and chains the result to p.  A forward pass whose
+    gradient is never asked for costs the simulation alone.
     """
 
     @staticmethod
     def forward(ctx, p, base, nsteps, ckpt_every=100, storage="f32", direction=(1.0, 0.0), prim=0):
-        J, g = drag_and_gradient(base, p.detach().cpu().numpy(), nsteps, ckpt_every, storage, direction,
-                                 prim)
-        ctx.save_for_backward(torch.as_tensor(g, dtype=p.dtype, device=p.device))
+        case, lat, mask, lprim, dq = _parameterised_lattice(base, p.detach().cpu().numpy(), storage, prim)
+        try:
+            J = lat.adjoint_forward(nsteps, ckpt_every, obj=case.prims[prim].obj, direction=direction)
+        except Exception:
+            lat.close()
+            raise
+        ctx.lat, ctx.geo, ctx.prim = lat, (mask, lprim, dq), prim
         return torch.tensor(J, dtype=p.dtype, device=p.device)
 
     @staticmethod
     def backward(ctx, grad_out):
-        (g,) = ctx.saved_tensors
+        lat = ctx.lat
+        try:
+            out = lat.adjoint_backward(want_init=True)
+        finally:
+            lat.close()
+            ctx.lat = None
+        g = torch.as_tensor(_chain(out, *ctx.geo, ctx.prim), dtype=grad_out.dtype, device=grad_out.device)
         return grad_out * g, None, None, None, None, None, None

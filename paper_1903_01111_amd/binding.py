@@ -16,7 +16,9 @@ import numpy as np
 from . import workloads as W
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblbm_vibb.so")
+# LBM_SANITIZE=1 loads the build whose host code runs under AddressSanitizer and
+# UBSan (paper_1903_01111_amd.build --sanitize; CPU tests only)
+LIB_PATH = os.path.join(HERE, "liblbm_vibb_san.so" if os.environ.get("LBM_SANITIZE") else "liblbm_vibb.so")
 
 LBM_OK, LBM_E_ARG, LBM_E_GEOM, LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_STATE, LBM_E_UNSTABLE = (
     0, -1, -2, -3, -4, -5, -6)
@@ -123,6 +125,8 @@ SIGNATURES = [
     ("lbm_adjoint_workspace_bytes", C.c_size_t, [_P, _I64, _I32]),
     ("lbm_adjoint_force", _I32, [_P, _P, C.c_size_t, _I64, _I32, _I32, _D, _D, _P, _P, _P, _P, _P, _P]),
     ("lbm_adjoint_force_noalloc", _I32, [_P, _I64, _I32, _I32, _D, _D, _P, _P, _P, _P, _P, _P]),
+    ("lbm_adjoint_forward", _I32, [_P, _P, C.c_size_t, _I64, _I32, _I32, _D, _D, _P]),
+    ("lbm_adjoint_backward", _I32, [_P, _P, C.c_size_t, _P, _P, _P, _P, _P]),
 ]
 
 
@@ -437,6 +441,26 @@ def lbm_adjoint_force(ctx, workspace_ptr, nbytes, nsteps, ckpt_every, obj, dir_x
     return dict(J=J.value, duin=duin, dq=dq, duw=duw, dstate=dstate, dinit=dinit)
 
 
+def lbm_adjoint_forward(ctx, workspace_ptr, nbytes, nsteps, ckpt_every, obj, dir_x, dir_y) -> float:
+    """The forward half of lbm_adjoint_force: returns J."""
+    J = C.c_double(0.0)
+    check(lib().lbm_adjoint_forward(ctx, workspace_ptr, nbytes, nsteps, ckpt_every, obj, float(dir_x),
+                                    float(dir_y), C.byref(J)), ctx)
+    return J.value
+
+
+def lbm_adjoint_backward(ctx, workspace_ptr, nbytes, *, ny, nx, n_links, want_state=False, want_init=False):
+    """The backward half: returns dict(duin, dq, duw, dstate, dinit) as lbm_adjoint_force."""
+    duin = np.zeros((ny, 2))
+    dq = np.zeros(max(n_links, 0))
+    duw = np.zeros((max(n_links, 0), 2))
+    dstate = np.zeros((ny, nx, 9)) if want_state else None
+    dinit = np.zeros((ny, nx, 3)) if want_init else None
+    check(lib().lbm_adjoint_backward(ctx, workspace_ptr, nbytes, _p(duin), _p(dq), _p(duw), _p(dstate),
+                                     _p(dinit)), ctx)
+    return dict(duin=duin, dq=dq, duw=duw, dstate=dstate, dinit=dinit)
+
+
 LBM_ADJOINT_SCRATCH_BYTES = 64 << 20
 
 
@@ -723,6 +747,30 @@ class Lattice:
                                 want_state=want_state, want_init=want_init)
         del ws
         return out
+
+    def adjoint_forward(self, nsteps, ckpt_every=100, obj=0, direction=(1.0, 0.0)):
+        """The forward half of adjoint_force: advances by nsteps, keeps the
+        checkpoints in a workspace held by the lattice, returns J."""
+        import torch
+
+        nbytes = lbm_adjoint_workspace_bytes(self.ctx, nsteps, ckpt_every)
+        if nbytes == 0:
+            raise LbmError(LBM_E_ARG, "adjoint: invalid arguments or storage")
+        self._adj_ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = self._adj_ws.data_ptr()
+        ptr += (-ptr) % 256
+        self._adj = (ptr, nbytes)
+        return lbm_adjoint_forward(self.ctx, ptr, nbytes, nsteps, ckpt_every, obj, direction[0], direction[1])
+
+    def adjoint_backward(self, want_state=False, want_init=False):
+        """The backward half after adjoint_forward: the gradients of its J."""
+        ptr, nbytes = self._adj
+        try:
+            return lbm_adjoint_backward(self.ctx, ptr, nbytes, ny=self.case.ny, nx=self.case.nx,
+                                        n_links=self.n_links, want_state=want_state, want_init=want_init)
+        finally:
+            self._adj_ws = None
+            self._adj = None
 
     @property
     def n_links(self):

@@ -64,14 +64,6 @@ bool adj_layout(const lbm_ctx *c, int64_t nsteps, int32_t k, AdjLayout *L)
 
 }  // namespace
 
-namespace lbm_host {
-
-lbm_status adjoint_force_impl(lbm_ctx *c, void *wsv, size_t ws_bytes, int64_t nsteps, int32_t k, int32_t obj,
-                              double dir_x, double dir_y, double *J, double *dJ_duin, double *dJ_dq,
-                              double *dJ_duw, double *dJ_dstate, double *dJ_dinit, bool no_alloc);
-
-}  // namespace lbm_host
-
 extern "C" {
 
 size_t lbm_adjoint_workspace_bytes(const lbm_ctx *c, int64_t nsteps, int32_t ckpt_every)
@@ -90,7 +82,25 @@ lbm_status lbm_adjoint_force(lbm_ctx *c, void *wsv, size_t ws_bytes, int64_t nst
                              double *dJ_duw, double *dJ_dstate, double *dJ_dinit)
 {
     return adjoint_force_impl(c, wsv, ws_bytes, nsteps, k, obj, dir_x, dir_y, J, dJ_duin, dJ_dq, dJ_duw, dJ_dstate,
-                              dJ_dinit, false);
+                              dJ_dinit, false, ADJ_BOTH);
+}
+
+lbm_status lbm_adjoint_forward(lbm_ctx *c, void *ws, size_t ws_bytes, int64_t nsteps, int32_t ckpt_every,
+                               int32_t obj, double dir_x, double dir_y, double *J)
+{
+    return adjoint_force_impl(c, ws, ws_bytes, nsteps, ckpt_every, obj, dir_x, dir_y, J, nullptr, nullptr, nullptr,
+                              nullptr, nullptr, false, ADJ_FORWARD);
+}
+
+lbm_status lbm_adjoint_backward(lbm_ctx *c, void *ws, size_t ws_bytes, double *dJ_duin, double *dJ_dq,
+                                double *dJ_duw, double *dJ_dstate, double *dJ_dinit)
+{
+    if (!c) return LBM_E_ARG;
+    if (!c->adj.valid || c->adj.ws != ws || c->adj.bytes != ws_bytes || c->step != c->adj.step_end)
+        return c->fail(LBM_E_STATE, "lbm_adjoint_backward without a matching lbm_adjoint_forward on this workspace "
+                                    "(or the context changed in between)");
+    return adjoint_force_impl(c, ws, ws_bytes, c->adj.nsteps, c->adj.k, c->adj.obj, c->adj.dir_x, c->adj.dir_y,
+                              nullptr, dJ_duin, dJ_dq, dJ_duw, dJ_dstate, dJ_dinit, false, ADJ_BACKWARD);
 }
 
 }  // extern "C"
@@ -103,9 +113,10 @@ lbm_status lbm_adjoint_force(lbm_ctx *c, void *wsv, size_t ws_bytes, int64_t nst
 lbm_status lbm_host::adjoint_force_impl(lbm_ctx *c, void *wsv, size_t ws_bytes, int64_t nsteps, int32_t k,
                                         int32_t obj, double dir_x, double dir_y, double *J, double *dJ_duin,
                                         double *dJ_dq, double *dJ_duw, double *dJ_dstate, double *dJ_dinit,
-                                        bool no_alloc)
+                                        bool no_alloc, int phase)
 {
     if (!c) return LBM_E_ARG;
+    if (phase != ADJ_BACKWARD) c->adj.valid = false;
     if (!c->have_geom || !c->have_init)
         return c->fail(LBM_E_STATE, "lbm_adjoint_force before lbm_set_geometry and initialisation");
     if (c->p.storage != LBM_F64 && c->p.storage != LBM_F32)
@@ -148,39 +159,58 @@ lbm_status lbm_host::adjoint_force_impl(lbm_ctx *c, void *wsv, size_t ws_bytes, 
 
     // forward sweep: checkpoints every k steps (the state and the side moments the
     // next link kernel reads); J from the running force sum
-    double last[2], sum0[2], sum1[2];
-    int64_t ns;
-    if ((s = lbm_force(c, obj, last, sum0, &ns))) return s;
-    for (int64_t j = 0; j < L.n_ck; ++j) {
-        if ((s = c->hip(hipMemcpyAsync(ck(j), c->cur, 9 * (size_t)c->lay.plane * elem_bytes(storage),
-                                       hipMemcpyDeviceToDevice, st), "checkpoint copy")))
-            return s;
-        if (mb && (s = c->hip(hipMemcpyAsync(ckM(j), c->side().M, mb, hipMemcpyDeviceToDevice, st),
+    double Jv = c->adj.J;
+    if (phase != ADJ_BACKWARD) {
+        double last[2], sum0[2], sum1[2];
+        int64_t ns;
+        if ((s = lbm_force(c, obj, last, sum0, &ns))) return s;
+        for (int64_t j = 0; j < L.n_ck; ++j) {
+            if ((s = c->hip(hipMemcpyAsync(ck(j), c->cur, 9 * (size_t)c->lay.plane * elem_bytes(storage),
+                                           hipMemcpyDeviceToDevice, st), "checkpoint copy")))
+                return s;
+            if (mb && (s = c->hip(hipMemcpyAsync(ckM(j), c->side().M, mb, hipMemcpyDeviceToDevice, st),
+                                  "checkpoint copy")))
+                return s;
+            if (j + 1 < L.n_ck) {
+                if (no_alloc) {
+                    for (int32_t t = 0; t < k; ++t)
+                        if ((s = enqueue_step(c, false))) return s;
+                } else if ((s = lbm_step(c, k))) {
+                    return s;
+                }
+                continue;
+            }
+            // the last segment is written straight into the tape: the reverse sweep
+            // starts on it without recomputing it
+            for (int64_t t = j * k; t < nsteps; ++t) {
+                const void *A = t == j * k ? c->cur : state(t);
+                void *Bn = t + 1 < nsteps ? state(t + 1) : c->nxt;
+                if ((s = enqueue_step_to(c, A, Bn, false))) return s;
+            }
+            std::swap(c->cur, c->nxt);
+        }
+        if (mb && (s = c->hip(hipMemcpyAsync(ckM(L.n_ck), c->side().M, mb, hipMemcpyDeviceToDevice, st),
                               "checkpoint copy")))
             return s;
-        if (j + 1 < L.n_ck) {
-            if (no_alloc) {
-                for (int32_t t = 0; t < k; ++t)
-                    if ((s = enqueue_step(c, false))) return s;
-            } else if ((s = lbm_step(c, k))) {
-                return s;
-            }
-            continue;
-        }
-        // the last segment is written straight into the tape: the reverse sweep
-        // starts on it without recomputing it
-        for (int64_t t = j * k; t < nsteps; ++t) {
-            const void *A = t == j * k ? c->cur : state(t);
-            void *Bn = t + 1 < nsteps ? state(t + 1) : c->nxt;
-            if ((s = enqueue_step_to(c, A, Bn, false))) return s;
-        }
-        std::swap(c->cur, c->nxt);
+        if ((s = lbm_force(c, obj, last, sum1, &ns))) return s;
+        Jv = (dir_x * (sum1[0] - sum0[0]) + dir_y * (sum1[1] - sum0[1])) / (double)nsteps;
     }
-    if (mb && (s = c->hip(hipMemcpyAsync(ckM(L.n_ck), c->side().M, mb, hipMemcpyDeviceToDevice, st),
-                          "checkpoint copy")))
-        return s;
-    if ((s = lbm_force(c, obj, last, sum1, &ns))) return s;
-    const double Jv = (dir_x * (sum1[0] - sum0[0]) + dir_y * (sum1[1] - sum0[1])) / (double)nsteps;
+    if (phase == ADJ_FORWARD) {
+        if (!std::isfinite(Jv)) return c->fail(LBM_E_UNSTABLE, "lbm_adjoint_forward: non-finite objective");
+        if (J) *J = Jv;
+        c->adj.valid = true;
+        c->adj.ws = wsv;
+        c->adj.bytes = ws_bytes;
+        c->adj.nsteps = nsteps;
+        c->adj.step_end = c->step;
+        c->adj.k = k;
+        c->adj.obj = obj;
+        c->adj.dir_x = dir_x;
+        c->adj.dir_y = dir_y;
+        c->adj.J = Jv;
+        return LBM_OK;
+    }
+    c->adj.valid = false;
 
     // reverse sweep
     struct Z {

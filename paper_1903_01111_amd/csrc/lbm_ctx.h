@@ -61,6 +61,17 @@ struct lbm_ctx {
     hipGraphExec_t gexec = nullptr;
     void *graph_cur = nullptr;
     int graph_dpar = 0;
+    // an adjoint call split in two (lbm_adjoint_forward, then lbm_adjoint_backward):
+    // what the forward half left in its workspace; any change of the state between
+    // the halves (steps, geometry, initialisation, a restored checkpoint) voids it
+    struct {
+        bool valid = false;
+        void *ws = nullptr;
+        size_t bytes = 0;
+        int64_t nsteps = 0, step_end = 0;
+        int32_t k = 0, obj = 0;
+        double dir_x = 0, dir_y = 0, J = 0;
+    } adj;
     // profiling
     bool prof = false;
     std::vector<hipEvent_t> events;
@@ -149,4 +160,13 @@ lbm_status enqueue_step(lbm_ctx *c, bool timed);
 // The same step from state A into B (any buffers of the context's layout); the
 // context's own buffers are left as they are.
 lbm_status enqueue_step_to(lbm_ctx *c, const void *A, void *B, bool timed);
+
+// The adjoint call (lbm_adjoint.cpp) over a device workspace: phase selects the
+// whole call, its forward half only (checkpoints and J, kept pending in the
+// context) or its backward half only (from the pending forward half); with
+// no_alloc nothing is allocated on the device or the host.
+enum { ADJ_BOTH = 0, ADJ_FORWARD = 1, ADJ_BACKWARD = 2 };
+lbm_status adjoint_force_impl(lbm_ctx *c, void *wsv, size_t ws_bytes, int64_t nsteps, int32_t k, int32_t obj,
+                              double dir_x, double dir_y, double *J, double *dJ_duin, double *dJ_dq,
+                              double *dJ_duw, double *dJ_dstate, double *dJ_dinit, bool no_alloc, int phase);
 }  // namespace lbm_host

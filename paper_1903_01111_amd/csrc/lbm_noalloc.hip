@@ -47,12 +47,6 @@ lbm_status scratch_on(lbm_ctx *c, int dev, void **out)
 
 }  // namespace
 
-namespace lbm_host {
-lbm_status adjoint_force_impl(lbm_ctx *c, void *wsv, size_t ws_bytes, int64_t nsteps, int32_t k, int32_t obj,
-                              double dir_x, double dir_y, double *J, double *dJ_duin, double *dJ_dq,
-                              double *dJ_duw, double *dJ_dstate, double *dJ_dinit, bool no_alloc);
-}
-
 extern "C" lbm_status lbm_adjoint_force_noalloc(lbm_ctx *c, int64_t nsteps, int32_t ckpt_every, int32_t obj,
                                                 double dir_x, double dir_y, double *J, double *dJ_duin,
                                                 double *dJ_dq, double *dJ_duw, double *dJ_dstate,
@@ -72,5 +66,6 @@ extern "C" lbm_status lbm_adjoint_force_noalloc(lbm_ctx *c, int64_t nsteps, int3
     lbm_status s = scratch_on(c, c->p.device, &ws);
     if (s) return s;
     return lbm_host::adjoint_force_impl(c, ws, (size_t)LBM_ADJOINT_SCRATCH_BYTES, nsteps, ckpt_every, obj, dir_x,
-                                        dir_y, J, dJ_duin, dJ_dq, dJ_duw, dJ_dstate, dJ_dinit, true);
+                                        dir_y, J, dJ_duin, dJ_dq, dJ_duw, dJ_dstate, dJ_dinit, true,
+                                        lbm_host::ADJ_BOTH);
 }

@@ -664,6 +664,7 @@ lbm_status lbm_set_geometry(lbm_ctx *c, const uint8_t *mask, int64_t n_links, co
                             const int8_t *scheme)
 {
     if (!c) return LBM_E_ARG;
+    c->adj.valid = false;
     std::string why;
     Prepared prep;
     lbm_status s = prepare_geometry(c->p, mask, n_links, node, dir, q, uw, obj, scheme, c->lay.pitch,
@@ -778,6 +779,7 @@ lbm_status lbm_set_inlet(lbm_ctx *c, const double *ux, const double *uy)
 lbm_status lbm_init_equilibrium(lbm_ctx *c, const double *rho, const double *ux, const double *uy)
 {
     if (!c) return LBM_E_ARG;
+    c->adj.valid = false;
     if (!c->have_geom) return c->fail(LBM_E_STATE, "lbm_init_equilibrium before lbm_set_geometry");
     c->drop_graph();
     const int nx = c->p.nx, ny = c->p.ny;
@@ -1068,6 +1070,7 @@ lbm_status lbm_get_state(lbm_ctx *c, void *host, size_t bytes)
 
 lbm_status lbm_set_state(lbm_ctx *c, const void *host, size_t bytes)
 {
+    if (c) c->adj.valid = false;
     if (!c || !host) return LBM_E_ARG;
     if (!c->have_geom) return c->fail(LBM_E_STATE, "lbm_set_state before lbm_set_geometry");
     if (bytes < lbm_state_bytes(c)) return c->fail(LBM_E_ARG, "lbm_set_state: buffer too small");

@@ -294,3 +294,26 @@ def test_full_size_drag_gradient(B):
     print(f"[adjoint] full size fp32 vs fp64: J {abs(J32 - J64) / abs(J64):.2e}, gradient {err}", flush=True)
     assert abs(J32 - J64) <= 1e-4 * abs(J64)
     assert err.max() <= 1e-3
+
+
+def test_split_forward_backward_equals_one_call(B):
+    """lbm_adjoint_forward then lbm_adjoint_backward give what lbm_adjoint_force
+    gives (to the FP64 bound: the gradient sums use FP64 atomics), and a step of
+    the context between the halves voids the forward half."""
+    case = _cyl()
+    a = B.Lattice(case, storage="f64")
+    ref = a.adjoint_force(40, 7, 0, (1.0, 0.3), want_state=True, want_init=True)
+    a.close()
+    b = B.Lattice(case, storage="f64")
+    J = b.adjoint_forward(40, 7, 0, (1.0, 0.3))
+    got = b.adjoint_backward(want_state=True, want_init=True)
+    assert abs(J - ref["J"]) <= 1e-13 * abs(ref["J"])
+    for key in ("duin", "dq", "duw", "dstate", "dinit"):
+        err = np.abs(got[key] - ref[key]).max() / np.abs(ref[key]).max()
+        assert err <= 1e-11, (key, err)
+    b.adjoint_forward(20, 5)
+    b.step(1)
+    with pytest.raises(B.LbmError) as e:
+        b.adjoint_backward()
+    assert e.value.status == B.LBM_E_STATE
+    b.close()
