@@ -302,13 +302,18 @@ typedef struct {
     int32_t bulk_rows;        /* row segments per bulk wavefront: 2 issues the second one's loads
                                  before the first is finished (needs bulk_block_x 256 and
                                  bulk_fused 0); 1 (or 0): one */
+    int32_t bulk_runs;        /* 1: each bulk wavefront takes a run of 64 consecutive fluid nodes
+                                 instead of a 64-node row segment, so every lane holds a node and
+                                 the planes are written in whole cache lines (compact layout,
+                                 periodic in x, bulk_fused 0; bulk_block_x, bulk_store_solid and
+                                 bulk_rows do not apply); 0: row segments */
 } lbm_kernel_config;
 
 lbm_status lbm_get_kernel_config(const lbm_ctx *ctx, lbm_kernel_config *cfg);
 /* Errors: LBM_E_ARG for an unsupported configuration (the previous one stays). */
 lbm_status lbm_set_kernel_config(lbm_ctx *ctx, const lbm_kernel_config *cfg);
 
-/* Autotuner: times every bulk shape (block, solid stores, XCD order, rows per wavefront, fused links) and link block size for steps_per_trial steps
+/* Autotuner: times every bulk shape (block, solid stores, XCD order, rows per wavefront, runs of fluid nodes, fused links) and link block size for steps_per_trial steps
  * on the current state, keeps the fastest, and restores the state (populations,
  * step counter, forces), so results do not depend on having tuned.  Needs host
  * memory for one checkpoint.  chosen and best_ms_per_step may be NULL. */

@@ -50,7 +50,7 @@ class lbm_params(C.Structure):
 class lbm_kernel_config(C.Structure):
     _fields_ = [("bulk_block_x", C.c_int32), ("bulk_store_solid", C.c_int32),
                 ("link_block", C.c_int32), ("graph_steps", C.c_int32), ("bulk_xcd", C.c_int32),
-                ("bulk_fused", C.c_int32), ("bulk_rows", C.c_int32)]
+                ("bulk_fused", C.c_int32), ("bulk_rows", C.c_int32), ("bulk_runs", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

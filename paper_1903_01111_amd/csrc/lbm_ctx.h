@@ -20,7 +20,7 @@ namespace lbm_host {
 struct Layout {
     int32_t pitch;
     int64_t plane;  // elements per population plane
-    size_t off_A, off_B, off_mask, off_seg, off_fmask, off_meta, off_q, off_uw, off_sf, off_sff, off_pf, off_pff,
+    size_t off_A, off_B, off_mask, off_seg, off_fmask, off_runs, off_meta, off_q, off_uw, off_sf, off_sff, off_pf, off_pff,
         off_pfi, off_li, off_kof, off_L, off_rec, off_mnode, off_pbase, off_M, off_P, off_M2, off_P2, off_wpart,
         off_wobj, off_uin,
         off_force, off_partials, off_stage, total;
@@ -52,7 +52,8 @@ struct lbm_ctx {
     std::vector<int32_t> colslot;
     void *cur = nullptr, *nxt = nullptr;
     int64_t step = 0, nsum = 0;
-    lbm_kernel_config kcfg{256, 0, 256, 16, 0, 0, 1};
+    lbm_kernel_config kcfg{256, 0, 256, 16, 0, 0, 1, 0};
+    int32_t nruns = 0, n_fluid = 0;  // runs of 64 fluid nodes (compact layout)
     // deposits (M, P) are double-buffered: dpar selects the pair the links of the
     // next step read; the bulk kernel deposits into the other one
     int dpar = 0;
@@ -84,7 +85,8 @@ struct lbm_ctx {
         return lbm::Grid{p.nx, p.ny, lay.pitch, p.x_bc == LBM_X_OPEN ? 1 : 0, lay.plane,
                          p.layout == LBM_LAYOUT_COMPACT ? 1 : 0, 0,
                          reinterpret_cast<const lbm::SegBase *>(ws + lay.off_seg),
-                         reinterpret_cast<const uint64_t *>(ws + lay.off_fmask)};
+                         reinterpret_cast<const uint64_t *>(ws + lay.off_fmask),
+                         reinterpret_cast<const lbm::RunBase *>(ws + lay.off_runs), nruns, n_fluid};
     }
     lbm::Phys phys() const
     {
@@ -108,7 +110,7 @@ struct lbm_ctx {
     lbm::BulkConfig bulk_config() const
     {
         return lbm::BulkConfig{kcfg.bulk_block_x, kcfg.bulk_store_solid, kcfg.bulk_xcd, kcfg.bulk_fused,
-                               kcfg.bulk_rows == 2 ? 2 : 1};
+                               kcfg.bulk_rows == 2 ? 2 : 1, kcfg.bulk_runs};
     }
     // deposits read with parity p (and written into the other pair)
     lbm::Side side_par(int p) const

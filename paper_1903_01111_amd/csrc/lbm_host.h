@@ -43,6 +43,8 @@ struct Prepared {
     std::vector<lbm::mask_t> mask;         // padded to the pitch: link bits, solid bit, side bit
     std::vector<lbm::SegBase> seg;         // per 64-node row segment, plus a sentinel with the totals
     std::vector<uint64_t> fmask;           // per segment: its fluid nodes (bit = lane)
+    std::vector<lbm::RunBase> runs;        // per run of 64 fluid nodes, plus a sentinel with the totals
+    int32_t n_fluid = 0;
     int64_t n_pops = 0;
     bool has_uw = false;
     bool has_pfi = false;       // some link reads f+_i(x_f) (Bouzidi, Yu): pfi is filled

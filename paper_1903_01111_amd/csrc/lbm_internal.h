@@ -13,6 +13,7 @@ namespace lbm {
 // f_i - w_i of node (x, y) at offset y*pitch + x.  pitch >= nx is a multiple of
 // 64 elements, so a 64-lane wavefront reads one aligned run of a row.
 struct SegBase;
+struct RunBase;
 
 // With compact set, plane i holds only the fluid nodes, the k-th fluid node in
 // (y, x) order at offset k: a node's offset is the fluid count before its
@@ -24,6 +25,9 @@ struct Grid {
     int32_t compact, pad;
     const SegBase *fseg;    // [ny * pitch / 64] (compact layout)
     const uint64_t *fmask;  // [ny * pitch / 64] (compact layout)
+    const RunBase *runs;    // [nruns + 1] (compact layout): see RunBase
+    int32_t nruns;          // runs of 64 fluid nodes: ceil(n_fluid / 64)
+    int32_t n_fluid;
 };
 
 struct Phys {
@@ -50,6 +54,16 @@ constexpr mask_t MASK_LINKS = 0xff, MASK_SOLID = 0x100, MASK_SIDE = 0x200;
 // come before it in plane order.
 struct SegBase {
     int32_t flagged, links, pops, fluid;
+};
+
+// Run w of the compact layout is the fluid nodes 64w .. 64w+63 in plane order.
+// Counts before its first node: flagged nodes (side records), links in (node, dir)
+// order and deposited populations; seg is the row segment of its first node; bit j
+// of (flag_hi, flag_lo) is set when node 64w + j is flagged (has a side record).
+// Entry nruns holds the totals.
+struct RunBase {
+    int32_t flagged, links, pops, seg;
+    uint32_t flag_lo, flag_hi, pad0, pad1;
 };
 
 // Data exchanged between the bulk kernel and the link kernel through compact
@@ -122,6 +136,7 @@ struct BulkConfig {
     int32_t xcd;          // contiguous runs of blocks per XCD (see bulk_kernel)
     int32_t fused;        // the bulk kernel evaluates the links of its nodes (no link kernel)
     int32_t rows;         // row segments per wavefront: 1, or 2 (block_x 256, not fused)
+    int32_t runs;         // one run of 64 fluid nodes per wavefront (compact layout, periodic x)
 };
 
 // What the fused bulk kernel needs for the links: link arrays, the per-segment

@@ -63,6 +63,8 @@ Layout make_layout(const lbm_params &p, int64_t max_links)
     L.off_mask = take((size_t)L.pitch * p.ny * sizeof(lbm::mask_t));
     L.off_seg = take(((size_t)(L.pitch / 64) * p.ny + 1) * sizeof(lbm::SegBase));
     L.off_fmask = take((size_t)(L.pitch / 64) * p.ny * sizeof(uint64_t));
+    // runs of 64 fluid nodes: at most one per segment, plus the sentinel
+    L.off_runs = take(((size_t)(L.pitch / 64) * p.ny + 1) * sizeof(lbm::RunBase));
     const size_t nl = (size_t)std::max<int64_t>(max_links, 0);
     L.off_meta = take(nl * 4);
     L.off_q = take(nl * rb);
@@ -344,6 +346,25 @@ lbm_status prepare_geometry(const lbm_params &p, const uint8_t *mask, int64_t n,
     }
     // sentinel after the last segment: the totals
     out->seg.push_back(lbm::SegBase{(int32_t)out->rec.size(), nlinks, npops, nfluid});
+    // runs of 64 fluid nodes in plane order: the counts before each run's first node
+    out->n_fluid = nfluid;
+    out->runs.clear();
+    {
+        int32_t fl = 0, nl = 0, np = 0, nf = 0;
+        for (int64_t o = 0; o < (int64_t)plane_n; ++o) {
+            if (out->mask[o] & lbm::MASK_SOLID) continue;
+            const int j = nf & 63;
+            if (j == 0) out->runs.push_back(lbm::RunBase{fl, nl, np, (int32_t)(o / 64), 0u, 0u, 0u, 0u});
+            ++nf;
+            if (bits[o]) {
+                (j < 32 ? out->runs.back().flag_lo : out->runs.back().flag_hi) |= 1u << (j & 31);
+                ++fl;
+                nl += __builtin_popcount(bits[o] & 0xffu);
+                np += __builtin_popcount(bits[o] >> 8);
+            }
+        }
+        out->runs.push_back(lbm::RunBase{fl, nl, np, (int32_t)nseg, 0u, 0u, 0u, 0u});
+    }
     out->n_pops = npops;
     auto rank_below = [](uint32_t set, int d) { return __builtin_popcount(set & ((1u << (d - 1)) - 1u)); };
     // links in (obj, node, dir) order; L entry = rank in (node, dir) order
@@ -710,7 +731,8 @@ lbm_status lbm_set_geometry(lbm_ctx *c, const uint8_t *mask, int64_t n_links, co
                {c->lay.off_mnode, prep.mnode.data(), K * 4},
                {c->lay.off_pbase, prep.pbase.data(), K * 4},
                {c->lay.off_seg, prep.seg.data(), prep.seg.size() * sizeof(lbm::SegBase)},
-               {c->lay.off_fmask, prep.fmask.data(), prep.fmask.size() * sizeof(uint64_t)}};
+               {c->lay.off_fmask, prep.fmask.data(), prep.fmask.size() * sizeof(uint64_t)},
+               {c->lay.off_runs, prep.runs.data(), prep.runs.size() * sizeof(lbm::RunBase)}};
     for (const Up &u : ups)
         if (u.bytes && (s = c->hip(hipMemcpyAsync(c->ws + u.off, u.src, u.bytes,
                                                   hipMemcpyHostToDevice, st), "link upload")))
@@ -738,6 +760,8 @@ lbm_status lbm_set_geometry(lbm_ctx *c, const uint8_t *mask, int64_t n_links, co
                     c->colslot[(size_t)side * c->p.ny + y] = (int32_t)(it - prep.mnode.begin());
             }
     c->n_moment_nodes = (int64_t)prep.rec.size();
+    c->n_fluid = prep.n_fluid;
+    c->nruns = (int32_t)prep.runs.size() - 1;
     c->has_uw = prep.has_uw;
     c->has_pfi = prep.has_pfi;
     c->has_ext_scheme = prep.has_ext_scheme;
@@ -1133,6 +1157,11 @@ lbm_status lbm_set_kernel_config(lbm_ctx *c, const lbm_kernel_config *cfg)
         return c->fail(LBM_E_ARG, "lbm_set_kernel_config: unsupported configuration");
     if (c->p.collision == LBM_COLLISION_MRT && (bx != 256 || cfg->bulk_fused))
         return c->fail(LBM_E_ARG, "lbm_set_kernel_config: MRT runs with bulk_block_x 256 and bulk_fused 0");
+    if (cfg->bulk_runs != 0 && cfg->bulk_runs != 1)
+        return c->fail(LBM_E_ARG, "lbm_set_kernel_config: bulk_runs must be 0 or 1");
+    if (cfg->bulk_runs && (c->p.layout != LBM_LAYOUT_COMPACT || c->p.x_bc == LBM_X_OPEN || cfg->bulk_fused))
+        return c->fail(LBM_E_ARG, "lbm_set_kernel_config: bulk_runs needs the compact layout, a periodic x "
+                                  "direction and bulk_fused 0");
     c->drop_graph();
     c->kcfg = *cfg;
     return LBM_OK;
@@ -1185,10 +1214,25 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps_per_trial, lbm_kernel_config *
                     k.bulk_xcd = xo;
                     k.bulk_fused = 0;
                     k.bulk_rows = rows;
+                    k.bulk_runs = 0;
                     double ms;
                     if ((s = trial(k, &ms))) break;
                     if (ms < best_ms) best_ms = ms, best = k;
                 }
+    // runs of 64 fluid nodes per wavefront (compact layout, periodic in x)
+    for (int xo : {0, 1}) {
+        if (s || c->p.layout != LBM_LAYOUT_COMPACT || c->p.x_bc == LBM_X_OPEN) break;
+        lbm_kernel_config k = best;
+        k.bulk_block_x = 256;
+        k.bulk_store_solid = 0;
+        k.bulk_xcd = xo;
+        k.bulk_fused = 0;
+        k.bulk_rows = 1;
+        k.bulk_runs = 1;
+        double ms;
+        if ((s = trial(k, &ms))) break;
+        if (ms < best_ms) best_ms = ms, best = k;
+    }
     for (int lb : {128, 256, 512, 1024}) {
         if (s) break;
         lbm_kernel_config k = best;
@@ -1205,6 +1249,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps_per_trial, lbm_kernel_config *
             lbm_kernel_config k = unfused;
             k.bulk_fused = 1;
             k.bulk_rows = 1;
+            k.bulk_runs = 0;
             k.bulk_block_x = 256;
             k.bulk_store_solid = ss;
             k.bulk_xcd = xo;

@@ -441,6 +441,63 @@ struct Pulled {
     bool live;  // the wavefront's row segment lies in the lattice (uniform)
 };
 
+// Compact layout, lane `lane` of row segment sx of row yu (x = 64 sx + lane): the
+// byte offsets in a plane of (x, r) (rk), of (x-1, r) (lf) and of (x+1, r) (rt) for
+// the rows r = y-1, y, y+1.  The fluid rank of (x, r) is the fluid base of the
+// segment in that row plus the fluid lanes below this one (v_mbcnt over the
+// segment's bitmask).  In plane order a fluid node at x-1 then has rank rk - 1 and
+// one at x+1 rank rk + fluid(x); offsets of solid nodes are only kept in bounds
+// (their values are discarded).  yu and sx are wavefront-uniform.
+template <uint32_t S, bool OPEN>
+__device__ __forceinline__ void cmp_ranks(const Grid &g, int yu, int sx, int lane, uint32_t (&rk)[3],
+                                          uint32_t (&lf)[3], uint32_t (&rt)[3])
+{
+    const int nsr = g.pitch >> 6;
+    const int rows3[3] = {yu == 0 ? g.ny - 1 : yu - 1, yu, yu == g.ny - 1 ? 0 : yu + 1};
+    const uint32_t last = (uint32_t)(g.plane - 1) * S;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const int32_t sg = rows3[r] * nsr + sx;
+        const uint64_t fm = ld_const(g.fmask + sg);
+        rk[r] = S * __builtin_amdgcn_mbcnt_hi((uint32_t)(fm >> 32),
+                                              __builtin_amdgcn_mbcnt_lo((uint32_t)fm, (uint32_t)ld_const(&g.fseg[sg].fluid)));
+        lf[r] = (rk[r] > S ? rk[r] : S) - S;
+        const uint32_t q = rk[r] + S * (uint32_t)((fm >> lane) & 1ull);
+        rt[r] = q < last ? q : last;
+    }
+    if (!OPEN) {
+        // periodic wrap in x: x = 0 pulls its e_x > 0 directions from x = nx-1 and
+        // x = nx-1 its e_x < 0 directions from x = 0
+        if (sx == 0 && lane == 0) {
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const int32_t sg = rows3[r] * nsr + nsr - 1;
+                lf[r] = S * (uint32_t)(ld_const(&g.fseg[sg].fluid) +
+                                        (int32_t)__popcll(ld_const(g.fmask + sg) & ((1ull << ((g.nx - 1) & 63)) - 1ull)));
+            }
+        }
+        if (sx == nsr - 1 && lane == ((g.nx - 1) & 63)) {
+#pragma unroll
+            for (int r = 0; r < 3; ++r) rt[r] = S * (uint32_t)ld_const(&g.fseg[rows3[r] * nsr].fluid);
+        }
+    }
+}
+
+// The nine pull sources f_i(x, t+1) = f+_i(x - e_i, t) from cmp_ranks' offsets.
+__device__ __forceinline__ void cmp_pull_offsets(const uint32_t (&rk)[3], const uint32_t (&lf)[3],
+                                                 const uint32_t (&rt)[3], uint32_t (&o)[9])
+{
+    o[0] = rk[1];
+    o[1] = lf[1];
+    o[2] = rk[0];
+    o[3] = rt[1];
+    o[4] = rk[2];
+    o[5] = lf[0];
+    o[6] = rt[0];
+    o[7] = rt[2];
+    o[8] = lf[2];
+}
+
 template <int ST, bool OPEN, bool CMP>
 __device__ __forceinline__ void bulk_issue(const Grid &g, const typename Codec<ST>::T *__restrict__ A,
                                            const mask_t *__restrict__ mask, int x, int y, Pulled<ST> &pl)
@@ -476,56 +533,15 @@ __device__ __forceinline__ void bulk_issue(const Grid &g, const typename Codec<S
     // byte offsets in a plane of the nine pull sources and of the node itself (own)
     uint32_t o[9], own, own_in = (uint32_t)row * S, own_out = (uint32_t)(row + g.nx - 1) * S;
     if (CMP) {
-        // compact layout: the fluid rank of (x, r) for the rows r = y-1, y, y+1 is the
-        // fluid base of the wavefront's segment in that row plus the fluid lanes below
-        // this one (v_mbcnt over the segment's bitmask).  In plane order a fluid
-        // source at x-1 then has rank rk - 1 and one at x+1 rank rk + fluid(x); solid
-        // sources are discarded, their offsets only kept in bounds.
-        const int nsr = g.pitch >> 6;
-        const int sx = __builtin_amdgcn_readfirstlane(x >> 6);
-        const int yu = __builtin_amdgcn_readfirstlane(y);
-        const int rows3[3] = {yu == 0 ? g.ny - 1 : yu - 1, yu, yu == g.ny - 1 ? 0 : yu + 1};
-        const uint32_t last = (uint32_t)(P - 1) * S;
         uint32_t rk[3], lf[3], rt[3];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            const int32_t sg = rows3[r] * nsr + sx;
-            const uint64_t fm = ld_const(g.fmask + sg);
-            rk[r] = S * __builtin_amdgcn_mbcnt_hi((uint32_t)(fm >> 32),
-                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)fm, (uint32_t)ld_const(&g.fseg[sg].fluid)));
-            lf[r] = (rk[r] > S ? rk[r] : S) - S;
-            const uint32_t q = rk[r] + S * (uint32_t)((fm >> lane) & 1ull);
-            rt[r] = q < last ? q : last;
-        }
-        if (!OPEN) {
-            // periodic wrap in x: x = 0 pulls its e_x > 0 directions from x = nx-1 and
-            // x = nx-1 its e_x < 0 directions from x = 0
-            if (sx == 0 && lane == 0) {
-#pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    const int32_t sg = rows3[r] * nsr + nsr - 1;
-                    lf[r] = S * (uint32_t)(ld_const(&g.fseg[sg].fluid) +
-                                            (int32_t)__popcll(ld_const(g.fmask + sg) & ((1ull << ((g.nx - 1) & 63)) - 1ull)));
-                }
-            }
-            if (sx == nsr - 1 && lane == ((g.nx - 1) & 63)) {
-#pragma unroll
-                for (int r = 0; r < 3; ++r) rt[r] = S * (uint32_t)ld_const(&g.fseg[rows3[r] * nsr].fluid);
-            }
-        } else {
+        cmp_ranks<S, OPEN>(g, __builtin_amdgcn_readfirstlane(y), __builtin_amdgcn_readfirstlane(x >> 6), lane, rk,
+                           lf, rt);
+        if (OPEN) {
             own_in = lf[1];   // (0, y), written by the lane x = 1 (both fluid)
             own_out = rt[1];  // (nx-1, y), written by the lane x = nx-2 (both fluid)
         }
         own = rk[1];
-        o[0] = rk[1];
-        o[1] = lf[1];
-        o[2] = rk[0];
-        o[3] = rt[1];
-        o[4] = rk[2];
-        o[5] = lf[0];
-        o[6] = rt[0];
-        o[7] = rt[2];
-        o[8] = lf[2];
+        cmp_pull_offsets(rk, lf, rt, o);
     } else {
         own = (uint32_t)(row + x) * S;
         o[0] = (uint32_t)(row + xc) * S;
@@ -551,8 +567,10 @@ __device__ __forceinline__ void bulk_issue(const Grid &g, const typename Codec<S
     pl.own_out = own_out;
 }
 
+// With RUN the wavefront is a run of fluid nodes (bulk_run_kernel): rbase holds
+// its bases, and x < nx marks the lanes that hold a node.
 template <int ST, bool OPEN, bool FORCE, int BX, bool STORE_SOLID, bool CMP = false, bool FUSE = false,
-          int COLL = 0>
+          int COLL = 0, bool RUN = false>
 __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
                                             typename Codec<ST>::T *__restrict__ B,
                                             const mask_t *__restrict__ mask,
@@ -561,8 +579,10 @@ __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
                                             typename Codec<ST>::R (*lds_m)[3 * 64],
                                             typename Codec<ST>::T (*lds_p)[8 * 64], const Pulled<ST> &pl,
                                             const FuseArgs *fa = nullptr,
-                                            typename Codec<ST>::T (*lds_l)[8 * 64] = nullptr)
+                                            typename Codec<ST>::T (*lds_l)[8 * 64] = nullptr,
+                                            const SegBase rbase = SegBase{0, 0, 0, 0})
 {
+    static_assert(!RUN || (CMP && !OPEN && !FUSE), "runs: compact layout, periodic in x, separate links");
     using C = Codec<ST>;
     using T = typename C::T;
     using R = typename C::R;
@@ -579,8 +599,12 @@ __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
     typename C::Reg a[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) a[i] = pl.a[i];
-    const int32_t seg = __builtin_amdgcn_readfirstlane(y * (g.pitch >> 6) + (x >> 6));
-    const SegBase sb = ld_seg(side.seg + seg);
+    int32_t seg = 0;
+    SegBase sb = rbase;
+    if constexpr (!RUN) {
+        seg = __builtin_amdgcn_readfirstlane(y * (g.pitch >> 6) + (x >> 6));
+        sb = ld_seg(side.seg + seg);
+    }
     if (FUSE) {
         // the wavefront's links are entries [lw, lw + nl) of the (node, dir) order
         // (segment bases; no need to wait for the mask words): one per lane,
@@ -635,8 +659,9 @@ __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
     const uint64_t flagged = __ballot((m & MASK_SIDE) != 0);
     const int32_t slot = sb.flagged + (int32_t)__popcll(flagged & ((1ull << lane) - 1ull));
     const uint32_t rec = (m & MASK_SIDE) ? ld_el(side.rec, slot) : 0u;
-    // links of this node (mask bits): exclusive wavefront prefix -> first L entry
-    const uint32_t lk = m & MASK_LINKS;
+    // links of this node (mask bits; with RUN, the side record's, as a run holds no
+    // mask words): exclusive wavefront prefix -> first L entry
+    const uint32_t lk = (RUN ? rec : (uint32_t)m) & MASK_LINKS;
     const uint32_t linc = wave_inclusive_scan((uint32_t)popc32(lk));
     const int32_t lbase = sb.links + (int32_t)(linc - (uint32_t)popc32(lk));
     // where x - e_i is solid, the link (x, i') with i' = opp(i) (bit i'-1 of the
@@ -985,6 +1010,112 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
         bulk_finish<ST, OPEN, FORCE, BX, STORE_SOLID, CMP, false, COLL>(g, ph, B, mask, uin, side, x, y1, tid >> 6,
                                                                         lds_m, lds_p, p1);
     }
+}
+
+// Runs of fluid nodes (compact layout, periodic in x): wavefront w of the launch
+// takes the fluid nodes 64w .. 64w+63 in plane order instead of one 64-node row
+// segment, so that every lane holds a fluid node (a porous row segment holds 38 of
+// 64 on average) and each plane is read at the node itself and written in
+// 256-byte-aligned runs of full cache lines.  The run spans a few row segments;
+// the wavefront first walks them with one lane per node of the segment (as in the
+// segment mapping), computes there the pull offsets of each fluid node, and hands
+// them through LDS to the lane that takes the node.  The side records, link values
+// and deposits of a run are contiguous ranges like those of a segment, with bases
+// from the run table.  The open columns are excluded: they are written by their
+// neighbour lanes, which a run may place in another wavefront.
+template <int ST, bool FORCE, int COLL>
+__global__ __launch_bounds__(256) void bulk_run_kernel(Grid g, Phys ph, const typename Codec<ST>::T *__restrict__ A,
+                                                       typename Codec<ST>::T *__restrict__ B,
+                                                       const mask_t *__restrict__ mask, Side side,
+                                                       double *__restrict__ zero_bank, int32_t n_zero, int32_t xcd,
+                                                       const double2 *__restrict__ red_part,
+                                                       const int32_t *__restrict__ red_obj, int64_t red_n,
+                                                       double *__restrict__ red_bank, double *__restrict__ red_sum)
+{
+    using C = Codec<ST>;
+    using R = typename C::R;
+    using T = typename C::T;
+    constexpr uint32_t S = sizeof(T);
+    // per wavefront: first the pull offsets of its 64 nodes (9 words each), then
+    // the deposit staging of bulk_finish in the same bytes
+    constexpr int OFF_BYTES = 9 * 64 * 4;
+    constexpr int DEP_BYTES = 64 * (3 * (int)sizeof(R) + 8 * (int)sizeof(T));
+    constexpr int WB = OFF_BYTES > DEP_BYTES ? OFF_BYTES : DEP_BYTES;
+    __shared__ __align__(16) unsigned char lds[4 * WB];
+    const int tid = threadIdx.x;
+    const int64_t nb = gridDim.x;
+    const int64_t b = blockIdx.x;
+    zero_bank_part(zero_bank, n_zero, b, nb, tid);
+    force_reduce_part(red_part, red_obj, red_n, red_bank, red_sum, b, tid);
+    // with xcd, XCD k takes the k-th contiguous range of blocks (runs of
+    // neighbouring nodes), as in bulk_kernel
+    int32_t blk = (int32_t)b;
+    if (xcd) {
+        const int32_t n = (int32_t)nb, q = n >> 3, r = n & 7, k = (int32_t)b & 7;
+        blk = k * q + (k < r ? k : r) + ((int32_t)b >> 3);
+    }
+    const int wv = tid >> 6, lane = tid & 63;
+    const int32_t w = __builtin_amdgcn_readfirstlane(blk * 4 + wv);
+    if (w >= g.nruns) return;
+    const RunBase rb{ld_const(&g.runs[w].flagged), ld_const(&g.runs[w].links), ld_const(&g.runs[w].pops),
+                     ld_const(&g.runs[w].seg), ld_const(&g.runs[w].flag_lo), ld_const(&g.runs[w].flag_hi), 0u, 0u};
+    const uint64_t rflag = ((uint64_t)rb.flag_hi << 32) | rb.flag_lo;
+    unsigned char *wl = lds + wv * WB;
+    uint32_t *lo = reinterpret_cast<uint32_t *>(wl);
+    const int32_t k0 = w * 64;
+    const int32_t kend = k0 + 64 < g.n_fluid ? k0 + 64 : g.n_fluid;
+    const int nsr = g.pitch >> 6;
+    {
+        // walk the row segments of the run; lane = bit of the segment
+        int yu = rb.seg / nsr;
+        int sx = rb.seg - yu * nsr;
+        for (;;) {
+            const int32_t sg = yu * nsr + sx;
+            if (ld_const(&g.fseg[sg].fluid) >= kend) break;  // the sentinel ends the last run
+            const uint64_t fm = ld_const(g.fmask + sg);
+            if (fm) {
+                uint32_t rk[3], lf[3], rt[3], o[9];
+                cmp_ranks<S, false>(g, yu, sx, lane, rk, lf, rt);
+                cmp_pull_offsets(rk, lf, rt, o);
+                const int32_t dst = (int32_t)(rk[1] / S) - k0;
+                if (((fm >> lane) & 1ull) && dst >= 0 && dst < 64) {
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) lo[i * 64 + dst] = o[i];
+                }
+            }
+            if (++sx == nsr) {
+                sx = 0;
+                ++yu;
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const bool live = k0 + lane < kend;
+    uint32_t o[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) o[i] = live ? lo[i * 64 + lane] : 0u;
+    // every lane has read its offsets before the bytes are reused for the deposits
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    Pulled<ST> pl;
+    pl.live = true;
+    // the node type: fluid, flagged from the run table; its link directions come
+    // from its side record in bulk_finish
+    pl.m = live ? (((rflag >> lane) & 1ull) ? (mask_t)MASK_SIDE : (mask_t)0) : (mask_t)MASK_SOLID;
+    const int64_t P = g.plane;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) pl.a[i] = C::reg(ld_at_nt(A + i * P, o[i]));
+    pl.own = (uint32_t)(k0 + lane) * S;
+    pl.own_in = 0;
+    pl.own_out = 0;
+    __builtin_amdgcn_sched_barrier(0);
+    bulk_finish<ST, false, FORCE, 256, false, true, false, COLL, true>(
+        g, ph, B, mask, nullptr, side, live ? 0 : g.nx, 0, 0, reinterpret_cast<R(*)[3 * 64]>(wl),
+        reinterpret_cast<T(*)[8 * 64]>(wl + 64 * 3 * sizeof(R)), pl, nullptr, nullptr,
+        SegBase{rb.flagged, rb.links, rb.pops, 0});
 }
 
 // The same step with the links of each wavefront's nodes evaluated in the
@@ -1360,12 +1491,33 @@ hipError_t bulk_shape(const Grid &g, const Phys &ph, const void *A, void *B, con
     return hipErrorInvalidValue;
 }
 
+template <int ST, bool FORCE, int COLL>
+hipError_t bulk_run_t(const Grid &g, const Phys &ph, const void *A, void *B, const mask_t *mask, const Side &side,
+                      double *zb, int32_t nz, int32_t xcd, hipStream_t s, const ForceReduce &fr)
+{
+    using C = Codec<ST>;
+    if (!g.compact || g.x_open || !g.runs || g.nruns < 0) return hipErrorInvalidValue;
+    // four runs per block; at least enough blocks for the force partials and one
+    // to clear the force bank
+    constexpr int64_t per_block = 256 * FOLD_CHUNK;
+    int64_t nb = ((int64_t)g.nruns + 3) / 4;
+    if (nb * per_block < fr.nw) nb = (fr.nw + per_block - 1) / per_block;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL((bulk_run_kernel<ST, FORCE, COLL>), dim3((unsigned)nb), dim3(256), 0, s, g, ph,
+                       static_cast<const typename C::T *>(A), static_cast<typename C::T *>(B), mask, side, zb, nz,
+                       xcd, fr.wpart, fr.wobj, fr.nw, fr.bank, fr.fsum);
+    return hipGetLastError();
+}
+
 template <int ST, int COLL>
 hipError_t bulk_coll(const Grid &g, const Phys &ph, const void *A, void *B, const mask_t *mask,
                      const void *uin, const Side &side, double *zb, int32_t nz, const BulkConfig &cf,
                      hipStream_t s, const ForceReduce &fr)
 {
     const bool force = ph.gx != 0.0 || ph.gy != 0.0;
+    if (cf.runs)
+        return force ? bulk_run_t<ST, true, COLL>(g, ph, A, B, mask, side, zb, nz, cf.xcd, s, fr)
+                     : bulk_run_t<ST, false, COLL>(g, ph, A, B, mask, side, zb, nz, cf.xcd, s, fr);
     if (g.x_open)
         return force ? bulk_shape<ST, true, true, COLL>(g, ph, A, B, mask, uin, side, zb, nz, cf, s, fr)
                      : bulk_shape<ST, true, false, COLL>(g, ph, A, B, mask, uin, side, zb, nz, cf, s, fr);

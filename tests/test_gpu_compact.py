@@ -2,7 +2,8 @@
 (in (y, x) order) must give bitwise the populations and moments of the dense
 layout for every storage, boundary type, lattice width (one to several 64-node
 segments per row, with the periodic wrap across them) and launch shape; forces
-agree to the summation order of FP64 atomics."""
+agree to the summation order of FP64 atomics.  The same holds for wavefronts that
+take runs of 64 fluid nodes instead of row segments (bulk_runs, periodic x)."""
 import numpy as np
 import pytest
 
@@ -82,6 +83,43 @@ def test_compact_launch_shapes(B, bx, fused, rows, xcd):
     case = CASES["porous_200x64"]()
     cfg = B.lbm_kernel_config(bx, 0, 256, 16, xcd, fused, rows)
     _same(_run(B, case, "f32", "compact", 40, cfg=cfg), _run(B, case, "f32", "dense", 40))
+
+
+PERIODIC = ["porous_48x40", "porous_100x37", "porous_200x64", "no_walls_128x40", "column_1x42"]
+
+
+def _runs_cfg(B, xcd=1):
+    return B.lbm_kernel_config(256, 0, 256, 16, xcd, 0, 1, 1)
+
+
+@pytest.mark.parametrize("name", PERIODIC + ["channel_200x34"])
+@pytest.mark.parametrize("storage", ["f32", "f64", "f16", "bf16", "f32w", "f32p"])
+def test_runs_equal_row_segments(B, name, storage):
+    """Runs of fluid nodes per wavefront give bitwise the populations of the row
+    segment mapping; the walled channel's solid rows make runs cross fluid-free
+    segments, the 128 x 40 lattice has a whole number of runs, the others end in a
+    partial run."""
+    case = CASES[name]() if name in CASES else W.perturb(W.poiseuille_channel(nx=200), seed=5)
+    k = 12 if storage == "f16" else 0
+    print(f"[compact] runs {name} {storage}", flush=True)
+    _same(_run(B, case, storage, "compact", 37, k, cfg=_runs_cfg(B)), _run(B, case, storage, "compact", 37, k))
+
+
+@pytest.mark.parametrize("xcd", [0, 1])
+def test_runs_mrt_and_xcd_order(B, xcd):
+    case = CASES["porous_200x64"]()
+    case.collision = "mrt"
+    print(f"[compact] runs mrt xcd {xcd}", flush=True)
+    _same(_run(B, case, "f32", "compact", 40, cfg=_runs_cfg(B, xcd)), _run(B, case, "f32", "dense", 40))
+
+
+def test_runs_refused_where_unsupported(B):
+    for name, layout in (("cylinder_open", "compact"), ("porous_48x40", "dense")):
+        lat = B.Lattice(CASES[name](), storage="f32", layout=layout)
+        with pytest.raises(B.LbmError) as e:
+            B.lbm_set_kernel_config(lat.ctx, _runs_cfg(B))
+        assert e.value.status == B.LBM_E_ARG
+        lat.close()
 
 
 def test_compact_checkpoint_resume(B):

@@ -457,13 +457,14 @@ def test_invalid_kernel_config_is_rejected(B):
     lat = B.Lattice(small_cylinder(64, 32, 4.0), storage="f32")
     for bad in ((96, 0, 256, 16), (256, 2, 256, 16), (256, 0, 100, 16), (256, 0, 256, 3), (256, 0, 256, 16, 2),
                 (128, 0, 256, 16, 0, 1), (256, 0, 256, 16, 0, 2), (256, 0, 256, 16, 0, 0, 3),
-                (128, 0, 256, 16, 0, 0, 2), (256, 0, 256, 16, 0, 1, 2), (256, 0, 256, 16, 0, 0, -1)):
+                (128, 0, 256, 16, 0, 0, 2), (256, 0, 256, 16, 0, 1, 2), (256, 0, 256, 16, 0, 0, -1),
+                (256, 0, 256, 16, 0, 0, 1, 2), (256, 0, 256, 16, 0, 0, 1, 1)):  # runs: compact, periodic x
         with pytest.raises(B.LbmError) as e:
             B.lbm_set_kernel_config(lat.ctx, B.lbm_kernel_config(*bad))
         assert e.value.status == B.LBM_E_ARG
     assert B.lbm_get_kernel_config(lat.ctx).as_dict() == dict(bulk_block_x=256, bulk_store_solid=0,
                                                              link_block=256, graph_steps=16, bulk_xcd=0,
-                                                             bulk_fused=0, bulk_rows=1)
+                                                             bulk_fused=0, bulk_rows=1, bulk_runs=0)
     lat.close()
 
 
