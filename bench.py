@@ -185,7 +185,8 @@ def form_precision(B, case, ref, steps_time, layout="compact", steps_long=20000,
     """Every storage form against the FP64 oracle on the full workload, from the
     same initial state: velocity error e_u = max|u - u_oracle| / max|u_oracle| and
     drag error after ref["steps"] steps; the 16-bit forms also against FP32 after
-    steps_long steps (e_u and the mean u_x, the superficial velocity); then
+    steps_long steps (e_u and the mean u_x, the superficial velocity), FP16 with the
+    scale 2^k from the FP32 run's largest deviation after steps_long steps; then
     throughput (graph replay) and the bulk kernel's time and algorithmic bandwidth.
     ref: dict(ux, uy, force, steps) from oracle_reference."""
     import numpy as np
@@ -207,10 +208,11 @@ def form_precision(B, case, ref, steps_time, layout="compact", steps_long=20000,
             r.update(e_u_vs_oracle=e_u((u, v), (uo, vo)),
                      drag_err_vs_oracle=float(abs(fs[0] - fo[0]) / abs(fo[0])))
             if st == "f32":
-                k16 = B.dev_scale_for(B.lbm_max_deviation(lat.ctx))
                 lat.step(steps_long - n)
                 _, ul, vl = lat.moments()
                 long32 = (ul, vl)
+                # the FP16 scale from the largest deviation of the developed flow
+                k16 = B.dev_scale_for(B.lbm_max_deviation(lat.ctx))
             elif st in ("f16", "bf16") and long32 is not None:
                 r["scale_log2"] = kk
                 lat.step(steps_long - n)
@@ -229,6 +231,22 @@ def form_precision(B, case, ref, steps_time, layout="compact", steps_long=20000,
         out[st] = r
         lat.close()
         print(f"[bench] precision {st}: {r}", file=sys.stderr, flush=True)
+    return out
+
+
+def form_mrt_porous(B, threads, steps_oracle=10, steps_time=500, steps_long=2000):
+    """The benchmark workload with the paper's MRT collision (Section 2) in FP32 and
+    FP16 storage: velocity and drag error against the FP64 MRT oracle after
+    steps_oracle steps of the full lattice, FP16 against FP32 after steps_long
+    steps, throughput and the bulk kernel's fraction of the HBM roofline."""
+    from paper_1903_01111_amd import workloads as W
+    case = W.porous_medium()
+    case.collision = "mrt"
+    ux, uy, force, sec, used = oracle_reference(case, steps_oracle, threads)
+    print(f"[bench] MRT oracle: {steps_oracle} steps on {used} threads in {sec:.1f}s", file=sys.stderr, flush=True)
+    out = form_precision(B, case, dict(ux=ux, uy=uy, force=force, steps=steps_oracle), steps_time,
+                         steps_long=steps_long, storages=[("f32", 0), ("f16", None)])
+    out["workload"] = f"{case.name}, MRT (s_e = s_eps = 1.5, s_q = 1.2, s_nu = 1/tau)"
     return out
 
 
@@ -696,7 +714,7 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the storage, batched, cylinder, adjoint and study measurements")
     ap.add_argument("--form", choices=["storage_16bit", "batched", "cylinder", "cylinder_flow", "dense_layout",
-                                       "adjoint", "wall_sweep", "couette", "magnus", "position"],
+                                       "adjoint", "wall_sweep", "couette", "magnus", "position", "mrt_porous"],
                     help="run only this form and print its JSON object")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -742,6 +760,8 @@ def main():
             res = form_magnus(B)
         elif args.form == "position":
             res = form_position(B)
+        elif args.form == "mrt_porous":
+            res = form_mrt_porous(B, threads)
         else:
             res = form_adjoint(B)
         print(json.dumps({"form": args.form, **res}), flush=True)
@@ -870,6 +890,7 @@ def main():
         forms = {}
         if ref is not None:
             forms["storage_16bit"] = form_precision(B, case, ref, 500)
+            forms["mrt_porous"] = form_mrt_porous(B, threads)
         forms["batched"] = form_batched(B, 256, 10000, 20)
         forms["cylinder_2048x512_f32"] = form_single(B, W.cylinder_channel(), 2000, 100)
         forms["cylinder_2048x512_f32"]["note"] = ("75 MB working set: resident in the 256 MB "

@@ -316,7 +316,13 @@ lbm_status lbm_set_kernel_config(lbm_ctx *ctx, const lbm_kernel_config *cfg);
 /* Autotuner: times every bulk shape (block, solid stores, XCD order, rows per wavefront, runs of fluid nodes, fused links) and link block size for steps_per_trial steps
  * on the current state, keeps the fastest, and restores the state (populations,
  * step counter, forces), so results do not depend on having tuned.  Needs host
- * memory for one checkpoint.  chosen and best_ms_per_step may be NULL. */
+ * memory for one checkpoint.  chosen and best_ms_per_step may be NULL.
+ * With the environment variable VIBB_TUNE_CACHE naming a file, a stored choice for
+ * the lattice's key (device architecture, size, boundary, storage, layout,
+ * collision, body force, link and fluid counts) is applied without trials, and a
+ * new choice is appended as one JSON line {"key", "config" (the eight fields of
+ * lbm_kernel_config in order), "ms"}; an unreadable or unwritable file only costs
+ * the trials. */
 lbm_status lbm_autotune(lbm_ctx *ctx, int32_t steps_per_trial, lbm_kernel_config *chosen,
                         double *best_ms_per_step);
 

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -1167,6 +1168,69 @@ lbm_status lbm_set_kernel_config(lbm_ctx *c, const lbm_kernel_config *cfg)
     return LBM_OK;
 }
 
+// Autotune cache: with the environment variable VIBB_TUNE_CACHE naming a file,
+// lbm_autotune first looks for the lattice's key there and applies the stored
+// configuration without timing trials; after a tuning run it appends the choice as
+// one JSON line {"key": "...", "config": [8 ints], "ms": t}.  The key holds what
+// the choice depends on: device architecture, lattice size and boundary, storage,
+// layout, collision, body force, link and fluid counts, moving walls and closures.
+// Every configuration computes the same result, so a stale or foreign entry can
+// only cost speed.  Lines that do not parse are ignored.
+namespace {
+
+std::string tune_key(const lbm_ctx *c)
+{
+    hipDeviceProp_t prop{};
+    const char *arch = hipGetDeviceProperties(&prop, c->p.device) == hipSuccess ? prop.gcnArchName : "unknown";
+    char k[512];
+    std::snprintf(k, sizeof k, "v1:%s:%dx%d:x%d:s%d:l%d:c%d:f%d:n%lld:k%d:o%d:u%d:e%d", arch, c->p.nx, c->p.ny,
+                  c->p.x_bc, c->p.storage, c->p.layout, c->p.collision,
+                  (c->p.gx != 0.0 || c->p.gy != 0.0) ? 1 : 0, (long long)c->n_links, c->n_fluid, c->p.n_obj,
+                  c->has_uw ? 1 : 0, c->has_ext_scheme ? 1 : 0);
+    for (char *q = k; *q; ++q)
+        if (*q == '"' || *q == '\\' || *q == '\n') *q = '_';
+    return k;
+}
+
+bool tune_lookup(const char *path, const std::string &key, lbm_kernel_config *cfg, double *ms)
+{
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    const std::string tag = "{\"key\": \"" + key + "\", \"config\": [";
+    char line[1024];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        if (std::strncmp(line, tag.c_str(), tag.size()) != 0) continue;
+        lbm_kernel_config k{};
+        double t = 0;
+        if (std::sscanf(line + tag.size(), "%d, %d, %d, %d, %d, %d, %d, %d], \"ms\": %lf", &k.bulk_block_x,
+                        &k.bulk_store_solid, &k.link_block, &k.graph_steps, &k.bulk_xcd, &k.bulk_fused, &k.bulk_rows,
+                        &k.bulk_runs, &t) == 9) {
+            *cfg = k;  // the last matching line wins
+            *ms = t;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void tune_store(const char *path, const std::string &key, const lbm_kernel_config &k, double ms)
+{
+    char line[1024];
+    const int n = std::snprintf(line, sizeof line,
+                                "{\"key\": \"%s\", \"config\": [%d, %d, %d, %d, %d, %d, %d, %d], \"ms\": %.6g}\n",
+                                key.c_str(), k.bulk_block_x, k.bulk_store_solid, k.link_block, k.graph_steps,
+                                k.bulk_xcd, k.bulk_fused, k.bulk_rows, k.bulk_runs, ms);
+    if (n <= 0 || n >= (int)sizeof line) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;  // an unwritable cache only costs the next run its trials
+    std::fputs(line, f);  // one write per line (append mode)
+    std::fclose(f);
+}
+
+}  // namespace
+
 // Times every bulk shape and link block size on the current state (steps_per_trial
 // steps each, HIP events on the context's stream), keeps the fastest and restores
 // the state, so the run continues as if no trial had been made.
@@ -1175,6 +1239,18 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps_per_trial, lbm_kernel_config *
 {
     if (!c || steps_per_trial < 1) return LBM_E_ARG;
     if (!c->have_geom || !c->have_init) return c->fail(LBM_E_STATE, "lbm_autotune before initialisation");
+    const char *cache = std::getenv("VIBB_TUNE_CACHE");
+    std::string key;
+    if (cache && *cache) {
+        key = tune_key(c);
+        lbm_kernel_config k{};
+        double ms = 0;
+        if (tune_lookup(cache, key, &k, &ms) && lbm_set_kernel_config(c, &k) == LBM_OK) {
+            if (chosen) *chosen = k;
+            if (best_ms_per_step) *best_ms_per_step = ms;
+            return LBM_OK;
+        }
+    }
     std::vector<char> saved(lbm_state_bytes(c));
     lbm_status s = lbm_get_state(c, saved.data(), saved.size());
     if (s) return s;
@@ -1264,6 +1340,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps_per_trial, lbm_kernel_config *
     if (!r) r = lbm_set_profiling(c, prof ? 1 : 0);
     if (s) return s;
     if (r) return r;
+    if (cache && *cache) tune_store(cache, key, best, best_ms);
     if (chosen) *chosen = best;
     if (best_ms_per_step) *best_ms_per_step = best_ms;
     return LBM_OK;

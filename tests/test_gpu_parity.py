@@ -486,6 +486,42 @@ def test_autotune_restores_the_state(B):
     b.close()
 
 
+def test_autotune_cache(B, tmp_path, monkeypatch):
+    """VIBB_TUNE_CACHE: a tuning run appends its choice for the lattice's key; a
+    later context with the same key applies the stored configuration without
+    trials (a planted entry for the key wins) and computes the same populations."""
+    import json
+    path = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("VIBB_TUNE_CACHE", str(path))
+    case = small_porous(128, 96, seed=13)
+    a = B.Lattice(case, storage="f32", layout="compact")
+    a.step(10)
+    cfg, ms = B.lbm_autotune(a.ctx, 3)
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1
+    entry = json.loads(lines[0])
+    assert entry["config"] == list(cfg.as_dict().values()) and entry["ms"] > 0
+    planted = [128, 0, 512, 8, 0, 0, 1, 0]
+    with open(path, "a") as f:
+        f.write("not json\n" + json.dumps({"key": entry["key"], "config": planted, "ms": 1.0}) + "\n")
+    b = B.Lattice(case, storage="f32", layout="compact")
+    b.step(10)
+    cfg_b, ms_b = B.lbm_autotune(b.ctx, 3)
+    assert list(cfg_b.as_dict().values()) == planted and ms_b == 1.0
+    assert list(B.lbm_get_kernel_config(b.ctx).as_dict().values()) == planted
+    assert len(path.read_text().splitlines()) == 3  # nothing appended
+    a.step(10)
+    b.step(10)
+    assert np.array_equal(a.populations(), b.populations())
+    # another lattice has another key: tuned and appended
+    c = B.Lattice(small_porous(64, 64, seed=3), storage="f32", layout="compact")
+    c.step(4)
+    B.lbm_autotune(c.ctx, 2)
+    assert len(path.read_text().splitlines()) == 4
+    for lat in (a, b, c):
+        lat.close()
+
+
 # --- curved walls: cylindrical Couette convergence on the GPU -------------------
 
 def test_cylindrical_couette_second_order_on_gpu(B):
