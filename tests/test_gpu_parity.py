@@ -441,6 +441,15 @@ def test_moments_device_equal_host_moments(B, storage, layout):
         assert np.array_equal(only.cpu().numpy(), ux)
         with pytest.raises(TypeError):
             B.lbm_moments_device(lat.ctx, d64[0], d32[1], None)
+        # refused before anything is launched: a tensor one element short, a host
+        # tensor, a non-contiguous view (the kernel would write ny*nx values)
+        short = torch.full((case.ny * case.nx - 1,), -7.0, dtype=torch.float64, device=lat.device)
+        for bad in (short, torch.zeros(case.ny, case.nx, dtype=torch.float64),
+                    torch.zeros(case.nx, case.ny, dtype=torch.float64, device=lat.device).t()):
+            with pytest.raises(ValueError):
+                B.lbm_moments_device(lat.ctx, bad, None, None)
+        torch.cuda.synchronize()
+        assert (short == -7.0).all()
         lat.close()
     p = B.make_params(64, 32)
     n = B.lbm_workspace_bytes(p, 10)
