@@ -59,11 +59,11 @@ struct SegBase {
 // Run w of the compact layout is the fluid nodes 64w .. 64w+63 in plane order.
 // Counts before its first node: flagged nodes (side records), links in (node, dir)
 // order and deposited populations; seg is the row segment of its first node; bit j
-// of (flag_hi, flag_lo) is set when node 64w + j is flagged (has a side record).
-// Entry nruns holds the totals.
+// of (flag_hi, flag_lo) is set when node 64w + j is flagged (has a side record);
+// nlinks is the number of links of the run's nodes.  Entry nruns holds the totals.
 struct RunBase {
     int32_t flagged, links, pops, seg;
-    uint32_t flag_lo, flag_hi, pad0, pad1;
+    uint32_t flag_lo, flag_hi, nlinks, pad;
 };
 
 // Data exchanged between the bulk kernel and the link kernel through compact

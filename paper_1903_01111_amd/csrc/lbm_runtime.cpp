@@ -365,6 +365,8 @@ lbm_status prepare_geometry(const lbm_params &p, const uint8_t *mask, int64_t n,
             }
         }
         out->runs.push_back(lbm::RunBase{fl, nl, np, (int32_t)nseg, 0u, 0u, 0u, 0u});
+        for (size_t r = 0; r + 1 < out->runs.size(); ++r)
+            out->runs[r].nlinks = (uint32_t)(out->runs[r + 1].links - out->runs[r].links);
     }
     out->n_pops = npops;
     auto rank_below = [](uint32_t set, int d) { return __builtin_popcount(set & ((1u << (d - 1)) - 1u)); };

@@ -483,6 +483,56 @@ __device__ __forceinline__ void cmp_ranks(const Grid &g, int yu, int sx, int lan
     }
 }
 
+// cmp_ranks in two halves for the run kernel, which loads the tables of several
+// row segments at once (one wait for all of them) before it computes any offsets.
+struct SegRows {
+    uint64_t fm[3];  // fluid bitmasks of the segment in rows y-1, y, y+1
+    int32_t fb[3];   // fluid counts before it in those rows
+};
+
+__device__ __forceinline__ void ld_seg_rows(const Grid &g, int yu, int sx, SegRows &t)
+{
+    const int nsr = g.pitch >> 6;
+    const int rows3[3] = {yu == 0 ? g.ny - 1 : yu - 1, yu, yu == g.ny - 1 ? 0 : yu + 1};
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const int32_t sg = rows3[r] * nsr + sx;
+        t.fm[r] = ld_const(g.fmask + sg);
+        t.fb[r] = ld_const(&g.fseg[sg].fluid);
+    }
+}
+
+// cmp_ranks' offsets of a periodic lattice from tables loaded by ld_seg_rows.
+template <uint32_t S>
+__device__ __forceinline__ void cmp_ranks_from(const Grid &g, const SegRows &t, int yu, int sx, int lane,
+                                               uint32_t (&rk)[3], uint32_t (&lf)[3], uint32_t (&rt)[3])
+{
+    const int nsr = g.pitch >> 6;
+    const int rows3[3] = {yu == 0 ? g.ny - 1 : yu - 1, yu, yu == g.ny - 1 ? 0 : yu + 1};
+    const uint32_t last = (uint32_t)(g.plane - 1) * S;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const uint64_t fm = t.fm[r];
+        rk[r] = S * __builtin_amdgcn_mbcnt_hi((uint32_t)(fm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fm, (uint32_t)t.fb[r]));
+        lf[r] = (rk[r] > S ? rk[r] : S) - S;
+        const uint32_t q = rk[r] + S * (uint32_t)((fm >> lane) & 1ull);
+        rt[r] = q < last ? q : last;
+    }
+    // periodic wrap in x, as in cmp_ranks
+    if (sx == 0 && lane == 0) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const int32_t sg = rows3[r] * nsr + nsr - 1;
+            lf[r] = S * (uint32_t)(ld_const(&g.fseg[sg].fluid) +
+                                    (int32_t)__popcll(ld_const(g.fmask + sg) & ((1ull << ((g.nx - 1) & 63)) - 1ull)));
+        }
+    }
+    if (sx == nsr - 1 && lane == ((g.nx - 1) & 63)) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) rt[r] = S * (uint32_t)ld_const(&g.fseg[rows3[r] * nsr].fluid);
+    }
+}
+
 // The nine pull sources f_i(x, t+1) = f+_i(x - e_i, t) from cmp_ranks' offsets.
 __device__ __forceinline__ void cmp_pull_offsets(const uint32_t (&rk)[3], const uint32_t (&lf)[3],
                                                  const uint32_t (&rt)[3], uint32_t (&o)[9])
@@ -666,8 +716,9 @@ __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
     const int32_t lbase = sb.links + (int32_t)(linc - (uint32_t)popc32(lk));
     // where x - e_i is solid, the link (x, i') with i' = opp(i) (bit i'-1 of the
     // mask word) supplies the population: its load is issued now, while the
-    // side record is still in flight
-    if (FUSE) {
+    // side record is still in flight (with FUSE, or RUN, the wavefront's link
+    // values are already in LDS, in (node, dir) order from entry sb.links on)
+    if (FUSE || RUN) {
         const int32_t lw = sb.links;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -1023,6 +1074,8 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
 // and deposits of a run are contiguous ranges like those of a segment, with bases
 // from the run table.  The open columns are excluded: they are written by their
 // neighbour lanes, which a run may place in another wavefront.
+constexpr int RUN_PRE = 3;  // row segments whose tables a run loads up front
+
 template <int ST, bool FORCE, int COLL>
 __global__ __launch_bounds__(256) void bulk_run_kernel(Grid g, Phys ph, const typename Codec<ST>::T *__restrict__ A,
                                                        typename Codec<ST>::T *__restrict__ B,
@@ -1036,11 +1089,13 @@ __global__ __launch_bounds__(256) void bulk_run_kernel(Grid g, Phys ph, const ty
     using R = typename C::R;
     using T = typename C::T;
     constexpr uint32_t S = sizeof(T);
-    // per wavefront: first the pull offsets of its 64 nodes (9 words each), then
-    // the deposit staging of bulk_finish in the same bytes
+    // per wavefront, in the same bytes one after the other: the pull offsets of its
+    // 64 nodes (9 words each), its link values, the deposit staging of bulk_finish
     constexpr int OFF_BYTES = 9 * 64 * 4;
+    constexpr int LNK_BYTES = 8 * 64 * (int)sizeof(T);  // at most 8 links per node
     constexpr int DEP_BYTES = 64 * (3 * (int)sizeof(R) + 8 * (int)sizeof(T));
-    constexpr int WB = OFF_BYTES > DEP_BYTES ? OFF_BYTES : DEP_BYTES;
+    constexpr int WB0 = OFF_BYTES > DEP_BYTES ? OFF_BYTES : DEP_BYTES;
+    constexpr int WB = WB0 > LNK_BYTES ? WB0 : LNK_BYTES;
     __shared__ __align__(16) unsigned char lds[4 * WB];
     const int tid = threadIdx.x;
     const int64_t nb = gridDim.x;
@@ -1058,7 +1113,8 @@ __global__ __launch_bounds__(256) void bulk_run_kernel(Grid g, Phys ph, const ty
     const int32_t w = __builtin_amdgcn_readfirstlane(blk * 4 + wv);
     if (w >= g.nruns) return;
     const RunBase rb{ld_const(&g.runs[w].flagged), ld_const(&g.runs[w].links), ld_const(&g.runs[w].pops),
-                     ld_const(&g.runs[w].seg), ld_const(&g.runs[w].flag_lo), ld_const(&g.runs[w].flag_hi), 0u, 0u};
+                     ld_const(&g.runs[w].seg), ld_const(&g.runs[w].flag_lo), ld_const(&g.runs[w].flag_hi),
+                     ld_const(&g.runs[w].nlinks), 0u};
     const uint64_t rflag = ((uint64_t)rb.flag_hi << 32) | rb.flag_lo;
     unsigned char *wl = lds + wv * WB;
     uint32_t *lo = reinterpret_cast<uint32_t *>(wl);
@@ -1066,26 +1122,57 @@ __global__ __launch_bounds__(256) void bulk_run_kernel(Grid g, Phys ph, const ty
     const int32_t kend = k0 + 64 < g.n_fluid ? k0 + 64 : g.n_fluid;
     const int nsr = g.pitch >> 6;
     {
-        // walk the row segments of the run; lane = bit of the segment
+        // walk the row segments of the run; lane = bit of the segment.  The tables
+        // of the first RUN_PRE segments are loaded together (a run spans two or
+        // three); a run that reaches beyond them continues one segment at a time.
+        auto emit = [&](const SegRows &t, int yu, int sx) {
+            uint32_t rk[3], lf[3], rt[3], o[9];
+            cmp_ranks_from<S>(g, t, yu, sx, lane, rk, lf, rt);
+            cmp_pull_offsets(rk, lf, rt, o);
+            const int32_t dst = (int32_t)(rk[1] / S) - k0;
+            if (((t.fm[1] >> lane) & 1ull) && dst >= 0 && dst < 64) {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) lo[i * 64 + dst] = o[i];
+            }
+        };
         int yu = rb.seg / nsr;
         int sx = rb.seg - yu * nsr;
-        for (;;) {
-            const int32_t sg = yu * nsr + sx;
-            if (ld_const(&g.fseg[sg].fluid) >= kend) break;  // the sentinel ends the last run
-            const uint64_t fm = ld_const(g.fmask + sg);
-            if (fm) {
-                uint32_t rk[3], lf[3], rt[3], o[9];
-                cmp_ranks<S, false>(g, yu, sx, lane, rk, lf, rt);
-                cmp_pull_offsets(rk, lf, rt, o);
-                const int32_t dst = (int32_t)(rk[1] / S) - k0;
-                if (((fm >> lane) & 1ull) && dst >= 0 && dst < 64) {
+        SegRows tb[RUN_PRE];
+        int yk[RUN_PRE], sk[RUN_PRE];
+        bool in[RUN_PRE];
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) lo[i * 64 + dst] = o[i];
-                }
-            }
+        for (int k = 0; k < RUN_PRE; ++k) {
+            yk[k] = yu;
+            sk[k] = sx;
+            in[k] = yu < g.ny;
+            if (in[k]) ld_seg_rows(g, yu, sx, tb[k]);
             if (++sx == nsr) {
                 sx = 0;
                 ++yu;
+            }
+        }
+        bool more = true;
+#pragma unroll
+        for (int k = 0; k < RUN_PRE; ++k) {
+            if (!more || !in[k] || tb[k].fb[1] >= kend) {
+                more = false;
+            } else if (tb[k].fm[1]) {
+                emit(tb[k], yk[k], sk[k]);
+            }
+        }
+        // (yu, sx) is the segment after the preloaded ones: at most the sentinel
+        // when the last preloaded one was inside the lattice
+        if (more && in[RUN_PRE - 1]) {
+            for (;;) {
+                const int32_t sg = yu * nsr + sx;
+                if (ld_const(&g.fseg[sg].fluid) >= kend) break;  // the sentinel ends the last run
+                SegRows t;
+                ld_seg_rows(g, yu, sx, t);
+                if (t.fm[1]) emit(t, yu, sx);
+                if (++sx == nsr) {
+                    sx = 0;
+                    ++yu;
+                }
             }
         }
     }
@@ -1096,7 +1183,8 @@ __global__ __launch_bounds__(256) void bulk_run_kernel(Grid g, Phys ph, const ty
     uint32_t o[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) o[i] = live ? lo[i * 64 + lane] : 0u;
-    // every lane has read its offsets before the bytes are reused for the deposits
+    // every lane has read its offsets before the bytes are reused for the link
+    // values and the deposits
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1105,16 +1193,28 @@ __global__ __launch_bounds__(256) void bulk_run_kernel(Grid g, Phys ph, const ty
     // the node type: fluid, flagged from the run table; its link directions come
     // from its side record in bulk_finish
     pl.m = live ? (((rflag >> lane) & 1ull) ? (mask_t)MASK_SIDE : (mask_t)0) : (mask_t)MASK_SOLID;
+    // The run's link values are L entries [rb.links, rb.links + nl): loaded as a
+    // contiguous range before the pulls, so that they do not wait for the side
+    // records that say which node takes which; staged in LDS for bulk_finish.
+    const int32_t nl = (int32_t)rb.nlinks;
+    const T *Lv = static_cast<const T *>(side.L);
+    T *ll = reinterpret_cast<T *>(wl);
+    T l0{}, l1{};
+    if (lane < nl) l0 = Lv[rb.links + lane];
+    if (lane + 64 < nl) l1 = Lv[rb.links + 64 + lane];
     const int64_t P = g.plane;
 #pragma unroll
     for (int i = 0; i < 9; ++i) pl.a[i] = C::reg(ld_at_nt(A + i * P, o[i]));
+    if (lane < nl) ll[lane] = l0;
+    if (lane + 64 < nl) ll[64 + lane] = l1;
+    for (int j = 128 + lane; j < nl; j += 64) ll[j] = Lv[rb.links + j];  // more than 128 links (rare)
     pl.own = (uint32_t)(k0 + lane) * S;
     pl.own_in = 0;
     pl.own_out = 0;
     __builtin_amdgcn_sched_barrier(0);
     bulk_finish<ST, false, FORCE, 256, false, true, false, COLL, true>(
         g, ph, B, mask, nullptr, side, live ? 0 : g.nx, 0, 0, reinterpret_cast<R(*)[3 * 64]>(wl),
-        reinterpret_cast<T(*)[8 * 64]>(wl + 64 * 3 * sizeof(R)), pl, nullptr, nullptr,
+        reinterpret_cast<T(*)[8 * 64]>(wl + 64 * 3 * sizeof(R)), pl, nullptr, reinterpret_cast<T(*)[8 * 64]>(wl),
         SegBase{rb.flagged, rb.links, rb.pops, 0});
 }
 
