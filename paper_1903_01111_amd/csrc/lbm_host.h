@@ -44,6 +44,7 @@ struct Prepared {
     std::vector<lbm::SegBase> seg;         // per 64-node row segment, plus a sentinel with the totals
     std::vector<uint64_t> fmask;           // per segment: its fluid nodes (bit = lane)
     std::vector<lbm::RunBase> runs;        // per run of 64 fluid nodes, plus a sentinel with the totals
+    std::vector<lbm::SegRow> frow;         // per segment: fmask and fluid base in one record, plus a sentinel
     int32_t n_fluid = 0;
     int64_t n_pops = 0;
     bool has_uw = false;

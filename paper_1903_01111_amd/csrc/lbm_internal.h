@@ -14,6 +14,7 @@ namespace lbm {
 // 64 elements, so a 64-lane wavefront reads one aligned run of a row.
 struct SegBase;
 struct RunBase;
+struct SegRow;
 
 // With compact set, plane i holds only the fluid nodes, the k-th fluid node in
 // (y, x) order at offset k: a node's offset is the fluid count before its
@@ -26,6 +27,7 @@ struct Grid {
     const SegBase *fseg;    // [ny * pitch / 64] (compact layout)
     const uint64_t *fmask;  // [ny * pitch / 64] (compact layout)
     const RunBase *runs;    // [nruns + 1] (compact layout): see RunBase
+    const SegRow *frow;     // [ny * pitch / 64 + 1] (compact layout): fmask and fseg.fluid in one record
     int32_t nruns;          // runs of 64 fluid nodes: ceil(n_fluid / 64)
     int32_t n_fluid;
 };
@@ -61,6 +63,13 @@ struct SegBase {
 // order and deposited populations; seg is the row segment of its first node; bit j
 // of (flag_hi, flag_lo) is set when node 64w + j is flagged (has a side record);
 // nlinks is the number of links of the run's nodes.  Entry nruns holds the totals.
+// A row segment's fluid bitmask and the fluid count before it, in one 16-byte
+// record (one scalar load); entry ny * pitch / 64 holds the total fluid count.
+struct SegRow {
+    uint32_t fm_lo, fm_hi;
+    int32_t fluid, pad;
+};
+
 struct RunBase {
     int32_t flagged, links, pops, seg;
     uint32_t flag_lo, flag_hi, nlinks, pad;

@@ -66,6 +66,7 @@ Layout make_layout(const lbm_params &p, int64_t max_links)
     L.off_fmask = take((size_t)(L.pitch / 64) * p.ny * sizeof(uint64_t));
     // runs of 64 fluid nodes: at most one per segment, plus the sentinel
     L.off_runs = take(((size_t)(L.pitch / 64) * p.ny + 1) * sizeof(lbm::RunBase));
+    L.off_frow = take(((size_t)(L.pitch / 64) * p.ny + 1) * sizeof(lbm::SegRow));
     const size_t nl = (size_t)std::max<int64_t>(max_links, 0);
     L.off_meta = take(nl * 4);
     L.off_q = take(nl * rb);
@@ -347,6 +348,11 @@ lbm_status prepare_geometry(const lbm_params &p, const uint8_t *mask, int64_t n,
     }
     // sentinel after the last segment: the totals
     out->seg.push_back(lbm::SegBase{(int32_t)out->rec.size(), nlinks, npops, nfluid});
+    out->frow.resize((size_t)nseg + 1);
+    for (int64_t sg = 0; sg <= nseg; ++sg) {
+        const uint64_t fm = sg < nseg ? out->fmask[sg] : 0;
+        out->frow[sg] = lbm::SegRow{(uint32_t)fm, (uint32_t)(fm >> 32), out->seg[sg].fluid, 0};
+    }
     // runs of 64 fluid nodes in plane order: the counts before each run's first node
     out->n_fluid = nfluid;
     out->runs.clear();
@@ -735,7 +741,8 @@ lbm_status lbm_set_geometry(lbm_ctx *c, const uint8_t *mask, int64_t n_links, co
                {c->lay.off_pbase, prep.pbase.data(), K * 4},
                {c->lay.off_seg, prep.seg.data(), prep.seg.size() * sizeof(lbm::SegBase)},
                {c->lay.off_fmask, prep.fmask.data(), prep.fmask.size() * sizeof(uint64_t)},
-               {c->lay.off_runs, prep.runs.data(), prep.runs.size() * sizeof(lbm::RunBase)}};
+               {c->lay.off_runs, prep.runs.data(), prep.runs.size() * sizeof(lbm::RunBase)},
+               {c->lay.off_frow, prep.frow.data(), prep.frow.size() * sizeof(lbm::SegRow)}};
     for (const Up &u : ups)
         if (u.bytes && (s = c->hip(hipMemcpyAsync(c->ws + u.off, u.src, u.bytes,
                                                   hipMemcpyHostToDevice, st), "link upload")))

@@ -496,9 +496,9 @@ __device__ __forceinline__ void ld_seg_rows(const Grid &g, int yu, int sx, SegRo
     const int rows3[3] = {yu == 0 ? g.ny - 1 : yu - 1, yu, yu == g.ny - 1 ? 0 : yu + 1};
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-        const int32_t sg = rows3[r] * nsr + sx;
-        t.fm[r] = ld_const(g.fmask + sg);
-        t.fb[r] = ld_const(&g.fseg[sg].fluid);
+        const SegRow q = ld_const_record(g.frow + rows3[r] * nsr + sx);
+        t.fm[r] = ((uint64_t)q.fm_hi << 32) | q.fm_lo;
+        t.fb[r] = q.fluid;
     }
 }
 
@@ -522,14 +522,14 @@ __device__ __forceinline__ void cmp_ranks_from(const Grid &g, const SegRows &t, 
     if (sx == 0 && lane == 0) {
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
-            const int32_t sg = rows3[r] * nsr + nsr - 1;
-            lf[r] = S * (uint32_t)(ld_const(&g.fseg[sg].fluid) +
-                                    (int32_t)__popcll(ld_const(g.fmask + sg) & ((1ull << ((g.nx - 1) & 63)) - 1ull)));
+            const SegRow q = ld_const_record(g.frow + rows3[r] * nsr + nsr - 1);
+            const uint64_t fm = ((uint64_t)q.fm_hi << 32) | q.fm_lo;
+            lf[r] = S * (uint32_t)(q.fluid + (int32_t)__popcll(fm & ((1ull << ((g.nx - 1) & 63)) - 1ull)));
         }
     }
     if (sx == nsr - 1 && lane == ((g.nx - 1) & 63)) {
 #pragma unroll
-        for (int r = 0; r < 3; ++r) rt[r] = S * (uint32_t)ld_const(&g.fseg[rows3[r] * nsr].fluid);
+        for (int r = 0; r < 3; ++r) rt[r] = S * (uint32_t)ld_const(&g.frow[rows3[r] * nsr].fluid);
     }
 }
 
@@ -1165,7 +1165,7 @@ __global__ __launch_bounds__(256) void bulk_run_kernel(Grid g, Phys ph, const ty
         if (more && in[RUN_PRE - 1]) {
             for (;;) {
                 const int32_t sg = yu * nsr + sx;
-                if (ld_const(&g.fseg[sg].fluid) >= kend) break;  // the sentinel ends the last run
+                if (ld_const(&g.frow[sg].fluid) >= kend) break;  // the sentinel ends the last run
                 SegRows t;
                 ld_seg_rows(g, yu, sx, t);
                 if (t.fm[1]) emit(t, yu, sx);
