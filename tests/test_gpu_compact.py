@@ -113,6 +113,62 @@ def test_runs_mrt_and_xcd_order(B, xcd):
     _same(_run(B, case, "f32", "compact", 40, cfg=_runs_cfg(B, xcd)), _run(B, case, "f32", "dense", 40))
 
 
+def _islands(nx=192, ny=24, seed=4):
+    """Fluid pairs (x % 3 != 2) on every other row, all else solid: 6 or 7 halfway
+    bounce-back links per fluid node (x_ff is solid), over 400 links per run of 64
+    fluid nodes, so the run kernel takes its path for more than 128 link values."""
+    import numpy as np
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    mask = np.where((xx % 3 != 2) & (yy % 2 == 0), 0, 1).astype(np.uint8)
+    ex = [0, 1, 0, -1, 0, 1, -1, -1, 1]
+    ey = [0, 0, 1, 0, -1, 1, 1, -1, -1]
+    node, d = [], []
+    for y, x in zip(*np.nonzero(mask == 0)):
+        for i in range(1, 9):
+            if mask[(y + ey[i]) % ny, (x + ex[i]) % nx]:
+                node.append(y * nx + x)
+                d.append(i)
+    n = len(node)
+    rng = np.random.default_rng(seed)
+    geo = (mask, np.array(node, np.int32), np.array(d, np.int8), rng.uniform(0.2, 0.9, n), None,
+           np.zeros(n, np.int32), None)
+    case = W.Case("islands", nx, ny, False, 0.8, gx=1e-5, gy=-3e-6)
+    case.init_ux = np.where(mask == 0, 1e-3 * rng.standard_normal((ny, nx)), 0.0)
+    case.init_uy = np.where(mask == 0, 1e-3 * rng.standard_normal((ny, nx)), 0.0)
+    return case, geo
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_runs_with_many_links_per_run(B, storage):
+    case, geo = _islands()
+    out = []
+    for layout, cfg in (("compact", _runs_cfg(B)), ("compact", None), ("dense", None)):
+        lat = B.Lattice(case, storage=storage, layout=layout, geometry=geo)
+        if cfg is not None:
+            B.lbm_set_kernel_config(lat.ctx, cfg)
+        lat.step(21)
+        out.append((lat.populations(), lat.moments(), [lat.force(0)], lat.mass()))
+        lat.close()
+    print(f"[compact] runs islands {storage}: {len(geo[1])} links", flush=True)
+    _same(out[0], out[1])
+    _same(out[0], out[2])
+
+
+def test_runs_on_a_lattice_without_fluid(B):
+    """No fluid node: no run, the launch only clears the force bank."""
+    import numpy as np
+    case = W.Case("solid", 70, 9, False, 0.8, gx=1e-5)
+    geo = (np.ones((9, 70), np.uint8), np.zeros(0, np.int32), np.zeros(0, np.int8), np.zeros(0), None,
+           np.zeros(0, np.int32), None)
+    lat = B.Lattice(case, storage="f32", layout="compact", geometry=geo)
+    B.lbm_set_kernel_config(lat.ctx, _runs_cfg(B))
+    lat.step(5)
+    assert lat.mass() == 0.0
+    _, s, n = lat.force(0)
+    assert n == 5 and not np.any(s)
+    lat.close()
+
+
 def test_runs_refused_where_unsupported(B):
     for name, layout in (("cylinder_open", "compact"), ("porous_48x40", "dense")):
         lat = B.Lattice(CASES[name](), storage="f32", layout=layout)
