@@ -113,6 +113,22 @@ def test_runs_mrt_and_xcd_order(B, xcd):
     _same(_run(B, case, "f32", "compact", 40, cfg=_runs_cfg(B, xcd)), _run(B, case, "f32", "dense", 40))
 
 
+@pytest.mark.parametrize("collision", ["bgk", "mrt"])
+def test_runs_with_moving_walls_and_all_closures(B, collision):
+    """Spinning and translating discs on a ragged periodic lattice, one object with
+    Bouzidi and one with Yu (deposits of f+_i(x_f) for both), the Galilean-invariant
+    force: runs give the populations of the row segments and of the dense layout
+    bitwise (the dense layout is checked against the oracle elsewhere)."""
+    from test_gpu_parity import spinning
+    case = spinning()
+    case.scheme_of_obj = [W.SCHEME_BOUZIDI, W.SCHEME_YU]
+    case.gi_mea = True
+    case.collision = collision
+    print(f"[compact] runs closures {collision}", flush=True)
+    _same(_run(B, case, "f32", "compact", 60, cfg=_runs_cfg(B)), _run(B, case, "f32", "compact", 60))
+    _same(_run(B, case, "f64", "compact", 60, cfg=_runs_cfg(B)), _run(B, case, "f64", "dense", 60))
+
+
 def _islands(nx=192, ny=24, seed=4):
     """Fluid pairs (x % 3 != 2) on every other row, all else solid: 6 or 7 halfway
     bounce-back links per fluid node (x_ff is solid), over 400 links per run of 64
