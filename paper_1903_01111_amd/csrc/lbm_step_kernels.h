@@ -58,9 +58,10 @@ __device__ __forceinline__ void link_load_record(const Links &L, int32_t k, Link
     a.sf = ld_at_nt(L.sf, o4);
     a.sff = ld_at_nt(L.sff, o4);
     a.pff = ld_at_nt(L.pff, o4);
-    // f+_i(x_f) of the outgoing direction: Bouzidi (q > 1/2) and Yu links only
-    a.pfi = L.pfi ? ld_at_nt(L.pfi, o4) : a.pf;
     a.q = ld_at_nt(static_cast<const R *>(L.q), (uint32_t)k * (uint32_t)sizeof(R));
+    // f+_i(x_f) of the outgoing direction: Bouzidi (q > 1/2) and Yu links only;
+    // -1 (pf is meant) when no link needs it, so that nothing waits for pf here
+    a.pfi = L.pfi ? ld_at_nt(L.pfi, o4) : -1;
     a.uwx = a.uwy = R(0);
     if (L.uw) {
         const R *u = static_cast<const R *>(L.uw);
@@ -82,7 +83,7 @@ __device__ __forceinline__ void link_load_deposits(const void *Mv, const void *P
     const int32_t sffc = a.sff < 0 ? a.sf : a.sff, pffc = a.sff < 0 ? a.pf : a.pff;
     a.pfv = P[a.pf];
     a.pffv = P[pffc];
-    a.pfiv = P[a.pfi];
+    a.pfiv = P[a.pfi < 0 ? a.pf : a.pfi];
     a.drf = M[3 * (int64_t)a.sf];
     a.ufx = M[3 * (int64_t)a.sf + 1];
     a.ufy = M[3 * (int64_t)a.sf + 2];
