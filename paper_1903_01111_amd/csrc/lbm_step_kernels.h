@@ -1075,20 +1075,17 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
 // and deposits of a run are contiguous ranges like those of a segment, with bases
 // from the run table.  The open columns are excluded: they are written by their
 // neighbour lanes, which a run may place in another wavefront.
-constexpr int RUN_PRE = 3;  // row segments whose tables a run loads up front
-
 // At most 96 scalar registers: the preloaded tables push the MRT instantiations to
 // 98, which leaves room for 7 wavefronts per SIMD instead of 8 (its bulk kernel
 // took 178 us against 167 us with the cap, two registers spilled to vector lanes).
+constexpr int RUN_PRE = 3;  // row segments whose tables a run loads up front
 
 template <int ST, bool FORCE, int COLL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(96))) void bulk_run_kernel(Grid g, Phys ph, const typename Codec<ST>::T *__restrict__ A,
-                                                       typename Codec<ST>::T *__restrict__ B,
-                                                       const mask_t *__restrict__ mask, Side side,
-                                                       double *__restrict__ zero_bank, int32_t n_zero, int32_t xcd,
-                                                       const double2 *__restrict__ red_part,
-                                                       const int32_t *__restrict__ red_obj, int64_t red_n,
-                                                       double *__restrict__ red_bank, double *__restrict__ red_sum)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(96))) void bulk_run_kernel(
+    Grid g, Phys ph, const typename Codec<ST>::T *__restrict__ A, typename Codec<ST>::T *__restrict__ B,
+    const mask_t *__restrict__ mask, Side side, double *__restrict__ zero_bank, int32_t n_zero, int32_t xcd,
+    const double2 *__restrict__ red_part, const int32_t *__restrict__ red_obj, int64_t red_n,
+    double *__restrict__ red_bank, double *__restrict__ red_sum)
 {
     using C = Codec<ST>;
     using R = typename C::R;
