@@ -48,11 +48,12 @@ def bulk_kernel_name(kcfg, layout, storage, coll=0):
     """Template name of the periodic forced bulk kernel (the porous workload) that a
     launch configuration runs (None for the fused form); coll 0 BGK, 1 MRT.  With
     bulk_runs the wavefronts take runs of fluid nodes (compact layout only)."""
-    if kcfg["bulk_fused"]:
-        return None
     st = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3, "f32w": 4, "f32p": 5}[storage]
     if kcfg.get("bulk_runs"):
-        return f"void bulk_run_kernel<{st}, true, {coll}>" if layout == "compact" else None
+        fused = "true" if kcfg["bulk_fused"] else "false"
+        return f"void bulk_run_kernel<{st}, true, {coll}, {fused}>" if layout == "compact" else None
+    if kcfg["bulk_fused"]:
+        return None
     b = lambda v: "true" if v else "false"
     return (f"void bulk_kernel<{st}, false, true, {kcfg['bulk_block_x']}, {b(kcfg['bulk_store_solid'])}, "
             f"{b(layout == 'compact')}, {max(kcfg.get('bulk_rows', 1), 1)}, {coll}>")

@@ -298,15 +298,16 @@ typedef struct {
                                  cache lines stay in one L2; 0: hardware order */
     int32_t bulk_fused;       /* 1: the bulk kernel evaluates the links of its own nodes (one
                                  launch per step plus the force reduction); needs bulk_block_x
-                                 256; 0: a separate link kernel */
+                                 256, and BGK unless bulk_runs; 0: a separate link kernel */
     int32_t bulk_rows;        /* row segments per bulk wavefront: 2 issues the second one's loads
                                  before the first is finished (needs bulk_block_x 256 and
                                  bulk_fused 0); 1 (or 0): one */
     int32_t bulk_runs;        /* 1: each bulk wavefront takes a run of 64 consecutive fluid nodes
                                  instead of a 64-node row segment, so every lane holds a node and
                                  the planes are written in whole cache lines (compact layout,
-                                 periodic in x, bulk_fused 0; bulk_block_x, bulk_store_solid and
-                                 bulk_rows do not apply); 0: row segments */
+                                 periodic in x; bulk_block_x, bulk_store_solid and bulk_rows do not
+                                 apply; with bulk_fused the run evaluates its own links, BGK or
+                                 MRT); 0: row segments */
 } lbm_kernel_config;
 
 lbm_status lbm_get_kernel_config(const lbm_ctx *ctx, lbm_kernel_config *cfg);

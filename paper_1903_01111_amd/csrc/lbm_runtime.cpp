@@ -1165,13 +1165,14 @@ lbm_status lbm_set_kernel_config(lbm_ctx *c, const lbm_kernel_config *cfg)
         cfg->link_block < 64 || cfg->link_block > 1024 || cfg->link_block % 64 ||
         cfg->graph_steps < 2 || cfg->graph_steps > 1024 || cfg->graph_steps % 2)
         return c->fail(LBM_E_ARG, "lbm_set_kernel_config: unsupported configuration");
-    if (c->p.collision == LBM_COLLISION_MRT && (bx != 256 || cfg->bulk_fused))
-        return c->fail(LBM_E_ARG, "lbm_set_kernel_config: MRT runs with bulk_block_x 256 and bulk_fused 0");
+    if (c->p.collision == LBM_COLLISION_MRT && (bx != 256 || (cfg->bulk_fused && !cfg->bulk_runs)))
+        return c->fail(LBM_E_ARG, "lbm_set_kernel_config: MRT runs with bulk_block_x 256, and fused only with "
+                                  "bulk_runs");
     if (cfg->bulk_runs != 0 && cfg->bulk_runs != 1)
         return c->fail(LBM_E_ARG, "lbm_set_kernel_config: bulk_runs must be 0 or 1");
-    if (cfg->bulk_runs && (c->p.layout != LBM_LAYOUT_COMPACT || c->p.x_bc == LBM_X_OPEN || cfg->bulk_fused))
-        return c->fail(LBM_E_ARG, "lbm_set_kernel_config: bulk_runs needs the compact layout, a periodic x "
-                                  "direction and bulk_fused 0");
+    if (cfg->bulk_runs && (c->p.layout != LBM_LAYOUT_COMPACT || c->p.x_bc == LBM_X_OPEN))
+        return c->fail(LBM_E_ARG, "lbm_set_kernel_config: bulk_runs needs the compact layout and a periodic x "
+                                  "direction");
     c->drop_graph();
     c->kcfg = *cfg;
     return LBM_OK;
@@ -1342,6 +1343,20 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps_per_trial, lbm_kernel_config *
             if ((s = trial(k, &ms))) break;
             if (ms < best_ms) best_ms = ms, best = k;
         }
+    // links inside the run kernel (compact layout, periodic in x)
+    for (int xo : {0, 1}) {
+        if (s || c->p.layout != LBM_LAYOUT_COMPACT || c->p.x_bc == LBM_X_OPEN) break;
+        lbm_kernel_config k = unfused;
+        k.bulk_fused = 1;
+        k.bulk_runs = 1;
+        k.bulk_rows = 1;
+        k.bulk_block_x = 256;
+        k.bulk_store_solid = 0;
+        k.bulk_xcd = xo;
+        double ms;
+        if ((s = trial(k, &ms))) break;
+        if (ms < best_ms) best_ms = ms, best = k;
+    }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     lbm_status r = lbm_set_kernel_config(c, s ? &base : &best);

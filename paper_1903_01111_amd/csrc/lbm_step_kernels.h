@@ -1080,10 +1080,13 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
 // took 178 us against 167 us with the cap, two registers spilled to vector lanes).
 constexpr int RUN_PRE = 3;  // row segments whose tables a run loads up front
 
-template <int ST, bool FORCE, int COLL>
+// With FUSE the wavefront also evaluates the links of its nodes (from the previous
+// step's deposits; no link kernel) and leaves one force partial per run in fa.
+template <int ST, bool FORCE, int COLL, bool FUSE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(96))) void bulk_run_kernel(
     Grid g, Phys ph, const typename Codec<ST>::T *__restrict__ A, typename Codec<ST>::T *__restrict__ B,
-    const mask_t *__restrict__ mask, Side side, double *__restrict__ zero_bank, int32_t n_zero, int32_t xcd,
+    const mask_t *__restrict__ mask, Side side, FuseArgs fa, double *__restrict__ zero_bank, int32_t n_zero,
+    int32_t xcd,
     const double2 *__restrict__ red_part, const int32_t *__restrict__ red_obj, int64_t red_n,
     double *__restrict__ red_bank, double *__restrict__ red_sum)
 {
@@ -1118,6 +1121,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(96))) void bulk
                      ld_const(&g.runs[w].seg), ld_const(&g.runs[w].flag_lo), ld_const(&g.runs[w].flag_hi),
                      ld_const(&g.runs[w].nlinks), 0u};
     const uint64_t rflag = ((uint64_t)rb.flag_hi << 32) | rb.flag_lo;
+    const int32_t nl = (int32_t)rb.nlinks;
+    // FUSE: the run's links are entries [rb.links, rb.links + nl) of the (node, dir)
+    // order; the first 64, one per lane, have their records loaded now and the
+    // deposits they point to with the pulls
+    LinkIn<ST> la;
+    const bool hl = FUSE && lane < nl;
+    if (hl) link_load_record<ST>(fa.L, fa.L.li_ident ? rb.links + lane : ld_el(fa.L.kof, rb.links + lane), la);
     unsigned char *wl = lds + wv * WB;
     uint32_t *lo = reinterpret_cast<uint32_t *>(wl);
     const int32_t k0 = w * 64;
@@ -1198,18 +1208,56 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(96))) void bulk
     // The run's link values are L entries [rb.links, rb.links + nl): loaded as a
     // contiguous range before the pulls, so that they do not wait for the side
     // records that say which node takes which; staged in LDS for bulk_finish.
-    const int32_t nl = (int32_t)rb.nlinks;
+    // With FUSE they are evaluated here instead.
     const T *Lv = static_cast<const T *>(side.L);
     T *ll = reinterpret_cast<T *>(wl);
     T l0{}, l1{};
-    if (lane < nl) l0 = Lv[rb.links + lane];
-    if (lane + 64 < nl) l1 = Lv[rb.links + 64 + lane];
+    if constexpr (FUSE) {
+        if (hl) link_load_deposits<ST>(side.M, side.P, la);
+    } else {
+        if (lane < nl) l0 = Lv[rb.links + lane];
+        if (lane + 64 < nl) l1 = Lv[rb.links + 64 + lane];
+    }
     const int64_t P = g.plane;
 #pragma unroll
     for (int i = 0; i < 9; ++i) pl.a[i] = C::reg(ld_at_nt(A + i * P, o[i]));
-    if (lane < nl) ll[lane] = l0;
-    if (lane + 64 < nl) ll[64 + lane] = l1;
-    for (int j = 128 + lane; j < nl; j += 64) ll[j] = Lv[rb.links + j];  // more than 128 links (rare)
+    if constexpr (FUSE) {
+        double fx = 0.0, fy = 0.0;
+        int obj = -1;
+        if (hl) ll[lane] = C::st(link_value<ST>(ph, la, fx, fy, obj), ph.scale);
+        for (int j = 64 + lane; j < nl; j += 64) {  // more than 64 links
+            const int32_t kk = fa.L.li_ident ? rb.links + j : ld_el(fa.L.kof, rb.links + j);
+            double lfx, lfy;
+            int o2;
+            ll[j] = C::st(link_eval<ST>(ph, fa.L, side.M, side.P, kk, lfx, lfy, o2), ph.scale);
+            if (obj < 0 || o2 == obj) {
+                obj = o2;
+                fx += lfx;
+                fy += lfy;
+            } else {
+                add_force(fa.bank, fa.fsum, o2, lfx, lfy);
+            }
+        }
+        // the run's force: one partial (entry w) when its links belong to one
+        // object, else added per lane
+        int top = obj;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) top = max(top, __shfl_xor(top, off));
+        if (__all(obj == top || obj < 0)) {
+            const double sx = wave_sum_to_last(fx), sy = wave_sum_to_last(fy);
+            if (lane == 63) {
+                fa.wpart[w] = make_double2(sx, sy);
+                fa.wobj[w] = top;
+            }
+        } else {
+            if (obj >= 0) add_force(fa.bank, fa.fsum, obj, fx, fy);
+            if (lane == 0) fa.wobj[w] = -1;
+        }
+    } else {
+        if (lane < nl) ll[lane] = l0;
+        if (lane + 64 < nl) ll[64 + lane] = l1;
+        for (int j = 128 + lane; j < nl; j += 64) ll[j] = Lv[rb.links + j];  // more than 128 links (rare)
+    }
     pl.own = (uint32_t)(k0 + lane) * S;
     pl.own_in = 0;
     pl.own_out = 0;
@@ -1530,14 +1578,28 @@ hipError_t bulk_fused_shape(const Grid &g, const Phys &ph, const void *A, void *
     return bulk_fused_t<ST, OPEN, FORCE, false, false>(g, ph, A, B, mask, uin, side, fa, zb, nz, cf.xcd, s);
 }
 
-// The fused form (links inside the bulk kernel) runs the BGK collision only.
+template <int ST, bool FORCE, int COLL, bool FUSE>
+hipError_t bulk_run_t(const Grid &g, const Phys &ph, const void *A, void *B, const mask_t *mask, const Side &side,
+                      const FuseArgs &fa, double *zb, int32_t nz, int32_t xcd, hipStream_t s, const ForceReduce &fr);
+
+// The fused form (links inside the bulk kernel): BGK in the row-segment mapping,
+// BGK or MRT in runs of fluid nodes.
 template <int ST>
 hipError_t bulk_fused_dispatch(const Grid &g, const Phys &ph, const void *A, void *B, const mask_t *mask,
                                const void *uin, const Side &side, const FuseArgs &fa, double *zb, int32_t nz,
                                const BulkConfig &cf, hipStream_t s)
 {
-    if (ph.coll != LBM_COLLISION_BGK) return hipErrorInvalidValue;
     const bool force = ph.gx != 0.0 || ph.gy != 0.0;
+    if (cf.runs) {
+        // runs of fluid nodes (BGK or MRT)
+        const ForceReduce none{};
+#define LBM_RUNF(FV, CV) bulk_run_t<ST, FV, CV, true>(g, ph, A, B, mask, side, fa, zb, nz, cf.xcd, s, none)
+        if (ph.coll == LBM_COLLISION_MRT) return force ? LBM_RUNF(true, 1) : LBM_RUNF(false, 1);
+        if (ph.coll == LBM_COLLISION_BGK) return force ? LBM_RUNF(true, 0) : LBM_RUNF(false, 0);
+#undef LBM_RUNF
+        return hipErrorInvalidValue;
+    }
+    if (ph.coll != LBM_COLLISION_BGK) return hipErrorInvalidValue;
     if (g.x_open)
         return force ? bulk_fused_shape<ST, true, true>(g, ph, A, B, mask, uin, side, fa, zb, nz, cf, s)
                      : bulk_fused_shape<ST, true, false>(g, ph, A, B, mask, uin, side, fa, zb, nz, cf, s);
@@ -1593,9 +1655,9 @@ hipError_t bulk_shape(const Grid &g, const Phys &ph, const void *A, void *B, con
     return hipErrorInvalidValue;
 }
 
-template <int ST, bool FORCE, int COLL>
+template <int ST, bool FORCE, int COLL, bool FUSE>
 hipError_t bulk_run_t(const Grid &g, const Phys &ph, const void *A, void *B, const mask_t *mask, const Side &side,
-                      double *zb, int32_t nz, int32_t xcd, hipStream_t s, const ForceReduce &fr)
+                      const FuseArgs &fa, double *zb, int32_t nz, int32_t xcd, hipStream_t s, const ForceReduce &fr)
 {
     using C = Codec<ST>;
     if (!g.compact || g.x_open || !g.runs || g.nruns < 0) return hipErrorInvalidValue;
@@ -1605,9 +1667,16 @@ hipError_t bulk_run_t(const Grid &g, const Phys &ph, const void *A, void *B, con
     int64_t nb = ((int64_t)g.nruns + 3) / 4;
     if (nb * per_block < fr.nw) nb = (fr.nw + per_block - 1) / per_block;
     if (nb < 1) nb = 1;
-    hipLaunchKernelGGL((bulk_run_kernel<ST, FORCE, COLL>), dim3((unsigned)nb), dim3(256), 0, s, g, ph,
-                       static_cast<const typename C::T *>(A), static_cast<typename C::T *>(B), mask, side, zb, nz,
-                       xcd, fr.wpart, fr.wobj, fr.nw, fr.bank, fr.fsum);
+    hipLaunchKernelGGL((bulk_run_kernel<ST, FORCE, COLL, FUSE>), dim3((unsigned)nb), dim3(256), 0, s, g, ph,
+                       static_cast<const typename C::T *>(A), static_cast<typename C::T *>(B), mask, side, fa, zb,
+                       nz, xcd, fr.wpart, fr.wobj, fr.nw, fr.bank, fr.fsum);
+    hipError_t e = hipGetLastError();
+    if (!FUSE || e != hipSuccess || g.nruns == 0) return e;
+    // the fused form's force partials, one per run
+    const int64_t nw = g.nruns;
+    const int64_t lanes = (nw + REDUCE_CHUNK - 1) / REDUCE_CHUNK;
+    hipLaunchKernelGGL(force_reduce_kernel, dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, s, fa.wpart,
+                       fa.wobj, nw, fa.bank, fa.fsum);
     return hipGetLastError();
 }
 
@@ -1618,8 +1687,8 @@ hipError_t bulk_coll(const Grid &g, const Phys &ph, const void *A, void *B, cons
 {
     const bool force = ph.gx != 0.0 || ph.gy != 0.0;
     if (cf.runs)
-        return force ? bulk_run_t<ST, true, COLL>(g, ph, A, B, mask, side, zb, nz, cf.xcd, s, fr)
-                     : bulk_run_t<ST, false, COLL>(g, ph, A, B, mask, side, zb, nz, cf.xcd, s, fr);
+        return force ? bulk_run_t<ST, true, COLL, false>(g, ph, A, B, mask, side, FuseArgs{}, zb, nz, cf.xcd, s, fr)
+                     : bulk_run_t<ST, false, COLL, false>(g, ph, A, B, mask, side, FuseArgs{}, zb, nz, cf.xcd, s, fr);
     if (g.x_open)
         return force ? bulk_shape<ST, true, true, COLL>(g, ph, A, B, mask, uin, side, zb, nz, cf, s, fr)
                      : bulk_shape<ST, true, false, COLL>(g, ph, A, B, mask, uin, side, zb, nz, cf, s, fr);

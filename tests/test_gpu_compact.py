@@ -56,7 +56,10 @@ def _run(B, case, storage, layout, n, k=0, cfg=None):
     return f, (rho, ux, uy), forces, mass
 
 
-def _same(a, b):
+def _same(a, b, fscale=None):
+    """Bitwise populations and moments; forces (summed in another order) within
+    1e-12 of the larger of the sum and fscale (the size of the terms summed, where
+    they cancel)."""
     fa, ma, Fa, mass_a = a
     fb, mb, Fb, mass_b = b
     assert np.array_equal(fa, fb)
@@ -64,7 +67,7 @@ def _same(a, b):
         assert np.array_equal(x, y)
     for (la, sa, na), (lb, sb, nb) in zip(Fa, Fb):
         assert na == nb
-        assert np.abs(sa - sb).max() <= 1e-12 * max(np.abs(sb).max(), 1e-30)
+        assert np.abs(sa - sb).max() <= 1e-12 * max(np.abs(sb).max(), fscale or 0.0, 1e-30)
     assert abs(mass_a - mass_b) <= 1e-12 * abs(mass_b)
 
 
@@ -183,6 +186,50 @@ def test_runs_on_a_lattice_without_fluid(B):
     _, s, n = lat.force(0)
     assert n == 5 and not np.any(s)
     lat.close()
+
+
+FUSED_CASES = {
+    "porous_200x64": lambda: CASES["porous_200x64"](),
+    "porous_100x37": lambda: CASES["porous_100x37"](),
+    "channel_200x34": lambda: W.perturb(W.poiseuille_channel(nx=200), seed=5),
+    "spinning_closures_mrt": lambda: _closures_case("mrt"),
+}
+
+
+def _closures_case(collision):
+    from test_gpu_parity import spinning
+    case = spinning()
+    case.scheme_of_obj = [W.SCHEME_BOUZIDI, W.SCHEME_YU]
+    case.gi_mea = True
+    case.collision = collision
+    return case
+
+
+@pytest.mark.parametrize("name", list(FUSED_CASES))
+@pytest.mark.parametrize("storage", ["f32", "f16", "f64"])
+def test_runs_with_fused_links(B, name, storage):
+    """Links evaluated inside the run kernel (bulk_fused with bulk_runs): bitwise the
+    populations of the separate link kernel, forces to the summation order."""
+    case = FUSED_CASES[name]()
+    k = 12 if storage == "f16" else 0
+    fused = B.lbm_kernel_config(256, 0, 256, 16, 1, 1, 1, 1)
+    print(f"[compact] runs fused {name} {storage}", flush=True)
+    a = _run(B, case, storage, "compact", 41, k, cfg=fused)
+    # the partial sums run over the links of each run instead of each 64 links: the
+    # wall forces of a channel cancel in y, so the scale is that of one wall's force
+    _same(a, _run(B, case, storage, "compact", 41, k, cfg=_runs_cfg(B)), fscale=41 * case.nx / 9.0)
+
+
+def test_runs_with_fused_links_many_per_run(B):
+    case, geo = _islands()
+    out = []
+    for cfg in (B.lbm_kernel_config(256, 0, 256, 16, 0, 1, 1, 1), _runs_cfg(B)):
+        lat = B.Lattice(case, storage="f32", layout="compact", geometry=geo)
+        B.lbm_set_kernel_config(lat.ctx, cfg)
+        lat.step(21)
+        out.append((lat.populations(), lat.moments(), [lat.force(0)], lat.mass()))
+        lat.close()
+    _same(out[0], out[1], fscale=21 * len(geo[1]) / 9.0)
 
 
 def test_runs_refused_where_unsupported(B):
