@@ -47,11 +47,13 @@ def kernel_hash():
 def bulk_kernel_name(kcfg, layout, storage, coll=0):
     """Template name of the periodic forced bulk kernel (the porous workload) that a
     launch configuration runs (None for the fused form); coll 0 BGK, 1 MRT.  With
-    bulk_runs the wavefronts take runs of fluid nodes (compact layout only)."""
+    bulk_runs the wavefronts take runs of fluid nodes (compact layout only), with
+    bulk_runs 2 reading neighbour words."""
     st = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3, "f32w": 4, "f32p": 5}[storage]
     if kcfg.get("bulk_runs"):
         fused = "true" if kcfg["bulk_fused"] else "false"
-        return f"void bulk_run_kernel<{st}, true, {coll}, {fused}>" if layout == "compact" else None
+        nbr = "true" if kcfg["bulk_runs"] == 2 else "false"
+        return f"void bulk_run_kernel<{st}, true, {coll}, {fused}, {nbr}>" if layout == "compact" else None
     if kcfg["bulk_fused"]:
         return None
     b = lambda v: "true" if v else "false"

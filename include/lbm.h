@@ -307,7 +307,13 @@ typedef struct {
                                  the planes are written in whole cache lines (compact layout,
                                  periodic in x; bulk_block_x, bulk_store_solid and bulk_rows do not
                                  apply; with bulk_fused the run evaluates its own links, BGK or
-                                 MRT); 0: row segments */
+                                 MRT); 2: runs whose lanes read their pull offsets from a
+                                 per-node neighbour word built with the geometry (4 bytes per
+                                 fluid node) instead of walking the row segments, refused with
+                                 LBM_E_ARG before a geometry is set or when the first and last
+                                 row and column hold more fluid nodes than the table's room (a
+                                 later geometry without the words turns 2 into 1);
+                                 0: row segments */
 } lbm_kernel_config;
 
 lbm_status lbm_get_kernel_config(const lbm_ctx *ctx, lbm_kernel_config *cfg);

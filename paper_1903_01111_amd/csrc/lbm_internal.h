@@ -30,6 +30,12 @@ struct Grid {
     const SegRow *frow;     // [ny * pitch / 64 + 1] (compact layout): fmask and fseg.fluid in one record
     int32_t nruns;          // runs of 64 fluid nodes: ceil(n_fluid / 64)
     int32_t n_fluid;
+    // per fluid node (compact layout, periodic x): the fluid ranks of (x, y-1) and
+    // (x, y+1) relative to the node's own, biased by 16384 in bits 0-14 and 16-30,
+    // whether those nodes are fluid in bits 15 and 31; bits 0-14 zero: the node's nine
+    // pull offsets (elements) are entry word >> 15 of nbr_slow
+    const uint32_t *nbr;
+    const uint32_t *nbr_slow;
 };
 
 struct Phys {

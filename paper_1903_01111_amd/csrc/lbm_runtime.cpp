@@ -67,6 +67,10 @@ Layout make_layout(const lbm_params &p, int64_t max_links)
     // runs of 64 fluid nodes: at most one per segment, plus the sentinel
     L.off_runs = take(((size_t)(L.pitch / 64) * p.ny + 1) * sizeof(lbm::RunBase));
     L.off_frow = take(((size_t)(L.pitch / 64) * p.ny + 1) * sizeof(lbm::SegRow));
+    // neighbour words: one per fluid node, and nine offsets per node of the first and
+    // last row and column
+    L.off_nbr = take((size_t)L.pitch * p.ny * sizeof(uint32_t));
+    L.off_nbrs = take(((size_t)2 * L.pitch + 2 * (size_t)p.ny) * 9 * sizeof(uint32_t));
     const size_t nl = (size_t)std::max<int64_t>(max_links, 0);
     L.off_meta = take(nl * 4);
     L.off_q = take(nl * rb);
@@ -373,6 +377,61 @@ lbm_status prepare_geometry(const lbm_params &p, const uint8_t *mask, int64_t n,
         out->runs.push_back(lbm::RunBase{fl, nl, np, (int32_t)nseg, 0u, 0u, 0u, 0u});
         for (size_t r = 0; r + 1 < out->runs.size(); ++r)
             out->runs[r].nlinks = (uint32_t)(out->runs[r + 1].links - out->runs[r].links);
+    }
+    // Neighbour words for runs that read their pull offsets instead of computing
+    // them from the segment tables (periodic x only; the x-open layout has no runs):
+    // per fluid node k at (x, y), the fluid ranks of (x, y-1) and (x, y+1) relative
+    // to k and whether those nodes are fluid, or, for the nodes of the first and last
+    // row and column (periodic wraps) and any rank difference beyond 15 bits, an
+    // index into a table of their nine pull offsets.
+    out->nbr.clear();
+    out->nbr_slow.clear();
+    if (p.x_bc != LBM_X_OPEN && p.layout == LBM_LAYOUT_COMPACT) {
+        const int64_t nsr = pitch / 64;
+        auto fluid_at = [&](int xx, int yy) { return !(out->mask[(size_t)yy * pitch + xx] & lbm::MASK_SOLID); };
+        // rank of (x, r): fluid nodes before it in plane order
+        auto rank = [&](int xx, int yy) -> int64_t {
+            const int64_t sg = yy * nsr + xx / 64;
+            return out->seg[sg].fluid + __builtin_popcountll(out->fmask[sg] & ((1ull << (xx & 63)) - 1ull));
+        };
+        const int64_t last = make_layout(p, 0).plane;  // the plane's element count bounds every offset
+        out->nbr.reserve((size_t)nfluid);
+        int64_t k = 0;
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                if (!fluid_at(x, y)) continue;
+                const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+                const int64_t rm = rank(x, ym), rp = rank(x, yp);
+                const int64_t dm = rm - k, dp = rp - k;
+                const bool slow = y == 0 || y == ny - 1 || x == 0 || x == nx - 1 || dm < -16383 || dm > 16383 ||
+                                  dp < -16383 || dp > 16383;
+                if (!slow) {
+                    out->nbr.push_back((uint32_t)(dm + 16384) | ((uint32_t)fluid_at(x, ym) << 15) |
+                                       ((uint32_t)(dp + 16384) << 16) | ((uint32_t)fluid_at(x, yp) << 31));
+                } else {
+                    // the nine offsets as the segment walk computes them (elements)
+                    const int64_t idx = (int64_t)out->nbr_slow.size() / 9;
+                    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+                    const int rows[3] = {ym, y, yp};
+                    int64_t rk[3], lf[3], rt[3];
+                    for (int r = 0; r < 3; ++r) {
+                        rk[r] = rank(x, rows[r]);
+                        lf[r] = x == 0 ? rank(xm, rows[r]) : std::max<int64_t>(rk[r] - 1, 0);
+                        rt[r] = x == nx - 1 ? rank(xp, rows[r])
+                                            : std::min<int64_t>(rk[r] + (fluid_at(x, rows[r]) ? 1 : 0), last - 1);
+                    }
+                    const int64_t o9[9] = {rk[1], lf[1], rk[0], rt[1], rk[2], lf[0], rt[0], rt[2], lf[2]};
+                    for (int i = 0; i < 9; ++i) out->nbr_slow.push_back((uint32_t)o9[i]);
+                    out->nbr.push_back((uint32_t)idx << 15);  // low 15 bits zero: a table entry
+                }
+                ++k;
+            }
+        // table entries beyond the workspace's room (the first and last row and column)
+        // or beyond 17 bits of index: no neighbour words
+        if ((int64_t)out->nbr_slow.size() / 9 > std::min<int64_t>(2 * (int64_t)pitch + 2 * ny, (1 << 17) - 1)) {
+            out->nbr.clear();
+            out->nbr_slow.clear();
+        }
     }
     out->n_pops = npops;
     auto rank_below = [](uint32_t set, int d) { return __builtin_popcount(set & ((1u << (d - 1)) - 1u)); };
@@ -742,7 +801,9 @@ lbm_status lbm_set_geometry(lbm_ctx *c, const uint8_t *mask, int64_t n_links, co
                {c->lay.off_seg, prep.seg.data(), prep.seg.size() * sizeof(lbm::SegBase)},
                {c->lay.off_fmask, prep.fmask.data(), prep.fmask.size() * sizeof(uint64_t)},
                {c->lay.off_runs, prep.runs.data(), prep.runs.size() * sizeof(lbm::RunBase)},
-               {c->lay.off_frow, prep.frow.data(), prep.frow.size() * sizeof(lbm::SegRow)}};
+               {c->lay.off_frow, prep.frow.data(), prep.frow.size() * sizeof(lbm::SegRow)},
+               {c->lay.off_nbr, prep.nbr.data(), prep.nbr.size() * sizeof(uint32_t)},
+               {c->lay.off_nbrs, prep.nbr_slow.data(), prep.nbr_slow.size() * sizeof(uint32_t)}};
     for (const Up &u : ups)
         if (u.bytes && (s = c->hip(hipMemcpyAsync(c->ws + u.off, u.src, u.bytes,
                                                   hipMemcpyHostToDevice, st), "link upload")))
@@ -772,6 +833,8 @@ lbm_status lbm_set_geometry(lbm_ctx *c, const uint8_t *mask, int64_t n_links, co
     c->n_moment_nodes = (int64_t)prep.rec.size();
     c->n_fluid = prep.n_fluid;
     c->nruns = (int32_t)prep.runs.size() - 1;
+    c->has_nbr = !prep.nbr.empty() || prep.n_fluid == 0;
+    if (c->kcfg.bulk_runs == 2 && !c->has_nbr) c->kcfg.bulk_runs = 1;  // offsets from the segment tables
     c->has_uw = prep.has_uw;
     c->has_pfi = prep.has_pfi;
     c->has_ext_scheme = prep.has_ext_scheme;
@@ -1168,11 +1231,15 @@ lbm_status lbm_set_kernel_config(lbm_ctx *c, const lbm_kernel_config *cfg)
     if (c->p.collision == LBM_COLLISION_MRT && (bx != 256 || (cfg->bulk_fused && !cfg->bulk_runs)))
         return c->fail(LBM_E_ARG, "lbm_set_kernel_config: MRT runs with bulk_block_x 256, and fused only with "
                                   "bulk_runs");
-    if (cfg->bulk_runs != 0 && cfg->bulk_runs != 1)
-        return c->fail(LBM_E_ARG, "lbm_set_kernel_config: bulk_runs must be 0 or 1");
+    if (cfg->bulk_runs < 0 || cfg->bulk_runs > 2)
+        return c->fail(LBM_E_ARG, "lbm_set_kernel_config: bulk_runs must be 0, 1 or 2");
     if (cfg->bulk_runs && (c->p.layout != LBM_LAYOUT_COMPACT || c->p.x_bc == LBM_X_OPEN))
         return c->fail(LBM_E_ARG, "lbm_set_kernel_config: bulk_runs needs the compact layout and a periodic x "
                                   "direction");
+    if (cfg->bulk_runs == 2 && !c->has_nbr)
+        return c->fail(LBM_E_ARG, "lbm_set_kernel_config: bulk_runs 2 needs the neighbour words of a geometry "
+                                  "(set one first; not built when the first and last row and column hold too "
+                                  "many fluid nodes)");
     c->drop_graph();
     c->kcfg = *cfg;
     return LBM_OK;
@@ -1305,20 +1372,23 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps_per_trial, lbm_kernel_config *
                     if ((s = trial(k, &ms))) break;
                     if (ms < best_ms) best_ms = ms, best = k;
                 }
-    // runs of 64 fluid nodes per wavefront (compact layout, periodic in x)
-    for (int xo : {0, 1}) {
-        if (s || c->p.layout != LBM_LAYOUT_COMPACT || c->p.x_bc == LBM_X_OPEN) break;
-        lbm_kernel_config k = best;
-        k.bulk_block_x = 256;
-        k.bulk_store_solid = 0;
-        k.bulk_xcd = xo;
-        k.bulk_fused = 0;
-        k.bulk_rows = 1;
-        k.bulk_runs = 1;
-        double ms;
-        if ((s = trial(k, &ms))) break;
-        if (ms < best_ms) best_ms = ms, best = k;
-    }
+    // runs of 64 fluid nodes per wavefront (compact layout, periodic in x), with
+    // offsets from the segment tables or from the neighbour words
+    for (int ru : {1, 2})
+        for (int xo : {0, 1}) {
+            if (s || c->p.layout != LBM_LAYOUT_COMPACT || c->p.x_bc == LBM_X_OPEN) break;
+            if (ru == 2 && !c->has_nbr) break;
+            lbm_kernel_config k = best;
+            k.bulk_block_x = 256;
+            k.bulk_store_solid = 0;
+            k.bulk_xcd = xo;
+            k.bulk_fused = 0;
+            k.bulk_rows = 1;
+            k.bulk_runs = ru;
+            double ms;
+            if ((s = trial(k, &ms))) break;
+            if (ms < best_ms) best_ms = ms, best = k;
+        }
     for (int lb : {128, 256, 512, 1024}) {
         if (s) break;
         lbm_kernel_config k = best;
@@ -1343,12 +1413,13 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps_per_trial, lbm_kernel_config *
             if ((s = trial(k, &ms))) break;
             if (ms < best_ms) best_ms = ms, best = k;
         }
-    // links inside the run kernel (compact layout, periodic in x)
+    // links inside the run kernel (compact layout, periodic in x), with the run
+    // form the unfused trials chose
     for (int xo : {0, 1}) {
         if (s || c->p.layout != LBM_LAYOUT_COMPACT || c->p.x_bc == LBM_X_OPEN) break;
         lbm_kernel_config k = unfused;
         k.bulk_fused = 1;
-        k.bulk_runs = 1;
+        k.bulk_runs = unfused.bulk_runs ? unfused.bulk_runs : 1;
         k.bulk_rows = 1;
         k.bulk_block_x = 256;
         k.bulk_store_solid = 0;

@@ -1082,7 +1082,9 @@ constexpr int RUN_PRE = 3;  // row segments whose tables a run loads up front
 
 // With FUSE the wavefront also evaluates the links of its nodes (from the previous
 // step's deposits; no link kernel) and leaves one force partial per run in fa.
-template <int ST, bool FORCE, int COLL, bool FUSE>
+// With NBR each lane reads its node's neighbour word (g.nbr) instead of the
+// wavefront walking the row segments: no segment tables, no LDS exchange.
+template <int ST, bool FORCE, int COLL, bool FUSE, bool NBR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(96))) void bulk_run_kernel(
     Grid g, Phys ph, const typename Codec<ST>::T *__restrict__ A, typename Codec<ST>::T *__restrict__ B,
     const mask_t *__restrict__ mask, Side side, FuseArgs fa, double *__restrict__ zero_bank, int32_t n_zero,
@@ -1133,6 +1135,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(96))) void bulk
     const int32_t k0 = w * 64;
     const int32_t kend = k0 + 64 < g.n_fluid ? k0 + 64 : g.n_fluid;
     const int nsr = g.pitch >> 6;
+    const bool live = k0 + lane < kend;
+    uint32_t o[9];
+    if constexpr (NBR) {
+        // the node's ranks in rows y-1 and y+1 from its neighbour word, as the
+        // segment walk below would compute them; the first and last row and
+        // column (periodic wraps) read their nine offsets from a table
+        const int32_t k = live ? k0 + lane : 0;
+        const uint32_t wd = live ? ld_at_nt(g.nbr, (uint32_t)k * 4u) : 1u;
+        if ((wd & 0x7fffu) == 0u) {
+            const uint32_t e = (wd >> 15) * 9u;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) o[i] = ld_el(g.nbr_slow, (int32_t)(e + i)) * S;
+        } else {
+            const uint32_t last = (uint32_t)(g.plane - 1) * S;
+            const int32_t dm = (int32_t)(wd & 0x7fffu) - 16384, dp = (int32_t)((wd >> 16) & 0x7fffu) - 16384;
+            const uint32_t rk[3] = {(uint32_t)(k + dm) * S, (uint32_t)k * S, (uint32_t)(k + dp) * S};
+            const uint32_t fl3[3] = {(wd >> 15) & 1u, 1u, wd >> 31};
+            uint32_t lf[3], rt[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                lf[r] = (rk[r] > S ? rk[r] : S) - S;
+                const uint32_t q = rk[r] + S * fl3[r];
+                rt[r] = q < last ? q : last;
+            }
+            cmp_pull_offsets(rk, lf, rt, o);
+        }
+        if (!live) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) o[i] = 0u;
+        }
+    } else {
     {
         // walk the row segments of the run; lane = bit of the segment.  The tables
         // of the first RUN_PRE segments are loaded together (a run spans two or
@@ -1191,10 +1224,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(96))) void bulk
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const bool live = k0 + lane < kend;
-    uint32_t o[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) o[i] = live ? lo[i * 64 + lane] : 0u;
+    }  // NBR
     // every lane has read its offsets before the bytes are reused for the link
     // values and the deposits
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1580,7 +1612,8 @@ hipError_t bulk_fused_shape(const Grid &g, const Phys &ph, const void *A, void *
 
 template <int ST, bool FORCE, int COLL, bool FUSE>
 hipError_t bulk_run_t(const Grid &g, const Phys &ph, const void *A, void *B, const mask_t *mask, const Side &side,
-                      const FuseArgs &fa, double *zb, int32_t nz, int32_t xcd, hipStream_t s, const ForceReduce &fr);
+                      const FuseArgs &fa, double *zb, int32_t nz, int32_t xcd, bool nbr, hipStream_t s,
+                      const ForceReduce &fr);
 
 // The fused form (links inside the bulk kernel): BGK in the row-segment mapping,
 // BGK or MRT in runs of fluid nodes.
@@ -1593,7 +1626,7 @@ hipError_t bulk_fused_dispatch(const Grid &g, const Phys &ph, const void *A, voi
     if (cf.runs) {
         // runs of fluid nodes (BGK or MRT)
         const ForceReduce none{};
-#define LBM_RUNF(FV, CV) bulk_run_t<ST, FV, CV, true>(g, ph, A, B, mask, side, fa, zb, nz, cf.xcd, s, none)
+#define LBM_RUNF(FV, CV) bulk_run_t<ST, FV, CV, true>(g, ph, A, B, mask, side, fa, zb, nz, cf.xcd, cf.runs == 2, s, none)
         if (ph.coll == LBM_COLLISION_MRT) return force ? LBM_RUNF(true, 1) : LBM_RUNF(false, 1);
         if (ph.coll == LBM_COLLISION_BGK) return force ? LBM_RUNF(true, 0) : LBM_RUNF(false, 0);
 #undef LBM_RUNF
@@ -1657,19 +1690,26 @@ hipError_t bulk_shape(const Grid &g, const Phys &ph, const void *A, void *B, con
 
 template <int ST, bool FORCE, int COLL, bool FUSE>
 hipError_t bulk_run_t(const Grid &g, const Phys &ph, const void *A, void *B, const mask_t *mask, const Side &side,
-                      const FuseArgs &fa, double *zb, int32_t nz, int32_t xcd, hipStream_t s, const ForceReduce &fr)
+                      const FuseArgs &fa, double *zb, int32_t nz, int32_t xcd, bool nbr, hipStream_t s,
+                      const ForceReduce &fr)
 {
     using C = Codec<ST>;
     if (!g.compact || g.x_open || !g.runs || g.nruns < 0) return hipErrorInvalidValue;
+    if (nbr && !g.nbr) return hipErrorInvalidValue;  // no neighbour words for this geometry
     // four runs per block; at least enough blocks for the force partials and one
     // to clear the force bank
     constexpr int64_t per_block = 256 * FOLD_CHUNK;
     int64_t nb = ((int64_t)g.nruns + 3) / 4;
     if (nb * per_block < fr.nw) nb = (fr.nw + per_block - 1) / per_block;
     if (nb < 1) nb = 1;
-    hipLaunchKernelGGL((bulk_run_kernel<ST, FORCE, COLL, FUSE>), dim3((unsigned)nb), dim3(256), 0, s, g, ph,
-                       static_cast<const typename C::T *>(A), static_cast<typename C::T *>(B), mask, side, fa, zb,
-                       nz, xcd, fr.wpart, fr.wobj, fr.nw, fr.bank, fr.fsum);
+    if (nbr)
+        hipLaunchKernelGGL((bulk_run_kernel<ST, FORCE, COLL, FUSE, true>), dim3((unsigned)nb), dim3(256), 0, s, g,
+                           ph, static_cast<const typename C::T *>(A), static_cast<typename C::T *>(B), mask, side, fa,
+                           zb, nz, xcd, fr.wpart, fr.wobj, fr.nw, fr.bank, fr.fsum);
+    else
+        hipLaunchKernelGGL((bulk_run_kernel<ST, FORCE, COLL, FUSE, false>), dim3((unsigned)nb), dim3(256), 0, s, g,
+                           ph, static_cast<const typename C::T *>(A), static_cast<typename C::T *>(B), mask, side, fa,
+                           zb, nz, xcd, fr.wpart, fr.wobj, fr.nw, fr.bank, fr.fsum);
     hipError_t e = hipGetLastError();
     if (!FUSE || e != hipSuccess || g.nruns == 0) return e;
     // the fused form's force partials, one per run
@@ -1687,8 +1727,10 @@ hipError_t bulk_coll(const Grid &g, const Phys &ph, const void *A, void *B, cons
 {
     const bool force = ph.gx != 0.0 || ph.gy != 0.0;
     if (cf.runs)
-        return force ? bulk_run_t<ST, true, COLL, false>(g, ph, A, B, mask, side, FuseArgs{}, zb, nz, cf.xcd, s, fr)
-                     : bulk_run_t<ST, false, COLL, false>(g, ph, A, B, mask, side, FuseArgs{}, zb, nz, cf.xcd, s, fr);
+        return force ? bulk_run_t<ST, true, COLL, false>(g, ph, A, B, mask, side, FuseArgs{}, zb, nz, cf.xcd,
+                                                         cf.runs == 2, s, fr)
+                     : bulk_run_t<ST, false, COLL, false>(g, ph, A, B, mask, side, FuseArgs{}, zb, nz, cf.xcd,
+                                                          cf.runs == 2, s, fr);
     if (g.x_open)
         return force ? bulk_shape<ST, true, true, COLL>(g, ph, A, B, mask, uin, side, zb, nz, cf, s, fr)
                      : bulk_shape<ST, true, false, COLL>(g, ph, A, B, mask, uin, side, zb, nz, cf, s, fr);

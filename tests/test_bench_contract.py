@@ -33,11 +33,14 @@ def test_bulk_kernel_names_follow_the_templates():
     assert bench.bulk_kernel_name(_cfg(bulk_rows=2), "compact", "bf16").endswith(", 2, 0>")
     assert bench.bulk_kernel_name(_cfg(), "compact", "f32", coll=1).endswith(", 1, 1>")
     assert bench.bulk_kernel_name(_cfg(bulk_fused=1), "compact", "f32") is None
-    assert bench.bulk_kernel_name(_cfg(bulk_runs=1), "compact", "f32") == "void bulk_run_kernel<1, true, 0, false>"
+    assert bench.bulk_kernel_name(_cfg(bulk_runs=1), "compact", "f32") == \
+        "void bulk_run_kernel<1, true, 0, false, false>"
     assert bench.bulk_kernel_name(_cfg(bulk_runs=1), "compact", "bf16", coll=1) == \
-        "void bulk_run_kernel<3, true, 1, false>"
+        "void bulk_run_kernel<3, true, 1, false, false>"
     assert bench.bulk_kernel_name(_cfg(bulk_runs=1, bulk_fused=1), "compact", "f32") == \
-        "void bulk_run_kernel<1, true, 0, true>"
+        "void bulk_run_kernel<1, true, 0, true, false>"
+    assert bench.bulk_kernel_name(_cfg(bulk_runs=2), "compact", "f32") == \
+        "void bulk_run_kernel<1, true, 0, false, true>"
     assert bench.bulk_kernel_name(_cfg(bulk_runs=1), "dense", "f32") is None
 
 

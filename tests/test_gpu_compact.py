@@ -232,12 +232,103 @@ def test_runs_with_fused_links_many_per_run(B):
     _same(out[0], out[1], fscale=21 * len(geo[1]) / 9.0)
 
 
+def _nbr_cfg(B, xcd=1, fused=0):
+    return B.lbm_kernel_config(256, 0, 256, 16, xcd, fused, 1, 2)
+
+
+@pytest.mark.parametrize("name", PERIODIC + ["channel_200x34"])
+@pytest.mark.parametrize("storage", ["f32", "f64", "f16"])
+def test_neighbour_words_equal_the_segment_walk(B, name, storage):
+    """Runs whose lanes read their pull offsets from neighbour words (bulk_runs 2)
+    give bitwise the populations of the runs that walk the row segments: the words
+    hold the same ranks, and the first and last row and column (the periodic wraps,
+    all of the 1-wide column) read theirs from the table."""
+    case = CASES[name]() if name in CASES else W.perturb(W.poiseuille_channel(nx=200), seed=5)
+    k = 12 if storage == "f16" else 0
+    print(f"[compact] neighbour words {name} {storage}", flush=True)
+    _same(_run(B, case, storage, "compact", 37, k, cfg=_nbr_cfg(B)),
+          _run(B, case, storage, "compact", 37, k, cfg=_runs_cfg(B)))
+
+
+@pytest.mark.parametrize("collision", ["bgk", "mrt"])
+def test_neighbour_words_with_closures_and_fused_links(B, collision):
+    """Moving walls, Bouzidi and Yu objects, the Galilean-invariant force: neighbour
+    words equal the segment walk, with the links in a separate kernel and inside the
+    run kernel (whose force partials are then summed in the same order)."""
+    case = _closures_case(collision)
+    print(f"[compact] neighbour words closures {collision}", flush=True)
+    _same(_run(B, case, "f32", "compact", 60, cfg=_nbr_cfg(B, 0)), _run(B, case, "f32", "compact", 60,
+                                                                          cfg=_runs_cfg(B, 0)))
+    _same(_run(B, case, "f32", "compact", 60, cfg=_nbr_cfg(B, 1, fused=1)),
+          _run(B, case, "f32", "compact", 60, cfg=B.lbm_kernel_config(256, 0, 256, 16, 1, 1, 1, 1)))
+
+
+def test_neighbour_words_with_many_links_and_without_fluid(B):
+    case, geo = _islands()
+    out = []
+    for cfg in (_nbr_cfg(B), _runs_cfg(B)):
+        lat = B.Lattice(case, storage="f32", layout="compact", geometry=geo)
+        B.lbm_set_kernel_config(lat.ctx, cfg)
+        lat.step(21)
+        out.append((lat.populations(), lat.moments(), [lat.force(0)], lat.mass()))
+        lat.close()
+    _same(out[0], out[1])
+    solid = W.Case("solid", 70, 9, False, 0.8, gx=1e-5)
+    geo = (np.ones((9, 70), np.uint8), np.zeros(0, np.int32), np.zeros(0, np.int8), np.zeros(0), None,
+           np.zeros(0, np.int32), None)
+    lat = B.Lattice(solid, storage="f32", layout="compact", geometry=geo)
+    B.lbm_set_kernel_config(lat.ctx, _nbr_cfg(B))
+    lat.step(5)
+    assert lat.mass() == 0.0
+    lat.close()
+
+
+def _wide(fluid_cols):
+    """A 16448 x 5 periodic lattice whose columns x < fluid_cols are fluid, the rest
+    solid, with halfway links (q = 1/2) wherever a fluid node pulls from a solid one."""
+    nx, ny = 16448, 5
+    mask = np.ones((ny, nx), np.uint8)
+    mask[:, :fluid_cols] = 0
+    ex = [0, 1, 0, -1, 0, 1, -1, -1, 1]
+    ey = [0, 0, 1, 0, -1, 1, 1, -1, -1]
+    node, d = [], []
+    for y, x in zip(*np.nonzero(mask == 0)):
+        for i in range(1, 9):
+            if mask[(y + ey[i]) % ny, (x + ex[i]) % nx]:
+                node.append(y * nx + x)
+                d.append(i)
+    n = len(node)
+    geo = (mask, np.array(node, np.int32), np.array(d, np.int8), np.full(n, 0.5), None, np.zeros(n, np.int32),
+           None)
+    return W.Case("wide", nx, ny, False, 0.8), geo
+
+
+def test_neighbour_words_absent_for_wide_rows(B):
+    """Rows of more than 16383 fluid nodes put the rank differences of every interior
+    node beyond the word's 15 bits and the table beyond its room: no words, so
+    bulk_runs 2 is refused, and a geometry set later without words turns it into 1."""
+    case, narrow = _wide(1000)
+    lat = B.Lattice(case, storage="f32", layout="compact", geometry=narrow)
+    B.lbm_set_kernel_config(lat.ctx, _nbr_cfg(B))
+    assert B.lbm_get_kernel_config(lat.ctx).bulk_runs == 2
+    _, full = _wide(16448)
+    B.lbm_set_geometry(lat.ctx, *full)
+    B.lbm_init_equilibrium(lat.ctx)
+    assert B.lbm_get_kernel_config(lat.ctx).bulk_runs == 1
+    with pytest.raises(B.LbmError) as e:
+        B.lbm_set_kernel_config(lat.ctx, _nbr_cfg(B))
+    assert e.value.status == B.LBM_E_ARG
+    lat.step(2)
+    lat.close()
+
+
 def test_runs_refused_where_unsupported(B):
     for name, layout in (("cylinder_open", "compact"), ("porous_48x40", "dense")):
         lat = B.Lattice(CASES[name](), storage="f32", layout=layout)
-        with pytest.raises(B.LbmError) as e:
-            B.lbm_set_kernel_config(lat.ctx, _runs_cfg(B))
-        assert e.value.status == B.LBM_E_ARG
+        for cfg in (_runs_cfg(B), _nbr_cfg(B)):
+            with pytest.raises(B.LbmError) as e:
+                B.lbm_set_kernel_config(lat.ctx, cfg)
+            assert e.value.status == B.LBM_E_ARG
         lat.close()
 
 
