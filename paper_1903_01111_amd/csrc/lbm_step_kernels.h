@@ -369,6 +369,45 @@ __device__ __forceinline__ void force_reduce_part(const double2 *__restrict__ wp
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int popc32(uint32_t v) { return __popc(v); }
 
+// LDS access by a 32-bit byte address (the low half of a flat pointer into LDS),
+// for the walks below that advance an address by one element per set bit: a bit
+// test, a compare and one address update per direction.  opaque() hides a value
+// from the optimiser, which would otherwise re-derive the address from a count.
+template <class T>
+__device__ __forceinline__ uint32_t lds_addr(const T *p)
+{
+    return (uint32_t)(uintptr_t)p;
+}
+template <int N>
+using uint_of = std::conditional_t<N == 2, uint16_t, std::conditional_t<N == 4, uint32_t, uint64_t>>;
+template <class T>
+__device__ __forceinline__ T lds_ld(uint32_t a)
+{
+    using U = uint_of<sizeof(T)>;
+    return __builtin_bit_cast(T, *(const __attribute__((address_space(3))) U *)(uintptr_t)a);
+}
+template <class T>
+__device__ __forceinline__ void lds_st(uint32_t a, T v)
+{
+    using U = uint_of<sizeof(T)>;
+    *(__attribute__((address_space(3))) U *)(uintptr_t)a = __builtin_bit_cast(U, v);
+}
+__device__ __forceinline__ uint32_t opaque(uint32_t v)
+{
+    asm("" : "+v"(v));
+    return v;
+}
+
+// e_i . (x, y) without products by 0 or +-1 (i is a constant once the direction
+// loops are unrolled): the same value as CX[i] x + CY[i] y, up to the sign of a
+// zero result.
+template <class A>
+__device__ __forceinline__ A edot(int i, A x, A y)
+{
+    const A sx = CX[i] > 0 ? x : -x, sy = CY[i] > 0 ? y : -y;
+    return CX[i] == 0 ? (CY[i] == 0 ? A(0) : sy) : (CY[i] == 0 ? sx : sx + sy);
+}
+
 // MRT collision (Section 2) of one node in deviation form: the six non-conserved
 // moments of the paper's M (e, epsilon, q_x, q_y, p_xx, p_xy) relax towards the
 // moments of the second-order equilibrium at their own rates (s_e, s_eps, s_q and
@@ -713,7 +752,18 @@ __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
     // links of this node (mask bits; with RUN, the side record's, as a run holds no
     // mask words): exclusive wavefront prefix -> first L entry
     const uint32_t lk = (RUN ? rec : (uint32_t)m) & MASK_LINKS;
-    const uint32_t linc = wave_inclusive_scan((uint32_t)popc32(lk));
+    // deposited populations of this node (side record), counted in the high half
+    // (with RUN the side record also gives the links, so that both prefixes come
+    // from one scan: a run holds at most 512 links, and the low half does not
+    // carry into the high one)
+    uint32_t linc, inc = 0u;
+    if constexpr (RUN) {
+        const uint32_t both = wave_inclusive_scan((uint32_t)popc32(lk) | ((uint32_t)popc32(rec >> 8) << 16));
+        linc = both & 0xffffu;
+        inc = both & 0xffff0000u;
+    } else {
+        linc = wave_inclusive_scan((uint32_t)popc32(lk));
+    }
     const int32_t lbase = sb.links + (int32_t)(linc - (uint32_t)popc32(lk));
     // where x - e_i is solid, the link (x, i') with i' = opp(i) (bit i'-1 of the
     // mask word) supplies the population: its load is issued now, while the
@@ -724,12 +774,15 @@ __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        constexpr int OPPI[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
-        const int lo = lbase - lw;
+        // the node's link values are consecutive in direction order: walk its
+        // link bits with an LDS address that advances past each value taken
+        constexpr int OPPD[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+        uint32_t la = lds_addr(&lds_l[wv][0]) + (uint32_t)(lbase - lw) * S;
 #pragma unroll
-        for (int i = 1; i < 9; ++i) {
-            const uint32_t bit = 1u << (OPPI[i] - 1);
-            if (lk & bit) a[i] = C::reg(lds_l[wv][lo + popc32(lk & (bit - 1u))]);
+        for (int d = 1; d < 9; ++d) {
+            const uint32_t t = opaque((lk >> (d - 1)) & 1u);
+            if (t) a[OPPD[d]] = C::reg(lds_ld<T>(la));
+            la = opaque(la + t * S);
         }
     } else {
         // a node's links are consecutive L entries in direction order: walk them
@@ -744,9 +797,9 @@ __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
                 lb += S;
             }
     }
-    // deposited populations of this node (side record): exclusive prefix -> first P entry
+    // deposited populations: exclusive prefix -> first P entry
     const uint32_t cnt = (uint32_t)popc32(rec >> 8) << 16;
-    const uint32_t inc = wave_inclusive_scan(cnt);
+    if constexpr (!RUN) inc = wave_inclusive_scan(cnt);
     const uint32_t exc = inc - cnt;
     const int32_t pbase = sb.pops + (int32_t)(exc >> 16);
     const int wave_pops = (int)((uint32_t)__builtin_amdgcn_readlane((int)inc, 63) >> 16);
@@ -854,11 +907,11 @@ __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
     for (int k = 0; k < 4; ++k) {
         const int i = PLUS[k];
         const A w = wgt<A>(i);
-        const A eu = A(CX[i]) * ux + A(CY[i]) * uy;
+        const A eu = edot(i, ux, uy);
         const A A2 = A(4.5) * eu * eu - h15;
         ev[k] = w * ((A2 + drho * A2) + drho);
         if (FORCE) {
-            const A eF = A(CX[i]) * Fx + A(CY[i]) * Fy;
+            const A eF = edot(i, Fx, Fy);
             const A cw = cf * w;
             gs[k] = cw * (A(9) * eu * eF - A(3) * uF);
             if (k >= 2) gd[k] = (A(3) * cw) * eF;
@@ -905,10 +958,14 @@ __device__ __forceinline__ void bulk_finish(const Grid &g, const Phys &ph,
         lds_m[wv][3 * ls] = R(drho);
         lds_m[wv][3 * ls + 1] = R(ux);
         lds_m[wv][3 * ls + 2] = R(uy);
-        int lp = (int)(exc >> 16);
+        // the deposits in direction order, an LDS address advancing past each
+        uint32_t pa = lds_addr(&lds_p[wv][0]) + (exc >> 16) * S;
 #pragma unroll
-        for (int d = 1; d < 9; ++d)
-            if (rec & (1u << (d + 7))) lds_p[wv][lp++] = C::st(R(f[d]), ph.scale);
+        for (int d = 1; d < 9; ++d) {
+            const uint32_t t = opaque((rec >> (d + 7)) & 1u);
+            if (t) lds_st<T>(pa, C::st(R(f[d]), ph.scale));
+            pa = opaque(pa + t * S);
+        }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -1080,6 +1137,40 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
 // took 178 us against 167 us with the cap, two registers spilled to vector lanes).
 constexpr int RUN_PRE = 3;  // row segments whose tables a run loads up front
 
+// The nine pull offsets (bytes) of fluid node k from its neighbour word (g.nbr):
+// the ranks of (x, y-1) and (x, y+1) relative to k and whether those nodes are
+// fluid give the same offsets as the segment walk (cmp_ranks); the first and last
+// row and column (periodic wraps) read theirs from the table g.nbr_slow.  A lane
+// without a node (live false) gets offset 0 everywhere.
+template <uint32_t S>
+__device__ __forceinline__ void nbr_offsets(const Grid &g, int32_t k, bool live, uint32_t (&o)[9])
+{
+    const uint32_t wd = live ? ld_at_nt(g.nbr, (uint32_t)k * 4u) : 1u;
+    if ((wd & 0x7fffu) == 0u) {
+        const uint32_t e = (wd >> 15) * 9u;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) o[i] = ld_el(g.nbr_slow, (int32_t)(e + i)) * S;
+    } else {
+        const uint32_t last = (uint32_t)(g.plane - 1) * S;
+        const int32_t kk = live ? k : 0;
+        const int32_t dm = (int32_t)(wd & 0x7fffu) - 16384, dp = (int32_t)((wd >> 16) & 0x7fffu) - 16384;
+        const uint32_t rk[3] = {(uint32_t)(kk + dm) * S, (uint32_t)kk * S, (uint32_t)(kk + dp) * S};
+        const uint32_t fl3[3] = {(wd >> 15) & 1u, 1u, wd >> 31};
+        uint32_t lf[3], rt[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            lf[r] = (rk[r] > S ? rk[r] : S) - S;
+            const uint32_t q = rk[r] + S * fl3[r];
+            rt[r] = q < last ? q : last;
+        }
+        cmp_pull_offsets(rk, lf, rt, o);
+    }
+    if (!live) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) o[i] = 0u;
+    }
+}
+
 // With FUSE the wavefront also evaluates the links of its nodes (from the previous
 // step's deposits; no link kernel) and leaves one force partial per run in fa.
 // With NBR each lane reads its node's neighbour word (g.nbr) instead of the
@@ -1138,33 +1229,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(96))) void bulk
     const bool live = k0 + lane < kend;
     uint32_t o[9];
     if constexpr (NBR) {
-        // the node's ranks in rows y-1 and y+1 from its neighbour word, as the
-        // segment walk below would compute them; the first and last row and
-        // column (periodic wraps) read their nine offsets from a table
-        const int32_t k = live ? k0 + lane : 0;
-        const uint32_t wd = live ? ld_at_nt(g.nbr, (uint32_t)k * 4u) : 1u;
-        if ((wd & 0x7fffu) == 0u) {
-            const uint32_t e = (wd >> 15) * 9u;
-#pragma unroll
-            for (int i = 0; i < 9; ++i) o[i] = ld_el(g.nbr_slow, (int32_t)(e + i)) * S;
-        } else {
-            const uint32_t last = (uint32_t)(g.plane - 1) * S;
-            const int32_t dm = (int32_t)(wd & 0x7fffu) - 16384, dp = (int32_t)((wd >> 16) & 0x7fffu) - 16384;
-            const uint32_t rk[3] = {(uint32_t)(k + dm) * S, (uint32_t)k * S, (uint32_t)(k + dp) * S};
-            const uint32_t fl3[3] = {(wd >> 15) & 1u, 1u, wd >> 31};
-            uint32_t lf[3], rt[3];
-#pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                lf[r] = (rk[r] > S ? rk[r] : S) - S;
-                const uint32_t q = rk[r] + S * fl3[r];
-                rt[r] = q < last ? q : last;
-            }
-            cmp_pull_offsets(rk, lf, rt, o);
-        }
-        if (!live) {
-#pragma unroll
-            for (int i = 0; i < 9; ++i) o[i] = 0u;
-        }
+        nbr_offsets<S>(g, k0 + lane, live, o);
     } else {
     {
         // walk the row segments of the run; lane = bit of the segment.  The tables
