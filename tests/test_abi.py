@@ -216,3 +216,20 @@ def test_geometry_fraction_derivatives_match_oracle_complex_step():
             sel = prim == p_
             assert np.abs(dq[sel, k] - cs[sel]).max() < 1e-9 * max(1.0, np.abs(cs[sel]).max())
             assert np.abs(cs[~sel]).max() == 0.0
+
+
+def test_compact_geometry_preparation_on_the_host():
+    """The compact layout's host preparation (segment and run tables, neighbour
+    words and their table, including the case that gets no words: rows of more
+    than 16 383 fluid nodes) runs through lbm_check_geometry on the CPU, so that
+    the sanitizer build of the host library covers it."""
+    case = W.porous_medium(nx=300, ny=70, seed=5)
+    mask, node, d, q, uw, obj = _links(case)
+    p = B.make_params(case.nx, case.ny, layout="compact")
+    assert B.lbm_check_geometry(p, mask, node, d, q, uw, obj) >= 0
+    # one wide all-fluid lattice: every interior rank difference exceeds 15 bits
+    p = B.make_params(16448, 5, layout="compact")
+    assert B.lbm_check_geometry(p, np.zeros((5, 16448), np.uint8), [], [], []) == 0
+    # a 1-wide column (every node on the first and last column)
+    p = B.make_params(1, 9, layout="compact")
+    assert B.lbm_check_geometry(p, np.zeros((9, 1), np.uint8), [], [], []) == 0
