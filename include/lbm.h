@@ -308,11 +308,13 @@ typedef struct {
                                  periodic in x; bulk_block_x, bulk_store_solid and bulk_rows do not
                                  apply; with bulk_fused the run evaluates its own links, BGK or
                                  MRT); 2: runs whose lanes read their pull offsets from a
-                                 per-node neighbour word built with the geometry (4 bytes per
-                                 fluid node) instead of walking the row segments, refused with
-                                 LBM_E_ARG before a geometry is set or when the first and last
-                                 row and column hold more fluid nodes than the table's room (a
-                                 later geometry without the words turns 2 into 1);
+                                 per-node neighbour word built with the geometry (2 bytes per
+                                 fluid node, 16 per run of 64) instead of walking the row
+                                 segments, refused with LBM_E_ARG before a geometry is set or
+                                 when the nodes the words cannot hold (first and last row and
+                                 column, runs whose rank differences spread over more than
+                                 126) exceed the offset table's room, 2 pitch + 2 ny + 1024
+                                 nodes (a later geometry without the words turns 2 into 1);
                                  0: row segments */
 } lbm_kernel_config;
 

@@ -20,7 +20,7 @@ namespace lbm_host {
 struct Layout {
     int32_t pitch;
     int64_t plane;  // elements per population plane
-    size_t off_A, off_B, off_mask, off_seg, off_fmask, off_runs, off_frow, off_nbr, off_nbrs, off_meta, off_q, off_uw, off_sf, off_sff, off_pf, off_pff,
+    size_t off_A, off_B, off_mask, off_seg, off_fmask, off_runs, off_frow, off_nbr, off_nbrr, off_nbrs, off_meta, off_q, off_uw, off_sf, off_sff, off_pf, off_pff,
         off_pfi, off_li, off_kof, off_L, off_rec, off_mnode, off_pbase, off_M, off_P, off_M2, off_P2, off_wpart,
         off_wobj, off_uin,
         off_force, off_partials, off_stage, total;
@@ -89,7 +89,8 @@ struct lbm_ctx {
                          reinterpret_cast<const uint64_t *>(ws + lay.off_fmask),
                          reinterpret_cast<const lbm::RunBase *>(ws + lay.off_runs),
                          reinterpret_cast<const lbm::SegRow *>(ws + lay.off_frow), nruns, n_fluid,
-                         has_nbr ? reinterpret_cast<const uint32_t *>(ws + lay.off_nbr) : nullptr,
+                         has_nbr ? reinterpret_cast<const uint16_t *>(ws + lay.off_nbr) : nullptr,
+                         reinterpret_cast<const lbm::NbrRun *>(ws + lay.off_nbrr),
                          reinterpret_cast<const uint32_t *>(ws + lay.off_nbrs)};
     }
     lbm::Phys phys() const

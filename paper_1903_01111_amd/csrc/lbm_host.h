@@ -45,7 +45,8 @@ struct Prepared {
     std::vector<uint64_t> fmask;           // per segment: its fluid nodes (bit = lane)
     std::vector<lbm::RunBase> runs;        // per run of 64 fluid nodes, plus a sentinel with the totals
     std::vector<lbm::SegRow> frow;         // per segment: fmask and fluid base in one record, plus a sentinel
-    std::vector<uint32_t> nbr;             // per fluid node: neighbour word (empty: not available)
+    std::vector<uint16_t> nbr;             // per fluid node: neighbour word (empty: not available)
+    std::vector<lbm::NbrRun> nbr_run;      // per run of 64 fluid nodes: word bases, plus a sentinel
     std::vector<uint32_t> nbr_slow;        // nine pull offsets per table entry of the neighbour words
     int32_t n_fluid = 0;
     int64_t n_pops = 0;

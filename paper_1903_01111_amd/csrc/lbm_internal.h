@@ -15,6 +15,7 @@ namespace lbm {
 struct SegBase;
 struct RunBase;
 struct SegRow;
+struct NbrRun;
 
 // With compact set, plane i holds only the fluid nodes, the k-th fluid node in
 // (y, x) order at offset k: a node's offset is the fluid count before its
@@ -31,10 +32,12 @@ struct Grid {
     int32_t nruns;          // runs of 64 fluid nodes: ceil(n_fluid / 64)
     int32_t n_fluid;
     // per fluid node (compact layout, periodic x): the fluid ranks of (x, y-1) and
-    // (x, y+1) relative to the node's own, biased by 16384 in bits 0-14 and 16-30,
-    // whether those nodes are fluid in bits 15 and 31; bits 0-14 zero: the node's nine
-    // pull offsets (elements) are entry word >> 15 of nbr_slow
-    const uint32_t *nbr;
+    // (x, y+1) relative to the node's own, minus its run's bases (nbr_run), in bits
+    // 0-6 and 8-14, whether those nodes are fluid in bits 7 and 15; 0xffff: the
+    // node's nine pull offsets (elements) are the next entry of nbr_slow after the
+    // run's base and the run's earlier such nodes
+    const uint16_t *nbr;
+    const NbrRun *nbr_run;  // [nruns + 1]
     const uint32_t *nbr_slow;
 };
 
@@ -74,6 +77,12 @@ struct SegBase {
 struct SegRow {
     uint32_t fm_lo, fm_hi;
     int32_t fluid, pad;
+};
+
+// Per run of 64 fluid nodes: the bases of its nodes' neighbour words and the
+// offset-table entries that precede it.
+struct NbrRun {
+    int32_t dm0, dp0, slow, pad;
 };
 
 struct RunBase {

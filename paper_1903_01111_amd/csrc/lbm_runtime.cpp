@@ -43,6 +43,14 @@ size_t bytes_per_link(int storage)
     return 53 + 15 * real_bytes(storage) + 7 * elem_bytes(storage);
 }
 
+// Room of the neighbour words' offset table: the first and last row and column
+// (the periodic wraps), plus 16 runs of 64 nodes whose rank differences spread too
+// far for the 16-bit words.
+int64_t nbr_table_room(int64_t pitch, int64_t ny)
+{
+    return 2 * pitch + 2 * ny + 16 * 64;
+}
+
 // Plane stride: rows padded to 64 elements; the plane size in 256-byte units is
 // kept odd so that the nine planes do not start on the same memory channel.
 Layout make_layout(const lbm_params &p, int64_t max_links)
@@ -69,8 +77,9 @@ Layout make_layout(const lbm_params &p, int64_t max_links)
     L.off_frow = take(((size_t)(L.pitch / 64) * p.ny + 1) * sizeof(lbm::SegRow));
     // neighbour words: one per fluid node, and nine offsets per node of the first and
     // last row and column
-    L.off_nbr = take((size_t)L.pitch * p.ny * sizeof(uint32_t));
-    L.off_nbrs = take(((size_t)2 * L.pitch + 2 * (size_t)p.ny) * 9 * sizeof(uint32_t));
+    L.off_nbr = take((size_t)L.pitch * p.ny * sizeof(uint16_t));
+    L.off_nbrr = take(((size_t)(L.pitch / 64) * p.ny + 1) * sizeof(lbm::NbrRun));
+    L.off_nbrs = take((size_t)nbr_table_room(L.pitch, p.ny) * 9 * sizeof(uint32_t));
     const size_t nl = (size_t)std::max<int64_t>(max_links, 0);
     L.off_meta = take(nl * 4);
     L.off_q = take(nl * rb);
@@ -379,12 +388,17 @@ lbm_status prepare_geometry(const lbm_params &p, const uint8_t *mask, int64_t n,
             out->runs[r].nlinks = (uint32_t)(out->runs[r + 1].links - out->runs[r].links);
     }
     // Neighbour words for runs that read their pull offsets instead of computing
-    // them from the segment tables (periodic x only; the x-open layout has no runs):
-    // per fluid node k at (x, y), the fluid ranks of (x, y-1) and (x, y+1) relative
-    // to k and whether those nodes are fluid, or, for the nodes of the first and last
-    // row and column (periodic wraps) and any rank difference beyond 15 bits, an
-    // index into a table of their nine pull offsets.
+    // them from the segment tables (periodic x only; the x-open layout has no runs).
+    // For fluid node k at (x, y) let dm and dp be the fluid ranks of (x, y-1) and
+    // (x, y+1) relative to k.  Within a run of 64 nodes they vary little, so each
+    // run stores the smallest dm and dp of its nodes (NbrRun) and each node a 16-bit
+    // word: dm and dp above those bases in 7 bits each, and whether (x, y-1) and
+    // (x, y+1) are fluid.  The nodes of the first and last row and column (periodic
+    // wraps), and every node of a run whose differences spread over more than 126,
+    // have the word 0xffff instead and their nine pull offsets in a table, in plane
+    // order (the run stores how many entries precede it).
     out->nbr.clear();
+    out->nbr_run.clear();
     out->nbr_slow.clear();
     if (p.x_bc != LBM_X_OPEN && p.layout == LBM_LAYOUT_COMPACT) {
         const int64_t nsr = pitch / 64;
@@ -395,41 +409,66 @@ lbm_status prepare_geometry(const lbm_params &p, const uint8_t *mask, int64_t n,
             return out->seg[sg].fluid + __builtin_popcountll(out->fmask[sg] & ((1ull << (xx & 63)) - 1ull));
         };
         const int64_t last = make_layout(p, 0).plane;  // the plane's element count bounds every offset
+        struct Node {
+            int x, y;
+            int64_t dm, dp;
+            bool fm, fp, edge;
+        };
+        std::vector<Node> run;
+        run.reserve(64);
+        auto flush = [&]() {
+            if (run.empty()) return;
+            int64_t m0 = INT64_MAX, m1 = INT64_MIN, p0 = INT64_MAX, p1 = INT64_MIN;
+            for (const Node &n : run)
+                if (!n.edge) {
+                    m0 = std::min(m0, n.dm), m1 = std::max(m1, n.dm);
+                    p0 = std::min(p0, n.dp), p1 = std::max(p1, n.dp);
+                }
+            const bool wide = m0 != INT64_MAX && (m1 - m0 > 126 || p1 - p0 > 126 || m0 < INT32_MIN ||
+                                                   m0 > INT32_MAX || p0 < INT32_MIN || p0 > INT32_MAX);
+            if (m0 == INT64_MAX || wide) m0 = p0 = 0;
+            out->nbr_run.push_back(lbm::NbrRun{(int32_t)m0, (int32_t)p0, (int32_t)(out->nbr_slow.size() / 9), 0});
+            for (const Node &n : run) {
+                if (!n.edge && !wide) {
+                    out->nbr.push_back((uint16_t)((uint32_t)(n.dm - m0) | ((uint32_t)n.fm << 7) |
+                                                  ((uint32_t)(n.dp - p0) << 8) | ((uint32_t)n.fp << 15)));
+                    continue;
+                }
+                // the nine offsets as the segment walk computes them (elements)
+                const int x = n.x, y = n.y;
+                const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+                const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+                const int rows[3] = {ym, y, yp};
+                int64_t rk[3], lf[3], rt[3];
+                for (int r = 0; r < 3; ++r) {
+                    rk[r] = rank(x, rows[r]);
+                    lf[r] = x == 0 ? rank(xm, rows[r]) : std::max<int64_t>(rk[r] - 1, 0);
+                    rt[r] = x == nx - 1 ? rank(xp, rows[r])
+                                        : std::min<int64_t>(rk[r] + (fluid_at(x, rows[r]) ? 1 : 0), last - 1);
+                }
+                const int64_t o9[9] = {rk[1], lf[1], rk[0], rt[1], rk[2], lf[0], rt[0], rt[2], lf[2]};
+                for (int i = 0; i < 9; ++i) out->nbr_slow.push_back((uint32_t)o9[i]);
+                out->nbr.push_back((uint16_t)0xffffu);
+            }
+            run.clear();
+        };
         out->nbr.reserve((size_t)nfluid);
         int64_t k = 0;
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 if (!fluid_at(x, y)) continue;
                 const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
-                const int64_t rm = rank(x, ym), rp = rank(x, yp);
-                const int64_t dm = rm - k, dp = rp - k;
-                const bool slow = y == 0 || y == ny - 1 || x == 0 || x == nx - 1 || dm < -16383 || dm > 16383 ||
-                                  dp < -16383 || dp > 16383;
-                if (!slow) {
-                    out->nbr.push_back((uint32_t)(dm + 16384) | ((uint32_t)fluid_at(x, ym) << 15) |
-                                       ((uint32_t)(dp + 16384) << 16) | ((uint32_t)fluid_at(x, yp) << 31));
-                } else {
-                    // the nine offsets as the segment walk computes them (elements)
-                    const int64_t idx = (int64_t)out->nbr_slow.size() / 9;
-                    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
-                    const int rows[3] = {ym, y, yp};
-                    int64_t rk[3], lf[3], rt[3];
-                    for (int r = 0; r < 3; ++r) {
-                        rk[r] = rank(x, rows[r]);
-                        lf[r] = x == 0 ? rank(xm, rows[r]) : std::max<int64_t>(rk[r] - 1, 0);
-                        rt[r] = x == nx - 1 ? rank(xp, rows[r])
-                                            : std::min<int64_t>(rk[r] + (fluid_at(x, rows[r]) ? 1 : 0), last - 1);
-                    }
-                    const int64_t o9[9] = {rk[1], lf[1], rk[0], rt[1], rk[2], lf[0], rt[0], rt[2], lf[2]};
-                    for (int i = 0; i < 9; ++i) out->nbr_slow.push_back((uint32_t)o9[i]);
-                    out->nbr.push_back((uint32_t)idx << 15);  // low 15 bits zero: a table entry
-                }
+                run.push_back(Node{x, y, rank(x, ym) - k, rank(x, yp) - k, fluid_at(x, ym), fluid_at(x, yp),
+                                   y == 0 || y == ny - 1 || x == 0 || x == nx - 1});
+                if (run.size() == 64) flush();
                 ++k;
             }
-        // table entries beyond the workspace's room (the first and last row and column)
-        // or beyond 17 bits of index: no neighbour words
-        if ((int64_t)out->nbr_slow.size() / 9 > std::min<int64_t>(2 * (int64_t)pitch + 2 * ny, (1 << 17) - 1)) {
+        flush();
+        out->nbr_run.push_back(lbm::NbrRun{0, 0, (int32_t)(out->nbr_slow.size() / 9), 0});  // sentinel
+        // table entries beyond the workspace's room: no neighbour words
+        if ((int64_t)out->nbr_slow.size() / 9 > nbr_table_room(pitch, ny)) {
             out->nbr.clear();
+            out->nbr_run.clear();
             out->nbr_slow.clear();
         }
     }
@@ -802,7 +841,8 @@ lbm_status lbm_set_geometry(lbm_ctx *c, const uint8_t *mask, int64_t n_links, co
                {c->lay.off_fmask, prep.fmask.data(), prep.fmask.size() * sizeof(uint64_t)},
                {c->lay.off_runs, prep.runs.data(), prep.runs.size() * sizeof(lbm::RunBase)},
                {c->lay.off_frow, prep.frow.data(), prep.frow.size() * sizeof(lbm::SegRow)},
-               {c->lay.off_nbr, prep.nbr.data(), prep.nbr.size() * sizeof(uint32_t)},
+               {c->lay.off_nbr, prep.nbr.data(), prep.nbr.size() * sizeof(uint16_t)},
+               {c->lay.off_nbrr, prep.nbr_run.data(), prep.nbr_run.size() * sizeof(lbm::NbrRun)},
                {c->lay.off_nbrs, prep.nbr_slow.data(), prep.nbr_slow.size() * sizeof(uint32_t)}};
     for (const Up &u : ups)
         if (u.bytes && (s = c->hip(hipMemcpyAsync(c->ws + u.off, u.src, u.bytes,

@@ -1137,25 +1137,34 @@ __global__ __launch_bounds__(256) void bulk_kernel(Grid g, Phys ph,
 // took 178 us against 167 us with the cap, two registers spilled to vector lanes).
 constexpr int RUN_PRE = 3;  // row segments whose tables a run loads up front
 
-// The nine pull offsets (bytes) of fluid node k from its neighbour word (g.nbr):
-// the ranks of (x, y-1) and (x, y+1) relative to k and whether those nodes are
-// fluid give the same offsets as the segment walk (cmp_ranks); the first and last
-// row and column (periodic wraps) read theirs from the table g.nbr_slow.  A lane
-// without a node (live false) gets offset 0 everywhere.
+// The nine pull offsets (bytes) of fluid node k, the lane-th node of run w, from
+// its neighbour word (g.nbr): the ranks of (x, y-1) and (x, y+1) relative to k are
+// the run's bases (g.nbr_run) plus the word's 7-bit excesses, and with whether those
+// nodes are fluid they give the same offsets as the segment walk (cmp_ranks).  A
+// node with the word 0xffff (the first and last row and column, whose periodic
+// wraps the words do not hold, and the nodes of a run whose differences spread too
+// far) reads its nine offsets from the table g.nbr_slow, at the run's base plus the
+// run's earlier such nodes.  A lane without a node (live false) gets offset 0
+// everywhere.  Called by the whole wavefront (a ballot).
 template <uint32_t S>
-__device__ __forceinline__ void nbr_offsets(const Grid &g, int32_t k, bool live, uint32_t (&o)[9])
+__device__ __forceinline__ void nbr_offsets(const Grid &g, int32_t w, int32_t k, bool live, uint32_t (&o)[9])
 {
-    const uint32_t wd = live ? ld_at_nt(g.nbr, (uint32_t)k * 4u) : 1u;
-    if ((wd & 0x7fffu) == 0u) {
-        const uint32_t e = (wd >> 15) * 9u;
+    const int lane = threadIdx.x & 63;
+    const int32_t dm0 = ld_const(&g.nbr_run[w].dm0), dp0 = ld_const(&g.nbr_run[w].dp0);
+    const int32_t sb = ld_const(&g.nbr_run[w].slow);
+    const uint32_t wd = live ? (uint32_t)ld_at_nt(g.nbr, (uint32_t)k * 2u) : 0u;
+    const bool slow = live && wd == 0xffffu;
+    const uint64_t sm = __ballot(slow);
+    if (slow) {
+        const uint32_t e = (uint32_t)(sb + (int32_t)__popcll(sm & ((1ull << lane) - 1ull))) * 9u;
 #pragma unroll
         for (int i = 0; i < 9; ++i) o[i] = ld_el(g.nbr_slow, (int32_t)(e + i)) * S;
     } else {
         const uint32_t last = (uint32_t)(g.plane - 1) * S;
         const int32_t kk = live ? k : 0;
-        const int32_t dm = (int32_t)(wd & 0x7fffu) - 16384, dp = (int32_t)((wd >> 16) & 0x7fffu) - 16384;
+        const int32_t dm = dm0 + (int32_t)(wd & 0x7fu), dp = dp0 + (int32_t)((wd >> 8) & 0x7fu);
         const uint32_t rk[3] = {(uint32_t)(kk + dm) * S, (uint32_t)kk * S, (uint32_t)(kk + dp) * S};
-        const uint32_t fl3[3] = {(wd >> 15) & 1u, 1u, wd >> 31};
+        const uint32_t fl3[3] = {(wd >> 7) & 1u, 1u, wd >> 15};
         uint32_t lf[3], rt[3];
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
@@ -1229,7 +1238,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(96))) void bulk
     const bool live = k0 + lane < kend;
     uint32_t o[9];
     if constexpr (NBR) {
-        nbr_offsets<S>(g, k0 + lane, live, o);
+        nbr_offsets<S>(g, w, k0 + lane, live, o);
     } else {
     {
         // walk the row segments of the run; lane = bit of the segment.  The tables

@@ -220,16 +220,30 @@ def test_geometry_fraction_derivatives_match_oracle_complex_step():
 
 def test_compact_geometry_preparation_on_the_host():
     """The compact layout's host preparation (segment and run tables, neighbour
-    words and their table, including the case that gets no words: rows of more
-    than 16 383 fluid nodes) runs through lbm_check_geometry on the CPU, so that
-    the sanitizer build of the host library covers it."""
+    words with their run bases and offset table) runs through lbm_check_geometry on
+    the CPU, so that the sanitizer build of the host library covers it: a porous
+    medium, all-fluid rows of 16 448 nodes (rank differences beyond 15 bits), a
+    lattice whose spread-out runs overflow the offset table (no words), and a
+    1-wide column."""
     case = W.porous_medium(nx=300, ny=70, seed=5)
     mask, node, d, q, uw, obj = _links(case)
     p = B.make_params(case.nx, case.ny, layout="compact")
     assert B.lbm_check_geometry(p, mask, node, d, q, uw, obj) >= 0
-    # one wide all-fluid lattice: every interior rank difference exceeds 15 bits
     p = B.make_params(16448, 5, layout="compact")
     assert B.lbm_check_geometry(p, np.zeros((5, 16448), np.uint8), [], [], []) == 0
+    sparse = np.zeros((64, 2048), np.uint8)
+    sparse[1::2, :] = 1
+    sparse[1::2, ::4] = 0
+    case = W.Case("sparse_rows", 2048, 64, False, 0.8)
+    node, d = [], []
+    for y, x in zip(*np.nonzero(sparse == 0)):
+        for i in range(1, 9):
+            if sparse[(y + [0, 0, 1, 0, -1, 1, 1, -1, -1][i]) % 64, (x + [0, 1, 0, -1, 0, 1, -1, -1, 1][i]) % 2048]:
+                node.append(y * 2048 + x)
+                d.append(i)
+    p = B.make_params(2048, 64, layout="compact")
+    assert B.lbm_check_geometry(p, sparse, np.array(node, np.int32), np.array(d, np.int8),
+                                np.full(len(node), 0.5)) >= 0
     # a 1-wide column (every node on the first and last column)
     p = B.make_params(1, 9, layout="compact")
     assert B.lbm_check_geometry(p, np.zeros((9, 1), np.uint8), [], [], []) == 0

@@ -283,12 +283,10 @@ def test_neighbour_words_with_many_links_and_without_fluid(B):
     lat.close()
 
 
-def _wide(fluid_cols):
-    """A 16448 x 5 periodic lattice whose columns x < fluid_cols are fluid, the rest
-    solid, with halfway links (q = 1/2) wherever a fluid node pulls from a solid one."""
-    nx, ny = 16448, 5
-    mask = np.ones((ny, nx), np.uint8)
-    mask[:, :fluid_cols] = 0
+def _halfway(mask):
+    """Halfway links (q = 1/2) wherever a fluid node of the periodic mask pulls from
+    a solid one, as a geometry tuple."""
+    ny, nx = mask.shape
     ex = [0, 1, 0, -1, 0, 1, -1, -1, 1]
     ey = [0, 0, 1, 0, -1, 1, 1, -1, -1]
     node, d = [], []
@@ -298,28 +296,66 @@ def _wide(fluid_cols):
                 node.append(y * nx + x)
                 d.append(i)
     n = len(node)
-    geo = (mask, np.array(node, np.int32), np.array(d, np.int8), np.full(n, 0.5), None, np.zeros(n, np.int32),
-           None)
-    return W.Case("wide", nx, ny, False, 0.8), geo
+    return (mask, np.array(node, np.int32), np.array(d, np.int8), np.full(n, 0.5), None, np.zeros(n, np.int32),
+            None)
 
 
-def test_neighbour_words_absent_for_wide_rows(B):
-    """Rows of more than 16383 fluid nodes put the rank differences of every interior
-    node beyond the word's 15 bits and the table beyond its room: no words, so
-    bulk_runs 2 is refused, and a geometry set later without words turns it into 1."""
-    case, narrow = _wide(1000)
-    lat = B.Lattice(case, storage="f32", layout="compact", geometry=narrow)
-    B.lbm_set_kernel_config(lat.ctx, _nbr_cfg(B))
-    assert B.lbm_get_kernel_config(lat.ctx).bulk_runs == 2
-    _, full = _wide(16448)
-    B.lbm_set_geometry(lat.ctx, *full)
-    B.lbm_init_equilibrium(lat.ctx)
-    assert B.lbm_get_kernel_config(lat.ctx).bulk_runs == 1
+def _sparse_rows():
+    """2048 x 64, even rows all fluid, odd rows fluid at every fourth x: a run of an
+    odd row spans 256 columns, over which its rank differences to the dense rows
+    spread by about 190 -- beyond the words' 7 bits, so each such node takes a table
+    entry, and the 256 such runs overflow the table."""
+    mask = np.zeros((64, 2048), np.uint8)
+    mask[1::2, :] = 1
+    mask[1::2, ::4] = 0
+    return W.Case("sparse_rows", 2048, 64, False, 0.8, gx=1e-5), _halfway(mask)
+
+
+def test_neighbour_words_absent_where_the_table_overflows(B):
+    """No words for a geometry whose spread-out runs overflow the offset table:
+    bulk_runs 2 is refused for it, accepted once a geometry with words is set, and
+    turned into 1 when the table-overflowing geometry is set again."""
+    case, sparse = _sparse_rows()
+    lat = B.Lattice(case, storage="f32", layout="compact", geometry=sparse)
     with pytest.raises(B.LbmError) as e:
         B.lbm_set_kernel_config(lat.ctx, _nbr_cfg(B))
     assert e.value.status == B.LBM_E_ARG
+    full = _halfway(np.zeros((64, 2048), np.uint8))
+    B.lbm_set_geometry(lat.ctx, *full)
+    B.lbm_init_equilibrium(lat.ctx)
+    B.lbm_set_kernel_config(lat.ctx, _nbr_cfg(B))
+    assert B.lbm_get_kernel_config(lat.ctx).bulk_runs == 2
+    lat.step(2)
+    B.lbm_set_geometry(lat.ctx, *sparse)
+    B.lbm_init_equilibrium(lat.ctx)
+    assert B.lbm_get_kernel_config(lat.ctx).bulk_runs == 1
     lat.step(2)
     lat.close()
+
+
+def test_neighbour_words_for_rows_beyond_15_bits(B):
+    """All-fluid rows of 16 448 nodes (rank differences beyond 15 bits, held by the
+    runs' 32-bit bases) and a lattice with a few spread-out runs (table entries
+    next to fast words in one run): bitwise the segment walk."""
+    rng = np.random.default_rng(7)
+    for nx, ny, mask in ((16448, 5, np.zeros((5, 16448), np.uint8)), (512, 12, None)):
+        if mask is None:
+            mask = np.zeros((ny, nx), np.uint8)
+            mask[5, :] = 1
+            mask[5, ::4] = 0
+        geo = _halfway(mask)
+        case = W.Case("wide_rows", nx, ny, False, 0.8, gx=1e-5, gy=2e-6)
+        case.init_ux = np.where(mask == 0, 1e-3 * rng.standard_normal((ny, nx)), 0.0)
+        case.init_uy = np.where(mask == 0, 1e-3 * rng.standard_normal((ny, nx)), 0.0)
+        out = []
+        for cfg in (_nbr_cfg(B), _runs_cfg(B)):
+            lat = B.Lattice(case, storage="f32", layout="compact", geometry=geo)
+            B.lbm_set_kernel_config(lat.ctx, cfg)
+            lat.step(9)
+            out.append((lat.populations(), lat.moments(), [lat.force(0)], lat.mass()))
+            lat.close()
+        print(f"[compact] neighbour words {nx}x{ny}", flush=True)
+        _same(out[0], out[1])
 
 
 def test_runs_refused_where_unsupported(B):
