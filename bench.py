@@ -224,7 +224,7 @@ def form_precision(B, case, ref, steps_time, layout="compact", steps_long=20000,
                          mean_ux_err_vs_f32_long=float(abs(ul.mean() - long32[0].mean()) / abs(long32[0].mean())))
         except B.LbmError as e:
             r["error"] = f"unstable ({e})"
-        B.lbm_autotune(lat.ctx, 10)
+        B.lbm_autotune(lat.ctx, 30)
         ms, link_ms, bulk_ms, ksteps = replay_then_timed(B, lat, steps_time)
         bulk_bytes, _ = algorithmic_bytes(case, lat.mask, lat.n_links, st)
         bulk_us = bulk_ms * 1e3 / ksteps
@@ -318,7 +318,7 @@ def form_single(B, case, steps, warmup, layout="dense"):
     shorter pass with HIP events around every launch."""
     lat = B.Lattice(case, storage="f32", layout=layout)
     lat.step(warmup)
-    B.lbm_autotune(lat.ctx, 10)
+    B.lbm_autotune(lat.ctx, 30)
     lat.step(warmup)
     ms, link_ms, bulk_ms, ksteps = replay_then_timed(B, lat, steps)
     lat.moments()
@@ -789,7 +789,7 @@ def main():
 
     lat.step(args.warmup)
     lat.sync()
-    cfg, tuned_ms = B.lbm_autotune(lat.ctx, 20)  # keeps the fastest launch shape, restores the state
+    cfg, tuned_ms = B.lbm_autotune(lat.ctx, 60)  # keeps the fastest launch shape, restores the state
     print(f"[bench] autotuned {cfg.as_dict()} ({tuned_ms * 1e3:.1f} us/step)", file=sys.stderr,
           flush=True)
     lat.moments()  # raises LBM_E_UNSTABLE on a non-finite state

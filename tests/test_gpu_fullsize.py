@@ -46,7 +46,7 @@ def _gpu(B, case, storage, n, layout="dense", k=0, tune=False):
     if tune:
         # the launch configuration bench.py times: the autotuner's choice (it
         # restores the state it started from)
-        cfg, _ = B.lbm_autotune(lat.ctx, 10)
+        cfg, _ = B.lbm_autotune(lat.ctx, 30)
         print(f"[fullsize] {storage}: autotuned {cfg.as_dict()}", flush=True)
     lat.step(n)
     _, ux, uy = lat.moments()
