@@ -21,7 +21,7 @@ struct Layout {
     int32_t pitch;
     int64_t plane;  // elements per population plane
     size_t off_A, off_B, off_mask, off_seg, off_fmask, off_runs, off_frow, off_nbr, off_nbrr, off_nbrs, off_meta, off_q, off_uw, off_sf, off_sff, off_pf, off_pff,
-        off_pfi, off_li, off_kof, off_L, off_rec, off_mnode, off_pbase, off_M, off_P, off_M2, off_P2, off_wpart,
+        off_pfi, off_crec, off_cbase, off_li, off_kof, off_L, off_rec, off_mnode, off_pbase, off_M, off_P, off_M2, off_P2, off_wpart,
         off_wobj, off_uin,
         off_force, off_partials, off_stage, total;
     int64_t wave_cap;  // wavefront partials of the link kernel
@@ -43,6 +43,7 @@ struct lbm_ctx {
     int64_t max_links = 0, n_links = 0, n_moment_nodes = 0;
     bool has_uw = false, have_geom = false, have_init = false;
     bool has_pfi = false;       // some link needs f+_i(x_f) (Bouzidi, Yu)
+    bool has_crec = false;      // compact link records uploaded (4-byte reals)
     bool has_ext_scheme = false;  // some link uses Bouzidi or Yu
     bool li_ident = false;  // links in (node, dir) order: L entry = link index
     // caller's index of each device link (links are kept in (obj, node, dir) order)
@@ -105,7 +106,9 @@ struct lbm_ctx {
         return lbm::Links{reinterpret_cast<const uint32_t *>(ws + lay.off_meta), ws + lay.off_q,
                           has_uw ? ws + lay.off_uw : nullptr, i32(lay.off_sf), i32(lay.off_sff),
                           i32(lay.off_pf), i32(lay.off_pff), i32(lay.off_li), n_links, li_ident ? 1 : 0, 0,
-                          li_ident ? nullptr : i32(lay.off_kof), has_pfi ? i32(lay.off_pfi) : nullptr};
+                          li_ident ? nullptr : i32(lay.off_kof), has_pfi ? i32(lay.off_pfi) : nullptr,
+                          has_crec ? reinterpret_cast<const lbm::LinkRec *>(ws + lay.off_crec) : nullptr,
+                          reinterpret_cast<const lbm::LinkRunBase *>(ws + lay.off_cbase)};
     }
     lbm::Reduce reduce() const
     {

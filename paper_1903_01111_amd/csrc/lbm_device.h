@@ -256,6 +256,14 @@ __device__ __forceinline__ T ld_const_record(const T *p)
     for (int i = 0; i < (int)(sizeof(T) / 4); ++i) d[i] = q[i];
     return v;
 }
+// A 16-byte record per lane through the non-temporal vector path (one 16-byte load).
+template <class T>
+__device__ __forceinline__ T ld_rec_nt(const T *p)
+{
+    static_assert(sizeof(T) == 16, "16-byte record");
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    return __builtin_bit_cast(T, __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p)));
+}
 // A segment-base record field by field (a record load of only the fields used
 // can become 12 bytes wide, which the scalar unit has no form for).
 __device__ __forceinline__ SegBase ld_seg(const SegBase *p)

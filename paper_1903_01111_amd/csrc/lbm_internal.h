@@ -118,6 +118,18 @@ struct Side {
 // Links in (obj, node, dir) order, so a wavefront usually serves one object.
 // The scheme in bits 4..7 of meta is the one evaluated: LBM_SCHEME_HBB also for a
 // link whose scheme needs x_ff where x_ff is unusable (then sff = -1).
+// Compact link record (storages with 4-byte reals): the direction word, q's bits,
+// and the M slots and P entries of x_f and x_ff as 16-bit excesses over the bases
+// of the link's run of 64 links (d_f: slot | entry << 16; d_ff likewise, slot
+// 0xffff: no x_ff).  A run whose excesses do not fit 16 bits has sf0 = -1 and its
+// links are read from the separate arrays.
+struct LinkRec {
+    uint32_t meta, q, d_f, d_ff;
+};
+struct LinkRunBase {
+    int32_t sf0, pf0, sff0, pff0;
+};
+
 struct Links {
     const uint32_t *meta;  // dir | (scheme << 4) | (obj << 8)
     const void *q;         // real[n]
@@ -133,6 +145,8 @@ struct Links {
     const int32_t *kof;    // inverse of li (null when li_ident)
     const int32_t *pfi;    // P entry of f+_i(x_f), i = opp(dir) (Bouzidi and Yu links; others
                            // repeat pf), or null when no link needs it
+    const LinkRec *crec;   // [n] compact records, or null (read meta, q, sf, sff, pf, pff)
+    const LinkRunBase *cbase;  // [n / 64 + 1] their bases
 };
 
 // Partial forces of the link kernel, one per run of 64 links, reduced per object

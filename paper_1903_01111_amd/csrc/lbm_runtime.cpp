@@ -89,6 +89,8 @@ Layout make_layout(const lbm_params &p, int64_t max_links)
     L.off_pf = take(nl * 4);
     L.off_pff = take(nl * 4);
     L.off_pfi = take(nl * 4);
+    L.off_crec = take(rb == 4 ? nl * sizeof(lbm::LinkRec) : 0);
+    L.off_cbase = take(rb == 4 ? (nl / 64 + 1) * sizeof(lbm::LinkRunBase) : 0);
     L.off_li = take(nl * 4);
     L.off_kof = take(nl * 4);
     L.off_L = take(nl * eb);
@@ -820,6 +822,39 @@ lbm_status lbm_set_geometry(lbm_ctx *c, const uint8_t *mask, int64_t n_links, co
     // link index of each (node, dir) rank, for the fused bulk kernel
     std::vector<int32_t> kof(n);
     for (size_t k = 0; k < n; ++k) kof[prep.li[k]] = (int32_t)k;
+    // compact records (4-byte reals): per run of 64 links the smallest M slot and P
+    // entry of x_f and of x_ff, per link the 16-bit excesses over them
+    std::vector<lbm::LinkRec> crec(rb == 4 ? n : 0);
+    std::vector<lbm::LinkRunBase> cbase(rb == 4 ? n / 64 + 1 : 0);
+    for (size_t r = 0; rb == 4 && r * 64 < n; ++r) {
+        const size_t a = r * 64, e = std::min(n, a + 64);
+        int64_t sf0 = INT64_MAX, pf0 = INT64_MAX, sff0 = INT64_MAX, pff0 = INT64_MAX;
+        int64_t sf1 = INT64_MIN, pf1 = INT64_MIN, sff1 = INT64_MIN, pff1 = INT64_MIN;
+        for (size_t k = a; k < e; ++k) {
+            sf0 = std::min<int64_t>(sf0, prep.sf[k]), sf1 = std::max<int64_t>(sf1, prep.sf[k]);
+            pf0 = std::min<int64_t>(pf0, prep.pf[k]), pf1 = std::max<int64_t>(pf1, prep.pf[k]);
+            if (prep.sff[k] >= 0) {
+                sff0 = std::min<int64_t>(sff0, prep.sff[k]), sff1 = std::max<int64_t>(sff1, prep.sff[k]);
+                pff0 = std::min<int64_t>(pff0, prep.pff[k]), pff1 = std::max<int64_t>(pff1, prep.pff[k]);
+            }
+        }
+        if (sff0 == INT64_MAX) sff0 = sff1 = pff0 = pff1 = 0;
+        const bool fit = sf1 - sf0 <= 0xffff && pf1 - pf0 <= 0xffff && sff1 - sff0 < 0xffff && pff1 - pff0 <= 0xffff;
+        cbase[r] = fit ? lbm::LinkRunBase{(int32_t)sf0, (int32_t)pf0, (int32_t)sff0, (int32_t)pff0}
+                       : lbm::LinkRunBase{-1, 0, 0, 0};
+        for (size_t k = a; k < e; ++k) {
+            uint32_t qb;
+            std::memcpy(&qb, &qf[k], 4);
+            if (!fit) {
+                crec[k] = lbm::LinkRec{prep.meta[k], qb, 0u, 0u};
+                continue;
+            }
+            const bool ff = prep.sff[k] >= 0;
+            crec[k] = lbm::LinkRec{prep.meta[k], qb, (uint32_t)(prep.sf[k] - sf0) | ((uint32_t)(prep.pf[k] - pf0) << 16),
+                                   ff ? (uint32_t)(prep.sff[k] - sff0) | ((uint32_t)(prep.pff[k] - pff0) << 16)
+                                      : 0xffffu};
+        }
+    }
     struct Up {
         size_t off;
         const void *src;
@@ -832,6 +867,8 @@ lbm_status lbm_set_geometry(lbm_ctx *c, const uint8_t *mask, int64_t n_links, co
                {c->lay.off_pf, prep.pf.data(), n * 4},
                {c->lay.off_pff, prep.pff.data(), n * 4},
                {c->lay.off_pfi, prep.pfi.data(), prep.has_pfi ? n * 4 : 0},
+               {c->lay.off_crec, crec.data(), crec.size() * sizeof(lbm::LinkRec)},
+               {c->lay.off_cbase, cbase.data(), cbase.size() * sizeof(lbm::LinkRunBase)},
                {c->lay.off_li, prep.li.data(), n * 4},
                {c->lay.off_kof, kof.data(), kof.size() * 4},
                {c->lay.off_rec, prep.rec.data(), K * 2},
@@ -877,6 +914,7 @@ lbm_status lbm_set_geometry(lbm_ctx *c, const uint8_t *mask, int64_t n_links, co
     if (c->kcfg.bulk_runs == 2 && !c->has_nbr) c->kcfg.bulk_runs = 1;  // offsets from the segment tables
     c->has_uw = prep.has_uw;
     c->has_pfi = prep.has_pfi;
+    c->has_crec = rb == 4 && n > 0;
     c->has_ext_scheme = prep.has_ext_scheme;
     c->have_geom = true;
     c->have_init = false;

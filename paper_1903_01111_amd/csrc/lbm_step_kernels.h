@@ -53,12 +53,36 @@ __device__ __forceinline__ void link_load_record(const Links &L, int32_t k, Link
 {
     using R = typename Codec<ST>::R;
     const uint32_t o4 = (uint32_t)k * 4u;
-    a.meta = ld_at_nt(L.meta, o4);
-    a.pf = ld_at_nt(L.pf, o4);
-    a.sf = ld_at_nt(L.sf, o4);
-    a.sff = ld_at_nt(L.sff, o4);
-    a.pff = ld_at_nt(L.pff, o4);
-    a.q = ld_at_nt(static_cast<const R *>(L.q), (uint32_t)k * (uint32_t)sizeof(R));
+    bool done = false;
+    if constexpr (sizeof(R) == 4) {
+        if (L.crec) {
+            // one 16-byte record and its run's bases (shared by the wavefront's lanes)
+            const LinkRunBase b = ld_rec_nt(L.cbase + (k >> 6));
+            const LinkRec r = ld_rec_nt(L.crec + k);
+            a.meta = r.meta;
+            a.q = __builtin_bit_cast(R, r.q);
+            if (b.sf0 >= 0) {
+                a.sf = b.sf0 + (int32_t)(r.d_f & 0xffffu);
+                a.pf = b.pf0 + (int32_t)(r.d_f >> 16);
+                a.sff = (r.d_ff & 0xffffu) == 0xffffu ? -1 : b.sff0 + (int32_t)(r.d_ff & 0xffffu);
+                a.pff = b.pff0 + (int32_t)(r.d_ff >> 16);
+            } else {
+                a.pf = ld_at_nt(L.pf, o4);
+                a.sf = ld_at_nt(L.sf, o4);
+                a.sff = ld_at_nt(L.sff, o4);
+                a.pff = ld_at_nt(L.pff, o4);
+            }
+            done = true;
+        }
+    }
+    if (!done) {
+        a.meta = ld_at_nt(L.meta, o4);
+        a.pf = ld_at_nt(L.pf, o4);
+        a.sf = ld_at_nt(L.sf, o4);
+        a.sff = ld_at_nt(L.sff, o4);
+        a.pff = ld_at_nt(L.pff, o4);
+        a.q = ld_at_nt(static_cast<const R *>(L.q), (uint32_t)k * (uint32_t)sizeof(R));
+    }
     // f+_i(x_f) of the outgoing direction: Bouzidi (q > 1/2) and Yu links only;
     // -1 (pf is meant) when no link needs it, so that nothing waits for pf here
     a.pfi = L.pfi ? ld_at_nt(L.pfi, o4) : -1;
