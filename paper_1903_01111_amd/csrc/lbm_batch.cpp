@@ -54,7 +54,7 @@ struct lbm_batch {
     size_t bytes = 0;
     // workspace offsets
     size_t off_A = 0, off_B = 0, off_mask = 0, off_seg = 0, off_meta = 0, off_q = 0, off_uw = 0, off_sf = 0,
-           off_sff = 0, off_pf = 0, off_pff = 0, off_pfi = 0, off_li = 0, off_L = 0, off_rec = 0, off_mnode = 0,
+           off_sff = 0, off_pf = 0, off_pff = 0, off_pfi = 0, off_crec = 0, off_cbase = 0, off_li = 0, off_L = 0, off_rec = 0, off_mnode = 0,
            off_pbase = 0, off_M = 0, off_P = 0, off_wpart = 0, off_wobj = 0, off_uin = 0, off_force = 0,
            off_insts = 0, off_tiles = 0, off_partials = 0, off_stage = 0, total = 0;
     // geometry, per instance until the batch is assembled
@@ -135,7 +135,9 @@ struct lbm_batch {
         auto i32 = [&](size_t off) { return reinterpret_cast<const int32_t *>(ws + off); };
         return lbm::Links{reinterpret_cast<const uint32_t *>(ws + off_meta), ws + off_q,
                           has_uw ? ws + off_uw : nullptr, i32(off_sf), i32(off_sff), i32(off_pf), i32(off_pff),
-                          i32(off_li), n_links, 0, 0, nullptr, has_pfi ? i32(off_pfi) : nullptr};
+                          i32(off_li), n_links, 0, 0, nullptr, has_pfi ? i32(off_pfi) : nullptr,
+                          rb() == 4 && n_links > 0 ? reinterpret_cast<const lbm::LinkRec *>(ws + off_crec) : nullptr,
+                          reinterpret_cast<const lbm::LinkRunBase *>(ws + off_cbase)};
     }
 };
 
@@ -189,6 +191,8 @@ size_t layout(lbm_batch *b)
     b->off_pf = take(nl * 4);
     b->off_pff = take(nl * 4);
     b->off_pfi = take(nl * 4);
+    b->off_crec = take(rb == 4 ? nl * sizeof(lbm::LinkRec) : 0);
+    b->off_cbase = take(rb == 4 ? (nl / 64 + 1) * sizeof(lbm::LinkRunBase) : 0);
     b->off_li = take(nl * 4);
     b->off_L = take(nl * eb);
     b->off_rec = take(2 * nl * 2);
@@ -330,6 +334,11 @@ lbm_status assemble(lbm_batch *b)
         uwsrc = uwf.data();
     }
     const size_t n = (size_t)links;
+    // compact link records (4-byte reals) over the batch's global numbering
+    std::vector<lbm::LinkRec> crec;
+    std::vector<lbm::LinkRunBase> cbase;
+    if (rb == 4)
+        build_link_records(n, meta.data(), qf.data(), sf.data(), sff.data(), pf.data(), pff.data(), &crec, &cbase);
     struct Up {
         size_t off;
         const void *src;
@@ -343,6 +352,8 @@ lbm_status assemble(lbm_batch *b)
                {b->off_pff, pff.data(), n * 4},
                {b->off_pfi, pfi.data(), b->has_pfi ? n * 4 : 0},
                {b->off_li, li.data(), n * 4},
+               {b->off_crec, crec.data(), crec.size() * sizeof(lbm::LinkRec)},
+               {b->off_cbase, cbase.data(), cbase.size() * sizeof(lbm::LinkRunBase)},
                {b->off_rec, rec.data(), rec.size() * 2},
                {b->off_mnode, mnode.data(), mnode.size() * 4},
                {b->off_pbase, pbase.data(), pbase.size() * 4},

@@ -63,4 +63,13 @@ lbm_status prepare_geometry(const lbm_params &p, const uint8_t *mask, int64_t n,
                             const int8_t *dir, const double *q, const double *uw, const int32_t *obj,
                             const int8_t *scheme, int32_t pitch, Prepared *out, std::string *why);
 
+// Compact link records of n links (4-byte reals): per run of 64 links the bases
+// (the smallest M slot and P entry of x_f and of x_ff), per link the direction
+// word, q's bits and the 16-bit excesses over the bases; runs that do not fit are
+// marked (sf0 = -1) and keep only the direction word and q.  crec gets n entries,
+// cbase n / 64 + 1.
+void build_link_records(size_t n, const uint32_t *meta, const float *q, const int32_t *sf, const int32_t *sff,
+                        const int32_t *pf, const int32_t *pff, std::vector<lbm::LinkRec> *crec,
+                        std::vector<lbm::LinkRunBase> *cbase);
+
 }  // namespace lbm_host

@@ -540,6 +540,41 @@ lbm_status prepare_geometry(const lbm_params &p, const uint8_t *mask, int64_t n,
     return LBM_OK;
 }
 
+void build_link_records(size_t n, const uint32_t *meta, const float *q, const int32_t *sf, const int32_t *sff,
+                        const int32_t *pf, const int32_t *pff, std::vector<lbm::LinkRec> *crec,
+                        std::vector<lbm::LinkRunBase> *cbase)
+{
+    crec->assign(n, lbm::LinkRec{0u, 0u, 0u, 0u});
+    cbase->assign(n / 64 + 1, lbm::LinkRunBase{-1, 0, 0, 0});
+    for (size_t r = 0; r * 64 < n; ++r) {
+        const size_t a = r * 64, e = std::min(n, a + 64);
+        int64_t sf0 = INT64_MAX, pf0 = INT64_MAX, sff0 = INT64_MAX, pff0 = INT64_MAX;
+        int64_t sf1 = INT64_MIN, pf1 = INT64_MIN, sff1 = INT64_MIN, pff1 = INT64_MIN;
+        for (size_t k = a; k < e; ++k) {
+            sf0 = std::min<int64_t>(sf0, sf[k]), sf1 = std::max<int64_t>(sf1, sf[k]);
+            pf0 = std::min<int64_t>(pf0, pf[k]), pf1 = std::max<int64_t>(pf1, pf[k]);
+            if (sff[k] >= 0) {
+                sff0 = std::min<int64_t>(sff0, sff[k]), sff1 = std::max<int64_t>(sff1, sff[k]);
+                pff0 = std::min<int64_t>(pff0, pff[k]), pff1 = std::max<int64_t>(pff1, pff[k]);
+            }
+        }
+        if (sff0 == INT64_MAX) sff0 = sff1 = pff0 = pff1 = 0;
+        // 0xffff is kept free in the x_ff slot excess: it marks a link without x_ff
+        const bool fit = sf1 - sf0 <= 0xffff && pf1 - pf0 <= 0xffff && sff1 - sff0 < 0xffff && pff1 - pff0 <= 0xffff;
+        if (fit) (*cbase)[r] = lbm::LinkRunBase{(int32_t)sf0, (int32_t)pf0, (int32_t)sff0, (int32_t)pff0};
+        for (size_t k = a; k < e; ++k) {
+            uint32_t qb;
+            std::memcpy(&qb, &q[k], 4);
+            uint32_t df = 0u, dff = 0u;
+            if (fit) {
+                df = (uint32_t)(sf[k] - sf0) | ((uint32_t)(pf[k] - pf0) << 16);
+                dff = sff[k] >= 0 ? (uint32_t)(sff[k] - sff0) | ((uint32_t)(pff[k] - pff0) << 16) : 0xffffu;
+            }
+            (*crec)[k] = lbm::LinkRec{meta[k], qb, df, dff};
+        }
+    }
+}
+
 }  // namespace lbm_host
 
 using namespace lbm_host;
@@ -822,39 +857,12 @@ lbm_status lbm_set_geometry(lbm_ctx *c, const uint8_t *mask, int64_t n_links, co
     // link index of each (node, dir) rank, for the fused bulk kernel
     std::vector<int32_t> kof(n);
     for (size_t k = 0; k < n; ++k) kof[prep.li[k]] = (int32_t)k;
-    // compact records (4-byte reals): per run of 64 links the smallest M slot and P
-    // entry of x_f and of x_ff, per link the 16-bit excesses over them
-    std::vector<lbm::LinkRec> crec(rb == 4 ? n : 0);
-    std::vector<lbm::LinkRunBase> cbase(rb == 4 ? n / 64 + 1 : 0);
-    for (size_t r = 0; rb == 4 && r * 64 < n; ++r) {
-        const size_t a = r * 64, e = std::min(n, a + 64);
-        int64_t sf0 = INT64_MAX, pf0 = INT64_MAX, sff0 = INT64_MAX, pff0 = INT64_MAX;
-        int64_t sf1 = INT64_MIN, pf1 = INT64_MIN, sff1 = INT64_MIN, pff1 = INT64_MIN;
-        for (size_t k = a; k < e; ++k) {
-            sf0 = std::min<int64_t>(sf0, prep.sf[k]), sf1 = std::max<int64_t>(sf1, prep.sf[k]);
-            pf0 = std::min<int64_t>(pf0, prep.pf[k]), pf1 = std::max<int64_t>(pf1, prep.pf[k]);
-            if (prep.sff[k] >= 0) {
-                sff0 = std::min<int64_t>(sff0, prep.sff[k]), sff1 = std::max<int64_t>(sff1, prep.sff[k]);
-                pff0 = std::min<int64_t>(pff0, prep.pff[k]), pff1 = std::max<int64_t>(pff1, prep.pff[k]);
-            }
-        }
-        if (sff0 == INT64_MAX) sff0 = sff1 = pff0 = pff1 = 0;
-        const bool fit = sf1 - sf0 <= 0xffff && pf1 - pf0 <= 0xffff && sff1 - sff0 < 0xffff && pff1 - pff0 <= 0xffff;
-        cbase[r] = fit ? lbm::LinkRunBase{(int32_t)sf0, (int32_t)pf0, (int32_t)sff0, (int32_t)pff0}
-                       : lbm::LinkRunBase{-1, 0, 0, 0};
-        for (size_t k = a; k < e; ++k) {
-            uint32_t qb;
-            std::memcpy(&qb, &qf[k], 4);
-            if (!fit) {
-                crec[k] = lbm::LinkRec{prep.meta[k], qb, 0u, 0u};
-                continue;
-            }
-            const bool ff = prep.sff[k] >= 0;
-            crec[k] = lbm::LinkRec{prep.meta[k], qb, (uint32_t)(prep.sf[k] - sf0) | ((uint32_t)(prep.pf[k] - pf0) << 16),
-                                   ff ? (uint32_t)(prep.sff[k] - sff0) | ((uint32_t)(prep.pff[k] - pff0) << 16)
-                                      : 0xffffu};
-        }
-    }
+    // compact link records (4-byte reals)
+    std::vector<lbm::LinkRec> crec;
+    std::vector<lbm::LinkRunBase> cbase;
+    if (rb == 4)
+        build_link_records(n, prep.meta.data(), qf.data(), prep.sf.data(), prep.sff.data(), prep.pf.data(),
+                           prep.pff.data(), &crec, &cbase);
     struct Up {
         size_t off;
         const void *src;
